@@ -1,0 +1,165 @@
+/*
+ * mvpb -- mixed-variational phononic band structures on one MI355X (gfx950).
+ *
+ * C-ABI of the library.  Plain pointers and sizes only.  The method is the
+ * mixed-variational (Nemat-Nasser / Srivastava) Galerkin formulation of
+ * arXiv:1310.6380:
+ *   - unit cell, lattice vectors h^1, h^2 and Bloch vector k = Q_i q^i: Sec. 2;
+ *   - Bloch-Fourier basis with cutoff M1, M2 (alpha in [-M1,M1], beta in
+ *     [-M2,M2]): Sec. 2.3 and eq. (approximation2d);
+ *   - matrices H, Omega, Phi, H* = -H^T: Sec. 4.1, eqs. (eh), (eo), (ep);
+ *   - eigenproblem (H Phi^-1 H*) U = lambda Omega U, omega = sqrt(lambda):
+ *     Sec. 3, eq. (eigenvalueproblem), solved in generalized Hermitian form.
+ *
+ * Conventions
+ *   Units: SI (lattice in metres, E in Pa, rho in kg/m^3, omega in rad/s).
+ *   Status: every call returns an int status (MVPB_OK = 0 or a negative
+ *     MVPB_E_* code).  On error out-parameters are left untouched and a
+ *     message is available from mvpb_last_error() on the calling thread.
+ *     The library never aborts or exits.
+ *   Ownership: all arrays are owned by the caller.  *_create calls deep-copy
+ *     their inputs, so the caller may free them on return.  Handles are owned
+ *     by the library and released only by the matching *_destroy.  A
+ *     context destroyed while cells or plans of it are alive stays usable by
+ *     them and is freed together with the last one; it accepts no new work.
+ *   Streams: all device work of a context runs on the stream given to
+ *     mvpb_ctx_create (NULL = a stream owned by the context).  Calls return
+ *     after the stream has finished unless MVPB_F_ASYNC is passed (then
+ *     device outputs are valid once the stream has drained, and device
+ *     errors surface at the next synchronising call).
+ *   Threads: a context and its cells/plans must not be used from two host
+ *     threads at once.
+ */
+#ifndef MVPB_H
+#define MVPB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mvpb_ctx_s *mvpb_ctx;
+typedef struct mvpb_cell_s *mvpb_cell;
+typedef struct mvpb_plan_s *mvpb_plan;
+
+enum {
+  MVPB_OK = 0,
+  MVPB_E_INVALID = -1,     /* bad argument (NULL, size, NaN, property range ...) */
+  MVPB_E_NOT_PD = -2,      /* a compliance/density matrix is not positive definite */
+  MVPB_E_NOMEM = -3,       /* device allocation failed or workspace cap exceeded */
+  MVPB_E_DEVICE = -4,      /* HIP runtime error */
+  MVPB_E_UNSUPPORTED = -5  /* valid request that this build does not implement */
+};
+
+/* Property table layouts (one row per phase). */
+enum {
+  MVPB_PROP_ISO_E_NU_RHO = 0 /* E [Pa], nu, rho [kg/m^3]; isotropic plane strain (Sec. 4) */
+};
+
+/* Precision of a plan. */
+enum {
+  MVPB_PREC_FP64 = 0,          /* everything in FP64 */
+  MVPB_PREC_SF_FP32 = 1,       /* structure-factor contraction in FP32 (FP32 accumulate) */
+  MVPB_PREC_SF_BF16 = 2,       /* structure-factor contraction in BF16 inputs, FP32 accumulate */
+  MVPB_PREC_EIG_FP32_RR64 = 4  /* FP32 tridiagonal eigensolve, FP64 Rayleigh-Ritz refinement */
+};
+
+/* Flags of mvpb_solve / mvpb_solve_batch. */
+enum {
+  MVPB_F_DEVICE_PTRS = 1, /* omega / U are device pointers (else host pointers) */
+  MVPB_F_ASYNC = 2        /* do not wait for the stream before returning */
+};
+
+/* Last error message of the calling thread (valid until its next mvpb call). */
+const char *mvpb_last_error(void);
+
+/* Library version string. */
+const char *mvpb_version(void);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (NULL: the context creates its own).  `workspace_cap` bounds the bytes of
+ * device workspace a single solve may allocate (0 = no bound); a solve that
+ * needs more returns MVPB_E_NOMEM. */
+int mvpb_ctx_create(int device, void *hip_stream, size_t workspace_cap, mvpb_ctx *out);
+int mvpb_ctx_destroy(mvpb_ctx ctx);
+
+/* A unit cell given as an nx x ny pixel map of phase ids.
+ * lattice[4] = {h1x, h1y, h2x, h2y} (rows of the matrix A of Sec. 4).
+ * phase[i*ny + j] is the phase of pixel (i, j), i along h1, in [0, n_phases).
+ * Pixel (i,j) covers fractional coordinates H1 in [i/nx,(i+1)/nx],
+ * H2 in [j/ny,(j+1)/ny].  props: n_phases rows in the layout prop_kind
+ * (ISO: E > 0, -1 < nu < 0.5, rho > 0).  Phases with no pixel are allowed.
+ * Host pointers; deep-copied. */
+int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], int nx, int ny,
+                            const int32_t *phase, int n_phases, int prop_kind,
+                            const double *props, mvpb_cell *out);
+int mvpb_cell_destroy(mvpb_cell cell);
+
+/* Build the k-independent part of the method for cutoff (M1, M2):
+ * structure factors of every phase on the (4M1+1)x(4M2+1) difference grid,
+ * the compliance matrix Phi and density matrix Omega (Sec. 4.1 eqs. (eo),
+ * (ep)), their Cholesky factors, and the coefficient matrices of the
+ * reduced operator, which is quadratic in the Bloch vector.  M1, M2 >= 0,
+ * N = (2M1+1)(2M2+1) <= 4096.  Returns MVPB_E_NOT_PD if Phi or Omega is
+ * not positive definite. */
+int mvpb_plan_create(mvpb_cell cell, int M1, int M2, int precision, mvpb_plan *out);
+/* n_u = 2N displacement unknowns, n_s = 3N stress unknowns (Sec. 4.1). */
+int mvpb_plan_dofs(mvpb_plan plan, int *n_u, int *n_s);
+int mvpb_plan_destroy(mvpb_plan plan);
+
+/* Solve for the lowest n_bands at each of n_k Bloch vectors.
+ * Q[2*t + i] = Q_i of point t (k = Q1 q^1 + Q2 q^2, finite).
+ * omega[t*n_bands + b]: frequencies in rad/s, ascending per point
+ *   (sqrt(max(lambda, 0))).
+ * U: NULL or space for n_k*n_bands*2N complex values (interleaved re, im),
+ *   U[((t*n_bands + b)*2N + r)], r < N the u1 coefficients, r >= N the u2
+ *   coefficients, in the plane-wave order I = (alpha+M1)(2M2+1)+(beta+M2);
+ *   normalised to U^H Omega U = 1 with the largest-modulus entry real > 0.
+ * 1 <= n_bands <= 2N.  Q, omega and U are host pointers unless
+ * MVPB_F_DEVICE_PTRS is set (then omega and U are device pointers; Q stays
+ * on the host). */
+int mvpb_solve(mvpb_plan plan, int n_k, const double *Q, int n_bands, double *omega, double *U,
+               unsigned flags);
+
+/* Many plans at once: all (plan, k) items in one batched launch sequence
+ * (captured in a HIP graph and replayed).  n_k[p] points for plan p taken
+ * from Q[p] (host pointers), results to omega[p][t*n_bands + b] (host
+ * pointers, or device pointers with MVPB_F_DEVICE_PTRS).  Every plan must
+ * belong to ctx and have 2N >= n_bands. */
+int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plans, const int *n_k,
+                     const double *const *Q, int n_bands, double *const *omega, unsigned flags);
+
+/* Phase-summed structure factors of a cell on the difference grid
+ * (debug/parity access to the first step of the method):
+ * F[(w*(4M1+1) + m+2M1)*(4M2+1) + q+2M2] (complex, interleaved) for the
+ * weights w = 0: d11+d12, 1: d11-d12, 2: rho, 3: 1, where
+ * F_w(m,q) = sum_p w_p int_{Omega_p} exp(i 2 pi (m H1 + q H2)) dx.
+ * `precision` selects the FP64, FP32 or BF16 contraction.  F: host pointer,
+ * 4*(4M1+1)*(4M2+1) complex values. */
+int mvpb_structure_factors(mvpb_cell cell, int M1, int M2, int precision, double *F);
+
+/* Points equally spaced in arc length on Gamma(0,0)-X(1/2,0)-M(1/2,1/2)-Gamma
+ * (the boundary of the irreducible zone of a square lattice), both ends
+ * Gamma.  Q: host pointer, 2*n_k doubles. */
+int mvpb_kpath_square(int n_k, double *Q);
+
+/* Kernel timers (diagnostics).  With profiling on, every kernel launch of a
+ * context is bracketed by HIP events on the context stream and its device
+ * time accumulated per kernel family.  Kernel ids: 0 structure_factors,
+ * 1 toeplitz_scatter, 2 potrf_trtri, 3 zgemm, 4 combine_coefficients,
+ * 5 form_operator, 6 hetrd_panel, 7 hetrd_update, 8 tridiag_eig,
+ * 9 backtransform, 10 rayleigh_ritz (MVPB_N_KERNELS in total).  Launches
+ * inside the HIP graph of mvpb_solve_batch are not timed.
+ * mvpb_ctx_profile(ctx, 1) clears the totals and starts timing, 0 stops.
+ * mvpb_ctx_profile_read waits for the recorded events and returns the total
+ * milliseconds, the number of launches and a static name string. */
+#define MVPB_N_KERNELS 11
+int mvpb_ctx_profile(mvpb_ctx ctx, int enable);
+int mvpb_ctx_profile_read(mvpb_ctx ctx, int kernel, double *total_ms, long long *launches, const char **name);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MVPB_H */

@@ -18,7 +18,11 @@ def band_error(omega, omega_ref, floor=1e-3):
         raise ValueError(f"shape mismatch {omega.shape} vs {ref.shape}")
     ref2 = ref.reshape(-1, ref.shape[-1])
     om2 = omega.reshape(-1, ref.shape[-1])
-    top = ref2[:, -1:]
+    top = ref2[:, -1:].copy()
+    # a k whose whole reference spectrum is zero (one plane wave at Gamma) is
+    # scaled by the largest reference frequency of the set instead
+    gmax = float(ref2.max()) if ref2.size else 0.0
+    top[top <= 0.0] = gmax if gmax > 0.0 else 1.0
     err = np.zeros_like(ref2)
     big = ref2 >= floor * top
     err[big] = np.abs(om2[big] - ref2[big]) / ref2[big]

@@ -1,0 +1,790 @@
+// Host side of the mvpb C-ABI: argument validation, handles, device buffers,
+// the k-independent plan build and the batched per-k solve.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/mvpb.h"
+#include "common.h"
+#include "kernels.h"
+#include "prof.h"
+
+using namespace mvpb;
+
+namespace mvpb {
+thread_local Profiler *t_prof = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// error state
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static int set_err(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return set_err(MVPB_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                     __LINE__);                                                              \
+  } while (0)
+
+// Device buffer owned by a host object.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t b) {
+    release();
+    if (b == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  // grow-only
+  hipError_t reserve(size_t b) {
+    if (b <= bytes) return hipSuccess;
+    return alloc(b);
+  }
+  template <typename T>
+  T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+struct mvpb_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t cap = 0;
+  DevBuf ws;          // per-solve workspace (grow-only)
+  DevBuf items;       // item table
+  DevBuf scratch;     // small host-visible results staging
+  hipGraphExec_t graph = nullptr;
+  std::string graph_key;
+  Profiler prof;
+  int children = 0;     // live cells and plans
+  bool closing = false; // mvpb_ctx_destroy called while children were alive
+};
+
+static void ctx_free(mvpb_ctx c) {
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->ws.release();
+  c->items.release();
+  c->scratch.release();
+  c->prof.reset();
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+// A cell or plan releases its hold on the context; the context goes once
+// it has been destroyed by the caller and no child is left.
+static void ctx_release(mvpb_ctx c) {
+  if (--c->children == 0 && c->closing) ctx_free(c);
+}
+
+// Routes the kernel timers of the calling thread to a context for one call.
+struct ProfBind {
+  Profiler *old;
+  explicit ProfBind(mvpb_ctx c) : old(t_prof) { t_prof = c ? &c->prof : nullptr; }
+  ~ProfBind() { t_prof = old; }
+};
+
+struct mvpb_cell_s {
+  mvpb_ctx ctx = nullptr;
+  double lattice[4];
+  double T[4];       // A^-1, row-major
+  double area = 0.0;
+  int nx = 0, ny = 0, n_phases = 0;
+  DevBuf phase;      // int32 [nx*ny]
+  DevBuf wtab;       // double [n_phases][4]
+};
+
+struct mvpb_plan_s {
+  mvpb_ctx ctx = nullptr;
+  int M1 = 0, M2 = 0, N = 0, prec = 0;
+  double T[4];
+  double area = 0.0;
+  DevBuf coef;       // 15 N x N
+  DevBuf linvR;      // N x N, L_R^-1
+};
+
+static int check_ctx(mvpb_ctx c) {
+  if (!c) return set_err(MVPB_E_INVALID, "NULL context");
+  if (c->closing) return set_err(MVPB_E_INVALID, "context has been destroyed");
+  return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// basic calls
+// ---------------------------------------------------------------------------
+extern "C" const char *mvpb_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *mvpb_version(void) { return "mvpb 0.1 (gfx950)"; }
+
+extern "C" int mvpb_ctx_create(int device, void *hip_stream, size_t workspace_cap, mvpb_ctx *out) {
+  if (!out) return set_err(MVPB_E_INVALID, "out is NULL");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return set_err(MVPB_E_INVALID, "device %d out of range [0,%d)", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  HIP_TRY(init_kernel_attributes());
+  mvpb_ctx c = new mvpb_ctx_s();
+  c->device = device;
+  c->cap = workspace_cap;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return set_err(MVPB_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_ctx_destroy(mvpb_ctx c) {
+  if (!c) return MVPB_OK;
+  if (c->closing) return set_err(MVPB_E_INVALID, "context destroyed twice");
+  if (c->children > 0) {
+    c->closing = true;  // freed with its last cell or plan
+    return MVPB_OK;
+  }
+  ctx_free(c);
+  return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// cell
+// ---------------------------------------------------------------------------
+static bool lattice_ok(const double *L, double *T, double *area) {
+  for (int i = 0; i < 4; ++i)
+    if (!isfinite(L[i])) return false;
+  const double det = L[0] * L[3] - L[1] * L[2];
+  if (!(fabs(det) > 0.0) || !isfinite(det)) return false;
+  // A = [[h1x, h1y], [h2x, h2y]]; T = A^-1
+  T[0] = L[3] / det;
+  T[1] = -L[1] / det;
+  T[2] = -L[2] / det;
+  T[3] = L[0] / det;
+  *area = fabs(det);
+  return true;
+}
+
+extern "C" int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], int nx, int ny,
+                                       const int32_t *phase, int n_phases, int prop_kind, const double *props,
+                                       mvpb_cell *out) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!lattice || !phase || !props || !out) return set_err(MVPB_E_INVALID, "NULL argument");
+  if (nx <= 0 || ny <= 0 || nx > 4096 || ny > 4096) return set_err(MVPB_E_INVALID, "bad grid %d x %d", nx, ny);
+  if (n_phases <= 0) return set_err(MVPB_E_INVALID, "n_phases must be positive");
+  if (prop_kind != MVPB_PROP_ISO_E_NU_RHO)
+    return set_err(MVPB_E_UNSUPPORTED, "property kind %d not supported", prop_kind);
+  double T[4], area;
+  if (!lattice_ok(lattice, T, &area)) return set_err(MVPB_E_INVALID, "degenerate or non-finite lattice");
+  for (size_t i = 0; i < (size_t)nx * ny; ++i)
+    if (phase[i] < 0 || phase[i] >= n_phases)
+      return set_err(MVPB_E_INVALID, "phase id %d at pixel %zu out of range [0,%d)", phase[i], i, n_phases);
+  std::vector<double> w((size_t)n_phases * 4);
+  for (int p = 0; p < n_phases; ++p) {
+    const double E = props[3 * p], nu = props[3 * p + 1], rho = props[3 * p + 2];
+    if (!(E > 0.0) || !isfinite(E)) return set_err(MVPB_E_INVALID, "phase %d: E must be positive", p);
+    if (!(nu > -1.0 && nu < 0.5)) return set_err(MVPB_E_INVALID, "phase %d: nu must be in (-1, 0.5)", p);
+    if (!(rho > 0.0) || !isfinite(rho)) return set_err(MVPB_E_INVALID, "phase %d: rho must be positive", p);
+    // plane-strain compliances: d11 + d12 = 1/(2(lam+mu)) = (1+nu)(1-2nu)/E,
+    // d11 - d12 = 1/(2 mu) = (1+nu)/E; the shear weight d33 = 2 (d11 - d12).
+    w[4 * p + 0] = (1.0 + nu) * (1.0 - 2.0 * nu) / E;
+    w[4 * p + 1] = (1.0 + nu) / E;
+    w[4 * p + 2] = rho;
+    w[4 * p + 3] = 1.0;
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  mvpb_cell c = new mvpb_cell_s();
+  c->ctx = ctx;
+  memcpy(c->lattice, lattice, sizeof c->lattice);
+  memcpy(c->T, T, sizeof T);
+  c->area = area;
+  c->nx = nx;
+  c->ny = ny;
+  c->n_phases = n_phases;
+  hipError_t e = c->phase.alloc(sizeof(int32_t) * nx * ny);
+  if (e == hipSuccess) e = c->wtab.alloc(sizeof(double) * w.size());
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->phase.p, phase, sizeof(int32_t) * nx * ny, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->wtab.p, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return set_err(MVPB_E_NOMEM, "cell upload: %s", hipGetErrorString(e));
+  }
+  ctx->children++;
+  *out = c;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_cell_destroy(mvpb_cell c) {
+  if (!c) return MVPB_OK;
+  mvpb_ctx ctx = c->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete c;
+  ctx_release(ctx);
+  return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// structure factors
+// ---------------------------------------------------------------------------
+static int run_structure_factors(mvpb_cell c, int M1, int M2, int precision, DevBuf &X, DevBuf &F) {
+  const int nm = 4 * M1 + 1, nq = 4 * M2 + 1;
+  HIP_TRY(X.reserve(sizeof(cd) * 4 * (size_t)std::max(c->nx, c->ny) * std::max(nm, nq)));
+  HIP_TRY(F.reserve(sizeof(cd) * 4 * (size_t)nm * nq));
+  hipStream_t st = c->ctx->stream;
+  if (precision == MVPB_PREC_FP64 || precision == MVPB_PREC_EIG_FP32_RR64) {
+    HIP_TRY(launch_structure_factors_f64(c->phase.as<int32_t>(), c->wtab.as<double>(), c->nx, c->ny, M1, M2,
+                                         c->area, X.as<cd>(), F.as<cd>(), st));
+  } else {
+    return set_err(MVPB_E_UNSUPPORTED, "precision %d not implemented for structure factors", precision);
+  }
+  return MVPB_OK;
+}
+
+static int check_cutoff(int M1, int M2) {
+  if (M1 < 0 || M2 < 0) return set_err(MVPB_E_INVALID, "cutoffs must be non-negative");
+  const long N = (long)(2 * M1 + 1) * (2 * M2 + 1);
+  if (2 * N > MAX_N) return set_err(MVPB_E_UNSUPPORTED, "2N = %ld exceeds %d", 2 * N, MAX_N);
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_structure_factors(mvpb_cell c, int M1, int M2, int precision, double *F) {
+  if (!c || !F) return set_err(MVPB_E_INVALID, "NULL argument");
+  int rc = check_cutoff(M1, M2);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(c->ctx->device));
+  ProfBind pb(c->ctx);
+  DevBuf X, Fd;
+  rc = run_structure_factors(c, M1, M2, precision, X, Fd);
+  if (rc) return rc;
+  const size_t cnt = 4 * (size_t)(4 * M1 + 1) * (4 * M2 + 1);
+  HIP_TRY(hipMemcpyAsync(F, Fd.p, sizeof(cd) * cnt, hipMemcpyDeviceToHost, c->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(c->ctx->stream));
+  return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+extern "C" int mvpb_plan_create(mvpb_cell c, int M1, int M2, int precision, mvpb_plan *out) {
+  if (!c || !out) return set_err(MVPB_E_INVALID, "NULL argument");
+  int rc = check_cutoff(M1, M2);
+  if (rc) return rc;
+  if (precision != MVPB_PREC_FP64)
+    return set_err(MVPB_E_UNSUPPORTED, "precision %d not implemented", precision);
+  mvpb_ctx ctx = c->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ProfBind pb(ctx);
+  hipStream_t st = ctx->stream;
+  const int N = (2 * M1 + 1) * (2 * M2 + 1);
+  const size_t NN = (size_t)N * N;
+
+  DevBuf X, F;
+  rc = run_structure_factors(c, M1, M2, precision, X, F);
+  if (rc) return rc;
+
+  // Sigma = T(d11+d12), Delta = T(d11-d12), R = T(rho); their inverse factors
+  DevBuf mats, linv, stat, ptrs, gvec;
+  HIP_TRY(mats.alloc(sizeof(cd) * 3 * NN));
+  HIP_TRY(linv.alloc(sizeof(cd) * 3 * NN));
+  HIP_TRY(stat.alloc(sizeof(int) * 3));
+  cd *Tm = mats.as<cd>();
+  cd *Li = linv.as<cd>();
+  HIP_TRY(launch_toeplitz_scatter(F.as<cd>(), M1, M2, N, Tm, Tm + NN, Tm + 2 * NN, st));
+
+  // pointer tables: [0..2] potrf inputs, [3..5] inverses, then GEMM tables
+  std::vector<void *> hp;
+  for (int i = 0; i < 3; ++i) hp.push_back(Tm + i * NN);
+  for (int i = 0; i < 3; ++i) hp.push_back(Li + i * NN);
+  // G_l vectors: G_0 = 1, G_l = 2 pi (T n)_l at Q = 0
+  std::vector<double> g(3 * (size_t)N);
+  for (int a = -M1; a <= M1; ++a)
+    for (int b = -M2; b <= M2; ++b) {
+      const int r = (a + M1) * (2 * M2 + 1) + (b + M2);
+      g[r] = 1.0;
+      g[N + r] = 2.0 * M_PI * (c->T[0] * a + c->T[1] * b);
+      g[2 * N + r] = 2.0 * M_PI * (c->T[2] * a + c->T[3] * b);
+    }
+  HIP_TRY(gvec.alloc(sizeof(double) * g.size()));
+  HIP_TRY(hipMemcpyAsync(gvec.p, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice, st));
+
+  DevBuf P, Xp;
+  HIP_TRY(P.alloc(sizeof(cd) * 6 * NN));
+  HIP_TRY(Xp.alloc(sizeof(cd) * 18 * NN));
+  cd *Pm = P.as<cd>();
+  cd *Xm = Xp.as<cd>();
+  // P_{x,l} = L_R^-1 diag(G_l) L_x^-H   (x = 0: Sigma, 1: Delta)
+  const size_t o_pA = hp.size();
+  for (int x = 0; x < 2; ++x)
+    for (int l = 0; l < 3; ++l) hp.push_back(Li + 2 * NN);
+  const size_t o_pB = hp.size();
+  for (int x = 0; x < 2; ++x)
+    for (int l = 0; l < 3; ++l) hp.push_back(Li + x * NN);
+  const size_t o_pC = hp.size();
+  for (int x = 0; x < 2; ++x)
+    for (int l = 0; l < 3; ++l) hp.push_back(Pm + (x * 3 + l) * NN);
+  const size_t o_pS = hp.size();
+  for (int x = 0; x < 2; ++x)
+    for (int l = 0; l < 3; ++l) hp.push_back(gvec.as<double>() + l * N);
+  // X_{x,l,m} = P_{x,l} P_{x,m}^H
+  const size_t o_xA = hp.size();
+  for (int x = 0; x < 2; ++x)
+    for (int l = 0; l < 3; ++l)
+      for (int m = 0; m < 3; ++m) hp.push_back(Pm + (x * 3 + l) * NN);
+  const size_t o_xB = hp.size();
+  for (int x = 0; x < 2; ++x)
+    for (int l = 0; l < 3; ++l)
+      for (int m = 0; m < 3; ++m) hp.push_back(Pm + (x * 3 + m) * NN);
+  const size_t o_xC = hp.size();
+  for (int x = 0; x < 2; ++x)
+    for (int l = 0; l < 3; ++l)
+      for (int m = 0; m < 3; ++m) hp.push_back(Xm + (x * 9 + l * 3 + m) * NN);
+  HIP_TRY(ptrs.alloc(sizeof(void *) * hp.size()));
+  HIP_TRY(hipMemcpyAsync(ptrs.p, hp.data(), sizeof(void *) * hp.size(), hipMemcpyHostToDevice, st));
+  void **dp = ptrs.as<void *>();
+
+  HIP_TRY(launch_potrf_trtri((cd *const *)dp, (cd *const *)(dp + 3), stat.as<int>(), 3, N, st));
+  int hstat[3] = {0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(hstat, stat.p, sizeof hstat, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const char *names[3] = {"compliance block Phi(d11+d12)", "compliance block Phi(d11-d12)", "density matrix Omega"};
+  for (int i = 0; i < 3; ++i)
+    if (hstat[i])
+      return set_err(MVPB_E_NOT_PD, "%s is not positive definite (pivot %d)", names[i], hstat[i] - 1);
+
+  {
+    GemmBatch bt{(const cd *const *)(dp + o_pA), (const cd *const *)(dp + o_pB), (cd *const *)(dp + o_pC),
+                 (const double *const *)(dp + o_pS), N, N, N};
+    HIP_TRY(launch_zgemm(OP_N, OP_C, N, N, N, mk(1.0, 0.0), bt, mk(0.0, 0.0), 6, st));
+  }
+  {
+    GemmBatch bt{(const cd *const *)(dp + o_xA), (const cd *const *)(dp + o_xB), (cd *const *)(dp + o_xC),
+                 nullptr, N, N, N};
+    HIP_TRY(launch_zgemm(OP_N, OP_C, N, N, N, mk(1.0, 0.0), bt, mk(0.0, 0.0), 18, st));
+  }
+  mvpb_plan pl = new mvpb_plan_s();
+  pl->ctx = ctx;
+  pl->M1 = M1;
+  pl->M2 = M2;
+  pl->N = N;
+  pl->prec = precision;
+  memcpy(pl->T, c->T, sizeof pl->T);
+  pl->area = c->area;
+  hipError_t e = pl->coef.alloc(sizeof(cd) * 15 * NN);
+  if (e == hipSuccess) e = pl->linvR.alloc(sizeof(cd) * NN);
+  if (e != hipSuccess) {
+    delete pl;
+    return set_err(MVPB_E_NOMEM, "plan buffers: %s", hipGetErrorString(e));
+  }
+  e = launch_combine(Xm, N, 0.5 * c->area * c->area, pl->coef.as<cd>(), st);
+  if (e == hipSuccess) e = hipMemcpyAsync(pl->linvR.p, Li + 2 * NN, sizeof(cd) * NN, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete pl;
+    return set_err(MVPB_E_DEVICE, "plan build: %s", hipGetErrorString(e));
+  }
+  ctx->children++;
+  *out = pl;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_plan_dofs(mvpb_plan p, int *n_u, int *n_s) {
+  if (!p) return set_err(MVPB_E_INVALID, "NULL plan");
+  if (n_u) *n_u = 2 * p->N;
+  if (n_s) *n_s = 3 * p->N;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_plan_destroy(mvpb_plan p) {
+  if (!p) return MVPB_OK;
+  mvpb_ctx ctx = p->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete p;
+  ctx_release(ctx);
+  return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-item workspace layout
+// ---------------------------------------------------------------------------
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static size_t item_bytes(int n, int nb) {
+  size_t s = 0;
+  s += align256(sizeof(cd) * (size_t)n * n) * 2;          // A, Ak
+  s += align256(sizeof(cd) * (size_t)n * PANEL);          // W
+  s += align256(sizeof(double) * n) * 2;                  // d, e
+  s += align256(sizeof(cd) * n);                          // tau
+  s += align256(sizeof(double) * (size_t)n * nb);         // X
+  s += align256(sizeof(double) * (size_t)5 * n * nb);     // lu
+  s += align256(sizeof(double) * nb) * 3;                 // lam_t, lam, omega
+  s += align256(sizeof(cd) * (size_t)n * nb) * 2;         // Y, Z
+  return s;
+}
+
+static EigItem carve_item(char *base, int n, int nb) {
+  EigItem it{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    char *p = base + o;
+    o += align256(b);
+    return p;
+  };
+  it.A = (cd *)take(sizeof(cd) * (size_t)n * n);
+  it.Ak = (cd *)take(sizeof(cd) * (size_t)n * n);
+  it.W = (cd *)take(sizeof(cd) * (size_t)n * PANEL);
+  it.d = (double *)take(sizeof(double) * n);
+  it.e = (double *)take(sizeof(double) * n);
+  it.tau = (cd *)take(sizeof(cd) * n);
+  it.X = (double *)take(sizeof(double) * (size_t)n * nb);
+  it.lu = (double *)take(sizeof(double) * (size_t)5 * n * nb);
+  it.lam_t = (double *)take(sizeof(double) * nb);
+  it.lam = (double *)take(sizeof(double) * nb);
+  it.omega = (double *)take(sizeof(double) * nb);
+  it.Y = (cd *)take(sizeof(cd) * (size_t)n * nb);
+  it.Z = (cd *)take(sizeof(cd) * (size_t)n * nb);
+  return it;
+}
+
+// Normalise each eigenvector (length len, complex) so that its
+// largest-modulus entry (lowest index on ties) is real and positive.
+__global__ void normalize_phase(cd *U, int len, int count) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  const int v = blockIdx.x;
+  if (v >= count) return;
+  cd *u = U + (size_t)v * len;
+  double best = -1.0;
+  int idx = 0;
+  for (int r = threadIdx.x; r < len; r += blockDim.x) {
+    const double a = abs2(u[r]);
+    if (a > best) { best = a; idx = r; }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double o = bv[threadIdx.x + s];
+      const int oi = bi[threadIdx.x + s];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const cd piv = u[bi[0]];
+  const double a = sqrt(abs2(piv));
+  if (a == 0.0) return;
+  const cd ph = mk(piv.re / a, -piv.im / a);
+  for (int r = threadIdx.x; r < len; r += blockDim.x) u[r] = u[r] * ph;
+}
+
+__global__ void gather_omega(const EigItem *items, int n_items, int nb, double *out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_items * nb) return;
+  const int i = t / nb, b = t % nb;
+  out[t] = items[i].omega[b];
+}
+
+// One batch of work items that share a workspace allocation.
+struct Job {
+  mvpb_plan plan;
+  double Q1, Q2;
+  int out_index;   // position in the caller's flattened output
+};
+
+static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double *omega_dev, double *U_dev,
+                     bool use_graph, const std::string &graph_key) {
+  hipStream_t st = ctx->stream;
+  const int n_items = (int)jobs.size();
+  if (n_items == 0) return MVPB_OK;
+  size_t total = 0;
+  int n_max = 0;
+  for (const Job &j : jobs) {
+    const int n = 2 * j.plan->N;
+    total += item_bytes(n, nb);
+    n_max = std::max(n_max, n);
+  }
+  if (ctx->cap && total > ctx->cap)
+    return set_err(MVPB_E_NOMEM, "workspace %zu bytes exceeds the cap of %zu bytes", total, ctx->cap);
+  const bool realloc = total > ctx->ws.bytes || sizeof(EigItem) * n_items > ctx->items.bytes;
+  HIP_TRY(ctx->ws.reserve(total));
+  HIP_TRY(ctx->items.reserve(sizeof(EigItem) * n_items));
+  std::vector<EigItem> items(n_items);
+  size_t off = 0;
+  for (int i = 0; i < n_items; ++i) {
+    const Job &j = jobs[i];
+    const int n = 2 * j.plan->N;
+    EigItem it = carve_item(ctx->ws.as<char>() + off, n, nb);
+    off += item_bytes(n, nb);
+    it.coef = j.plan->coef.as<cd>();
+    it.N = j.plan->N;
+    it.nb = nb;
+    const double *T = j.plan->T;
+    it.kap1 = 2.0 * M_PI * (T[0] * j.Q1 + T[1] * j.Q2);
+    it.kap2 = 2.0 * M_PI * (T[2] * j.Q1 + T[3] * j.Q2);
+    items[i] = it;
+  }
+  HIP_TRY(hipMemcpyAsync(ctx->items.p, items.data(), sizeof(EigItem) * n_items, hipMemcpyHostToDevice, st));
+  const EigItem *d_items = ctx->items.as<EigItem>();
+
+  auto enqueue = [&]() -> hipError_t {
+    hipError_t e = launch_form_operator(d_items, n_items, n_max, st);
+    if (e == hipSuccess) e = launch_hetrd(d_items, n_items, n_max, st);
+    if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, st);
+    if (e == hipSuccess) e = launch_backtransform(d_items, n_items, st);
+    if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, st);
+    return e;
+  };
+  if (use_graph) {
+    if (realloc || ctx->graph_key != graph_key || !ctx->graph) {
+      if (ctx->graph) {
+        (void)hipGraphExecDestroy(ctx->graph);
+        ctx->graph = nullptr;
+      }
+      hipGraph_t g;
+      HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      Profiler *saved = t_prof;
+      t_prof = nullptr;  // no event records inside the captured graph
+      hipError_t e = enqueue();
+      t_prof = saved;
+      hipError_t e2 = hipStreamEndCapture(st, &g);
+      if (e != hipSuccess) return set_err(MVPB_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+      if (e2 != hipSuccess) return set_err(MVPB_E_DEVICE, "graph capture end: %s", hipGetErrorString(e2));
+      e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return set_err(MVPB_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+      ctx->graph_key = graph_key;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->graph, st));
+  } else {
+    HIP_TRY(enqueue());
+  }
+  // gather frequencies in job order
+  HIP_TRY(ctx->scratch.reserve(sizeof(double) * (size_t)n_items * nb));
+  hipLaunchKernelGGL(gather_omega, dim3((n_items * nb + 255) / 256), dim3(256), 0, st, d_items, n_items, nb,
+                     ctx->scratch.as<double>());
+  HIP_TRY(hipGetLastError());
+  // scatter to caller order (jobs may be sorted)
+  for (int i = 0; i < n_items; ++i) {
+    HIP_TRY(hipMemcpyAsync(omega_dev + (size_t)jobs[i].out_index * nb, ctx->scratch.as<double>() + (size_t)i * nb,
+                           sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
+  }
+  if (U_dev) {
+    // U_t = [L_R^-H Z_t(0:N, :); L_R^-H Z_t(N:2N, :)], written in caller order
+    std::vector<const void *> hp;
+    hp.reserve(6 * n_items);
+    for (int i = 0; i < n_items; ++i) hp.push_back(jobs[i].plan->linvR.p);
+    for (int i = 0; i < n_items; ++i) hp.push_back(jobs[i].plan->linvR.p);
+    for (int i = 0; i < n_items; ++i) hp.push_back(items[i].Z);
+    for (int i = 0; i < n_items; ++i) hp.push_back(items[i].Z + jobs[i].plan->N);
+    for (int i = 0; i < n_items; ++i) hp.push_back(U_dev + (size_t)jobs[i].out_index * nb * 2 * jobs[i].plan->N * 2);
+    for (int i = 0; i < n_items; ++i)
+      hp.push_back(U_dev + ((size_t)jobs[i].out_index * nb * 2 * jobs[i].plan->N + jobs[i].plan->N) * 2);
+    DevBuf ptrs;
+    HIP_TRY(ptrs.alloc(sizeof(void *) * hp.size()));
+    HIP_TRY(hipMemcpyAsync(ptrs.p, hp.data(), sizeof(void *) * hp.size(), hipMemcpyHostToDevice, st));
+    void **dp = ptrs.as<void *>();
+    // all items of one call share N (single plan) or are issued per item
+    for (int i = 0; i < n_items; ++i) {
+      const int N = jobs[i].plan->N, n = 2 * N;
+      GemmBatch b1{(const cd *const *)(dp + 0 * n_items + i), (const cd *const *)(dp + 2 * n_items + i),
+                   (cd *const *)(dp + 4 * n_items + i), nullptr, N, n, n};
+      HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), b1, mk(0.0, 0.0), 1, st));
+      GemmBatch b2{(const cd *const *)(dp + 1 * n_items + i), (const cd *const *)(dp + 3 * n_items + i),
+                   (cd *const *)(dp + 5 * n_items + i), nullptr, N, n, n};
+      HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), b2, mk(0.0, 0.0), 1, st));
+      hipLaunchKernelGGL(normalize_phase, dim3(nb), dim3(256), 0, st,
+                         (cd *)(U_dev + (size_t)jobs[i].out_index * nb * n * 2), n, nb);
+      HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return MVPB_OK;
+}
+
+static bool q_ok(const double *Q, int n) {
+  for (int i = 0; i < 2 * n; ++i)
+    if (!isfinite(Q[i])) return false;
+  return true;
+}
+
+extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, double *omega, double *U,
+                          unsigned flags) {
+  if (!p || !Q || !omega) return set_err(MVPB_E_INVALID, "NULL argument");
+  if (n_k < 0) return set_err(MVPB_E_INVALID, "n_k must be non-negative");
+  if (n_k == 0) return MVPB_OK;
+  if (n_bands < 1 || n_bands > 2 * p->N || n_bands > RR_MAX_BANDS)
+    return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, min(2N=%d, %d)]", n_bands, 2 * p->N, RR_MAX_BANDS);
+  if (!q_ok(Q, n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
+  mvpb_ctx ctx = p->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ProfBind pb(ctx);
+  hipStream_t st = ctx->stream;
+  const bool dev = flags & MVPB_F_DEVICE_PTRS;
+  const int n = 2 * p->N;
+  // chunk the k list so that the workspace stays within the cap
+  int chunk = n_k;
+  const size_t per = item_bytes(n, n_bands);
+  const size_t budget = ctx->cap ? ctx->cap : (size_t)32 << 30;
+  if (per > budget) return set_err(MVPB_E_NOMEM, "one item needs %zu bytes, cap is %zu", per, budget);
+  chunk = (int)std::min<size_t>((size_t)n_k, budget / per);
+  DevBuf om_dev, u_dev;
+  double *om_out = omega;
+  double *u_out = U;
+  if (!dev) {
+    HIP_TRY(om_dev.alloc(sizeof(double) * (size_t)n_k * n_bands));
+    om_out = om_dev.as<double>();
+    if (U) {
+      HIP_TRY(u_dev.alloc(sizeof(double) * 2 * (size_t)n_k * n_bands * n));
+      u_out = u_dev.as<double>();
+    }
+  }
+  for (int k0 = 0; k0 < n_k; k0 += chunk) {
+    const int kc = std::min(chunk, n_k - k0);
+    std::vector<Job> jobs(kc);
+    for (int t = 0; t < kc; ++t) jobs[t] = Job{p, Q[2 * (k0 + t)], Q[2 * (k0 + t) + 1], t};
+    int rc = run_items(ctx, jobs, n_bands, om_out + (size_t)k0 * n_bands,
+                       u_out ? u_out + 2 * (size_t)k0 * n_bands * n : nullptr, false, "");
+    if (rc) return rc;
+  }
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(omega, om_out, sizeof(double) * (size_t)n_k * n_bands, hipMemcpyDeviceToHost, st));
+    if (U)
+      HIP_TRY(hipMemcpyAsync(U, u_out, sizeof(double) * 2 * (size_t)n_k * n_bands * n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  } else if (!(flags & MVPB_F_ASYNC)) {
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plans, const int *n_k,
+                                const double *const *Q, int n_bands, double *const *omega, unsigned flags) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (n_plans < 0 || (n_plans > 0 && (!plans || !n_k || !Q || !omega)))
+    return set_err(MVPB_E_INVALID, "NULL argument");
+  if (n_bands < 1 || n_bands > RR_MAX_BANDS) return set_err(MVPB_E_INVALID, "n_bands = %d out of range", n_bands);
+  std::vector<Job> jobs;
+  std::vector<size_t> base(n_plans + 1, 0);
+  std::string key = "b" + std::to_string(n_bands);
+  for (int i = 0; i < n_plans; ++i) {
+    if (!plans[i] || plans[i]->ctx != ctx) return set_err(MVPB_E_INVALID, "plan %d missing or from another context", i);
+    if (n_k[i] < 0 || (n_k[i] > 0 && (!Q[i] || !omega[i]))) return set_err(MVPB_E_INVALID, "plan %d: bad k list", i);
+    if (2 * plans[i]->N < n_bands) return set_err(MVPB_E_INVALID, "plan %d: n_bands > 2N", i);
+    if (!q_ok(Q[i], n_k[i])) return set_err(MVPB_E_INVALID, "plan %d: non-finite Bloch vector", i);
+    base[i + 1] = base[i] + n_k[i];
+    char tmp[64];
+    snprintf(tmp, sizeof tmp, ":%p/%d", (void *)plans[i], n_k[i]);
+    key += tmp;
+    for (int t = 0; t < n_k[i]; ++t)
+      jobs.push_back(Job{plans[i], Q[i][2 * t], Q[i][2 * t + 1], (int)(base[i] + t)});
+  }
+  if (jobs.empty()) return MVPB_OK;
+  for (const Job &j : jobs) { char tmp[48]; snprintf(tmp, sizeof tmp, "%a,%a;", j.Q1, j.Q2); key += tmp; }
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  // largest items first so the longest work starts earliest
+  std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.plan->N > b.plan->N; });
+  DevBuf om;
+  HIP_TRY(om.alloc(sizeof(double) * base[n_plans] * n_bands));
+  rc = run_items(ctx, jobs, n_bands, om.as<double>(), nullptr, true, key);
+  if (rc) return rc;
+  const bool dev = flags & MVPB_F_DEVICE_PTRS;
+  for (int i = 0; i < n_plans; ++i) {
+    if (n_k[i] == 0) continue;
+    HIP_TRY(hipMemcpyAsync(omega[i], om.as<double>() + base[i] * n_bands, sizeof(double) * n_k[i] * n_bands,
+                           dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  }
+  if (!dev || !(flags & MVPB_F_ASYNC)) HIP_TRY(hipStreamSynchronize(st));
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_kpath_square(int n_k, double *Q) {
+  if (!Q || n_k < 1) return set_err(MVPB_E_INVALID, "bad arguments");
+  const double cx[4] = {0.0, 0.5, 0.5, 0.0}, cy[4] = {0.0, 0.0, 0.5, 0.0};
+  double seg[3], cum[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < 3; ++s) {
+    seg[s] = hypot(cx[s + 1] - cx[s], cy[s + 1] - cy[s]);
+    cum[s + 1] = cum[s] + seg[s];
+  }
+  if (n_k == 1) {
+    Q[0] = 0.0;
+    Q[1] = 0.0;
+    return MVPB_OK;
+  }
+  for (int t = 0; t < n_k; ++t) {
+    const double s = cum[3] * (double)t / (double)(n_k - 1);
+    int k = 0;
+    while (k < 2 && s >= cum[k + 1]) ++k;
+    const double u = (s - cum[k]) / seg[k];
+    Q[2 * t] = cx[k] + u * (cx[k + 1] - cx[k]);
+    Q[2 * t + 1] = cy[k] + u * (cy[k + 1] - cy[k]);
+  }
+  return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timers
+// ---------------------------------------------------------------------------
+static const char *k_names[K_COUNT] = {"structure_factors", "toeplitz_scatter", "potrf_trtri", "zgemm",
+                                       "combine_coefficients", "form_operator", "hetrd_panel", "hetrd_update",
+                                       "tridiag_eig", "backtransform", "rayleigh_ritz"};
+
+extern "C" int mvpb_ctx_profile(mvpb_ctx ctx, int enable) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  (void)hipSetDevice(ctx->device);
+  ctx->prof.reset();
+  ctx->prof.on = enable != 0;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_ctx_profile_read(mvpb_ctx ctx, int kernel, double *total_ms, long long *launches,
+                                     const char **name) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (kernel < 0 || kernel >= K_COUNT) return set_err(MVPB_E_INVALID, "kernel id %d out of range", kernel);
+  (void)hipSetDevice(ctx->device);
+  ctx->prof.drain();
+  if (total_ms) *total_ms = ctx->prof.total_ms[kernel];
+  if (launches) *launches = ctx->prof.launches[kernel];
+  if (name) *name = k_names[kernel];
+  return MVPB_OK;
+}

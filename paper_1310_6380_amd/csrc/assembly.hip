@@ -1,0 +1,256 @@
+// Assembly kernels: phase-summed structure factors on the difference grid,
+// Toeplitz scatter of the compliance / density matrices, the per-cell
+// coefficient combination and the per-k formation of the reduced operator.
+//
+// Method (arXiv:1310.6380): every entry of Phi and Omega (Sec. 4.1, eqs.
+// (eo), (ep)) is an integral of a piecewise-constant weight times
+// f = exp(i (K^{ab} - K^{te}) . x).  The Bloch part cancels in the
+// difference, so with x = A^T H the entry depends only on the integer
+// difference m = n_ab - n_te of the two plane-wave indices:
+//   F_w(m, q) = sum_p w_p int_{Omega_p} exp(i 2 pi (m H1 + q H2)) dx.
+// For a pixel cell this is a factored 2-D DFT
+//   F_w = S o (E1 . W_w . E2^T),
+// E1[m,i] = exp(i pi m (2i+1)/nx), E2[q,j] = exp(i pi q (2j+1)/ny),
+// W_w[i,j] = w_{phase(i,j)}, S(m,q) = |Omega|/(nx ny) sinc(m/nx) sinc(q/ny).
+#include "common.h"
+#include "kernels.h"
+#include "prof.h"
+
+namespace mvpb {
+
+// ---------------------------------------------------------------------------
+// Structure factors, FP64 (two factored passes of the DFT contraction).
+// ---------------------------------------------------------------------------
+
+// Pass A: X[w][i][qi] = sum_j W_w[i,j] * E2[q, j], one block per pixel row i.
+// wtab: [n_phases][4] weights (d11+d12, d11-d12, rho, 1).
+__global__ void __launch_bounds__(256) sf_pass_a_f64(const int32_t *__restrict__ phase,
+                                                     const double *__restrict__ wtab, int nx, int ny,
+                                                     int M2, cd *__restrict__ X) {
+  extern __shared__ double smem[];
+  const int nq = 4 * M2 + 1;
+  double *wl = smem;                // [4][ny]
+  double *tc = wl + 4 * ny;         // cos(pi t / ny), t in [0, 2 ny)
+  double *ts = tc + 2 * ny;         // sin(pi t / ny)
+  const int i = blockIdx.x;
+  for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+    const int p = phase[i * ny + j];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wl[w * ny + j] = wtab[p * 4 + w];
+  }
+  for (int t = threadIdx.x; t < 2 * ny; t += blockDim.x) {
+    double s, c;
+    sincospi((double)t / (double)ny, &s, &c);
+    tc[t] = c;
+    ts[t] = s;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 4 * nq; idx += blockDim.x) {
+    const int w = idx / nq, qi = idx % nq, q = qi - 2 * M2;
+    // exact argument reduction: angle = pi * (q (2j+1) mod 2ny) / ny
+    const int two_ny = 2 * ny;
+    int step = ((2 * q) % two_ny + two_ny) % two_ny;
+    int t = ((q % two_ny) + two_ny) % two_ny;
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < ny; ++j) {
+      const double v = wl[w * ny + j];
+      ar = fma(v, tc[t], ar);
+      ai = fma(v, ts[t], ai);
+      t += step;
+      if (t >= two_ny) t -= two_ny;
+    }
+    X[((size_t)w * nx + i) * nq + qi] = mk(ar, ai);
+  }
+}
+
+// Pass B: F[w][mi][qi] = S(m,q) * sum_i E1[m,i] X[w][i][qi]; one block per (mi, w).
+__global__ void __launch_bounds__(256) sf_pass_b_f64(const cd *__restrict__ X, int nx, int ny, int M1,
+                                                     int M2, double area, cd *__restrict__ F) {
+  extern __shared__ double smem[];
+  const int nm = 4 * M1 + 1, nq = 4 * M2 + 1;
+  const int mi = blockIdx.x, w = blockIdx.y, m = mi - 2 * M1;
+  double *er = smem, *ei = smem + nx;
+  const int two_nx = 2 * nx;
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+    long t = ((long)m * (2 * i + 1)) % two_nx;
+    if (t < 0) t += two_nx;
+    double s, c;
+    sincospi((double)t / (double)nx, &s, &c);
+    er[i] = c;
+    ei[i] = s;
+  }
+  __syncthreads();
+  double sm = 1.0;
+  if (m != 0) sm = sinpi((double)m / nx) / (M_PI * (double)m / nx);
+  for (int qi = threadIdx.x; qi < nq; qi += blockDim.x) {
+    const int q = qi - 2 * M2;
+    double sq = 1.0;
+    if (q != 0) sq = sinpi((double)q / ny) / (M_PI * (double)q / ny);
+    cd acc = mk(0.0, 0.0);
+    for (int i = 0; i < nx; ++i) acc = cfma(mk(er[i], ei[i]), X[((size_t)w * nx + i) * nq + qi], acc);
+    const double s = area / ((double)nx * ny) * sm * sq;
+    F[((size_t)w * nm + mi) * nq + qi] = s * acc;
+  }
+}
+
+hipError_t launch_structure_factors_f64(const int32_t *phase, const double *wtab, int nx, int ny, int M1,
+                                        int M2, double area, cd *X, cd *F, hipStream_t st) {
+  const int nm = 4 * M1 + 1;
+  ProfScope ps(K_SF, st);
+  size_t sha = sizeof(double) * (4 * ny + 4 * ny);
+  hipLaunchKernelGGL(sf_pass_a_f64, dim3(nx), dim3(256), sha, st, phase, wtab, nx, ny, M2, X);
+  size_t shb = sizeof(double) * 2 * nx;
+  hipLaunchKernelGGL(sf_pass_b_f64, dim3(nm, 4), dim3(256), shb, st, X, nx, ny, M1, M2, area, F);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Toeplitz scatter: T_w[r, c] = F_w(n_c - n_r) for w = 0 (Sigma), 1 (Delta),
+// 2 (rho).  Column-major N x N outputs.  n_r = (alpha_r, beta_r) with
+// r = (alpha+M1)(2M2+1) + (beta+M2).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) toeplitz_scatter(const cd *__restrict__ F, int M1, int M2, int N,
+                                                        cd *__restrict__ T0, cd *__restrict__ T1,
+                                                        cd *__restrict__ T2) {
+  const int nb = 2 * M2 + 1, nm = 4 * M1 + 1, nq = 4 * M2 + 1;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= N) return;
+  const int ar = r / nb, br = r - ar * nb;
+  const int ac = c / nb, bc = c - ac * nb;
+  const int dm = ac - ar + 2 * M1, dq = bc - br + 2 * M2;
+  const size_t o = (size_t)dm * nq + dq;
+  const size_t dst = (size_t)c * N + r;
+  T0[dst] = F[o];
+  T1[dst] = F[(size_t)nm * nq + o];
+  T2[dst] = F[(size_t)2 * nm * nq + o];
+}
+
+hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T0, cd *T1, cd *T2,
+                                   hipStream_t st) {
+  ProfScope ps(K_SCATTER, st);
+  hipLaunchKernelGGL(toeplitz_scatter, dim3((N + 255) / 256, N), dim3(256), 0, st, F, M1, M2, N, T0, T1, T2);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Combine the products X_lm = P_l P_m^H (X in {Sigma, Delta}, l, m in 0..2,
+// stored at Xp[(x*9 + l*3 + m) * N*N]) into the 15 coefficient matrices of
+// the reduced operator C(k) (block form; kappa = Bloch vector):
+//   C11 = A11_0 + k1 A11_1 + k2 A11_2 + k1^2 S0 + k2^2 D0
+//   C22 = A22_0 + k1 A22_1 + k2 A22_2 + k1^2 D0 + k2^2 S0
+//   C12 = A12_0 + k1 A12_1 + k2 A12_2 + k1 k2 G0
+//   C21 = A21_0 + k1 A21_1 + k2 A21_2 + k1 k2 G0
+// all scaled by s = |Omega|^2 / 2.  Output order:
+//   0..2 A11, 3..5 A22, 6..8 A12, 9..11 A21, 12 S0, 13 D0, 14 G0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) combine_coefficients(const cd *__restrict__ Xp, size_t NN, double s,
+                                                            cd *__restrict__ coef) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NN) return;
+#define S_(l, m) Xp[(size_t)(0 * 9 + (l) * 3 + (m)) * NN + e]
+#define D_(l, m) Xp[(size_t)(1 * 9 + (l) * 3 + (m)) * NN + e]
+  const cd s00 = S_(0, 0), s01 = S_(0, 1), s02 = S_(0, 2), s10 = S_(1, 0), s11 = S_(1, 1), s12 = S_(1, 2),
+           s20 = S_(2, 0), s21 = S_(2, 1), s22 = S_(2, 2);
+  const cd d00 = D_(0, 0), d01 = D_(0, 1), d02 = D_(0, 2), d10 = D_(1, 0), d11 = D_(1, 1), d12 = D_(1, 2),
+           d20 = D_(2, 0), d21 = D_(2, 1), d22 = D_(2, 2);
+#undef S_
+#undef D_
+  cd *o = coef + e;
+  o[0 * NN] = s * (s11 + d11 + d22);
+  o[1 * NN] = s * (s10 + s01 + d10 + d01);
+  o[2 * NN] = s * (d20 + d02);
+  o[3 * NN] = s * (s22 + d22 + d11);
+  o[4 * NN] = s * (d10 + d01);
+  o[5 * NN] = s * (s20 + s02 + d20 + d02);
+  o[6 * NN] = s * (s12 - d12 + d21);
+  o[7 * NN] = s * (s02 - d02 + d20);
+  o[8 * NN] = s * (s10 - d10 + d01);
+  o[9 * NN] = s * (s21 - d21 + d12);
+  o[10 * NN] = s * (s20 - d20 + d02);
+  o[11 * NN] = s * (s01 - d01 + d10);
+  o[12 * NN] = s * (s00 + d00);
+  o[13 * NN] = s * d00;
+  o[14 * NN] = s * s00;
+}
+
+hipError_t launch_combine(const cd *Xp, int N, double s, cd *coef, hipStream_t st) {
+  const size_t NN = (size_t)N * N;
+  ProfScope ps(K_COMBINE, st);
+  hipLaunchKernelGGL(combine_coefficients, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, st, Xp, NN, s,
+                     coef);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-k formation of C(k) (2N x 2N, Hermitian, full storage, column-major)
+// from the coefficient matrices.  One block per 32 x 32 tile (I >= J) of the
+// lower triangle; the upper triangle gets the conjugate transpose through an
+// LDS tile, so the result is exactly Hermitian with a real diagonal.  Two
+// copies are written: the working copy (overwritten by the reduction to
+// tridiagonal form) and the kept copy used by the Rayleigh-Ritz step.
+// ---------------------------------------------------------------------------
+template <typename Item>
+__global__ void __launch_bounds__(256) form_operator(const Item *__restrict__ items, int tiles_max) {
+  __shared__ cd tile[32][33];
+  const Item it = items[blockIdx.y];
+  const int N = it.N, n = 2 * N;
+  const int nt = (n + 31) / 32;
+  // linear lower-triangle tile index -> (I, J), I >= J
+  int t = blockIdx.x;
+  if (t >= nt * (nt + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const double k1 = it.kap1, k2 = it.kap2;
+  const size_t NN = (size_t)N * N;
+  const cd *cf = it.coef;
+  const int lr = threadIdx.x & 31, lc0 = threadIdx.x >> 5;
+  for (int lc = lc0; lc < 32; lc += 8) {
+    const int r = I * 32 + lr, c = J * 32 + lc;
+    cd v = mk(0.0, 0.0);
+    if (r < n && c < n && r >= c) {
+      const int br = r >= N, bc = c >= N;
+      const int i = r - br * N, j = c - bc * N;
+      const size_t e = (size_t)j * N + i;
+      if (!br && !bc) {
+        v = cf[e] + k1 * cf[NN + e] + k2 * cf[2 * NN + e] + (k1 * k1) * cf[12 * NN + e] +
+            (k2 * k2) * cf[13 * NN + e];
+      } else if (br && bc) {
+        v = cf[3 * NN + e] + k1 * cf[4 * NN + e] + k2 * cf[5 * NN + e] + (k1 * k1) * cf[13 * NN + e] +
+            (k2 * k2) * cf[12 * NN + e];
+      } else if (!br && bc) {
+        v = cf[6 * NN + e] + k1 * cf[7 * NN + e] + k2 * cf[8 * NN + e] + (k1 * k2) * cf[14 * NN + e];
+      } else {
+        v = cf[9 * NN + e] + k1 * cf[10 * NN + e] + k2 * cf[11 * NN + e] + (k1 * k2) * cf[14 * NN + e];
+      }
+      if (r == c) v.im = 0.0;
+      const size_t dst = (size_t)c * n + r;
+      it.A[dst] = v;
+      it.Ak[dst] = v;
+    }
+    tile[lc][lr] = v;
+  }
+  __syncthreads();
+  // mirrored tile (J, I): element (r', c') = (J*32 + lr, I*32 + lc) with r' < c'
+  for (int lc = lc0; lc < 32; lc += 8) {
+    const int r = J * 32 + lr, c = I * 32 + lc;
+    if (r < n && c < n && r < c) {
+      const cd v = conj(tile[lr][lc]);
+      const size_t dst = (size_t)c * n + r;
+      it.A[dst] = v;
+      it.Ak[dst] = v;
+    }
+  }
+}
+
+hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, hipStream_t st) {
+  const int nt = (n_max + 31) / 32;
+  const int tiles = nt * (nt + 1) / 2;
+  ProfScope ps(K_FORM, st);
+  hipLaunchKernelGGL(form_operator<EigItem>, dim3(tiles, n_items), dim3(256), 0, st, items, tiles);
+  return hipGetLastError();
+}
+
+}  // namespace mvpb

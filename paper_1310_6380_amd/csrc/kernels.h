@@ -1,0 +1,78 @@
+// Device work descriptors and kernel launchers of the mvpb library.
+#pragma once
+
+#include "common.h"
+
+namespace mvpb {
+
+// Largest reduced-operator order handled by the eigensolver kernels
+// (2N <= MAX_N; vectors of this length are staged in LDS).
+constexpr int MAX_N = 4096;
+// Panel width of the blocked reduction to tridiagonal form.
+constexpr int PANEL = 32;
+// Largest number of bands per solve (Rayleigh-Ritz block in LDS).
+constexpr int RR_MAX_BANDS = 64;
+
+// One (cell, k) work item of the eigensolve.  All pointers are device memory
+// owned by the solve that built the item table.
+struct EigItem {
+  // operator formation
+  const cd *coef;   // 15 coefficient matrices, N x N each (plan-owned)
+  double kap1, kap2;
+  int N;            // plane waves; the operator has order n = 2N
+  int nb;           // bands wanted
+  // reduction to tridiagonal form
+  cd *A;            // n x n working matrix; holds the Householder vectors afterwards
+  cd *Ak;           // n x n kept copy of C(k) for Rayleigh-Ritz
+  cd *W;            // n x PANEL panel workspace
+  double *d;        // n diagonal
+  double *e;        // n off-diagonal (real)
+  cd *tau;          // n reflector scalars
+  // tridiagonal eigenproblem
+  double *X;        // n x nb eigenvectors of the tridiagonal matrix
+  double *lu;       // 5 n x nb factorisation scratch
+  double *lam_t;    // nb eigenvalues of the tridiagonal matrix
+  // back-transform and refinement
+  cd *Y;            // n x nb eigenvectors of C(k)
+  cd *Z;            // n x nb scratch (C Y)
+  double *lam;      // nb refined eigenvalues (lambda = omega^2)
+  double *omega;    // nb output frequencies (device)
+  int status;       // reserved
+};
+
+// assembly.hip
+hipError_t launch_structure_factors_f64(const int32_t *phase, const double *wtab, int nx, int ny, int M1,
+                                        int M2, double area, cd *X, cd *F, hipStream_t st);
+hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T0, cd *T1, cd *T2,
+                                   hipStream_t st);
+hipError_t launch_combine(const cd *Xp, int N, double s, cd *coef, hipStream_t st);
+hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, hipStream_t st);
+
+// dense.hip
+// Cholesky (lower, in place) and explicit inverse of the factor for `count`
+// matrices A[b] (N x N, column-major); Linv[b] receives L^-1 (lower, the
+// strict upper part zeroed).  status[b] = 0 on success, j+1 if the pivot of
+// column j was not positive.
+hipError_t launch_potrf_trtri(cd *const *A, cd *const *Linv, int *status, int count, int N, hipStream_t st);
+
+enum Op { OP_N = 0, OP_C = 1 };
+// Batched complex GEMM: C[b] = alpha * op(A[b]) * diag(s[b]) * op(B[b]) + beta * C[b].
+// All matrices column-major; s[b] may be NULL (no scaling); M x K by K x N.
+struct GemmBatch {
+  const cd *const *A;
+  const cd *const *B;
+  cd *const *C;
+  const double *const *s;
+  int lda, ldb, ldc;
+};
+hipError_t launch_zgemm(Op opA, Op opB, int M, int N, int K, cd alpha, GemmBatch bt, cd beta, int count,
+                        hipStream_t st);
+
+// eigen.hip
+hipError_t init_kernel_attributes();  // once per device, before the first launch
+hipError_t launch_hetrd(const EigItem *items, int n_items, int n_max, hipStream_t st);
+hipError_t launch_tridiag_eig(const EigItem *items, int n_items, hipStream_t st);
+hipError_t launch_backtransform(const EigItem *items, int n_items, hipStream_t st);
+hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, hipStream_t st);
+
+}  // namespace mvpb

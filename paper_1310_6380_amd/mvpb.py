@@ -1,0 +1,298 @@
+"""Thin ctypes binding of the mvpb C-ABI (argument marshalling only).
+
+Every step of the band-structure path runs in the HIP library
+``libmvpb.so`` built next to this file; this module only converts Python
+arguments to pointers and status codes to exceptions.  It fails loudly when
+the library is missing.
+
+Device buffers for device-pointer outputs are allocated through the same HIP
+runtime the library is linked against (``DeviceBuffer``).  The torch wheel of
+this image carries its own, older HIP/HSA runtime; a second HSA runtime cannot
+open the GPU in a process where the first one already has, so torch tensors
+are not used as buffers here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmvpb.so")
+
+OK = 0
+E_INVALID = -1
+E_NOT_PD = -2
+E_NOMEM = -3
+E_DEVICE = -4
+E_UNSUPPORTED = -5
+
+PROP_ISO_E_NU_RHO = 0
+
+PREC_FP64 = 0
+PREC_SF_FP32 = 1
+PREC_SF_BF16 = 2
+PREC_EIG_FP32_RR64 = 4
+
+F_DEVICE_PTRS = 1
+F_ASYNC = 2
+
+EXPORTS = [
+    "mvpb_last_error", "mvpb_version", "mvpb_ctx_create", "mvpb_ctx_destroy",
+    "mvpb_cell_create_pixels", "mvpb_cell_destroy", "mvpb_plan_create", "mvpb_plan_dofs",
+    "mvpb_plan_destroy", "mvpb_solve", "mvpb_solve_batch", "mvpb_structure_factors",
+    "mvpb_kpath_square", "mvpb_ctx_profile", "mvpb_ctx_profile_read",
+]
+N_KERNELS = 11
+
+
+class MvpbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mvpb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmvpb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with paper_1310_6380_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    D = ctypes.POINTER(ctypes.c_double)
+    lib.mvpb_last_error.restype = ctypes.c_char_p
+    lib.mvpb_version.restype = ctypes.c_char_p
+    lib.mvpb_ctx_create.argtypes = [I, P, ctypes.c_size_t, ctypes.POINTER(P)]
+    lib.mvpb_ctx_destroy.argtypes = [P]
+    lib.mvpb_cell_create_pixels.argtypes = [P, D, I, I, ctypes.POINTER(ctypes.c_int32), I, I, D, ctypes.POINTER(P)]
+    lib.mvpb_cell_destroy.argtypes = [P]
+    lib.mvpb_plan_create.argtypes = [P, I, I, I, ctypes.POINTER(P)]
+    lib.mvpb_plan_dofs.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
+    lib.mvpb_plan_destroy.argtypes = [P]
+    lib.mvpb_solve.argtypes = [P, I, D, I, P, P, ctypes.c_uint]
+    lib.mvpb_solve_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(D), I,
+                                     ctypes.POINTER(P), ctypes.c_uint]
+    lib.mvpb_structure_factors.argtypes = [P, I, I, I, D]
+    lib.mvpb_kpath_square.argtypes = [I, D]
+    lib.mvpb_ctx_profile.argtypes = [P, I]
+    lib.mvpb_ctx_profile_read.argtypes = [P, I, D, ctypes.POINTER(ctypes.c_longlong),
+                                          ctypes.POINTER(ctypes.c_char_p)]
+    for name in EXPORTS:
+        fn = getattr(lib, name)
+        if name not in ("mvpb_last_error", "mvpb_version"):
+            fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+_hip = None
+
+
+def _hiprt():
+    """The HIP runtime libmvpb.so is linked against (already loaded with it)."""
+    global _hip
+    if _hip is None:
+        load()
+        _hip = ctypes.CDLL("libamdhip64.so.7")
+        _hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+        _hip.hipFree.argtypes = [ctypes.c_void_p]
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipDeviceSynchronize.argtypes = []
+        for f in (_hip.hipMalloc, _hip.hipFree, _hip.hipMemcpy, _hip.hipDeviceSynchronize):
+            f.restype = ctypes.c_int
+    return _hip
+
+
+class DeviceBuffer:
+    """Raw device allocation (hipMalloc) of the library's HIP runtime."""
+
+    def __init__(self, nbytes: int):
+        self.ptr = ctypes.c_void_p()
+        self.nbytes = int(nbytes)
+        rc = _hiprt().hipMalloc(ctypes.byref(self.ptr), max(self.nbytes, 1))
+        if rc != 0:
+            raise MvpbError(E_DEVICE, f"hipMalloc({nbytes}) failed with {rc}")
+
+    @property
+    def value(self) -> int:
+        return int(self.ptr.value)
+
+    def to_numpy(self, dtype, shape) -> np.ndarray:
+        out = np.empty(shape, dtype=dtype)
+        assert out.nbytes <= self.nbytes
+        rc = _hiprt().hipMemcpy(out.ctypes.data, self.ptr, out.nbytes, 2)  # device to host
+        if rc != 0:
+            raise MvpbError(E_DEVICE, f"hipMemcpy failed with {rc}")
+        return out
+
+    def free(self):
+        if self.ptr:
+            _hiprt().hipFree(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def device_synchronize():
+    rc = _hiprt().hipDeviceSynchronize()
+    if rc != 0:
+        raise MvpbError(E_DEVICE, f"hipDeviceSynchronize failed with {rc}")
+
+
+def _check(rc):
+    if rc != OK:
+        raise MvpbError(rc, load().mvpb_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def version() -> str:
+    return load().mvpb_version().decode()
+
+
+def kpath_square(n_k: int) -> np.ndarray:
+    Q = np.zeros((n_k, 2), dtype=np.float64)
+    _check(load().mvpb_kpath_square(n_k, _dptr(Q)))
+    return Q
+
+
+class Context:
+    """A device context (HIP device + stream + workspace)."""
+
+    def __init__(self, device: int = 0, stream=None, workspace_cap: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        s = ctypes.c_void_p(int(stream)) if stream is not None else None
+        _check(lib.mvpb_ctx_create(device, s, workspace_cap, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            load().mvpb_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool = True):
+        _check(load().mvpb_ctx_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total_ms, launches)} of the timed launches."""
+        out = {}
+        for k in range(N_KERNELS):
+            ms = ctypes.c_double()
+            n = ctypes.c_longlong()
+            nm = ctypes.c_char_p()
+            _check(load().mvpb_ctx_profile_read(self.h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(nm)))
+            out[nm.value.decode()] = (ms.value, n.value)
+        return out
+
+    def cell(self, phase, props, lattice=None):
+        return Cell(self, phase, props, lattice)
+
+    def solve_batch(self, plans, Qs, n_bands: int) -> list:
+        lib = load()
+        n = len(plans)
+        Qs = [np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1, 2)) for q in Qs]
+        outs = [np.zeros((q.shape[0], n_bands)) for q in Qs]
+        ph = (ctypes.c_void_p * n)(*[p.h for p in plans])
+        nk = (ctypes.c_int * n)(*[q.shape[0] for q in Qs])
+        qp = (ctypes.POINTER(ctypes.c_double) * n)(*[_dptr(q) for q in Qs])
+        op = (ctypes.c_void_p * n)(*[o.ctypes.data for o in outs])
+        _check(lib.mvpb_solve_batch(self.h, n, ph, nk, qp, n_bands, op, 0))
+        return outs
+
+
+class Cell:
+    """A pixel unit cell: phase map [nx, ny] (i along h1) and (E, nu, rho) rows."""
+
+    def __init__(self, ctx: Context, phase, props, lattice=None):
+        lib = load()
+        self.ctx = ctx
+        ph = np.ascontiguousarray(np.asarray(phase, dtype=np.int32))
+        pr = np.ascontiguousarray(np.asarray(props, dtype=np.float64).reshape(-1, 3))
+        lat = np.ascontiguousarray(np.asarray(lattice if lattice is not None else np.eye(2), dtype=np.float64).reshape(4))
+        h = ctypes.c_void_p()
+        _check(lib.mvpb_cell_create_pixels(ctx.h, _dptr(lat), ph.shape[0], ph.shape[1],
+                                           ph.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), pr.shape[0],
+                                           PROP_ISO_E_NU_RHO, _dptr(pr), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            load().mvpb_cell_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def structure_factors(self, M1: int, M2: int, precision: int = PREC_FP64) -> np.ndarray:
+        F = np.zeros((4, 4 * M1 + 1, 4 * M2 + 1), dtype=np.complex128)
+        _check(load().mvpb_structure_factors(self.h, M1, M2, precision,
+                                             F.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return F
+
+    def plan(self, M1: int, M2: int = None, precision: int = PREC_FP64):
+        return Plan(self, M1, M1 if M2 is None else M2, precision)
+
+
+class Plan:
+    """k-independent part of the method for one cell and cutoff."""
+
+    def __init__(self, cell: Cell, M1: int, M2: int, precision: int = PREC_FP64):
+        lib = load()
+        self.ctx = cell.ctx
+        h = ctypes.c_void_p()
+        _check(lib.mvpb_plan_create(cell.h, M1, M2, precision, ctypes.byref(h)))
+        self.h = h
+        nu, ns = ctypes.c_int(), ctypes.c_int()
+        _check(lib.mvpb_plan_dofs(h, ctypes.byref(nu), ctypes.byref(ns)))
+        self.n_u, self.n_s = nu.value, ns.value
+
+    def close(self):
+        if self.h:
+            load().mvpb_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, Q, n_bands: int, vectors: bool = False):
+        """Frequencies [n_k, n_bands] (rad/s) and optionally U [n_k, n_bands, 2N]."""
+        lib = load()
+        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, 2))
+        om = np.zeros((Q.shape[0], n_bands))
+        U = np.zeros((Q.shape[0], n_bands, self.n_u), dtype=np.complex128) if vectors else None
+        _check(lib.mvpb_solve(self.h, Q.shape[0], _dptr(Q), n_bands, ctypes.c_void_p(om.ctypes.data),
+                              ctypes.c_void_p(U.ctypes.data) if vectors else None, 0))
+        return (om, U) if vectors else om
+
+    def solve_device(self, Q, n_bands: int, omega_ptr: int, flags: int = F_DEVICE_PTRS):
+        """Write frequencies to device memory at omega_ptr (e.g. DeviceBuffer.value)."""
+        lib = load()
+        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, 2))
+        _check(lib.mvpb_solve(self.h, Q.shape[0], _dptr(Q), n_bands, ctypes.c_void_p(omega_ptr), None,
+                              flags | F_DEVICE_PTRS))

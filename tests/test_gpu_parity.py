@@ -1,0 +1,183 @@
+"""Parity of the HIP path (through the C-ABI) against the CPU oracle.
+
+Bar: relative eigenfrequency error <= 1e-9 (FP64 path), measured by
+oracle.compare.band_error (acoustic modes next to Gamma compared on lambda
+against 2e-9 of the top band at that k).  Structure factors: entry-wise
+within 1e-13 of the largest entry (same closed form, different summation
+order).
+"""
+import numpy as np
+import pytest
+
+from oracle import mixed_oracle as mo
+from oracle.compare import band_error
+from synth import Cell, circle_cell, config0, config1, kpath_gxmg, layered_cell, random_iso_props
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+OBLIQUE = np.array([[1.0, 0.0], [0.5, np.sqrt(3.0) / 2.0]])
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1310_6380_amd import mvpb
+    c = mvpb.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rand_cell(nx, ny, P, seed, lattice=None):
+    rng = np.random.default_rng(seed)
+    phase = rng.integers(0, P, (nx, ny)).astype(np.int32)
+    return Cell(np.eye(2) if lattice is None else lattice, phase, random_iso_props(P, rng))
+
+
+def _oracle_tables(cell, M1, M2):
+    I = mo.subdomain_integral_tables(cell.phase, cell.n_phases, cell.lattice, M1, M2)
+    J, R, Ph = mo.phase_sum_tables(I, cell.props)
+    return J, R, Ph
+
+
+@pytest.mark.parametrize("M1,M2,lat", [(3, 3, "sq"), (2, 4, "ob"), (5, 0, "sq")])
+def test_structure_factors_match_oracle(ctx, M1, M2, lat):
+    lattice = np.eye(2) if lat == "sq" else OBLIQUE
+    cell = _rand_cell(9, 7, 4, 5, lattice)
+    _say("structure factors", M1, M2, lat)
+    F = ctx.cell(cell.phase, cell.props, cell.lattice).structure_factors(M1, M2)
+    J, R, Ph = _oracle_tables(cell, M1, M2)
+    ref = [Ph[0, 0] + Ph[0, 1], Ph[0, 0] - Ph[0, 1], R, J]
+    for w in range(4):
+        scale = np.abs(ref[w]).max()
+        assert np.max(np.abs(F[w] - ref[w])) <= 1e-13 * scale, w
+
+
+def _check_bands(ctx, cell, M1, M2, Q, nb, tol=TOL64):
+    plan = ctx.cell(cell.phase, cell.props, cell.lattice).plan(M1, M2)
+    om = plan.solve(Q, nb)
+    ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, M1, M2, Q, nb)
+    err = band_error(om, ref)
+    _say("  band error", err)
+    assert err <= tol, err
+    return om, ref
+
+
+def test_config0_full_path(ctx):
+    """Simple inclusion cell: 16x16, 7x7 plane waves, 30 k on G-X-M-G, 6 bands."""
+    c = config0()
+    _say("config0")
+    _check_bands(ctx, c["cell"], c["M"], c["M"], c["Q"], c["n_bands"])
+
+
+@pytest.mark.parametrize("M1,M2,lat,nb", [(2, 3, "ob", 7), (4, 4, "sq", 12), (1, 1, "sq", 18), (0, 0, "sq", 2)])
+def test_random_cells(ctx, M1, M2, lat, nb):
+    """Cells without symmetry, M1 != M2, oblique lattice, all bands at tiny N."""
+    lattice = np.eye(2) if lat == "sq" else OBLIQUE
+    cell = _rand_cell(8, 6, 3, 17 + M1, lattice)
+    Q = np.array([[0.0, 0.0], [0.13, 0.27], [0.5, 0.5], [-0.31, 0.44], [0.5, 0.0]])
+    _say("random cell", M1, M2, lat, nb)
+    _check_bands(ctx, cell, M1, M2, Q, nb)
+
+
+def test_layered_cell_1d(ctx):
+    props = [(200e9, 0.3, 7800.0), (4e9, 0.38, 1200.0), (60e9, 0.25, 2500.0)]
+    cell = layered_cell([5, 4, 7], props, 16)
+    Q = np.array([[0.0, 0.0], [0.1, 0.0], [0.3, 0.0], [0.5, 0.0]])
+    _say("layered 1-D")
+    _check_bands(ctx, cell, 12, 0, Q, 8)
+
+
+def test_homogeneous_cell_free_dispersion(ctx):
+    """Closed form: omega = c_{L,T} |k + G| (no oracle involved)."""
+    E, nu, rho = 70e9, 0.33, 2700.0
+    cell = circle_cell(12, 0.3, inc=(E, nu, rho), mat=(E, nu, rho))
+    M = 4
+    Q = np.array([[0.25, 0.1], [0.5, 0.0], [0.31, 0.47]])
+    _say("homogeneous")
+    om = ctx.cell(cell.phase, cell.props).plan(M).solve(Q, 16)
+    lam, mu = mo.lame(E, nu)
+    cL, cT = np.sqrt((lam + 2 * mu) / rho), np.sqrt(mu / rho)
+    n = mo.plane_wave_indices(M, M)
+    for t, q in enumerate(Q):
+        kk = np.linalg.norm(2 * np.pi * (q[None, :] + n), axis=1)
+        ref = np.sort(np.concatenate([cL * kk, cT * kk]))[:16]
+        assert band_error(om[t:t + 1], ref[None]) <= TOL64
+
+
+def test_eigenvectors_residual_and_normalisation(ctx):
+    cell = _rand_cell(8, 8, 3, 3)
+    M = 3
+    Q = np.array([[0.21, 0.35], [0.5, 0.5]])
+    _say("eigenvectors")
+    plan = ctx.cell(cell.phase, cell.props).plan(M)
+    om, U = plan.solve(Q, 8, vectors=True)
+    I = mo.subdomain_integral_tables(cell.phase, 3, np.eye(2), M, M)
+    for t, q in enumerate(Q):
+        mats = mo.assemble(I, cell.props, np.eye(2), M, M, q)
+        A = mo.reduced_operator(mats)
+        Om = mats["Omega"]
+        V = U[t].T                                    # [2N, nb]
+        lam = om[t] ** 2
+        res = np.linalg.norm(A @ V - Om @ V * lam[None]) / np.linalg.norm(A)
+        assert res < 1e-10, res
+        assert np.allclose(V.conj().T @ Om @ V, np.eye(8), atol=1e-9)
+        k = np.argmax(np.abs(V), axis=0)
+        piv = V[k, np.arange(8)]
+        assert np.all(np.abs(piv.imag) < 1e-12 * np.abs(piv)) and np.all(piv.real > 0)
+
+
+def test_config1_full_size_sampled(ctx):
+    """1132-phase Voronoi cell, 21x21 plane waves (2N = 882), 18 bands: every
+    k of the 60-point path on the GPU, four of them checked against the oracle."""
+    c = config1()
+    cell = c["cell"]
+    _say("config1 full size")
+    plan = ctx.cell(cell.phase, cell.props).plan(c["M"])
+    om = plan.solve(c["Q"], c["n_bands"])
+    assert om.shape == (60, 18) and np.all(np.isfinite(om))
+    assert np.all(np.diff(om, axis=1) >= 0)
+    pick = [0, 17, 33, 52]
+    ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, c["M"], c["M"], c["Q"][pick], c["n_bands"])
+    err = band_error(om[pick], ref)
+    _say("  config1 error", err)
+    assert err <= TOL64
+
+
+def test_batch_matches_single_solves(ctx):
+    """Several cells with different cutoffs in one batched launch."""
+    cells = [_rand_cell(8, 8, 2, 40 + i) for i in range(4)]
+    Ms = [2, 4, 3, 1]
+    Qs = [kpath_gxmg(5), kpath_gxmg(3), kpath_gxmg(7), kpath_gxmg(2)]
+    _say("batch")
+    plans = [ctx.cell(c.phase, c.props).plan(M) for c, M in zip(cells, Ms)]
+    outs = ctx.solve_batch(plans, Qs, 6)
+    outs2 = ctx.solve_batch(plans, Qs, 6)          # graph replay
+    for c, M, Q, o, o2, pl in zip(cells, Ms, Qs, outs, outs2, plans):
+        ref, _ = mo.bands(c.phase, c.props, c.lattice, M, M, Q, 6)
+        assert band_error(o, ref) <= TOL64
+        assert np.array_equal(o, o2)
+        assert band_error(pl.solve(Q, 6), ref) <= TOL64
+
+
+def test_invalid_inputs_rejected(ctx):
+    from paper_1310_6380_amd import mvpb
+    cell = _rand_cell(4, 4, 2, 1)
+    props = cell.props.copy()
+    props[1, 1] = 0.5
+    with pytest.raises(mvpb.MvpbError) as ei:
+        ctx.cell(cell.phase, props)
+    assert ei.value.code == mvpb.E_INVALID
+    bad = cell.phase.copy()
+    bad[0, 0] = 7
+    with pytest.raises(mvpb.MvpbError):
+        ctx.cell(bad, cell.props)
+    plan = ctx.cell(cell.phase, cell.props).plan(1)
+    with pytest.raises(mvpb.MvpbError):
+        plan.solve(np.array([[np.nan, 0.0]]), 2)
+    with pytest.raises(mvpb.MvpbError):
+        plan.solve(np.array([[0.1, 0.0]]), 2 * 9 + 1)
+    assert plan.solve(np.zeros((0, 2)), 3).shape == (0, 3)
