@@ -57,11 +57,76 @@ def cpu_baseline(cell, M, Q, nb, omega_gpu, n_sample):
     ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, M, M, Q[idx], nb)
     dt = time.perf_counter() - t0
     err = band_error(omega_gpu[idx], ref)
-    return {
+    return ({
         "value": n_sample / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
         "sample": f"{n_sample} of the {Q.shape[0]} k-points of the same cell (incl. its subdomain integrals), "
                   f"NumPy/SciPy LAPACK, {dt:.1f} s",
-    }, err
+    }, err, idx, ref)
+
+
+def batched_error(cfg, om_batch, n_cells=4, n_k=3):
+    """Oracle check of a few (small-cutoff) cells of the batched workload."""
+    from oracle import mixed_oracle as mo
+    from oracle.compare import band_error
+    order = sorted(range(len(cfg["cells"])), key=lambda i: cfg["cells"][i]["M"])[:n_cells]
+    kidx = np.linspace(0, cfg["Q"].shape[0] - 1, n_k).round().astype(int)
+    worst = 0.0
+    for i in order:
+        c = cfg["cells"][i]
+        ref, _ = mo.bands(c["cell"].phase, c["cell"].props, c["cell"].lattice, c["M"], c["M"],
+                          cfg["Q"][kidx], cfg["n_bands"])
+        worst = max(worst, band_error(om_batch[i][kidx], ref))
+    return worst
+
+
+def run_timed(fn, steps, warmup, mvpb):
+    for _ in range(warmup):
+        fn()
+    mvpb.device_synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    mvpb.device_synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def variant_mixed(mvpb, ctx, dcell, M, Q, nb, steps, warmup):
+    """Same cell and k list; FP32 structure factors, FP32 reduction to
+    tridiagonal form and back-transform, FP64 Rayleigh-Ritz."""
+    prec = mvpb.PREC_SF_FP32 | mvpb.PREC_EIG_FP32_RR64
+    out = {}
+
+    def step():
+        plan = dcell.plan(M, M, prec)
+        out["om"] = plan.solve(Q, nb)
+        plan.close()
+
+    dt = run_timed(step, steps, warmup, mvpb)
+    return {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt,
+            "precision": "SF fp32 (MFMA), reduction fp32, Rayleigh-Ritz fp64"}, out["om"]
+
+
+def variant_batched(mvpb, ctx, steps, warmup):
+    """256 seeded two-phase inclusion cells on 32x32, cutoff M uniform in 5..12
+    (2N = 242..1250), 40 k each, 10 bands, FP64: batched per-cell assembly and
+    all 10 240 (cell, k) items through one captured launch sequence per size class."""
+    from synth import config2
+    cfg = config2()
+    cells = [ctx.cell(c["cell"].phase, c["cell"].props, c["cell"].lattice) for c in cfg["cells"]]
+    Ms = [c["M"] for c in cfg["cells"]]
+    Q, nb = cfg["Q"], cfg["n_bands"]
+    out = {}
+
+    def step():
+        plans = ctx.plans(cells, Ms)
+        out["om"] = ctx.solve_batch(plans, [Q] * len(plans), nb)
+        for p in plans:
+            p.close()
+
+    dt = run_timed(step, steps, warmup, mvpb)
+    items = len(cells) * Q.shape[0]
+    return {"value": items / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt, "items": items,
+            "precision": "fp64"}, out["om"], cfg
 
 
 def main():
@@ -70,6 +135,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=6, help="k-points timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--no-variants", action="store_true", help="only the headline FP64 workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note",
@@ -123,6 +189,11 @@ def main():
                 "frac": None, "traffic": None, "avg_launch_ms": tot_ms / max(launches, 1), "launches": launches}
 
     omega = om_dev.to_numpy(np.float64, (Q.shape[0], nb))
+    variants = {}
+    om_mixed = om_batch = cfg2 = None
+    if not args.no_variants:
+        variants["mixed_1132_phase"], om_mixed = variant_mixed(mvpb, ctx, dcell, M, Q, nb, args.steps, args.warmup)
+        variants["batched_256_cells"], om_batch, cfg2 = variant_batched(mvpb, ctx, max(1, args.steps // 2), 1)
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -133,10 +204,17 @@ def main():
         "roofline": roof,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
     }
+    if variants:
+        out["variants"] = variants
     if args.cpu_sample > 0:
-        cb, err = cpu_baseline(cell, M, Q, nb, omega, args.cpu_sample)
+        cb, err, ref_idx, ref = cpu_baseline(cell, M, Q, nb, omega, args.cpu_sample)
         out["cpu_baseline"] = cb
         out["max_rel_freq_err_vs_oracle"] = err
+        if om_mixed is not None:
+            from oracle.compare import band_error
+            variants["mixed_1132_phase"]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om_mixed[ref_idx], ref)
+        if om_batch is not None:
+            variants["batched_256_cells"]["max_rel_freq_err_vs_fp64_oracle"] = batched_error(cfg2, om_batch)
     print(json.dumps(out), flush=True)
 
 

@@ -58,12 +58,16 @@ enum {
   MVPB_PROP_ISO_E_NU_RHO = 0 /* E [Pa], nu, rho [kg/m^3]; isotropic plane strain (Sec. 4) */
 };
 
-/* Precision of a plan. */
+/* Precision of a plan: bit flags.  The structure-factor contraction runs on
+ * the matrix cores (FP64 by default); at most one of SF_FP32 / SF_BF16 may be
+ * set.  EIG_FP32_RR64 may be combined with either. */
 enum {
-  MVPB_PREC_FP64 = 0,          /* everything in FP64 */
-  MVPB_PREC_SF_FP32 = 1,       /* structure-factor contraction in FP32 (FP32 accumulate) */
-  MVPB_PREC_SF_BF16 = 2,       /* structure-factor contraction in BF16 inputs, FP32 accumulate */
-  MVPB_PREC_EIG_FP32_RR64 = 4  /* FP32 tridiagonal eigensolve, FP64 Rayleigh-Ritz refinement */
+  MVPB_PREC_FP64 = 0,           /* everything in FP64 */
+  MVPB_PREC_SF_FP32 = 1,        /* structure factors: FP32 inputs, FP32 accumulate */
+  MVPB_PREC_SF_BF16 = 2,        /* structure factors: BF16 inputs, FP32 accumulate */
+  MVPB_PREC_EIG_FP32_RR64 = 4,  /* FP32 reduction to tridiagonal form and back-transform,
+                                   FP64 Rayleigh-Ritz refinement on the FP64 operator */
+  MVPB_PREC_SF_PLAIN64 = 8      /* structure factors by the scalar FP64 kernel (cross-check) */
 };
 
 /* Flags of mvpb_solve / mvpb_solve_batch. */
@@ -105,6 +109,12 @@ int mvpb_cell_destroy(mvpb_cell cell);
  * N = (2M1+1)(2M2+1) <= 4096.  Returns MVPB_E_NOT_PD if Phi or Omega is
  * not positive definite. */
 int mvpb_plan_create(mvpb_cell cell, int M1, int M2, int precision, mvpb_plan *out);
+/* Plans for n cells of one context at once (same precision): cells with
+ * equal cutoffs share batched launches for the factorisations and the
+ * coefficient GEMMs.  out[i] receives the plan of cells[i]; on error no plan
+ * is returned (MVPB_E_NOT_PD names the failing cell index). */
+int mvpb_plan_create_batch(mvpb_ctx ctx, int n, const mvpb_cell *cells, const int *M1, const int *M2,
+                           int precision, mvpb_plan *out);
 /* n_u = 2N displacement unknowns, n_s = 3N stress unknowns (Sec. 4.1). */
 int mvpb_plan_dofs(mvpb_plan plan, int *n_u, int *n_s);
 int mvpb_plan_destroy(mvpb_plan plan);

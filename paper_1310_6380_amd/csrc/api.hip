@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -77,8 +78,8 @@ struct mvpb_ctx_s {
   DevBuf ws;          // per-solve workspace (grow-only)
   DevBuf items;       // item table
   DevBuf scratch;     // small host-visible results staging
-  hipGraphExec_t graph = nullptr;
-  std::string graph_key;
+  std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences by batch signature
+  std::vector<EigItem> host_items;                // staging of the item table (kept alive for async copies)
   Profiler prof;
   int children = 0;     // live cells and plans
   bool closing = false; // mvpb_ctx_destroy called while children were alive
@@ -87,7 +88,8 @@ struct mvpb_ctx_s {
 static void ctx_free(mvpb_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
   c->ws.release();
   c->items.release();
   c->scratch.release();
@@ -261,15 +263,26 @@ extern "C" int mvpb_cell_destroy(mvpb_cell c) {
 // ---------------------------------------------------------------------------
 static int run_structure_factors(mvpb_cell c, int M1, int M2, int precision, DevBuf &X, DevBuf &F) {
   const int nm = 4 * M1 + 1, nq = 4 * M2 + 1;
-  HIP_TRY(X.reserve(sizeof(cd) * 4 * (size_t)std::max(c->nx, c->ny) * std::max(nm, nq)));
+  const size_t plain = sizeof(cd) * 4 * (size_t)std::max(c->nx, c->ny) * std::max(nm, nq);
+  const size_t mfma = sizeof(double) * 8 * (size_t)c->nx * nq;
+  HIP_TRY(X.reserve(std::max(plain, mfma)));
   HIP_TRY(F.reserve(sizeof(cd) * 4 * (size_t)nm * nq));
   hipStream_t st = c->ctx->stream;
-  if (precision == MVPB_PREC_FP64 || precision == MVPB_PREC_EIG_FP32_RR64) {
+  if (precision & MVPB_PREC_SF_PLAIN64) {
     HIP_TRY(launch_structure_factors_f64(c->phase.as<int32_t>(), c->wtab.as<double>(), c->nx, c->ny, M1, M2,
                                          c->area, X.as<cd>(), F.as<cd>(), st));
   } else {
-    return set_err(MVPB_E_UNSUPPORTED, "precision %d not implemented for structure factors", precision);
+    const int sf = precision & 3;  // 0: FP64, 1: FP32, 2: BF16 matrix-core contraction
+    HIP_TRY(launch_structure_factors_mfma(sf, c->phase.as<int32_t>(), c->wtab.as<double>(), c->nx, c->ny, M1, M2,
+                                          c->area, X.as<double>(), F.as<cd>(), st));
   }
+  return MVPB_OK;
+}
+
+static int check_precision(int precision) {
+  const int sf = precision & 3;
+  if ((precision & ~15) || sf == 3 || ((precision & MVPB_PREC_SF_PLAIN64) && sf))
+    return set_err(MVPB_E_INVALID, "bad precision flags %d", precision);
   return MVPB_OK;
 }
 
@@ -283,6 +296,8 @@ static int check_cutoff(int M1, int M2) {
 extern "C" int mvpb_structure_factors(mvpb_cell c, int M1, int M2, int precision, double *F) {
   if (!c || !F) return set_err(MVPB_E_INVALID, "NULL argument");
   int rc = check_cutoff(M1, M2);
+  if (rc) return rc;
+  rc = check_precision(precision);
   if (rc) return rc;
   HIP_TRY(hipSetDevice(c->ctx->device));
   ProfBind pb(c->ctx);
@@ -298,125 +313,204 @@ extern "C" int mvpb_structure_factors(mvpb_cell c, int M1, int M2, int precision
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
-extern "C" int mvpb_plan_create(mvpb_cell c, int M1, int M2, int precision, mvpb_plan *out) {
-  if (!c || !out) return set_err(MVPB_E_INVALID, "NULL argument");
-  int rc = check_cutoff(M1, M2);
-  if (rc) return rc;
-  if (precision != MVPB_PREC_FP64)
-    return set_err(MVPB_E_UNSUPPORTED, "precision %d not implemented", precision);
-  mvpb_ctx ctx = c->ctx;
-  HIP_TRY(hipSetDevice(ctx->device));
-  ProfBind pb(ctx);
+// Build the plans of g cells that share the cutoff (M1, M2): structure
+// factors and Toeplitz scatter per cell, then one factorisation launch for
+// all 3g matrices and two batched GEMM launches.  On error every plan built
+// here is released and none is returned.
+static int build_plan_group(mvpb_ctx ctx, const mvpb_cell *cells, int g, int M1, int M2, int precision,
+                            mvpb_plan *out, int index_base) {
   hipStream_t st = ctx->stream;
   const int N = (2 * M1 + 1) * (2 * M2 + 1);
   const size_t NN = (size_t)N * N;
+  const int nm = 4 * M1 + 1, nq = 4 * M2 + 1;
+  const size_t fsz = (size_t)4 * nm * nq;
 
-  DevBuf X, F;
-  rc = run_structure_factors(c, M1, M2, precision, X, F);
-  if (rc) return rc;
-
-  // Sigma = T(d11+d12), Delta = T(d11-d12), R = T(rho); their inverse factors
-  DevBuf mats, linv, stat, ptrs, gvec;
-  HIP_TRY(mats.alloc(sizeof(cd) * 3 * NN));
-  HIP_TRY(linv.alloc(sizeof(cd) * 3 * NN));
-  HIP_TRY(stat.alloc(sizeof(int) * 3));
-  cd *Tm = mats.as<cd>();
-  cd *Li = linv.as<cd>();
-  HIP_TRY(launch_toeplitz_scatter(F.as<cd>(), M1, M2, N, Tm, Tm + NN, Tm + 2 * NN, st));
-
-  // pointer tables: [0..2] potrf inputs, [3..5] inverses, then GEMM tables
+  DevBuf X, F1, F, mats, linv, stat, ptrs, gvec, P, Xp;
+  HIP_TRY(F.alloc(sizeof(cd) * fsz * g));
+  HIP_TRY(mats.alloc(sizeof(cd) * 3 * NN * g));
+  HIP_TRY(linv.alloc(sizeof(cd) * 3 * NN * g));
+  HIP_TRY(stat.alloc(sizeof(int) * 3 * g));
+  HIP_TRY(P.alloc(sizeof(cd) * 6 * NN * g));
+  HIP_TRY(Xp.alloc(sizeof(cd) * 18 * NN * g));
+  cd *Tm = mats.as<cd>(), *Li = linv.as<cd>(), *Pm = P.as<cd>(), *Xm = Xp.as<cd>();
+  // structure factors and Sigma = T(d11+d12), Delta = T(d11-d12), R = T(rho)
+  for (int c = 0; c < g; ++c) {
+    int rc = run_structure_factors(cells[c], M1, M2, precision, X, F1);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(F.as<cd>() + c * fsz, F1.p, sizeof(cd) * fsz, hipMemcpyDeviceToDevice, st));
+    cd *Tc = Tm + 3 * NN * c;
+    HIP_TRY(launch_toeplitz_scatter(F.as<cd>() + c * fsz, M1, M2, N, Tc, Tc + NN, Tc + 2 * NN, st));
+  }
+  // G_l vectors per cell: G_0 = 1, G_l = 2 pi (T n)_l at Q = 0
+  std::vector<double> gv(3 * (size_t)N * g);
+  for (int c = 0; c < g; ++c)
+    for (int a = -M1; a <= M1; ++a)
+      for (int b = -M2; b <= M2; ++b) {
+        const int r = (a + M1) * (2 * M2 + 1) + (b + M2);
+        double *gc = gv.data() + 3 * (size_t)N * c;
+        gc[r] = 1.0;
+        gc[N + r] = 2.0 * M_PI * (cells[c]->T[0] * a + cells[c]->T[1] * b);
+        gc[2 * N + r] = 2.0 * M_PI * (cells[c]->T[2] * a + cells[c]->T[3] * b);
+      }
+  HIP_TRY(gvec.alloc(sizeof(double) * gv.size()));
+  HIP_TRY(hipMemcpyAsync(gvec.p, gv.data(), sizeof(double) * gv.size(), hipMemcpyHostToDevice, st));
+  // pointer tables
   std::vector<void *> hp;
-  for (int i = 0; i < 3; ++i) hp.push_back(Tm + i * NN);
-  for (int i = 0; i < 3; ++i) hp.push_back(Li + i * NN);
-  // G_l vectors: G_0 = 1, G_l = 2 pi (T n)_l at Q = 0
-  std::vector<double> g(3 * (size_t)N);
-  for (int a = -M1; a <= M1; ++a)
-    for (int b = -M2; b <= M2; ++b) {
-      const int r = (a + M1) * (2 * M2 + 1) + (b + M2);
-      g[r] = 1.0;
-      g[N + r] = 2.0 * M_PI * (c->T[0] * a + c->T[1] * b);
-      g[2 * N + r] = 2.0 * M_PI * (c->T[2] * a + c->T[3] * b);
-    }
-  HIP_TRY(gvec.alloc(sizeof(double) * g.size()));
-  HIP_TRY(hipMemcpyAsync(gvec.p, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice, st));
-
-  DevBuf P, Xp;
-  HIP_TRY(P.alloc(sizeof(cd) * 6 * NN));
-  HIP_TRY(Xp.alloc(sizeof(cd) * 18 * NN));
-  cd *Pm = P.as<cd>();
-  cd *Xm = Xp.as<cd>();
+  for (int c = 0; c < g; ++c)
+    for (int i = 0; i < 3; ++i) hp.push_back(Tm + (3 * c + i) * NN);
+  const size_t o_inv = hp.size();
+  for (int c = 0; c < g; ++c)
+    for (int i = 0; i < 3; ++i) hp.push_back(Li + (3 * c + i) * NN);
   // P_{x,l} = L_R^-1 diag(G_l) L_x^-H   (x = 0: Sigma, 1: Delta)
   const size_t o_pA = hp.size();
-  for (int x = 0; x < 2; ++x)
-    for (int l = 0; l < 3; ++l) hp.push_back(Li + 2 * NN);
+  for (int c = 0; c < g; ++c)
+    for (int x = 0; x < 2; ++x)
+      for (int l = 0; l < 3; ++l) hp.push_back(Li + (3 * c + 2) * NN);
   const size_t o_pB = hp.size();
-  for (int x = 0; x < 2; ++x)
-    for (int l = 0; l < 3; ++l) hp.push_back(Li + x * NN);
+  for (int c = 0; c < g; ++c)
+    for (int x = 0; x < 2; ++x)
+      for (int l = 0; l < 3; ++l) hp.push_back(Li + (3 * c + x) * NN);
   const size_t o_pC = hp.size();
-  for (int x = 0; x < 2; ++x)
-    for (int l = 0; l < 3; ++l) hp.push_back(Pm + (x * 3 + l) * NN);
+  for (int c = 0; c < g; ++c)
+    for (int x = 0; x < 2; ++x)
+      for (int l = 0; l < 3; ++l) hp.push_back(Pm + (6 * c + x * 3 + l) * NN);
   const size_t o_pS = hp.size();
-  for (int x = 0; x < 2; ++x)
-    for (int l = 0; l < 3; ++l) hp.push_back(gvec.as<double>() + l * N);
+  for (int c = 0; c < g; ++c)
+    for (int x = 0; x < 2; ++x)
+      for (int l = 0; l < 3; ++l) hp.push_back(gvec.as<double>() + 3 * (size_t)N * c + l * N);
   // X_{x,l,m} = P_{x,l} P_{x,m}^H
   const size_t o_xA = hp.size();
-  for (int x = 0; x < 2; ++x)
-    for (int l = 0; l < 3; ++l)
-      for (int m = 0; m < 3; ++m) hp.push_back(Pm + (x * 3 + l) * NN);
+  for (int c = 0; c < g; ++c)
+    for (int x = 0; x < 2; ++x)
+      for (int l = 0; l < 3; ++l)
+        for (int m = 0; m < 3; ++m) hp.push_back(Pm + (6 * c + x * 3 + l) * NN);
   const size_t o_xB = hp.size();
-  for (int x = 0; x < 2; ++x)
-    for (int l = 0; l < 3; ++l)
-      for (int m = 0; m < 3; ++m) hp.push_back(Pm + (x * 3 + m) * NN);
+  for (int c = 0; c < g; ++c)
+    for (int x = 0; x < 2; ++x)
+      for (int l = 0; l < 3; ++l)
+        for (int m = 0; m < 3; ++m) hp.push_back(Pm + (6 * c + x * 3 + m) * NN);
   const size_t o_xC = hp.size();
-  for (int x = 0; x < 2; ++x)
-    for (int l = 0; l < 3; ++l)
-      for (int m = 0; m < 3; ++m) hp.push_back(Xm + (x * 9 + l * 3 + m) * NN);
+  for (int c = 0; c < g; ++c)
+    for (int x = 0; x < 2; ++x)
+      for (int l = 0; l < 3; ++l)
+        for (int m = 0; m < 3; ++m) hp.push_back(Xm + (18 * c + x * 9 + l * 3 + m) * NN);
   HIP_TRY(ptrs.alloc(sizeof(void *) * hp.size()));
   HIP_TRY(hipMemcpyAsync(ptrs.p, hp.data(), sizeof(void *) * hp.size(), hipMemcpyHostToDevice, st));
   void **dp = ptrs.as<void *>();
 
-  HIP_TRY(launch_potrf_trtri((cd *const *)dp, (cd *const *)(dp + 3), stat.as<int>(), 3, N, st));
-  int hstat[3] = {0, 0, 0};
-  HIP_TRY(hipMemcpyAsync(hstat, stat.p, sizeof hstat, hipMemcpyDeviceToHost, st));
+  HIP_TRY(launch_potrf_trtri((cd *const *)dp, (cd *const *)(dp + o_inv), stat.as<int>(), 3 * g, N, st));
+  std::vector<int> hstat(3 * g, 0);
+  HIP_TRY(hipMemcpyAsync(hstat.data(), stat.p, sizeof(int) * 3 * g, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const char *names[3] = {"compliance block Phi(d11+d12)", "compliance block Phi(d11-d12)", "density matrix Omega"};
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 3 * g; ++i)
     if (hstat[i])
-      return set_err(MVPB_E_NOT_PD, "%s is not positive definite (pivot %d)", names[i], hstat[i] - 1);
-
+      return set_err(MVPB_E_NOT_PD, "cell %d: %s is not positive definite (pivot %d)", index_base + i / 3,
+                     names[i % 3], hstat[i] - 1);
   {
     GemmBatch bt{(const cd *const *)(dp + o_pA), (const cd *const *)(dp + o_pB), (cd *const *)(dp + o_pC),
                  (const double *const *)(dp + o_pS), N, N, N};
-    HIP_TRY(launch_zgemm(OP_N, OP_C, N, N, N, mk(1.0, 0.0), bt, mk(0.0, 0.0), 6, st));
+    HIP_TRY(launch_zgemm(OP_N, OP_C, N, N, N, mk(1.0, 0.0), bt, mk(0.0, 0.0), 6 * g, st));
   }
   {
     GemmBatch bt{(const cd *const *)(dp + o_xA), (const cd *const *)(dp + o_xB), (cd *const *)(dp + o_xC),
                  nullptr, N, N, N};
-    HIP_TRY(launch_zgemm(OP_N, OP_C, N, N, N, mk(1.0, 0.0), bt, mk(0.0, 0.0), 18, st));
+    HIP_TRY(launch_zgemm(OP_N, OP_C, N, N, N, mk(1.0, 0.0), bt, mk(0.0, 0.0), 18 * g, st));
   }
-  mvpb_plan pl = new mvpb_plan_s();
-  pl->ctx = ctx;
-  pl->M1 = M1;
-  pl->M2 = M2;
-  pl->N = N;
-  pl->prec = precision;
-  memcpy(pl->T, c->T, sizeof pl->T);
-  pl->area = c->area;
-  hipError_t e = pl->coef.alloc(sizeof(cd) * 15 * NN);
-  if (e == hipSuccess) e = pl->linvR.alloc(sizeof(cd) * NN);
-  if (e != hipSuccess) {
-    delete pl;
-    return set_err(MVPB_E_NOMEM, "plan buffers: %s", hipGetErrorString(e));
+  std::vector<mvpb_plan> made;
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < g && e == hipSuccess; ++c) {
+    mvpb_plan pl = new mvpb_plan_s();
+    pl->ctx = ctx;
+    pl->M1 = M1;
+    pl->M2 = M2;
+    pl->N = N;
+    pl->prec = precision;
+    memcpy(pl->T, cells[c]->T, sizeof pl->T);
+    pl->area = cells[c]->area;
+    made.push_back(pl);
+    e = pl->coef.alloc(sizeof(cd) * 15 * NN);
+    if (e == hipSuccess) e = pl->linvR.alloc(sizeof(cd) * NN);
+    if (e == hipSuccess) e = launch_combine(Xm + 18 * NN * c, N, 0.5 * pl->area * pl->area, pl->coef.as<cd>(), st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pl->linvR.p, Li + (3 * c + 2) * NN, sizeof(cd) * NN, hipMemcpyDeviceToDevice, st);
   }
-  e = launch_combine(Xm, N, 0.5 * c->area * c->area, pl->coef.as<cd>(), st);
-  if (e == hipSuccess) e = hipMemcpyAsync(pl->linvR.p, Li + 2 * NN, sizeof(cd) * NN, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
-    delete pl;
-    return set_err(MVPB_E_DEVICE, "plan build: %s", hipGetErrorString(e));
+    for (mvpb_plan pl : made) delete pl;
+    return set_err(MVPB_E_NOMEM, "plan build: %s", hipGetErrorString(e));
   }
-  ctx->children++;
+  for (int c = 0; c < g; ++c) {
+    ctx->children++;
+    out[c] = made[c];
+  }
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_plan_create(mvpb_cell c, int M1, int M2, int precision, mvpb_plan *out) {
+  if (!c || !out) return set_err(MVPB_E_INVALID, "NULL argument");
+  int rc = check_cutoff(M1, M2);
+  if (rc) return rc;
+  rc = check_precision(precision);
+  if (rc) return rc;
+  mvpb_ctx ctx = c->ctx;
+  if (ctx->closing) return set_err(MVPB_E_INVALID, "context has been destroyed");
+  HIP_TRY(hipSetDevice(ctx->device));
+  ProfBind pb(ctx);
+  mvpb_plan pl = nullptr;
+  rc = build_plan_group(ctx, &c, 1, M1, M2, precision, &pl, 0);
+  if (rc) return rc;
   *out = pl;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_plan_create_batch(mvpb_ctx ctx, int n, const mvpb_cell *cells, const int *M1, const int *M2,
+                                      int precision, mvpb_plan *out) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && (!cells || !M1 || !M2 || !out))) return set_err(MVPB_E_INVALID, "NULL argument");
+  rc = check_precision(precision);
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i) {
+    if (!cells[i] || cells[i]->ctx != ctx) return set_err(MVPB_E_INVALID, "cell %d missing or from another context", i);
+    rc = check_cutoff(M1[i], M2[i]);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  ProfBind pb(ctx);
+  // group by cutoff, keep each group's temporaries under ~8 GB
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return M1[a] != M1[b] ? M1[a] < M1[b] : M2[a] < M2[b];
+  });
+  std::vector<mvpb_plan> res(n, nullptr);
+  auto release = [&]() {
+    for (mvpb_plan p : res)
+      if (p) mvpb_plan_destroy(p);
+  };
+  size_t i0 = 0;
+  while (i0 < (size_t)n) {
+    size_t i1 = i0;
+    while (i1 < (size_t)n && M1[order[i1]] == M1[order[i0]] && M2[order[i1]] == M2[order[i0]]) ++i1;
+    const size_t N = (size_t)(2 * M1[order[i0]] + 1) * (2 * M2[order[i0]] + 1);
+    const size_t per = 30 * N * N * sizeof(cd) + 64 * N * sizeof(cd);
+    const size_t gmax = std::max<size_t>(1, ((size_t)8 << 30) / per);
+    for (size_t s = i0; s < i1; s += gmax) {
+      const size_t g = std::min(gmax, i1 - s);
+      std::vector<mvpb_cell> cs(g);
+      std::vector<mvpb_plan> ps(g, nullptr);
+      for (size_t k = 0; k < g; ++k) cs[k] = cells[order[s + k]];
+      rc = build_plan_group(ctx, cs.data(), (int)g, M1[order[s]], M2[order[s]], precision, ps.data(), (int)s);
+      if (rc) {
+        release();
+        return rc;
+      }
+      for (size_t k = 0; k < g; ++k) res[order[s + k]] = ps[k];
+    }
+    i0 = i1;
+  }
+  for (int i = 0; i < n; ++i) out[i] = res[i];
   return MVPB_OK;
 }
 
@@ -442,20 +536,25 @@ extern "C" int mvpb_plan_destroy(mvpb_plan p) {
 // ---------------------------------------------------------------------------
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static size_t item_bytes(int n, int nb) {
+static size_t item_bytes(int n, int nb, bool fp32) {
+  const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
   size_t s = 0;
-  s += align256(sizeof(cd) * (size_t)n * n) * 2;          // A, Ak
-  s += align256(sizeof(cd) * (size_t)n * PANEL);          // W
-  s += align256(sizeof(double) * n) * 2;                  // d, e
-  s += align256(sizeof(cd) * n);                          // tau
-  s += align256(sizeof(double) * (size_t)n * nb);         // X
-  s += align256(sizeof(double) * (size_t)5 * n * nb);     // lu
-  s += align256(sizeof(double) * nb) * 3;                 // lam_t, lam, omega
-  s += align256(sizeof(cd) * (size_t)n * nb) * 2;         // Y, Z
+  s += align256(es * (size_t)n * n);                       // A
+  s += align256(sizeof(cd) * (size_t)n * n);               // Ak
+  s += align256(es * (size_t)n * PANEL);                   // W
+  s += align256(es * (size_t)n * 2 * PANEL_SLOTS);         // Yw
+  s += align256(sizeof(double) * n) * 2;                   // d, e
+  s += align256(es * n);                                   // tau
+  s += align256(sizeof(double) * (size_t)n * nb);          // X
+  s += align256(sizeof(double) * (size_t)5 * n * nb);      // lu
+  s += align256(sizeof(double) * nb) * 3;                  // lam_t, lam, omega
+  s += align256(sizeof(cd) * (size_t)n * nb) * 2;          // Y, Z
+  if (fp32) s += align256(sizeof(cf) * (size_t)n * nb);    // Yb
   return s;
 }
 
-static EigItem carve_item(char *base, int n, int nb) {
+static EigItem carve_item(char *base, int n, int nb, bool fp32) {
+  const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
   EigItem it{};
   size_t o = 0;
   auto take = [&](size_t b) {
@@ -463,12 +562,13 @@ static EigItem carve_item(char *base, int n, int nb) {
     o += align256(b);
     return p;
   };
-  it.A = (cd *)take(sizeof(cd) * (size_t)n * n);
+  it.A = take(es * (size_t)n * n);
   it.Ak = (cd *)take(sizeof(cd) * (size_t)n * n);
-  it.W = (cd *)take(sizeof(cd) * (size_t)n * PANEL);
+  it.W = take(es * (size_t)n * PANEL);
+  it.Yw = take(es * (size_t)n * 2 * PANEL_SLOTS);
   it.d = (double *)take(sizeof(double) * n);
   it.e = (double *)take(sizeof(double) * n);
-  it.tau = (cd *)take(sizeof(cd) * n);
+  it.tau = take(es * n);
   it.X = (double *)take(sizeof(double) * (size_t)n * nb);
   it.lu = (double *)take(sizeof(double) * (size_t)5 * n * nb);
   it.lam_t = (double *)take(sizeof(double) * nb);
@@ -476,6 +576,7 @@ static EigItem carve_item(char *base, int n, int nb) {
   it.omega = (double *)take(sizeof(double) * nb);
   it.Y = (cd *)take(sizeof(cd) * (size_t)n * nb);
   it.Z = (cd *)take(sizeof(cd) * (size_t)n * nb);
+  it.Yb = fp32 ? (void *)take(sizeof(cf) * (size_t)n * nb) : (void *)it.Y;
   return it;
 }
 
@@ -530,6 +631,8 @@ struct Job {
 
 static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double *omega_dev, double *U_dev,
                      bool use_graph, const std::string &graph_key) {
+  // the reduction precision is shared by every item of one launch sequence
+  const bool fp32 = jobs.empty() ? false : (jobs[0].plan->prec & MVPB_PREC_EIG_FP32_RR64) != 0;
   hipStream_t st = ctx->stream;
   const int n_items = (int)jobs.size();
   if (n_items == 0) return MVPB_OK;
@@ -537,21 +640,30 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   int n_max = 0;
   for (const Job &j : jobs) {
     const int n = 2 * j.plan->N;
-    total += item_bytes(n, nb);
+    total += item_bytes(n, nb, fp32);
     n_max = std::max(n_max, n);
   }
   if (ctx->cap && total > ctx->cap)
     return set_err(MVPB_E_NOMEM, "workspace %zu bytes exceeds the cap of %zu bytes", total, ctx->cap);
   const bool realloc = total > ctx->ws.bytes || sizeof(EigItem) * n_items > ctx->items.bytes;
+  if (realloc) {
+    // captured graphs point into the old buffers
+    HIP_TRY(hipStreamSynchronize(st));
+    for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+  }
   HIP_TRY(ctx->ws.reserve(total));
   HIP_TRY(ctx->items.reserve(sizeof(EigItem) * n_items));
-  std::vector<EigItem> items(n_items);
+  // the staging vector may still feed an earlier asynchronous copy
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<EigItem> &items = ctx->host_items;
+  items.assign(n_items, EigItem{});
   size_t off = 0;
   for (int i = 0; i < n_items; ++i) {
     const Job &j = jobs[i];
     const int n = 2 * j.plan->N;
-    EigItem it = carve_item(ctx->ws.as<char>() + off, n, nb);
-    off += item_bytes(n, nb);
+    EigItem it = carve_item(ctx->ws.as<char>() + off, n, nb, fp32);
+    off += item_bytes(n, nb, fp32);
     it.coef = j.plan->coef.as<cd>();
     it.N = j.plan->N;
     it.nb = nb;
@@ -564,19 +676,17 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   const EigItem *d_items = ctx->items.as<EigItem>();
 
   auto enqueue = [&]() -> hipError_t {
-    hipError_t e = launch_form_operator(d_items, n_items, n_max, st);
-    if (e == hipSuccess) e = launch_hetrd(d_items, n_items, n_max, st);
+    hipError_t e = launch_form_operator(d_items, n_items, n_max, fp32, st);
+    if (e == hipSuccess) e = launch_hetrd(d_items, n_items, n_max, fp32, st);
     if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, st);
-    if (e == hipSuccess) e = launch_backtransform(d_items, n_items, st);
+    if (e == hipSuccess) e = launch_backtransform(d_items, n_items, fp32, st);
     if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, st);
     return e;
   };
   if (use_graph) {
-    if (realloc || ctx->graph_key != graph_key || !ctx->graph) {
-      if (ctx->graph) {
-        (void)hipGraphExecDestroy(ctx->graph);
-        ctx->graph = nullptr;
-      }
+    auto found = ctx->graphs.find(graph_key);
+    hipGraphExec_t exec = nullptr;
+    if (found == ctx->graphs.end()) {
       hipGraph_t g;
       HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       Profiler *saved = t_prof;
@@ -586,12 +696,14 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
       hipError_t e2 = hipStreamEndCapture(st, &g);
       if (e != hipSuccess) return set_err(MVPB_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
       if (e2 != hipSuccess) return set_err(MVPB_E_DEVICE, "graph capture end: %s", hipGetErrorString(e2));
-      e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+      e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return set_err(MVPB_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-      ctx->graph_key = graph_key;
+      ctx->graphs[graph_key] = exec;
+    } else {
+      exec = found->second;
     }
-    HIP_TRY(hipGraphLaunch(ctx->graph, st));
+    HIP_TRY(hipGraphLaunch(exec, st));
   } else {
     HIP_TRY(enqueue());
   }
@@ -660,7 +772,7 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
   const int n = 2 * p->N;
   // chunk the k list so that the workspace stays within the cap
   int chunk = n_k;
-  const size_t per = item_bytes(n, n_bands);
+  const size_t per = item_bytes(n, n_bands, (p->prec & MVPB_PREC_EIG_FP32_RR64) != 0);
   const size_t budget = ctx->cap ? ctx->cap : (size_t)32 << 30;
   if (per > budget) return set_err(MVPB_E_NOMEM, "one item needs %zu bytes, cap is %zu", per, budget);
   chunk = (int)std::min<size_t>((size_t)n_k, budget / per);
@@ -703,29 +815,60 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
   if (n_bands < 1 || n_bands > RR_MAX_BANDS) return set_err(MVPB_E_INVALID, "n_bands = %d out of range", n_bands);
   std::vector<Job> jobs;
   std::vector<size_t> base(n_plans + 1, 0);
-  std::string key = "b" + std::to_string(n_bands);
+  // signature of the batch (plans, k lists, bands) for the graph cache
+  uint64_t hsh = 1469598103934665603ull;
+  auto mix = [&](const void *p, size_t len) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < len; ++i) hsh = (hsh ^ b[i]) * 1099511628211ull;
+  };
+  mix(&n_bands, sizeof n_bands);
   for (int i = 0; i < n_plans; ++i) {
     if (!plans[i] || plans[i]->ctx != ctx) return set_err(MVPB_E_INVALID, "plan %d missing or from another context", i);
     if (n_k[i] < 0 || (n_k[i] > 0 && (!Q[i] || !omega[i]))) return set_err(MVPB_E_INVALID, "plan %d: bad k list", i);
     if (2 * plans[i]->N < n_bands) return set_err(MVPB_E_INVALID, "plan %d: n_bands > 2N", i);
+    if ((plans[i]->prec & MVPB_PREC_EIG_FP32_RR64) != (plans[0]->prec & MVPB_PREC_EIG_FP32_RR64))
+      return set_err(MVPB_E_INVALID, "plan %d: all plans of a batch need the same eigensolver precision", i);
     if (!q_ok(Q[i], n_k[i])) return set_err(MVPB_E_INVALID, "plan %d: non-finite Bloch vector", i);
     base[i + 1] = base[i] + n_k[i];
-    char tmp[64];
-    snprintf(tmp, sizeof tmp, ":%p/%d", (void *)plans[i], n_k[i]);
-    key += tmp;
+    mix(&plans[i], sizeof(void *));
+    mix(&n_k[i], sizeof(int));
+    if (n_k[i] > 0) mix(Q[i], sizeof(double) * 2 * n_k[i]);
     for (int t = 0; t < n_k[i]; ++t)
       jobs.push_back(Job{plans[i], Q[i][2 * t], Q[i][2 * t + 1], (int)(base[i] + t)});
   }
+  char keybuf[32];
+  snprintf(keybuf, sizeof keybuf, "%016llx", (unsigned long long)hsh);
+  const std::string key = keybuf;
   if (jobs.empty()) return MVPB_OK;
-  for (const Job &j : jobs) { char tmp[48]; snprintf(tmp, sizeof tmp, "%a,%a;", j.Q1, j.Q2); key += tmp; }
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
-  // largest items first so the longest work starts earliest
+  // largest items first so the longest work starts earliest; chunks of
+  // similar size share one launch sequence (captured once, replayed)
   std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.plan->N > b.plan->N; });
+  const bool fp32 = (jobs[0].plan->prec & MVPB_PREC_EIG_FP32_RR64) != 0;
+  const size_t budget = ctx->cap ? ctx->cap : (size_t)24 << 30;
   DevBuf om;
   HIP_TRY(om.alloc(sizeof(double) * base[n_plans] * n_bands));
-  rc = run_items(ctx, jobs, n_bands, om.as<double>(), nullptr, true, key);
-  if (rc) return rc;
+  size_t j0 = 0;
+  int chunk = 0;
+  while (j0 < jobs.size()) {
+    size_t j1 = j0, bytes = 0;
+    const int n0 = 2 * jobs[j0].plan->N;
+    while (j1 < jobs.size()) {
+      const size_t b = item_bytes(2 * jobs[j1].plan->N, n_bands, fp32);
+      // keep items of one chunk within a factor ~1.5 in order so that the
+      // launch sequence sized for the largest wastes little on the rest
+      if (j1 > j0 && (bytes + b > budget || 3 * jobs[j1].plan->N < n0)) break;
+      bytes += b;
+      ++j1;
+    }
+    if (bytes > budget) return set_err(MVPB_E_NOMEM, "one item needs %zu bytes, cap is %zu", bytes, budget);
+    std::vector<Job> part(jobs.begin() + j0, jobs.begin() + j1);
+    rc = run_items(ctx, part, n_bands, om.as<double>(), nullptr, true, key + "#" + std::to_string(chunk));
+    if (rc) return rc;
+    j0 = j1;
+    ++chunk;
+  }
   const bool dev = flags & MVPB_F_DEVICE_PTRS;
   for (int i = 0; i < n_plans; ++i) {
     if (n_k[i] == 0) continue;

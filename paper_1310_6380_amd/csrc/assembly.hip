@@ -105,6 +105,203 @@ hipError_t launch_structure_factors_f64(const int32_t *phase, const double *wtab
 }
 
 // ---------------------------------------------------------------------------
+// Structure factors on the matrix cores.  The same factored contraction as
+// above, F_w = S o (E1 . W_w . E2^T), as two real/complex GEMM passes tiled
+// 16 x 16 per wavefront:
+//   pass A: X_w = W_w . E2^T          (nx x ny) . (ny x nq), E2 = cos + i sin
+//   pass B: F_w = S o (E1 . X_w)      (nm x nx) . (nx x nq), complex
+// Precision P: 0 = FP64 inputs / FP64 accumulate (v_mfma_f64_16x16x4f64),
+// 1 = FP32 inputs / FP32 accumulate (v_mfma_f32_16x16x4f32), 2 = BF16 inputs
+// / FP32 accumulate (v_mfma_f32_16x16x16bf16_1k).  Trig factors are computed
+// in FP64 with exact argument reduction and rounded to the input type.
+// Operand layout (16 x 16 x K): lane l supplies A[l%16][k] and B[k][l%16]
+// for its K-slot, k = (l/16)*KPL + v; it receives D[row(l,v)][l%16] with
+// row = 4(l/16) + v for the FP32-accumulating forms and l/16 + 4v for FP64.
+// ---------------------------------------------------------------------------
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+template <int P>
+struct Mma;
+template <>
+struct Mma<0> {
+  typedef double acc;
+  typedef d4_t acc4;
+  static constexpr int KPL = 1;
+  MVPB_DEV static acc4 zero() { return acc4{0.0, 0.0, 0.0, 0.0}; }
+  MVPB_DEV static acc4 mma(const double (&a)[1], const double (&b)[1], acc4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+  }
+  MVPB_DEV static double round_in(double x) { return x; }
+  // output row of register v in this lane (FP64 16x16x4: rows interleave by 4)
+  MVPB_DEV static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct Mma<1> {
+  typedef float acc;
+  typedef f4_t acc4;
+  static constexpr int KPL = 1;
+  MVPB_DEV static acc4 zero() { return acc4{0.f, 0.f, 0.f, 0.f}; }
+  MVPB_DEV static acc4 mma(const double (&a)[1], const double (&b)[1], acc4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[0], (float)b[0], c, 0, 0, 0);
+  }
+  MVPB_DEV static double round_in(double x) { return (double)(float)x; }
+  MVPB_DEV static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+// round-to-nearest-even FP32 -> BF16 bits
+MVPB_DEV short bf16_bits(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+MVPB_DEV float bf16_value(short b) { return __uint_as_float(((unsigned)(unsigned short)b) << 16); }
+template <>
+struct Mma<2> {
+  typedef float acc;
+  typedef f4_t acc4;
+  static constexpr int KPL = 4;
+  MVPB_DEV static acc4 zero() { return acc4{0.f, 0.f, 0.f, 0.f}; }
+  MVPB_DEV static acc4 mma(const double (&a)[4], const double (&b)[4], acc4 c) {
+    s4_t av, bv;
+    av[0] = bf16_bits((float)a[0]); av[1] = bf16_bits((float)a[1]);
+    av[2] = bf16_bits((float)a[2]); av[3] = bf16_bits((float)a[3]);
+    bv[0] = bf16_bits((float)b[0]); bv[1] = bf16_bits((float)b[1]);
+    bv[2] = bf16_bits((float)b[2]); bv[3] = bf16_bits((float)b[3]);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+  }
+  MVPB_DEV static double round_in(double x) { return (double)bf16_value(bf16_bits((float)x)); }
+  MVPB_DEV static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+MVPB_DEV void twiddle(long num, int n, double *c, double *s) {
+  // exp(i pi num / n) with num reduced modulo 2n first
+  long t = num % (2L * n);
+  if (t < 0) t += 2L * n;
+  sincospi((double)t / (double)n, s, c);
+}
+
+// Pass A: one wavefront per (w, 16-row tile of i, 16-column tile of q).
+// X is stored in FP64 as re/im planes [4][nx][nq].
+template <int P>
+__global__ void __launch_bounds__(256) sf_mfma_pass_a(const int32_t *__restrict__ phase, const double *__restrict__ wtab,
+                                                      int nx, int ny, int M2, double *__restrict__ XR,
+                                                      double *__restrict__ XI) {
+  typedef Mma<P> T;
+  constexpr int K = 4 * T::KPL;
+  const int nq = 4 * M2 + 1;
+  const int lane = threadIdx.x & 63;
+  const int tiles_q = (nq + 15) / 16, tiles_i = (nx + 15) / 16;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= 4 * tiles_i * tiles_q) return;
+  const int w = tile / (tiles_i * tiles_q);
+  const int ti = (tile / tiles_q) % tiles_i, tq = tile % tiles_q;
+  const int i = ti * 16 + (lane & 15);       // A row of this lane
+  const int qc = tq * 16 + (lane & 15);      // B column of this lane
+  const int q = qc - 2 * M2;
+  typename T::acc4 accR = T::zero(), accI = T::zero();
+  for (int k0 = 0; k0 < ny; k0 += K) {
+    double a[T::KPL], bc[T::KPL], bs[T::KPL];
+#pragma unroll
+    for (int v = 0; v < T::KPL; ++v) {
+      const int j = k0 + (lane >> 4) * T::KPL + v;
+      a[v] = (i < nx && j < ny) ? wtab[phase[i * ny + j] * 4 + w] : 0.0;
+      double c = 0.0, s = 0.0;
+      if (qc < nq && j < ny) twiddle((long)q * (2 * j + 1), ny, &c, &s);
+      bc[v] = c;
+      bs[v] = s;
+    }
+    accR = T::mma(a, bc, accR);
+    accI = T::mma(a, bs, accI);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int io = ti * 16 + T::row(lane, v);
+    if (io < nx && qc < nq) {
+      const size_t o = ((size_t)w * nx + io) * nq + qc;
+      XR[o] = (double)accR[v];
+      XI[o] = (double)accI[v];
+    }
+  }
+}
+
+// Pass B: one wavefront per (w, 16-row tile of m, 16-column tile of q).
+template <int P>
+__global__ void __launch_bounds__(256) sf_mfma_pass_b(const double *__restrict__ XR, const double *__restrict__ XI,
+                                                      int nx, int ny, int M1, int M2, double area,
+                                                      cd *__restrict__ F) {
+  typedef Mma<P> T;
+  constexpr int K = 4 * T::KPL;
+  const int nm = 4 * M1 + 1, nq = 4 * M2 + 1;
+  const int lane = threadIdx.x & 63;
+  const int tiles_q = (nq + 15) / 16, tiles_m = (nm + 15) / 16;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= 4 * tiles_m * tiles_q) return;
+  const int w = tile / (tiles_m * tiles_q);
+  const int tm = (tile / tiles_q) % tiles_m, tq = tile % tiles_q;
+  const int mr = tm * 16 + (lane & 15);
+  const int m = mr - 2 * M1;
+  const int qc = tq * 16 + (lane & 15);
+  typename T::acc4 fr = T::zero(), fi = T::zero();
+  for (int k0 = 0; k0 < nx; k0 += K) {
+    double ec[T::KPL], es[T::KPL], ens[T::KPL], xr[T::KPL], xi[T::KPL];
+#pragma unroll
+    for (int v = 0; v < T::KPL; ++v) {
+      const int ii = k0 + (lane >> 4) * T::KPL + v;
+      double c = 0.0, s = 0.0;
+      if (mr < nm && ii < nx) twiddle((long)m * (2 * ii + 1), nx, &c, &s);
+      ec[v] = c;
+      es[v] = s;
+      ens[v] = -s;
+      const bool ok = ii < nx && qc < nq;
+      const size_t o = ((size_t)w * nx + ii) * nq + qc;
+      xr[v] = ok ? T::round_in(XR[o]) : 0.0;
+      xi[v] = ok ? T::round_in(XI[o]) : 0.0;
+    }
+    fr = T::mma(ec, xr, fr);
+    fr = T::mma(ens, xi, fr);
+    fi = T::mma(ec, xi, fi);
+    fi = T::mma(es, xr, fi);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int mo = tm * 16 + T::row(lane, v);
+    if (mo < nm && qc < nq) {
+      const int mm = mo - 2 * M1, qq = qc - 2 * M2;
+      const double sm = (mm == 0) ? 1.0 : sinpi((double)mm / nx) / (M_PI * (double)mm / nx);
+      const double sq = (qq == 0) ? 1.0 : sinpi((double)qq / ny) / (M_PI * (double)qq / ny);
+      const double sc = area / ((double)nx * ny) * sm * sq;
+      F[((size_t)w * nm + mo) * nq + qc] = mk(sc * (double)fr[v], sc * (double)fi[v]);
+    }
+  }
+}
+
+// X must hold 2 * 4 * nx * (4 M2 + 1) doubles.
+hipError_t launch_structure_factors_mfma(int prec, const int32_t *phase, const double *wtab, int nx, int ny, int M1,
+                                         int M2, double area, double *X, cd *F, hipStream_t st) {
+  const int nq = 4 * M2 + 1, nm = 4 * M1 + 1;
+  double *XR = X, *XI = X + (size_t)4 * nx * nq;
+  const int ta = 4 * ((nx + 15) / 16) * ((nq + 15) / 16);
+  const int tb = 4 * ((nm + 15) / 16) * ((nq + 15) / 16);
+  ProfScope ps(K_SF, st);
+  switch (prec) {
+    case 0:
+      hipLaunchKernelGGL(sf_mfma_pass_a<0>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
+      hipLaunchKernelGGL(sf_mfma_pass_b<0>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
+      break;
+    case 1:
+      hipLaunchKernelGGL(sf_mfma_pass_a<1>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
+      hipLaunchKernelGGL(sf_mfma_pass_b<1>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
+      break;
+    default:
+      hipLaunchKernelGGL(sf_mfma_pass_a<2>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
+      hipLaunchKernelGGL(sf_mfma_pass_b<2>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Toeplitz scatter: T_w[r, c] = F_w(n_c - n_r) for w = 0 (Sigma), 1 (Delta),
 // 2 (rho).  Column-major N x N outputs.  n_r = (alpha_r, beta_r) with
 // r = (alpha+M1)(2M2+1) + (beta+M2).
@@ -190,7 +387,7 @@ hipError_t launch_combine(const cd *Xp, int N, double s, cd *coef, hipStream_t s
 // copies are written: the working copy (overwritten by the reduction to
 // tridiagonal form) and the kept copy used by the Rayleigh-Ritz step.
 // ---------------------------------------------------------------------------
-template <typename Item>
+template <typename Item, typename R>
 __global__ void __launch_bounds__(256) form_operator(const Item *__restrict__ items, int tiles_max) {
   __shared__ cd tile[32][33];
   const Item it = items[blockIdx.y];
@@ -227,7 +424,7 @@ __global__ void __launch_bounds__(256) form_operator(const Item *__restrict__ it
       }
       if (r == c) v.im = 0.0;
       const size_t dst = (size_t)c * n + r;
-      it.A[dst] = v;
+      ((cx<R> *)it.A)[dst] = ccast<R>(v);
       it.Ak[dst] = v;
     }
     tile[lc][lr] = v;
@@ -239,17 +436,20 @@ __global__ void __launch_bounds__(256) form_operator(const Item *__restrict__ it
     if (r < n && c < n && r < c) {
       const cd v = conj(tile[lr][lc]);
       const size_t dst = (size_t)c * n + r;
-      it.A[dst] = v;
+      ((cx<R> *)it.A)[dst] = ccast<R>(v);
       it.Ak[dst] = v;
     }
   }
 }
 
-hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, hipStream_t st) {
+hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, bool fp32, hipStream_t st) {
   const int nt = (n_max + 31) / 32;
   const int tiles = nt * (nt + 1) / 2;
   ProfScope ps(K_FORM, st);
-  hipLaunchKernelGGL(form_operator<EigItem>, dim3(tiles, n_items), dim3(256), 0, st, items, tiles);
+  if (fp32)
+    hipLaunchKernelGGL((form_operator<EigItem, float>), dim3(tiles, n_items), dim3(256), 0, st, items, tiles);
+  else
+    hipLaunchKernelGGL((form_operator<EigItem, double>), dim3(tiles, n_items), dim3(256), 0, st, items, tiles);
   return hipGetLastError();
 }
 

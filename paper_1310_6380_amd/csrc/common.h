@@ -8,44 +8,73 @@
 #define MVPB_HD __host__ __device__ __forceinline__
 
 // ---------------------------------------------------------------------------
-// Complex double, interleaved (re, im), 16-byte aligned for dwordx4 access.
+// Complex numbers, interleaved (re, im); cx<double> is 16-byte aligned for
+// dwordx4 access.  cd = complex double, cf = complex float.
 // ---------------------------------------------------------------------------
-struct __align__(16) cd {
-  double re, im;
+template <typename R>
+struct __align__(2 * sizeof(R)) cx {
+  R re, im;
 };
+using cd = cx<double>;
+using cf = cx<float>;
 
-MVPB_HD cd mk(double r, double i) { cd z; z.re = r; z.im = i; return z; }
-MVPB_HD cd operator+(cd a, cd b) { return mk(a.re + b.re, a.im + b.im); }
-MVPB_HD cd operator-(cd a, cd b) { return mk(a.re - b.re, a.im - b.im); }
-MVPB_HD cd operator-(cd a) { return mk(-a.re, -a.im); }
-MVPB_HD cd operator*(cd a, cd b) { return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
-MVPB_HD cd operator*(double s, cd a) { return mk(s * a.re, s * a.im); }
-MVPB_HD cd operator*(cd a, double s) { return mk(s * a.re, s * a.im); }
-MVPB_HD cd conj(cd a) { return mk(a.re, -a.im); }
-MVPB_HD double abs2(cd a) { return a.re * a.re + a.im * a.im; }
+template <typename R>
+MVPB_HD cx<R> mkc(R r, R i) { cx<R> z; z.re = r; z.im = i; return z; }
+MVPB_HD cd mk(double r, double i) { return mkc<double>(r, i); }
+template <typename R>
+MVPB_HD cx<R> czero() { return mkc<R>(R(0), R(0)); }
+template <typename R>
+MVPB_HD cx<R> operator+(cx<R> a, cx<R> b) { return mkc<R>(a.re + b.re, a.im + b.im); }
+template <typename R>
+MVPB_HD cx<R> operator-(cx<R> a, cx<R> b) { return mkc<R>(a.re - b.re, a.im - b.im); }
+template <typename R>
+MVPB_HD cx<R> operator-(cx<R> a) { return mkc<R>(-a.re, -a.im); }
+template <typename R>
+MVPB_HD cx<R> operator*(cx<R> a, cx<R> b) {
+  return mkc<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R>
+MVPB_HD cx<R> operator*(R s, cx<R> a) { return mkc<R>(s * a.re, s * a.im); }
+template <typename R>
+MVPB_HD cx<R> operator*(cx<R> a, R s) { return mkc<R>(s * a.re, s * a.im); }
+template <typename R>
+MVPB_HD cx<R> conj(cx<R> a) { return mkc<R>(a.re, -a.im); }
+template <typename R>
+MVPB_HD R abs2(cx<R> a) { return a.re * a.re + a.im * a.im; }
 // a + b * c
-MVPB_HD cd cfma(cd b, cd c, cd a) {
-  return mk(fma(b.re, c.re, fma(-b.im, c.im, a.re)), fma(b.re, c.im, fma(b.im, c.re, a.im)));
+template <typename R>
+MVPB_HD cx<R> cfma(cx<R> b, cx<R> c, cx<R> a) {
+  return mkc<R>(fma(b.re, c.re, fma(-b.im, c.im, a.re)), fma(b.re, c.im, fma(b.im, c.re, a.im)));
 }
 // a + conj(b) * c
-MVPB_HD cd cfma_cj(cd b, cd c, cd a) {
-  return mk(fma(b.re, c.re, fma(b.im, c.im, a.re)), fma(b.re, c.im, fma(-b.im, c.re, a.im)));
+template <typename R>
+MVPB_HD cx<R> cfma_cj(cx<R> b, cx<R> c, cx<R> a) {
+  return mkc<R>(fma(b.re, c.re, fma(b.im, c.im, a.re)), fma(b.re, c.im, fma(-b.im, c.re, a.im)));
 }
-MVPB_HD cd cdiv(cd a, cd b) {
+template <typename R>
+MVPB_HD cx<R> cdiv(cx<R> a, cx<R> b) {
   // Smith's algorithm
   if (fabs(b.re) >= fabs(b.im)) {
-    double r = b.im / b.re, den = b.re + b.im * r;
-    return mk((a.re + a.im * r) / den, (a.im - a.re * r) / den);
+    R r = b.im / b.re, den = b.re + b.im * r;
+    return mkc<R>((a.re + a.im * r) / den, (a.im - a.re * r) / den);
   } else {
-    double r = b.re / b.im, den = b.re * r + b.im;
-    return mk((a.re * r + a.im) / den, (a.im * r - a.re) / den);
+    R r = b.re / b.im, den = b.re * r + b.im;
+    return mkc<R>((a.re * r + a.im) / den, (a.im * r - a.re) / den);
   }
 }
+// precision conversions
+template <typename To, typename From>
+MVPB_HD cx<To> ccast(cx<From> a) { return mkc<To>((To)a.re, (To)a.im); }
 
 // ---------------------------------------------------------------------------
 // Wavefront / block reductions (64-wide wavefronts).
 // ---------------------------------------------------------------------------
 MVPB_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+MVPB_DEV float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -69,16 +98,17 @@ MVPB_DEV double block_sum(double v, double *red) {
   return s;
 }
 
-// Complex block sum (two doubles in one pass); `red` holds 2*nwaves doubles.
-MVPB_DEV cd block_sum_c(cd v, double *red) {
+// Complex block sum (two values in one pass); `red` holds 2*nwaves doubles.
+template <typename R>
+MVPB_DEV cx<R> block_sum_c(cx<R> v, double *red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double a = wave_sum(v.re), b = wave_sum(v.im);
-  if (lane == 0) { red[2 * wid] = a; red[2 * wid + 1] = b; }
+  R a = wave_sum(v.re), b = wave_sum(v.im);
+  if (lane == 0) { red[2 * wid] = (double)a; red[2 * wid + 1] = (double)b; }
   __syncthreads();
-  cd s = mk(0.0, 0.0);
-  for (int w = 0; w < nw; ++w) { s.re += red[2 * w]; s.im += red[2 * w + 1]; }
+  double sr = 0.0, si = 0.0;
+  for (int w = 0; w < nw; ++w) { sr += red[2 * w]; si += red[2 * w + 1]; }
   __syncthreads();
-  return s;
+  return mkc<R>((R)sr, (R)si);
 }
 
 // ---------------------------------------------------------------------------

@@ -22,24 +22,72 @@ namespace mvpb {
 
 constexpr int EIG_THREADS = 1024;
 constexpr int EIG_WAVES = EIG_THREADS / 64;
+// Panel kernel: columns of the trailing matrix consumed per load batch.
+constexpr int PANEL_THREADS = 1024;
+constexpr int PANEL_WAVES = PANEL_THREADS / 64;
+static_assert(PANEL_WAVES == PANEL_SLOTS, "one partial-sum slot per panel wave");
+constexpr int COLS = 8;
+
+// Sum 8 complex values over the 64 lanes of a wavefront, one value per
+// column: after the butterfly, lanes with (lane >> 3) & 7 == k hold the sum
+// of column k.  Contents of v are destroyed.
+template <typename R>
+MVPB_DEV cx<R> reduce8_columns(cx<R> (&v)[8], int lane) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const bool hi = lane & 32;
+    cx<R> snd = hi ? v[k] : v[k + 4];
+    const cx<R> keep = hi ? v[k + 4] : v[k];
+    snd.re = __shfl_xor(snd.re, 32, 64);
+    snd.im = __shfl_xor(snd.im, 32, 64);
+    v[k] = keep + snd;
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const bool hi = lane & 16;
+    cx<R> snd = hi ? v[k] : v[k + 2];
+    const cx<R> keep = hi ? v[k + 2] : v[k];
+    snd.re = __shfl_xor(snd.re, 16, 64);
+    snd.im = __shfl_xor(snd.im, 16, 64);
+    v[k] = keep + snd;
+  }
+  {
+    const bool hi = lane & 8;
+    cx<R> snd = hi ? v[0] : v[1];
+    const cx<R> keep = hi ? v[1] : v[0];
+    snd.re = __shfl_xor(snd.re, 8, 64);
+    snd.im = __shfl_xor(snd.im, 8, 64);
+    v[0] = keep + snd;
+  }
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) {
+    v[0].re += __shfl_xor(v[0].re, o, 64);
+    v[0].im += __shfl_xor(v[0].im, o, 64);
+  }
+  return v[0];
+}
 
 // ---------------------------------------------------------------------------
 // 1a. Panel kernel: columns p .. p+nbp-1 of every item.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(EIG_THREADS) hetrd_panel(const EigItem *__restrict__ items, int p) {
-  extern __shared__ cd sh[];
-  cd *v = sh;                  // MAX_N: current reflector (rows j+1..n-1)
-  cd *y = v + MAX_N;           // MAX_N: new column of W
-  cd *part = y + MAX_N;        // 1024: matrix-vector partial sums
-  __shared__ double red[2 * EIG_WAVES];
-  __shared__ cd t1[PANEL], t2[PANEL], wj[PANEL], vj[PANEL];
+template <typename R>
+__global__ void __launch_bounds__(PANEL_THREADS) hetrd_panel(const EigItem *__restrict__ items, int p, int nmax) {
+  typedef cx<R> C;
+  typedef const __attribute__((address_space(1))) C gC;
+  extern __shared__ __align__(16) unsigned char shraw[];
+  C *v = (C *)shraw;                            // nmax: current reflector (rows j+1..n-1)
+  R *yr = (R *)(v + nmax);              // nmax: real parts of the new W column
+  R *yi = yr + nmax;                    // nmax: imaginary parts
+  __shared__ double red[2 * PANEL_WAVES];
+  __shared__ C t1[PANEL], t2[PANEL], wj[PANEL], vj[PANEL];
+  __shared__ C colsum[PANEL_WAVES * 64];
   const EigItem it = items[blockIdx.x];
   const int n = 2 * it.N;
   if (p >= n - 1) return;
   const int nbp = min(PANEL, n - 1 - p);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  cd *__restrict__ A = it.A;
-  cd *__restrict__ W = it.W;
+  C *__restrict__ A = (C *)it.A;
+  C *__restrict__ W = (C *)it.W;
   const size_t ld = (size_t)n;
 
   for (int i = 0; i < nbp; ++i) {
@@ -50,34 +98,47 @@ __global__ void __launch_bounds__(EIG_THREADS) hetrd_panel(const EigItem *__rest
       vj[tid] = conj(A[(size_t)(p + tid) * ld + j]);
     }
     __syncthreads();
-    for (int r = j + tid; r < n; r += EIG_THREADS) {
-      cd acc = A[(size_t)j * ld + r];
-      for (int k = 0; k < i; ++k) {
-        acc = acc - A[(size_t)(p + k) * ld + r] * wj[k];
-        acc = acc - W[(size_t)k * ld + r] * vj[k];
+    for (int r = j + tid; r < n; r += PANEL_THREADS) {
+      C acc = A[(size_t)j * ld + r];
+      for (int k0 = 0; k0 < i; k0 += 8) {
+        C av[8], wv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const bool ok = k0 + k < i;
+          av[k] = ok ? A[(size_t)(p + k0 + k) * ld + r] : czero<R>();
+          wv[k] = ok ? W[(size_t)(k0 + k) * ld + r] : czero<R>();
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (k0 + k < i) {
+            acc = acc - av[k] * wj[k0 + k];
+            acc = acc - wv[k] * vj[k0 + k];
+          }
+        }
       }
-      if (r == j) acc.im = 0.0;
+      if (r == j) acc.im = R(0);
       A[(size_t)j * ld + r] = acc;
     }
     __syncthreads();
     // --- step 2: reflector annihilating A[j+2:n, j]
     double xn2 = 0.0;
-    for (int r = j + 2 + tid; r < n; r += EIG_THREADS) xn2 += abs2(A[(size_t)j * ld + r]);
+    for (int r = j + 2 + tid; r < n; r += PANEL_THREADS) xn2 += (double)abs2(A[(size_t)j * ld + r]);
     xn2 = block_sum(xn2, red);
-    const cd alpha = A[(size_t)j * ld + j + 1];
-    cd tau = mk(0.0, 0.0), scale = mk(0.0, 0.0);
-    double beta = alpha.re;
-    if (!(xn2 == 0.0 && alpha.im == 0.0)) {
-      const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2);
-      beta = alpha.re >= 0.0 ? -nrm : nrm;
-      tau = mk((beta - alpha.re) / beta, -alpha.im / beta);
-      scale = cdiv(mk(1.0, 0.0), alpha - mk(beta, 0.0));
+    const C alpha = A[(size_t)j * ld + j + 1];
+    C tau = czero<R>(), scale = czero<R>();
+    double beta = (double)alpha.re;
+    if (!(xn2 == 0.0 && alpha.im == R(0))) {
+      const double ar = alpha.re, ai = alpha.im;
+      const double nrm = sqrt(ar * ar + ai * ai + xn2);
+      beta = ar >= 0.0 ? -nrm : nrm;
+      tau = mkc<R>((R)((beta - ar) / beta), (R)(-ai / beta));
+      scale = ccast<R>(cdiv(mk(1.0, 0.0), mk(ar - beta, ai)));
     }
     const int m = n - j - 1;
-    for (int r = j + 1 + tid; r < n; r += EIG_THREADS) {
-      cd x;
+    for (int r = j + 1 + tid; r < n; r += PANEL_THREADS) {
+      C x;
       if (r == j + 1) {
-        x = mk(1.0, 0.0);
+        x = mkc<R>(R(1), R(0));
       } else {
         x = A[(size_t)j * ld + r] * scale;
       }
@@ -85,60 +146,126 @@ __global__ void __launch_bounds__(EIG_THREADS) hetrd_panel(const EigItem *__rest
       v[r - j - 1] = x;
     }
     if (tid == 0) {
-      it.d[j] = A[(size_t)j * ld + j].re;
-      it.e[j] = beta;
-      it.tau[j] = tau;
+      it.d[j] = (double)A[(size_t)j * ld + j].re;
+      it.e[j] = (double)(R)beta;
+      ((C *)it.tau)[j] = tau;
     }
     __syncthreads();
-    // --- step 3: y = A22 v with A22 = A[j+1:, j+1:] (pre-panel values)
-    const cd *A22 = A + (size_t)(j + 1) * ld + (j + 1);
-    const int S = (m + 63) / 64;
-    if (S >= EIG_WAVES) {
-      for (int s = w; s < S; s += EIG_WAVES) {
+    // --- step 3: y = A22 v with A22 = A[j+1:, j+1:] (pre-panel values).
+    // Hermitian product from the lower triangle only: 64 x 64 tiles (s >= cb)
+    // spread over the waves; a lane owns one row, COLS columns are loaded at
+    // a time, the row sums stay in the lane and the column sums (conjugate
+    // side) are folded across lanes by a butterfly.  Each wave accumulates
+    // into its own slot; the slots are summed in a fixed order, so the result
+    // is bitwise reproducible.
+    const C *A22 = A + (size_t)(j + 1) * ld + (j + 1);
+    // this wave's partial sums: row side and conjugate (column) side kept
+    // apart, so that every entry is only ever touched by one lane
+    C *ywr = (C *)it.Yw + (size_t)(2 * w) * ld;
+    C *ywc = ywr + ld;
+    for (int r = lane; r < m; r += 64) ywr[r] = czero<R>();
+    // column c of a chunk is written by lane 8 (c % 8); clear it with that lane
+    if ((lane & 7) == 0)
+      for (int c = lane >> 3; c < m; c += 8) ywc[c] = czero<R>();
+    {
+      // tiles in column-major order over the lower triangle, a contiguous
+      // range per wave, so a wave stays on one column block for long runs and
+      // keeps that block's conjugate-side sums in registers
+      const int S = (m + 63) / 64;
+      const int ntile = S * (S + 1) / 2;
+      const int t0 = (int)((long)ntile * w / PANEL_WAVES), t1 = (int)((long)ntile * (w + 1) / PANEL_WAVES);
+      int cb = 0, s = 0;
+      {
+        int t = t0;
+        while (t >= S - cb) { t -= S - cb; ++cb; }
+        s = cb + t;
+      }
+      // conjugate-side sums of the current column block: 64 per wave in LDS,
+      // slot q*8 + k only ever touched by lane 8k
+      C *colacc = colsum + w * 64;
+      if ((lane & 7) == 0)
+        for (int q = 0; q < 8; ++q) colacc[q * 8 + (lane >> 3)] = czero<R>();
+      for (int t = t0; t < t1; ++t) {
         const int r = s * 64 + lane;
-        if (r < m) {
-          cd a0 = mk(0.0, 0.0), a1 = mk(0.0, 0.0);
-          int c = 0;
-          for (; c + 1 < m; c += 2) {
-            a0 = cfma(A22[(size_t)c * ld + r], v[c], a0);
-            a1 = cfma(A22[(size_t)(c + 1) * ld + r], v[c + 1], a1);
+        const bool rv = r < m;
+        const int rc = rv ? r : m - 1;                 // clamped row: loads stay inside the matrix
+        const C vr = rv ? v[r] : czero<R>();
+        const bool diag = (s == cb);                    // uniform per tile
+        C accr = czero<R>();
+        const int cend = min(cb * 64 + 64, m);
+        const gC *colp = (const gC *)(A22 + (size_t)(cb * 64) * ld + rc);
+#pragma unroll 1
+        for (int q = 0; q < 8; ++q) {
+          const int c0 = cb * 64 + q * COLS;
+          if (c0 >= cend) break;
+          const int kmax = min(COLS, cend - c0);        // uniform
+          C a[COLS];
+#pragma unroll
+          for (int k = 0; k < COLS; ++k) {
+            if (k < kmax) {
+              const gC *pq = colp + (size_t)(q * COLS + k) * ld;
+              a[k] = mkc<R>(pq->re, pq->im);
+            } else {
+              a[k] = czero<R>();
+            }
           }
-          if (c < m) a0 = cfma(A22[(size_t)c * ld + r], v[c], a0);
-          y[r] = a0 + a1;
+          if (!diag) {
+#pragma unroll
+            for (int k = 0; k < COLS; ++k) {
+              const C vc = (k < kmax) ? v[c0 + k] : czero<R>();
+              accr = cfma(a[k], vc, accr);
+              a[k] = cfma_cj(a[k], vr, czero<R>());   // conjugate side
+            }
+          } else {
+            // diagonal tile: lower triangle only, the diagonal counted once
+#pragma unroll
+            for (int k = 0; k < COLS; ++k) {
+              const int c = c0 + k;
+              const R wt = (k < kmax && r >= c) ? R(1) : R(0);
+              const R wc = (k < kmax && r > c) ? R(1) : R(0);
+              const C vc = (k < kmax) ? v[c] : czero<R>();
+              accr = cfma(wt * a[k], vc, accr);
+              a[k] = wc * cfma_cj(a[k], vr, czero<R>());
+            }
+          }
+          const C cs = reduce8_columns<R>(a, lane);
+          if ((lane & 7) == 0) colacc[q * 8 + (lane >> 3)] = colacc[q * 8 + (lane >> 3)] + cs;
+        }
+        if (rv) ywr[r] = ywr[r] + accr;
+        // next tile; flush the column sums when the column block changes
+        ++s;
+        if (s >= S || t + 1 == t1) {
+          if ((lane & 7) == 0) {
+            for (int q = 0; q < 8; ++q) {
+              const int c = cb * 64 + q * COLS + (lane >> 3);
+              if (c < m) ywc[c] = ywc[c] + colacc[q * 8 + (lane >> 3)];
+              colacc[q * 8 + (lane >> 3)] = czero<R>();
+            }
+          }
+          if (s >= S) {
+            ++cb;
+            s = cb;
+          }
         }
       }
-    } else {
-      const int G = EIG_WAVES / S;
-      const int s = w % S, g = w / S;
-      if (g < G) {
-        const int c0 = (int)((long)g * m / G), c1 = (int)((long)(g + 1) * m / G);
-        const int r = s * 64 + lane;
-        cd a0 = mk(0.0, 0.0), a1 = mk(0.0, 0.0);
-        if (r < m) {
-          int c = c0;
-          for (; c + 1 < c1; c += 2) {
-            a0 = cfma(A22[(size_t)c * ld + r], v[c], a0);
-            a1 = cfma(A22[(size_t)(c + 1) * ld + r], v[c + 1], a1);
-          }
-          if (c < c1) a0 = cfma(A22[(size_t)c * ld + r], v[c], a0);
-        }
-        part[g * S * 64 + s * 64 + lane] = a0 + a1;
-      }
-      __syncthreads();
-      for (int r = tid; r < m; r += EIG_THREADS) {
-        cd acc = mk(0.0, 0.0);
-        for (int gg = 0; gg < G; ++gg) acc = acc + part[gg * S * 64 + r];
-        y[r] = acc;
-      }
+    }
+    __syncthreads();
+    for (int r = tid; r < m; r += PANEL_THREADS) {
+      C acc = czero<R>();
+#pragma unroll
+      for (int q = 0; q < 2 * PANEL_WAVES; ++q) acc = acc + ((const C *)it.Yw)[(size_t)q * ld + r];
+      yr[r] = acc.re;
+      yi[r] = acc.im;
     }
     __syncthreads();
     // corrections with the panel's earlier columns (V = A[:, p:p+i], W[:, 0:i])
     if (i > 0) {
-      for (int k = w; k < 2 * i; k += EIG_WAVES) {
+      for (int k = w; k < 2 * i; k += PANEL_WAVES) {
         const bool isW = k < i;
         const int kk = isW ? k : k - i;
-        const cd *col = isW ? (W + (size_t)kk * ld) : (A + (size_t)(p + kk) * ld);
-        cd acc = mk(0.0, 0.0);
+        const C *col = isW ? (W + (size_t)kk * ld) : (A + (size_t)(p + kk) * ld);
+        C acc = czero<R>();
+#pragma unroll 8
         for (int r = j + 1 + lane; r < n; r += 64) acc = cfma_cj(col[r], v[r - j - 1], acc);
         acc.re = wave_sum(acc.re);
         acc.im = wave_sum(acc.im);
@@ -147,27 +274,41 @@ __global__ void __launch_bounds__(EIG_THREADS) hetrd_panel(const EigItem *__rest
         }
       }
       __syncthreads();
-      for (int r = j + 1 + tid; r < n; r += EIG_THREADS) {
-        cd acc = y[r - j - 1];
-        for (int k = 0; k < i; ++k) {
-          acc = acc - A[(size_t)(p + k) * ld + r] * t1[k];
-          acc = acc - W[(size_t)k * ld + r] * t2[k];
+      for (int r = j + 1 + tid; r < n; r += PANEL_THREADS) {
+        C acc = mkc<R>(yr[r - j - 1], yi[r - j - 1]);
+        for (int k0 = 0; k0 < i; k0 += 8) {
+          C av[8], wv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const bool ok = k0 + k < i;
+            av[k] = ok ? A[(size_t)(p + k0 + k) * ld + r] : czero<R>();
+            wv[k] = ok ? W[(size_t)(k0 + k) * ld + r] : czero<R>();
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            if (k0 + k < i) {
+              acc = acc - av[k] * t1[k0 + k];
+              acc = acc - wv[k] * t2[k0 + k];
+            }
+          }
         }
-        y[r - j - 1] = acc;
+        yr[r - j - 1] = acc.re;
+        yi[r - j - 1] = acc.im;
       }
       __syncthreads();
     }
     // y = tau y ; y += (-1/2 tau (y^H v)) v
-    cd dot = mk(0.0, 0.0);
-    for (int r = tid; r < m; r += EIG_THREADS) {
-      const cd yy = tau * y[r];
-      y[r] = yy;
+    C dot = czero<R>();
+    for (int r = tid; r < m; r += PANEL_THREADS) {
+      const C yy = tau * mkc<R>(yr[r], yi[r]);
+      yr[r] = yy.re;
+      yi[r] = yy.im;
       dot = cfma_cj(yy, v[r], dot);
     }
     dot = block_sum_c(dot, red);
-    const cd al2 = mk(-0.5, 0.0) * tau * dot;
-    for (int r = tid; r < m; r += EIG_THREADS) {
-      const cd yy = cfma(al2, v[r], y[r]);
+    const C al2 = mkc<R>(R(-0.5), R(0)) * tau * dot;
+    for (int r = tid; r < m; r += PANEL_THREADS) {
+      const C yy = cfma(al2, v[r], mkc<R>(yr[r], yi[r]));
       W[(size_t)i * ld + j + 1 + r] = yy;
     }
     __syncthreads();
@@ -175,33 +316,38 @@ __global__ void __launch_bounds__(EIG_THREADS) hetrd_panel(const EigItem *__rest
 }
 
 // ---------------------------------------------------------------------------
-// 1b. Trailing update A[q0:, q0:] -= V W^H + W V^H, q0 = p + nbp (full square).
+// 1b. Trailing update A[q0:, q0:] -= V W^H + W V^H, q0 = p + nbp, on the
+//     lower triangle (upper entries of diagonal tiles are updated too but
+//     never read).
 // ---------------------------------------------------------------------------
+template <typename R>
 __global__ void __launch_bounds__(256) hetrd_update(const EigItem *__restrict__ items, int p) {
+  typedef cx<R> C;
   constexpr int BK = 8;
-  __shared__ cd Vr[BK][65], Wr[BK][65], Vc[BK][65], Wc[BK][65];
+  __shared__ C Vr[BK][65], Wr[BK][65], Vc[BK][65], Wc[BK][65];
   const EigItem it = items[blockIdx.z];
   const int n = 2 * it.N;
   if (p >= n - 1) return;
   const int nbp = min(PANEL, n - 1 - p);
   const int q0 = p + nbp, m = n - q0;
   const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
-  if (r0 >= m || c0 >= m) return;
-  cd *__restrict__ A = it.A;
-  const cd *__restrict__ W = it.W;
+  // only the lower triangle (tiles with row block >= column block) is kept
+  if (r0 >= m || c0 >= m || blockIdx.x < blockIdx.y) return;
+  C *__restrict__ A = (C *)it.A;
+  const C *__restrict__ W = (const C *)it.W;
   const size_t ld = (size_t)n;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  cd acc[4][4];
+  C acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = mk(0.0, 0.0);
+    for (int b = 0; b < 4; ++b) acc[a][b] = czero<R>();
   for (int k0 = 0; k0 < nbp; k0 += BK) {
     for (int e = tid; e < 64 * BK; e += 256) {
       const int i = e & 63, k = e >> 6;
       const int gk = k0 + k;
       const int gr = q0 + r0 + i, gc = q0 + c0 + i;
-      cd vr = mk(0.0, 0.0), wr = vr, vc = vr, wc = vr;
+      C vr = czero<R>(), wr = vr, vc = vr, wc = vr;
       if (gk < nbp) {
         if (gr < n) {
           vr = A[(size_t)(p + gk) * ld + gr];
@@ -220,7 +366,7 @@ __global__ void __launch_bounds__(256) hetrd_update(const EigItem *__restrict__ 
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < BK; ++k) {
-      cd a1[4], a2[4], b1[4], b2[4];
+      C a1[4], a2[4], b1[4], b2[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         a1[a] = Vr[k][tx + 16 * a];
@@ -246,28 +392,36 @@ __global__ void __launch_bounds__(256) hetrd_update(const EigItem *__restrict__ 
     for (int a = 0; a < 4; ++a) {
       const int gr = q0 + r0 + tx + 16 * a;
       if (gr >= n) continue;
-      cd *dst = A + (size_t)gc * ld + gr;
-      *dst = *dst - acc[a][b];
+      C *dst = A + (size_t)gc * ld + gr;
+      const C nv = *dst - acc[a][b];
+      *dst = nv;
+      // the last diagonal entry has no reflector; the last update fixes it
+      if (gr == n - 1 && gc == n - 1) it.d[n - 1] = (double)nv.re;
     }
   }
 }
 
-hipError_t launch_hetrd(const EigItem *items, int n_items, int n_max, hipStream_t st) {
-  const size_t sh = sizeof(cd) * (2 * MAX_N + 1024);
+template <typename R>
+static hipError_t launch_hetrd_t(const EigItem *items, int n_items, int n_max, hipStream_t st) {
+  const size_t sh = sizeof(cx<R>) * 2 * (size_t)n_max;
   for (int p = 0; p < n_max - 1; p += PANEL) {
     {
       ProfScope ps(K_HETRD_PANEL, st);
-      hipLaunchKernelGGL(hetrd_panel, dim3(n_items), dim3(EIG_THREADS), sh, st, items, p);
+      hipLaunchKernelGGL(hetrd_panel<R>, dim3(n_items), dim3(PANEL_THREADS), sh, st, items, p, n_max);
     }
     const int nbp = min(PANEL, n_max - 1 - p);
     const int m = n_max - p - nbp;
     if (m > 0) {
       const int t = (m + 63) / 64;
       ProfScope ps(K_HETRD_UPDATE, st);
-      hipLaunchKernelGGL(hetrd_update, dim3(t, t, n_items), dim3(256), 0, st, items, p);
+      hipLaunchKernelGGL(hetrd_update<R>, dim3(t, t, n_items), dim3(256), 0, st, items, p);
     }
   }
   return hipGetLastError();
+}
+
+hipError_t launch_hetrd(const EigItem *items, int n_items, int n_max, bool fp32, hipStream_t st) {
+  return fp32 ? launch_hetrd_t<float>(items, n_items, n_max, st) : launch_hetrd_t<double>(items, n_items, n_max, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,7 +484,8 @@ __device__ void orthonormalize_real(double *X, int n, int nb, double *h, double 
 __global__ void __launch_bounds__(EIG_THREADS) tridiag_eig(const EigItem *__restrict__ items) {
   extern __shared__ double shd[];
   double *dd = shd;            // MAX_N
-  double *ee2 = dd + MAX_N;    // MAX_N
+  double *ee2 = dd + MAX_N;    // MAX_N: e^2
+  double *ee = ee2 + MAX_N;    // MAX_N: e
   __shared__ double lo[64], hi[64], xs[EIG_THREADS];
   __shared__ int cnts[EIG_THREADS];
   __shared__ double red[2 * EIG_WAVES];
@@ -339,15 +494,17 @@ __global__ void __launch_bounds__(EIG_THREADS) tridiag_eig(const EigItem *__rest
   const EigItem it = items[blockIdx.x];
   const int n = 2 * it.N, nb = it.nb;
   const int tid = threadIdx.x;
-  if (tid == 0) it.d[n - 1] = it.A[(size_t)(n - 1) * n + (n - 1)].re;
   // stage d, e^2; Gershgorin bounds
   double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
   for (int r = tid; r < n; r += EIG_THREADS) {
-    const double dr = (r == n - 1) ? it.A[(size_t)(n - 1) * n + (n - 1)].re : it.d[r];
+    const double dr = it.d[r];
     const double er = (r < n - 1) ? it.e[r] : 0.0;
     const double el = (r > 0) ? it.e[r - 1] : 0.0;
     dd[r] = dr;
-    if (r < n - 1) ee2[r] = er * er;
+    if (r < n - 1) {
+      ee2[r] = er * er;
+      ee[r] = er;
+    }
     const double rad = fabs(er) + fabs(el);
     gl = fmin(gl, dr - rad);
     gu = fmax(gu, dr + rad);
@@ -425,69 +582,65 @@ __global__ void __launch_bounds__(EIG_THREADS) tridiag_eig(const EigItem *__rest
 #define DU(r) lu[((size_t)2 * n + (r)) * nb + bb]
 #define DU2(r) lu[((size_t)3 * n + (r)) * nb + bb]
 #define PV(r) lu[((size_t)4 * n + (r)) * nb + bb]
-    for (int r = 0; r < n; ++r) {
-      DG(r) = dd[r] - lam;
-      if (r < n - 1) {
-        const double er = it.e[r];
-        DL(r) = er;
-        DU(r) = er;
-      }
-    }
-    // LU with partial pivoting of the tridiagonal T - lam I
+    // LU with partial pivoting of T - lam I; the running row lives in
+    // registers and the inputs come from LDS, so only stores go to memory
+    double dr = dd[0] - lam, ur = (n > 1) ? ee[0] : 0.0;
     for (int r = 0; r < n - 1; ++r) {
-      const double dr = DG(r), lr = DL(r);
+      const double lr = ee[r];
+      const double dn = dd[r + 1] - lam;
+      const double un = (r < n - 2) ? ee[r + 1] : 0.0;
       if (fabs(dr) >= fabs(lr)) {
         const double piv = (dr == 0.0) ? pert : dr;
-        DG(r) = piv;
         const double f = lr / piv;
-        DL(r) = f;
-        DG(r + 1) = DG(r + 1) - f * DU(r);
-        if (r < n - 2) DU2(r) = 0.0;
-        PV(r) = 0.0;
+        DG(r) = piv; DU(r) = ur; DU2(r) = 0.0; DL(r) = f; PV(r) = 0.0;
+        dr = dn - f * ur;
+        ur = un;
       } else {
         const double f = dr / lr;
-        DG(r) = lr;
-        DL(r) = f;
-        const double tmp = DU(r);
-        DU(r) = DG(r + 1);
-        DG(r + 1) = tmp - f * DG(r + 1);
-        if (r < n - 2) {
-          DU2(r) = DU(r + 1);
-          DU(r + 1) = -f * DU(r + 1);
-        }
-        PV(r) = 1.0;
+        DG(r) = lr; DU(r) = dn; DU2(r) = un; DL(r) = f; PV(r) = 1.0;
+        dr = ur - f * dn;
+        ur = -f * un;
       }
     }
-    if (DG(n - 1) == 0.0) DG(n - 1) = pert;
+    DG(n - 1) = (dr == 0.0) ? pert : dr;
     for (int r = 0; r < n; ++r) X[(size_t)r * nb + bb] = hash_uniform(r + 1, bb + 7);
   }
   for (int iter = 0; iter < 3; ++iter) {
     if (tid < nb) {
       const int bb = tid;
-      // forward: apply P and L^-1
+      // forward: apply P and L^-1; the running entry stays in a register
+      double cur = X[bb];
       for (int r = 0; r < n - 1; ++r) {
-        double xr = X[(size_t)r * nb + bb], xr1 = X[(size_t)(r + 1) * nb + bb];
-        if (PV(r) != 0.0) { const double t = xr; xr = xr1; xr1 = t; X[(size_t)r * nb + bb] = xr; }
-        X[(size_t)(r + 1) * nb + bb] = xr1 - DL(r) * xr;
+        const double nxt = X[(size_t)(r + 1) * nb + bb];
+        const bool sw = PV(r) != 0.0;
+        const double br = sw ? nxt : cur;
+        const double br1 = sw ? cur : nxt;
+        X[(size_t)r * nb + bb] = br;
+        cur = br1 - DL(r) * br;
       }
-      // back substitution with U (diag, super, super-super), scaled to avoid overflow
-      double xmax = 0.0;
+      X[(size_t)(n - 1) * nb + bb] = cur;
+      // back substitution with U (diagonal, super and second super diagonal)
+      double x1 = 0.0, x2 = 0.0, xmax = 0.0, sc = 1.0;
       for (int r = n - 1; r >= 0; --r) {
-        double s = X[(size_t)r * nb + bb];
-        if (r + 1 < n) s -= DU(r) * X[(size_t)(r + 1) * nb + bb];
-        if (r + 2 < n) s -= DU2(r) * X[(size_t)(r + 2) * nb + bb];
+        double s = sc * X[(size_t)r * nb + bb];
+        if (r + 1 < n) s -= DU(r) * x1;
+        if (r + 2 < n) s -= DU2(r) * x2;
         double xv = s / DG(r);
         if (!isfinite(xv)) xv = 0.0;
+        if (fabs(xv) > 1e150) {
+          // keep the iterate finite: rescale what is solved and what is left
+          const double f = 1e-150;
+          for (int q = r + 1; q < n; ++q) X[(size_t)q * nb + bb] *= f;
+          x1 *= f;
+          x2 *= f;
+          xmax *= f;
+          sc *= f;
+          xv *= f;
+        }
         X[(size_t)r * nb + bb] = xv;
         xmax = fmax(xmax, fabs(xv));
-        if (xmax > 1e150) {
-          // rescale the solved tail to keep it finite
-          const double sc = 1.0 / xmax;
-          for (int q = r; q < n; ++q) X[(size_t)q * nb + bb] *= sc;
-          xmax = 1.0;
-          // unsolved head is scaled as well so the system stays consistent
-          for (int q = 0; q < r; ++q) X[(size_t)q * nb + bb] *= sc;
-        }
+        x2 = x1;
+        x1 = xv;
       }
       const double inv = xmax > 0.0 ? 1.0 / xmax : 1.0;
       for (int r = 0; r < n; ++r) X[(size_t)r * nb + bb] *= inv;
@@ -504,63 +657,115 @@ __global__ void __launch_bounds__(EIG_THREADS) tridiag_eig(const EigItem *__rest
 
 hipError_t launch_tridiag_eig(const EigItem *items, int n_items, hipStream_t st) {
   ProfScope ps(K_TRIDIAG, st);
-  hipLaunchKernelGGL(tridiag_eig, dim3(n_items), dim3(EIG_THREADS), sizeof(double) * 2 * MAX_N, st, items);
+  hipLaunchKernelGGL(tridiag_eig, dim3(n_items), dim3(EIG_THREADS), sizeof(double) * 3 * MAX_N, st, items);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // 3. Back-transform Y = Q X, Q = H_0 H_1 ... H_{n-2}, H_j = I - tau_j v_j v_j^H.
-//    Each wave owns a set of columns, so no block-wide barrier is needed.
+//    The reflectors of each panel are applied at once in compact WY form,
+//    Q_panel = I - V T V^H (T upper triangular, built as in the forward
+//    columnwise recurrence T_ii = tau_i, T(0:i, i) = -tau_i T(0:i,0:i) V^H v_i),
+//    last panel first.
 // ---------------------------------------------------------------------------
+template <typename R>
 __global__ void __launch_bounds__(EIG_THREADS) backtransform(const EigItem *__restrict__ items) {
+  typedef cx<R> C;
+  __shared__ C Sm[PANEL][PANEL + 1];
+  __shared__ C Tm[PANEL][PANEL + 1];
+  __shared__ C W1[PANEL][RR_MAX_BANDS];
+  __shared__ C W2[PANEL][RR_MAX_BANDS];
+  __shared__ C taus[PANEL];
   const EigItem it = items[blockIdx.x];
   const int n = 2 * it.N, nb = it.nb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const size_t ld = (size_t)n;
-  cd *__restrict__ Y = it.Y;
-  const cd *__restrict__ A = it.A;
+  C *__restrict__ Y = (C *)it.Yb;     // working vectors (== it.Y in FP64)
+  const C *__restrict__ A = (const C *)it.A;
   for (size_t e = tid; e < (size_t)n * nb; e += EIG_THREADS) {
     const int r = (int)(e % n), b = (int)(e / n);
-    Y[e] = mk(it.X[(size_t)r * nb + b], 0.0);
+    Y[e] = mkc<R>((R)it.X[(size_t)r * nb + b], R(0));
   }
   __syncthreads();
-  constexpr int CPW = 4;  // columns per wave pass
-  for (int b0 = w * CPW; b0 < nb; b0 += EIG_WAVES * CPW) {
-    const int ncol = min(CPW, nb - b0);
-    for (int j = n - 2; j >= 0; --j) {
-      const cd tau = it.tau[j];
-      if (tau.re == 0.0 && tau.im == 0.0) continue;
-      cd s[CPW];
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) s[c] = mk(0.0, 0.0);
-      for (int r = j + 1 + lane; r < n; r += 64) {
-        const cd vr = (r == j + 1) ? mk(1.0, 0.0) : A[(size_t)j * ld + r];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-          if (c < ncol) s[c] = cfma_cj(vr, Y[(size_t)(b0 + c) * ld + r], s[c]);
-      }
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        s[c].re = wave_sum(s[c].re);
-        s[c].im = wave_sum(s[c].im);
-        s[c] = tau * s[c];
-      }
-      for (int r = j + 1 + lane; r < n; r += 64) {
-        const cd vr = (r == j + 1) ? mk(1.0, 0.0) : A[(size_t)j * ld + r];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-          if (c < ncol) {
-            cd *y = Y + (size_t)(b0 + c) * ld + r;
-            *y = *y - vr * s[c];
-          }
+  // v_i[r] of the panel starting at p: 0 above row p+i+1, 1 at it, A below
+  auto vent = [&](int p, int i, int r) -> C {
+    const int j = p + i;
+    if (r <= j) return czero<R>();
+    if (r == j + 1) return mkc<R>(R(1), R(0));
+    return A[(size_t)j * ld + r];
+  };
+  const int np = (n - 1 + PANEL - 1) / PANEL;
+  for (int pi = np - 1; pi >= 0; --pi) {
+    const int p = pi * PANEL;
+    const int nbp = min(PANEL, n - 1 - p);
+    if (tid < nbp) taus[tid] = ((const C *)it.tau)[p + tid];
+    // S(i, k) = v_i^H v_k, i < k
+    for (int e = w; e < nbp * nbp; e += EIG_WAVES) {
+      const int i = e % nbp, k = e / nbp;
+      if (i >= k) continue;
+      C acc = czero<R>();
+      for (int r = p + k + 1 + lane; r < n; r += 64) acc = cfma_cj(vent(p, i, r), vent(p, k, r), acc);
+      acc.re = wave_sum(acc.re);
+      acc.im = wave_sum(acc.im);
+      if (lane == 0) Sm[i][k] = acc;
+    }
+    // W1 = V^H Y
+    for (int e = w; e < nbp * nb; e += EIG_WAVES) {
+      const int i = e % nbp, c = e / nbp;
+      C acc = czero<R>();
+      for (int r = p + i + 1 + lane; r < n; r += 64) acc = cfma_cj(vent(p, i, r), Y[(size_t)c * ld + r], acc);
+      acc.re = wave_sum(acc.re);
+      acc.im = wave_sum(acc.im);
+      if (lane == 0) W1[i][c] = acc;
+    }
+    __syncthreads();
+    // T by the forward recurrence (small, one wave).  Lane a owns row a of T
+    // and only ever reads entries of its own row, so no barrier is needed.
+    if (w == 0 && lane < PANEL) {
+      for (int i = 0; i < nbp; ++i) {
+        C t = czero<R>();
+        if (lane < i) {
+          for (int b = lane; b < i; ++b) t = cfma(Tm[lane][b], Sm[b][i], t);
+          Tm[lane][i] = czero<R>() - taus[i] * t;
+        } else if (lane == i) {
+          Tm[i][i] = taus[i];
+        } else {
+          Tm[lane][i] = czero<R>();
+        }
       }
     }
+    __syncthreads();
+    // W2 = T W1
+    for (int e = tid; e < nbp * nb; e += EIG_THREADS) {
+      const int i = e % nbp, c = e / nbp;
+      C acc = czero<R>();
+      for (int a = i; a < nbp; ++a) acc = cfma(Tm[i][a], W1[a][c], acc);
+      W2[i][c] = acc;
+    }
+    __syncthreads();
+    // Y -= V W2 on rows p+1 .. n-1
+    const int rows = n - p - 1;
+    for (size_t e = tid; e < (size_t)rows * nb; e += EIG_THREADS) {
+      const int r = p + 1 + (int)(e % rows), c = (int)(e / rows);
+      const int imax = min(nbp - 1, r - p - 1);
+      C acc = czero<R>();
+      for (int i = 0; i <= imax; ++i) acc = cfma(vent(p, i, r), W2[i][c], acc);
+      C *y = Y + (size_t)c * ld + r;
+      *y = *y - acc;
+    }
+    __syncthreads();
+  }
+  if (sizeof(R) != sizeof(double)) {
+    for (size_t e = tid; e < (size_t)n * nb; e += EIG_THREADS) it.Y[e] = ccast<double>(Y[e]);
   }
 }
 
-hipError_t launch_backtransform(const EigItem *items, int n_items, hipStream_t st) {
+hipError_t launch_backtransform(const EigItem *items, int n_items, bool fp32, hipStream_t st) {
   ProfScope ps(K_BACKTRANSFORM, st);
-  hipLaunchKernelGGL(backtransform, dim3(n_items), dim3(EIG_THREADS), 0, st, items);
+  if (fp32)
+    hipLaunchKernelGGL(backtransform<float>, dim3(n_items), dim3(EIG_THREADS), 0, st, items);
+  else
+    hipLaunchKernelGGL(backtransform<double>, dim3(n_items), dim3(EIG_THREADS), 0, st, items);
   return hipGetLastError();
 }
 
@@ -777,11 +982,14 @@ hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, hipStream_t s
 
 // Dynamic LDS above the default limit has to be opted into per kernel.
 hipError_t init_kernel_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void *)hetrd_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(sizeof(cd) * (2 * MAX_N + 1024)));
+  hipError_t e = hipFuncSetAttribute((const void *)hetrd_panel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(sizeof(cd) * 2 * MAX_N));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)hetrd_panel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(sizeof(cf) * 2 * MAX_N));
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void *)tridiag_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(sizeof(double) * 2 * MAX_N));
+                             (int)(sizeof(double) * 3 * MAX_N));
 }
 
 }  // namespace mvpb

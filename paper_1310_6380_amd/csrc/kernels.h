@@ -10,6 +10,8 @@ namespace mvpb {
 constexpr int MAX_N = 4096;
 // Panel width of the blocked reduction to tridiagonal form.
 constexpr int PANEL = 32;
+// Waves of the panel kernel (one partial-sum slot each).
+constexpr int PANEL_SLOTS = 16;
 // Largest number of bands per solve (Rayleigh-Ritz block in LDS).
 constexpr int RR_MAX_BANDS = 64;
 
@@ -22,18 +24,22 @@ struct EigItem {
   int N;            // plane waves; the operator has order n = 2N
   int nb;           // bands wanted
   // reduction to tridiagonal form
-  cd *A;            // n x n working matrix; holds the Householder vectors afterwards
-  cd *Ak;           // n x n kept copy of C(k) for Rayleigh-Ritz
-  cd *W;            // n x PANEL panel workspace
+  // Buffers marked (R) hold complex numbers of the reduction precision:
+  // complex double on the FP64 path, complex float on the FP32 one.
+  void *A;          // (R) n x n working matrix; holds the Householder vectors afterwards
+  cd *Ak;           // n x n kept copy of C(k) for Rayleigh-Ritz (always FP64)
+  void *W;          // (R) n x PANEL panel workspace
+  void *Yw;         // (R) n x 2*PANEL_SLOTS per-wave partial sums of the panel kernel
   double *d;        // n diagonal
   double *e;        // n off-diagonal (real)
-  cd *tau;          // n reflector scalars
+  void *tau;        // (R) n reflector scalars
   // tridiagonal eigenproblem
   double *X;        // n x nb eigenvectors of the tridiagonal matrix
   double *lu;       // 5 n x nb factorisation scratch
   double *lam_t;    // nb eigenvalues of the tridiagonal matrix
   // back-transform and refinement
-  cd *Y;            // n x nb eigenvectors of C(k)
+  cd *Y;            // n x nb eigenvectors of C(k) (FP64, input of Rayleigh-Ritz)
+  void *Yb;         // (R) back-transform working vectors (== Y on the FP64 path)
   cd *Z;            // n x nb scratch (C Y)
   double *lam;      // nb refined eigenvalues (lambda = omega^2)
   double *omega;    // nb output frequencies (device)
@@ -43,10 +49,14 @@ struct EigItem {
 // assembly.hip
 hipError_t launch_structure_factors_f64(const int32_t *phase, const double *wtab, int nx, int ny, int M1,
                                         int M2, double area, cd *X, cd *F, hipStream_t st);
+// Matrix-core variant: prec 0 = FP64, 1 = FP32, 2 = BF16 inputs (FP32 accumulate).
+// X: scratch of 8 * nx * (4 M2 + 1) doubles.
+hipError_t launch_structure_factors_mfma(int prec, const int32_t *phase, const double *wtab, int nx, int ny, int M1,
+                                         int M2, double area, double *X, cd *F, hipStream_t st);
 hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T0, cd *T1, cd *T2,
                                    hipStream_t st);
 hipError_t launch_combine(const cd *Xp, int N, double s, cd *coef, hipStream_t st);
-hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, hipStream_t st);
+hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, bool fp32, hipStream_t st);
 
 // dense.hip
 // Cholesky (lower, in place) and explicit inverse of the factor for `count`
@@ -70,9 +80,9 @@ hipError_t launch_zgemm(Op opA, Op opB, int M, int N, int K, cd alpha, GemmBatch
 
 // eigen.hip
 hipError_t init_kernel_attributes();  // once per device, before the first launch
-hipError_t launch_hetrd(const EigItem *items, int n_items, int n_max, hipStream_t st);
+hipError_t launch_hetrd(const EigItem *items, int n_items, int n_max, bool fp32, hipStream_t st);
 hipError_t launch_tridiag_eig(const EigItem *items, int n_items, hipStream_t st);
-hipError_t launch_backtransform(const EigItem *items, int n_items, hipStream_t st);
+hipError_t launch_backtransform(const EigItem *items, int n_items, bool fp32, hipStream_t st);
 hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, hipStream_t st);
 
 }  // namespace mvpb

@@ -34,6 +34,7 @@ PREC_FP64 = 0
 PREC_SF_FP32 = 1
 PREC_SF_BF16 = 2
 PREC_EIG_FP32_RR64 = 4
+PREC_SF_PLAIN64 = 8
 
 F_DEVICE_PTRS = 1
 F_ASYNC = 2
@@ -42,7 +43,7 @@ EXPORTS = [
     "mvpb_last_error", "mvpb_version", "mvpb_ctx_create", "mvpb_ctx_destroy",
     "mvpb_cell_create_pixels", "mvpb_cell_destroy", "mvpb_plan_create", "mvpb_plan_dofs",
     "mvpb_plan_destroy", "mvpb_solve", "mvpb_solve_batch", "mvpb_structure_factors",
-    "mvpb_kpath_square", "mvpb_ctx_profile", "mvpb_ctx_profile_read",
+    "mvpb_kpath_square", "mvpb_ctx_profile", "mvpb_ctx_profile_read", "mvpb_plan_create_batch",
 ]
 N_KERNELS = 11
 
@@ -81,6 +82,8 @@ def load(path: str = LIB_PATH):
                                      ctypes.POINTER(P), ctypes.c_uint]
     lib.mvpb_structure_factors.argtypes = [P, I, I, I, D]
     lib.mvpb_kpath_square.argtypes = [I, D]
+    lib.mvpb_plan_create_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I,
+                                           ctypes.POINTER(P)]
     lib.mvpb_ctx_profile.argtypes = [P, I]
     lib.mvpb_ctx_profile_read.argtypes = [P, I, D, ctypes.POINTER(ctypes.c_longlong),
                                           ctypes.POINTER(ctypes.c_char_p)]
@@ -206,6 +209,25 @@ class Context:
 
     def cell(self, phase, props, lattice=None):
         return Cell(self, phase, props, lattice)
+
+    def plans(self, cells, Ms, precision: int = PREC_FP64) -> list:
+        """Plans for many cells at once (batched per-cell assembly)."""
+        n = len(cells)
+        ch = (ctypes.c_void_p * n)(*[c.h for c in cells])
+        m1 = (ctypes.c_int * n)(*[int(M if np.isscalar(M) else M[0]) for M in Ms])
+        m2 = (ctypes.c_int * n)(*[int(M if np.isscalar(M) else M[1]) for M in Ms])
+        out = (ctypes.c_void_p * n)()
+        _check(load().mvpb_plan_create_batch(self.h, n, ch, m1, m2, precision, out))
+        res = []
+        for i in range(n):
+            p = Plan.__new__(Plan)
+            p.ctx = self
+            p.h = ctypes.c_void_p(out[i])
+            nu, ns = ctypes.c_int(), ctypes.c_int()
+            _check(load().mvpb_plan_dofs(p.h, ctypes.byref(nu), ctypes.byref(ns)))
+            p.n_u, p.n_s = nu.value, ns.value
+            res.append(p)
+        return res
 
     def solve_batch(self, plans, Qs, n_bands: int) -> list:
         lib = load()

@@ -181,3 +181,97 @@ def test_invalid_inputs_rejected(ctx):
     with pytest.raises(mvpb.MvpbError):
         plan.solve(np.array([[0.1, 0.0]]), 2 * 9 + 1)
     assert plan.solve(np.zeros((0, 2)), 3).shape == (0, 3)
+
+
+# ----------------------------------------------------------------- precision variants
+
+@pytest.mark.parametrize("prec,tol", [(8, 1e-13), (0, 1e-13), (1, 1e-5), (2, 3e-2)])
+def test_structure_factor_precisions(ctx, prec, tol):
+    """Scalar FP64 kernel and the matrix-core contraction with FP64, FP32 and
+    BF16 inputs, against the oracle; error relative to the largest entry."""
+    cell = _rand_cell(32, 16, 5, 77)
+    M1, M2 = 6, 5
+    _say("structure factors precision", prec)
+    F = ctx.cell(cell.phase, cell.props, cell.lattice).structure_factors(M1, M2, prec)
+    J, R, Ph = _oracle_tables(cell, M1, M2)
+    ref = [Ph[0, 0] + Ph[0, 1], Ph[0, 0] - Ph[0, 1], R, J]
+    errs = [np.max(np.abs(F[w] - ref[w])) / np.abs(ref[w]).max() for w in range(4)]
+    _say("  rel errors", errs)
+    assert max(errs) <= tol
+    if prec in (1, 2):
+        assert max(errs) > 1e-12     # really computed at reduced precision
+
+
+@pytest.mark.parametrize("prec,tol", [(4, 1e-5), (1, 1e-5), (5, 1e-5)])
+def test_precision_plans_config0(ctx, prec, tol):
+    """FP32 reduction + FP64 Rayleigh-Ritz, FP32 structure factors, both."""
+    c = config0()
+    cell = c["cell"]
+    _say("precision plan", prec)
+    om = ctx.cell(cell.phase, cell.props).plan(c["M"], c["M"], prec).solve(c["Q"], c["n_bands"])
+    ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, c["M"], c["M"], c["Q"], c["n_bands"])
+    err = band_error(om, ref)
+    _say("  band error", err)
+    assert err <= tol
+
+
+def test_precision_plans_config1_sampled(ctx):
+    """FP32 reduction + FP64 Rayleigh-Ritz at full size (2N = 882, 18 bands)."""
+    c = config1()
+    cell = c["cell"]
+    pick = [0, 21, 44]
+    ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, c["M"], c["M"], c["Q"][pick], c["n_bands"])
+    for prec in (4, 5):
+        _say("config1 precision", prec)
+        om = ctx.cell(cell.phase, cell.props).plan(c["M"], c["M"], prec).solve(c["Q"][pick], c["n_bands"])
+        err = band_error(om, ref)
+        _say("  band error", err)
+        assert err <= 1e-5
+
+
+def test_bf16_structure_factors_miss_the_bar(ctx):
+    """BF16 structure factors alone are reported, not used: their band error is
+    far above 1e-5 on the simple cell."""
+    c = config0()
+    cell = c["cell"]
+    om = ctx.cell(cell.phase, cell.props).plan(c["M"], c["M"], 2).solve(c["Q"][:6], c["n_bands"])
+    ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, c["M"], c["M"], c["Q"][:6], c["n_bands"])
+    err = band_error(om, ref)
+    _say("bf16 band error", err)
+    assert 1e-5 < err < 1e-1
+
+
+# ----------------------------------------------------------------- batching
+
+def test_batched_plans_match_single_plans(ctx):
+    """Batched per-cell assembly (cells grouped by cutoff) gives the same bands
+    as one plan per cell, and both match the oracle; workload shaped like the
+    inclusion batch (circle/square/cross cells, several cutoffs)."""
+    from synth import config2
+    cfg = config2(n_cells=6)
+    items = cfg["cells"]
+    Q = cfg["Q"][::13]
+    _say("batched plans", [c["M"] for c in items])
+    cells = [ctx.cell(c["cell"].phase, c["cell"].props) for c in items]
+    plans = ctx.plans(cells, [c["M"] for c in items])
+    outs = ctx.solve_batch(plans, [Q] * len(plans), cfg["n_bands"])
+    for c, dc, o in zip(items, cells, outs):
+        single = dc.plan(c["M"]).solve(Q, cfg["n_bands"])
+        assert np.array_equal(o, single)
+    for c, o in list(zip(items, outs))[:3]:
+        ref, _ = mo.bands(c["cell"].phase, c["cell"].props, c["cell"].lattice, c["M"], c["M"], Q, cfg["n_bands"])
+        err = band_error(o, ref)
+        _say("  M", c["M"], "error", err)
+        assert err <= TOL64
+
+
+def test_workspace_cap_is_enforced(ctx):
+    from paper_1310_6380_amd import mvpb
+    small = mvpb.Context(0, workspace_cap=1 << 20)
+    cell = _rand_cell(8, 8, 2, 5)
+    plan = small.cell(cell.phase, cell.props).plan(6)
+    with pytest.raises(mvpb.MvpbError) as ei:
+        plan.solve(np.array([[0.1, 0.2]]), 4)
+    assert ei.value.code == mvpb.E_NOMEM
+    plan.close()
+    small.close()
