@@ -53,6 +53,7 @@ def cpu_baseline(cell, M, Q, nb, omega_gpu, n_sample):
     except Exception:
         threads = os.cpu_count() or 1
     idx = np.linspace(0, Q.shape[0] - 1, n_sample).round().astype(int)
+    progress("cpu baseline: oracle on", n_sample, "k-points")
     t0 = time.perf_counter()
     ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, M, M, Q[idx], nb)
     dt = time.perf_counter() - t0
@@ -79,13 +80,19 @@ def batched_error(cfg, om_batch, n_cells=4, n_k=3):
     return worst
 
 
-def run_timed(fn, steps, warmup, mvpb):
-    for _ in range(warmup):
+def progress(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def run_timed(fn, steps, warmup, mvpb, name=""):
+    for i in range(warmup):
         fn()
+        progress(name, "warm-up step", i + 1, "of", warmup)
     mvpb.device_synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         fn()
+        progress(name, "timed step", i + 1, "of", steps)
     mvpb.device_synchronize()
     return (time.perf_counter() - t0) / steps
 
@@ -101,7 +108,7 @@ def variant_mixed(mvpb, ctx, dcell, M, Q, nb, steps, warmup):
         out["om"] = plan.solve(Q, nb)
         plan.close()
 
-    dt = run_timed(step, steps, warmup, mvpb)
+    dt = run_timed(step, steps, warmup, mvpb, "mixed")
     return {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt,
             "precision": "SF fp32 (MFMA), reduction fp32, Rayleigh-Ritz fp64"}, out["om"]
 
@@ -123,7 +130,7 @@ def variant_batched(mvpb, ctx, steps, warmup):
         for p in plans:
             p.close()
 
-    dt = run_timed(step, steps, warmup, mvpb)
+    dt = run_timed(step, steps, warmup, mvpb, "batched")
     items = len(cells) * Q.shape[0]
     return {"value": items / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt, "items": items,
             "precision": "fp64"}, out["om"], cfg
@@ -158,13 +165,15 @@ def main():
         plan.solve_device(Q, nb, om_dev.value)
         plan.close()
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        progress("fp64 warm-up step", i + 1)
     mvpb.device_synchronize()
     ctx.profile(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         step()
+        progress("fp64 timed step", i + 1)
     mvpb.device_synchronize()
     dt = time.perf_counter() - t0
     prof = ctx.profile_read()

@@ -155,6 +155,34 @@ int mvpb_structure_factors(mvpb_cell cell, int M1, int M2, int precision, double
  * Gamma.  Q: host pointer, 2*n_k doubles. */
 int mvpb_kpath_square(int n_k, double *Q);
 
+/* ---------------------------------------------------------------------------
+ * Learned screening surrogate (not part of the paper's method).  A small
+ * periodic CNN maps a binary 32 x 32 pixel cell (phase 1 = the stiff
+ * inclusion material, phase 0 = the matrix) to 400 outputs: the lowest 10
+ * bands at 40 k-points, normalised frequencies as supplied in the targets.
+ * Layers: three-by-three circular convolutions 1->32 (stride 1), 32->32
+ * (stride 2) x3, ReLU; fully connected 512->256 (ReLU) -> 400; mean squared
+ * error; Adam (beta1 0.9, beta2 0.999, eps 1e-8).  Parameters are one flat
+ * FP32 vector (conv weights [ky][kx][ci][co], dense weights [in][out], each
+ * followed by its bias).  precision 0 runs every product in FP32, 1 on the
+ * matrix cores with BF16 inputs and FP32 accumulation; master weights and
+ * moments are FP32.  cells: batch*1024 bytes (0/1, row-major [32][32]),
+ * target / out: batch*400 floats; host pointers unless MVPB_F_DEVICE_PTRS.
+ * ------------------------------------------------------------------------- */
+typedef struct mvpb_sur_s *mvpb_sur;
+int mvpb_sur_create(mvpb_ctx ctx, int max_batch, int precision, uint64_t seed, mvpb_sur *out);
+int mvpb_sur_destroy(mvpb_sur net);
+int mvpb_sur_n_params(mvpb_sur net, int *n);
+int mvpb_sur_get_params(mvpb_sur net, float *params);
+int mvpb_sur_set_params(mvpb_sur net, const float *params);  /* also clears the Adam moments */
+int mvpb_sur_infer(mvpb_sur net, int batch, const uint8_t *cells, float *out, unsigned flags);
+/* loss and the gradient of the loss with respect to every parameter */
+int mvpb_sur_gradients(mvpb_sur net, int batch, const uint8_t *cells, const float *target, float *loss,
+                       float *grads, unsigned flags);
+/* one Adam step on the batch; *loss (nullable) is the loss before the step */
+int mvpb_sur_train_step(mvpb_sur net, int batch, const uint8_t *cells, const float *target, float lr,
+                        float *loss, unsigned flags);
+
 /* Kernel timers (diagnostics).  With profiling on, every kernel launch of a
  * context is bracketed by HIP events on the context stream and its device
  * time accumulated per kernel family.  Kernel ids: 0 structure_factors,

@@ -130,6 +130,23 @@ struct mvpb_plan_s {
   DevBuf linvR;      // N x N, L_R^-1
 };
 
+namespace mvpb {
+int set_error(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+hipStream_t ctx_stream(mvpb_ctx c) { return c->stream; }
+int ctx_device(mvpb_ctx c) { return c->device; }
+bool ctx_closing(mvpb_ctx c) { return c->closing; }
+void ctx_retain(mvpb_ctx c) { c->children++; }
+void ctx_release_child(mvpb_ctx c) { ctx_release(c); }
+}  // namespace mvpb
+
 static int check_ctx(mvpb_ctx c) {
   if (!c) return set_err(MVPB_E_INVALID, "NULL context");
   if (c->closing) return set_err(MVPB_E_INVALID, "context has been destroyed");

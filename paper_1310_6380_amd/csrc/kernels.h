@@ -3,7 +3,18 @@
 
 #include "common.h"
 
+typedef struct mvpb_ctx_s *mvpb_ctx;
+
 namespace mvpb {
+
+// Error reporting and context access shared by the translation units of the
+// library (defined with the C-ABI entry points).
+int set_error(int code, const char *fmt, ...);
+hipStream_t ctx_stream(mvpb_ctx c);
+int ctx_device(mvpb_ctx c);
+bool ctx_closing(mvpb_ctx c);
+void ctx_retain(mvpb_ctx c);         // a child object (cell, plan, network) now holds the context
+void ctx_release_child(mvpb_ctx c);  // ... and lets it go
 
 // Largest reduced-operator order handled by the eigensolver kernels
 // (2N <= MAX_N; vectors of this length are staged in LDS).

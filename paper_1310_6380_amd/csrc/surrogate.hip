@@ -1,0 +1,639 @@
+// Learned screening surrogate: a small periodic CNN that maps a binary
+// 32 x 32 pixel cell to its lowest 10 bands at 40 k-points (normalised
+// frequencies), trained on bands computed by the method itself.
+//
+//   conv1 3x3  1->32 s1, conv2..4 3x3 32->32 s2 (circular padding, ReLU)
+//   flatten 4x4x32 = 512 -> fc1 256 (ReLU) -> fc2 400, mean squared error.
+//
+// Activations are NHWC FP32; convolutions are im2col + GEMM, the backward
+// data pass is a gather col2im (every input pixel collects its taps, so no
+// atomics and bitwise-reproducible results).  GEMMs run either as FP32 FMA
+// tiles or on the matrix cores with BF16 inputs and FP32 accumulation
+// (v_mfma_f32_16x16x16bf16_1k); master weights and Adam moments stay FP32.
+#include <math.h>
+#include <stdio.h>
+
+#include <vector>
+
+#include "../../include/mvpb.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace mvpb {
+
+// ---------------------------------------------------------------------------
+// GEMM, row-major: C[M x N] = alpha op(A) op(B) + beta C.
+// op(A) = A (A[i*lda+k]) or A^T (A[k*lda+i]); op(B) = B (B[k*ldb+j]) or B^T (B[j*ldb+k]).
+// ---------------------------------------------------------------------------
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+template <int TA, int TB>
+MVPB_DEV void load_tiles(const float *A, int lda, const float *B, int ldb, int M, int N, int K, int m0, int n0,
+                         int k0, float (&As)[GBK][GBM + 4], float (&Bs)[GBK][GBN + 4]) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < GBM * GBK; e += 256) {
+    int i, k;
+    if (TA == 0) { i = e / GBK; k = e % GBK; } else { k = e / GBM; i = e % GBM; }
+    const int gi = m0 + i, gk = k0 + k;
+    float v = 0.f;
+    if (gi < M && gk < K) v = TA == 0 ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi];
+    As[k][i] = v;
+  }
+  for (int e = tid; e < GBK * GBN; e += 256) {
+    int k, j;
+    if (TB == 0) { k = e / GBN; j = e % GBN; } else { j = e / GBK; k = e % GBK; }
+    const int gk = k0 + k, gj = n0 + j;
+    float v = 0.f;
+    if (gk < K && gj < N) v = TB == 0 ? B[(size_t)gk * ldb + gj] : B[(size_t)gj * ldb + gk];
+    Bs[k][j] = v;
+  }
+}
+
+template <int TA, int TB>
+__global__ void __launch_bounds__(256) sgemm_f32(int M, int N, int K, float alpha, const float *__restrict__ A, int lda,
+                                                 const float *__restrict__ B, int ldb, float beta,
+                                                 float *__restrict__ C, int ldc) {
+  __shared__ float As[GBK][GBM + 4];
+  __shared__ float Bs[GBK][GBN + 4];
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += GBK) {
+    load_tiles<TA, TB>(A, lda, B, ldb, M, N, K, m0, n0, k0, As, Bs);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = As[kk][ty + 16 * q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = Bs[kk][tx + 16 * q];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fmaf(a[p], b[q], acc[p][q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int i = m0 + ty + 16 * p;
+    if (i >= M) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = n0 + tx + 16 * q;
+      if (j >= N) continue;
+      float *c = C + (size_t)i * ldc + j;
+      *c = alpha * acc[p][q] + (beta != 0.f ? beta * *c : 0.f);
+    }
+  }
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+MVPB_DEV short to_bf16(float f) {  // round to nearest even
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+// Matrix-core GEMM: 64 x 64 block tile, 4 wavefronts of 32 x 32 (2 x 2 MFMA
+// 16 x 16 x 16 tiles).  Lane l feeds A[row = l%16][k = 4(l/16)+v] and
+// B[k = 4(l/16)+v][col = l%16] and receives D[4(l/16)+v][l%16].
+template <int TA, int TB>
+__global__ void __launch_bounds__(256) sgemm_bf16(int M, int N, int K, float alpha, const float *__restrict__ A, int lda,
+                                                  const float *__restrict__ B, int ldb, float beta,
+                                                  float *__restrict__ C, int ldc) {
+  __shared__ float As[GBK][GBM + 4];
+  __shared__ float Bs[GBK][GBN + 4];
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  f4v acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = f4v{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += GBK) {
+    load_tiles<TA, TB>(A, lda, B, ldb, M, N, K, m0, n0, k0, As, Bs);
+    __syncthreads();
+    s4v af[2], bf[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) af[p][v] = to_bf16(As[4 * (lane >> 4) + v][wr + 16 * p + (lane & 15)]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bf[q][v] = to_bf16(Bs[4 * (lane >> 4) + v][wc + 16 * q + (lane & 15)]);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[p], bf[q], acc[p][q], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = m0 + wr + 16 * p + 4 * (lane >> 4) + v;
+        const int j = n0 + wc + 16 * q + (lane & 15);
+        if (i < M && j < N) {
+          float *c = C + (size_t)i * ldc + j;
+          *c = alpha * acc[p][q][v] + (beta != 0.f ? beta * *c : 0.f);
+        }
+      }
+}
+
+static hipError_t gemm(bool bf16, int ta, int tb, int M, int N, int K, float alpha, const float *A, int lda,
+                       const float *B, int ldb, float beta, float *C, int ldc, hipStream_t st) {
+  dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM);
+#define MVPB_GEMM_CASE(TA, TB)                                                                             \
+  if (ta == TA && tb == TB) {                                                                              \
+    if (bf16)                                                                                              \
+      hipLaunchKernelGGL((sgemm_bf16<TA, TB>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc); \
+    else                                                                                                   \
+      hipLaunchKernelGGL((sgemm_f32<TA, TB>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);  \
+  }
+  MVPB_GEMM_CASE(0, 0)
+  MVPB_GEMM_CASE(0, 1)
+  MVPB_GEMM_CASE(1, 0)
+  MVPB_GEMM_CASE(1, 1)
+#undef MVPB_GEMM_CASE
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise and reduction kernels
+// ---------------------------------------------------------------------------
+__global__ void cells_to_float(const uint8_t *__restrict__ cells, float *__restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = cells[i] ? 1.f : 0.f;
+}
+
+// col[p][(ky*3+kx)*C + c] = a[b][(s oy + ky - 1) mod H][(s ox + kx - 1) mod W][c], p = (b, oy, ox)
+__global__ void im2col(const float *__restrict__ a, float *__restrict__ col, int B, int H, int W, int C, int s) {
+  const int Ho = H / s, Wo = W / s, K = 9 * C;
+  const size_t total = (size_t)B * Ho * Wo * K;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e % K);
+    const size_t p = e / K;
+    const int ox = (int)(p % Wo), oy = (int)((p / Wo) % Ho), b = (int)(p / ((size_t)Wo * Ho));
+    const int c = k % C, tap = k / C, ky = tap / 3, kx = tap % 3;
+    const int y = (s * oy + ky - 1 + H) % H, x = (s * ox + kx - 1 + W) % W;
+    col[e] = a[(((size_t)b * H + y) * W + x) * C + c];
+  }
+}
+
+// Gather form of col2im: da[b][y][x][c] = sum over taps of dcol at the output
+// pixel that reads (y, x) through that tap (if any).
+__global__ void col2im(const float *__restrict__ dcol, float *__restrict__ da, int B, int H, int W, int C, int s) {
+  const int Ho = H / s, Wo = W / s, K = 9 * C;
+  const size_t total = (size_t)B * H * W * C;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % C);
+    const size_t pix = e / C;
+    const int x = (int)(pix % W), y = (int)((pix / W) % H), b = (int)(pix / ((size_t)W * H));
+    float acc = 0.f;
+    for (int ky = 0; ky < 3; ++ky) {
+      const int ty = (y - ky + 1 + H) % H;
+      if (ty % s) continue;
+      const int oy = ty / s;
+      for (int kx = 0; kx < 3; ++kx) {
+        const int tx = (x - kx + 1 + W) % W;
+        if (tx % s) continue;
+        const int ox = tx / s;
+        const size_t p = ((size_t)b * Ho + oy) * Wo + ox;
+        acc += dcol[p * K + (ky * 3 + kx) * C + c];
+      }
+    }
+    da[e] = acc;
+  }
+}
+
+__global__ void bias_act(float *__restrict__ z, const float *__restrict__ bias, size_t rows, int C, int relu) {
+  const size_t total = rows * C;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    float v = z[e] + bias[e % C];
+    z[e] = relu ? fmaxf(v, 0.f) : v;
+  }
+}
+
+__global__ void relu_mask(float *__restrict__ d, const float *__restrict__ a, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    if (!(a[e] > 0.f)) d[e] = 0.f;
+}
+
+// db[c] = sum_r d[r][c]; one block per 64-column slab, fixed reduction order
+__global__ void __launch_bounds__(256) column_sums(const float *__restrict__ d, size_t rows, int C, float *__restrict__ db) {
+  __shared__ float part[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+  float acc = 0.f;
+  if (c < C)
+    for (size_t r = g; r < rows; r += 4) acc += d[r * C + c];
+  part[g][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (g == 0 && c < C) db[c] = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
+}
+
+// dout = 2 (out - y) / n and per-block partial sums of (out - y)^2
+__global__ void __launch_bounds__(256) mse_grad(const float *__restrict__ out, const float *__restrict__ y, int n,
+                                                float *__restrict__ dout, float *__restrict__ partial) {
+  __shared__ float red[256];
+  float acc = 0.f;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const float r = out[e] - y[e];
+    dout[e] = 2.f * r / (float)n;
+    acc += r * r;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void adam_step(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                          int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void init_uniform(float *__restrict__ p, int n, float lim, unsigned long long seed, unsigned long long offset) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // counter-based hash (splitmix64 finaliser) -> uniform in [-lim, lim)
+  unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (offset + i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const float u = (float)((z >> 40) * (1.0 / 16777216.0));
+  p[i] = (2.f * u - 1.f) * lim;
+}
+
+}  // namespace mvpb
+
+using namespace mvpb;
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Layer {
+  int ci, co, s, H, W;  // input H, W
+};
+const Layer kConv[4] = {{1, 32, 1, 32, 32}, {32, 32, 2, 32, 32}, {32, 32, 2, 16, 16}, {32, 32, 2, 8, 8}};
+constexpr int kFcIn = 512, kFcHid = 256, kOut = 400, kPix = 32 * 32;
+
+int param_offsets(int *off) {  // 12 tensors
+  int o = 0, t = 0;
+  for (int l = 0; l < 4; ++l) {
+    off[t++] = o;
+    o += 9 * kConv[l].ci * kConv[l].co;
+    off[t++] = o;
+    o += kConv[l].co;
+  }
+  off[t++] = o;
+  o += kFcIn * kFcHid;
+  off[t++] = o;
+  o += kFcHid;
+  off[t++] = o;
+  o += kFcHid * kOut;
+  off[t++] = o;
+  o += kOut;
+  return o;
+}
+
+template <typename T>
+struct Buf {
+  T *p = nullptr;
+  size_t n = 0;
+  ~Buf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t count) {
+    n = count;
+    return hipMalloc(&p, sizeof(T) * count);
+  }
+};
+
+}  // namespace
+
+struct mvpb_sur_s {
+  mvpb_ctx ctx = nullptr;
+  hipStream_t st = nullptr;
+  int max_batch = 0;
+  bool bf16 = true;
+  int n_params = 0;
+  int off[12];
+  long long step = 0;
+  Buf<float> params, grads, m, v;
+  Buf<float> act[5];        // act[0] input [B,32,32,1]; act[l+1] output of conv l (NHWC)
+  Buf<float> col, dcol, dact, dact2;
+  Buf<float> h, out, dout, dh, dflat, partial;
+  Buf<uint8_t> cells;
+  Buf<float> target;
+};
+
+extern "C" int mvpb_sur_destroy(mvpb_sur net);
+
+static int sur_forward(mvpb_sur net, int B) {
+  hipStream_t st = net->st;
+  float *P = net->params.p;
+  for (int l = 0; l < 4; ++l) {
+    const Layer &L = kConv[l];
+    const int Ho = L.H / L.s, Wo = L.W / L.s;
+    const size_t rows = (size_t)B * Ho * Wo;
+    const int K = 9 * L.ci;
+    const size_t tot = rows * K;
+    hipLaunchKernelGGL(im2col, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 65535)), dim3(256), 0, st,
+                       net->act[l].p, net->col.p, B, L.H, L.W, L.ci, L.s);
+    hipError_t e = gemm(net->bf16, 0, 0, (int)rows, L.co, K, 1.f, net->col.p, K, P + net->off[2 * l], L.co, 0.f,
+                        net->act[l + 1].p, L.co, st);
+    if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "surrogate gemm: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL(bias_act, dim3((unsigned)std::min<size_t>((rows * L.co + 255) / 256, 65535)), dim3(256), 0, st,
+                       net->act[l + 1].p, P + net->off[2 * l + 1], rows, L.co, 1);
+  }
+  // fc1 (ReLU), fc2
+  hipError_t e = gemm(net->bf16, 0, 0, B, kFcHid, kFcIn, 1.f, net->act[4].p, kFcIn, P + net->off[8], kFcHid, 0.f,
+                      net->h.p, kFcHid, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(bias_act, dim3((B * kFcHid + 255) / 256), dim3(256), 0, st, net->h.p, P + net->off[9],
+                       (size_t)B, kFcHid, 1);
+    e = gemm(net->bf16, 0, 0, B, kOut, kFcHid, 1.f, net->h.p, kFcHid, P + net->off[10], kOut, 0.f, net->out.p, kOut, st);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(bias_act, dim3((B * kOut + 255) / 256), dim3(256), 0, st, net->out.p, P + net->off[11],
+                       (size_t)B, kOut, 0);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "surrogate forward: %s", hipGetErrorString(e));
+  return MVPB_OK;
+}
+
+// Backward from net->dout; gradients into net->grads.
+static int sur_backward(mvpb_sur net, int B) {
+  hipStream_t st = net->st;
+  float *P = net->params.p, *G = net->grads.p;
+  hipError_t e = gemm(net->bf16, 1, 0, kFcHid, kOut, B, 1.f, net->h.p, kFcHid, net->dout.p, kOut, 0.f,
+                      G + net->off[10], kOut, st);
+  hipLaunchKernelGGL(column_sums, dim3((kOut + 63) / 64), dim3(256), 0, st, net->dout.p, (size_t)B, kOut, G + net->off[11]);
+  if (e == hipSuccess)
+    e = gemm(net->bf16, 0, 1, B, kFcHid, kOut, 1.f, net->dout.p, kOut, P + net->off[10], kOut, 0.f, net->dh.p, kFcHid, st);
+  hipLaunchKernelGGL(relu_mask, dim3((B * kFcHid + 255) / 256), dim3(256), 0, st, net->dh.p, net->h.p, (size_t)B * kFcHid);
+  if (e == hipSuccess)
+    e = gemm(net->bf16, 1, 0, kFcIn, kFcHid, B, 1.f, net->act[4].p, kFcIn, net->dh.p, kFcHid, 0.f, G + net->off[8],
+             kFcHid, st);
+  hipLaunchKernelGGL(column_sums, dim3((kFcHid + 63) / 64), dim3(256), 0, st, net->dh.p, (size_t)B, kFcHid, G + net->off[9]);
+  if (e == hipSuccess)
+    e = gemm(net->bf16, 0, 1, B, kFcIn, kFcHid, 1.f, net->dh.p, kFcHid, P + net->off[8], kFcHid, 0.f, net->dact.p,
+             kFcIn, st);
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "surrogate backward: %s", hipGetErrorString(e));
+  float *da = net->dact.p, *da_next = net->dact2.p;
+  for (int l = 3; l >= 0; --l) {
+    const Layer &L = kConv[l];
+    const int Ho = L.H / L.s, Wo = L.W / L.s;
+    const size_t rows = (size_t)B * Ho * Wo;
+    const int K = 9 * L.ci;
+    // dz = da * relu'(act[l+1])
+    hipLaunchKernelGGL(relu_mask, dim3((unsigned)std::min<size_t>((rows * L.co + 255) / 256, 65535)), dim3(256), 0, st,
+                       da, net->act[l + 1].p, rows * L.co);
+    // dW = col^T dz (col recomputed), db = column sums of dz
+    const size_t tot = rows * K;
+    hipLaunchKernelGGL(im2col, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 65535)), dim3(256), 0, st,
+                       net->act[l].p, net->col.p, B, L.H, L.W, L.ci, L.s);
+    e = gemm(net->bf16, 1, 0, K, L.co, (int)rows, 1.f, net->col.p, K, da, L.co, 0.f, G + net->off[2 * l], L.co, st);
+    hipLaunchKernelGGL(column_sums, dim3((L.co + 63) / 64), dim3(256), 0, st, da, rows, L.co, G + net->off[2 * l + 1]);
+    if (l > 0 && e == hipSuccess) {
+      // dcol = dz W^T, then gather back onto the input pixels
+      e = gemm(net->bf16, 0, 1, (int)rows, K, L.co, 1.f, da, L.co, P + net->off[2 * l], L.co, 0.f, net->dcol.p, K, st);
+      const size_t tin = (size_t)B * L.H * L.W * L.ci;
+      hipLaunchKernelGGL(col2im, dim3((unsigned)std::min<size_t>((tin + 255) / 256, 65535)), dim3(256), 0, st,
+                         net->dcol.p, da_next, B, L.H, L.W, L.ci, L.s);
+      float *t = da;
+      da = da_next;
+      da_next = t;
+    }
+    if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "surrogate backward: %s", hipGetErrorString(e));
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "surrogate backward: %s", hipGetErrorString(e));
+  return MVPB_OK;
+}
+
+static int stage_inputs(mvpb_sur net, int B, const uint8_t *cells, const float *target, unsigned flags,
+                        const float **tgt_dev) {
+  const bool dev = flags & MVPB_F_DEVICE_PTRS;
+  const uint8_t *c = cells;
+  if (!dev) {
+    hipError_t e = hipMemcpyAsync(net->cells.p, cells, (size_t)B * kPix, hipMemcpyHostToDevice, net->st);
+    if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "upload: %s", hipGetErrorString(e));
+    c = net->cells.p;
+  }
+  hipLaunchKernelGGL(cells_to_float, dim3((B * kPix + 255) / 256), dim3(256), 0, net->st, c, net->act[0].p, B * kPix);
+  if (target) {
+    if (!dev) {
+      hipError_t e = hipMemcpyAsync(net->target.p, target, sizeof(float) * B * kOut, hipMemcpyHostToDevice, net->st);
+      if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "upload: %s", hipGetErrorString(e));
+      *tgt_dev = net->target.p;
+    } else {
+      *tgt_dev = target;
+    }
+  }
+  return MVPB_OK;
+}
+
+static int loss_and_grad_out(mvpb_sur net, int B, const float *tgt, float *loss) {
+  const int n = B * kOut, nblk = 64;
+  hipLaunchKernelGGL(mse_grad, dim3(nblk), dim3(256), 0, net->st, net->out.p, tgt, n, net->dout.p, net->partial.p);
+  float part[64];
+  hipError_t e = hipMemcpyAsync(part, net->partial.p, sizeof part, hipMemcpyDeviceToHost, net->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->st);
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "loss: %s", hipGetErrorString(e));
+  double s = 0.0;
+  for (int i = 0; i < nblk; ++i) s += part[i];
+  if (loss) *loss = (float)(s / n);
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_sur_create(mvpb_ctx ctx, int max_batch, int precision, uint64_t seed, mvpb_sur *out) {
+  if (!ctx || !out) return set_error(MVPB_E_INVALID, "NULL argument");
+  if (ctx_closing(ctx)) return set_error(MVPB_E_INVALID, "context has been destroyed");
+  if (max_batch < 1 || max_batch > 65536) return set_error(MVPB_E_INVALID, "max_batch out of range");
+  if (precision != 0 && precision != 1) return set_error(MVPB_E_INVALID, "precision must be 0 (FP32) or 1 (BF16)");
+  (void)hipSetDevice(ctx_device(ctx));
+  mvpb_sur net = new mvpb_sur_s();
+  net->ctx = ctx;
+  net->st = ctx_stream(ctx);
+  net->max_batch = max_batch;
+  net->bf16 = precision == 1;
+  net->n_params = param_offsets(net->off);
+  const size_t B = max_batch;
+  size_t colmax = 0, actmax = 0;
+  for (int l = 0; l < 4; ++l) {
+    const Layer &L = kConv[l];
+    colmax = std::max(colmax, B * (L.H / L.s) * (L.W / L.s) * 9 * L.ci);
+    actmax = std::max(actmax, B * L.H * L.W * L.ci);
+    actmax = std::max(actmax, B * (L.H / L.s) * (L.W / L.s) * L.co);
+  }
+  hipError_t e = hipSuccess;
+  auto A = [&](Buf<float> &b, size_t n) {
+    if (e == hipSuccess) e = b.alloc(n);
+  };
+  A(net->params, net->n_params);
+  A(net->grads, net->n_params);
+  A(net->m, net->n_params);
+  A(net->v, net->n_params);
+  A(net->act[0], B * kPix);
+  for (int l = 0; l < 4; ++l) A(net->act[l + 1], B * (kConv[l].H / kConv[l].s) * (kConv[l].W / kConv[l].s) * kConv[l].co);
+  A(net->col, colmax);
+  A(net->dcol, colmax);
+  A(net->dact, actmax);
+  A(net->dact2, actmax);
+  A(net->h, B * kFcHid);
+  A(net->dh, B * kFcHid);
+  A(net->out, B * kOut);
+  A(net->dout, B * kOut);
+  A(net->partial, 64);
+  A(net->target, B * kOut);
+  if (e == hipSuccess) e = net->cells.alloc(B * kPix);
+  if (e != hipSuccess) {
+    delete net;
+    return set_error(MVPB_E_NOMEM, "surrogate buffers: %s", hipGetErrorString(e));
+  }
+  // He-uniform weights (counter-based generator), zero biases and moments
+  for (int t = 0; t < 12; ++t) {
+    const int n = (t + 1 < 12 ? net->off[t + 1] : net->n_params) - net->off[t];
+    if (t % 2 == 1) {
+      e = hipMemsetAsync(net->params.p + net->off[t], 0, sizeof(float) * n, net->st);
+    } else {
+      const int fan_in = t < 8 ? 9 * kConv[t / 2].ci : (t == 8 ? kFcIn : kFcHid);
+      hipLaunchKernelGGL(init_uniform, dim3((n + 255) / 256), dim3(256), 0, net->st, net->params.p + net->off[t], n,
+                         sqrtf(6.f / fan_in), (unsigned long long)seed, (unsigned long long)net->off[t]);
+    }
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(net->m.p, 0, sizeof(float) * net->n_params, net->st);
+  if (e == hipSuccess) e = hipMemsetAsync(net->v.p, 0, sizeof(float) * net->n_params, net->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->st);
+  if (e != hipSuccess) {
+    delete net;
+    return set_error(MVPB_E_DEVICE, "surrogate init: %s", hipGetErrorString(e));
+  }
+  ctx_retain(ctx);
+  *out = net;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_sur_destroy(mvpb_sur net) {
+  if (!net) return MVPB_OK;
+  mvpb_ctx ctx = net->ctx;
+  (void)hipSetDevice(ctx_device(ctx));
+  (void)hipStreamSynchronize(net->st);
+  delete net;
+  ctx_release_child(ctx);
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_sur_n_params(mvpb_sur net, int *n) {
+  if (!net || !n) return set_error(MVPB_E_INVALID, "NULL argument");
+  *n = net->n_params;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_sur_get_params(mvpb_sur net, float *host) {
+  if (!net || !host) return set_error(MVPB_E_INVALID, "NULL argument");
+  (void)hipSetDevice(ctx_device(net->ctx));
+  hipError_t e = hipMemcpyAsync(host, net->params.p, sizeof(float) * net->n_params, hipMemcpyDeviceToHost, net->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->st);
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "get params: %s", hipGetErrorString(e));
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_sur_set_params(mvpb_sur net, const float *host) {
+  if (!net || !host) return set_error(MVPB_E_INVALID, "NULL argument");
+  for (int i = 0; i < net->n_params; ++i)
+    if (!isfinite(host[i])) return set_error(MVPB_E_INVALID, "non-finite parameter %d", i);
+  (void)hipSetDevice(ctx_device(net->ctx));
+  hipError_t e = hipMemcpyAsync(net->params.p, host, sizeof(float) * net->n_params, hipMemcpyHostToDevice, net->st);
+  if (e == hipSuccess) e = hipMemsetAsync(net->m.p, 0, sizeof(float) * net->n_params, net->st);
+  if (e == hipSuccess) e = hipMemsetAsync(net->v.p, 0, sizeof(float) * net->n_params, net->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->st);
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "set params: %s", hipGetErrorString(e));
+  net->step = 0;
+  return MVPB_OK;
+}
+
+static int check_batch(mvpb_sur net, int B, const void *cells) {
+  if (!net || !cells) return set_error(MVPB_E_INVALID, "NULL argument");
+  if (B < 1 || B > net->max_batch) return set_error(MVPB_E_INVALID, "batch %d outside [1, %d]", B, net->max_batch);
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_sur_infer(mvpb_sur net, int batch, const uint8_t *cells, float *out, unsigned flags) {
+  int rc = check_batch(net, batch, cells);
+  if (rc) return rc;
+  if (!out) return set_error(MVPB_E_INVALID, "NULL output");
+  (void)hipSetDevice(ctx_device(net->ctx));
+  rc = stage_inputs(net, batch, cells, nullptr, flags, nullptr);
+  if (!rc) rc = sur_forward(net, batch);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(out, net->out.p, sizeof(float) * batch * kOut,
+                                (flags & MVPB_F_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, net->st);
+  if (e == hipSuccess && !(flags & MVPB_F_ASYNC)) e = hipStreamSynchronize(net->st);
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "infer: %s", hipGetErrorString(e));
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_sur_gradients(mvpb_sur net, int batch, const uint8_t *cells, const float *target, float *loss,
+                                  float *grads, unsigned flags) {
+  int rc = check_batch(net, batch, cells);
+  if (rc) return rc;
+  if (!target || !grads) return set_error(MVPB_E_INVALID, "NULL argument");
+  (void)hipSetDevice(ctx_device(net->ctx));
+  const float *tgt = nullptr;
+  rc = stage_inputs(net, batch, cells, target, flags, &tgt);
+  if (!rc) rc = sur_forward(net, batch);
+  if (!rc) rc = loss_and_grad_out(net, batch, tgt, loss);
+  if (!rc) rc = sur_backward(net, batch);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(grads, net->grads.p, sizeof(float) * net->n_params,
+                                (flags & MVPB_F_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, net->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->st);
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "gradients: %s", hipGetErrorString(e));
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_sur_train_step(mvpb_sur net, int batch, const uint8_t *cells, const float *target, float lr,
+                                   float *loss, unsigned flags) {
+  int rc = check_batch(net, batch, cells);
+  if (rc) return rc;
+  if (!target) return set_error(MVPB_E_INVALID, "NULL target");
+  if (!(lr > 0.f) || !isfinite(lr)) return set_error(MVPB_E_INVALID, "learning rate must be positive");
+  (void)hipSetDevice(ctx_device(net->ctx));
+  const float *tgt = nullptr;
+  rc = stage_inputs(net, batch, cells, target, flags, &tgt);
+  if (!rc) rc = sur_forward(net, batch);
+  if (!rc) rc = loss_and_grad_out(net, batch, tgt, loss);
+  if (!rc) rc = sur_backward(net, batch);
+  if (rc) return rc;
+  net->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)net->step), c2 = 1.f - powf(b2, (float)net->step);
+  hipLaunchKernelGGL(adam_step, dim3((net->n_params + 255) / 256), dim3(256), 0, net->st, net->params.p, net->grads.p,
+                     net->m.p, net->v.p, net->n_params, lr, b1, b2, 1e-8f, c1, c2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "adam: %s", hipGetErrorString(e));
+  return MVPB_OK;
+}

@@ -44,6 +44,8 @@ EXPORTS = [
     "mvpb_cell_create_pixels", "mvpb_cell_destroy", "mvpb_plan_create", "mvpb_plan_dofs",
     "mvpb_plan_destroy", "mvpb_solve", "mvpb_solve_batch", "mvpb_structure_factors",
     "mvpb_kpath_square", "mvpb_ctx_profile", "mvpb_ctx_profile_read", "mvpb_plan_create_batch",
+    "mvpb_sur_create", "mvpb_sur_destroy", "mvpb_sur_n_params", "mvpb_sur_get_params", "mvpb_sur_set_params",
+    "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step",
 ]
 N_KERNELS = 11
 
@@ -84,6 +86,15 @@ def load(path: str = LIB_PATH):
     lib.mvpb_kpath_square.argtypes = [I, D]
     lib.mvpb_plan_create_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I,
                                            ctypes.POINTER(P)]
+    F = ctypes.POINTER(ctypes.c_float)
+    lib.mvpb_sur_create.argtypes = [P, I, I, ctypes.c_uint64, ctypes.POINTER(P)]
+    lib.mvpb_sur_destroy.argtypes = [P]
+    lib.mvpb_sur_n_params.argtypes = [P, ctypes.POINTER(I)]
+    lib.mvpb_sur_get_params.argtypes = [P, F]
+    lib.mvpb_sur_set_params.argtypes = [P, F]
+    lib.mvpb_sur_infer.argtypes = [P, I, P, P, ctypes.c_uint]
+    lib.mvpb_sur_gradients.argtypes = [P, I, P, P, F, P, ctypes.c_uint]
+    lib.mvpb_sur_train_step.argtypes = [P, I, P, P, ctypes.c_float, F, ctypes.c_uint]
     lib.mvpb_ctx_profile.argtypes = [P, I]
     lib.mvpb_ctx_profile_read.argtypes = [P, I, D, ctypes.POINTER(ctypes.c_longlong),
                                           ctypes.POINTER(ctypes.c_char_p)]
@@ -318,3 +329,81 @@ class Plan:
         Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, 2))
         _check(lib.mvpb_solve(self.h, Q.shape[0], _dptr(Q), n_bands, ctypes.c_void_p(omega_ptr), None,
                               flags | F_DEVICE_PTRS))
+
+
+class Surrogate:
+    """Band-structure screening network trained and run by the library's kernels.
+
+    precision 0: FP32 products; 1: BF16 matrix-core products with FP32
+    accumulation.  cells: uint8 [B, 32, 32]; targets / outputs float32 [B, 400].
+    """
+    N_OUT = 400
+
+    def __init__(self, ctx: Context, max_batch: int = 256, precision: int = 1, seed: int = 0):
+        lib = load()
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib.mvpb_sur_create(ctx.h, max_batch, precision, seed, ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int()
+        _check(lib.mvpb_sur_n_params(h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if self.h:
+            load().mvpb_sur_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.n_params, dtype=np.float32)
+        _check(load().mvpb_sur_get_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        _check(load().mvpb_sur_set_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    @staticmethod
+    def _cells(cells):
+        return np.ascontiguousarray(np.asarray(cells, dtype=np.uint8).reshape(-1, 32 * 32))
+
+    def infer(self, cells) -> np.ndarray:
+        c = self._cells(cells)
+        out = np.zeros((c.shape[0], self.N_OUT), dtype=np.float32)
+        _check(load().mvpb_sur_infer(self.h, c.shape[0], ctypes.c_void_p(c.ctypes.data),
+                                     ctypes.c_void_p(out.ctypes.data), 0))
+        return out
+
+    def infer_device(self, batch: int, cells_ptr: int, out_ptr: int):
+        _check(load().mvpb_sur_infer(self.h, batch, ctypes.c_void_p(cells_ptr), ctypes.c_void_p(out_ptr),
+                                     F_DEVICE_PTRS))
+
+    def gradients(self, cells, target):
+        c = self._cells(cells)
+        t = np.ascontiguousarray(np.asarray(target, dtype=np.float32).reshape(c.shape[0], self.N_OUT))
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(load().mvpb_sur_gradients(self.h, c.shape[0], ctypes.c_void_p(c.ctypes.data),
+                                         ctypes.c_void_p(t.ctypes.data), ctypes.byref(loss),
+                                         ctypes.c_void_p(g.ctypes.data), 0))
+        return float(loss.value), g
+
+    def train_step(self, cells, target, lr: float = 1e-3) -> float:
+        c = self._cells(cells)
+        t = np.ascontiguousarray(np.asarray(target, dtype=np.float32).reshape(c.shape[0], self.N_OUT))
+        loss = ctypes.c_float()
+        _check(load().mvpb_sur_train_step(self.h, c.shape[0], ctypes.c_void_p(c.ctypes.data),
+                                          ctypes.c_void_p(t.ctypes.data), lr, ctypes.byref(loss), 0))
+        return float(loss.value)
+
+    def train_step_device(self, batch: int, cells_ptr: int, target_ptr: int, lr: float = 1e-3) -> float:
+        loss = ctypes.c_float()
+        _check(load().mvpb_sur_train_step(self.h, batch, ctypes.c_void_p(cells_ptr), ctypes.c_void_p(target_ptr),
+                                          lr, ctypes.byref(loss), F_DEVICE_PTRS))
+        return float(loss.value)

@@ -1,0 +1,86 @@
+"""GPU surrogate network against its FP64 NumPy reference: forward pass,
+gradients (per tensor, relative 2-norm), and a short training run.
+Bars: FP32 products 1e-4, BF16 products 2e-2."""
+import numpy as np
+import pytest
+
+from oracle import surrogate_ref as sr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1310_6380_amd import mvpb
+    c = mvpb.Context(0)
+    yield c
+    c.close()
+
+
+def _batch(B, seed):
+    rng = np.random.default_rng(seed)
+    cells = (rng.uniform(size=(B, 32, 32)) > 0.5).astype(np.uint8)
+    target = rng.uniform(0.2, 1.5, (B, sr.N_OUT)).astype(np.float32)
+    return cells, target
+
+
+def _nudge_biases(theta, rng):
+    o = 0
+    for s in sr.param_shapes():
+        n = int(np.prod(s))
+        if len(s) == 1:
+            theta[o:o + n] = rng.uniform(-0.2, 0.2, n)
+        o += n
+    return theta
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
+def test_forward_matches_reference(ctx, prec, tol):
+    from paper_1310_6380_amd import mvpb
+    print("surrogate forward", prec, flush=True)
+    net = mvpb.Surrogate(ctx, max_batch=16, precision=prec, seed=11)
+    theta = _nudge_biases(net.get_params().astype(np.float64), np.random.default_rng(0))
+    net.set_params(theta)
+    theta = net.get_params().astype(np.float64)          # exactly the FP32 values the GPU holds
+    cells, _ = _batch(16, 1)
+    out = net.infer(cells)
+    ref = sr.forward(theta, cells.astype(np.float64))
+    err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    print("  rel err", err, flush=True)
+    assert err <= tol
+    net.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
+def test_gradients_match_reference(ctx, prec, tol):
+    from paper_1310_6380_amd import mvpb
+    print("surrogate gradients", prec, flush=True)
+    net = mvpb.Surrogate(ctx, max_batch=8, precision=prec, seed=5)
+    theta = _nudge_biases(net.get_params().astype(np.float64), np.random.default_rng(2))
+    net.set_params(theta)
+    theta = net.get_params().astype(np.float64)
+    cells, target = _batch(8, 3)
+    loss, g = net.gradients(cells, target)
+    L, gref = sr.gradients(theta, cells.astype(np.float64), target.astype(np.float64))
+    assert abs(loss - L) <= tol * L
+    o = 0
+    for s in sr.param_shapes():
+        n = int(np.prod(s))
+        a, b = g[o:o + n], gref[o:o + n]
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print("  tensor", s, "rel err", err, flush=True)
+        assert err <= tol, (s, err)
+        o += n
+    net.close()
+
+
+def test_training_reduces_loss(ctx):
+    from paper_1310_6380_amd import mvpb
+    net = mvpb.Surrogate(ctx, max_batch=32, precision=1, seed=7)
+    cells, target = _batch(32, 9)
+    first = net.train_step(cells, target, 1e-3)
+    for _ in range(40):
+        last = net.train_step(cells, target, 1e-3)
+    print("loss", first, "->", last, flush=True)
+    assert last < 0.5 * first
+    net.close()
