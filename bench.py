@@ -136,6 +136,70 @@ def variant_batched(mvpb, ctx, steps, warmup):
             "precision": "fp64"}, out["om"], cfg
 
 
+def variant_surrogate(mvpb, ctx, n_train=1024, n_test=256, epochs=15):
+    """Binary GRF cells on 32x32 (correlation length 4 px, fill U[0.2,0.8]),
+    labels by the batched FP64 solver at 15x15 plane waves, 40 k, 10 bands;
+    network trained by the library's kernels (BF16 matrix cores); inference
+    timed on batches of 4096 cells.  One "solve" = one cell at one k."""
+    from paper_1310_6380_amd import screening as sc
+    from synth import config4_cells
+    cells = config4_cells(0, n_train + n_test)
+    t0 = time.perf_counter()
+    y = sc.label_cells(ctx, cells)
+    t_label = time.perf_counter() - t0
+    progress("surrogate labels", cells.shape[0], "cells in", round(t_label, 1), "s")
+    net = mvpb.Surrogate(ctx, max_batch=4096, precision=1, seed=0)
+    t0 = time.perf_counter()
+    sc.train(net, cells[:n_train], y[:n_train], epochs=epochs, batch=256, lr=1e-3, log=progress)
+    t_train = time.perf_counter() - t0
+    err = sc.relative_errors(net.infer(cells[n_train:]), y[n_train:])
+    batch = np.resize(cells[n_train:], (4096, 32, 32))
+    dcells = mvpb.DeviceBuffer(batch.size).upload(batch)
+    dout = mvpb.DeviceBuffer(4 * 4096 * 400)
+
+    def step():
+        net.infer_device(4096, dcells.value, dout.value)
+
+    dt = run_timed(step, 5, 2, mvpb, "surrogate inference")
+    stats = sc.screen(ctx, net, cells[:64], b=2, rounds=2, n_candidates=4096, top_k=16, log=progress)
+    net.close()
+    return {"value": 4096 * sc.N_K / dt, "unit": "solves/s", "cells_per_s": 4096 / dt,
+            "ms_per_batch_4096": 1e3 * dt, "precision": "bf16 matrix cores, fp32 accumulate",
+            "held_out_rel_err": {"p50": float(np.median(err)), "p99": float(np.percentile(err, 99)),
+                                 "max": float(err.max()), "cells": int(n_test)},
+            "train": {"cells": n_train, "epochs": epochs, "seconds": t_train},
+            "labels": {"cells": int(cells.shape[0]), "solves_per_s": cells.shape[0] * sc.N_K / t_label},
+            "screening": {"candidates": stats["predicted"], "verified": stats["verified"],
+                          "fallback_rate": stats["fallbacks"] / max(1, stats["verified"]),
+                          "best_verified_gap_b2_b3": stats["best_gap"],
+                          "surrogate_s_per_cell": stats["t_surrogate"] / stats["predicted"],
+                          "solve_s_per_cell": stats["t_solve"] / stats["verified"]}}
+
+
+def variant_precision(mvpb, ctx):
+    """4096 Voronoi phases on 128x128, 31x31 plane waves (2N = 1922), 60 k,
+    24 bands: FP64, FP32 and BF16 structure factors, and FP32 reduction with
+    FP64 Rayleigh-Ritz.  One step per precision after one warm-up."""
+    from synth import config3
+    cfg = config3()
+    cell, M, Q, nb = cfg["cell"], cfg["M"], cfg["Q"], cfg["n_bands"]
+    dcell = ctx.cell(cell.phase, cell.props, cell.lattice)
+    res, oms = {}, {}
+    for name, prec in (("fp64", mvpb.PREC_FP64), ("sf_fp32", mvpb.PREC_SF_FP32), ("sf_bf16", mvpb.PREC_SF_BF16),
+                       ("sf_fp32_eig_fp32_rr64", mvpb.PREC_SF_FP32 | mvpb.PREC_EIG_FP32_RR64)):
+        out = {}
+
+        def step():
+            plan = dcell.plan(M, M, prec)
+            out["om"] = plan.solve(Q, nb)
+            plan.close()
+
+        dt = run_timed(step, 1, 1, mvpb, "precision " + name)
+        res[name] = {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt}
+        oms[name] = out["om"]
+    return res, oms, cfg
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,10 +263,12 @@ def main():
 
     omega = om_dev.to_numpy(np.float64, (Q.shape[0], nb))
     variants = {}
-    om_mixed = om_batch = cfg2 = None
+    om_mixed = om_batch = cfg2 = om_prec = cfg3 = None
     if not args.no_variants:
         variants["mixed_1132_phase"], om_mixed = variant_mixed(mvpb, ctx, dcell, M, Q, nb, args.steps, args.warmup)
         variants["batched_256_cells"], om_batch, cfg2 = variant_batched(mvpb, ctx, max(1, args.steps // 2), 1)
+        variants["surrogate_grf_cells"] = variant_surrogate(mvpb, ctx)
+        variants["precision_4096_phase"], om_prec, cfg3 = variant_precision(mvpb, ctx)
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -224,6 +290,15 @@ def main():
             variants["mixed_1132_phase"]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om_mixed[ref_idx], ref)
         if om_batch is not None:
             variants["batched_256_cells"]["max_rel_freq_err_vs_fp64_oracle"] = batched_error(cfg2, om_batch)
+        if om_prec is not None:
+            from oracle import mixed_oracle as mo
+            from oracle.compare import band_error
+            c3 = cfg3["cell"]
+            kk = [7, 41]
+            progress("cpu baseline: oracle on the 4096-phase cell,", len(kk), "k-points")
+            ref3, _ = mo.bands(c3.phase, c3.props, c3.lattice, cfg3["M"], cfg3["M"], cfg3["Q"][kk], cfg3["n_bands"])
+            for name, om in om_prec.items():
+                variants["precision_4096_phase"][name]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om[kk], ref3)
     print(json.dumps(out), flush=True)
 
 

@@ -138,6 +138,14 @@ class DeviceBuffer:
     def value(self) -> int:
         return int(self.ptr.value)
 
+    def upload(self, arr):
+        a = np.ascontiguousarray(arr)
+        assert a.nbytes <= self.nbytes
+        rc = _hiprt().hipMemcpy(self.ptr, a.ctypes.data, a.nbytes, 1)  # host to device
+        if rc != 0:
+            raise MvpbError(E_DEVICE, f"hipMemcpy failed with {rc}")
+        return self
+
     def to_numpy(self, dtype, shape) -> np.ndarray:
         out = np.empty(shape, dtype=dtype)
         assert out.nbytes <= self.nbytes

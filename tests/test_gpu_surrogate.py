@@ -84,3 +84,49 @@ def test_training_reduces_loss(ctx):
     print("loss", first, "->", last, flush=True)
     assert last < 0.5 * first
     net.close()
+
+
+def test_labels_training_and_screening(ctx):
+    """The workflow on a small scale: labels from the batched solver (checked
+    against the oracle), training on shifted batches, held-out error, and one
+    screening round whose top candidates are verified by the plain solve."""
+    from oracle import mixed_oracle as mo
+    from oracle.compare import band_error
+    from paper_1310_6380_amd import mvpb, screening as sc
+    from synth import config4_cells, kpath_gxmg
+
+    cells = config4_cells(0, 96)
+    print("labels", flush=True)
+    y = sc.label_cells(ctx, cells)
+    assert y.shape == (96, 400) and np.all(np.isfinite(y))
+    Q = kpath_gxmg(40)
+    props = np.array([sc.MATRIX, sc.INCLUSION])
+    for i in (0, 1):
+        ref, _ = mo.bands(cells[i].astype(np.int32), props, np.eye(2), 7, 7, Q[[0, 15, 30]], 10)
+        got = y[i].reshape(40, 10)[[0, 15, 30]].astype(np.float64) * 2 * np.pi * sc.C_REF
+        # labels are stored as float32 (the solve itself is FP64)
+        assert band_error(got, ref) <= 1e-6
+    net = mvpb.Surrogate(ctx, max_batch=4096, precision=1, seed=1)
+    losses = sc.train(net, cells[:64], y[:64], epochs=10, batch=32, lr=2e-3)
+    assert losses[-1] < losses[0]
+    err = sc.relative_errors(net.infer(cells[64:]), y[64:])
+    print("held-out median rel err", float(np.median(err)), flush=True)
+    assert np.all(np.isfinite(err))
+    stats = sc.screen(ctx, net, cells[:16], b=2, rounds=1, n_candidates=512, top_k=4)
+    assert stats["verified"] == 4 and 0 <= stats["fallbacks"] <= 4
+    per_pred = stats["t_surrogate"] / stats["predicted"]
+    per_solve = stats["t_solve"] / stats["verified"]
+    print("surrogate s/cell", per_pred, "solve s/cell", per_solve, flush=True)
+    assert per_solve > 10 * per_pred
+    net.close()
+
+
+def test_screening_fallback_with_zero_tolerance(ctx):
+    """A zero tolerance sends every verified candidate to the plain solve."""
+    from paper_1310_6380_amd import mvpb, screening as sc
+    from synth import config4_cells
+    cells = config4_cells(100, 116)
+    net = mvpb.Surrogate(ctx, max_batch=256, precision=1, seed=2)
+    stats = sc.screen(ctx, net, cells, b=2, rounds=1, n_candidates=64, top_k=3, tol=0.0)
+    assert stats["fallbacks"] == stats["verified"] == 3
+    net.close()
