@@ -187,13 +187,14 @@ int mvpb_sur_train_step(mvpb_sur net, int batch, const uint8_t *cells, const flo
  * context is bracketed by HIP events on the context stream and its device
  * time accumulated per kernel family.  Kernel ids: 0 structure_factors,
  * 1 toeplitz_scatter, 2 potrf_trtri, 3 zgemm, 4 combine_coefficients,
- * 5 form_operator, 6 hetrd_panel, 7 hetrd_update, 8 tridiag_eig,
- * 9 backtransform, 10 rayleigh_ritz (MVPB_N_KERNELS in total).  Launches
+ * 5 form_operator, 6 he2hb_panel, 7 he2hb_hemm, 8 he2hb_wform,
+ * 9 he2hb_her2k, 10 hb2st, 11 tridiag_eig, 12 backtransform,
+ * 13 rayleigh_ritz (MVPB_N_KERNELS in total).  Launches
  * inside the HIP graph of mvpb_solve_batch are not timed.
  * mvpb_ctx_profile(ctx, 1) clears the totals and starts timing, 0 stops.
  * mvpb_ctx_profile_read waits for the recorded events and returns the total
  * milliseconds, the number of launches and a static name string. */
-#define MVPB_N_KERNELS 11
+#define MVPB_N_KERNELS 14
 int mvpb_ctx_profile(mvpb_ctx ctx, int enable);
 int mvpb_ctx_profile_read(mvpb_ctx ctx, int kernel, double *total_ms, long long *launches, const char **name);
 

@@ -553,47 +553,77 @@ extern "C" int mvpb_plan_destroy(mvpb_plan p) {
 // ---------------------------------------------------------------------------
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static size_t item_bytes(int n, int nb, bool fp32) {
+// Sizes of the per-item buffers, in carving order.
+static void item_layout(int n, int nb, bool fp32, size_t *sz, int *count) {
   const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
+  const size_t nrb = (size_t)(n + 63) / 64, npan = (size_t)(n + HB - 1) / HB;
+  const size_t nrefl = (size_t)refl_total(n);
+  int k = 0;
+  sz[k++] = es * (size_t)n * n;                  // A
+  sz[k++] = sizeof(cd) * (size_t)n * n;          // Ak
+  sz[k++] = es * (size_t)n * HB;                 // X0
+  sz[k++] = es * (size_t)n * HB;                 // Wm
+  sz[k++] = es * nrb * HB * HB;                  // M0p
+  sz[k++] = es * npan * HB * HB;                 // T1
+  sz[k++] = es * (size_t)n * (2 * HB + 1);       // WB
+  sz[k++] = es * nrefl * HB;                     // V2
+  sz[k++] = es * nrefl;                          // tau2
+  sz[k++] = sizeof(double) * n;                  // d
+  sz[k++] = sizeof(double) * n;                  // e
+  sz[k++] = sizeof(int);                         // flag
+  sz[k++] = sizeof(double) * (size_t)n * nb;     // X
+  sz[k++] = sizeof(double) * (size_t)5 * n * nb; // lu
+  sz[k++] = sizeof(double) * nb;                 // lam_t
+  sz[k++] = sizeof(double) * nb;                 // lam
+  sz[k++] = sizeof(double) * nb;                 // omega
+  sz[k++] = sizeof(cd) * (size_t)n * nb;         // Y
+  sz[k++] = sizeof(cd) * (size_t)n * nb;         // Z
+  sz[k++] = fp32 ? sizeof(cf) * (size_t)n * nb : 0;  // Yb (FP32 path only)
+  *count = k;
+}
+
+static size_t item_bytes(int n, int nb, bool fp32) {
+  size_t sz[32];
+  int cnt = 0;
+  item_layout(n, nb, fp32, sz, &cnt);
   size_t s = 0;
-  s += align256(es * (size_t)n * n);                       // A
-  s += align256(sizeof(cd) * (size_t)n * n);               // Ak
-  s += align256(es * (size_t)n * PANEL);                   // W
-  s += align256(es * (size_t)n * 2 * PANEL_SLOTS);         // Yw
-  s += align256(sizeof(double) * n) * 2;                   // d, e
-  s += align256(es * n);                                   // tau
-  s += align256(sizeof(double) * (size_t)n * nb);          // X
-  s += align256(sizeof(double) * (size_t)5 * n * nb);      // lu
-  s += align256(sizeof(double) * nb) * 3;                  // lam_t, lam, omega
-  s += align256(sizeof(cd) * (size_t)n * nb) * 2;          // Y, Z
-  if (fp32) s += align256(sizeof(cf) * (size_t)n * nb);    // Yb
+  for (int i = 0; i < cnt; ++i) s += align256(sz[i]);
   return s;
 }
 
 static EigItem carve_item(char *base, int n, int nb, bool fp32) {
-  const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
+  size_t sz[32];
+  int cnt = 0;
+  item_layout(n, nb, fp32, sz, &cnt);
   EigItem it{};
   size_t o = 0;
-  auto take = [&](size_t b) {
+  int k = 0;
+  auto take = [&]() {
     char *p = base + o;
-    o += align256(b);
+    o += align256(sz[k++]);
     return p;
   };
-  it.A = take(es * (size_t)n * n);
-  it.Ak = (cd *)take(sizeof(cd) * (size_t)n * n);
-  it.W = take(es * (size_t)n * PANEL);
-  it.Yw = take(es * (size_t)n * 2 * PANEL_SLOTS);
-  it.d = (double *)take(sizeof(double) * n);
-  it.e = (double *)take(sizeof(double) * n);
-  it.tau = take(es * n);
-  it.X = (double *)take(sizeof(double) * (size_t)n * nb);
-  it.lu = (double *)take(sizeof(double) * (size_t)5 * n * nb);
-  it.lam_t = (double *)take(sizeof(double) * nb);
-  it.lam = (double *)take(sizeof(double) * nb);
-  it.omega = (double *)take(sizeof(double) * nb);
-  it.Y = (cd *)take(sizeof(cd) * (size_t)n * nb);
-  it.Z = (cd *)take(sizeof(cd) * (size_t)n * nb);
-  it.Yb = fp32 ? (void *)take(sizeof(cf) * (size_t)n * nb) : (void *)it.Y;
+  it.A = take();
+  it.Ak = (cd *)take();
+  it.X0 = take();
+  it.Wm = take();
+  it.M0p = take();
+  it.T1 = take();
+  it.WB = take();
+  it.V2 = take();
+  it.tau2 = take();
+  it.d = (double *)take();
+  it.e = (double *)take();
+  it.flag = (int *)take();
+  it.X = (double *)take();
+  it.lu = (double *)take();
+  it.lam_t = (double *)take();
+  it.lam = (double *)take();
+  it.omega = (double *)take();
+  it.Y = (cd *)take();
+  it.Z = (cd *)take();
+  char *yb = take();
+  it.Yb = fp32 ? (void *)yb : (void *)it.Y;
   return it;
 }
 
@@ -654,11 +684,12 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   const int n_items = (int)jobs.size();
   if (n_items == 0) return MVPB_OK;
   size_t total = 0;
-  int n_max = 0;
+  int n_max = 0, n_min = 1 << 30;
   for (const Job &j : jobs) {
     const int n = 2 * j.plan->N;
     total += item_bytes(n, nb, fp32);
     n_max = std::max(n_max, n);
+    n_min = std::min(n_min, n);
   }
   if (ctx->cap && total > ctx->cap)
     return set_err(MVPB_E_NOMEM, "workspace %zu bytes exceeds the cap of %zu bytes", total, ctx->cap);
@@ -694,9 +725,9 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
 
   auto enqueue = [&]() -> hipError_t {
     hipError_t e = launch_form_operator(d_items, n_items, n_max, fp32, st);
-    if (e == hipSuccess) e = launch_hetrd(d_items, n_items, n_max, fp32, st);
+    if (e == hipSuccess) e = launch_reduce(d_items, n_items, n_min, n_max, fp32, st);
     if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, st);
-    if (e == hipSuccess) e = launch_backtransform(d_items, n_items, fp32, st);
+    if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_max, nb, fp32, st);
     if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, st);
     return e;
   };
@@ -924,8 +955,9 @@ extern "C" int mvpb_kpath_square(int n_k, double *Q) {
 // kernel timers
 // ---------------------------------------------------------------------------
 static const char *k_names[K_COUNT] = {"structure_factors", "toeplitz_scatter", "potrf_trtri", "zgemm",
-                                       "combine_coefficients", "form_operator", "hetrd_panel", "hetrd_update",
-                                       "tridiag_eig", "backtransform", "rayleigh_ritz"};
+                                       "combine_coefficients", "form_operator", "he2hb_panel", "he2hb_hemm",
+                                       "he2hb_wform", "he2hb_her2k", "hb2st", "tridiag_eig", "backtransform",
+                                       "rayleigh_ritz"};
 
 extern "C" int mvpb_ctx_profile(mvpb_ctx ctx, int enable) {
   int rc = check_ctx(ctx);

@@ -19,42 +19,48 @@ void ctx_release_child(mvpb_ctx c);  // ... and lets it go
 // Largest reduced-operator order handled by the eigensolver kernels
 // (2N <= MAX_N; vectors of this length are staged in LDS).
 constexpr int MAX_N = 4096;
-// Panel width of the blocked reduction to tridiagonal form.
-constexpr int PANEL = 32;
-// Waves of the panel kernel (one partial-sum slot each).
-constexpr int PANEL_SLOTS = 16;
+// Half bandwidth of the band form produced by the first reduction stage
+// (also the length of the bulge-chasing reflectors of the second stage).
+constexpr int HB = 16;
+// LDS budget of the back-transform's eigenvector block.
+constexpr int BT_LDS_BYTES = 128 * 1024;
 // Largest number of bands per solve (Rayleigh-Ritz block in LDS).
 constexpr int RR_MAX_BANDS = 64;
 
 // One (cell, k) work item of the eigensolve.  All pointers are device memory
-// owned by the solve that built the item table.
+// owned by the solve that built the item table.  Buffers marked (R) hold
+// complex numbers of the reduction precision: complex double on the FP64
+// path, complex float on the FP32 one.
 struct EigItem {
   // operator formation
   const cd *coef;   // 15 coefficient matrices, N x N each (plan-owned)
   double kap1, kap2;
   int N;            // plane waves; the operator has order n = 2N
   int nb;           // bands wanted
-  // reduction to tridiagonal form
-  // Buffers marked (R) hold complex numbers of the reduction precision:
-  // complex double on the FP64 path, complex float on the FP32 one.
-  void *A;          // (R) n x n working matrix; holds the Householder vectors afterwards
+  // stage 1: dense -> band
+  void *A;          // (R) n x n working matrix; the panels' reflectors stay below the band
   cd *Ak;           // n x n kept copy of C(k) for Rayleigh-Ritz (always FP64)
-  void *W;          // (R) n x PANEL panel workspace
-  void *Yw;         // (R) n x 2*PANEL_SLOTS per-wave partial sums of the panel kernel
+  void *X0;         // (R) n x HB product of the trailing matrix with the panel reflectors
+  void *Wm;         // (R) n x HB rank-2HB update factor
+  void *M0p;        // (R) ceil(n/64) x HB x HB Gram partials
+  void *T1;         // (R) ceil(n/HB) x HB x HB compact-WY factors of the panels
+  // stage 2: band -> tridiagonal
+  void *WB;         // (R) n x (2 HB + 1) band working copy
+  void *V2;         // (R) reflectors of the bulge chasing, HB entries each
+  void *tau2;       // (R) their scalars
   double *d;        // n diagonal
   double *e;        // n off-diagonal (real)
-  void *tau;        // (R) n reflector scalars
+  int *flag;        // nonzero: a kernel gave up waiting (diagnostic)
   // tridiagonal eigenproblem
-  double *X;        // n x nb eigenvectors of the tridiagonal matrix
+  double *X;        // n x nb eigenvectors of the tridiagonal matrix (row-major)
   double *lu;       // 5 n x nb factorisation scratch
   double *lam_t;    // nb eigenvalues of the tridiagonal matrix
   // back-transform and refinement
   cd *Y;            // n x nb eigenvectors of C(k) (FP64, input of Rayleigh-Ritz)
-  void *Yb;         // (R) back-transform working vectors (== Y on the FP64 path)
+  void *Yb;         // (R) back-transform output (== Y on the FP64 path)
   cd *Z;            // n x nb scratch (C Y)
   double *lam;      // nb refined eigenvalues (lambda = omega^2)
   double *omega;    // nb output frequencies (device)
-  int status;       // reserved
 };
 
 // assembly.hip
@@ -89,11 +95,18 @@ struct GemmBatch {
 hipError_t launch_zgemm(Op opA, Op opB, int M, int N, int K, cd alpha, GemmBatch bt, cd beta, int count,
                         hipStream_t st);
 
+// band.hip
+hipError_t init_band_attributes();
+// Stage 1 (dense -> band) and stage 2 (band -> tridiagonal d, e) for every item.
+hipError_t launch_reduce(const EigItem *items, int n_items, int n_min, int n_max, bool fp32, hipStream_t st);
+// Eigenvectors of C(k) from those of the tridiagonal matrix (X -> Y).
+hipError_t launch_backtransform(const EigItem *items, int n_items, int n_max, int nb, bool fp32, hipStream_t st);
+int backtransform_cols(int n_max, bool fp32);
+long long refl_total(int n);   // number of stage-2 reflectors of an item of order n
+
 // eigen.hip
 hipError_t init_kernel_attributes();  // once per device, before the first launch
-hipError_t launch_hetrd(const EigItem *items, int n_items, int n_max, bool fp32, hipStream_t st);
 hipError_t launch_tridiag_eig(const EigItem *items, int n_items, hipStream_t st);
-hipError_t launch_backtransform(const EigItem *items, int n_items, bool fp32, hipStream_t st);
 hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, hipStream_t st);
 
 }  // namespace mvpb

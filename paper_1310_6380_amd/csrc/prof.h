@@ -14,8 +14,11 @@ enum KernelId {
   K_GEMM,
   K_COMBINE,
   K_FORM,
-  K_HETRD_PANEL,
-  K_HETRD_UPDATE,
+  K_PANEL,
+  K_HEMM,
+  K_WFORM,
+  K_HER2K,
+  K_HB2ST,
   K_TRIDIAG,
   K_BACKTRANSFORM,
   K_RR,

@@ -47,7 +47,7 @@ EXPORTS = [
     "mvpb_sur_create", "mvpb_sur_destroy", "mvpb_sur_n_params", "mvpb_sur_get_params", "mvpb_sur_set_params",
     "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step",
 ]
-N_KERNELS = 11
+N_KERNELS = 14
 
 
 class MvpbError(RuntimeError):
