@@ -578,6 +578,8 @@ static void item_layout(int n, int nb, bool fp32, size_t *sz, int *count) {
   sz[k++] = sizeof(double) * nb;                 // omega
   sz[k++] = sizeof(cd) * (size_t)n * nb;         // Y
   sz[k++] = sizeof(cd) * (size_t)n * nb;         // Z
+  sz[k++] = sizeof(cd) * ((size_t)(n + 63) / 64) * 2 * nb * nb;  // Gp
+  sz[k++] = sizeof(cd) * (size_t)nb * nb;        // Lr
   sz[k++] = fp32 ? sizeof(cf) * (size_t)n * nb : 0;  // Yb (FP32 path only)
   *count = k;
 }
@@ -622,6 +624,8 @@ static EigItem carve_item(char *base, int n, int nb, bool fp32) {
   it.omega = (double *)take();
   it.Y = (cd *)take();
   it.Z = (cd *)take();
+  it.Gp = (cd *)take();
+  it.Lr = (cd *)take();
   char *yb = take();
   it.Yb = fp32 ? (void *)yb : (void *)it.Y;
   return it;
@@ -726,9 +730,9 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   auto enqueue = [&]() -> hipError_t {
     hipError_t e = launch_form_operator(d_items, n_items, n_max, fp32, st);
     if (e == hipSuccess) e = launch_reduce(d_items, n_items, n_min, n_max, fp32, st);
-    if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, st);
+    if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, n_max, nb, st);
     if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_max, nb, fp32, st);
-    if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, st);
+    if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, n_max, nb, st);
     return e;
   };
   if (use_graph) {

@@ -31,7 +31,7 @@ namespace mvpb {
 constexpr int PQ_THREADS = 512;
 constexpr int PQ_WAVES = PQ_THREADS / 64;
 constexpr int HB_LDB = 2 * HB + 1;   // stored subdiagonals of the band copy (0 .. 2 HB)
-constexpr int BT_THREADS = 256;
+constexpr int BT_THREADS = 512;
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
 constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
@@ -350,12 +350,21 @@ MVPB_DEV cx<R> panel_v(const cx<R> *Vp, size_t ld, int r, int t, int m, int kq) 
 // partial V[rb]^H X0[rb] (HB x HB) of the row block.
 // ---------------------------------------------------------------------------
 template <typename R>
+MVPB_DEV cx<R> hemm_elem(const cx<R> *A22, size_t ld, int m, int gr, int gc) {
+  // A22(gr, gc) of the Hermitian trailing matrix from its lower triangle
+  if (gr >= m || gc >= m) return czero<R>();
+  if (gr > gc) return A22[(size_t)gc * ld + gr];
+  if (gr < gc) return conj(A22[(size_t)gr * ld + gc]);
+  return mkc<R>(A22[(size_t)gc * ld + gr].re, R(0));
+}
+
+template <typename R>
 __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ items, int p) {
   typedef cx<R> C;
   constexpr int TC = 32;
+  constexpr int PER = 64 * TC / 256;   // tile elements loaded per thread
   __shared__ C tile[TC][65];        // tile[cc][rr] = A22(rb*64 + rr, cb*TC + cc)
   __shared__ C Vc[TC][HB];          // V rows of the column block
-  __shared__ C Vr[64][HB + 1];      // V rows of the row block
   const EigItem it = items[blockIdx.y];
   const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
   const int rb = blockIdx.x;
@@ -366,48 +375,45 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
   const C *__restrict__ Vp = (const C *)it.A + (size_t)c0 * ld + (c0 + HB);
   const int tid = threadIdx.x, r = tid & 63, ks = tid >> 6;
   const int r0 = rb * 64;
-  for (int e = tid; e < 64 * HB; e += 256) {
-    const int i = e & 63, t = e >> 6;
-    Vr[i][t] = panel_v<R>(Vp, ld, r0 + i, t, m, kq);
-  }
+  // Element e = tid + 256 u of a 64 x TC tile: below the row block it is read
+  // down a stored column (rr fastest), right of it across (cc fastest, then
+  // conjugate-transposed) so that both reads are coalesced.
+  C nxt[PER], vnx[2];
+  auto fetch = [&](int cb0) {
+    const bool above = cb0 >= r0 + 64;   // entirely right of the diagonal block
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      int rr, cc;
+      if (above) { cc = e % TC; rr = e / TC; } else { rr = e & 63; cc = e >> 6; }
+      nxt[u] = hemm_elem<R>(A22, ld, m, r0 + rr, cb0 + cc);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + 256 * u;
+      vnx[u] = panel_v<R>(Vp, ld, cb0 + e % TC, e / TC, m, kq);
+    }
+  };
   C acc[HB];
 #pragma unroll
   for (int t = 0; t < HB; ++t) acc[t] = czero<R>();
+  fetch(0);
   for (int cb0 = 0; cb0 < m; cb0 += TC) {
-    for (int e = tid; e < TC * HB; e += 256) {
-      const int i = e % TC, t = e / TC;
-      Vc[i][t] = panel_v<R>(Vp, ld, cb0 + i, t, m, kq);
+    const bool above = cb0 >= r0 + 64;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      int rr, cc;
+      if (above) { cc = e % TC; rr = e / TC; } else { rr = e & 63; cc = e >> 6; }
+      tile[cc][rr] = nxt[u];
     }
-    // tile element (rr, cc): global row R = r0 + rr, column Cc = cb0 + cc
-    if (cb0 + TC <= r0) {
-      // entirely in the lower triangle
-      for (int e = tid; e < 64 * TC; e += 256) {
-        const int rr = e & 63, cc = e >> 6;
-        const int gr = r0 + rr, gc = cb0 + cc;
-        tile[cc][rr] = (gr < m && gc < m) ? A22[(size_t)gc * ld + gr] : czero<R>();
-      }
-    } else if (cb0 >= r0 + 64) {
-      // entirely above: read the stored block rows cb0.., columns r0.., conj-transposed
-      for (int e = tid; e < 64 * TC; e += 256) {
-        const int i = e % TC, jc = e / TC;   // stored row cb0+i, stored column r0+jc
-        const int sr = cb0 + i, sc = r0 + jc;
-        tile[i][jc] = (sr < m && sc < m) ? conj(A22[(size_t)sc * ld + sr]) : czero<R>();
-      }
-    } else {
-      // straddles the diagonal: element by element from the lower triangle
-      for (int e = tid; e < 64 * TC; e += 256) {
-        const int rr = e & 63, cc = e >> 6;
-        const int gr = r0 + rr, gc = cb0 + cc;
-        C v = czero<R>();
-        if (gr < m && gc < m) {
-          if (gr > gc) v = A22[(size_t)gc * ld + gr];
-          else if (gr < gc) v = conj(A22[(size_t)gr * ld + gc]);
-          else v = mkc<R>(A22[(size_t)gc * ld + gr].re, R(0));
-        }
-        tile[cc][rr] = v;
-      }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + 256 * u;
+      Vc[e % TC][e / TC] = vnx[u];
     }
     __syncthreads();
+    if (cb0 + TC < m) fetch(cb0 + TC);   // in flight during the products below
 #pragma unroll 2
     for (int cc = ks; cc < TC; cc += 4) {
       const C a = tile[cc][r];
@@ -426,21 +432,28 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
     __syncthreads();
     for (int e = tid; e < 64 * (HB / 2); e += 256) {
       const int rr = e % 64, t = e / 64;
-      C s = czero<R>();
+      C sm = czero<R>();
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s = s + red[(q * 64 + rr) * (HB / 2) + t];
-      X0s[rr][h * (HB / 2) + t] = s;
-      if (r0 + rr < m) X0[(size_t)(h * (HB / 2) + t) * ld + r0 + rr] = s;
+      for (int q = 0; q < 4; ++q) sm = sm + red[(q * 64 + rr) * (HB / 2) + t];
+      X0s[rr][h * (HB / 2) + t] = sm;
+      if (r0 + rr < m) X0[(size_t)(h * (HB / 2) + t) * ld + r0 + rr] = sm;
     }
     __syncthreads();
   }
-  // Gram partial G[i][j] = sum_rr conj(V[rr][i]) X0[rr][j]
+  // Gram partial G[i][j] = sum_rr conj(V[rr][i]) X0[rr][j]; V rows of this
+  // block staged through the tile buffer
+  C *Vr = &tile[0][0];   // [64][HB]
+  for (int e = tid; e < 64 * HB; e += 256) {
+    const int i = e & 63, t = e >> 6;
+    Vr[i * HB + t] = panel_v<R>(Vp, ld, r0 + i, t, m, kq);
+  }
+  __syncthreads();
   C *M0p = (C *)it.M0p + (size_t)rb * HB * HB;
   for (int e = tid; e < HB * HB; e += 256) {
     const int i = e % HB, jx = e / HB;
-    C s = czero<R>();
-    for (int rr = 0; rr < 64; ++rr) s = cfma_cj(Vr[rr][i], X0s[rr][jx], s);
-    M0p[e] = s;
+    C sm = czero<R>();
+    for (int rr = 0; rr < 64; ++rr) sm = cfma_cj(Vr[rr * HB + i], X0s[rr][jx], sm);
+    M0p[e] = sm;
   }
 }
 
@@ -542,19 +555,25 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
     Vc[k][i] = (gc < m && kr) ? conj(Wm[(size_t)k * ld + gc]) : czero<R>();
     Wc[k][i] = conj(panel_v<R>(Vp, ld, gc, k, m, kq));
   }
+  // the output tile is fetched before the product so that its latency overlaps it
+  C cur[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int gc = cc0 + ty + 16 * b;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int gr = r0 + tx + 16 * a;
+      cur[a][b] = (gc < m && gr < m) ? A22[(size_t)gc * ld + gr] : czero<R>();
+    }
+  }
   __syncthreads();
-  C acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = czero<R>();
-#pragma unroll 2
+#pragma unroll 1
   for (int k = 0; k < HB; ++k) {
     C a1[4], a2[4], b1[4], b2[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      a1[a] = Vr[k][tx + 16 * a];
-      a2[a] = Wr[k][tx + 16 * a];
+      a1[a] = -Vr[k][tx + 16 * a];
+      a2[a] = -Wr[k][tx + 16 * a];
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -564,7 +583,7 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = cfma(a2[a], b2[b], cfma(a1[a], b1[b], acc[a][b]));
+      for (int b = 0; b < 4; ++b) cur[a][b] = cfma(a1[a], b1[b], cfma(a2[a], b2[b], cur[a][b]));
   }
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
@@ -574,8 +593,7 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
     for (int a = 0; a < 4; ++a) {
       const int gr = r0 + tx + 16 * a;
       if (gr >= m) continue;
-      C *dst = A22 + (size_t)gc * ld + gr;
-      *dst = *dst - acc[a][b];
+      A22[(size_t)gc * ld + gr] = cur[a][b];
     }
   }
 }
@@ -610,6 +628,47 @@ MVPB_DEV cx<R> shfl_c(cx<R> v, int src) {
 template <typename R>
 MVPB_DEV cx<R> shfl_xor_c(cx<R> v, int o) {
   return mkc<R>(__shfl_xor(v.re, o, 64), __shfl_xor(v.im, o, 64));
+}
+template <typename R>
+MVPB_DEV cx<R> readlane_c(cx<R> v, int lane);
+template <>
+MVPB_DEV cx<double> readlane_c(cx<double> v, int lane) {
+  const long long a = __double_as_longlong(v.re), b = __double_as_longlong(v.im);
+  const int a0 = __builtin_amdgcn_readlane((int)a, lane), a1 = __builtin_amdgcn_readlane((int)(a >> 32), lane);
+  const int b0 = __builtin_amdgcn_readlane((int)b, lane), b1 = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return mk(__longlong_as_double(((long long)a1 << 32) | (unsigned)a0),
+            __longlong_as_double(((long long)b1 << 32) | (unsigned)b0));
+}
+template <>
+MVPB_DEV cx<float> readlane_c(cx<float> v, int lane) {
+  return mkc<float>(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.re), lane)),
+                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.im), lane)));
+}
+
+// Cross-lane moves within a row of 16 lanes (DPP).
+template <int CTRL>
+MVPB_DEV double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+MVPB_DEV float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// Sum over the 16 lanes of a row; every lane of the row gets the total.
+template <typename T>
+MVPB_DEV T row16_sum(T v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm(1,0,3,2)
+  v += dpp_mov<0x4E>(v);   // quad_perm(2,3,0,1)
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  return v;
+}
+template <typename R>
+MVPB_DEV cx<R> row16_sum_c(cx<R> v) {
+  return mkc<R>(row16_sum(v.re), row16_sum(v.im));
 }
 
 static_assert(HB == 16, "the lane layout of the bulge-chasing kernel assumes HB = 16");
@@ -672,29 +731,35 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
       }
       const int s = i + 1 + k * HB;
       const int L = min(HB, n - s);
-      C vq, tau;
+      const int ps = s - HB;   // J_{k-1} = [s-HB, s-1] (k >= 1)
+      // ---- every load of the task at once: the column / block being
+      // annihilated and the diagonal block D = A[J_k, J_k]
+      C y[4], dq[4];
       if (k == 0) {
-        // x = A[s .. s+L-1, i] at distances 1 .. L of column i
         const C x = (q < L) ? WB[(size_t)i * HB_LDB + 1 + q] : czero<R>();
-        double xn2 = (q >= 1 && q < L) ? (double)abs2(x) : 0.0;
 #pragma unroll
-        for (int o = 1; o < 16; o <<= 1) xn2 += __shfl_xor(xn2, o, 64);
-        const C alpha = shfl_c(x, lane & 48);
-        double beta;
-        C scale;
-        make_reflector<R>(alpha, xn2, beta, tau, scale);
-        vq = (q == 0) ? mkc<R>(R(1), R(0)) : (q < L ? x * scale : czero<R>());
-        if (g == 0 && q < L) WB[(size_t)i * HB_LDB + 1 + q] = (q == 0) ? mkc<R>((R)beta, R(0)) : czero<R>();
+        for (int t = 0; t < 4; ++t) y[t] = x;
       } else {
-        // Y = A[J_k, J_{k-1}], J_{k-1} = [s-HB, s-1] (full): element (q, c) at
-        // distance HB + q - c of column s - HB + c
-        const int ps = s - HB;
-        C y[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int c = 4 * g + t;
           y[t] = (q < L) ? WB[(size_t)(ps + c) * HB_LDB + HB + q - c] : czero<R>();
         }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = 4 * g + t;
+        C v = czero<R>();
+        if (q < L && c < L) {
+          if (q >= c) v = WB[(size_t)(s + c) * HB_LDB + q - c];
+          else v = conj(WB[(size_t)(s + q) * HB_LDB + c - q]);
+        }
+        dq[t] = v;
+      }
+      C vq, tau, x;
+      if (k == 0) {
+        x = y[0];
+      } else {
         // (a) Y <- Y - tau_p (Y v_p) v_p^H
         C vp[4];
 #pragma unroll
@@ -707,31 +772,31 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
         const C ty = tauprev * yv;
 #pragma unroll
         for (int t = 0; t < 4; ++t) y[t] = y[t] - ty * conj(vp[t]);
-        // (b) reflector from column 0 (held by lanes of group 0 in y[0])
-        const C x = shfl_c(y[0], q);
-        double xn2 = (q >= 1 && q < L) ? (double)abs2(x) : 0.0;
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) xn2 += __shfl_xor(xn2, o, 64);
-        const C alpha = shfl_c(y[0], 0);
-        double beta;
-        C scale;
-        make_reflector<R>(alpha, xn2, beta, tau, scale);
-        vq = (q == 0) ? mkc<R>(R(1), R(0)) : (q < L ? x * scale : czero<R>());
-        if (g == 0) y[0] = (q == 0) ? mkc<R>((R)beta, R(0)) : czero<R>();
+        // column 0 of Y, held by the lanes of row group 0, to every row group
+        x = shfl_c(y[0], q);
+      }
+      // (b) reflector annihilating x[1:]
+      double xn2 = (q >= 1 && q < L) ? (double)abs2(x) : 0.0;
+      xn2 = row16_sum(xn2);
+      const C alpha = readlane_c(x, 0);
+      double beta;
+      C scale;
+      make_reflector<R>(alpha, xn2, beta, tau, scale);
+      vq = (q == 0) ? mkc<R>(R(1), R(0)) : (q < L ? x * scale : czero<R>());
+      const C betac = (q == 0) ? mkc<R>((R)beta, R(0)) : czero<R>();
+      if (k == 0) {
+        if (g == 0 && q < L) WB[(size_t)i * HB_LDB + 1 + q] = betac;
+      } else {
+        if (g == 0) y[0] = betac;
         // (c) columns c >= 1: y <- y - conj(tau) v (v^H y)
         C vh[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) vh[t] = cfma_cj(vq, y[t], czero<R>());
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) vh[t] = vh[t] + shfl_xor_c(vh[t], o);
-        }
-        const C tb = conj(tau);
+        for (int t = 0; t < 4; ++t) vh[t] = row16_sum_c(cfma_cj(vq, y[t], czero<R>()));
+        const C tv = conj(tau) * vq;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int c = 4 * g + t;
-          if (c >= 1) y[t] = y[t] - (tb * vq) * vh[t];
+          if (c >= 1) y[t] = y[t] - tv * vh[t];
         }
         if (q < L) {
 #pragma unroll
@@ -741,28 +806,18 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
           }
         }
       }
-      // (d) two-sided update of D = A[J_k, J_k]
+      // (d) two-sided update of D
       {
-        C dq[4], vc[4];
+        C vc[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int c = 4 * g + t;
-          vc[t] = shfl_c(vq, c);
-          C v = czero<R>();
-          if (q < L && c < L) {
-            if (q >= c) v = WB[(size_t)(s + c) * HB_LDB + q - c];
-            else v = conj(WB[(size_t)(s + q) * HB_LDB + c - q]);
-          }
-          dq[t] = v;
-        }
+        for (int t = 0; t < 4; ++t) vc[t] = shfl_c(vq, 4 * g + t);
         C w0 = czero<R>();
 #pragma unroll
         for (int t = 0; t < 4; ++t) w0 = cfma(dq[t], vc[t], w0);
         w0 = w0 + shfl_xor_c(w0, 16);
         w0 = w0 + shfl_xor_c(w0, 32);
         double vw = (double)(vq.re * w0.re + vq.im * w0.im);   // Re(conj(v_q) w0_q)
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) vw += __shfl_xor(vw, o, 64);
+        vw = row16_sum(vw);
         const R a2 = (R)(-0.5 * (double)abs2(tau) * vw);
         const C wq = tau * w0 + a2 * vq;
         C wc[4];
@@ -780,6 +835,10 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
           }
         }
       }
+      __threadfence_block();
+      if (lane == 0)
+        __hip_atomic_store(&prog[w], i * 1024 + k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      // the reflector for the back-transform (after the release: not waited for)
       if (g == 0) {
         C *dst = V2 + (size_t)(roff + k) * HB + q;
         __builtin_nontemporal_store(vq.re, &dst->re);
@@ -788,9 +847,6 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
       if (lane == 0) tau2[roff + k] = tau;
       vprev = vq;
       tauprev = tau;
-      __threadfence_block();
-      if (lane == 0)
-        __hip_atomic_store(&prog[w], i * 1024 + k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
   __syncthreads();
@@ -825,38 +881,55 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
     Z[e] = (c < ncl) ? mkc<R>((R)it.X[(size_t)r * nb + cbase + c], R(0)) : czero<R>();
   }
   __syncthreads();
-  // ---- stage 2: sweeps i = n-2 .. 0; the blocks of one sweep are disjoint
+  // ---- stage 2: sweeps i = n-2 .. 0; the blocks of one sweep are disjoint.
+  // Thread e owns the (block, column) pair (e / ncl, e % ncl) of every sweep;
+  // the reflector of the next sweep is loaded while this one is applied.
   const C *V2 = (const C *)it.V2;
   const C *tau2 = (const C *)it.tau2;
-  for (int i = n - 2; i >= 0; --i) {
+  const long long rtot = refl_count(n - 1);
+  auto fetch = [&](int i, C (&vv)[HB], C &tau) {
     const int nsteps = (n - 1 - i + HB - 1) / HB;
-    const long long roff = refl_count(n - 1) - refl_count(n - 1 - i);
-    for (int e = tid; e < nsteps * ncl; e += BT_THREADS) {
-      const int k = e / ncl, c = e % ncl;
+    const int k = tid / ncl;
+    if (i < 0 || k >= nsteps) return;
+    const long long ri = rtot - refl_count(n - 1 - i) + k;
+    const C *v = V2 + (size_t)ri * HB;
+    const int L = min(HB, n - (i + 1 + k * HB));
+#pragma unroll
+    for (int j = 0; j < HB; ++j) vv[j] = (j < L) ? v[j] : czero<R>();
+    tau = tau2[ri];
+  };
+  C vcur[HB], vnxt[HB], tcur = czero<R>(), tnxt = czero<R>();
+#pragma unroll
+  for (int j = 0; j < HB; ++j) vcur[j] = vnxt[j] = czero<R>();
+  fetch(n - 2, vcur, tcur);
+  for (int i = n - 2; i >= 0; --i) {
+    fetch(i - 1, vnxt, tnxt);
+    const int nsteps = (n - 1 - i + HB - 1) / HB;
+    const int k = tid / ncl, c = tid % ncl;
+    if (k < nsteps) {
       const int s = i + 1 + k * HB;
       const int L = min(HB, n - s);
-      const C *v = V2 + (size_t)(roff + k) * HB;
-      const C tau = tau2[roff + k];
-      C vv[HB];
-#pragma unroll
-      for (int j = 0; j < HB; ++j) vv[j] = (j < L) ? v[j] : czero<R>();
+      C *zc = Z + (size_t)s * nc + c;
       C d0 = czero<R>(), d1 = czero<R>();
 #pragma unroll
       for (int j = 0; j < HB; j += 2) {
-        if (j < L) d0 = cfma_cj(vv[j], Z[(size_t)(s + j) * nc + c], d0);
-        if (j + 1 < L) d1 = cfma_cj(vv[j + 1], Z[(size_t)(s + j + 1) * nc + c], d1);
+        if (j < L) d0 = cfma_cj(vcur[j], zc[(size_t)j * nc], d0);
+        if (j + 1 < L) d1 = cfma_cj(vcur[j + 1], zc[(size_t)(j + 1) * nc], d1);
       }
-      const C td = tau * (d0 + d1);
+      const C td = tcur * (d0 + d1);
 #pragma unroll
       for (int j = 0; j < HB; ++j)
-        if (j < L) Z[(size_t)(s + j) * nc + c] = Z[(size_t)(s + j) * nc + c] - vv[j] * td;
+        if (j < L) zc[(size_t)j * nc] = zc[(size_t)j * nc] - vcur[j] * td;
     }
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < HB; ++j) vcur[j] = vnxt[j];
+    tcur = tnxt;
   }
   // ---- stage 1: panels last to first; rows c0+HB .. n-1
   const int npan = n > HB ? (n - 1) / HB : 0;   // panels with m = n - p HB - HB > 0
   const C *A = (const C *)it.A;
-  const int rg = tid & 15, tt = tid >> 4;         // (row phase, reflector column) for V^H Z
+  const int rg = tid & 15, tt = (tid >> 4) & (HB - 1);   // (row phase, reflector column) for V^H Z
   for (int p = npan - 1; p >= 0; --p) {
     const int c0 = p * HB, m = n - c0 - HB;
     const int kq = min(m, HB);
@@ -867,7 +940,7 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
     C acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = czero<R>();
-    if (tt < kq) {
+    if (tt < kq && tid < 16 * HB) {
       for (int r = tt + rg; r < m; r += 16) {   // V(r, tt) = 0 for r < tt
         const C v = (r == tt) ? mkc<R>(R(1), R(0)) : Vp[(size_t)tt * ld + r];
         const C *zr = Z + (size_t)(c0 + HB + r) * nc;
@@ -881,7 +954,7 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
 #pragma unroll
       for (int c = 0; c < 8; ++c) acc[c] = acc[c] + shfl_xor_c(acc[c], o);
     }
-    if (rg == 0) {
+    if (rg == 0 && tid < 16 * HB) {
 #pragma unroll
       for (int c = 0; c < 8; ++c) S[tt][c] = acc[c];
     }
@@ -971,10 +1044,14 @@ hipError_t launch_reduce(const EigItem *items, int n_items, int n_min, int n_max
               : launch_reduce_t<double>(items, n_items, n_min, n_max, st);
 }
 
+// Eigenvector columns per back-transform workgroup: bounded by the LDS
+// budget and by one (block, column) pair of a stage-2 sweep per thread.
 int backtransform_cols(int n_max, bool fp32) {
   const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
   const size_t cap = (size_t)BT_LDS_BYTES / (es * (size_t)n_max);
-  return (int)std::min<size_t>(8, std::max<size_t>(1, cap));
+  const size_t blocks = (size_t)std::max(1, (n_max - 1 + HB - 1) / HB);
+  const size_t cap2 = (size_t)BT_THREADS / blocks;
+  return (int)std::min<size_t>(8, std::max<size_t>(1, std::min(cap, cap2)));
 }
 
 hipError_t launch_backtransform(const EigItem *items, int n_items, int n_max, int nb, bool fp32, hipStream_t st) {

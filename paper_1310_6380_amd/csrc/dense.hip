@@ -1,80 +1,301 @@
-// Dense complex FP64 building blocks: Cholesky with explicit inverse of the
-// factor (one workgroup per matrix) and a batched tiled GEMM.
+// Dense complex FP64 building blocks: blocked Cholesky with the explicit
+// inverse of the factor, and a batched tiled GEMM.
 #include "common.h"
 #include "kernels.h"
 #include "prof.h"
 
+#include <algorithm>
+
 namespace mvpb {
 
 // ---------------------------------------------------------------------------
-// Cholesky A = L L^H (lower, in place) followed by X = L^-1 (lower).
-// One 1024-thread workgroup per matrix; the current column of L (or row of
-// X) is staged in LDS.  A right-looking rank-1 sweep per column: the
-// per-cell factorisations are off the per-k hot path.
+// Cholesky A = L L^H (lower, in place) and X = L^-1 (lower, strict upper part
+// zero) for a batch of N x N matrices, blocked by 64:
+//   potrf_diag    factor of the diagonal block jb and its inverse (one
+//                 workgroup per matrix, in LDS);
+//   potrf_panel   L[i, jb] = A[i, jb] L_jj^-H for the row blocks below;
+//   potrf_update  A[i, k] -= L[i, jb] L[k, jb]^H on the lower trailing tiles;
+//   potri_row     X[i, j] = -X_ii sum_{k=j}^{i-1} L[i, k] X[k, j], row block
+//                 i at a time (X_ii from potrf_diag).
+// status[b] = j+1 if the pivot of column j of matrix b was not positive; the
+// later launches skip that matrix.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) potrf_trtri(cd *const *Aarr, cd *const *Xarr, int *status, int N) {
-  extern __shared__ cd vec[];  // N entries
-  __shared__ double piv_s;
+constexpr int CB = 64;
+
+__global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xarr, int *status, int N, int jb) {
+  __shared__ cd D[CB][CB + 1];
+  __shared__ cd Di[CB][CB + 1];
   __shared__ int fail;
-  cd *A = Aarr[blockIdx.x];
-  cd *X = Xarr[blockIdx.x];
-  const int tid = threadIdx.x, T = blockDim.x;
-  const int lane = tid & 63, w = tid >> 6, nw = T >> 6;
+  const int b = blockIdx.x;
+  if (status[b]) return;
+  cd *A = Aarr[b];
+  cd *X = Xarr[b];
+  const int nb = min(CB, N - jb);
+  const int tid = threadIdx.x;
+  const size_t ld = (size_t)N;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e % CB, c = e / CB;
+    D[r][c] = (r < nb && c < nb && r >= c) ? A[(size_t)(jb + c) * ld + jb + r] : mk(0.0, 0.0);
+  }
   if (tid == 0) fail = 0;
   __syncthreads();
-  for (int j = 0; j < N; ++j) {
-    if (tid == 0) {
-      const double p = A[(size_t)j * N + j].re;
-      if (!(p > 0.0) || !isfinite(p)) fail = j + 1;
-      piv_s = sqrt(p);
+  for (int j = 0; j < nb; ++j) {
+    const double piv = D[j][j].re;
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (tid == 0) status[b] = jb + j + 1;
+      return;   // uniform: every thread read the same pivot
     }
+    const double sq = sqrt(piv), inv = 1.0 / sq;
     __syncthreads();
-    if (fail) break;
-    const double s = piv_s, inv = 1.0 / s;
-    for (int i = j + tid; i < N; i += T) {
-      cd v = (i == j) ? mk(s, 0.0) : inv * A[(size_t)j * N + i];
-      A[(size_t)j * N + i] = v;
-      vec[i] = v;
-    }
+    for (int r = j + tid; r < nb; r += 256) D[r][j] = (r == j) ? mk(sq, 0.0) : inv * D[r][j];
     __syncthreads();
-    for (int k = j + 1 + w; k < N; k += nw) {
-      const cd ck = conj(vec[k]);
-      cd *colk = A + (size_t)k * N;
-      for (int i = k + lane; i < N; i += 64) colk[i] = colk[i] - vec[i] * ck;
+    const int m = nb - j - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int r = j + 1 + e % m, c = j + 1 + e / m;
+      if (r >= c) D[r][c] = D[r][c] - D[r][j] * conj(D[c][j]);
     }
     __syncthreads();
   }
-  if (tid == 0) status[blockIdx.x] = fail;
-  if (fail) return;
-  // X = I
-  for (size_t e = tid; e < (size_t)N * N; e += T) {
-    const int r = (int)(e % N), c = (int)(e / N);
-    X[e] = mk(r == c ? 1.0 : 0.0, 0.0);
+  // Di = D^-1 (lower): column c by thread c, forward substitution
+  if (tid < nb) {
+    const int c = tid;
+    for (int k = 0; k < nb; ++k) {
+      if (k < c) {
+        Di[k][c] = mk(0.0, 0.0);
+        continue;
+      }
+      cd v = mk(k == c ? 1.0 : 0.0, 0.0);
+      for (int m = c; m < k; ++m) v = v - D[k][m] * Di[m][c];
+      Di[k][c] = (1.0 / D[k][k].re) * v;
+    }
   }
   __syncthreads();
-  // forward substitution on all right-hand sides at once, row by row
-  cd *rowk = vec;  // row k of X (columns 0..k)
-  for (int k = 0; k < N; ++k) {
-    const double inv = 1.0 / A[(size_t)k * N + k].re;
-    for (int c = tid; c <= k; c += T) {
-      const cd v = inv * X[(size_t)c * N + k];
-      X[(size_t)c * N + k] = v;
-      rowk[c] = v;
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int r = e % nb, c = e / nb;
+    if (r >= c) A[(size_t)(jb + c) * ld + jb + r] = D[r][c];
+    X[(size_t)(jb + c) * ld + jb + r] = (r >= c) ? Di[r][c] : mk(0.0, 0.0);
+  }
+}
+
+// L[i0:i0+64, jb:jb+nb] = A[i0:i0+64, jb:jb+nb] X_jj^H
+__global__ void __launch_bounds__(256) potrf_panel(cd *const *Aarr, cd *const *Xarr, const int *status, int N,
+                                                    int jb) {
+  __shared__ cd P[CB][CB + 1];    // P[r][k]
+  __shared__ cd Di[CB][CB + 1];   // Di[c][k] = X_jj(c, k)
+  const int b = blockIdx.y;
+  if (status[b]) return;
+  cd *A = Aarr[b];
+  const cd *X = Xarr[b];
+  const int nb = min(CB, N - jb);
+  const int i0 = jb + nb + blockIdx.x * CB;
+  if (i0 >= N) return;
+  const int rows = min(CB, N - i0);
+  const size_t ld = (size_t)N;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e % CB, k = e / CB;
+    P[r][k] = (r < rows && k < nb) ? A[(size_t)(jb + k) * ld + i0 + r] : mk(0.0, 0.0);
+    Di[r][k] = (r < nb && k < nb && r >= k) ? X[(size_t)(jb + k) * ld + jb + r] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  cd acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
+  for (int k = 0; k < nb; ++k) {
+    cd pv[4], dv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) pv[a] = P[tx + 16 * a][k];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dv[c] = conj(Di[ty + 16 * c][k]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int cc = ty + 16 * c;
+    if (cc >= nb) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = tx + 16 * a;
+      if (r < rows) A[(size_t)(jb + cc) * ld + i0 + r] = acc[a][c];
+    }
+  }
+}
+
+// A[i, k] -= L[i, jb] L[k, jb]^H on the lower 64 x 64 tiles right of jb+nb
+__global__ void __launch_bounds__(256) potrf_update(cd *const *Aarr, const int *status, int N, int jb) {
+  __shared__ cd Lr[CB][CB + 1];   // Lr[r][k] = L(tile rows, jb+k)
+  __shared__ cd Lc[CB][CB + 1];   // Lc[c][k] = L(tile cols, jb+k)
+  const int b = blockIdx.y;
+  if (status[b]) return;
+  cd *A = Aarr[b];
+  const int nb = min(CB, N - jb);
+  const int q0 = jb + nb, m = N - q0;
+  if (m <= 0) return;
+  const int nt = (m + CB - 1) / CB;
+  const int t = blockIdx.x;
+  if (t >= nt * (nt + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int r0 = q0 + I * CB, c0 = q0 + J * CB;
+  const size_t ld = (size_t)N;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int i = e % CB, k = e / CB;
+    Lr[i][k] = (r0 + i < N && k < nb) ? A[(size_t)(jb + k) * ld + r0 + i] : mk(0.0, 0.0);
+    Lc[i][k] = (c0 + i < N && k < nb) ? A[(size_t)(jb + k) * ld + c0 + i] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  cd acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
+  for (int k = 0; k < nb; ++k) {
+    cd pv[4], dv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) pv[a] = Lr[tx + 16 * a][k];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dv[c] = conj(Lc[ty + 16 * c][k]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int cc = c0 + ty + 16 * c;
+    if (cc >= N) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = r0 + tx + 16 * a;
+      if (r < N && r >= cc) {
+        cd *dst = A + (size_t)cc * ld + r;
+        *dst = *dst - acc[a][c];
+      }
+    }
+  }
+}
+
+// X[i-block, j-block] = -X_ii sum_{k=j}^{i-1} L[i, k] X[k, j] for j < i = ib
+__global__ void __launch_bounds__(256) potri_row(cd *const *Aarr, cd *const *Xarr, const int *status, int N,
+                                                  int ib) {
+  __shared__ cd Ls[CB][17];    // Ls[r][kk] = L(i rows, k cols chunk)
+  __shared__ cd Xs[16][CB + 1];   // Xs[kk][c] = X(k rows chunk, j cols)
+  __shared__ cd Ts[CB][CB + 1];
+  const int b = blockIdx.y;
+  if (status[b]) return;
+  const cd *A = Aarr[b];
+  cd *X = Xarr[b];
+  const int jbk = blockIdx.x;
+  const int i0 = ib * CB, j0 = jbk * CB;
+  const int rows = min(CB, N - i0), cols = min(CB, N - j0);
+  const size_t ld = (size_t)N;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  cd acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
+  // T = sum over k = j0 .. i0-1 of L[i rows, k] X[k, j cols]
+  for (int k0 = j0; k0 < i0; k0 += 16) {
+    for (int e = tid; e < CB * 16; e += 256) {
+      const int r = e % CB, kk = e / CB;
+      Ls[r][kk] = (r < rows) ? A[(size_t)(k0 + kk) * ld + i0 + r] : mk(0.0, 0.0);
+      const int kr = e / CB, cc = e % CB;   // same flattening for Xs
+      Xs[kr][cc] = (cc < cols) ? X[(size_t)(j0 + cc) * ld + k0 + kr] : mk(0.0, 0.0);
     }
     __syncthreads();
-    const cd *Lk = A + (size_t)k * N;
-    for (int c = w; c <= k; c += nw) {
-      const cd xv = rowk[c];
-      cd *colc = X + (size_t)c * N;
-      for (int i = k + 1 + lane; i < N; i += 64) colc[i] = colc[i] - Lk[i] * xv;
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      cd pv[4], dv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) pv[a] = Ls[tx + 16 * a][kk];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dv[c] = Xs[kk][ty + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Ts[tx + 16 * a][ty + 16 * c] = acc[a][c];
+  // X_ii (lower) into the Ls/Xs space is too small: read it from global
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
+  for (int k = 0; k < rows; ++k) {
+    cd pv[4], dv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = tx + 16 * a;
+      pv[a] = (r < rows && r >= k) ? X[(size_t)(i0 + k) * ld + i0 + r] : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dv[c] = Ts[k][ty + 16 * c];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int cc = ty + 16 * c;
+    if (cc >= cols) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = tx + 16 * a;
+      if (r < rows) X[(size_t)(j0 + cc) * ld + i0 + r] = mk(0.0, 0.0) - acc[a][c];
+    }
+  }
+}
+
+__global__ void zero_upper_blocks(cd *const *Xarr, const int *status, int N) {
+  // strict upper block part of X (block rows above the diagonal block)
+  const int b = blockIdx.y;
+  if (status[b]) return;
+  cd *X = Xarr[b];
+  const size_t total = (size_t)N * N;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % N), c = (int)(e / N);
+    if (r / CB < c / CB) X[e] = mk(0.0, 0.0);
+  }
+}
+
+__global__ void clear_status(int *status, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) status[t] = 0;
 }
 
 hipError_t launch_potrf_trtri(cd *const *A, cd *const *Linv, int *status, int count, int N, hipStream_t st) {
   ProfScope ps(K_POTRF, st);
-  hipLaunchKernelGGL(potrf_trtri, dim3(count), dim3(1024), sizeof(cd) * N, st, A, Linv, status, N);
+  hipLaunchKernelGGL(clear_status, dim3((count + 255) / 256), dim3(256), 0, st, status, count);
+  for (int jb = 0; jb < N; jb += CB) {
+    const int nb = std::min(CB, N - jb);
+    hipLaunchKernelGGL(potrf_diag, dim3(count), dim3(256), 0, st, A, Linv, status, N, jb);
+    const int m = N - jb - nb;
+    if (m > 0) {
+      const int rb = (m + CB - 1) / CB;
+      hipLaunchKernelGGL(potrf_panel, dim3(rb, count), dim3(256), 0, st, A, Linv, status, N, jb);
+      hipLaunchKernelGGL(potrf_update, dim3(rb * (rb + 1) / 2, count), dim3(256), 0, st, A, status, N, jb);
+    }
+  }
+  const int nbk = (N + CB - 1) / CB;
+  for (int ib = 1; ib < nbk; ++ib)
+    hipLaunchKernelGGL(potri_row, dim3(ib, count), dim3(256), 0, st, A, Linv, status, N, ib);
+  hipLaunchKernelGGL(zero_upper_blocks, dim3(64, count), dim3(256), 0, st, Linv, status, N);
   return hipGetLastError();
 }
 

@@ -13,21 +13,44 @@
 
 namespace mvpb {
 
-constexpr int EIG_THREADS = 1024;
-constexpr int EIG_WAVES = EIG_THREADS / 64;
 
 // ---------------------------------------------------------------------------
 // 1. Tridiagonal eigenproblem: multisection for the lowest nb eigenvalues,
 //    inverse iteration for the eigenvectors.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int sturm_count(const double *dd, const double *ee2, int n, double x, double pivmin) {
-  // number of eigenvalues of T strictly below x (LDL^T pivots)
+// Number of eigenvalues of T strictly below x (signs of the LDL^T pivots).
+// The division uses the hardware reciprocal refined by one Newton step: a
+// few ulps of error per pivot keep the count backward stable.
+__device__ __forceinline__ double fast_rcp(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ int sturm_count(const double *__restrict__ dd, const double *__restrict__ ee2, int n,
+                                           double x, double pivmin) {
   int cnt = 0;
   double q = dd[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0.0;
-  for (int k = 1; k < n; ++k) {
-    q = dd[k] - x - ee2[k - 1] / q;
+  int k = 1;
+  for (; k + 3 < n; k += 4) {
+    const double d0 = dd[k], d1 = dd[k + 1], d2 = dd[k + 2], d3 = dd[k + 3];
+    const double e0 = ee2[k - 1], e1 = ee2[k], e2 = ee2[k + 1], e3 = ee2[k + 2];
+    q = (d0 - x) - e0 * fast_rcp(q);
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    q = (d1 - x) - e1 * fast_rcp(q);
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    q = (d2 - x) - e2 * fast_rcp(q);
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    q = (d3 - x) - e3 * fast_rcp(q);
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  for (; k < n; ++k) {
+    q = (dd[k] - x) - ee2[k - 1] * fast_rcp(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -44,321 +67,366 @@ __device__ __forceinline__ double hash_uniform(unsigned a, unsigned b) {
   return (double)(h & 0xFFFFFF) / (double)0x1000000 * 2.0 - 1.0;
 }
 
-// Orthonormalise the nb columns of the real row-major block X[r*nb + b]
-// (classical Gram-Schmidt, two passes).  Whole-block cooperative.
-__device__ void orthonormalize_real(double *X, int n, int nb, double *h, double *red) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int b = 0; b < nb; ++b) {
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int c = w; c < b; c += EIG_WAVES) {
-        double acc = 0.0;
-        for (int r = lane; r < n; r += 64) acc = fma(X[(size_t)r * nb + c], X[(size_t)r * nb + b], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) h[c] = acc;
-      }
-      __syncthreads();
-      for (int r = tid; r < n; r += EIG_THREADS) {
-        double acc = X[(size_t)r * nb + b];
-        for (int c = 0; c < b; ++c) acc = fma(-h[c], X[(size_t)r * nb + c], acc);
-        X[(size_t)r * nb + b] = acc;
-      }
-      __syncthreads();
-    }
-    double s = 0.0;
-    for (int r = tid; r < n; r += EIG_THREADS) s = fma(X[(size_t)r * nb + b], X[(size_t)r * nb + b], s);
-    s = block_sum(s, red);
-    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-    for (int r = tid; r < n; r += EIG_THREADS) X[(size_t)r * nb + b] *= inv;
-    __syncthreads();
-  }
-}
-
-__global__ void __launch_bounds__(EIG_THREADS) tridiag_eig(const EigItem *__restrict__ items) {
-  extern __shared__ double shd[];
-  double *dd = shd;            // MAX_N
-  double *ee2 = dd + MAX_N;    // MAX_N: e^2
-  double *ee = ee2 + MAX_N;    // MAX_N: e
-  __shared__ double lo[64], hi[64], xs[EIG_THREADS];
-  __shared__ int cnts[EIG_THREADS];
-  __shared__ double red[2 * EIG_WAVES];
-  __shared__ double h[64];
-  __shared__ int done_s;
-  const EigItem it = items[blockIdx.x];
-  const int n = 2 * it.N, nb = it.nb;
-  const int tid = threadIdx.x;
-  // stage d, e^2; Gershgorin bounds
-  double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
-  for (int r = tid; r < n; r += EIG_THREADS) {
-    const double dr = it.d[r];
-    const double er = (r < n - 1) ? it.e[r] : 0.0;
-    const double el = (r > 0) ? it.e[r - 1] : 0.0;
-    dd[r] = dr;
-    if (r < n - 1) {
-      ee2[r] = er * er;
-      ee[r] = er;
-    }
+// Gershgorin bounds of T (every thread receives them); red holds 3 * waves doubles.
+MVPB_DEV void gershgorin(const double *dd, const double *ee, int n, double *red, double &gl, double &gu,
+                         double &emax2) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  gl = DBL_MAX;
+  gu = -DBL_MAX;
+  emax2 = 0.0;
+  for (int r = tid; r < n; r += blockDim.x) {
+    const double er = (r < n - 1) ? ee[r] : 0.0;
+    const double el = (r > 0) ? ee[r - 1] : 0.0;
     const double rad = fabs(er) + fabs(el);
-    gl = fmin(gl, dr - rad);
-    gu = fmax(gu, dr + rad);
+    gl = fmin(gl, dd[r] - rad);
+    gu = fmax(gu, dd[r] + rad);
     emax2 = fmax(emax2, er * er);
   }
-  // block min / max through the sum helper on transformed values
-  {
-    const int lane = tid & 63, wid = tid >> 6;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      gl = fmin(gl, __shfl_xor(gl, o, 64));
-      gu = fmax(gu, __shfl_xor(gu, o, 64));
-      emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
-    }
-    __shared__ double mm[3 * EIG_WAVES];
-    if (lane == 0) { mm[3 * wid] = gl; mm[3 * wid + 1] = gu; mm[3 * wid + 2] = emax2; }
-    __syncthreads();
-    gl = DBL_MAX; gu = -DBL_MAX; emax2 = 0.0;
-    for (int q = 0; q < EIG_WAVES; ++q) {
-      gl = fmin(gl, mm[3 * q]);
-      gu = fmax(gu, mm[3 * q + 1]);
-      emax2 = fmax(emax2, mm[3 * q + 2]);
-    }
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, o, 64));
+    gu = fmax(gu, __shfl_xor(gu, o, 64));
+    emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
   }
+  if (lane == 0) {
+    red[3 * wid] = gl;
+    red[3 * wid + 1] = gu;
+    red[3 * wid + 2] = emax2;
+  }
+  __syncthreads();
+  gl = DBL_MAX;
+  gu = -DBL_MAX;
+  emax2 = 0.0;
+  for (int q = 0; q < nw; ++q) {
+    gl = fmin(gl, red[3 * q]);
+    gu = fmax(gu, red[3 * q + 1]);
+    emax2 = fmax(emax2, red[3 * q + 2]);
+  }
+  __syncthreads();
+}
+
+// 1a. Eigenvalue j of T (ascending) by multisection: one workgroup per
+// (eigenvalue, item); every round evaluates BIS_THREADS Sturm counts in the
+// current interval and keeps the sub-interval holding eigenvalue j.
+constexpr int BIS_THREADS = 256;
+__global__ void __launch_bounds__(BIS_THREADS) tridiag_bisect(const EigItem *__restrict__ items) {
+  extern __shared__ double shd[];
+  __shared__ double red[3 * (BIS_THREADS / 64)];
+  __shared__ double xs[BIS_THREADS];
+  __shared__ int first_s[BIS_THREADS / 64];
+  __shared__ double lo_s, hi_s;
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N, j = blockIdx.x;
+  if (j >= it.nb) return;
+  double *dd = shd, *ee = dd + n, *ee2 = ee + n;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int r = tid; r < n; r += BIS_THREADS) {
+    dd[r] = it.d[r];
+    const double er = (r < n - 1) ? it.e[r] : 0.0;
+    ee[r] = er;
+    ee2[r] = er * er;
+  }
+  __syncthreads();
+  double gl, gu, emax2;
+  gershgorin(dd, ee, n, red, gl, gu, emax2);
   const double bnorm = fmax(fabs(gl), fabs(gu));
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
   gl -= 2.0 * DBL_EPSILON * bnorm * n + 2.0 * pivmin;
   gu += 2.0 * DBL_EPSILON * bnorm * n + 2.0 * pivmin;
-  if (tid < nb) { lo[tid] = gl; hi[tid] = gu; }
-  __syncthreads();
-  // multisection: G probes per wanted eigenvalue
-  const int G = EIG_THREADS / nb;
-  const int b = tid / G, g = tid % G;
-  for (int round = 0; round < 24; ++round) {
-    if (b < nb) {
-      const double l = lo[b], hh = hi[b];
-      const double x = l + (hh - l) * (double)(g + 1) / (double)(G + 1);
-      xs[tid] = x;
-      cnts[tid] = sturm_count(dd, ee2, n, x, pivmin);
+  double lo = gl, hi = gu;
+  // a shift within a few ulps of |T| is all inverse iteration and the final
+  // Rayleigh-Ritz step need
+  const double tol_abs = 2.0 * DBL_EPSILON * bnorm + 4.0 * pivmin;
+  for (int round = 0; round < 16; ++round) {
+    if (hi - lo <= fmax(tol_abs, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
+    const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(BIS_THREADS + 1);
+    xs[tid] = x;
+    const int cnt = sturm_count(dd, ee2, n, x, pivmin);
+    // first probe with more than j eigenvalues below it
+    const unsigned long long bal = __ballot(cnt > j);
+    if (lane == 0) first_s[w] = bal ? w * 64 + __builtin_ctzll(bal) : BIS_THREADS;
+    __syncthreads();
+    if (tid == 0) {
+      int g = BIS_THREADS;
+      for (int q = 0; q < BIS_THREADS / 64; ++q) g = min(g, first_s[q]);
+      const double nl = (g > 0) ? xs[g - 1] : lo;
+      const double nh = (g < BIS_THREADS) ? xs[g] : hi;
+      lo_s = nl;
+      hi_s = nh;
     }
     __syncthreads();
-    if (tid < nb) {
-      const int base = tid * G;
-      double nl = lo[tid], nh = hi[tid];
-      int gg = 0;
-      while (gg < G && cnts[base + gg] <= tid) ++gg;   // first probe with more than tid eigenvalues below
-      if (gg < G) nh = xs[base + gg];
-      if (gg > 0) nl = xs[base + gg - 1];
-      lo[tid] = nl;
-      hi[tid] = nh;
-    }
-    if (tid == 0) done_s = 1;
-    __syncthreads();
-    if (tid < nb) {
-      const double tol = 2.0 * DBL_EPSILON * fmax(fabs(lo[tid]), fabs(hi[tid])) + 4.0 * pivmin;
-      if (hi[tid] - lo[tid] > tol) atomicAnd(&done_s, 0);
-    }
-    __syncthreads();
-    if (done_s) break;
+    lo = lo_s;
+    hi = hi_s;
     __syncthreads();
   }
-  if (tid < nb) it.lam_t[tid] = 0.5 * (lo[tid] + hi[tid]);
-  __syncthreads();
-  // inverse iteration, one thread per eigenvalue; scratch lu[(a*n + r)*nb + b]
-  double *lu = it.lu;
-  double *X = it.X;
-  // pivot used in place of an exact zero (the all-zero operator at Gamma with one plane wave)
-  const double pert = fmax(DBL_EPSILON * bnorm, 1e-280);
-  if (tid < nb) {
-    const int bb = tid;
-    const double lam = 0.5 * (lo[bb] + hi[bb]);
-#define DL(r) lu[((size_t)0 * n + (r)) * nb + bb]
-#define DG(r) lu[((size_t)1 * n + (r)) * nb + bb]
-#define DU(r) lu[((size_t)2 * n + (r)) * nb + bb]
-#define DU2(r) lu[((size_t)3 * n + (r)) * nb + bb]
-#define PV(r) lu[((size_t)4 * n + (r)) * nb + bb]
-    // LU with partial pivoting of T - lam I; the running row lives in
-    // registers and the inputs come from LDS, so only stores go to memory
-    double dr = dd[0] - lam, ur = (n > 1) ? ee[0] : 0.0;
-    for (int r = 0; r < n - 1; ++r) {
-      const double lr = ee[r];
-      const double dn = dd[r + 1] - lam;
-      const double un = (r < n - 2) ? ee[r + 1] : 0.0;
-      if (fabs(dr) >= fabs(lr)) {
-        const double piv = (dr == 0.0) ? pert : dr;
-        const double f = lr / piv;
-        DG(r) = piv; DU(r) = ur; DU2(r) = 0.0; DL(r) = f; PV(r) = 0.0;
-        dr = dn - f * ur;
-        ur = un;
-      } else {
-        const double f = dr / lr;
-        DG(r) = lr; DU(r) = dn; DU2(r) = un; DL(r) = f; PV(r) = 1.0;
-        dr = ur - f * dn;
-        ur = -f * un;
-      }
-    }
-    DG(n - 1) = (dr == 0.0) ? pert : dr;
-    for (int r = 0; r < n; ++r) X[(size_t)r * nb + bb] = hash_uniform(r + 1, bb + 7);
-  }
-  for (int iter = 0; iter < 3; ++iter) {
-    if (tid < nb) {
-      const int bb = tid;
-      // forward: apply P and L^-1; the running entry stays in a register
-      double cur = X[bb];
-      for (int r = 0; r < n - 1; ++r) {
-        const double nxt = X[(size_t)(r + 1) * nb + bb];
-        const bool sw = PV(r) != 0.0;
-        const double br = sw ? nxt : cur;
-        const double br1 = sw ? cur : nxt;
-        X[(size_t)r * nb + bb] = br;
-        cur = br1 - DL(r) * br;
-      }
-      X[(size_t)(n - 1) * nb + bb] = cur;
-      // back substitution with U (diagonal, super and second super diagonal)
-      double x1 = 0.0, x2 = 0.0, xmax = 0.0, sc = 1.0;
-      for (int r = n - 1; r >= 0; --r) {
-        double s = sc * X[(size_t)r * nb + bb];
-        if (r + 1 < n) s -= DU(r) * x1;
-        if (r + 2 < n) s -= DU2(r) * x2;
-        double xv = s / DG(r);
-        if (!isfinite(xv)) xv = 0.0;
-        if (fabs(xv) > 1e150) {
-          // keep the iterate finite: rescale what is solved and what is left
-          const double f = 1e-150;
-          for (int q = r + 1; q < n; ++q) X[(size_t)q * nb + bb] *= f;
-          x1 *= f;
-          x2 *= f;
-          xmax *= f;
-          sc *= f;
-          xv *= f;
-        }
-        X[(size_t)r * nb + bb] = xv;
-        xmax = fmax(xmax, fabs(xv));
-        x2 = x1;
-        x1 = xv;
-      }
-      const double inv = xmax > 0.0 ? 1.0 / xmax : 1.0;
-      for (int r = 0; r < n; ++r) X[(size_t)r * nb + bb] *= inv;
-    }
-#undef DL
-#undef DG
-#undef DU
-#undef DU2
-#undef PV
-    __syncthreads();
-    orthonormalize_real(X, n, nb, h, red);
+  if (tid == 0) it.lam_t[j] = 0.5 * (lo + hi);
+}
+
+// Sequential kernels of inverse iteration (one lane).  The recurrences run in
+// chunks of 8 steps whose operands are loaded one chunk ahead, so that LDS
+// latency is paid once per chunk and overlaps the arithmetic.
+constexpr int TCH = 8;
+
+// One pivoted elimination step of T - sh I (row r): state (dr, ur) in, out.
+MVPB_DEV void lu_step(int r, double lr, double dns, double un, double pert, double &dr, double &ur,
+                      double *__restrict__ DL, double *__restrict__ DGi, double *__restrict__ DU,
+                      double *__restrict__ DU2, double *__restrict__ PV) {
+  if (fabs(dr) >= fabs(lr)) {
+    const double ip = fast_rcp(dr == 0.0 ? pert : dr);
+    const double f = lr * ip;
+    DGi[r] = ip; DU[r] = ur; DU2[r] = 0.0; DL[r] = f; PV[r] = 0.0;
+    dr = dns - f * ur;
+    ur = un;
+  } else {
+    const double ip = fast_rcp(lr);
+    const double f = dr * ip;
+    DGi[r] = ip; DU[r] = dns; DU2[r] = un; DL[r] = f; PV[r] = 1.0;
+    dr = ur - f * dns;
+    ur = -f * un;
   }
 }
 
-hipError_t launch_tridiag_eig(const EigItem *items, int n_items, hipStream_t st) {
+// LU with partial pivoting of T - sh I: multipliers DL, reciprocal pivots DGi,
+// first and second superdiagonal of U (DU, DU2), row swaps PV (0/1).
+MVPB_DEV void tri_lu(const double *__restrict__ dd, const double *__restrict__ ee, int n, double sh, double pert,
+                     double *__restrict__ DL, double *__restrict__ DGi, double *__restrict__ DU,
+                     double *__restrict__ DU2, double *__restrict__ PV) {
+  double dr = dd[0] - sh, ur = (n > 1) ? ee[0] : 0.0;
+  int r = 0;
+  // a full chunk at r needs ee[r .. r+TCH] and dd[r+1 .. r+TCH], all < n-1 / < n
+  if (r + TCH < n - 1) {
+    double ec[TCH + 1], dc[TCH];
+#pragma unroll
+    for (int u = 0; u <= TCH; ++u) ec[u] = ee[r + u];
+#pragma unroll
+    for (int u = 0; u < TCH; ++u) dc[u] = dd[r + 1 + u];
+    for (; r + TCH < n - 1; r += TCH) {
+      double en[TCH + 1], dn[TCH];
+      const bool more = r + 2 * TCH < n - 1;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u <= TCH; ++u) en[u] = ee[r + TCH + u];
+#pragma unroll
+        for (int u = 0; u < TCH; ++u) dn[u] = dd[r + TCH + 1 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < TCH; ++u) lu_step(r + u, ec[u], dc[u] - sh, ec[u + 1], pert, dr, ur, DL, DGi, DU, DU2, PV);
+      if (more) {
+#pragma unroll
+        for (int u = 0; u <= TCH; ++u) ec[u] = en[u];
+#pragma unroll
+        for (int u = 0; u < TCH; ++u) dc[u] = dn[u];
+      }
+    }
+  }
+  for (; r < n - 1; ++r)
+    lu_step(r, ee[r], dd[r + 1] - sh, (r < n - 2) ? ee[r + 1] : 0.0, pert, dr, ur, DL, DGi, DU, DU2, PV);
+  DGi[n - 1] = fast_rcp(dr == 0.0 ? pert : dr);
+}
+
+// x <- (T - sh I)^-1 x with the factors of tri_lu (x in place).
+MVPB_DEV void tri_solve(double *__restrict__ xv, int n, const double *__restrict__ DL,
+                        const double *__restrict__ DGi, const double *__restrict__ DU,
+                        const double *__restrict__ DU2, const double *__restrict__ PV) {
+  // forward: apply P and L^-1.  Step r reads x[r+1], PV[r], DL[r]; writes x[r].
+  double cur = xv[0];
+  int r = 0;
+  if (r + TCH < n - 1) {
+    double xc[TCH], pc[TCH], lc[TCH];
+#pragma unroll
+    for (int u = 0; u < TCH; ++u) {
+      xc[u] = xv[r + 1 + u];
+      pc[u] = PV[r + u];
+      lc[u] = DL[r + u];
+    }
+    for (; r + TCH < n - 1; r += TCH) {
+      double xn[TCH], pn[TCH], ln[TCH];
+      const bool more = r + 2 * TCH < n - 1;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < TCH; ++u) {
+          xn[u] = xv[r + TCH + 1 + u];
+          pn[u] = PV[r + TCH + u];
+          ln[u] = DL[r + TCH + u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TCH; ++u) {
+        const bool sw = pc[u] != 0.0;
+        const double br = sw ? xc[u] : cur;
+        const double br1 = sw ? cur : xc[u];
+        xv[r + u] = br;
+        cur = br1 - lc[u] * br;
+      }
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < TCH; ++u) {
+          xc[u] = xn[u];
+          pc[u] = pn[u];
+          lc[u] = ln[u];
+        }
+      }
+    }
+  }
+  for (; r < n - 1; ++r) {
+    const double nxt = xv[r + 1];
+    const bool sw = PV[r] != 0.0;
+    const double br = sw ? nxt : cur;
+    const double br1 = sw ? cur : nxt;
+    xv[r] = br;
+    cur = br1 - DL[r] * br;
+  }
+  xv[n - 1] = cur;
+  // backward substitution with U, rows n-1 .. 0.  Step r reads x[r], DU[r],
+  // DU2[r], DGi[r]; writes x[r].  Rescaling (rare) touches the rows above r.
+  double x1 = 0.0, x2 = 0.0, sc = 1.0;
+  int rr = n - 1;
+  auto bstep = [&](int q, double b, double u1, double u2, double gi) {
+    double sacc = sc * b;
+    if (q + 1 < n) sacc -= u1 * x1;
+    if (q + 2 < n) sacc -= u2 * x2;
+    double x = sacc * gi;
+    if (!isfinite(x)) x = 0.0;
+    if (fabs(x) > 1e150) {
+      // keep the iterate finite: rescale what is solved and what is left
+      const double f = 1e-150;
+      for (int t = q + 1; t < n; ++t) xv[t] *= f;
+      x1 *= f;
+      x2 *= f;
+      sc *= f;
+      x *= f;
+    }
+    xv[q] = x;
+    x2 = x1;
+    x1 = x;
+  };
+  if (rr - TCH + 1 >= 0) {
+    double bc[TCH], uc[TCH], vc[TCH], gc[TCH];
+#pragma unroll
+    for (int u = 0; u < TCH; ++u) {
+      const int q = rr - u;
+      bc[u] = xv[q];
+      uc[u] = DU[q];
+      vc[u] = DU2[q];
+      gc[u] = DGi[q];
+    }
+    for (; rr - TCH + 1 >= 0; rr -= TCH) {
+      double bn[TCH], un[TCH], vn[TCH], gn[TCH];
+      const bool more = rr - 2 * TCH + 1 >= 0;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < TCH; ++u) {
+          const int q = rr - TCH - u;
+          bn[u] = xv[q];
+          un[u] = DU[q];
+          vn[u] = DU2[q];
+          gn[u] = DGi[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TCH; ++u) bstep(rr - u, bc[u], uc[u], vc[u], gc[u]);
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < TCH; ++u) {
+          bc[u] = bn[u];
+          uc[u] = un[u];
+          vc[u] = vn[u];
+          gc[u] = gn[u];
+        }
+      }
+    }
+  }
+  for (; rr >= 0; --rr) bstep(rr, xv[rr], DU[rr], DU2[rr], DGi[rr]);
+}
+
+// 1b. Eigenvectors of T by inverse iteration with a pivoted LU of T - lam I
+// (two solves from a pseudo-random start).  One wavefront per eigenvalue;
+// lane 0 runs the sequential factorisation and solves, the wavefront the
+// normalisation.  Eigenvalues closer than 1e-9 |T| form a cluster, handled
+// in order by the wavefront of its first member with Gram-Schmidt against
+// the earlier members after every solve.  LU_LDS: the five LU arrays live
+// in LDS (else in the item's global scratch).
+constexpr int INV_LDS_MAX_N = 2400;
+template <bool LU_LDS>
+__global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ items) {
+  extern __shared__ double shd[];
+  __shared__ double red[3];
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N, nb = it.nb, j0 = blockIdx.x;
+  if (j0 >= nb) return;
+  const int lane = threadIdx.x;
+  double *dd = shd, *ee = dd + n, *xv = ee + n;
+  double *lub = LU_LDS ? xv + n : it.lu + (size_t)5 * n * j0;
+  double *DL = lub, *DGi = lub + n, *DU = lub + 2 * n, *DU2 = lub + 3 * n, *PV = lub + 4 * n;
+  for (int r = lane; r < n; r += 64) {
+    dd[r] = it.d[r];
+    ee[r] = (r < n - 1) ? it.e[r] : 0.0;
+  }
+  __syncthreads();
+  double gl, gu, emax2;
+  gershgorin(dd, ee, n, red, gl, gu, emax2);
+  const double bnorm = fmax(fabs(gl), fabs(gu));
+  const double thr = 1e-9 * bnorm;
+  const double *lam = it.lam_t;
+  if (j0 > 0 && lam[j0] - lam[j0 - 1] <= thr) return;   // not the first member of its cluster
+  int j1 = j0 + 1;
+  while (j1 < nb && lam[j1] - lam[j1 - 1] <= thr) ++j1;
+  const double pert = fmax(DBL_EPSILON * bnorm, 1e-280);
+  double *X = it.X;
+  for (int jm = j0; jm < j1; ++jm) {
+    const double sh = lam[jm];
+    if (lane == 0) tri_lu(dd, ee, n, sh, pert, DL, DGi, DU, DU2, PV);
+    for (int r = lane; r < n; r += 64) xv[r] = hash_uniform(r + 1, jm + 7);
+    __syncthreads();
+    for (int iter = 0; iter < 2; ++iter) {
+      if (lane == 0) tri_solve(xv, n, DL, DGi, DU, DU2, PV);
+      __syncthreads();
+      // orthogonalise against the earlier members of the cluster, normalise
+      for (int pass = 0; pass < (jm > j0 ? 2 : 1); ++pass) {
+        for (int q = j0; q < jm; ++q) {
+          double dot = 0.0;
+          for (int r = lane; r < n; r += 64) dot = fma(X[(size_t)r * nb + q], xv[r], dot);
+          dot = wave_sum(dot);
+          for (int r = lane; r < n; r += 64) xv[r] = fma(-dot, X[(size_t)r * nb + q], xv[r]);
+          __syncthreads();
+        }
+        double amax = 0.0;
+        for (int r = lane; r < n; r += 64) amax = fmax(amax, fabs(xv[r]));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+        const double ia = amax > 0.0 ? 1.0 / amax : 1.0;
+        double s2 = 0.0;
+        for (int r = lane; r < n; r += 64) {
+          const double v = xv[r] * ia;
+          s2 = fma(v, v, s2);
+        }
+        s2 = wave_sum(s2);
+        const double inv = s2 > 0.0 ? ia / sqrt(s2) : 0.0;
+        for (int r = lane; r < n; r += 64) xv[r] *= inv;
+        __syncthreads();
+      }
+    }
+    for (int r = lane; r < n; r += 64) X[(size_t)r * nb + jm] = xv[r];
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st) {
   ProfScope ps(K_TRIDIAG, st);
-  hipLaunchKernelGGL(tridiag_eig, dim3(n_items), dim3(EIG_THREADS), sizeof(double) * 3 * MAX_N, st, items);
+  hipLaunchKernelGGL(tridiag_bisect, dim3(nb, n_items), dim3(BIS_THREADS), sizeof(double) * 3 * n_max, st, items);
+  if (n_max <= INV_LDS_MAX_N)
+    hipLaunchKernelGGL(tridiag_invit<true>, dim3(nb, n_items), dim3(64), sizeof(double) * 8 * n_max, st, items);
+  else
+    hipLaunchKernelGGL(tridiag_invit<false>, dim3(nb, n_items), dim3(64), sizeof(double) * 3 * n_max, st, items);
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// 2. Rayleigh-Ritz in FP64: orthonormalise Y, G = Y^H C Y, Jacobi
-//    eigen-decomposition of G (parallel round-robin ordering), Y <- Y V.
-//    Final vectors go to it.Z, eigenvalues to it.lam, frequencies to it.omega.
-// ---------------------------------------------------------------------------
-constexpr int RR_MAXB = RR_MAX_BANDS;
-
-__device__ void orthonormalize_complex(cd *Y, int n, int nb, cd *h, double *red) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const size_t ld = (size_t)n;
-  for (int b = 0; b < nb; ++b) {
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int c = w; c < b; c += EIG_WAVES) {
-        cd acc = mk(0.0, 0.0);
-        for (int r = lane; r < n; r += 64) acc = cfma_cj(Y[(size_t)c * ld + r], Y[(size_t)b * ld + r], acc);
-        acc.re = wave_sum(acc.re);
-        acc.im = wave_sum(acc.im);
-        if (lane == 0) h[c] = acc;
-      }
-      __syncthreads();
-      for (int r = tid; r < n; r += EIG_THREADS) {
-        cd acc = Y[(size_t)b * ld + r];
-        for (int c = 0; c < b; ++c) acc = acc - h[c] * Y[(size_t)c * ld + r];
-        Y[(size_t)b * ld + r] = acc;
-      }
-      __syncthreads();
-    }
-    double s = 0.0;
-    for (int r = tid; r < n; r += EIG_THREADS) s += abs2(Y[(size_t)b * ld + r]);
-    s = block_sum(s, red);
-    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-    for (int r = tid; r < n; r += EIG_THREADS) Y[(size_t)b * ld + r] = inv * Y[(size_t)b * ld + r];
-    __syncthreads();
-  }
-}
-
-__global__ void __launch_bounds__(EIG_THREADS) rayleigh_ritz(const EigItem *__restrict__ items) {
-  __shared__ cd Gs[RR_MAXB][RR_MAXB + 1];
-  __shared__ cd Vs[RR_MAXB][RR_MAXB + 1];
-  __shared__ cd h[RR_MAXB];
-  __shared__ double red[2 * EIG_WAVES];
-  __shared__ double rc[RR_MAXB / 2 + 1], rs[RR_MAXB / 2 + 1];
-  __shared__ cd rph[RR_MAXB / 2 + 1];
-  __shared__ int pa[RR_MAXB / 2 + 1], pb[RR_MAXB / 2 + 1];
-  __shared__ int perm[RR_MAXB];
-  __shared__ double evs[RR_MAXB];
-  __shared__ int active_s;
-  const EigItem it = items[blockIdx.x];
-  const int n = 2 * it.N, nb = it.nb;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const size_t ld = (size_t)n;
-  cd *__restrict__ Y = it.Y;
-  cd *__restrict__ Z = it.Z;
-  const cd *__restrict__ C = it.Ak;
-  orthonormalize_complex(Y, n, nb, h, red);
-  // Z = C Y, waves over 64-row strips, 8 columns of Y per pass
-  constexpr int NBC = 8;
-  const int S = (n + 63) / 64;
-  for (int b0 = 0; b0 < nb; b0 += NBC) {
-    const int nc = min(NBC, nb - b0);
-    for (int s = w; s < S; s += EIG_WAVES) {
-      const int r = s * 64 + lane;
-      cd acc[NBC];
-#pragma unroll
-      for (int c = 0; c < NBC; ++c) acc[c] = mk(0.0, 0.0);
-      if (r < n) {
-        for (int col = 0; col < n; ++col) {
-          const cd a = C[(size_t)col * ld + r];
-#pragma unroll
-          for (int c = 0; c < NBC; ++c)
-            if (c < nc) acc[c] = cfma(a, Y[(size_t)(b0 + c) * ld + col], acc[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < NBC; ++c)
-          if (c < nc) Z[(size_t)(b0 + c) * ld + r] = acc[c];
-      }
-    }
-  }
-  __syncthreads();
-  // G = Y^H Z (Hermitian part), V = I
-  for (int e = w; e < nb * nb; e += EIG_WAVES) {
-    const int a = e % nb, b = e / nb;
-    cd acc = mk(0.0, 0.0);
-    for (int r = lane; r < n; r += 64) acc = cfma_cj(Y[(size_t)a * ld + r], Z[(size_t)b * ld + r], acc);
-    acc.re = wave_sum(acc.re);
-    acc.im = wave_sum(acc.im);
-    if (lane == 0) Gs[a][b] = acc;
-  }
-  for (int e = tid; e < nb * nb; e += EIG_THREADS) {
-    const int a = e % nb, b = e / nb;
-    Vs[a][b] = mk(a == b ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  for (int e = tid; e < nb * nb; e += EIG_THREADS) {
-    const int a = e % nb, b = e / nb;
-    if (a < b) {
-      const cd x = Gs[a][b], y2 = Gs[b][a];
-      const cd hm = mk(0.5 * (x.re + y2.re), 0.5 * (x.im - y2.im));
-      Gs[a][b] = hm;
-      Gs[b][a] = conj(hm);
-    } else if (a == b) {
-      Gs[a][a].im = 0.0;
-    }
-  }
-  __syncthreads();
-  // parallel cyclic Jacobi, round-robin pairing over nbe (even) indices
+// Cyclic Jacobi on the Hermitian nb x nb matrix G (LDS), rotations
+// accumulated into V; parallel round-robin pairing over nbe (even) indices.
+MVPB_DEV void jacobi_eig(cd (*Gs)[RR_MAX_BANDS + 1], cd (*Vs)[RR_MAX_BANDS + 1], int nb, double *rc, double *rs,
+                         cd *rph, int *pa, int *pb) {
+  const int tid = threadIdx.x, T = blockDim.x;
   const int nbe = nb + (nb & 1);
   const int npair = nbe / 2;
   double fro = 0.0;
@@ -403,7 +471,7 @@ __global__ void __launch_bounds__(EIG_THREADS) rayleigh_ritz(const EigItem *__re
       }
       __syncthreads();
       // columns: G J and V J, J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on (p, q)
-      for (int e = tid; e < npair * nb; e += EIG_THREADS) {
+      for (int e = tid; e < npair * nb; e += T) {
         const int k = e / nb, row = e % nb;
         const int pp = pa[k], qq = pb[k];
         if (pp == qq || rs[k] == 0.0) continue;
@@ -418,7 +486,7 @@ __global__ void __launch_bounds__(EIG_THREADS) rayleigh_ritz(const EigItem *__re
       }
       __syncthreads();
       // rows: J^H (G J)
-      for (int e = tid; e < npair * nb; e += EIG_THREADS) {
+      for (int e = tid; e < npair * nb; e += T) {
         const int k = e / nb, col = e % nb;
         const int pp = pa[k], qq = pb[k];
         if (pp == qq || rs[k] == 0.0) continue;
@@ -431,9 +499,186 @@ __global__ void __launch_bounds__(EIG_THREADS) rayleigh_ritz(const EigItem *__re
       __syncthreads();
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// 2. Rayleigh-Ritz in FP64 on span(Y), Y = the back-transformed eigenvectors
+//    (orthonormal up to the inverse iteration's accuracy):
+//    rr_product  Z = C Y over 64-row blocks of the kept copy of C(k), and the
+//                blocks' Gram partials Y_b^H Z_b, Y_b^H Y_b;
+//    rr_small    G = Y^H C Y, M = Y^H Y; M = L L^H; eigenpairs of
+//                L^-1 G L^-H (cyclic Jacobi, parallel round-robin pairs);
+//                vectors Y L^-H V, lambda ascending, omega = sqrt(max(lambda, 0)).
+// ---------------------------------------------------------------------------
+constexpr int RR_MAXB = RR_MAX_BANDS;
+constexpr int RRP_BC = 24;   // bands per pass of the product kernel
+
+__global__ void __launch_bounds__(256) rr_product(const EigItem *__restrict__ items) {
+  extern __shared__ __align__(16) unsigned char rr_raw[];
+  __shared__ cd Ys[64][RRP_BC + 1];
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N, nb = it.nb;
+  const int rb = blockIdx.x, r0 = rb * 64;
+  if (r0 >= n) return;
+  const size_t ld = (size_t)n;
+  cd *Yr = (cd *)rr_raw;       // [64][nb]
+  cd *Zr = Yr + 64 * nb;       // [64][nb]
+  const int tid = threadIdx.x, r = tid & 63, ks = tid >> 6;
+  const cd *__restrict__ Y = it.Y;
+  const cd *__restrict__ Cm = it.Ak;
+  const int rows = min(64, n - r0);
+  for (int e = tid; e < 64 * nb; e += 256) {
+    const int rr = e % 64, b = e / 64;
+    Yr[rr * nb + b] = (rr < rows) ? Y[(size_t)b * ld + r0 + rr] : mk(0.0, 0.0);
+  }
+  for (int b0 = 0; b0 < nb; b0 += RRP_BC) {
+    const int bc = min(RRP_BC, nb - b0);
+    cd acc[RRP_BC];
+#pragma unroll
+    for (int b = 0; b < RRP_BC; ++b) acc[b] = mk(0.0, 0.0);
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      __syncthreads();
+      for (int e = tid; e < 64 * RRP_BC; e += 256) {
+        const int cc = e % 64, b = e / 64;
+        Ys[cc][b] = (c0 + cc < n && b < bc) ? Y[(size_t)(b0 + b) * ld + c0 + cc] : mk(0.0, 0.0);
+      }
+      __syncthreads();
+      if (r < rows) {
+        const int cmax = min(64, n - c0);
+        for (int cc = ks; cc < cmax; cc += 4) {
+          const cd a = Cm[(size_t)(c0 + cc) * ld + r0 + r];
+#pragma unroll
+          for (int b = 0; b < RRP_BC; ++b) acc[b] = cfma(a, Ys[cc][b], acc[b]);
+        }
+      }
+    }
+    // sum the four column phases into Zr
+    for (int ph = 0; ph < 4; ++ph) {
+      if (ks == ph) {
+#pragma unroll
+        for (int b = 0; b < RRP_BC; ++b)
+          if (b < bc) Zr[r * nb + b0 + b] = (ph == 0) ? acc[b] : Zr[r * nb + b0 + b] + acc[b];
+      }
+      __syncthreads();
+    }
+  }
+  cd *Z = it.Z;
+  for (int e = tid; e < rows * nb; e += 256) {
+    const int rr = e % rows, b = e / rows;
+    Z[(size_t)b * ld + r0 + rr] = Zr[rr * nb + b];
+  }
+  // Gram partials of this row block: [0] Y^H Z, [1] Y^H Y
+  cd *Gp = it.Gp + (size_t)rb * 2 * nb * nb;
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int a = e % nb, b = e / nb;
+    cd g = mk(0.0, 0.0), m = mk(0.0, 0.0);
+    for (int rr = 0; rr < rows; ++rr) {
+      const cd ya = Yr[rr * nb + a];
+      g = cfma_cj(ya, Zr[rr * nb + b], g);
+      m = cfma_cj(ya, Yr[rr * nb + b], m);
+    }
+    Gp[e] = g;
+    Gp[nb * nb + e] = m;
+  }
+}
+
+__global__ void __launch_bounds__(256) rr_small(const EigItem *__restrict__ items) {
+  constexpr int T = 256;
+  __shared__ cd Gs[RR_MAXB][RR_MAXB + 1];
+  __shared__ cd Vs[RR_MAXB][RR_MAXB + 1];
+  __shared__ double rc[RR_MAXB / 2 + 1], rs[RR_MAXB / 2 + 1];
+  __shared__ cd rph[RR_MAXB / 2 + 1];
+  __shared__ int pa[RR_MAXB / 2 + 1], pb[RR_MAXB / 2 + 1];
+  __shared__ int perm[RR_MAXB];
+  __shared__ double evs[RR_MAXB];
+  const EigItem it = items[blockIdx.x];
+  const int n = 2 * it.N, nb = it.nb;
+  const int tid = threadIdx.x;
+  const size_t ld = (size_t)n;
+  const int nrb = (n + 63) / 64;
+  // G (Hermitian part) and M from the row-block partials
+  for (int e = tid; e < nb * nb; e += T) {
+    const int a = e % nb, b = e / nb;
+    cd g = mk(0.0, 0.0), m = mk(0.0, 0.0);
+    for (int q = 0; q < nrb; ++q) {
+      const cd *P = it.Gp + (size_t)q * 2 * nb * nb;
+      g = g + P[e];
+      m = m + P[nb * nb + e];
+    }
+    Gs[a][b] = g;
+    Vs[a][b] = m;
+  }
+  __syncthreads();
+  for (int e = tid; e < nb * nb; e += T) {
+    const int a = e % nb, b = e / nb;
+    if (a < b) {
+      const cd x = Gs[a][b], y2 = Gs[b][a];
+      const cd hm = mk(0.5 * (x.re + y2.re), 0.5 * (x.im - y2.im));
+      Gs[a][b] = hm;
+      Gs[b][a] = conj(hm);
+    } else if (a == b) {
+      Gs[a][a].im = 0.0;
+      Vs[a][a].im = 0.0;
+    }
+  }
+  __syncthreads();
+  // Cholesky M = L L^H in Vs (lower), column by column
+  for (int j = 0; j < nb; ++j) {
+    const double piv = sqrt(fmax(Vs[j][j].re, 1e-300));
+    __syncthreads();
+    for (int i = j + tid; i < nb; i += T) Vs[i][j] = (i == j) ? mk(piv, 0.0) : (1.0 / piv) * Vs[i][j];
+    __syncthreads();
+    for (int e = tid; e < nb * nb; e += T) {
+      const int i = e % nb, k = e / nb;
+      if (k > j && i >= k) Vs[i][k] = Vs[i][k] - Vs[i][j] * conj(Vs[k][j]);
+    }
+    __syncthreads();
+  }
+  cd *Lr = it.Lr;
+  for (int e = tid; e < nb * nb; e += T) Lr[e] = Vs[e % nb][e / nb];
+  __syncthreads();
+  // H1 = L^-1 G (column c by thread c, in place)
+  if (tid < nb) {
+    const int c = tid;
+    for (int i = 0; i < nb; ++i) {
+      cd x = Gs[i][c];
+      for (int k = 0; k < i; ++k) x = x - Vs[i][k] * Gs[k][c];
+      Gs[i][c] = (1.0 / Vs[i][i].re) * x;
+    }
+  }
+  __syncthreads();
+  // G' = L^-1 H1^H into Vs (column c from the conjugated row c of H1); L is
+  // read from Lr, so Vs can be overwritten column by column
+  if (tid < nb) {
+    const int c = tid;
+    for (int i = 0; i < nb; ++i) {
+      cd v = conj(Gs[c][i]);
+      for (int k = 0; k < i; ++k) v = v - Lr[i + (size_t)k * nb] * Vs[k][c];
+      Vs[i][c] = (1.0 / Lr[i + (size_t)i * nb].re) * v;
+    }
+  }
+  __syncthreads();
+  // Jacobi on G' (now Vs), eigenvectors accumulated in Gs (= I)
+  for (int e = tid; e < nb * nb; e += T) {
+    const int a = e % nb, b = e / nb;
+    Gs[a][b] = mk(a == b ? 1.0 : 0.0, 0.0);
+  }
+  for (int e = tid; e < nb * nb; e += T) {
+    const int a = e % nb, b = e / nb;
+    if (a < b) {
+      const cd x = Vs[a][b], y2 = Vs[b][a];
+      const cd hm = mk(0.5 * (x.re + y2.re), 0.5 * (x.im - y2.im));
+      Vs[a][b] = hm;
+      Vs[b][a] = conj(hm);
+    } else if (a == b) {
+      Vs[a][a].im = 0.0;
+    }
+  }
+  __syncthreads();
+  jacobi_eig(Vs, Gs, nb, rc, rs, rph, pa, pb);
   // sort eigenvalues ascending
   if (tid == 0) {
-    for (int a = 0; a < nb; ++a) { perm[a] = a; evs[a] = Gs[a][a].re; }
+    for (int a = 0; a < nb; ++a) { perm[a] = a; evs[a] = Vs[a][a].re; }
     for (int a = 0; a < nb; ++a) {
       int best = a;
       for (int b = a + 1; b < nb; ++b)
@@ -447,27 +692,49 @@ __global__ void __launch_bounds__(EIG_THREADS) rayleigh_ritz(const EigItem *__re
     it.lam[tid] = lam;
     it.omega[tid] = sqrt(fmax(lam, 0.0));
   }
-  // Z = Y V(:, perm)
-  for (size_t e = tid; e < (size_t)n * nb; e += EIG_THREADS) {
+  // P = L^-H V: back substitution with L^H, column c by thread c (in place in Gs)
+  if (tid < nb) {
+    const int c = tid;
+    for (int i = nb - 1; i >= 0; --i) {
+      cd x = Gs[i][c];
+      for (int k = i + 1; k < nb; ++k) x = x - conj(Lr[k + (size_t)i * nb]) * Gs[k][c];
+      Gs[i][c] = (1.0 / Lr[i + (size_t)i * nb].re) * x;
+    }
+  }
+  __syncthreads();
+  // Z = Y P(:, perm)
+  const cd *Y = it.Y;
+  cd *Z = it.Z;
+  for (size_t e = tid; e < (size_t)n * nb; e += T) {
     const int r = (int)(e % n), b = (int)(e / n);
     const int pbb = perm[b];
     cd acc = mk(0.0, 0.0);
-    for (int a = 0; a < nb; ++a) acc = cfma(Y[(size_t)a * ld + r], Vs[a][pbb], acc);
+    for (int a = 0; a < nb; ++a) acc = cfma(Y[(size_t)a * ld + r], Gs[a][pbb], acc);
     Z[(size_t)b * ld + r] = acc;
   }
-  (void)active_s;
 }
 
-hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, hipStream_t st) {
+hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st) {
   ProfScope ps(K_RR, st);
-  hipLaunchKernelGGL(rayleigh_ritz, dim3(n_items), dim3(EIG_THREADS), 0, st, items);
+  const int nrb = (n_max + 63) / 64;
+  hipLaunchKernelGGL(rr_product, dim3(nrb, n_items), dim3(256), sizeof(cd) * 2 * 64 * nb, st, items);
+  hipLaunchKernelGGL(rr_small, dim3(n_items), dim3(256), 0, st, items);
   return hipGetLastError();
 }
 
 // Dynamic LDS above the default limit has to be opted into per kernel.
 hipError_t init_kernel_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void *)tridiag_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void *)tridiag_bisect, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)(sizeof(double) * 3 * MAX_N));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)tridiag_invit<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(double) * 8 * INV_LDS_MAX_N));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)tridiag_invit<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(double) * 3 * MAX_N));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)rr_product, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(cd) * 2 * 64 * RR_MAX_BANDS));
   if (e != hipSuccess) return e;
   return init_band_attributes();
 }

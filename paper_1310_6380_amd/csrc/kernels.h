@@ -53,12 +53,14 @@ struct EigItem {
   int *flag;        // nonzero: a kernel gave up waiting (diagnostic)
   // tridiagonal eigenproblem
   double *X;        // n x nb eigenvectors of the tridiagonal matrix (row-major)
-  double *lu;       // 5 n x nb factorisation scratch
+  double *lu;       // 5 n x nb factorisation scratch (orders above the LDS limit)
   double *lam_t;    // nb eigenvalues of the tridiagonal matrix
   // back-transform and refinement
   cd *Y;            // n x nb eigenvectors of C(k) (FP64, input of Rayleigh-Ritz)
   void *Yb;         // (R) back-transform output (== Y on the FP64 path)
-  cd *Z;            // n x nb scratch (C Y)
+  cd *Z;            // n x nb: C Y, then the refined eigenvectors
+  cd *Gp;           // ceil(n/64) x 2 x nb x nb Gram partials of Rayleigh-Ritz
+  cd *Lr;           // nb x nb Cholesky factor of Y^H Y
   double *lam;      // nb refined eigenvalues (lambda = omega^2)
   double *omega;    // nb output frequencies (device)
 };
@@ -106,7 +108,7 @@ long long refl_total(int n);   // number of stage-2 reflectors of an item of ord
 
 // eigen.hip
 hipError_t init_kernel_attributes();  // once per device, before the first launch
-hipError_t launch_tridiag_eig(const EigItem *items, int n_items, hipStream_t st);
-hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, hipStream_t st);
+hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st);
+hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st);
 
 }  // namespace mvpb
