@@ -570,7 +570,7 @@ static void item_layout(int n, int nb, bool fp32, size_t *sz, int *count) {
   sz[k++] = es * nrefl;                          // tau2
   sz[k++] = sizeof(double) * n;                  // d
   sz[k++] = sizeof(double) * n;                  // e
-  sz[k++] = sizeof(int);                         // flag
+  sz[k++] = sizeof(int) * ((size_t)n + 2);       // flag: error, abort, progress of each sweep
   sz[k++] = sizeof(double) * (size_t)n * nb;     // X
   sz[k++] = sizeof(double) * (size_t)5 * n * nb; // lu
   sz[k++] = sizeof(double) * nb;                 // lam_t

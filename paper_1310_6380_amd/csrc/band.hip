@@ -104,9 +104,27 @@ MVPB_DEV void make_reflector(cx<R> alpha, double xn2, double &beta, cx<R> &tau, 
   }
   const double nrm = sqrt(ar * ar + ai * ai + xn2);
   beta = ar >= 0.0 ? -nrm : nrm;
-  tau = mkc<R>((R)((beta - ar) / beta), (R)(-ai / beta));
-  const cd s = cdiv(mk(1.0, 0.0), mk(ar - beta, ai));
-  scale = ccast<R>(s);
+  const double ib = 1.0 / beta;
+  tau = mkc<R>((R)((beta - ar) * ib), (R)(-ai * ib));
+  // 1 / (alpha - beta); |alpha - beta| >= |beta| > 0, so no scaling is needed
+  const double dr = ar - beta, id = 1.0 / (dr * dr + ai * ai);
+  scale = mkc<R>((R)(dr * id), (R)(-ai * id));
+}
+
+// Guarded load without a branch: the address is clamped to element 0 (always
+// valid) when ok is false and the value is replaced by zero, so that many such
+// loads can be in flight at once.
+// Load from a clamped address with no select on the value, for prefetches:
+// the caller applies the mask where the value is used, so that the wait for
+// the load is not forced at the load itself.
+template <typename R>
+MVPB_DEV cx<R> ld_raw(const cx<R> *p, size_t idx, bool ok) {
+  return gld(p, ok ? idx : 0);
+}
+template <typename R>
+MVPB_DEV cx<R> ld_or0(const cx<R> *p, size_t idx, bool ok) {
+  const cx<R> v = gld(p, ok ? idx : 0);
+  return ok ? v : czero<R>();
 }
 
 // ---------------------------------------------------------------------------
@@ -153,7 +171,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
       const int r = tid + PQ_THREADS * s;
 #pragma unroll
       for (int t = 0; t < SW; ++t)
-        x[s][t] = (r < m && cs + t < HB) ? P[(size_t)(cs + t) * ld + r] : czero<R>();
+        x[s][t] = ld_or0<R>(P, (size_t)(cs + t) * ld + r, r < m && cs + t < HB);
     }
     // ---- column loop of the sub-panel.  The registers rotate by one column
     // per step, so that position 0 always holds the current column j:
@@ -243,7 +261,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
       if (r < m) {
 #pragma unroll
         for (int t = 0; t < SW; ++t)
-          if (cs + t < HB) P[(size_t)(cs + t) * ld + r] = x[s][t];
+          if (cs + t < HB) gst(P, (size_t)(cs + t) * ld + r, x[s][t]);
       }
     }
     if (SW < HB && (cs > 0 || cs + SW < HB)) {
@@ -264,7 +282,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
               if (o < nother) {
                 const bool isB = o < nrem;
                 const int col = isB ? cs + SW + o : o - nrem;
-                C b = P[(size_t)col * ld + r];
+                C b = gld(P, (size_t)col * ld + r);
                 if (!isB && r <= col) b = czero<R>();   // r >= cs > col: never taken
 #pragma unroll
                 for (int t = 0; t < SW; ++t) {
@@ -311,14 +329,14 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
         const int r = tid + PQ_THREADS * s;
         if (r < m && r >= cs) {
           for (int u = 0; u < nrem; ++u) {
-            C *bp = P + (size_t)(cs + SW + u) * ld + r;
-            C b = *bp;
+            const size_t bi = (size_t)(cs + SW + u) * ld + r;
+            C b = gld(P, bi);
 #pragma unroll
             for (int t = 0; t < SW; ++t) {
               const C vs = (r > cs + t) ? x[s][t] : (r == cs + t ? mkc<R>(R(1), R(0)) : czero<R>());
               b = b - vs * Sb[t][u];
             }
-            *bp = b;
+            gst(P, bi, b);
           }
         }
       }
@@ -330,16 +348,16 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
   __syncthreads();
   for (int e = tid; e < HB * HB; e += PQ_THREADS) {
     const int i = e % HB, jx = e / HB;
-    T1[e] = (i < kq && jx < kq && i <= jx) ? Tm[i][jx] : czero<R>();
+    gst(T1, e, (i < kq && jx < kq && i <= jx) ? Tm[i][jx] : czero<R>());
   }
 }
 
 // V(r, t) of panel p: unit lower trapezoidal, stored strictly below its diagonal.
 template <typename R>
 MVPB_DEV cx<R> panel_v(const cx<R> *Vp, size_t ld, int r, int t, int m, int kq) {
-  if (r >= m || t >= kq || r < t) return czero<R>();
-  if (r == t) return mkc<R>(R(1), R(0));
-  return Vp[(size_t)t * ld + r];
+  const bool in = r < m && t < kq;
+  const cx<R> v = ld_or0<R>(Vp, (size_t)t * ld + r, in && r > t);
+  return (in && r == t) ? mkc<R>(R(1), R(0)) : v;
 }
 
 // ---------------------------------------------------------------------------
@@ -352,19 +370,58 @@ MVPB_DEV cx<R> panel_v(const cx<R> *Vp, size_t ld, int r, int t, int m, int kq) 
 template <typename R>
 MVPB_DEV cx<R> hemm_elem(const cx<R> *A22, size_t ld, int m, int gr, int gc) {
   // A22(gr, gc) of the Hermitian trailing matrix from its lower triangle
-  if (gr >= m || gc >= m) return czero<R>();
-  if (gr > gc) return A22[(size_t)gc * ld + gr];
-  if (gr < gc) return conj(A22[(size_t)gr * ld + gc]);
-  return mkc<R>(A22[(size_t)gc * ld + gr].re, R(0));
+  const bool in = gr < m && gc < m, lower = gr >= gc;
+  const size_t idx = lower ? (size_t)gc * ld + gr : (size_t)gr * ld + gc;
+  cx<R> v = ld_or0<R>(A22, idx, in);
+  if (!lower) v.im = -v.im;
+  if (gr == gc) v.im = R(0);
+  return v;
 }
 
+// Matrix-core step of the complex product: C += A B with A (16 x 4) and
+// B (4 x 16) complex, as four real 16x16x4 products (FP64: v_mfma_f64;
+// FP32: v_mfma_f32).  Lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+// holds D[row][l%16], row = l/16 + 4v (FP64) or 4(l/16) + v (FP32).
+typedef double hd4_t __attribute__((ext_vector_type(4)));
+typedef float hf4_t __attribute__((ext_vector_type(4)));
+template <typename R>
+struct CMma;
+template <>
+struct CMma<double> {
+  typedef hd4_t acc;
+  MVPB_DEV static acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  MVPB_DEV static void step(cd a, cd b, acc &cr, acc &ci) {
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, cr, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, ci, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, ci, 0, 0, 0);
+  }
+  MVPB_DEV static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct CMma<float> {
+  typedef hf4_t acc;
+  MVPB_DEV static acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  MVPB_DEV static void step(cf a, cf b, acc &cr, acc &ci) {
+    cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, b.re, cr, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.im, b.im, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, b.im, ci, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, b.re, ci, 0, 0, 0);
+  }
+  MVPB_DEV static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// X0 for row block rb (64 rows) on the matrix cores: wavefront wv owns rows
+// 16 wv .. 16 wv + 15 and all HB = 16 columns; column blocks of TC are
+// staged in LDS (the next block is loaded into registers meanwhile).
 template <typename R>
 __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ items, int p) {
   typedef cx<R> C;
+  typedef CMma<R> M;
   constexpr int TC = 32;
   constexpr int PER = 64 * TC / 256;   // tile elements loaded per thread
-  __shared__ C tile[TC][65];        // tile[cc][rr] = A22(rb*64 + rr, cb*TC + cc)
-  __shared__ C Vc[TC][HB];          // V rows of the column block
+  __shared__ C tile[TC][65];        // tile[cc][rr] = A22(rb*64 + rr, cb*TC + cc); X0 of the block at the end
+  __shared__ C Vc[TC][HB + 1];      // V rows of the column block
   const EigItem it = items[blockIdx.y];
   const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
   const int rb = blockIdx.x;
@@ -373,30 +430,42 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
   const size_t ld = (size_t)n;
   const C *__restrict__ A22 = (const C *)it.A + (size_t)(c0 + HB) * ld + (c0 + HB);
   const C *__restrict__ Vp = (const C *)it.A + (size_t)c0 * ld + (c0 + HB);
-  const int tid = threadIdx.x, r = tid & 63, ks = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r0 = rb * 64;
   // Element e = tid + 256 u of a 64 x TC tile: below the row block it is read
   // down a stored column (rr fastest), right of it across (cc fastest, then
   // conjugate-transposed) so that both reads are coalesced.
+  // Raw values with per-element flags (bit 0: in range, bit 1: read
+  // transposed, so conjugate; bit 2: diagonal, so real), applied at the LDS
+  // store so that the loads stay in flight during the products.
   C nxt[PER], vnx[2];
+  unsigned fl = 0;
   auto fetch = [&](int cb0) {
     const bool above = cb0 >= r0 + 64;   // entirely right of the diagonal block
+    fl = 0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 256 * u;
       int rr, cc;
       if (above) { cc = e % TC; rr = e / TC; } else { rr = e & 63; cc = e >> 6; }
-      nxt[u] = hemm_elem<R>(A22, ld, m, r0 + rr, cb0 + cc);
+      const int gr = r0 + rr, gc = cb0 + cc;
+      const bool in = gr < m && gc < m, lower = gr >= gc;
+      const size_t idx = lower ? (size_t)gc * ld + gr : (size_t)gr * ld + gc;
+      nxt[u] = ld_raw<R>(A22, idx, in);
+      fl |= ((in ? 1u : 0u) | (lower ? 0u : 2u) | (gr == gc ? 4u : 0u)) << (3 * u);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int e = tid + 256 * u;
-      vnx[u] = panel_v<R>(Vp, ld, cb0 + e % TC, e / TC, m, kq);
+      const int r = cb0 + e % TC, t = e / TC;
+      const bool in = r < m && t < kq;
+      vnx[u] = ld_raw<R>(Vp, (size_t)t * ld + r, in && r > t);
+      fl |= ((in && r > t) ? 1u : 0u) << (24 + 2 * u);
+      fl |= ((in && r == t) ? 1u : 0u) << (25 + 2 * u);
     }
   };
-  C acc[HB];
-#pragma unroll
-  for (int t = 0; t < HB; ++t) acc[t] = czero<R>();
+  typename M::acc cr = M::zero(), ci = M::zero();
+  const int ai = lane & 15, ak = lane >> 4;   // operand slot of this lane
   fetch(0);
   for (int cb0 = 0; cb0 < m; cb0 += TC) {
     const bool above = cb0 >= r0 + 64;
@@ -405,56 +474,55 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
       const int e = tid + 256 * u;
       int rr, cc;
       if (above) { cc = e % TC; rr = e / TC; } else { rr = e & 63; cc = e >> 6; }
-      tile[cc][rr] = nxt[u];
+      const unsigned f = fl >> (3 * u);
+      C v = nxt[u];
+      if (f & 2u) v.im = -v.im;
+      if (f & 4u) v.im = R(0);
+      tile[cc][rr] = (f & 1u) ? v : czero<R>();
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int e = tid + 256 * u;
-      Vc[e % TC][e / TC] = vnx[u];
+      const unsigned f = fl >> (24 + 2 * u);
+      Vc[e % TC][e / TC] = (f & 1u) ? vnx[u] : ((f & 2u) ? mkc<R>(R(1), R(0)) : czero<R>());
     }
-    __syncthreads();
-    if (cb0 + TC < m) fetch(cb0 + TC);   // in flight during the products below
-#pragma unroll 2
-    for (int cc = ks; cc < TC; cc += 4) {
-      const C a = tile[cc][r];
+    lds_barrier();
+    fetch(cb0 + TC);   // in flight during the products below (past the end: clamped, unused)
 #pragma unroll
-      for (int t = 0; t < HB; ++t) acc[t] = cfma(a, Vc[cc][t], acc[t]);
+    for (int k0 = 0; k0 < TC; k0 += 4) {
+      const C a = tile[k0 + ak][16 * wv + ai];
+      const C b = Vc[k0 + ak][ai];
+      M::step(a, b, cr, ci);
     }
-    __syncthreads();
+    lds_barrier();
   }
-  // sum the 4 column phases (two halves of HB through the tile buffer)
-  C *red = &tile[0][0];   // [4][64][HB/2]
+  // X0 rows of this block: lane holds D[row][t = lane % 16]
   C *X0 = (C *)it.X0;
-  __shared__ C X0s[64][HB + 1];
-  for (int h = 0; h < 2; ++h) {
+  C *X0s = &tile[0][0];   // [64][HB + 1]
 #pragma unroll
-    for (int t = 0; t < HB / 2; ++t) red[(ks * 64 + r) * (HB / 2) + t] = acc[h * (HB / 2) + t];
-    __syncthreads();
-    for (int e = tid; e < 64 * (HB / 2); e += 256) {
-      const int rr = e % 64, t = e / 64;
-      C sm = czero<R>();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sm = sm + red[(q * 64 + rr) * (HB / 2) + t];
-      X0s[rr][h * (HB / 2) + t] = sm;
-      if (r0 + rr < m) X0[(size_t)(h * (HB / 2) + t) * ld + r0 + rr] = sm;
-    }
-    __syncthreads();
+  for (int v = 0; v < 4; ++v) {
+    const int rr = 16 * wv + M::row(lane, v), t = lane & 15;
+    const C x = mkc<R>(cr[v], ci[v]);
+    X0s[rr * (HB + 1) + t] = x;
+    if (r0 + rr < m) gst(X0, (size_t)t * ld + r0 + rr, x);
   }
-  // Gram partial G[i][j] = sum_rr conj(V[rr][i]) X0[rr][j]; V rows of this
-  // block staged through the tile buffer
-  C *Vr = &tile[0][0];   // [64][HB]
-  for (int e = tid; e < 64 * HB; e += 256) {
-    const int i = e & 63, t = e >> 6;
-    Vr[i * HB + t] = panel_v<R>(Vp, ld, r0 + i, t, m, kq);
-  }
-  __syncthreads();
+  // Gram partial G[i][j] = sum_rr conj(V[rr][i]) X0[rr][j]; V rows of the block in Vc
+  lds_barrier();
+  C *Vr = &Vc[0][0];   // [64][HB] would not fit: two passes of 32 rows
   C *M0p = (C *)it.M0p + (size_t)rb * HB * HB;
-  for (int e = tid; e < HB * HB; e += 256) {
-    const int i = e % HB, jx = e / HB;
-    C sm = czero<R>();
-    for (int rr = 0; rr < 64; ++rr) sm = cfma_cj(Vr[rr * HB + i], X0s[rr][jx], sm);
-    M0p[e] = sm;
+  C gsum = czero<R>();
+  const int gi = tid % HB, gj = tid / HB;   // 256 threads = HB x HB
+  for (int h = 0; h < 2; ++h) {
+    for (int e = tid; e < 32 * HB; e += 256) {
+      const int i = e % 32, t = e / 32;
+      Vr[i * (HB + 1) + t] = panel_v<R>(Vp, ld, r0 + 32 * h + i, t, m, kq);
+    }
+    lds_barrier();
+    for (int rr = 0; rr < 32; ++rr)
+      gsum = cfma_cj(Vr[rr * (HB + 1) + gi], X0s[(32 * h + rr) * (HB + 1) + gj], gsum);
+    lds_barrier();
   }
+  gst(M0p, (size_t)gi + (size_t)gj * HB, gsum);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,9 +545,9 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
   for (int e = tid; e < HB * HB; e += 256) {
     const int i = e % HB, jx = e / HB;
     C s = czero<R>();
-    for (int b = 0; b < nrb; ++b) s = s + M0p[(size_t)b * HB * HB + e];
+    for (int b = 0; b < nrb; ++b) s = s + gld(M0p, (size_t)b * HB * HB + e);
     G[i][jx] = s;
-    Tm[i][jx] = T1[e];
+    Tm[i][jx] = gld(T1, e);
   }
   __syncthreads();
   for (int e = tid; e < HB * HB; e += 256) {
@@ -505,7 +573,7 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
   C xr[HB], vr[HB];
 #pragma unroll
   for (int t = 0; t < HB; ++t) {
-    xr[t] = X0[(size_t)t * ld + r];
+    xr[t] = gld(X0, (size_t)t * ld + r);
     vr[t] = panel_v<R>(Vp, ld, r, t, m, kq);
   }
 #pragma unroll
@@ -517,18 +585,25 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
       if (l <= t) s = cfma(xr[l], Tm[l][t], s);
       s = s - R(0.5) * (vr[l] * Y[l][t]);
     }
-    Wm[(size_t)t * ld + r] = s;
+    gst(Wm, (size_t)t * ld + r, s);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Stage 1d.  A22 <- A22 - W V^H - V W^H on the lower 64 x 64 tiles
-// (upper entries of diagonal tiles are written too but never read).
+// Stage 1d.  A22 <- A22 - W V^H - V W^H on the lower 64 x 64 tiles, on the
+// matrix cores.  The update D = W V^H + V W^H is Hermitian: the product is
+// formed for the transposed position, Out[c][r] = D[c][r] (columns of the
+// tile as the M index), so that a lane's outputs D[r][c] = conj(Out[c][r])
+// sit on consecutive stored rows r.  Wavefront wv owns tile columns
+// 16 wv .. 16 wv + 15 and all 64 rows.  The tile being updated is read
+// before the products (upper entries of diagonal tiles are written too but
+// never read).
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ items, int p) {
   typedef cx<R> C;
-  __shared__ C Vr[HB][65], Wr[HB][65], Vc[HB][65], Wc[HB][65];
+  typedef CMma<R> M;
+  __shared__ C Vr[HB][65], Wr[HB][65], Vc[HB][65], Wc[HB][65];   // [k][i]: rows (r) / columns (c) of the tile
   const EigItem it = items[blockIdx.y];
   const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
   if (m <= 0) return;
@@ -545,55 +620,58 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
   const C *__restrict__ Vp = (const C *)it.A + (size_t)c0 * ld + (c0 + HB);
   const C *__restrict__ Wm = (const C *)it.Wm;
   const int r0 = I * 64, cc0 = J * 64;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int ai = lane & 15, ak = lane >> 4;
+  // the tile values this lane updates: rows r0 + 16 rb + ai, columns
+  // cc0 + 16 wv + M::row(lane, v)
+  C cur[4][4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int gr = r0 + 16 * rb + ai;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gc = cc0 + 16 * wv + M::row(lane, v);
+      cur[rb][v] = ld_raw<R>(A22, (size_t)gc * ld + gr, gc < m && gr < m);   // stored only in bounds
+    }
+  }
   for (int e = tid; e < 64 * HB; e += 256) {
     const int i = e & 63, k = e >> 6;
     const int gr = r0 + i, gc = cc0 + i;
     const bool kr = k < kq;
     Vr[k][i] = panel_v<R>(Vp, ld, gr, k, m, kq);
-    Wr[k][i] = (gr < m && kr) ? Wm[(size_t)k * ld + gr] : czero<R>();
-    Vc[k][i] = (gc < m && kr) ? conj(Wm[(size_t)k * ld + gc]) : czero<R>();
-    Wc[k][i] = conj(panel_v<R>(Vp, ld, gc, k, m, kq));
+    Wr[k][i] = ld_or0<R>(Wm, (size_t)k * ld + gr, gr < m && kr);
+    Vc[k][i] = panel_v<R>(Vp, ld, gc, k, m, kq);
+    Wc[k][i] = ld_or0<R>(Wm, (size_t)k * ld + gc, gc < m && kr);
   }
-  // the output tile is fetched before the product so that its latency overlaps it
-  C cur[4][4];
+  lds_barrier();
+  typename M::acc cr[4], ci[4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int gc = cc0 + ty + 16 * b;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int gr = r0 + tx + 16 * a;
-      cur[a][b] = (gc < m && gr < m) ? A22[(size_t)gc * ld + gr] : czero<R>();
-    }
-  }
-  __syncthreads();
-#pragma unroll 1
-  for (int k = 0; k < HB; ++k) {
-    C a1[4], a2[4], b1[4], b2[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      a1[a] = -Vr[k][tx + 16 * a];
-      a2[a] = -Wr[k][tx + 16 * a];
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      b1[b] = Vc[k][ty + 16 * b];
-      b2[b] = Wc[k][ty + 16 * b];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) cur[a][b] = cfma(a1[a], b1[b], cfma(a2[a], b2[b], cur[a][b]));
+  for (int rb = 0; rb < 4; ++rb) {
+    cr[rb] = M::zero();
+    ci[rb] = M::zero();
   }
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int gc = cc0 + ty + 16 * b;
-    if (gc >= m) continue;
+  for (int k0 = 0; k0 < HB; k0 += 4) {
+    const C aw = Wc[k0 + ak][16 * wv + ai];   // W[c][k]
+    const C av = Vc[k0 + ak][16 * wv + ai];   // V[c][k]
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int gr = r0 + tx + 16 * a;
-      if (gr >= m) continue;
-      A22[(size_t)gc * ld + gr] = cur[a][b];
+    for (int rb = 0; rb < 4; ++rb) {
+      const C bv = conj(Vr[k0 + ak][16 * rb + ai]);   // conj(V[r][k])
+      const C bw = conj(Wr[k0 + ak][16 * rb + ai]);   // conj(W[r][k])
+      M::step(aw, bv, cr[rb], ci[rb]);
+      M::step(av, bw, cr[rb], ci[rb]);
+    }
+  }
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int gr = r0 + 16 * rb + ai;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gc = cc0 + 16 * wv + M::row(lane, v);
+      if (gc < m && gr < m) {
+        const C d = mkc<R>(cr[rb][v], -ci[rb][v]);   // D[r][c] = conj(Out[c][r])
+        gst(A22, (size_t)gc * ld + gr, cur[rb][v] - d);
+      }
     }
   }
 }
@@ -674,60 +752,124 @@ MVPB_DEV cx<R> row16_sum_c(cx<R> v) {
 static_assert(HB == 16, "the lane layout of the bulge-chasing kernel assumes HB = 16");
 constexpr int CH_WAVES = 16;
 constexpr long long CH_SPIN_LIMIT = 1ll << 24;
+// workgroups per item of the bulge chasing, and the CUs that may be used
+// (one 1024-thread workgroup per CU keeps every workgroup resident)
+constexpr int HB2ST_MAX_WG = 4;
+constexpr int HB2ST_CU_BUDGET = 256;
 
+// Copy the band (subdiagonals 0 .. HB) of the stage-1 result into the
+// working band WB (subdiagonals HB+1 .. 2 HB zero) and clear the item's
+// progress counters: flag[0] error, flag[1] abort, flag[2 + i] blocks done by
+// sweep i.
 template <typename R>
-__global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict__ items) {
+__global__ void __launch_bounds__(256) hb2st_init(const EigItem *__restrict__ items) {
+  typedef cx<R> C;
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N;
+  const size_t ld = (size_t)n;
+  const C *A = (const C *)it.A;
+  C *WB = (C *)it.WB;
+  const size_t total = (size_t)n * HB_LDB;
+  for (size_t e = blockIdx.x * (size_t)256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const int c = (int)(e / HB_LDB), d = (int)(e % HB_LDB), r = c + d;
+    const bool ok = d <= HB && r < n;
+    C v = ld_or0<R>(A, (size_t)c * ld + r, ok);
+    if (d == 0) v.im = R(0);
+    gst(WB, e, v);
+  }
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n + 2; e += gridDim.x * 256) gst(it.flag, e, 0);
+}
+
+// d, e of the tridiagonal result.
+template <typename R>
+__global__ void __launch_bounds__(256) hb2st_fini(const EigItem *__restrict__ items) {
+  typedef cx<R> C;
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N;
+  const C *WB = (const C *)it.WB;
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    gst(it.d, r, (double)gld(WB, (size_t)r * HB_LDB).re);
+    if (r < n - 1) gst(it.e, r, (double)gld(WB, (size_t)r * HB_LDB + 1).re);
+  }
+}
+
+// Workgroup layout of the bulge chasing: P workgroups per item, all on the
+// XCD (L2) of the item: workgroup L of the 1-D grid runs on XCD L % 8, and
+// item j is given the slots s = (j / 8) P .. (j / 8) P + P - 1 of XCD j % 8.
+// Sweep i belongs to workgroup (i / 16) % P, wavefront i % 16.  Sweeps hand
+// over within a workgroup through LDS counters and between workgroups
+// through counters in the shared L2 (the consumer invalidates its L1 before
+// reading the producer's blocks).
+template <typename R>
+__global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict__ items, int n_items, int P) {
   typedef cx<R> C;
   __shared__ int prog[CH_WAVES];
   __shared__ int abort_s;
-  const EigItem it = items[blockIdx.x];
+  const int L = blockIdx.x, xcd = L & 7, slot = L >> 3;
+  const int item = (slot / P) * 8 + xcd, a = slot % P;
+  if (item >= n_items) return;
+  const EigItem it = items[item];
   const int n = 2 * it.N;
-  const size_t ld = (size_t)n;
-  const C *__restrict__ A = (const C *)it.A;
   C *__restrict__ WB = (C *)it.WB;
   C *__restrict__ V2 = (C *)it.V2;
   C *__restrict__ tau2 = (C *)it.tau2;
+  int *gflag = it.flag;
   const int tid = threadIdx.x;
-  for (size_t e = tid; e < (size_t)n * HB_LDB; e += CH_WAVES * 64) {
-    const int c = (int)(e / HB_LDB), d = (int)(e % HB_LDB), r = c + d;
-    C v = czero<R>();
-    if (d <= HB && r < n) {
-      v = A[(size_t)c * ld + r];
-      if (d == 0) v.im = R(0);
-    }
-    WB[e] = v;
-  }
   if (tid < CH_WAVES) prog[tid] = -1;
-  if (tid == 0) {
-    abort_s = 0;
-    *it.flag = 0;
-  }
+  if (tid == 0) abort_s = 0;
   __syncthreads();
   const int w = tid >> 6, lane = tid & 63, q = lane & 15, g = lane >> 4;
   bool aborted = false;
-  for (int i = w; i < n - 1 && !aborted; i += CH_WAVES) {
+  for (int i0 = CH_WAVES * a; i0 < n - 1 && !aborted; i0 += CH_WAVES * P) {
+    const int i = i0 + w;
+    if (i >= n - 1) break;
     const int nsteps = (n - 1 - i + HB - 1) / HB;
     const int nprev = (n - i + HB - 1) / HB;   // blocks of sweep i-1
     const long long roff = refl_count(n - 1) - refl_count(n - 1 - i);
+    const bool cross = (w == 0) && (P > 1) && (i > 0);   // sweep i-1 is in another workgroup
     C vprev = czero<R>(), tauprev = czero<R>();
     for (int k = 0; k < nsteps; ++k) {
       if (i > 0) {
-        const int need = (i - 1) * 1024 + min(k + 3, nprev);
+        const int nd = min(k + 3, nprev);
         long long spins = 0;
-        while (__hip_atomic_load(&prog[(i - 1) % CH_WAVES], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
-          if (__hip_atomic_load(&abort_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-            aborted = true;
-            break;
+        if (!cross) {
+          const int need = (i - 1) * 1024 + nd;
+          while (__hip_atomic_load(&prog[(i - 1) % CH_WAVES], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+            if (__hip_atomic_load(&abort_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+              aborted = true;
+              break;
+            }
+            if (++spins > CH_SPIN_LIMIT) {
+              aborted = true;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
           }
-          if (++spins > CH_SPIN_LIMIT) {
-            __hip_atomic_store(&abort_s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (lane == 0) *it.flag = 1;
-            aborted = true;
-            break;
+        } else {
+          while (__hip_atomic_load(gflag + 2 + (i - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nd) {
+            if (__hip_atomic_load(gflag + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                __hip_atomic_load(&abort_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+              aborted = true;
+              break;
+            }
+            if (++spins > CH_SPIN_LIMIT) {
+              aborted = true;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
           }
-          __builtin_amdgcn_s_sleep(1);
+          // the blocks of sweep i-1 were written from another CU of this XCD:
+          // drop stale L1 lines before reading them
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        if (aborted) break;
+        if (aborted) {
+          __hip_atomic_store(&abort_s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (lane == 0) {
+            __hip_atomic_store(gflag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          break;
+        }
       }
       const int s = i + 1 + k * HB;
       const int L = min(HB, n - s);
@@ -736,24 +878,23 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
       // annihilated and the diagonal block D = A[J_k, J_k]
       C y[4], dq[4];
       if (k == 0) {
-        const C x = (q < L) ? WB[(size_t)i * HB_LDB + 1 + q] : czero<R>();
+        const C x = ld_or0<R>(WB, (size_t)i * HB_LDB + 1 + q, q < L);
 #pragma unroll
         for (int t = 0; t < 4; ++t) y[t] = x;
       } else {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int c = 4 * g + t;
-          y[t] = (q < L) ? WB[(size_t)(ps + c) * HB_LDB + HB + q - c] : czero<R>();
+          y[t] = ld_or0<R>(WB, (size_t)(ps + c) * HB_LDB + HB + q - c, q < L);
         }
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int c = 4 * g + t;
-        C v = czero<R>();
-        if (q < L && c < L) {
-          if (q >= c) v = WB[(size_t)(s + c) * HB_LDB + q - c];
-          else v = conj(WB[(size_t)(s + q) * HB_LDB + c - q]);
-        }
+        const bool lo = q >= c;
+        const size_t idx = lo ? (size_t)(s + c) * HB_LDB + q - c : (size_t)(s + q) * HB_LDB + c - q;
+        C v = ld_or0<R>(WB, idx, q < L && c < L);
+        if (!lo) v.im = -v.im;
         dq[t] = v;
       }
       C vq, tau, x;
@@ -785,7 +926,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
       vq = (q == 0) ? mkc<R>(R(1), R(0)) : (q < L ? x * scale : czero<R>());
       const C betac = (q == 0) ? mkc<R>((R)beta, R(0)) : czero<R>();
       if (k == 0) {
-        if (g == 0 && q < L) WB[(size_t)i * HB_LDB + 1 + q] = betac;
+        if (g == 0 && q < L) gst(WB, (size_t)i * HB_LDB + 1 + q, betac);
       } else {
         if (g == 0) y[0] = betac;
         // (c) columns c >= 1: y <- y - conj(tau) v (v^H y)
@@ -802,7 +943,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int c = 4 * g + t;
-            WB[(size_t)(ps + c) * HB_LDB + HB + q - c] = y[t];
+            gst(WB, (size_t)(ps + c) * HB_LDB + HB + q - c, y[t]);
           }
         }
       }
@@ -830,32 +971,37 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
             if (c <= q) {
               C v = dq[t] - vq * conj(wc[t]) - wq * conj(vc[t]);
               if (c == q) v.im = R(0);
-              WB[(size_t)(s + c) * HB_LDB + q - c] = v;
+              gst(WB, (size_t)(s + c) * HB_LDB + q - c, v);
             }
           }
         }
       }
       __threadfence_block();
-      if (lane == 0)
+      if (lane == 0) {
         __hip_atomic_store(&prog[w], i * 1024 + k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        // the last sweep of a group of 16 also reports to the next workgroup
+        if (w == CH_WAVES - 1 && P > 1)
+          __hip_atomic_store(gflag + 2 + i, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       // the reflector for the back-transform (after the release: not waited for)
       if (g == 0) {
-        C *dst = V2 + (size_t)(roff + k) * HB + q;
-        __builtin_nontemporal_store(vq.re, &dst->re);
-        __builtin_nontemporal_store(vq.im, &dst->im);
+        MVPB_GAS R *dst = (MVPB_GAS R *)(V2 + (size_t)(roff + k) * HB + q);
+        __builtin_nontemporal_store(vq.re, dst);
+        __builtin_nontemporal_store(vq.im, dst + 1);
       }
-      if (lane == 0) tau2[roff + k] = tau;
+      if (lane == 0) gst(tau2, roff + k, tau);
       vprev = vq;
       tauprev = tau;
     }
   }
-  __syncthreads();
-  if (abort_s) return;
-  for (int r = tid; r < n; r += CH_WAVES * 64) {
-    it.d[r] = (double)WB[(size_t)r * HB_LDB].re;
-    if (r < n - 1) it.e[r] = (double)WB[(size_t)r * HB_LDB + 1].re;
-  }
 }
+
+// LDS index of entry (r, c) of an n x nc block of eigenvector columns: rows
+// padded to nc+1 entries and skewed by one entry every 16 rows, so that the
+// rows touched by one wavefront (consecutive, or 16 apart) fall in
+// different banks.
+MVPB_HD int zidx(int r, int c, int nc) { return r * (nc + 1) + c + (r >> 4); }
+MVPB_HD size_t zbytes(int n, int nc, size_t es) { return es * ((size_t)n * (nc + 1) + (size_t)n / 16 + 1); }
 
 // ---------------------------------------------------------------------------
 // Back-transform.  Z (n x nc columns of the tridiagonal eigenvectors) in LDS;
@@ -867,7 +1013,7 @@ template <typename R>
 __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__restrict__ items, int nc) {
   typedef cx<R> C;
   extern __shared__ __align__(16) unsigned char shraw[];
-  C *Z = (C *)shraw;   // Z[r * nc + c]
+  C *Z = (C *)shraw;   // Z[zidx(r, c, nc)]
   __shared__ C S[HB][8], S2[HB][8], Tm[HB][HB + 1];
   const EigItem it = items[blockIdx.y];
   const int n = 2 * it.N, nb = it.nb;
@@ -878,7 +1024,7 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
   const size_t ld = (size_t)n;
   for (int e = tid; e < n * nc; e += BT_THREADS) {
     const int r = e / nc, c = e % nc;
-    Z[e] = (c < ncl) ? mkc<R>((R)it.X[(size_t)r * nb + cbase + c], R(0)) : czero<R>();
+    Z[zidx(r, c, nc)] = (c < ncl) ? mkc<R>((R)gld(it.X, (size_t)r * nb + cbase + c), R(0)) : czero<R>();
   }
   __syncthreads();
   // ---- stage 2: sweeps i = n-2 .. 0; the blocks of one sweep are disjoint.
@@ -887,78 +1033,118 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
   const C *V2 = (const C *)it.V2;
   const C *tau2 = (const C *)it.tau2;
   const long long rtot = refl_count(n - 1);
+  // Branch-free (clamped addresses, values of absent blocks unused), so that
+  // the loads stay in flight across the loop iterations.
   auto fetch = [&](int i, C (&vv)[HB], C &tau) {
-    const int nsteps = (n - 1 - i + HB - 1) / HB;
-    const int k = tid / ncl;
-    if (i < 0 || k >= nsteps) return;
-    const long long ri = rtot - refl_count(n - 1 - i) + k;
+    const int ic = max(i, 0);
+    const int nsteps = (n - 1 - ic + HB - 1) / HB;
+    const int k = min(tid / ncl, nsteps - 1);
+    const long long ri = rtot - refl_count(n - 1 - ic) + k;
     const C *v = V2 + (size_t)ri * HB;
-    const int L = min(HB, n - (i + 1 + k * HB));
 #pragma unroll
-    for (int j = 0; j < HB; ++j) vv[j] = (j < L) ? v[j] : czero<R>();
-    tau = tau2[ri];
+    for (int j = 0; j < HB; ++j) vv[j] = gld(v, j);
+    tau = gld(tau2, ri);
   };
-  C vcur[HB], vnxt[HB], tcur = czero<R>(), tnxt = czero<R>();
+  // three register stages: sweep i (applied now), i-1 and i-2 (in flight)
+  C va[HB], vb[HB], vc2[HB], ta = czero<R>(), tb = czero<R>(), tc = czero<R>();
 #pragma unroll
-  for (int j = 0; j < HB; ++j) vcur[j] = vnxt[j] = czero<R>();
-  fetch(n - 2, vcur, tcur);
-  for (int i = n - 2; i >= 0; --i) {
-    fetch(i - 1, vnxt, tnxt);
+  for (int j = 0; j < HB; ++j) va[j] = vb[j] = vc2[j] = czero<R>();
+  fetch(n - 2, va, ta);
+  fetch(n - 3, vb, tb);
+  auto apply = [&](int i, const C (&vcur)[HB], C tcur) {
     const int nsteps = (n - 1 - i + HB - 1) / HB;
     const int k = tid / ncl, c = tid % ncl;
     if (k < nsteps) {
       const int s = i + 1 + k * HB;
       const int L = min(HB, n - s);
-      C *zc = Z + (size_t)s * nc + c;
       C d0 = czero<R>(), d1 = czero<R>();
 #pragma unroll
       for (int j = 0; j < HB; j += 2) {
-        if (j < L) d0 = cfma_cj(vcur[j], zc[(size_t)j * nc], d0);
-        if (j + 1 < L) d1 = cfma_cj(vcur[j + 1], zc[(size_t)(j + 1) * nc], d1);
+        if (j < L) d0 = cfma_cj(vcur[j], Z[zidx(s + j, c, nc)], d0);
+        if (j + 1 < L) d1 = cfma_cj(vcur[j + 1], Z[zidx(s + j + 1, c, nc)], d1);
       }
       const C td = tcur * (d0 + d1);
 #pragma unroll
       for (int j = 0; j < HB; ++j)
-        if (j < L) zc[(size_t)j * nc] = zc[(size_t)j * nc] - vcur[j] * td;
+        if (j < L) Z[zidx(s + j, c, nc)] = Z[zidx(s + j, c, nc)] - vcur[j] * td;
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < HB; ++j) vcur[j] = vnxt[j];
-    tcur = tnxt;
+    lds_barrier();
+  };
+  int i = n - 2;
+  for (; i >= 2; i -= 3) {
+    fetch(i - 2, vc2, tc);
+    apply(i, va, ta);
+    fetch(i - 3, va, ta);
+    apply(i - 1, vb, tb);
+    fetch(i - 4, vb, tb);
+    apply(i - 2, vc2, tc);
   }
-  // ---- stage 1: panels last to first; rows c0+HB .. n-1
+  // the remaining sweeps (at most two) are already in va, vb
+  if (i >= 0) apply(i, va, ta);
+  if (i >= 1) apply(i - 1, vb, tb);
+  C *Y = (C *)it.Yb;
+  for (int e = tid; e < n * ncl; e += BT_THREADS) {
+    const int r = e % n, c = e / n;
+    gst(Y, (size_t)(cbase + c) * ld + r, Z[zidx(r, c, nc)]);
+  }
+}
+
+// Stage-1 part of the back-transform: Y <- Q1 Y with the block reflectors of
+// the panels, last panel first; nc columns of Y per workgroup in LDS.
+template <typename R>
+__global__ void __launch_bounds__(BT_THREADS) backtransform_s1(const EigItem *__restrict__ items, int nc) {
+  typedef cx<R> C;
+  extern __shared__ __align__(16) unsigned char shraw[];
+  C *Z = (C *)shraw;   // Z[zidx(r, c, nc)]
+  __shared__ C S[HB][8], S2[HB][9], Tm[HB][HB + 1];
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N, nb = it.nb;
+  const int cbase = blockIdx.x * nc;
+  if (cbase >= nb) return;
+  const int ncl = min(nc, nb - cbase);
+  const int tid = threadIdx.x;
+  const size_t ld = (size_t)n;
+  C *Yb = (C *)it.Yb;
+  for (int e = tid; e < n * nc; e += BT_THREADS) {
+    const int r = e % n, c = e / n;
+    Z[zidx(r, c, nc)] = (c < ncl) ? gld(Yb, (size_t)(cbase + c) * ld + r) : czero<R>();
+  }
+  __syncthreads();
+  // panels last to first; rows c0+HB .. n-1
   const int npan = n > HB ? (n - 1) / HB : 0;   // panels with m = n - p HB - HB > 0
   const C *A = (const C *)it.A;
-  const int rg = tid & 15, tt = (tid >> 4) & (HB - 1);   // (row phase, reflector column) for V^H Z
+  constexpr int RG = BT_THREADS / HB;          // row phases of V^H Z
+  const int rg = tid % RG, tt = tid / RG;      // lanes of a wavefront: consecutive rows
   for (int p = npan - 1; p >= 0; --p) {
     const int c0 = p * HB, m = n - c0 - HB;
     const int kq = min(m, HB);
     const C *Vp = A + (size_t)c0 * ld + (c0 + HB);
     const C *T1 = (const C *)it.T1 + (size_t)p * HB * HB;
-    for (int e = tid; e < HB * HB; e += BT_THREADS) Tm[e % HB][e / HB] = T1[e];
-    // S = V^H Z[rows]: thread (rg, tt) sums rows rg, rg+16, ...
+    for (int e = tid; e < HB * HB; e += BT_THREADS) Tm[e % HB][e / HB] = gld(T1, e);
+    // S = V^H Z[rows]: thread (rg, tt) sums rows tt+rg, tt+rg+RG, ...
     C acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = czero<R>();
-    if (tt < kq && tid < 16 * HB) {
-      for (int r = tt + rg; r < m; r += 16) {   // V(r, tt) = 0 for r < tt
-        const C v = (r == tt) ? mkc<R>(R(1), R(0)) : Vp[(size_t)tt * ld + r];
-        const C *zr = Z + (size_t)(c0 + HB + r) * nc;
+    if (tt < kq) {
+      for (int r = tt + rg; r < m; r += RG) {   // V(r, tt) = 0 for r < tt
+        const C vl = gld(Vp, (size_t)tt * ld + r);
+        const C v = (r == tt) ? mkc<R>(R(1), R(0)) : vl;
+        const C *zr = Z + zidx(c0 + HB + r, 0, nc);
 #pragma unroll
         for (int c = 0; c < 8; ++c)
           if (c < ncl) acc[c] = cfma_cj(v, zr[c], acc[c]);
       }
     }
 #pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
+    for (int o = 1; o < RG; o <<= 1) {
 #pragma unroll
       for (int c = 0; c < 8; ++c) acc[c] = acc[c] + shfl_xor_c(acc[c], o);
     }
-    if (rg == 0 && tid < 16 * HB) {
+    if (rg == 0) {
 #pragma unroll
       for (int c = 0; c < 8; ++c) S[tt][c] = acc[c];
     }
-    __syncthreads();
+    lds_barrier();
     // S2 = T S
     for (int e = tid; e < HB * 8; e += BT_THREADS) {
       const int a = e / 8, c = e % 8;
@@ -967,27 +1153,34 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
         for (int l = a; l < kq; ++l) s2 = cfma(Tm[a][l], S[l][c], s2);
       S2[a][c] = s2;
     }
-    __syncthreads();
-    // Z[rows] -= V S2
-    for (int e = tid; e < m * ncl; e += BT_THREADS) {
-      const int r = e / ncl, c = e % ncl;
-      C s2 = czero<R>();
-      const int lmax = min(kq - 1, r);
-      for (int l = 0; l <= lmax; ++l) {
-        const C v = (r == l) ? mkc<R>(R(1), R(0)) : Vp[(size_t)l * ld + r];
-        s2 = cfma(v, S2[l][c], s2);
+    lds_barrier();
+    // Z[rows] -= V S2: one row per thread, its V row loaded once
+    for (int r = tid; r < m; r += BT_THREADS) {
+      C vr[HB];
+#pragma unroll
+      for (int l = 0; l < HB; ++l) {
+        const C vl = ld_or0<R>(Vp, (size_t)l * ld + r, l < kq && r > l);
+        vr[l] = (l < kq && r == l) ? mkc<R>(R(1), R(0)) : vl;
       }
-      C *z = Z + (size_t)(c0 + HB + r) * nc + c;
-      *z = *z - s2;
+      C *zr = Z + zidx(c0 + HB + r, 0, nc);
+#pragma unroll 1
+      for (int c = 0; c < 8; ++c) {
+        if (c < ncl) {
+          C s2 = czero<R>();
+#pragma unroll
+          for (int l = 0; l < HB; ++l) s2 = cfma(vr[l], S2[l][c], s2);
+          zr[c] = zr[c] - s2;
+        }
+      }
     }
-    __syncthreads();
+    lds_barrier();
   }
   C *Y = (C *)it.Yb;
   for (int e = tid; e < n * ncl; e += BT_THREADS) {
     const int r = e % n, c = e / n;
-    const C z = Z[(size_t)r * nc + c];
-    Y[(size_t)(cbase + c) * ld + r] = z;
-    if (sizeof(R) != sizeof(double)) it.Y[(size_t)(cbase + c) * ld + r] = ccast<double>(z);
+    const C z = Z[zidx(r, c, nc)];
+    gst(Y, (size_t)(cbase + c) * ld + r, z);
+    if (sizeof(R) != sizeof(double)) gst(it.Y, (size_t)(cbase + c) * ld + r, ccast<double>(z));
   }
 }
 
@@ -1034,7 +1227,12 @@ static hipError_t launch_reduce_t(const EigItem *items, int n_items, int n_min, 
   }
   {
     ProfScope ps(K_HB2ST, st);
-    hipLaunchKernelGGL((hb2st<R>), dim3(n_items), dim3(CH_WAVES * 64), 0, st, items);
+    const int nmax_items_xcd = (n_items + 7) / 8;
+    const int P = std::max(1, std::min(HB2ST_MAX_WG, HB2ST_CU_BUDGET / (8 * nmax_items_xcd)));
+    const int chunks = (n_max - 1 + HB - 1) / HB;
+    hipLaunchKernelGGL((hb2st_init<R>), dim3(std::max(1, chunks), n_items), dim3(256), 0, st, items);
+    hipLaunchKernelGGL((hb2st<R>), dim3(8 * nmax_items_xcd * P), dim3(CH_WAVES * 64), 0, st, items, n_items, P);
+    hipLaunchKernelGGL((hb2st_fini<R>), dim3((n_max + 255) / 256, n_items), dim3(256), 0, st, items);
   }
   return hipGetLastError();
 }
@@ -1048,7 +1246,8 @@ hipError_t launch_reduce(const EigItem *items, int n_items, int n_min, int n_max
 // budget and by one (block, column) pair of a stage-2 sweep per thread.
 int backtransform_cols(int n_max, bool fp32) {
   const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
-  const size_t cap = (size_t)BT_LDS_BYTES / (es * (size_t)n_max);
+  size_t cap = 1;
+  while (cap < 8 && zbytes(n_max, (int)cap + 1, es) <= (size_t)BT_LDS_BYTES) ++cap;
   const size_t blocks = (size_t)std::max(1, (n_max - 1 + HB - 1) / HB);
   const size_t cap2 = (size_t)BT_THREADS / blocks;
   return (int)std::min<size_t>(8, std::max<size_t>(1, std::min(cap, cap2)));
@@ -1059,20 +1258,25 @@ hipError_t launch_backtransform(const EigItem *items, int n_items, int n_max, in
   const int nc = backtransform_cols(n_max, fp32);
   const int groups = (nb + nc - 1) / nc;
   const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
-  const size_t sh = es * (size_t)n_max * nc;
-  if (fp32)
+  const size_t sh = zbytes(n_max, nc, es);
+  if (fp32) {
     hipLaunchKernelGGL((backtransform_2s<float>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
-  else
+    hipLaunchKernelGGL((backtransform_s1<float>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
+  } else {
     hipLaunchKernelGGL((backtransform_2s<double>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
+    hipLaunchKernelGGL((backtransform_s1<double>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
+  }
   return hipGetLastError();
 }
 
 hipError_t init_band_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void *)backtransform_2s<double>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, BT_LDS_BYTES);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)backtransform_2s<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             BT_LDS_BYTES);
+  const void *fs[4] = {(const void *)backtransform_2s<double>, (const void *)backtransform_2s<float>,
+                       (const void *)backtransform_s1<double>, (const void *)backtransform_s1<float>};
+  for (const void *f : fs) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, BT_LDS_BYTES);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mvpb

@@ -111,6 +111,37 @@ MVPB_DEV cx<R> block_sum_c(cx<R> v, double *red) {
   return mkc<R>((R)sr, (R)si);
 }
 
+// Global-memory accessors.  Buffers reached through a work-item table are
+// generic pointers to the compiler, which then emits flat accesses; those
+// also count against the LDS wait counter, so an LDS wait would drain every
+// global load in flight.  Accessing them through address space 1 yields
+// global loads and stores.
+#define MVPB_GAS __attribute__((address_space(1)))
+template <typename R>
+MVPB_DEV cx<R> gld(const cx<R> *p, size_t i) {
+  const MVPB_GAS cx<R> *q = (const MVPB_GAS cx<R> *)(p + i);
+  return mkc<R>(q->re, q->im);
+}
+template <typename R>
+MVPB_DEV void gst(cx<R> *p, size_t i, cx<R> v) {
+  MVPB_GAS cx<R> *q = (MVPB_GAS cx<R> *)(p + i);
+  q->re = v.re;
+  q->im = v.im;
+}
+MVPB_DEV double gld(const double *p, size_t i) { return *((const MVPB_GAS double *)(p + i)); }
+MVPB_DEV void gst(double *p, size_t i, double v) { *((MVPB_GAS double *)(p + i)) = v; }
+MVPB_DEV int gld(const int *p, size_t i) { return *((const MVPB_GAS int *)(p + i)); }
+MVPB_DEV void gst(int *p, size_t i, int v) { *((MVPB_GAS int *)(p + i)) = v; }
+
+// Workgroup barrier that orders LDS accesses only: global loads issued before
+// it stay in flight (__syncthreads also waits for every outstanding global
+// access, which defeats prefetching across the barrier).
+MVPB_DEV void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch status helper.
 // ---------------------------------------------------------------------------

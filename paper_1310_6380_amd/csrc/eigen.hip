@@ -385,9 +385,9 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
       for (int pass = 0; pass < (jm > j0 ? 2 : 1); ++pass) {
         for (int q = j0; q < jm; ++q) {
           double dot = 0.0;
-          for (int r = lane; r < n; r += 64) dot = fma(X[(size_t)r * nb + q], xv[r], dot);
+          for (int r = lane; r < n; r += 64) dot = fma(gld(X, (size_t)r * nb + q), xv[r], dot);
           dot = wave_sum(dot);
-          for (int r = lane; r < n; r += 64) xv[r] = fma(-dot, X[(size_t)r * nb + q], xv[r]);
+          for (int r = lane; r < n; r += 64) xv[r] = fma(-dot, gld(X, (size_t)r * nb + q), xv[r]);
           __syncthreads();
         }
         double amax = 0.0;
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
         __syncthreads();
       }
     }
-    for (int r = lane; r < n; r += 64) X[(size_t)r * nb + jm] = xv[r];
+    for (int r = lane; r < n; r += 64) gst(X, (size_t)r * nb + jm, xv[r]);
     __threadfence_block();
     __syncthreads();
   }
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(256) rr_product(const EigItem *__restrict__ it
   const int rows = min(64, n - r0);
   for (int e = tid; e < 64 * nb; e += 256) {
     const int rr = e % 64, b = e / 64;
-    Yr[rr * nb + b] = (rr < rows) ? Y[(size_t)b * ld + r0 + rr] : mk(0.0, 0.0);
+    Yr[rr * nb + b] = (rr < rows) ? gld(Y, (size_t)b * ld + r0 + rr) : mk(0.0, 0.0);
   }
   for (int b0 = 0; b0 < nb; b0 += RRP_BC) {
     const int bc = min(RRP_BC, nb - b0);
@@ -540,13 +540,13 @@ __global__ void __launch_bounds__(256) rr_product(const EigItem *__restrict__ it
       __syncthreads();
       for (int e = tid; e < 64 * RRP_BC; e += 256) {
         const int cc = e % 64, b = e / 64;
-        Ys[cc][b] = (c0 + cc < n && b < bc) ? Y[(size_t)(b0 + b) * ld + c0 + cc] : mk(0.0, 0.0);
+        Ys[cc][b] = (c0 + cc < n && b < bc) ? gld(Y, (size_t)(b0 + b) * ld + c0 + cc) : mk(0.0, 0.0);
       }
       __syncthreads();
       if (r < rows) {
         const int cmax = min(64, n - c0);
         for (int cc = ks; cc < cmax; cc += 4) {
-          const cd a = Cm[(size_t)(c0 + cc) * ld + r0 + r];
+          const cd a = gld(Cm, (size_t)(c0 + cc) * ld + r0 + r);
 #pragma unroll
           for (int b = 0; b < RRP_BC; ++b) acc[b] = cfma(a, Ys[cc][b], acc[b]);
         }
@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(256) rr_product(const EigItem *__restrict__ it
   cd *Z = it.Z;
   for (int e = tid; e < rows * nb; e += 256) {
     const int rr = e % rows, b = e / rows;
-    Z[(size_t)b * ld + r0 + rr] = Zr[rr * nb + b];
+    gst(Z, (size_t)b * ld + r0 + rr, Zr[rr * nb + b]);
   }
   // Gram partials of this row block: [0] Y^H Z, [1] Y^H Y
   cd *Gp = it.Gp + (size_t)rb * 2 * nb * nb;
@@ -577,8 +577,8 @@ __global__ void __launch_bounds__(256) rr_product(const EigItem *__restrict__ it
       g = cfma_cj(ya, Zr[rr * nb + b], g);
       m = cfma_cj(ya, Yr[rr * nb + b], m);
     }
-    Gp[e] = g;
-    Gp[nb * nb + e] = m;
+    gst(Gp, e, g);
+    gst(Gp, (size_t)nb * nb + e, m);
   }
 }
 
@@ -602,8 +602,8 @@ __global__ void __launch_bounds__(256) rr_small(const EigItem *__restrict__ item
     cd g = mk(0.0, 0.0), m = mk(0.0, 0.0);
     for (int q = 0; q < nrb; ++q) {
       const cd *P = it.Gp + (size_t)q * 2 * nb * nb;
-      g = g + P[e];
-      m = m + P[nb * nb + e];
+      g = g + gld(P, e);
+      m = m + gld(P, (size_t)nb * nb + e);
     }
     Gs[a][b] = g;
     Vs[a][b] = m;
@@ -709,8 +709,8 @@ __global__ void __launch_bounds__(256) rr_small(const EigItem *__restrict__ item
     const int r = (int)(e % n), b = (int)(e / n);
     const int pbb = perm[b];
     cd acc = mk(0.0, 0.0);
-    for (int a = 0; a < nb; ++a) acc = cfma(Y[(size_t)a * ld + r], Gs[a][pbb], acc);
-    Z[(size_t)b * ld + r] = acc;
+    for (int a = 0; a < nb; ++a) acc = cfma(gld(Y, (size_t)a * ld + r), Gs[a][pbb], acc);
+    gst(Z, (size_t)b * ld + r, acc);
   }
 }
 

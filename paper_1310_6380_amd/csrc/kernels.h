@@ -50,7 +50,7 @@ struct EigItem {
   void *tau2;       // (R) their scalars
   double *d;        // n diagonal
   double *e;        // n off-diagonal (real)
-  int *flag;        // nonzero: a kernel gave up waiting (diagnostic)
+  int *flag;        // n + 2: [0] a kernel gave up waiting (diagnostic), [1] abort, [2 + i] progress of sweep i
   // tridiagonal eigenproblem
   double *X;        // n x nb eigenvectors of the tridiagonal matrix (row-major)
   double *lu;       // 5 n x nb factorisation scratch (orders above the LDS limit)
