@@ -33,15 +33,88 @@ METRIC = "k-point band solves/sec at ≤1e-5 rel freq err (mixed/batched/surroga
 HBM_PEAK_GBS = 8000.0
 
 
-def hetrd_panel_bytes(n: int, panel: int = 32):
-    """Algorithmic HBM bytes of each launch of the panel kernel for one item of
-    order n: every column j of the panel multiplies the full trailing matrix
-    (order n-j-1, complex FP64) by a vector once."""
-    out = []
-    for p in range(0, n - 1, panel):
-        nbp = min(panel, n - 1 - p)
-        out.append(sum(16.0 * (n - j - 1) ** 2 for j in range(p, p + nbp)))
+HB = 16                 # band width of the two-stage reduction
+FP64_PEAK_TFLOPS = 78.6  # vector FP64 (fp64 matrix cores have the same rate)
+CMAC = 8.0               # real flops of one complex multiply-add
+
+
+def _trailing(n: int):
+    """(m, kq) of every stage-1 panel step of an item of order n: the trailing
+    matrix after the panel has order m, the panel has kq = min(HB, m) reflectors."""
+    out, c0 = [], 0
+    while n - c0 - HB > 0:
+        m = n - c0 - HB
+        out.append((m, min(HB, m)))
+        c0 += HB
     return out
+
+
+def hb2st_flops(n: int) -> float:
+    """Algorithmic flops of the bulge chasing of one item: per block of L rows,
+    the right application of the previous reflector and the left application of
+    the new one to the L x HB block below the band (2 L HB + 2 L (HB-1) complex
+    MACs, none for the first block of a sweep), the Hermitian product D v and the
+    rank-2 update of the block's lower triangle (L^2 + L (L+1))."""
+    tot = 0
+    for i in range(n - 1):
+        s, k = i + 1, 0
+        while s <= n - 1:
+            L = min(HB, n - s)
+            c = L * L + L * (L + 1) + L
+            if k > 0:
+                c += 2 * L * HB + 2 * L * (HB - 1)
+            tot += c
+            s += HB
+            k += 1
+    return CMAC * tot
+
+
+def backtransform_flops(n: int, nb: int) -> float:
+    """Applying every reflector of both stages to nb eigenvector columns:
+    H z = z - tau v (v^H z) costs two complex MACs per reflector entry and column."""
+    t = n - 1
+    q, r = divmod(t, HB)
+    n_refl = HB * q * (q + 1) // 2 + r * (q + 1)
+    s2 = 2 * HB * n_refl * nb
+    s1 = sum(2 * m * kq * nb + kq * kq * nb for m, kq in _trailing(n))
+    return CMAC * (s2 + s1)
+
+
+# Roofline models of the kernels that can dominate a step: (bound, unit, peak,
+# algorithmic amount of one item of order n).  Bytes are complex FP64 entries
+# moved once: the Hermitian trailing matrix is stored by its lower triangle.
+def roofline_models(n: int, nb: int):
+    tr = _trailing(n)
+    return {
+        "hb2st": ("alu", "TFLOP/s", FP64_PEAK_TFLOPS, hb2st_flops(n)),
+        "he2hb_her2k": ("hbm", "GB/s", HBM_PEAK_GBS,
+                        sum(16.0 * m * (m + 1) + 2 * 16.0 * m * kq for m, kq in tr)),
+        "he2hb_hemm": ("hbm", "GB/s", HBM_PEAK_GBS,
+                       sum(8.0 * m * (m + 1) + 2 * 16.0 * m * kq for m, kq in tr)),
+        "he2hb_panel": ("hbm", "GB/s", HBM_PEAK_GBS, sum(2 * 16.0 * m * HB for m, kq in tr)),
+        "backtransform": ("alu", "TFLOP/s", FP64_PEAK_TFLOPS, backtransform_flops(n, nb)),
+    }
+
+
+def measured_traffic(kernel: str):
+    """Calibrated HBM bytes per launch of `kernel` from the committed counter
+    summary of this workload, or None when it is missing or was taken on other
+    sources."""
+    path = os.path.join(HERE, "profiles", "hbm_traffic_voronoi1132_fp64.md")
+    if not os.path.exists(path):
+        return None
+    digest, row = None, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("source digest:"):
+                digest = line.split(":", 1)[1].strip()
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 5 and cells[0] == kernel:
+                row = cells
+    from paper_1310_6380_amd.profile_summary import source_digest
+    if digest != source_digest() or row is None:
+        return None
+    return float(row[4])
 
 
 def cpu_baseline(cell, M, Q, nb, omega_gpu, n_sample):
@@ -200,6 +273,23 @@ def variant_precision(mvpb, ctx):
     return res, oms, cfg
 
 
+def copy_calibration(mib: int):
+    """One copy of a known byte count by the library's copy16 kernel, so that
+    hardware traffic counters can be scaled to bytes."""
+    from paper_1310_6380_amd import mvpb
+    nbytes = mib << 20
+    ctx = mvpb.Context(0)
+    src, dst = mvpb.DeviceBuffer(nbytes), mvpb.DeviceBuffer(nbytes)
+    src.upload(np.arange(nbytes // 8, dtype=np.int64))
+    t0 = time.perf_counter()
+    ctx.copy_device(dst.value, src.value, nbytes)
+    dt = time.perf_counter() - t0
+    ok = bool(np.array_equal(dst.to_numpy(np.int64, (nbytes // 8,))[-4:], np.arange(nbytes // 8 - 4, nbytes // 8)))
+    print(json.dumps({"copy_bytes": nbytes, "read_bytes": nbytes, "write_bytes": nbytes, "seconds": dt,
+                      "tail_ok": ok}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,7 +297,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=6, help="k-points timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-variants", action="store_true", help="only the headline FP64 workload")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB once with the library's plain copy kernel (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note",
               file=sys.stderr)
@@ -245,22 +340,23 @@ def main():
     ms_step = 1e3 * dt / args.steps
     value = Q.shape[0] * args.steps / dt
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel: algorithmic work per launch over the
+    # kernel's average launch time (HIP events on the context stream)
     dom = max(prof.items(), key=lambda kv: kv[1][0])
     name, (tot_ms, launches) = dom
-    roof = None
-    if name == "hetrd_panel" and launches:
-        per_item = hetrd_panel_bytes(n)
-        bytes_total = Q.shape[0] * sum(per_item) * args.steps
+    models = roofline_models(n, nb)
+    roof = {"kernel": name, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None, "avg_launch_ms": tot_ms / max(launches, 1), "launches": launches}
+    if name in models and launches:
+        bound, unit, peak, per_item = models[name]
+        per_launch = per_item * Q.shape[0] * args.steps / launches
         avg_s = tot_ms / launches / 1e3
-        achieved = bytes_total / launches / avg_s / 1e9
-        roof = {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "avg_launch_ms": tot_ms / launches, "launches": launches}
-    else:
-        roof = {"kernel": name, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None, "avg_launch_ms": tot_ms / max(launches, 1), "launches": launches}
-
+        scale = 1e9 if unit == "GB/s" else 1e12
+        achieved = per_launch / avg_s / scale
+        roof.update({"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+                     "algorithmic_per_launch": per_launch,
+                     "algorithmic_unit": "bytes" if unit == "GB/s" else "flops",
+                     "traffic": measured_traffic(name)})
     omega = om_dev.to_numpy(np.float64, (Q.shape[0], nb))
     variants = {}
     om_mixed = om_batch = cfg2 = om_prec = cfg3 = None

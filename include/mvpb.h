@@ -129,7 +129,9 @@ int mvpb_plan_destroy(mvpb_plan plan);
  *   normalised to U^H Omega U = 1 with the largest-modulus entry real > 0.
  * 1 <= n_bands <= 2N.  Q, omega and U are host pointers unless
  * MVPB_F_DEVICE_PTRS is set (then omega and U are device pointers; Q stays
- * on the host). */
+ * on the host).  If the device could not finish a point (the reduction to
+ * tridiagonal form gave up waiting on a hand-over), its frequencies are NaN;
+ * with host pointers the call then returns MVPB_E_DEVICE. */
 int mvpb_solve(mvpb_plan plan, int n_k, const double *Q, int n_bands, double *omega, double *U,
                unsigned flags);
 
@@ -154,6 +156,13 @@ int mvpb_structure_factors(mvpb_cell cell, int M1, int M2, int precision, double
  * (the boundary of the irreducible zone of a square lattice), both ends
  * Gamma.  Q: host pointer, 2*n_k doubles. */
 int mvpb_kpath_square(int n_k, double *Q);
+
+/* Plain device-to-device copy of `bytes` bytes (a multiple of 16, buffers
+ * 16-byte aligned and not overlapping) by one kernel (copy16) on the context
+ * stream; returns when it has finished.  It reads and writes each byte once,
+ * which makes it the reference for calibrating hardware traffic counters
+ * against a known byte count. */
+int mvpb_copy_device(mvpb_ctx ctx, void *dst, const void *src, size_t bytes);
 
 /* ---------------------------------------------------------------------------
  * Learned screening surrogate (not part of the paper's method).  A small
@@ -188,13 +197,14 @@ int mvpb_sur_train_step(mvpb_sur net, int batch, const uint8_t *cells, const flo
  * time accumulated per kernel family.  Kernel ids: 0 structure_factors,
  * 1 toeplitz_scatter, 2 potrf_trtri, 3 zgemm, 4 combine_coefficients,
  * 5 form_operator, 6 he2hb_panel, 7 he2hb_hemm, 8 he2hb_wform,
- * 9 he2hb_her2k, 10 hb2st, 11 tridiag_eig, 12 backtransform,
- * 13 rayleigh_ritz (MVPB_N_KERNELS in total).  Launches
+ * 9 he2hb_her2k, 10 hb2st (the bulge chasing itself), 11 tridiag_eig,
+ * 12 backtransform, 13 rayleigh_ritz, 14 hb2st_copy (band copy in and
+ * tridiagonal out around hb2st) (MVPB_N_KERNELS in total).  Launches
  * inside the HIP graph of mvpb_solve_batch are not timed.
  * mvpb_ctx_profile(ctx, 1) clears the totals and starts timing, 0 stops.
  * mvpb_ctx_profile_read waits for the recorded events and returns the total
  * milliseconds, the number of launches and a static name string. */
-#define MVPB_N_KERNELS 14
+#define MVPB_N_KERNELS 15
 int mvpb_ctx_profile(mvpb_ctx ctx, int enable);
 int mvpb_ctx_profile_read(mvpb_ctx ctx, int kernel, double *total_ms, long long *launches, const char **name);
 

@@ -666,11 +666,15 @@ __global__ void normalize_phase(cd *U, int len, int count) {
   for (int r = threadIdx.x; r < len; r += blockDim.x) u[r] = u[r] * ph;
 }
 
+// Frequencies of every item to its row of the caller's output; an item whose
+// bulge chasing gave up gets NaN.
 __global__ void gather_omega(const EigItem *items, int n_items, int nb, double *out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_items * nb) return;
   const int i = t / nb, b = t % nb;
-  out[t] = items[i].omega[b];
+  const EigItem &it = items[i];
+  const double v = __hip_atomic_load(it.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? NAN : it.omega[b];
+  out[(size_t)it.slot * nb + b] = v;
 }
 
 // One batch of work items that share a workspace allocation.
@@ -719,6 +723,7 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     it.coef = j.plan->coef.as<cd>();
     it.N = j.plan->N;
     it.nb = nb;
+    it.slot = j.out_index;
     const double *T = j.plan->T;
     it.kap1 = 2.0 * M_PI * (T[0] * j.Q1 + T[1] * j.Q2);
     it.kap2 = 2.0 * M_PI * (T[2] * j.Q1 + T[3] * j.Q2);
@@ -759,16 +764,10 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   } else {
     HIP_TRY(enqueue());
   }
-  // gather frequencies in job order
-  HIP_TRY(ctx->scratch.reserve(sizeof(double) * (size_t)n_items * nb));
+  // frequencies to the caller's order (jobs may be sorted)
   hipLaunchKernelGGL(gather_omega, dim3((n_items * nb + 255) / 256), dim3(256), 0, st, d_items, n_items, nb,
-                     ctx->scratch.as<double>());
+                     omega_dev);
   HIP_TRY(hipGetLastError());
-  // scatter to caller order (jobs may be sorted)
-  for (int i = 0; i < n_items; ++i) {
-    HIP_TRY(hipMemcpyAsync(omega_dev + (size_t)jobs[i].out_index * nb, ctx->scratch.as<double>() + (size_t)i * nb,
-                           sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
-  }
   if (U_dev) {
     // U_t = [L_R^-H Z_t(0:N, :); L_R^-H Z_t(N:2N, :)], written in caller order
     std::vector<const void *> hp;
@@ -799,6 +798,19 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     }
     HIP_TRY(hipStreamSynchronize(st));
   }
+  return MVPB_OK;
+}
+
+// Host-side check of returned frequencies: NaN marks an item whose bulge
+// chasing gave up (a hand-over that never came, or a workgroup placement the
+// hand-over does not support).
+static int check_failed_items(const double *om, size_t count, int nb) {
+  size_t bad = 0;
+  for (size_t i = 0; i < count; ++i)
+    if (isnan(om[i])) ++bad;
+  if (bad)
+    return set_err(MVPB_E_DEVICE, "the reduction to tridiagonal form gave up on %zu k-point(s)",
+                   (bad + nb - 1) / nb);
   return MVPB_OK;
 }
 
@@ -852,6 +864,7 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
     if (U)
       HIP_TRY(hipMemcpyAsync(U, u_out, sizeof(double) * 2 * (size_t)n_k * n_bands * n, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return check_failed_items(omega, (size_t)n_k * n_bands, n_bands);
   } else if (!(flags & MVPB_F_ASYNC)) {
     HIP_TRY(hipStreamSynchronize(st));
   }
@@ -928,6 +941,32 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
                            dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
   }
   if (!dev || !(flags & MVPB_F_ASYNC)) HIP_TRY(hipStreamSynchronize(st));
+  if (!dev)
+    for (int i = 0; i < n_plans; ++i) {
+      rc = check_failed_items(omega[i], (size_t)n_k[i] * n_bands, n_bands);
+      if (rc) return rc;
+    }
+  return MVPB_OK;
+}
+
+__global__ void __launch_bounds__(256) copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) dst[e] = src[e];
+}
+
+extern "C" int mvpb_copy_device(mvpb_ctx ctx, void *dst, const void *src, size_t bytes) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
+    return set_err(MVPB_E_INVALID, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+  const char *d = (const char *)dst, *s = (const char *)src;
+  if (d < s + bytes && s < d + bytes) return set_err(MVPB_E_INVALID, "copy buffers overlap");
+  if (bytes == 0) return MVPB_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const size_t n = bytes / 16;
+  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(copy16, dim3(grid), dim3(256), 0, ctx->stream, (uint4 *)dst, (const uint4 *)src, n);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
   return MVPB_OK;
 }
 
@@ -961,7 +1000,7 @@ extern "C" int mvpb_kpath_square(int n_k, double *Q) {
 static const char *k_names[K_COUNT] = {"structure_factors", "toeplitz_scatter", "potrf_trtri", "zgemm",
                                        "combine_coefficients", "form_operator", "he2hb_panel", "he2hb_hemm",
                                        "he2hb_wform", "he2hb_her2k", "hb2st", "tridiag_eig", "backtransform",
-                                       "rayleigh_ritz"};
+                                       "rayleigh_ritz", "hb2st_copy"};
 
 extern "C" int mvpb_ctx_profile(mvpb_ctx ctx, int enable) {
   int rc = check_ctx(ctx);

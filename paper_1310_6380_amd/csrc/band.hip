@@ -19,8 +19,10 @@
 //    first), then the stage-1 block reflectors (last panel first), applied
 //    to the eigenvectors of the tridiagonal matrix held in LDS.
 #include <float.h>
+#include <stdlib.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 #include "kernels.h"
@@ -683,6 +685,10 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
 // block k >= 1 right-applies the previous reflector to A[J_k, J_{k-1}],
 // annihilates its first column and left-applies to the rest; every block
 // ends with the two-sided update of A[J_k, J_k].
+// Only the lower band is stored, so block k of sweep i reads and writes rows
+// J_k(i) alone; of sweep i-1 only blocks k and k+1 touch those rows.  Block k
+// of sweep i therefore starts once sweep i-1 has finished its blocks 0 .. k+1,
+// and consecutive sweeps run two blocks apart.
 // A lane of a wavefront holds row q = lane % 16 and columns 4 g .. 4 g + 3
 // (g = lane / 16) of a 16 x 16 block.
 // ---------------------------------------------------------------------------
@@ -750,7 +756,7 @@ MVPB_DEV cx<R> row16_sum_c(cx<R> v) {
 }
 
 static_assert(HB == 16, "the lane layout of the bulge-chasing kernel assumes HB = 16");
-constexpr int CH_WAVES = 16;
+constexpr int CH_WAVES = 8;
 constexpr long long CH_SPIN_LIMIT = 1ll << 24;
 // workgroups per item of the bulge chasing, and the CUs that may be used
 // (one 1024-thread workgroup per CU keeps every workgroup resident)
@@ -793,15 +799,34 @@ __global__ void __launch_bounds__(256) hb2st_fini(const EigItem *__restrict__ it
   }
 }
 
+// XCD (accelerator complex die) the calling workgroup runs on: the XCC_ID
+// hardware register, bits 3:0.
+MVPB_DEV int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & 0xF; }
+
+// One entry per workgroup: the XCD it ran on.
+__global__ void __launch_bounds__(64) xcd_probe(int *out, int n) {
+  if (threadIdx.x == 0 && (int)blockIdx.x < n) gst(out, blockIdx.x, xcc_id());
+}
+
 // Workgroup layout of the bulge chasing: P workgroups per item, all on the
 // XCD (L2) of the item: workgroup L of the 1-D grid runs on XCD L % 8, and
 // item j is given the slots s = (j / 8) P .. (j / 8) P + P - 1 of XCD j % 8.
-// Sweep i belongs to workgroup (i / 16) % P, wavefront i % 16.  Sweeps hand
-// over within a workgroup through LDS counters and between workgroups
-// through counters in the shared L2 (the consumer invalidates its L1 before
-// reading the producer's blocks).
+// Sweeps are dealt out in groups of G consecutive ones: sweep i belongs to
+// workgroup (i / G) % P, wavefront ((i / (G P)) G + i % G) % CH_WAVES.  The
+// sweeps in flight (about n / (2 HB) of them) then span several CUs; a
+// hand-over between CUs costs more than two wavefronts sharing a SIMD, so
+// G = CH_WAVES is the default.  Sweeps hand over within a
+// workgroup through LDS counters and between workgroups through counters in
+// the shared L2: the consumer invalidates its L1 before reading the
+// producer's blocks.  With same_l2 set (the device was found to place
+// workgroup L on XCD L % 8, and every workgroup checks that it did) producer
+// and consumer share one L2, and the producer only waits until its stores
+// are acknowledged (the L1 writes through to the L2) before it bumps the
+// counter; otherwise the counter is released at agent scope, which also
+// writes the L2 back to memory.
 template <typename R>
-__global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict__ items, int n_items, int P) {
+__global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict__ items, int n_items, int P, int G,
+                                                      int same_l2) {
   typedef cx<R> C;
   __shared__ int prog[CH_WAVES];
   __shared__ int abort_s;
@@ -809,6 +834,14 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
   const int item = (slot / P) * 8 + xcd, a = slot % P;
   if (item >= n_items) return;
   const EigItem it = items[item];
+  if (same_l2 && P > 1 && xcc_id() != xcd) {
+    // placement differs from the one the hand-over relies on: fail the item
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(it.flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(it.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
   const int n = 2 * it.N;
   C *__restrict__ WB = (C *)it.WB;
   C *__restrict__ V2 = (C *)it.V2;
@@ -820,21 +853,24 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
   __syncthreads();
   const int w = tid >> 6, lane = tid & 63, q = lane & 15, g = lane >> 4;
   bool aborted = false;
-  for (int i0 = CH_WAVES * a; i0 < n - 1 && !aborted; i0 += CH_WAVES * P) {
-    const int i = i0 + w;
-    if (i >= n - 1) break;
+  const int R_ = CH_WAVES / G, gp = G * P;
+  // the wavefront that runs sweep j of this workgroup's share
+  auto wave_of = [&](int j) { return ((j / gp) % R_) * G + j % G; };
+  const bool report = (w % G == G - 1) && P > 1;   // sweep i+1 is in another workgroup
+  for (int i = gp * (w / G) + G * a + w % G; i < n - 1 && !aborted; i += CH_WAVES * P) {
     const int nsteps = (n - 1 - i + HB - 1) / HB;
     const int nprev = (n - i + HB - 1) / HB;   // blocks of sweep i-1
     const long long roff = refl_count(n - 1) - refl_count(n - 1 - i);
-    const bool cross = (w == 0) && (P > 1) && (i > 0);   // sweep i-1 is in another workgroup
+    const bool cross = (w % G == 0) && (P > 1) && (i > 0);   // sweep i-1 is in another workgroup
+    const int wprev = wave_of(i - 1);
     C vprev = czero<R>(), tauprev = czero<R>();
     for (int k = 0; k < nsteps; ++k) {
       if (i > 0) {
-        const int nd = min(k + 3, nprev);
+        const int nd = min(k + 2, nprev);
         long long spins = 0;
         if (!cross) {
           const int need = (i - 1) * 1024 + nd;
-          while (__hip_atomic_load(&prog[(i - 1) % CH_WAVES], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+          while (__hip_atomic_load(&prog[wprev], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
             if (__hip_atomic_load(&abort_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
               aborted = true;
               break;
@@ -979,9 +1015,16 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
       __threadfence_block();
       if (lane == 0) {
         __hip_atomic_store(&prog[w], i * 1024 + k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        // the last sweep of a group of 16 also reports to the next workgroup
-        if (w == CH_WAVES - 1 && P > 1)
-          __hip_atomic_store(gflag + 2 + i, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the last sweep of a group also reports to the next workgroup
+        if (report) {
+          if (same_l2) {
+            // every store of this wavefront acknowledged by the shared L2
+            __builtin_amdgcn_s_waitcnt(0);
+            __hip_atomic_store(gflag + 2 + i, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            __hip_atomic_store(gflag + 2 + i, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
       }
       // the reflector for the back-transform (after the release: not waited for)
       if (g == 0) {
@@ -1198,6 +1241,21 @@ static void launch_panel_class(const EigItem *items, int n_items, int p, int m_l
   hipLaunchKernelGGL((he2hb_panel<R, RPT>), dim3(n_items), dim3(PQ_THREADS), 0, st, items, p);
 }
 
+// Per device: 1 if workgroup L of a 1-D grid was seen to run on XCD L % 8.
+constexpr int MAX_DEVICES = 64;
+static int g_xcd_round_robin[MAX_DEVICES];
+
+// Sweeps per group of the bulge-chasing layout (a divisor of CH_WAVES);
+// MVPB_HB2ST_GROUP overrides it for tuning.
+static int hb2st_group() {
+  static const int g = [] {
+    const char *e = getenv("MVPB_HB2ST_GROUP");
+    const int v = e ? atoi(e) : 0;
+    return (v >= 1 && v <= CH_WAVES && CH_WAVES % v == 0) ? v : CH_WAVES;
+  }();
+  return g;
+}
+
 template <typename R>
 static hipError_t launch_reduce_t(const EigItem *items, int n_items, int n_min, int n_max, hipStream_t st) {
   for (int p = 0;; ++p) {
@@ -1226,13 +1284,25 @@ static hipError_t launch_reduce_t(const EigItem *items, int n_items, int n_min, 
     }
   }
   {
-    ProfScope ps(K_HB2ST, st);
     const int nmax_items_xcd = (n_items + 7) / 8;
     const int P = std::max(1, std::min(HB2ST_MAX_WG, HB2ST_CU_BUDGET / (8 * nmax_items_xcd)));
     const int chunks = (n_max - 1 + HB - 1) / HB;
-    hipLaunchKernelGGL((hb2st_init<R>), dim3(std::max(1, chunks), n_items), dim3(256), 0, st, items);
-    hipLaunchKernelGGL((hb2st<R>), dim3(8 * nmax_items_xcd * P), dim3(CH_WAVES * 64), 0, st, items, n_items, P);
-    hipLaunchKernelGGL((hb2st_fini<R>), dim3((n_max + 255) / 256, n_items), dim3(256), 0, st, items);
+    {
+      ProfScope ps(K_HB2ST_IO, st);
+      hipLaunchKernelGGL((hb2st_init<R>), dim3(std::max(1, chunks), n_items), dim3(256), 0, st, items);
+    }
+    {
+      ProfScope ps(K_HB2ST, st);
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      const int same_l2 = (dev >= 0 && dev < MAX_DEVICES) ? g_xcd_round_robin[dev] : 0;
+      hipLaunchKernelGGL((hb2st<R>), dim3(8 * nmax_items_xcd * P), dim3(CH_WAVES * 64), 0, st, items, n_items, P,
+                         hb2st_group(), same_l2);
+    }
+    {
+      ProfScope ps(K_HB2ST_IO, st);
+      hipLaunchKernelGGL((hb2st_fini<R>), dim3((n_max + 255) / 256, n_items), dim3(256), 0, st, items);
+    }
   }
   return hipGetLastError();
 }
@@ -1269,6 +1339,33 @@ hipError_t launch_backtransform(const EigItem *items, int n_items, int n_max, in
   return hipGetLastError();
 }
 
+// Record whether the current device deals workgroups to its 8 XCDs round
+// robin (the layout the bulge chasing's fast hand-over assumes).
+static hipError_t probe_xcd_layout() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipSuccess;
+  g_xcd_round_robin[dev] = 0;
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return e;
+  const int n = 16 * prop.multiProcessorCount;
+  int *d = nullptr;
+  e = hipMalloc(&d, sizeof(int) * n);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(xcd_probe, dim3(n), dim3(64), 0, 0, d, n);
+  std::vector<int> h(n, -1);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(h.data(), d, sizeof(int) * n, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return e;
+  bool rr = true;
+  for (int i = 0; i < n; ++i) rr = rr && h[i] == i % 8;
+  g_xcd_round_robin[dev] = rr ? 1 : 0;
+  return hipSuccess;
+}
+
 hipError_t init_band_attributes() {
   const void *fs[4] = {(const void *)backtransform_2s<double>, (const void *)backtransform_2s<float>,
                        (const void *)backtransform_s1<double>, (const void *)backtransform_s1<float>};
@@ -1276,7 +1373,7 @@ hipError_t init_band_attributes() {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, BT_LDS_BYTES);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return probe_xcd_layout();
 }
 
 }  // namespace mvpb

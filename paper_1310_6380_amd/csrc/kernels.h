@@ -37,6 +37,7 @@ struct EigItem {
   double kap1, kap2;
   int N;            // plane waves; the operator has order n = 2N
   int nb;           // bands wanted
+  int slot;         // row of this item's frequencies in the output
   // stage 1: dense -> band
   void *A;          // (R) n x n working matrix; the panels' reflectors stay below the band
   cd *Ak;           // n x n kept copy of C(k) for Rayleigh-Ritz (always FP64)
@@ -50,7 +51,8 @@ struct EigItem {
   void *tau2;       // (R) their scalars
   double *d;        // n diagonal
   double *e;        // n off-diagonal (real)
-  int *flag;        // n + 2: [0] a kernel gave up waiting (diagnostic), [1] abort, [2 + i] progress of sweep i
+  int *flag;        // n + 2: [0] nonzero if the bulge chasing gave up (its frequencies are then NaN),
+                    // [1] abort, [2 + i] progress of sweep i
   // tridiagonal eigenproblem
   double *X;        // n x nb eigenvectors of the tridiagonal matrix (row-major)
   double *lu;       // 5 n x nb factorisation scratch (orders above the LDS limit)

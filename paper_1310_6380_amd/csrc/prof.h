@@ -22,6 +22,7 @@ enum KernelId {
   K_TRIDIAG,
   K_BACKTRANSFORM,
   K_RR,
+  K_HB2ST_IO,
   K_COUNT
 };
 

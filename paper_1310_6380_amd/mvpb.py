@@ -45,9 +45,9 @@ EXPORTS = [
     "mvpb_plan_destroy", "mvpb_solve", "mvpb_solve_batch", "mvpb_structure_factors",
     "mvpb_kpath_square", "mvpb_ctx_profile", "mvpb_ctx_profile_read", "mvpb_plan_create_batch",
     "mvpb_sur_create", "mvpb_sur_destroy", "mvpb_sur_n_params", "mvpb_sur_get_params", "mvpb_sur_set_params",
-    "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step",
+    "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step", "mvpb_copy_device",
 ]
-N_KERNELS = 14
+N_KERNELS = 15
 
 
 class MvpbError(RuntimeError):
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
     lib.mvpb_sur_infer.argtypes = [P, I, P, P, ctypes.c_uint]
     lib.mvpb_sur_gradients.argtypes = [P, I, P, P, F, P, ctypes.c_uint]
     lib.mvpb_sur_train_step.argtypes = [P, I, P, P, ctypes.c_float, F, ctypes.c_uint]
+    lib.mvpb_copy_device.argtypes = [P, P, P, ctypes.c_size_t]
     lib.mvpb_ctx_profile.argtypes = [P, I]
     lib.mvpb_ctx_profile_read.argtypes = [P, I, D, ctypes.POINTER(ctypes.c_longlong),
                                           ctypes.POINTER(ctypes.c_char_p)]
@@ -225,6 +226,10 @@ class Context:
             _check(load().mvpb_ctx_profile_read(self.h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(nm)))
             out[nm.value.decode()] = (ms.value, n.value)
         return out
+
+    def copy_device(self, dst: int, src: int, nbytes: int):
+        """Plain device-to-device copy by the library's copy16 kernel (waits for it)."""
+        _check(load().mvpb_copy_device(self.h, ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes))
 
     def cell(self, phase, props, lattice=None):
         return Cell(self, phase, props, lattice)
