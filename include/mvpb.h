@@ -206,6 +206,10 @@ int mvpb_sur_train_step(mvpb_sur net, int batch, const uint8_t *cells, const flo
  * milliseconds, the number of launches and a static name string. */
 #define MVPB_N_KERNELS 15
 int mvpb_ctx_profile(mvpb_ctx ctx, int enable);
+/* As mvpb_ctx_profile(ctx, 1), but only the kernels whose bit (1 << id) is
+ * set in mask are bracketed by events (mask 0 stops timing), so that timing
+ * one kernel family barely disturbs the rest. */
+int mvpb_ctx_profile_mask(mvpb_ctx ctx, unsigned long long mask);
 int mvpb_ctx_profile_read(mvpb_ctx ctx, int kernel, double *total_ms, long long *launches, const char **name);
 
 #ifdef __cplusplus

@@ -44,21 +44,82 @@ static int set_err(int code, const char *fmt, ...) {
                      __LINE__);                                                              \
   } while (0)
 
-// Device buffer owned by a host object.
+// Stream-ordered cache of device allocations, one per context.  Every use of
+// a context's memory is ordered on the context stream, so a block given back
+// by the host may be handed out again at once: the later work that reuses it
+// runs after the earlier work that used it.  hipFree (which waits for the
+// whole device) only runs when the context goes or an allocation fails.
+struct Pool {
+  std::multimap<size_t, void *> idle;   // size -> block
+  std::map<void *, size_t> size_of;     // every block this pool owns
+  ~Pool() { trim(); }
+  static size_t round(size_t b) {
+    const size_t g = b >= ((size_t)1 << 20) ? ((size_t)1 << 16) : 256;
+    return (b + g - 1) / g * g;
+  }
+  hipError_t get(size_t b, void **out) {
+    b = round(b);
+    // an idle block of at least b and at most 2 b (or 1 MB for small requests)
+    auto it = idle.lower_bound(b);
+    if (it != idle.end() && it->first <= std::max(2 * b, (size_t)1 << 20)) {
+      *out = it->second;
+      idle.erase(it);
+      return hipSuccess;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      e = hipMalloc(&p, b);
+      if (e != hipSuccess) return e;
+    }
+    size_of[p] = b;
+    *out = p;
+    return hipSuccess;
+  }
+  void put(void *p) {
+    auto it = size_of.find(p);
+    if (it != size_of.end()) idle.emplace(it->second, p);
+  }
+  void trim() {
+    for (auto &kv : idle) {
+      (void)hipFree(kv.second);
+      size_of.erase(kv.second);
+    }
+    idle.clear();
+  }
+};
+
+// Device buffer owned by a host object; from the context's pool when one is
+// given, else straight from hipMalloc.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  Pool *pool = nullptr;
+  DevBuf() = default;
+  explicit DevBuf(Pool *pl) : pool(pl) {}
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (pool)
+        pool->put(p);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
   }
   hipError_t alloc(size_t b) {
     release();
     if (b == 0) return hipSuccess;
-    hipError_t e = hipMalloc(&p, b);
-    if (e == hipSuccess) bytes = b;
+    hipError_t e = pool ? pool->get(b, &p) : hipMalloc(&p, b);
+    if (e == hipSuccess)
+      bytes = b;
+    else
+      p = nullptr;
     return e;
   }
   // grow-only
@@ -75,9 +136,10 @@ struct mvpb_ctx_s {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   size_t cap = 0;
-  DevBuf ws;          // per-solve workspace (grow-only)
-  DevBuf items;       // item table
-  DevBuf scratch;     // small host-visible results staging
+  Pool pool;          // declared before every buffer that returns to it
+  DevBuf ws{&pool};      // per-solve workspace (grow-only)
+  DevBuf items{&pool};   // item table
+  DevBuf scratch{&pool}; // small host-visible results staging
   std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences by batch signature
   std::vector<EigItem> host_items;                // staging of the item table (kept alive for async copies)
   Profiler prof;
@@ -93,6 +155,7 @@ static void ctx_free(mvpb_ctx c) {
   c->ws.release();
   c->items.release();
   c->scratch.release();
+  c->pool.trim();
   c->prof.reset();
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -249,6 +312,8 @@ extern "C" int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], in
   c->nx = nx;
   c->ny = ny;
   c->n_phases = n_phases;
+  c->phase.pool = &ctx->pool;
+  c->wtab.pool = &ctx->pool;
   hipError_t e = c->phase.alloc(sizeof(int32_t) * nx * ny);
   if (e == hipSuccess) e = c->wtab.alloc(sizeof(double) * w.size());
   if (e == hipSuccess)
@@ -318,7 +383,7 @@ extern "C" int mvpb_structure_factors(mvpb_cell c, int M1, int M2, int precision
   if (rc) return rc;
   HIP_TRY(hipSetDevice(c->ctx->device));
   ProfBind pb(c->ctx);
-  DevBuf X, Fd;
+  DevBuf X(&c->ctx->pool), Fd(&c->ctx->pool);
   rc = run_structure_factors(c, M1, M2, precision, X, Fd);
   if (rc) return rc;
   const size_t cnt = 4 * (size_t)(4 * M1 + 1) * (4 * M2 + 1);
@@ -342,7 +407,8 @@ static int build_plan_group(mvpb_ctx ctx, const mvpb_cell *cells, int g, int M1,
   const int nm = 4 * M1 + 1, nq = 4 * M2 + 1;
   const size_t fsz = (size_t)4 * nm * nq;
 
-  DevBuf X, F1, F, mats, linv, stat, ptrs, gvec, P, Xp;
+  Pool *pool = &ctx->pool;
+  DevBuf X(pool), F1(pool), F(pool), mats(pool), linv(pool), stat(pool), ptrs(pool), gvec(pool), P(pool), Xp(pool);
   HIP_TRY(F.alloc(sizeof(cd) * fsz * g));
   HIP_TRY(mats.alloc(sizeof(cd) * 3 * NN * g));
   HIP_TRY(linv.alloc(sizeof(cd) * 3 * NN * g));
@@ -445,6 +511,8 @@ static int build_plan_group(mvpb_ctx ctx, const mvpb_cell *cells, int g, int M1,
     pl->prec = precision;
     memcpy(pl->T, cells[c]->T, sizeof pl->T);
     pl->area = cells[c]->area;
+    pl->coef.pool = &ctx->pool;
+    pl->linvR.pool = &ctx->pool;
     made.push_back(pl);
     e = pl->coef.alloc(sizeof(cd) * 15 * NN);
     if (e == hipSuccess) e = pl->linvR.alloc(sizeof(cd) * NN);
@@ -452,8 +520,8 @@ static int build_plan_group(mvpb_ctx ctx, const mvpb_cell *cells, int g, int M1,
     if (e == hipSuccess)
       e = hipMemcpyAsync(pl->linvR.p, Li + (3 * c + 2) * NN, sizeof(cd) * NN, hipMemcpyDeviceToDevice, st);
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
     for (mvpb_plan pl : made) delete pl;
     return set_err(MVPB_E_NOMEM, "plan build: %s", hipGetErrorString(e));
   }
@@ -542,8 +610,7 @@ extern "C" int mvpb_plan_destroy(mvpb_plan p) {
   if (!p) return MVPB_OK;
   mvpb_ctx ctx = p->ctx;
   (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->stream);
-  delete p;
+  delete p;   // its buffers return to the stream-ordered pool
   ctx_release(ctx);
   return MVPB_OK;
 }
@@ -779,7 +846,7 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     for (int i = 0; i < n_items; ++i) hp.push_back(U_dev + (size_t)jobs[i].out_index * nb * 2 * jobs[i].plan->N * 2);
     for (int i = 0; i < n_items; ++i)
       hp.push_back(U_dev + ((size_t)jobs[i].out_index * nb * 2 * jobs[i].plan->N + jobs[i].plan->N) * 2);
-    DevBuf ptrs;
+    DevBuf ptrs(&ctx->pool);
     HIP_TRY(ptrs.alloc(sizeof(void *) * hp.size()));
     HIP_TRY(hipMemcpyAsync(ptrs.p, hp.data(), sizeof(void *) * hp.size(), hipMemcpyHostToDevice, st));
     void **dp = ptrs.as<void *>();
@@ -840,7 +907,7 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
   const size_t budget = ctx->cap ? ctx->cap : (size_t)32 << 30;
   if (per > budget) return set_err(MVPB_E_NOMEM, "one item needs %zu bytes, cap is %zu", per, budget);
   chunk = (int)std::min<size_t>((size_t)n_k, budget / per);
-  DevBuf om_dev, u_dev;
+  DevBuf om_dev(&ctx->pool), u_dev(&ctx->pool);
   double *om_out = omega;
   double *u_out = U;
   if (!dev) {
@@ -912,7 +979,7 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
   std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.plan->N > b.plan->N; });
   const bool fp32 = (jobs[0].plan->prec & MVPB_PREC_EIG_FP32_RR64) != 0;
   const size_t budget = ctx->cap ? ctx->cap : (size_t)24 << 30;
-  DevBuf om;
+  DevBuf om(&ctx->pool);
   HIP_TRY(om.alloc(sizeof(double) * base[n_plans] * n_bands));
   size_t j0 = 0;
   int chunk = 0;
@@ -1008,6 +1075,17 @@ extern "C" int mvpb_ctx_profile(mvpb_ctx ctx, int enable) {
   (void)hipSetDevice(ctx->device);
   ctx->prof.reset();
   ctx->prof.on = enable != 0;
+  ctx->prof.mask = ~0ull;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_ctx_profile_mask(mvpb_ctx ctx, unsigned long long mask) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  (void)hipSetDevice(ctx->device);
+  ctx->prof.reset();
+  ctx->prof.on = mask != 0;
+  ctx->prof.mask = mask;
   return MVPB_OK;
 }
 

@@ -22,10 +22,15 @@ namespace mvpb {
 // ---------------------------------------------------------------------------
 constexpr int CB = 64;
 
+// Factor and inverse of one diagonal block together: step j of the
+// elimination scales column j of L and row j of the inverse, then updates
+// the trailing lower triangle of the block and the rows of the inverse below
+// j (forward elimination of [L | I]).  The diagonal of L is kept apart so that
+// the pivot of the next step is read without a third barrier.
 __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xarr, int *status, int N, int jb) {
   __shared__ cd D[CB][CB + 1];
   __shared__ cd Di[CB][CB + 1];
-  __shared__ int fail;
+  __shared__ double dg[CB];
   const int b = blockIdx.x;
   if (status[b]) return;
   cd *A = Aarr[b];
@@ -36,8 +41,8 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
   for (int e = tid; e < CB * CB; e += 256) {
     const int r = e % CB, c = e / CB;
     D[r][c] = (r < nb && c < nb && r >= c) ? A[(size_t)(jb + c) * ld + jb + r] : mk(0.0, 0.0);
+    Di[r][c] = mk(r == c ? 1.0 : 0.0, 0.0);
   }
-  if (tid == 0) fail = 0;
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
     const double piv = D[j][j].re;
@@ -46,33 +51,31 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
       return;   // uniform: every thread read the same pivot
     }
     const double sq = sqrt(piv), inv = 1.0 / sq;
-    __syncthreads();
-    for (int r = j + tid; r < nb; r += 256) D[r][j] = (r == j) ? mk(sq, 0.0) : inv * D[r][j];
+    // column j of L below the diagonal, row j of the inverse (entries c <= j)
+    if (tid < CB) {
+      const int r = tid;
+      if (r > j && r < nb) D[r][j] = inv * D[r][j];
+      if (r <= j) Di[j][r] = inv * Di[j][r];
+      if (r == 0) dg[j] = sq;
+    }
     __syncthreads();
     const int m = nb - j - 1;
+    // D[r][c] -= L[r][j] conj(L[c][j]) for j < c <= r
     for (int e = tid; e < m * m; e += 256) {
       const int r = j + 1 + e % m, c = j + 1 + e / m;
       if (r >= c) D[r][c] = D[r][c] - D[r][j] * conj(D[c][j]);
     }
+    // Di[r][c] -= L[r][j] Di[j][c] for r > j, c <= j
+    const int w = j + 1;
+    for (int e = tid; e < m * w; e += 256) {
+      const int r = j + 1 + e % m, c = e / m;
+      Di[r][c] = Di[r][c] - D[r][j] * Di[j][c];
+    }
     __syncthreads();
   }
-  // Di = D^-1 (lower): column c by thread c, forward substitution
-  if (tid < nb) {
-    const int c = tid;
-    for (int k = 0; k < nb; ++k) {
-      if (k < c) {
-        Di[k][c] = mk(0.0, 0.0);
-        continue;
-      }
-      cd v = mk(k == c ? 1.0 : 0.0, 0.0);
-      for (int m = c; m < k; ++m) v = v - D[k][m] * Di[m][c];
-      Di[k][c] = (1.0 / D[k][k].re) * v;
-    }
-  }
-  __syncthreads();
   for (int e = tid; e < nb * nb; e += 256) {
     const int r = e % nb, c = e / nb;
-    if (r >= c) A[(size_t)(jb + c) * ld + jb + r] = D[r][c];
+    if (r >= c) A[(size_t)(jb + c) * ld + jb + r] = (r == c) ? mk(dg[r], 0.0) : D[r][c];
     X[(size_t)(jb + c) * ld + jb + r] = (r >= c) ? Di[r][c] : mk(0.0, 0.0);
   }
 }
@@ -230,25 +233,31 @@ __global__ void __launch_bounds__(256) potri_row(cd *const *Aarr, cd *const *Xar
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) Ts[tx + 16 * a][ty + 16 * c] = acc[a][c];
-  // X_ii (lower) into the Ls/Xs space is too small: read it from global
-  __syncthreads();
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
-  for (int k = 0; k < rows; ++k) {
-    cd pv[4], dv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = tx + 16 * a;
-      pv[a] = (r < rows && r >= k) ? X[(size_t)(i0 + k) * ld + i0 + r] : mk(0.0, 0.0);
+  // X_ii (lower) times T, X_ii staged 16 columns at a time in Ls
+  for (int k0 = 0; k0 < rows; k0 += 16) {
+    __syncthreads();
+    for (int e = tid; e < CB * 16; e += 256) {
+      const int r = e % CB, kk = e / CB, k = k0 + kk;
+      Ls[r][kk] = (r < rows && k < rows && r >= k) ? X[(size_t)(i0 + k) * ld + i0 + r] : mk(0.0, 0.0);
     }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      if (k0 + kk >= rows) break;
+      cd pv[4], dv[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) dv[c] = Ts[k][ty + 16 * c];
+      for (int a = 0; a < 4; ++a) pv[a] = Ls[tx + 16 * a][kk];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) dv[c] = Ts[k0 + kk][ty + 16 * c];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
+    }
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {

@@ -28,6 +28,7 @@ enum KernelId {
 
 struct Profiler {
   bool on = false;
+  unsigned long long mask = ~0ull;   // kernel ids timed while on
   struct Rec {
     int kernel;
     hipEvent_t a, b;
@@ -82,7 +83,7 @@ struct ProfScope {
   int k;
   hipEvent_t a = nullptr;
   ProfScope(int kernel, hipStream_t s) : p(t_prof), st(s), k(kernel) {
-    if (p && p->on) {
+    if (p && p->on && ((p->mask >> kernel) & 1ull)) {
       a = p->get();
       (void)hipEventRecord(a, st);
     }

@@ -46,6 +46,7 @@ EXPORTS = [
     "mvpb_kpath_square", "mvpb_ctx_profile", "mvpb_ctx_profile_read", "mvpb_plan_create_batch",
     "mvpb_sur_create", "mvpb_sur_destroy", "mvpb_sur_n_params", "mvpb_sur_get_params", "mvpb_sur_set_params",
     "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step", "mvpb_copy_device",
+    "mvpb_ctx_profile_mask",
 ]
 N_KERNELS = 15
 
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.mvpb_sur_train_step.argtypes = [P, I, P, P, ctypes.c_float, F, ctypes.c_uint]
     lib.mvpb_copy_device.argtypes = [P, P, P, ctypes.c_size_t]
     lib.mvpb_ctx_profile.argtypes = [P, I]
+    lib.mvpb_ctx_profile_mask.argtypes = [P, ctypes.c_ulonglong]
     lib.mvpb_ctx_profile_read.argtypes = [P, I, D, ctypes.POINTER(ctypes.c_longlong),
                                           ctypes.POINTER(ctypes.c_char_p)]
     for name in EXPORTS:
@@ -215,6 +217,19 @@ class Context:
 
     def profile(self, enable: bool = True):
         _check(load().mvpb_ctx_profile(self.h, 1 if enable else 0))
+
+    def profile_only(self, names):
+        """Time only the named kernel families (empty: stop timing)."""
+        ids = [self.kernel_names().index(n) for n in names]
+        _check(load().mvpb_ctx_profile_mask(self.h, sum(1 << i for i in ids)))
+
+    def kernel_names(self) -> list:
+        out = []
+        for k in range(N_KERNELS):
+            nm = ctypes.c_char_p()
+            _check(load().mvpb_ctx_profile_read(self.h, k, None, None, ctypes.byref(nm)))
+            out.append(nm.value.decode())
+        return out
 
     def profile_read(self) -> dict:
         """{kernel name: (total_ms, launches)} of the timed launches."""
