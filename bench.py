@@ -98,23 +98,18 @@ def roofline_models(n: int, nb: int):
 
 def measured_traffic(kernel: str):
     """Calibrated HBM bytes per launch of `kernel` from the committed counter
-    summary of this workload, or None when it is missing or was taken on other
-    sources."""
+    summary of this workload, or None when it is missing or was taken on
+    other sources of that kernel."""
+    from paper_1310_6380_amd.profile_summary import source_digest
     path = os.path.join(HERE, "profiles", "hbm_traffic_voronoi1132_fp64.md")
     if not os.path.exists(path):
         return None
-    digest, row = None, None
     with open(path) as fh:
         for line in fh:
-            if line.startswith("source digest:"):
-                digest = line.split(":", 1)[1].strip()
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
-            if len(cells) >= 5 and cells[0] == kernel:
-                row = cells
-    from paper_1310_6380_amd.profile_summary import source_digest
-    if digest != source_digest() or row is None:
-        return None
-    return float(row[4])
+            if len(cells) >= 6 and cells[0] == kernel:
+                return float(cells[4]) if cells[5] == source_digest(kernel) else None
+    return None
 
 
 def cpu_baseline(cell, M, Q, nb, omega_gpu, n_sample):

@@ -2,6 +2,7 @@
 // the k-independent plan build and the batched per-k solve.
 #include <math.h>
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -131,10 +132,26 @@ struct DevBuf {
   T *as() const { return reinterpret_cast<T *>(p); }
 };
 
+// Side streams of a context, and the number of independent parts stage 1 of
+// a solve is split into (one stream each; MVPB_STAGE1_PARTS overrides it).
+constexpr int MAX_SIDE = 3;
+static int stage1_parts() {
+  static const int v = [] {
+    const char *e = getenv("MVPB_STAGE1_PARTS");
+    const int k = e ? atoi(e) : 0;
+    return (k >= 1 && k <= MAX_SIDE + 1) ? k : 2;
+  }();
+  return v;
+}
+
 struct mvpb_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // side streams (owned) for work that overlaps the main stream, and the
+  // events of the fork from and the joins back to it
+  hipStream_t side[MAX_SIDE] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[MAX_SIDE] = {};
   size_t cap = 0;
   Pool pool;          // declared before every buffer that returns to it
   DevBuf ws{&pool};      // per-solve workspace (grow-only)
@@ -157,6 +174,14 @@ static void ctx_free(mvpb_ctx c) {
   c->scratch.release();
   c->pool.trim();
   c->prof.reset();
+  for (int q = 0; q < MAX_SIDE; ++q) {
+    if (c->side[q]) {
+      (void)hipStreamSynchronize(c->side[q]);
+      (void)hipStreamDestroy(c->side[q]);
+    }
+    if (c->ev_join[q]) (void)hipEventDestroy(c->ev_join[q]);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -242,6 +267,15 @@ extern "C" int mvpb_ctx_create(int device, void *hip_stream, size_t workspace_ca
       return set_err(MVPB_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
     }
     c->own_stream = true;
+  }
+  hipError_t e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  for (int q = 0; q < MAX_SIDE && e == hipSuccess; ++q) {
+    e = hipStreamCreateWithFlags(&c->side[q], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[q], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    ctx_free(c);
+    return set_err(MVPB_E_DEVICE, "side stream: %s", hipGetErrorString(e));
   }
   *out = c;
   return MVPB_OK;
@@ -766,6 +800,8 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     n_max = std::max(n_max, n);
     n_min = std::min(n_min, n);
   }
+  const size_t ctl_off = total;   // bulge-chasing launch control words after the items
+  total += align256(sizeof(int) * hb2st_ctl_ints(n_items));
   if (ctx->cap && total > ctx->cap)
     return set_err(MVPB_E_NOMEM, "workspace %zu bytes exceeds the cap of %zu bytes", total, ctx->cap);
   const bool realloc = total > ctx->ws.bytes || sizeof(EigItem) * n_items > ctx->items.bytes;
@@ -801,7 +837,33 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
 
   auto enqueue = [&]() -> hipError_t {
     hipError_t e = launch_form_operator(d_items, n_items, n_max, fp32, st);
-    if (e == hipSuccess) e = launch_reduce(d_items, n_items, n_min, n_max, fp32, st);
+    // stage 1 in independent parts of the items, one per stream
+    ItemPart parts[MAX_SIDE + 1];
+    const int n_parts = std::max(1, std::min(stage1_parts(), n_items));
+    for (int q = 0; q < n_parts; ++q) {
+      const int i0 = (int)((long long)n_items * q / n_parts), i1 = (int)((long long)n_items * (q + 1) / n_parts);
+      ItemPart &pt = parts[q];
+      pt.items = d_items + i0;
+      pt.n_items = i1 - i0;
+      pt.n_min = 1 << 30;
+      pt.n_max = 0;
+      for (int i = i0; i < i1; ++i) {
+        pt.n_min = std::min(pt.n_min, 2 * jobs[i].plan->N);
+        pt.n_max = std::max(pt.n_max, 2 * jobs[i].plan->N);
+      }
+      pt.stream = q == 0 ? st : ctx->side[q - 1];
+    }
+    if (e == hipSuccess && n_parts > 1) {
+      e = hipEventRecord(ctx->ev_fork, st);
+      for (int q = 1; q < n_parts && e == hipSuccess; ++q) e = hipStreamWaitEvent(parts[q].stream, ctx->ev_fork, 0);
+    }
+    if (e == hipSuccess) e = launch_stage1(parts, n_parts, fp32);
+    for (int q = 1; q < n_parts && e == hipSuccess; ++q) {
+      e = hipEventRecord(ctx->ev_join[q - 1], parts[q].stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->ev_join[q - 1], 0);
+    }
+    int *ctl = reinterpret_cast<int *>(ctx->ws.as<char>() + ctl_off);
+    if (e == hipSuccess) e = launch_stage2(d_items, n_items, n_max, fp32, ctl, st);
     if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, n_max, nb, st);
     if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_max, nb, fp32, st);
     if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, n_max, nb, st);

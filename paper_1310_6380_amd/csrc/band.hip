@@ -22,6 +22,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -758,18 +759,23 @@ MVPB_DEV cx<R> row16_sum_c(cx<R> v) {
 static_assert(HB == 16, "the lane layout of the bulge-chasing kernel assumes HB = 16");
 constexpr int CH_WAVES = 8;
 constexpr long long CH_SPIN_LIMIT = 1ll << 24;
-// workgroups per item of the bulge chasing, and the CUs that may be used
-// (one 1024-thread workgroup per CU keeps every workgroup resident)
+// workgroups per item of the bulge chasing (more than one only while every
+// workgroup of the launch can be resident at once, one per CU)
 constexpr int HB2ST_MAX_WG = 4;
-constexpr int HB2ST_CU_BUDGET = 256;
+// launch control words of the bulge chasing: per-XCD slot counters, the next
+// item, and the item of every group of P workgroups (per XCD)
+constexpr int HB2ST_CTL_ITEM = 16, HB2ST_CTL_TABLE = 32, HB2ST_MAX_XCC = 16;
+size_t hb2st_ctl_ints(int n_items) { return HB2ST_CTL_TABLE + (size_t)HB2ST_MAX_XCC * 8 * ((n_items + 7) / 8); }
 
 // Copy the band (subdiagonals 0 .. HB) of the stage-1 result into the
 // working band WB (subdiagonals HB+1 .. 2 HB zero) and clear the item's
 // progress counters: flag[0] error, flag[1] abort, flag[2 + i] blocks done by
 // sweep i.
 template <typename R>
-__global__ void __launch_bounds__(256) hb2st_init(const EigItem *__restrict__ items) {
+__global__ void __launch_bounds__(256) hb2st_init(const EigItem *__restrict__ items, int *ctl, int ctl_ints) {
   typedef cx<R> C;
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int e = threadIdx.x; e < ctl_ints; e += 256) gst(ctl, e, e < HB2ST_CTL_TABLE ? 0 : -1);
   const EigItem it = items[blockIdx.y];
   const int n = 2 * it.N;
   const size_t ld = (size_t)n;
@@ -803,45 +809,55 @@ __global__ void __launch_bounds__(256) hb2st_fini(const EigItem *__restrict__ it
 // hardware register, bits 3:0.
 MVPB_DEV int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & 0xF; }
 
-// One entry per workgroup: the XCD it ran on.
-__global__ void __launch_bounds__(64) xcd_probe(int *out, int n) {
-  if (threadIdx.x == 0 && (int)blockIdx.x < n) gst(out, blockIdx.x, xcc_id());
-}
-
-// Workgroup layout of the bulge chasing: P workgroups per item, all on the
-// XCD (L2) of the item: workgroup L of the 1-D grid runs on XCD L % 8, and
-// item j is given the slots s = (j / 8) P .. (j / 8) P + P - 1 of XCD j % 8.
+// Workgroup layout of the bulge chasing: P workgroups per item, all on one
+// XCD so that they share its L2.  Every workgroup reads the XCD it runs on
+// (XCC_ID) and takes the next slot s of that XCD; the first workgroup of each
+// group of P slots claims the next item and publishes it to the other P - 1.
+// The launch has 8 K P workgroups, so any round-robin placement over the 8
+// XCDs leaves whole groups on each; a group that stays incomplete makes its
+// item give up (bounded waits), never share blocks across L2s.
 // Sweeps are dealt out in groups of G consecutive ones: sweep i belongs to
 // workgroup (i / G) % P, wavefront ((i / (G P)) G + i % G) % CH_WAVES.  The
 // sweeps in flight (about n / (2 HB) of them) then span several CUs; a
 // hand-over between CUs costs more than two wavefronts sharing a SIMD, so
 // G = CH_WAVES is the default.  Sweeps hand over within a
 // workgroup through LDS counters and between workgroups through counters in
-// the shared L2: the consumer invalidates its L1 before reading the
-// producer's blocks.  With same_l2 set (the device was found to place
-// workgroup L on XCD L % 8, and every workgroup checks that it did) producer
-// and consumer share one L2, and the producer only waits until its stores
-// are acknowledged (the L1 writes through to the L2) before it bumps the
-// counter; otherwise the counter is released at agent scope, which also
-// writes the L2 back to memory.
+// the shared L2: the producer waits until its stores are acknowledged (the
+// L1 writes through to the L2) before it bumps the counter, and the consumer
+// invalidates its L1 before reading the producer's blocks.
 template <typename R>
 __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict__ items, int n_items, int P, int G,
-                                                      int same_l2) {
+                                                      int *ctl) {
   typedef cx<R> C;
   __shared__ int prog[CH_WAVES];
   __shared__ int abort_s;
-  const int L = blockIdx.x, xcd = L & 7, slot = L >> 3;
-  const int item = (slot / P) * 8 + xcd, a = slot % P;
-  if (item >= n_items) return;
-  const EigItem it = items[item];
-  if (same_l2 && P > 1 && xcc_id() != xcd) {
-    // placement differs from the one the hand-over relies on: fail the item
-    if (threadIdx.x == 0) {
-      __hip_atomic_store(it.flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(it.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __shared__ int claim[2];
+  if (threadIdx.x == 0) {
+    const int gmax = (int)(gridDim.x / P);   // groups an XCD can hold
+    const int x = xcc_id();
+    const int s = atomicAdd(ctl + x, 1);
+    const int grp = s / P;
+    int item = -1;
+    if (grp < gmax) {
+      int *entry = ctl + HB2ST_CTL_TABLE + x * gmax + grp;
+      if (s % P == 0) {
+        item = atomicAdd(ctl + HB2ST_CTL_ITEM, 1);
+        __hip_atomic_store(entry, item, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        for (long long spins = 0; spins < CH_SPIN_LIMIT; ++spins) {
+          item = __hip_atomic_load(entry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (item >= 0) break;
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
     }
-    return;
+    claim[0] = item;
+    claim[1] = s % P;
   }
+  __syncthreads();
+  const int item = claim[0], a = claim[1];
+  if (item < 0 || item >= n_items) return;
+  const EigItem it = items[item];
   const int n = 2 * it.N;
   C *__restrict__ WB = (C *)it.WB;
   C *__restrict__ V2 = (C *)it.V2;
@@ -1017,13 +1033,9 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
         __hip_atomic_store(&prog[w], i * 1024 + k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         // the last sweep of a group also reports to the next workgroup
         if (report) {
-          if (same_l2) {
-            // every store of this wavefront acknowledged by the shared L2
-            __builtin_amdgcn_s_waitcnt(0);
-            __hip_atomic_store(gflag + 2 + i, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          } else {
-            __hip_atomic_store(gflag + 2 + i, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          }
+          // every store of this wavefront acknowledged by the shared L2
+          __builtin_amdgcn_s_waitcnt(0);
+          __hip_atomic_store(gflag + 2 + i, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       // the reflector for the back-transform (after the release: not waited for)
@@ -1129,6 +1141,133 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
   for (int e = tid; e < n * ncl; e += BT_THREADS) {
     const int r = e % n, c = e / n;
     gst(Y, (size_t)(cbase + c) * ld + r, Z[zidx(r, c, nc)]);
+  }
+}
+
+// Stage-2 back-transform with one wavefront per two eigenvector columns, for
+// n - 1 <= 64 HB.  During sweep i lane k holds rows i+1+16k .. i+16+16k of the
+// column (zero past n-1) in registers and applies reflector (i, k) to them;
+// the blocks of one sweep are disjoint, so no lane waits for another.  Between
+// sweeps the window slides up by one row: every lane hands its last row to the
+// next lane (DPP wave shift) and lane 0 takes row i of the tridiagonal
+// eigenvector.  The register slot of a window row rotates with the sweep
+// count, so the sweep loop is unrolled 16 times to keep every index static.
+// The reflectors of one sweep are consecutive in V2 (one 16-vector per
+// block) and are loaded one sweep ahead; the wavefronts of a workgroup are
+// columns of one item and read the same reflectors (the CU's L1 serves them).
+constexpr int BTW_WAVES = 4;   // wavefronts per workgroup
+constexpr int BTW_COLS = 2;    // eigenvector columns per wavefront
+template <typename R>
+MVPB_DEV cx<R> wave_shr1_c(cx<R> v);
+template <>
+MVPB_DEV cx<double> wave_shr1_c(cx<double> v) {
+  return mk(dpp_mov<0x138>(v.re), dpp_mov<0x138>(v.im));   // lane l <- lane l-1, lane 0 <- 0
+}
+template <>
+MVPB_DEV cx<float> wave_shr1_c(cx<float> v) {
+  return mkc<float>(dpp_mov<0x138>(v.re), dpp_mov<0x138>(v.im));
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BTW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+backtransform_2s_wave(const EigItem *__restrict__ items) {
+  typedef cx<R> C;
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N, nb = it.nb;
+  const int lane = threadIdx.x & 63;
+  const int cb = (blockIdx.x * BTW_WAVES + (threadIdx.x >> 6)) * BTW_COLS;   // first column of the wavefront
+  if (cb >= nb) return;   // whole wavefronts
+  const int ncw = min(BTW_COLS, nb - cb);
+  const size_t ld = (size_t)n;
+  const C *V2 = (const C *)it.V2;
+  const C *tau2 = (const C *)it.tau2;
+  const double *X = it.X;
+  C *Y = (C *)it.Yb;
+  const long long rtot = refl_count(n - 1);
+  const int T = n - 1;   // sweeps, applied for i = n-2 .. 0
+  // reflector of sweep i for this lane's block (tau = 0 where the block is
+  // absent, so that the update leaves the zero rows alone), and row i+1 of
+  // the input columns (the row lane 0 takes when sweep i starts)
+  auto fetch = [&](int i, C (&v)[HB], C &tau, R (&xin)[BTW_COLS]) {
+    const int ic = max(i, 0);
+    const int nsteps = (n - 1 - ic + HB - 1) / HB;
+    const bool ok = i >= 0 && lane < nsteps;
+    const long long ri = rtot - refl_count(n - 1 - ic) + min(lane, nsteps - 1);
+#pragma unroll
+    for (int j = 0; j < HB; ++j) v[j] = gld(V2, (size_t)ri * HB + j);
+    const C t = gld(tau2, ri);
+    tau = ok ? t : czero<R>();
+#pragma unroll
+    for (int q = 0; q < BTW_COLS; ++q) xin[q] = (R)gld(X, (size_t)(ic + 1) * nb + cb + min(q, ncw - 1));
+  };
+  C w[BTW_COLS][HB];
+#pragma unroll
+  for (int q = 0; q < BTW_COLS; ++q)
+#pragma unroll
+    for (int j = 0; j < HB; ++j) w[q][j] = czero<R>();
+  C va[HB], vb[HB], ta, tb;
+  R xa[BTW_COLS], xb[BTW_COLS];
+  fetch(T - 1, va, ta, xa);
+  // one sweep; S0 = slot of logical window row 0 after the slide
+  auto sweep = [&](auto S0c, const C (&v)[HB], C tau, const R (&xin)[BTW_COLS]) {
+    constexpr int S0 = decltype(S0c)::value;
+#pragma unroll
+    for (int q = 0; q < BTW_COLS; ++q) {
+      const C out = w[q][S0];              // old last row (logical 15 before the slide)
+      C in = wave_shr1_c<R>(out);
+      if (lane == 0) in = mkc<R>(xin[q], R(0));
+      w[q][S0] = in;
+    }
+    C d[BTW_COLS];
+#pragma unroll
+    for (int q = 0; q < BTW_COLS; ++q) {
+      C d0 = czero<R>(), d1 = czero<R>();
+#pragma unroll
+      for (int j = 0; j < HB; j += 2) {
+        d0 = cfma_cj(v[j], w[q][(S0 + j) % HB], d0);
+        d1 = cfma_cj(v[j + 1], w[q][(S0 + j + 1) % HB], d1);
+      }
+      d[q] = tau * (d0 + d1);
+    }
+#pragma unroll
+    for (int q = 0; q < BTW_COLS; ++q)
+#pragma unroll
+      for (int j = 0; j < HB; ++j) w[q][(S0 + j) % HB] = w[q][(S0 + j) % HB] - v[j] * d[q];
+  };
+  auto finish = [&](auto S0c) {
+    constexpr int S0 = decltype(S0c)::value;
+#pragma unroll
+    for (int q = 0; q < BTW_COLS; ++q) {
+      if (q >= ncw) break;
+#pragma unroll
+      for (int j = 0; j < HB; ++j) {
+        const int r = 1 + HB * lane + j;
+        if (r < n) gst(Y, (size_t)(cb + q) * ld + r, w[q][(S0 + j) % HB]);
+      }
+      if (lane == 0) gst(Y, (size_t)(cb + q) * ld, mkc<R>((R)gld(X, (size_t)(cb + q)), R(0)));
+    }
+  };
+  // sweep t (t = 0 .. T-1) is i = T-1-t; the slot of row 0 after its slide
+  // is (-(t+1)) mod 16 = (15 (t+1)) mod 16.  Two register stages: the
+  // reflectors of sweep t+1 load while sweep t is applied.
+  for (int t0 = 0; t0 < T; t0 += HB) {
+#define MVPB_BTW_STEP(u, VCUR, TCUR, XCUR, VN, TN, XN)                                   \
+    {                                                                                 \
+      const int t = t0 + (u);                                                         \
+      if (t >= T) break;                                                              \
+      fetch(T - 2 - t, VN, TN, XN);                                                   \
+      sweep(std::integral_constant<int, (15 * ((u) + 1)) % HB>{}, VCUR, TCUR, XCUR);   \
+      if (t == T - 1) finish(std::integral_constant<int, (15 * ((u) + 1)) % HB>{});    \
+    }
+    MVPB_BTW_STEP(0, va, ta, xa, vb, tb, xb) MVPB_BTW_STEP(1, vb, tb, xb, va, ta, xa)
+    MVPB_BTW_STEP(2, va, ta, xa, vb, tb, xb) MVPB_BTW_STEP(3, vb, tb, xb, va, ta, xa)
+    MVPB_BTW_STEP(4, va, ta, xa, vb, tb, xb) MVPB_BTW_STEP(5, vb, tb, xb, va, ta, xa)
+    MVPB_BTW_STEP(6, va, ta, xa, vb, tb, xb) MVPB_BTW_STEP(7, vb, tb, xb, va, ta, xa)
+    MVPB_BTW_STEP(8, va, ta, xa, vb, tb, xb) MVPB_BTW_STEP(9, vb, tb, xb, va, ta, xa)
+    MVPB_BTW_STEP(10, va, ta, xa, vb, tb, xb) MVPB_BTW_STEP(11, vb, tb, xb, va, ta, xa)
+    MVPB_BTW_STEP(12, va, ta, xa, vb, tb, xb) MVPB_BTW_STEP(13, vb, tb, xb, va, ta, xa)
+    MVPB_BTW_STEP(14, va, ta, xa, vb, tb, xb) MVPB_BTW_STEP(15, vb, tb, xb, va, ta, xa)
+#undef MVPB_BTW_STEP
   }
 }
 
@@ -1241,9 +1380,18 @@ static void launch_panel_class(const EigItem *items, int n_items, int p, int m_l
   hipLaunchKernelGGL((he2hb_panel<R, RPT>), dim3(n_items), dim3(PQ_THREADS), 0, st, items, p);
 }
 
-// Per device: 1 if workgroup L of a 1-D grid was seen to run on XCD L % 8.
+// Compute units of the current device (cached per device).
 constexpr int MAX_DEVICES = 64;
-static int g_xcd_round_robin[MAX_DEVICES];
+static int g_cu_count[MAX_DEVICES];
+static int device_cus() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return 0;
+  if (!g_cu_count[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) g_cu_count[dev] = v;
+  }
+  return g_cu_count[dev];
+}
 
 // Sweeps per group of the bulge-chasing layout (a divisor of CH_WAVES);
 // MVPB_HB2ST_GROUP overrides it for tuning.
@@ -1256,48 +1404,69 @@ static int hb2st_group() {
   return g;
 }
 
+// Stage 1 of every part, step by step: the parts are independent sets of
+// items on their own streams, so that one part's latency-bound panel overlaps
+// the other's bandwidth-bound trailing update.
 template <typename R>
-static hipError_t launch_reduce_t(const EigItem *items, int n_items, int n_min, int n_max, hipStream_t st) {
-  for (int p = 0;; ++p) {
-    const int c0 = p * HB, m = n_max - c0 - HB;
-    if (m <= 0) break;
-    const int m_lo = std::max(1, n_min - c0 - HB);
-    {
-      ProfScope ps(K_PANEL, st);
-      launch_panel_class<R, 1>(items, n_items, p, m_lo, m, st);
-      launch_panel_class<R, 2>(items, n_items, p, m_lo, m, st);
-      launch_panel_class<R, 4>(items, n_items, p, m_lo, m, st);
-      launch_panel_class<R, 8>(items, n_items, p, m_lo, m, st);
-    }
-    const int nrb = (m + 63) / 64;
-    {
-      ProfScope ps(K_HEMM, st);
-      hipLaunchKernelGGL((he2hb_hemm<R>), dim3(nrb, n_items), dim3(256), 0, st, items, p);
-    }
-    {
-      ProfScope ps(K_WFORM, st);
-      hipLaunchKernelGGL((he2hb_wform<R>), dim3(nrb, n_items), dim3(256), 0, st, items, p);
-    }
-    {
-      ProfScope ps(K_HER2K, st);
-      hipLaunchKernelGGL((he2hb_her2k<R>), dim3(nrb * (nrb + 1) / 2, n_items), dim3(256), 0, st, items, p);
+static hipError_t launch_stage1_t(const ItemPart *parts, int n_parts) {
+  int steps = 0;
+  for (int q = 0; q < n_parts; ++q) steps = std::max(steps, (parts[q].n_max - 1) / HB + 1);
+  for (int p = 0; p < steps; ++p) {
+    for (int q = 0; q < n_parts; ++q) {
+      const ItemPart &pt = parts[q];
+      const EigItem *items = pt.items;
+      const int n_items = pt.n_items;
+      hipStream_t st = pt.stream;
+      const int c0 = p * HB, m = pt.n_max - c0 - HB;
+      if (n_items <= 0 || m <= 0) continue;
+      const int m_lo = std::max(1, pt.n_min - c0 - HB);
+      {
+        ProfScope ps(K_PANEL, st);
+        launch_panel_class<R, 1>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 2>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 4>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 8>(items, n_items, p, m_lo, m, st);
+      }
+      const int nrb = (m + 63) / 64;
+      {
+        ProfScope ps(K_HEMM, st);
+        hipLaunchKernelGGL((he2hb_hemm<R>), dim3(nrb, n_items), dim3(256), 0, st, items, p);
+      }
+      {
+        ProfScope ps(K_WFORM, st);
+        hipLaunchKernelGGL((he2hb_wform<R>), dim3(nrb, n_items), dim3(256), 0, st, items, p);
+      }
+      {
+        ProfScope ps(K_HER2K, st);
+        hipLaunchKernelGGL((he2hb_her2k<R>), dim3(nrb * (nrb + 1) / 2, n_items), dim3(256), 0, st, items, p);
+      }
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_stage1(const ItemPart *parts, int n_parts, bool fp32) {
+  return fp32 ? launch_stage1_t<float>(parts, n_parts) : launch_stage1_t<double>(parts, n_parts);
+}
+
+// Stage 2 (bulge chasing) of all items on one stream; ctl holds
+// hb2st_ctl_ints(n_items) ints.  Every workgroup of the launch must be
+// resident at once when P > 1, so nothing else may run beside it.
+template <typename R>
+static hipError_t launch_stage2_t(const EigItem *items, int n_items, int n_max, int *ctl, hipStream_t st) {
   {
     const int nmax_items_xcd = (n_items + 7) / 8;
-    const int P = std::max(1, std::min(HB2ST_MAX_WG, HB2ST_CU_BUDGET / (8 * nmax_items_xcd)));
+    const int P = std::max(1, std::min(HB2ST_MAX_WG, device_cus() / (8 * nmax_items_xcd)));
     const int chunks = (n_max - 1 + HB - 1) / HB;
     {
       ProfScope ps(K_HB2ST_IO, st);
-      hipLaunchKernelGGL((hb2st_init<R>), dim3(std::max(1, chunks), n_items), dim3(256), 0, st, items);
+      hipLaunchKernelGGL((hb2st_init<R>), dim3(std::max(1, chunks), n_items), dim3(256), 0, st, items, ctl,
+                         (int)hb2st_ctl_ints(n_items));
     }
     {
       ProfScope ps(K_HB2ST, st);
-      int dev = 0;
-      (void)hipGetDevice(&dev);
-      const int same_l2 = (dev >= 0 && dev < MAX_DEVICES) ? g_xcd_round_robin[dev] : 0;
       hipLaunchKernelGGL((hb2st<R>), dim3(8 * nmax_items_xcd * P), dim3(CH_WAVES * 64), 0, st, items, n_items, P,
-                         hb2st_group(), same_l2);
+                         hb2st_group(), ctl);
     }
     {
       ProfScope ps(K_HB2ST_IO, st);
@@ -1307,9 +1476,9 @@ static hipError_t launch_reduce_t(const EigItem *items, int n_items, int n_min, 
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const EigItem *items, int n_items, int n_min, int n_max, bool fp32, hipStream_t st) {
-  return fp32 ? launch_reduce_t<float>(items, n_items, n_min, n_max, st)
-              : launch_reduce_t<double>(items, n_items, n_min, n_max, st);
+hipError_t launch_stage2(const EigItem *items, int n_items, int n_max, bool fp32, int *ctl, hipStream_t st) {
+  return fp32 ? launch_stage2_t<float>(items, n_items, n_max, ctl, st)
+              : launch_stage2_t<double>(items, n_items, n_max, ctl, st);
 }
 
 // Eigenvector columns per back-transform workgroup: bounded by the LDS
@@ -1329,41 +1498,23 @@ hipError_t launch_backtransform(const EigItem *items, int n_items, int n_max, in
   const int groups = (nb + nc - 1) / nc;
   const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
   const size_t sh = zbytes(n_max, nc, es);
+  // stage 2: one wavefront per column pair while every block of a sweep has a lane
+  const bool wave = n_max - 1 <= 64 * HB;
+  const dim3 gw((nb + BTW_WAVES * BTW_COLS - 1) / (BTW_WAVES * BTW_COLS), n_items);
   if (fp32) {
-    hipLaunchKernelGGL((backtransform_2s<float>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
+    if (wave)
+      hipLaunchKernelGGL((backtransform_2s_wave<float>), gw, dim3(BTW_WAVES * 64), 0, st, items);
+    else
+      hipLaunchKernelGGL((backtransform_2s<float>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
     hipLaunchKernelGGL((backtransform_s1<float>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
   } else {
-    hipLaunchKernelGGL((backtransform_2s<double>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
+    if (wave)
+      hipLaunchKernelGGL((backtransform_2s_wave<double>), gw, dim3(BTW_WAVES * 64), 0, st, items);
+    else
+      hipLaunchKernelGGL((backtransform_2s<double>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
     hipLaunchKernelGGL((backtransform_s1<double>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
   }
   return hipGetLastError();
-}
-
-// Record whether the current device deals workgroups to its 8 XCDs round
-// robin (the layout the bulge chasing's fast hand-over assumes).
-static hipError_t probe_xcd_layout() {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= MAX_DEVICES) return hipSuccess;
-  g_xcd_round_robin[dev] = 0;
-  hipDeviceProp_t prop;
-  e = hipGetDeviceProperties(&prop, dev);
-  if (e != hipSuccess) return e;
-  const int n = 16 * prop.multiProcessorCount;
-  int *d = nullptr;
-  e = hipMalloc(&d, sizeof(int) * n);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(xcd_probe, dim3(n), dim3(64), 0, 0, d, n);
-  std::vector<int> h(n, -1);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpy(h.data(), d, sizeof(int) * n, hipMemcpyDeviceToHost);
-  (void)hipFree(d);
-  if (e != hipSuccess) return e;
-  bool rr = true;
-  for (int i = 0; i < n; ++i) rr = rr && h[i] == i % 8;
-  g_xcd_round_robin[dev] = rr ? 1 : 0;
-  return hipSuccess;
 }
 
 hipError_t init_band_attributes() {
@@ -1373,7 +1524,7 @@ hipError_t init_band_attributes() {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, BT_LDS_BYTES);
     if (e != hipSuccess) return e;
   }
-  return probe_xcd_layout();
+  return hipSuccess;
 }
 
 }  // namespace mvpb

@@ -102,7 +102,20 @@ hipError_t launch_zgemm(Op opA, Op opB, int M, int N, int K, cd alpha, GemmBatch
 // band.hip
 hipError_t init_band_attributes();
 // Stage 1 (dense -> band) and stage 2 (band -> tridiagonal d, e) for every item.
-hipError_t launch_reduce(const EigItem *items, int n_items, int n_min, int n_max, bool fp32, hipStream_t st);
+// A set of items (consecutive in the device item table) with its size range
+// and the stream its launches go to.
+struct ItemPart {
+  const EigItem *items = nullptr;
+  int n_items = 0, n_min = 0, n_max = 0;
+  hipStream_t stream = nullptr;
+};
+// Reduction to band form (stage 1) of every part, the parts' launches
+// interleaved step by step on their own streams.
+hipError_t launch_stage1(const ItemPart *parts, int n_parts, bool fp32);
+// Band to tridiagonal (stage 2, bulge chasing) and d, e of all items; ctl
+// points to hb2st_ctl_ints(n_items) ints of device memory.
+size_t hb2st_ctl_ints(int n_items);
+hipError_t launch_stage2(const EigItem *items, int n_items, int n_max, bool fp32, int *ctl, hipStream_t st);
 // Eigenvectors of C(k) from those of the tridiagonal matrix (X -> Y).
 hipError_t launch_backtransform(const EigItem *items, int n_items, int n_max, int nb, bool fp32, hipStream_t st);
 int backtransform_cols(int n_max, bool fp32);

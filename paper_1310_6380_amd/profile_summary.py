@@ -10,8 +10,9 @@
       what the same counter reads for the library's plain copy kernel (copy16)
       moving B bytes each way.
 
-Both print Markdown on stdout.  The traffic summary ends with the digest of
-the HIP sources it was taken on; figures for other sources are stale.
+Both print Markdown on stdout.  Each traffic row carries the digest of the
+source file of its kernel (and the shared headers) it was taken on; figures
+for other sources are stale.
 """
 from __future__ import annotations
 
@@ -27,12 +28,37 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def source_digest() -> str:
+SHARED_HEADERS = ("common.h", "kernels.h")
+# kernel families timed as one launch -> a kernel of the family
+FAMILY = {"backtransform": "backtransform_2s", "tridiag_eig": "tridiag_invit", "rayleigh_ritz": "rr_product",
+          "potrf_trtri": "potrf_diag", "zgemm": "zgemm_kernel", "structure_factors": "sf_mfma_pass_a",
+          "combine_coefficients": "combine_coefficients"}
+
+
+def kernel_source(name: str):
+    """The HIP source file that defines kernel `name` (or a kernel of that family)."""
+    name = FAMILY.get(name, name)
+    csrc = os.path.join(HERE, "csrc")
+    pat = re.compile(r"__global__[^;{]*?\b" + re.escape(name) + r"\s*\(", re.S)
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith(".hip"):
+            with open(os.path.join(csrc, f)) as fh:
+                if pat.search(fh.read()):
+                    return f
+    return None
+
+
+def source_digest(name: str) -> str:
+    """SHA-256 of the file defining the kernel and of the shared headers: counter
+    figures taken on other sources of that kernel do not apply."""
+    f = kernel_source(name)
+    if f is None:
+        return "unknown"
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + b"\0" + fh.read())
+    for g in (f,) + SHARED_HEADERS:
+        with open(os.path.join(csrc, g), "rb") as fh:
+            h.update(g.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -119,8 +145,9 @@ def cmd_traffic(a):
     print(f"calibration: `{a.cmd_copy}` (copy16 moving {a.copy_bytes} bytes each way; "
           f"FETCH_SIZE {sum(cf) / len(cf):.1f} KiB, WRITE_SIZE {sum(cw) / len(cw):.1f} KiB per dispatch)\n")
     print(f"scale factors: fetch {f_fetch:.4f}, write {f_write:.4f}\n")
-    print("| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | calibrated bytes/dispatch |")
-    print("|---|---:|---:|---:|---:|")
+    print("| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | calibrated bytes/dispatch "
+          "| source digest |")
+    print("|---|---:|---:|---:|---:|---|")
     rows = {}
     for k in sorted(set(fetch) | set(write)):
         fv, wv = fetch.get(k, []), write.get(k, [])
@@ -132,8 +159,7 @@ def cmd_traffic(a):
         a2, a1 = rows["backtransform_2s"], rows["backtransform_s1"]
         rows["backtransform"] = (a2[0], a2[1] + a1[1], a2[2] + a1[2], a2[3] + a1[3])
     for k, (nd, fa, wa, b) in sorted(rows.items(), key=lambda kv: -kv[1][3] * kv[1][0]):
-        print(f"| {k} | {nd} | {fa:.1f} | {wa:.1f} | {b:.0f} |")
-    print(f"\nsource digest: {source_digest()}")
+        print(f"| {k} | {nd} | {fa:.1f} | {wa:.1f} | {b:.0f} | {source_digest(k)} |")
 
 
 def main(argv=None):
