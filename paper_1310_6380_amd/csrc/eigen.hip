@@ -1,8 +1,9 @@
 // Tridiagonal eigenpairs and the FP64 Rayleigh-Ritz refinement of the
 // batched Hermitian eigensolve (the reductions live in band.hip).
-//  1. Lowest nb eigenvalues of T by multisection on Sturm counts; their
-//     eigenvectors by inverse iteration with a pivoted tridiagonal LU,
-//     re-orthonormalised as a block after each sweep.
+//  1. Lowest nb eigenvalues of T by multisection on Sturm counts; the
+//     eigenvectors of isolated ones by the twisted factorization, those of
+//     close clusters by inverse iteration with a pivoted tridiagonal LU and
+//     Gram-Schmidt within the cluster.
 //  2. FP64 Rayleigh-Ritz on span(Y) with the kept copy of C(k):
 //     eigenpairs of Y^H C Y, omega = sqrt(max(lambda, 0)).
 #include <float.h>
@@ -18,45 +19,13 @@ namespace mvpb {
 // 1. Tridiagonal eigenproblem: multisection for the lowest nb eigenvalues,
 //    inverse iteration for the eigenvectors.
 // ---------------------------------------------------------------------------
-// Number of eigenvalues of T strictly below x (signs of the LDL^T pivots).
-// The division uses the hardware reciprocal refined by one Newton step: a
-// few ulps of error per pivot keep the count backward stable.
+// Reciprocal for the LDL^T pivot recurrences: the hardware reciprocal refined
+// by one Newton step (a few ulps per pivot keep them backward stable).
 __device__ __forceinline__ double fast_rcp(double q) {
   double r = __builtin_amdgcn_rcp(q);
   r = fma(r, fma(-q, r, 1.0), r);
   return r;
 }
-__device__ __forceinline__ int sturm_count(const double *__restrict__ dd, const double *__restrict__ ee2, int n,
-                                           double x, double pivmin) {
-  int cnt = 0;
-  double q = dd[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += q < 0.0;
-  int k = 1;
-  for (; k + 3 < n; k += 4) {
-    const double d0 = dd[k], d1 = dd[k + 1], d2 = dd[k + 2], d3 = dd[k + 3];
-    const double e0 = ee2[k - 1], e1 = ee2[k], e2 = ee2[k + 1], e3 = ee2[k + 2];
-    q = (d0 - x) - e0 * fast_rcp(q);
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
-    q = (d1 - x) - e1 * fast_rcp(q);
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
-    q = (d2 - x) - e2 * fast_rcp(q);
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
-    q = (d3 - x) - e3 * fast_rcp(q);
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
-  }
-  for (; k < n; ++k) {
-    q = (dd[k] - x) - ee2[k - 1] * fast_rcp(q);
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
-  }
-  return cnt;
-}
-
 __device__ __forceinline__ double hash_uniform(unsigned a, unsigned b) {
   unsigned h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
   h ^= h >> 15;
@@ -105,61 +74,144 @@ MVPB_DEV void gershgorin(const double *dd, const double *ee, int n, double *red,
   __syncthreads();
 }
 
-// 1a. Eigenvalue j of T (ascending) by multisection: one workgroup per
-// (eigenvalue, item); every round evaluates BIS_THREADS Sturm counts in the
-// current interval and keeps the sub-interval holding eigenvalue j.
-constexpr int BIS_THREADS = 256;
-__global__ void __launch_bounds__(BIS_THREADS) tridiag_bisect(const EigItem *__restrict__ items) {
-  extern __shared__ double shd[];
-  __shared__ double red[3 * (BIS_THREADS / 64)];
-  __shared__ double xs[BIS_THREADS];
-  __shared__ int first_s[BIS_THREADS / 64];
-  __shared__ double lo_s, hi_s;
-  const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, j = blockIdx.x;
-  if (j >= it.nb) return;
-  double *dd = shd, *ee = dd + n, *ee2 = ee + n;
+// Number of eigenvalues of T below x without divisions: the signs of the
+// leading principal minors p_k = det(T_k - x I), from the three-term
+// recurrence p_{k+1} = (d_k - x) p_k - e_{k-1}^2 p_{k-1} (a Sturm sequence:
+// every change of sign between consecutive minors is one eigenvalue below
+// x).  Each step is one dependent FMA.  Every 8 steps both carried minors are
+// multiplied by the same power of two, which keeps the signs exactly; with
+// T scaled to |T| = O(1) a minor changes by at most 3^8 between rescalings.
+// A minor that is exactly zero counts as positive: the next minor,
+// -e^2 p_{k-1}, then supplies the one change of sign the zero stands for.
+// e2p[k] = e_{k-1}^2 (e2p[0] = 0).
+constexpr int SC_CHUNK = 8;
+__device__ __forceinline__ int sturm_count_minors(const double *__restrict__ dd, const double *__restrict__ e2p,
+                                                  int n, double x) {
+  double pp = 0.0, p = 1.0;
+  int cnt = 0, k = 0;
+  for (; k + SC_CHUNK <= n; k += SC_CHUNK) {
+    double dc[SC_CHUNK], ec[SC_CHUNK];
+#pragma unroll
+    for (int u = 0; u < SC_CHUNK; ++u) {
+      dc[u] = dd[k + u] - x;
+      ec[u] = e2p[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < SC_CHUNK; ++u) {
+      const double pn = fma(dc[u], p, -ec[u] * pp);
+      cnt += (pn < 0.0) != (p < 0.0);
+      pp = p;
+      p = pn;
+    }
+    int ex = 0;
+    (void)frexp(p, &ex);
+    p = ldexp(p, -ex);
+    pp = ldexp(pp, -ex);
+  }
+  for (; k < n; ++k) {
+    const double pn = fma(dd[k] - x, p, -e2p[k] * pp);
+    cnt += (pn < 0.0) != (p < 0.0);
+    pp = p;
+    p = pn;
+  }
+  return cnt;
+}
+
+// 1a. The lowest nb eigenvalues of T by multisection, one workgroup per item.
+// The first round spreads BISI_THREADS probes over the Gershgorin interval,
+// and every eigenvalue takes its bracket from their counts; later rounds deal
+// the probes out evenly over the eigenvalues whose bracket is still wider
+// than a few ulps of |T|.
+constexpr int BISI_THREADS = 512;
+__global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigItem *__restrict__ items) {
+  extern __shared__ double shd[];   // dd (n), ee (n), e2p (n + 1)
+  __shared__ double red[3 * (BISI_THREADS / 64)];
+  __shared__ double xs[BISI_THREADS];
+  __shared__ int cnt_s[BISI_THREADS];
+  __shared__ int first_s[BISI_THREADS / 64][RR_MAX_BANDS];
+  __shared__ double lo_s[RR_MAX_BANDS], hi_s[RR_MAX_BANDS];
+  __shared__ int act_s[RR_MAX_BANDS];
+  __shared__ int nact_s;
+  const EigItem it = items[blockIdx.x];
+  const int n = 2 * it.N, nb = it.nb;
+  double *dd = shd, *ee = dd + n, *e2p = ee + n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int r = tid; r < n; r += BIS_THREADS) {
+  for (int r = tid; r < n; r += BISI_THREADS) {
     dd[r] = it.d[r];
-    const double er = (r < n - 1) ? it.e[r] : 0.0;
-    ee[r] = er;
-    ee2[r] = er * er;
+    ee[r] = (r < n - 1) ? it.e[r] : 0.0;
   }
   __syncthreads();
   double gl, gu, emax2;
   gershgorin(dd, ee, n, red, gl, gu, emax2);
   const double bnorm = fmax(fabs(gl), fabs(gu));
-  const double pivmin = DBL_MIN * fmax(1.0, emax2);
-  gl -= 2.0 * DBL_EPSILON * bnorm * n + 2.0 * pivmin;
-  gu += 2.0 * DBL_EPSILON * bnorm * n + 2.0 * pivmin;
-  double lo = gl, hi = gu;
-  // a shift within a few ulps of |T| is all inverse iteration and the final
-  // Rayleigh-Ritz step need
-  const double tol_abs = 2.0 * DBL_EPSILON * bnorm + 4.0 * pivmin;
-  for (int round = 0; round < 16; ++round) {
-    if (hi - lo <= fmax(tol_abs, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
-    const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(BIS_THREADS + 1);
+  // exact power-of-two scale that brings |T| near 1
+  int sex = 0;
+  if (bnorm > 0.0) (void)frexp(bnorm, &sex);
+  for (int r = tid; r < n; r += BISI_THREADS) {
+    dd[r] = ldexp(dd[r], -sex);
+    const double er = ldexp(r > 0 ? ee[r - 1] : 0.0, -sex);
+    e2p[r] = er * er;
+  }
+  const double bn = ldexp(bnorm, -sex);
+  const double slack = 2.0 * DBL_EPSILON * bn * n;
+  const double glo = ldexp(gl, -sex) - slack, ghi = ldexp(gu, -sex) + slack;
+  const double tol_abs = 2.0 * DBL_EPSILON * bn;
+  __syncthreads();
+  // round 0: one set of probes for every eigenvalue
+  {
+    const double x = glo + (ghi - glo) * (double)(tid + 1) / (double)(BISI_THREADS + 1);
     xs[tid] = x;
-    const int cnt = sturm_count(dd, ee2, n, x, pivmin);
-    // first probe with more than j eigenvalues below it
-    const unsigned long long bal = __ballot(cnt > j);
-    if (lane == 0) first_s[w] = bal ? w * 64 + __builtin_ctzll(bal) : BIS_THREADS;
-    __syncthreads();
-    if (tid == 0) {
-      int g = BIS_THREADS;
-      for (int q = 0; q < BIS_THREADS / 64; ++q) g = min(g, first_s[q]);
-      const double nl = (g > 0) ? xs[g - 1] : lo;
-      const double nh = (g < BIS_THREADS) ? xs[g] : hi;
-      lo_s = nl;
-      hi_s = nh;
+    const int c = sturm_count_minors(dd, e2p, n, x);
+    for (int j = 0; j < nb; ++j) {
+      const unsigned long long bal = __ballot(c > j);
+      if (lane == 0) first_s[w][j] = bal ? w * 64 + __builtin_ctzll(bal) : BISI_THREADS;
     }
     __syncthreads();
-    lo = lo_s;
-    hi = hi_s;
+    if (tid < nb) {
+      int g = BISI_THREADS;
+      for (int q = 0; q < BISI_THREADS / 64; ++q) g = min(g, first_s[q][tid]);
+      lo_s[tid] = (g > 0) ? xs[g - 1] : glo;
+      hi_s[tid] = (g < BISI_THREADS) ? xs[g] : ghi;
+    }
     __syncthreads();
   }
-  if (tid == 0) it.lam_t[j] = 0.5 * (lo + hi);
+  for (int round = 0; round < 24; ++round) {
+    if (tid == 0) {
+      int na = 0;
+      for (int j = 0; j < nb; ++j) {
+        const double lo = lo_s[j], hi = hi_s[j];
+        if (hi - lo > fmax(tol_abs, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) act_s[na++] = j;
+      }
+      nact_s = na;
+    }
+    __syncthreads();
+    const int na = nact_s;
+    if (na == 0) break;
+    const int P = BISI_THREADS / na;   // probes per open eigenvalue (>= 8 for nb <= 64)
+    const int a = tid / P, pq = tid % P;
+    if (a < na) {
+      const int j = act_s[a];
+      const double lo = lo_s[j], hi = hi_s[j];
+      const double x = lo + (hi - lo) * (double)(pq + 1) / (double)(P + 1);
+      xs[tid] = x;
+      cnt_s[tid] = sturm_count_minors(dd, e2p, n, x);
+    }
+    __syncthreads();
+    if (tid < na) {
+      const int j = act_s[tid];
+      int g = P;
+      for (int q = 0; q < P; ++q)
+        if (cnt_s[tid * P + q] > j) {
+          g = q;
+          break;
+        }
+      const double lo = lo_s[j], hi = hi_s[j];
+      lo_s[j] = (g > 0) ? xs[tid * P + g - 1] : lo;
+      hi_s[j] = (g < P) ? xs[tid * P + g] : hi;
+    }
+    __syncthreads();
+  }
+  if (tid < nb) it.lam_t[tid] = ldexp(0.5 * (lo_s[tid] + hi_s[tid]), sex);
 }
 
 // Sequential kernels of inverse iteration (one lane).  The recurrences run in
@@ -339,6 +391,117 @@ MVPB_DEV void tri_solve(double *__restrict__ xv, int n, const double *__restrict
   for (; rr >= 0; --rr) bstep(rr, xv[rr], DU[rr], DU2[rr], DGi[rr]);
 }
 
+// Eigenvalues closer than CLUSTER_REL |T| to a neighbour form a cluster: their
+// eigenvectors come from inverse iteration with Gram-Schmidt (1b); isolated
+// ones from the twisted factorization (1c).
+constexpr double CLUSTER_REL = 1e-7;
+
+// 1c. Eigenvector of an isolated eigenvalue lam by the twisted factorization
+// of T - lam I: the pivots of the top-down (dp) and bottom-up (dm) LDL^T
+// factorizations, computed side by side by two lanes; the twist index r
+// minimising |gamma_r| = |dp_r + dm_r - (d_r - lam)|; then z_r = 1 and
+// z_i = -(e_i / dp_i) z_{i+1} above r, z_i = -(e_{i-1} / dm_i) z_{i-1} below,
+// again on two lanes (the ratios are formed by the whole wavefront first).
+// Isolated means a gap above CLUSTER_REL |T| to both neighbours, so the
+// vector's error, of order sqrt(n) eps |T| / gap, is far below what the
+// Rayleigh-Ritz step that follows needs.  One wavefront per eigenvalue.
+__global__ void __launch_bounds__(64) tridiag_twisted(const EigItem *__restrict__ items) {
+  extern __shared__ double shd[];   // dd, ee, dp, dm (n each)
+  __shared__ double red[3];
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N, nb = it.nb, j = blockIdx.x;
+  if (j >= nb) return;
+  const int lane = threadIdx.x;
+  double *dd = shd, *ee = dd + n, *dp = ee + n, *dm = dp + n;
+  for (int r = lane; r < n; r += 64) {
+    dd[r] = it.d[r];
+    ee[r] = (r < n - 1) ? it.e[r] : 0.0;
+  }
+  __syncthreads();
+  double gl, gu, emax2;
+  gershgorin(dd, ee, n, red, gl, gu, emax2);
+  const double bnorm = fmax(fabs(gl), fabs(gu));
+  const double thr = CLUSTER_REL * bnorm;
+  const double *lam = it.lam_t;
+  const double lj = lam[j];
+  if ((j > 0 && lj - lam[j - 1] <= thr) || (j + 1 < nb && lam[j + 1] - lj <= thr)) return;   // cluster member
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  if (lane == 0) {
+    double q = dd[0] - lj;
+    if (fabs(q) < pivmin) q = -pivmin;
+    dp[0] = q;
+    for (int i = 1; i < n; ++i) {
+      const double e = ee[i - 1];
+      q = (dd[i] - lj) - e * e * fast_rcp(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      dp[i] = q;
+    }
+  } else if (lane == 1) {
+    double q = dd[n - 1] - lj;
+    if (fabs(q) < pivmin) q = -pivmin;
+    dm[n - 1] = q;
+    for (int i = n - 2; i >= 0; --i) {
+      const double e = ee[i];
+      q = (dd[i] - lj) - e * e * fast_rcp(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      dm[i] = q;
+    }
+  }
+  __syncthreads();
+  // twist index: smallest |gamma|, lowest index on ties
+  double gbest = DBL_MAX;
+  int rbest = 0;
+  for (int i = lane; i < n; i += 64) {
+    const double g = fabs(dp[i] + dm[i] - (dd[i] - lj));
+    if (g < gbest) {
+      gbest = g;
+      rbest = i;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double go = __shfl_xor(gbest, o, 64);
+    const int ro = __shfl_xor(rbest, o, 64);
+    if (go < gbest || (go == gbest && ro < rbest)) {
+      gbest = go;
+      rbest = ro;
+    }
+  }
+  const int r = rbest;
+  // ratios in place: dp[i] <- -e_i / dp_i (i < r), dm[i] <- -e_{i-1} / dm_i (i > r)
+  for (int i = lane; i < n; i += 64) {
+    if (i < r) dp[i] = -ee[i] / dp[i];
+    if (i > r) dm[i] = -ee[i - 1] / dm[i];
+  }
+  __syncthreads();
+  if (lane == 0) {
+    double z = 1.0;
+    for (int i = r - 1; i >= 0; --i) {
+      z *= dp[i];
+      dp[i] = z;
+    }
+  } else if (lane == 1) {
+    double z = 1.0;
+    for (int i = r + 1; i < n; ++i) {
+      z *= dm[i];
+      dm[i] = z;
+    }
+  }
+  __syncthreads();
+  double s2 = 0.0;
+  for (int i = lane; i < n; i += 64) {
+    const double z = i < r ? dp[i] : (i > r ? dm[i] : 1.0);
+    s2 = fma(z, z, s2);
+  }
+  s2 = wave_sum(s2);
+  const double inv = 1.0 / sqrt(s2);
+  double *X = it.X;
+  for (int i = lane; i < n; i += 64) {
+    const double z = i < r ? dp[i] : (i > r ? dm[i] : 1.0);
+    gst(X, (size_t)i * nb + j, z * inv);
+  }
+}
+
 // 1b. Eigenvectors of T by inverse iteration with a pivoted LU of T - lam I
 // (two solves from a pseudo-random start).  One wavefront per eigenvalue;
 // lane 0 runs the sequential factorisation and solves, the wavefront the
@@ -366,11 +529,12 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
   double gl, gu, emax2;
   gershgorin(dd, ee, n, red, gl, gu, emax2);
   const double bnorm = fmax(fabs(gl), fabs(gu));
-  const double thr = 1e-9 * bnorm;
+  const double thr = CLUSTER_REL * bnorm;
   const double *lam = it.lam_t;
   if (j0 > 0 && lam[j0] - lam[j0 - 1] <= thr) return;   // not the first member of its cluster
   int j1 = j0 + 1;
   while (j1 < nb && lam[j1] - lam[j1 - 1] <= thr) ++j1;
+  if (j1 == j0 + 1) return;                              // isolated: twisted factorization
   const double pert = fmax(DBL_EPSILON * bnorm, 1e-280);
   double *X = it.X;
   for (int jm = j0; jm < j1; ++jm) {
@@ -414,7 +578,9 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
 
 hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st) {
   ProfScope ps(K_TRIDIAG, st);
-  hipLaunchKernelGGL(tridiag_bisect, dim3(nb, n_items), dim3(BIS_THREADS), sizeof(double) * 3 * n_max, st, items);
+  hipLaunchKernelGGL(tridiag_bisect_item, dim3(n_items), dim3(BISI_THREADS), sizeof(double) * (3 * n_max + 1), st,
+                     items);
+  hipLaunchKernelGGL(tridiag_twisted, dim3(nb, n_items), dim3(64), sizeof(double) * 4 * n_max, st, items);
   if (n_max <= INV_LDS_MAX_N)
     hipLaunchKernelGGL(tridiag_invit<true>, dim3(nb, n_items), dim3(64), sizeof(double) * 8 * n_max, st, items);
   else
@@ -724,8 +890,11 @@ hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, in
 
 // Dynamic LDS above the default limit has to be opted into per kernel.
 hipError_t init_kernel_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void *)tridiag_bisect, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(sizeof(double) * 3 * MAX_N));
+  hipError_t e = hipFuncSetAttribute((const void *)tridiag_bisect_item, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(sizeof(double) * (3 * MAX_N + 1)));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)tridiag_twisted, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(double) * 4 * MAX_N));
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)tridiag_invit<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(sizeof(double) * 8 * INV_LDS_MAX_N));
