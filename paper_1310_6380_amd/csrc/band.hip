@@ -31,8 +31,7 @@
 
 namespace mvpb {
 
-constexpr int PQ_THREADS = 512;
-constexpr int PQ_WAVES = PQ_THREADS / 64;
+constexpr int PQ_THREADS = 512;       // workgroup of the panel factorization
 constexpr int HB_LDB = 2 * HB + 1;   // stored subdiagonals of the band copy (0 .. 2 HB)
 constexpr int BT_THREADS = 512;
 
@@ -40,7 +39,7 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
 constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
 
 // Sum D doubles (D a power of two, D <= 128) over the 64 lanes of a
-// wavefront by halving exchanges.  Afterwards, for D <= 64, v[0] of lane l
+// wavefront by halving exchanges over the butterfly stages of xchg.  Afterwards, for D <= 64, v[0] of lane l
 // holds the total of value (l >> (6 - log2 D)); for D = 128, v[k] holds the
 // total of value 2 l + k.
 template <int D, int S>
@@ -55,10 +54,10 @@ MVPB_DEV void wave_reduce_step(double *v, int lane) {
       for (int k = 0; k < h; ++k) {
         const double snd = hi ? v[k] : v[k + h];
         const double keep = hi ? v[k + h] : v[k];
-        v[k] = keep + __shfl_xor(snd, o, 64);
+        v[k] = keep + xchg<S>(snd);
       }
     } else {
-      v[0] += __shfl_xor(v[0], o, 64);
+      v[0] += xchg<S>(v[0]);
     }
     wave_reduce_step<D, S + 1>(v, lane);
   }
@@ -132,15 +131,15 @@ MVPB_DEV cx<R> ld_or0(const cx<R> *p, size_t idx, bool ok) {
 
 // ---------------------------------------------------------------------------
 // Stage 1a.  Panel QR.  Panel p covers columns c0 = p HB .. c0+HB-1; its rows
-// below the band are local rows r = 0 .. m-1 (global c0+HB+r).  Thread t
-// holds rows t, t+PQ_THREADS, ... (RPT of them) of SW = HB/RPT columns at a
+// below the band are local rows r = 0 .. m-1 (global c0+HB+r).  Thread t of
+// NT holds rows t, t+NT, ... (RPT of them) of SW = HB/RPT columns at a
 // time (a sub-panel); with RPT > 1 the panel is factored in HB/SW sub-panels and the
 // later columns are updated by each sub-panel's block reflector.
 // Output: V (unit lower trapezoidal, strictly below its diagonal) and R (on
 // and above) in place, T (upper, kq x kq) in T1[p].
 // ---------------------------------------------------------------------------
-template <typename R, int RPT>
-__global__ void __launch_bounds__(PQ_THREADS) __attribute__((amdgpu_waves_per_eu(1, 2)))
+template <typename R, int RPT, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
 he2hb_panel(const EigItem *__restrict__ items, int p) {
   typedef cx<R> C;
   constexpr int SW = HB / RPT;                 // sub-panel width held in registers
@@ -150,28 +149,30 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
   constexpr int DMAX = DC > DX ? DC : DX;
   static_assert(DMAX <= 64, "reduction too large");
   __shared__ C rowj[2][SW];
-  __shared__ double scratch[PQ_WAVES * DMAX];
+  __shared__ double scratch[(NT / 64) * DMAX];
   __shared__ double sums[DMAX];
   __shared__ C Tm[HB][HB + 1];
   __shared__ C Sx[HB][SW];    // Sx[o][t]: o < nrem: (V_s^H B)[t][o]; o >= nrem: (V_prev^H V_s)[o - nrem][t]
   __shared__ C Sb[SW][HB];    // T_s^H V_s^H B
   __shared__ C M1[HB][SW];    // (V_prev^H V_s) T_s
+  __shared__ C Ub[SW][SW + 1];   // u of each column of the sub-panel
+  __shared__ C taus[SW];
   const EigItem it = items[blockIdx.x];
   const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
-  // this launch handles the items whose panel height is in (RPT/2, RPT] x PQ_THREADS
-  if (m <= (RPT / 2) * PQ_THREADS || m > RPT * PQ_THREADS) return;
+  // this launch handles the items whose panel height is in (RPT/2, RPT] x NT
+  if (m <= (RPT / 2) * NT || m > RPT * NT) return;
   const int kq = min(m, HB);
   const size_t ld = (size_t)n;
   C *__restrict__ P = (C *)it.A + (size_t)c0 * ld + (c0 + HB);
   const int tid = threadIdx.x;
-  for (int e = tid; e < HB * (HB + 1); e += PQ_THREADS) (&Tm[0][0])[e] = czero<R>();
+  for (int e = tid; e < HB * (HB + 1); e += NT) (&Tm[0][0])[e] = czero<R>();
   __syncthreads();
 
   C x[RPT][SW];
   for (int cs = 0; cs < kq; cs += SW) {
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
-      const int r = tid + PQ_THREADS * s;
+      const int r = tid + NT * s;
 #pragma unroll
       for (int t = 0; t < SW; ++t)
         x[s][t] = ld_or0<R>(P, (size_t)(cs + t) * ld + r, r < m && cs + t < HB);
@@ -195,7 +196,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
         for (int q = 0; q < DC; ++q) acc[q] = 0.0;
 #pragma unroll
         for (int s = 0; s < RPT; ++s) {
-          const int r = tid + PQ_THREADS * s;
+          const int r = tid + NT * s;
           if (r > j && r < m) {
             const C xj = x[s][0];
             acc[0] += (double)(xj.re * xj.re + xj.im * xj.im);
@@ -207,7 +208,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
             }
           }
         }
-        block_reduce_vec<DC, PQ_WAVES>(acc, scratch, sums);
+        block_reduce_vec<DC, (NT / 64)>(acc, scratch, sums);
         const C *rj = rowj[jj & 1];
         const C alpha = rj[0];
         double beta;
@@ -223,7 +224,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
         }
 #pragma unroll
         for (int s = 0; s < RPT; ++s) {
-          const int r = tid + PQ_THREADS * s;
+          const int r = tid + NT * s;
           if (r < m && r >= j) {
             const bool diag = (r == j);
             const C vr = diag ? mkc<R>(R(1), R(0)) : x[s][0] * scale;
@@ -234,19 +235,14 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
             x[s][0] = diag ? mkc<R>((R)beta, R(0)) : vr;
           }
         }
-        // T of the sub-panel, column jj: T_s[0:jj, jj] = -tau T_s[0:jj,0:jj] u,
-        // u_l = v_l^H v_j = conj(V[j][l]) + scale g_l  (column cs+l at position nfw+l)
+        // for T of the sub-panel (formed after its last column):
+        // u_l = v_l^H v_j = conj(V[j][l]) + scale g_l (column cs+l at position nfw+l)
         if (tid < jj) {
-          C a = czero<R>();
-          for (int l = tid; l < jj; ++l) {
-            const int q = nfw + l;
-            const C g = mkc<R>((R)sums[2 * q], (R)sums[2 * q + 1]);
-            const C u = conj(rj[q]) + scale * g;
-            a = cfma(Tm[cs + tid][cs + l], u, a);
-          }
-          Tm[cs + tid][j] = czero<R>() - tau * a;
+          const int q = nfw + tid;
+          const C g = mkc<R>((R)sums[2 * q], (R)sums[2 * q + 1]);
+          Ub[tid][jj] = conj(rj[q]) + scale * g;
         }
-        if (tid == 0) Tm[j][j] = tau;
+        if (tid == 0) taus[jj] = tau;
       }
       // rotate by one column (also for skipped steps, to restore the order)
 #pragma unroll
@@ -257,10 +253,23 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
         x[s][SW - 1] = first;
       }
     }
+    // ---- T of the sub-panel: T_s[0:jj, jj] = -tau_jj T_s[0:jj, 0:jj] u_jj,
+    // column by column (off the per-column critical path)
+    __syncthreads();
+    const int swe = min(SW, kq - cs);
+    for (int jj = 0; jj < swe; ++jj) {
+      if (tid < jj) {
+        C a = czero<R>();
+        for (int l = tid; l < jj; ++l) a = cfma(Tm[cs + tid][cs + l], Ub[l][jj], a);
+        Tm[cs + tid][cs + jj] = czero<R>() - taus[jj] * a;
+      }
+      if (tid == 0) Tm[cs + jj][cs + jj] = taus[jj];
+      __syncthreads();
+    }
     // ---- write the sub-panel back
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
-      const int r = tid + PQ_THREADS * s;
+      const int r = tid + NT * s;
       if (r < m) {
 #pragma unroll
         for (int t = 0; t < SW; ++t)
@@ -277,7 +286,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
         for (int t = 0; t < DX; ++t) acc[t] = 0.0;
 #pragma unroll
         for (int s = 0; s < RPT; ++s) {
-          const int r = tid + PQ_THREADS * s;
+          const int r = tid + NT * s;
           if (r < m && r >= cs) {
 #pragma unroll
             for (int u = 0; u < CW; ++u) {
@@ -298,21 +307,21 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
             }
           }
         }
-        block_reduce_vec<DX, PQ_WAVES>(acc, scratch, sums);
-        for (int e = tid; e < CW * SW; e += PQ_THREADS) {
+        block_reduce_vec<DX, (NT / 64)>(acc, scratch, sums);
+        for (int e = tid; e < CW * SW; e += NT) {
           const int u = e / SW, t = e % SW;
           if (o0 + u < nother) Sx[o0 + u][t] = mkc<R>((R)sums[2 * e], (R)sums[2 * e + 1]);
         }
       }
       __syncthreads();
       // Sb = T_s^H (V_s^H B);  M1 = (V_prev^H V_s) T_s
-      for (int e = tid; e < SW * nrem; e += PQ_THREADS) {
+      for (int e = tid; e < SW * nrem; e += NT) {
         const int t = e / nrem, u = e % nrem;
         C a = czero<R>();
         for (int l = 0; l <= t; ++l) a = cfma(conj(Tm[cs + l][cs + t]), Sx[u][l], a);
         Sb[t][u] = a;
       }
-      for (int e = tid; e < cs * SW; e += PQ_THREADS) {
+      for (int e = tid; e < cs * SW; e += NT) {
         const int q = e / SW, t = e % SW;
         C a = czero<R>();
         for (int l = 0; l <= t; ++l) a = cfma(Sx[nrem + q][l], Tm[cs + l][cs + t], a);
@@ -320,7 +329,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
       }
       __syncthreads();
       // T[0:cs, cs:cs+SW] = -T[0:cs, 0:cs] M1
-      for (int e = tid; e < cs * SW; e += PQ_THREADS) {
+      for (int e = tid; e < cs * SW; e += NT) {
         const int q = e / SW, t = e % SW;
         C a = czero<R>();
         for (int l = q; l < cs; ++l) a = cfma(Tm[q][l], M1[l][t], a);
@@ -329,7 +338,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
       // B <- B - V_s Sb  (rows >= cs)
 #pragma unroll
       for (int s = 0; s < RPT; ++s) {
-        const int r = tid + PQ_THREADS * s;
+        const int r = tid + NT * s;
         if (r < m && r >= cs) {
           for (int u = 0; u < nrem; ++u) {
             const size_t bi = (size_t)(cs + SW + u) * ld + r;
@@ -349,7 +358,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
   // T of the panel (kq x kq, zero-padded to HB x HB), column-major
   C *T1 = (C *)it.T1 + (size_t)p * HB * HB;
   __syncthreads();
-  for (int e = tid; e < HB * HB; e += PQ_THREADS) {
+  for (int e = tid; e < HB * HB; e += NT) {
     const int i = e % HB, jx = e / HB;
     gst(T1, e, (i < kq && jx < kq && i <= jx) ? Tm[i][jx] : czero<R>());
   }
@@ -711,10 +720,6 @@ MVPB_DEV cx<R> shfl_c(cx<R> v, int src) {
   return mkc<R>(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
 }
 template <typename R>
-MVPB_DEV cx<R> shfl_xor_c(cx<R> v, int o) {
-  return mkc<R>(__shfl_xor(v.re, o, 64), __shfl_xor(v.im, o, 64));
-}
-template <typename R>
 MVPB_DEV cx<R> readlane_c(cx<R> v, int lane);
 template <>
 MVPB_DEV cx<double> readlane_c(cx<double> v, int lane) {
@@ -960,8 +965,8 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
         C yv = czero<R>();
 #pragma unroll
         for (int t = 0; t < 4; ++t) yv = cfma(y[t], vp[t], yv);
-        yv = yv + shfl_xor_c(yv, 16);
-        yv = yv + shfl_xor_c(yv, 32);
+        yv = yv + xchg_c<1>(yv);
+        yv = yv + xchg_c<0>(yv);
         const C ty = tauprev * yv;
 #pragma unroll
         for (int t = 0; t < 4; ++t) y[t] = y[t] - ty * conj(vp[t]);
@@ -1007,8 +1012,8 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
         C w0 = czero<R>();
 #pragma unroll
         for (int t = 0; t < 4; ++t) w0 = cfma(dq[t], vc[t], w0);
-        w0 = w0 + shfl_xor_c(w0, 16);
-        w0 = w0 + shfl_xor_c(w0, 32);
+        w0 = w0 + xchg_c<1>(w0);
+        w0 = w0 + xchg_c<0>(w0);
         double vw = (double)(vq.re * w0.re + vq.im * w0.im);   // Re(conj(v_q) w0_q)
         vw = row16_sum(vw);
         const R a2 = (R)(-0.5 * (double)abs2(tau) * vw);
@@ -1317,10 +1322,14 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_s1(const EigItem *__
           if (c < ncl) acc[c] = cfma_cj(v, zr[c], acc[c]);
       }
     }
+    static_assert(RG == 32, "the row-phase sum spans the 32 lanes of a half wavefront");
 #pragma unroll
-    for (int o = 1; o < RG; o <<= 1) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] = acc[c] + shfl_xor_c(acc[c], o);
+    for (int c = 0; c < 8; ++c) {
+      acc[c] = acc[c] + xchg_c<1>(acc[c]);
+      acc[c] = acc[c] + xchg_c<2>(acc[c]);
+      acc[c] = acc[c] + xchg_c<3>(acc[c]);
+      acc[c] = acc[c] + xchg_c<4>(acc[c]);
+      acc[c] = acc[c] + xchg_c<5>(acc[c]);
     }
     if (rg == 0) {
 #pragma unroll
@@ -1373,11 +1382,15 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_s1(const EigItem *__
 // item's own panel height, so an item's arithmetic does not depend on the
 // other items of the launch: one launch per height class present, and the
 // items of the other classes return at once.
-template <typename R, int RPT>
+// Panel height classes (lo, hi]: the register blocking RPT and the workgroup
+// size NT with lo = (RPT/2) NT and hi = RPT NT.  Every wavefront repeats the
+// per-column reductions, but a smaller workgroup needs sub-panels (RPT > 1)
+// whose cross updates cost more: 512 threads measured fastest throughout.
+template <typename R, int RPT, int NT>
 static void launch_panel_class(const EigItem *items, int n_items, int p, int m_lo, int m_hi, hipStream_t st) {
-  const int lo = (RPT / 2) * PQ_THREADS, hi = RPT * PQ_THREADS;   // class: lo < m <= hi
+  const int lo = (RPT / 2) * NT, hi = RPT * NT;   // class: lo < m <= hi
   if (m_hi <= lo || m_lo > hi) return;
-  hipLaunchKernelGGL((he2hb_panel<R, RPT>), dim3(n_items), dim3(PQ_THREADS), 0, st, items, p);
+  hipLaunchKernelGGL((he2hb_panel<R, RPT, NT>), dim3(n_items), dim3(NT), 0, st, items, p);
 }
 
 // Compute units of the current device (cached per device).
@@ -1422,10 +1435,10 @@ static hipError_t launch_stage1_t(const ItemPart *parts, int n_parts) {
       const int m_lo = std::max(1, pt.n_min - c0 - HB);
       {
         ProfScope ps(K_PANEL, st);
-        launch_panel_class<R, 1>(items, n_items, p, m_lo, m, st);
-        launch_panel_class<R, 2>(items, n_items, p, m_lo, m, st);
-        launch_panel_class<R, 4>(items, n_items, p, m_lo, m, st);
-        launch_panel_class<R, 8>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 1, PQ_THREADS>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 2, PQ_THREADS>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 4, PQ_THREADS>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 8, PQ_THREADS>(items, n_items, p, m_lo, m, st);
       }
       const int nrb = (m + 63) / 64;
       {

@@ -67,18 +67,58 @@ template <typename To, typename From>
 MVPB_HD cx<To> ccast(cx<From> a) { return mkc<To>((To)a.re, (To)a.im); }
 
 // ---------------------------------------------------------------------------
+// Cross-lane exchanges of a 64-wide wavefront without LDS.  Stage S of the
+// butterfly pairs every lane with one partner: S = 0: lane ^ 32 and S = 1:
+// lane ^ 16 (gfx950 lane-swap instructions); S = 2: mirror within 16 lanes;
+// S = 3: mirror within 8; S = 4: lane ^ 2; S = 5: lane ^ 1 (DPP).  The
+// partners of stage S agree in every lane-id bit above bit 5 - S, and the
+// lane with that bit set is the upper one, so a halving reduction over these
+// stages leaves the same values in the same lanes as one over lane ^ (32 >> S).
+// ---------------------------------------------------------------------------
+template <int S>
+MVPB_DEV unsigned xchg_u32(unsigned v) {
+  if constexpr (S == 0) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (__lane_id() & 32) ? r[0] : r[1];
+  } else if constexpr (S == 1) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (__lane_id() & 16) ? r[0] : r[1];
+  } else {
+    constexpr int ctrl = S == 2 ? 0x140 : S == 3 ? 0x141 : S == 4 ? 0x4E : 0xB1;
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, false);
+  }
+}
+template <int S>
+MVPB_DEV double xchg(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = xchg_u32<S>((unsigned)b), hi = xchg_u32<S>((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int S>
+MVPB_DEV float xchg(float v) {
+  return __uint_as_float(xchg_u32<S>(__float_as_uint(v)));
+}
+// Partner value of stage S for a complex number.
+template <int S, typename R>
+MVPB_DEV cx<R> xchg_c(cx<R> v) {
+  return mkc<R>(xchg<S>(v.re), xchg<S>(v.im));
+}
+
+// ---------------------------------------------------------------------------
 // Wavefront / block reductions (64-wide wavefronts).
 // ---------------------------------------------------------------------------
-MVPB_DEV double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+template <typename T>
+MVPB_DEV T wave_sum_fast(T v) {
+  v += xchg<0>(v);
+  v += xchg<1>(v);
+  v += xchg<2>(v);
+  v += xchg<3>(v);
+  v += xchg<4>(v);
+  v += xchg<5>(v);
   return v;
 }
-MVPB_DEV float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+MVPB_DEV double wave_sum(double v) { return wave_sum_fast(v); }
+MVPB_DEV float wave_sum(float v) { return wave_sum_fast(v); }
 MVPB_DEV int wave_sum_i(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -117,12 +117,14 @@ __device__ __forceinline__ int sturm_count_minors(const double *__restrict__ dd,
   return cnt;
 }
 
-// 1a. The lowest nb eigenvalues of T by multisection, one workgroup per item.
-// The first round spreads BISI_THREADS probes over the Gershgorin interval,
-// and every eigenvalue takes its bracket from their counts; later rounds deal
-// the probes out evenly over the eigenvalues whose bracket is still wider
-// than a few ulps of |T|.
+// 1a. The lowest nb eigenvalues of T by multisection.  BISI_GROUPS
+// workgroups per item, workgroup g bracketing eigenvalues g, g + BISI_GROUPS,
+// ...  The first round spreads BISI_THREADS probes over the Gershgorin
+// interval, and every eigenvalue takes its bracket from their counts; later
+// rounds deal the probes out evenly over the eigenvalues whose bracket is
+// still wider than a few ulps of |T|.
 constexpr int BISI_THREADS = 512;
+constexpr int BISI_GROUPS = 4;
 __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigItem *__restrict__ items) {
   extern __shared__ double shd[];   // dd (n), ee (n), e2p (n + 1)
   __shared__ double red[3 * (BISI_THREADS / 64)];
@@ -132,8 +134,10 @@ __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigIte
   __shared__ double lo_s[RR_MAX_BANDS], hi_s[RR_MAX_BANDS];
   __shared__ int act_s[RR_MAX_BANDS];
   __shared__ int nact_s;
-  const EigItem it = items[blockIdx.x];
-  const int n = 2 * it.N, nb = it.nb;
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N, nb_all = it.nb, g0 = blockIdx.x;
+  if (g0 >= nb_all) return;
+  const int nb = (nb_all - g0 + BISI_GROUPS - 1) / BISI_GROUPS;   // eigenvalues of this workgroup
   double *dd = shd, *ee = dd + n, *e2p = ee + n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int r = tid; r < n; r += BISI_THREADS) {
@@ -163,7 +167,7 @@ __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigIte
     xs[tid] = x;
     const int c = sturm_count_minors(dd, e2p, n, x);
     for (int j = 0; j < nb; ++j) {
-      const unsigned long long bal = __ballot(c > j);
+      const unsigned long long bal = __ballot(c > g0 + BISI_GROUPS * j);
       if (lane == 0) first_s[w][j] = bal ? w * 64 + __builtin_ctzll(bal) : BISI_THREADS;
     }
     __syncthreads();
@@ -199,9 +203,10 @@ __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigIte
     __syncthreads();
     if (tid < na) {
       const int j = act_s[tid];
+      const int jg = g0 + BISI_GROUPS * j;   // index among all eigenvalues
       int g = P;
       for (int q = 0; q < P; ++q)
-        if (cnt_s[tid * P + q] > j) {
+        if (cnt_s[tid * P + q] > jg) {
           g = q;
           break;
         }
@@ -211,7 +216,7 @@ __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigIte
     }
     __syncthreads();
   }
-  if (tid < nb) it.lam_t[tid] = ldexp(0.5 * (lo_s[tid] + hi_s[tid]), sex);
+  if (tid < nb) it.lam_t[g0 + BISI_GROUPS * tid] = ldexp(0.5 * (lo_s[tid] + hi_s[tid]), sex);
 }
 
 // Sequential kernels of inverse iteration (one lane).  The recurrences run in
@@ -394,7 +399,7 @@ MVPB_DEV void tri_solve(double *__restrict__ xv, int n, const double *__restrict
 // Eigenvalues closer than CLUSTER_REL |T| to a neighbour form a cluster: their
 // eigenvectors come from inverse iteration with Gram-Schmidt (1b); isolated
 // ones from the twisted factorization (1c).
-constexpr double CLUSTER_REL = 1e-7;
+constexpr double CLUSTER_REL = 1e-9;
 
 // 1c. Eigenvector of an isolated eigenvalue lam by the twisted factorization
 // of T - lam I: the pivots of the top-down (dp) and bottom-up (dm) LDL^T
@@ -402,9 +407,12 @@ constexpr double CLUSTER_REL = 1e-7;
 // minimising |gamma_r| = |dp_r + dm_r - (d_r - lam)|; then z_r = 1 and
 // z_i = -(e_i / dp_i) z_{i+1} above r, z_i = -(e_{i-1} / dm_i) z_{i-1} below,
 // again on two lanes (the ratios are formed by the whole wavefront first).
-// Isolated means a gap above CLUSTER_REL |T| to both neighbours, so the
-// vector's error, of order sqrt(n) eps |T| / gap, is far below what the
-// Rayleigh-Ritz step that follows needs.  One wavefront per eigenvalue.
+// Isolated means a gap above CLUSTER_REL |T| to both neighbours: the vector's
+// residual is of order sqrt(n) eps |T|, and the Rayleigh-Ritz step that
+// follows turns it into an eigenvalue error of order residual^2 / gap.  One
+// wavefront per eigenvalue; lane 0 runs the top-down and lane 1 the bottom-up
+// recurrences in one instruction stream (no divergent branches), their
+// operands loaded a chunk ahead.
 __global__ void __launch_bounds__(64) tridiag_twisted(const EigItem *__restrict__ items) {
   extern __shared__ double shd[];   // dd, ee, dp, dm (n each)
   __shared__ double red[3];
@@ -426,25 +434,42 @@ __global__ void __launch_bounds__(64) tridiag_twisted(const EigItem *__restrict_
   const double lj = lam[j];
   if ((j > 0 && lj - lam[j - 1] <= thr) || (j + 1 < nb && lam[j + 1] - lj <= thr)) return;   // cluster member
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
-  if (lane == 0) {
-    double q = dd[0] - lj;
+  // lane 0: dp_i = (d_i - lam) - e_{i-1}^2 / dp_{i-1}, i = 0 .. n-1;
+  // lane 1: dm_i = (d_i - lam) - e_i^2 / dm_{i+1}, i = n-1 .. 0
+  if (lane < 2) {
+    const bool fw = lane == 0;
+    double *dst = fw ? dp : dm;
+    const int step = fw ? 1 : -1;
+    int i = fw ? 0 : n - 1;
+    // e index of step t: fw: i - 1, bw: i (zero where absent)
+    double q = dd[i] - lj;
     if (fabs(q) < pivmin) q = -pivmin;
-    dp[0] = q;
-    for (int i = 1; i < n; ++i) {
-      const double e = ee[i - 1];
-      q = (dd[i] - lj) - e * e * fast_rcp(q);
-      if (fabs(q) < pivmin) q = -pivmin;
-      dp[i] = q;
+    dst[i] = q;
+    int t = 1;
+    constexpr int CH = 8;
+    for (; t + CH <= n; t += CH) {
+      double dc[CH], ec[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int ii = i + step * (u + 1);
+        dc[u] = dd[ii] - lj;
+        const double e = ee[fw ? ii - 1 : ii];
+        ec[u] = e * e;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        q = dc[u] - ec[u] * fast_rcp(q);
+        if (fabs(q) < pivmin) q = -pivmin;
+        dst[i + step * (u + 1)] = q;
+      }
+      i += step * CH;
     }
-  } else if (lane == 1) {
-    double q = dd[n - 1] - lj;
-    if (fabs(q) < pivmin) q = -pivmin;
-    dm[n - 1] = q;
-    for (int i = n - 2; i >= 0; --i) {
-      const double e = ee[i];
+    for (; t < n; ++t) {
+      i += step;
+      const double e = ee[fw ? i - 1 : i];
       q = (dd[i] - lj) - e * e * fast_rcp(q);
       if (fabs(q) < pivmin) q = -pivmin;
-      dm[i] = q;
+      dst[i] = q;
     }
   }
   __syncthreads();
@@ -474,17 +499,18 @@ __global__ void __launch_bounds__(64) tridiag_twisted(const EigItem *__restrict_
     if (i > r) dm[i] = -ee[i - 1] / dm[i];
   }
   __syncthreads();
-  if (lane == 0) {
+  // z above r (lane 0, in dp) and below r (lane 1, in dm): products of the ratios
+  if (lane < 2) {
+    const bool up = lane == 0;
+    double *buf = up ? dp : dm;
+    const int step = up ? -1 : 1;
+    const int len = up ? r : n - 1 - r;
     double z = 1.0;
-    for (int i = r - 1; i >= 0; --i) {
-      z *= dp[i];
-      dp[i] = z;
-    }
-  } else if (lane == 1) {
-    double z = 1.0;
-    for (int i = r + 1; i < n; ++i) {
-      z *= dm[i];
-      dm[i] = z;
+    int i = r;
+    for (int t = 0; t < len; ++t) {
+      i += step;
+      z *= buf[i];
+      buf[i] = z;
     }
   }
   __syncthreads();
@@ -578,8 +604,8 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
 
 hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st) {
   ProfScope ps(K_TRIDIAG, st);
-  hipLaunchKernelGGL(tridiag_bisect_item, dim3(n_items), dim3(BISI_THREADS), sizeof(double) * (3 * n_max + 1), st,
-                     items);
+  hipLaunchKernelGGL(tridiag_bisect_item, dim3(BISI_GROUPS, n_items), dim3(BISI_THREADS),
+                     sizeof(double) * (3 * n_max + 1), st, items);
   hipLaunchKernelGGL(tridiag_twisted, dim3(nb, n_items), dim3(64), sizeof(double) * 4 * n_max, st, items);
   if (n_max <= INV_LDS_MAX_N)
     hipLaunchKernelGGL(tridiag_invit<true>, dim3(nb, n_items), dim3(64), sizeof(double) * 8 * n_max, st, items);
