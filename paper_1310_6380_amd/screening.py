@@ -50,9 +50,35 @@ def label_cells(ctx: mvpb.Context, cells: np.ndarray, chunk: int = 512, precisio
     return out
 
 
-def train(net: mvpb.Surrogate, cells, labels, epochs=20, batch=256, lr=1e-3, seed=0, log=None):
+class Normalizer:
+    """Per-output standardisation of the 400 band targets (the network learns
+    (y - mean) / std, whose outputs all have unit scale)."""
+
+    def __init__(self, labels):
+        y = np.asarray(labels, dtype=np.float64)
+        self.mean = y.mean(axis=0).astype(np.float32)
+        self.std = (y.std(axis=0) + 1e-3).astype(np.float32)
+
+    def encode(self, y):
+        return ((np.asarray(y, dtype=np.float32) - self.mean) / self.std).astype(np.float32)
+
+    def decode(self, z):
+        return (np.asarray(z, dtype=np.float32) * self.std + self.mean).astype(np.float32)
+
+
+def predict(net: mvpb.Surrogate, cells, norm: Normalizer = None, chunk: int = 4096):
+    """Normalised bands [n, 400] predicted by the network."""
+    out = np.concatenate([net.infer(cells[i:i + chunk]) for i in range(0, cells.shape[0], chunk)])
+    return norm.decode(out) if norm is not None else out
+
+
+def train(net: mvpb.Surrogate, cells, labels, epochs=20, batch=256, lr=1e-3, seed=0, log=None,
+          norm: Normalizer = None):
     """Adam on shuffled mini-batches; every batch is shifted by a random
-    circular translation (the bands of a periodic cell are invariant to it)."""
+    circular translation (the bands of a periodic cell are invariant to it).
+    With norm the network is fitted to the standardised targets."""
+    if norm is not None:
+        labels = norm.encode(labels)
     rng = np.random.default_rng(seed)
     n = cells.shape[0]
     losses = []
@@ -102,7 +128,8 @@ def mutate(cells, rng, flips=24):
     return out
 
 
-def screen(ctx, net, population, b, rounds=3, n_candidates=4096, top_k=16, tol=0.05, seed=0, log=None):
+def screen(ctx, net, population, b, rounds=3, n_candidates=4096, top_k=16, tol=0.05, seed=0, log=None,
+           norm: Normalizer = None):
     """Band-gap maximisation: each round mutates the population into
     n_candidates cells, ranks them by the surrogate's predicted gap, verifies
     the top_k with the plain solve and keeps the best verified cells.  A
@@ -117,7 +144,7 @@ def screen(ctx, net, population, b, rounds=3, n_candidates=4096, top_k=16, tol=0
         parents = pop[rng.integers(0, pop.shape[0], n_candidates)]
         cand = mutate(parents, rng)
         t0 = time.perf_counter()
-        pred = np.concatenate([net.infer(cand[i:i + 4096]) for i in range(0, n_candidates, 4096)])
+        pred = predict(net, cand, norm)
         stats["t_surrogate"] += time.perf_counter() - t0
         stats["predicted"] += n_candidates
         gp = band_gap(pred, b)

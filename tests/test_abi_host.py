@@ -53,3 +53,17 @@ def test_null_handles_are_rejected():
     # destroying NULL handles is a no-op
     assert lib.mvpb_ctx_destroy(None) == 0 and lib.mvpb_cell_destroy(None) == 0
     assert lib.mvpb_plan_destroy(None) == 0
+
+
+def test_screening_normalizer_round_trip_and_scale():
+    """The label standardisation is exactly undone by decode and gives
+    unit-variance, zero-mean targets (up to its variance floor)."""
+    from paper_1310_6380_amd import screening as sc
+    rng = np.random.default_rng(1)
+    y = (rng.standard_normal((300, 400)) * rng.uniform(0.01, 3.0, 400) + rng.uniform(0, 5, 400)).astype(np.float32)
+    nm = sc.Normalizer(y)
+    z = nm.encode(y)
+    assert z.dtype == np.float32
+    assert np.allclose(z.mean(axis=0), 0.0, atol=1e-4)
+    assert np.allclose(z.std(axis=0), y.std(axis=0) / (y.std(axis=0) + 1e-3), rtol=1e-3)
+    assert np.allclose(nm.decode(z), y, rtol=1e-5, atol=1e-5)
