@@ -123,7 +123,7 @@ __device__ __forceinline__ int sturm_count_minors(const double *__restrict__ dd,
 // interval, and every eigenvalue takes its bracket from their counts; later
 // rounds deal the probes out evenly over the eigenvalues whose bracket is
 // still wider than a few ulps of |T|.
-constexpr int BISI_THREADS = 512;
+constexpr int BISI_THREADS = 256;
 constexpr int BISI_GROUPS = 4;
 __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigItem *__restrict__ items) {
   extern __shared__ double shd[];   // dd (n), ee (n), e2p (n + 1)
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigIte
     __syncthreads();
     const int na = nact_s;
     if (na == 0) break;
-    const int P = BISI_THREADS / na;   // probes per open eigenvalue (>= 8 for nb <= 64)
+    const int P = BISI_THREADS / na;   // probes per open eigenvalue (>= 16 for nb <= 64)
     const int a = tid / P, pq = tid % P;
     if (a < na) {
       const int j = act_s[a];
@@ -400,6 +400,9 @@ MVPB_DEV void tri_solve(double *__restrict__ xv, int n, const double *__restrict
 // eigenvectors come from inverse iteration with Gram-Schmidt (1b); isolated
 // ones from the twisted factorization (1c).
 constexpr double CLUSTER_REL = 1e-9;
+MVPB_DEV bool in_cluster(const double *lam, int j, int nb, double thr) {
+  return (j > 0 && lam[j] - lam[j - 1] <= thr) || (j + 1 < nb && lam[j + 1] - lam[j] <= thr);
+}
 
 // 1c. Eigenvector of an isolated eigenvalue lam by the twisted factorization
 // of T - lam I: the pivots of the top-down (dp) and bottom-up (dm) LDL^T
@@ -432,7 +435,7 @@ __global__ void __launch_bounds__(64) tridiag_twisted(const EigItem *__restrict_
   const double thr = CLUSTER_REL * bnorm;
   const double *lam = it.lam_t;
   const double lj = lam[j];
-  if ((j > 0 && lj - lam[j - 1] <= thr) || (j + 1 < nb && lam[j + 1] - lj <= thr)) return;   // cluster member
+  if (in_cluster(lam, j, nb, thr)) return;   // cluster member: inverse iteration
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
   // lane 0: dp_i = (d_i - lam) - e_{i-1}^2 / dp_{i-1}, i = 0 .. n-1;
   // lane 1: dm_i = (d_i - lam) - e_i^2 / dm_{i+1}, i = n-1 .. 0
@@ -528,24 +531,25 @@ __global__ void __launch_bounds__(64) tridiag_twisted(const EigItem *__restrict_
   }
 }
 
-// 1b. Eigenvectors of T by inverse iteration with a pivoted LU of T - lam I
-// (two solves from a pseudo-random start).  One wavefront per eigenvalue;
-// lane 0 runs the sequential factorisation and solves, the wavefront the
-// normalisation.  Eigenvalues closer than 1e-9 |T| form a cluster, handled
-// in order by the wavefront of its first member with Gram-Schmidt against
-// the earlier members after every solve.  LU_LDS: the five LU arrays live
-// in LDS (else in the item's global scratch).
+// 1b. Eigenvectors of cluster members (eigenvalues within CLUSTER_REL |T|
+// of a neighbour) by inverse iteration with a pivoted LU of T - lam I: two
+// solves from a pseudo-random start that differs per member, so that members
+// of a (near-)degenerate cluster come out independent.  One wavefront per
+// member, all members at once; lane 0 runs the sequential factorisation and
+// solves, the wavefront the normalisation.  tridiag_cluster_gs then
+// orthonormalises every cluster.  LU_LDS: the five LU arrays live in LDS
+// (else in the item's global scratch).
 constexpr int INV_LDS_MAX_N = 2400;
 template <bool LU_LDS>
 __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ items) {
   extern __shared__ double shd[];
   __shared__ double red[3];
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, nb = it.nb, j0 = blockIdx.x;
-  if (j0 >= nb) return;
+  const int n = 2 * it.N, nb = it.nb, jm = blockIdx.x;
+  if (jm >= nb) return;
   const int lane = threadIdx.x;
   double *dd = shd, *ee = dd + n, *xv = ee + n;
-  double *lub = LU_LDS ? xv + n : it.lu + (size_t)5 * n * j0;
+  double *lub = LU_LDS ? xv + n : it.lu + (size_t)5 * n * jm;
   double *DL = lub, *DGi = lub + n, *DU = lub + 2 * n, *DU2 = lub + 3 * n, *PV = lub + 4 * n;
   for (int r = lane; r < n; r += 64) {
     dd[r] = it.d[r];
@@ -555,50 +559,82 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
   double gl, gu, emax2;
   gershgorin(dd, ee, n, red, gl, gu, emax2);
   const double bnorm = fmax(fabs(gl), fabs(gu));
-  const double thr = CLUSTER_REL * bnorm;
   const double *lam = it.lam_t;
-  if (j0 > 0 && lam[j0] - lam[j0 - 1] <= thr) return;   // not the first member of its cluster
+  if (!in_cluster(lam, jm, nb, CLUSTER_REL * bnorm)) return;   // isolated: twisted factorization
+  const double pert = fmax(DBL_EPSILON * bnorm, 1e-280);
+  const double sh = lam[jm];
+  if (lane == 0) tri_lu(dd, ee, n, sh, pert, DL, DGi, DU, DU2, PV);
+  for (int r = lane; r < n; r += 64) xv[r] = hash_uniform(r + 1, jm + 7);
+  __syncthreads();
+  for (int iter = 0; iter < 2; ++iter) {
+    if (lane == 0) tri_solve(xv, n, DL, DGi, DU, DU2, PV);
+    __syncthreads();
+    double amax = 0.0;
+    for (int r = lane; r < n; r += 64) amax = fmax(amax, fabs(xv[r]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+    const double ia = amax > 0.0 ? 1.0 / amax : 1.0;
+    double s2 = 0.0;
+    for (int r = lane; r < n; r += 64) {
+      const double v = xv[r] * ia;
+      s2 = fma(v, v, s2);
+    }
+    s2 = wave_sum(s2);
+    const double inv = s2 > 0.0 ? ia / sqrt(s2) : 0.0;
+    for (int r = lane; r < n; r += 64) xv[r] *= inv;
+    __syncthreads();
+  }
+  double *X = it.X;
+  for (int r = lane; r < n; r += 64) gst(X, (size_t)r * nb + jm, xv[r]);
+}
+
+// 1b'. Modified Gram-Schmidt (two passes) over the eigenvectors of every
+// cluster, in eigenvalue order; one wavefront per cluster, started by the
+// wavefront of the cluster's first member.
+__global__ void __launch_bounds__(64) tridiag_cluster_gs(const EigItem *__restrict__ items) {
+  __shared__ double red[3];
+  const EigItem it = items[blockIdx.y];
+  const int n = 2 * it.N, nb = it.nb, j0 = blockIdx.x;
+  if (j0 >= nb) return;
+  const int lane = threadIdx.x;
+  // |T| from the Gershgorin bounds, read straight from d and e
+  double gl = DBL_MAX, gu = -DBL_MAX;
+  for (int r = lane; r < n; r += 64) {
+    const double er = (r < n - 1) ? fabs(it.e[r]) : 0.0, el = (r > 0) ? fabs(it.e[r - 1]) : 0.0;
+    gl = fmin(gl, it.d[r] - er - el);
+    gu = fmax(gu, it.d[r] + er + el);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, o, 64));
+    gu = fmax(gu, __shfl_xor(gu, o, 64));
+  }
+  (void)red;
+  const double thr = CLUSTER_REL * fmax(fabs(gl), fabs(gu));
+  const double *lam = it.lam_t;
+  if (j0 > 0 && lam[j0] - lam[j0 - 1] <= thr) return;   // not the first member
   int j1 = j0 + 1;
   while (j1 < nb && lam[j1] - lam[j1 - 1] <= thr) ++j1;
-  if (j1 == j0 + 1) return;                              // isolated: twisted factorization
-  const double pert = fmax(DBL_EPSILON * bnorm, 1e-280);
+  if (j1 == j0 + 1) return;                              // isolated
   double *X = it.X;
   for (int jm = j0; jm < j1; ++jm) {
-    const double sh = lam[jm];
-    if (lane == 0) tri_lu(dd, ee, n, sh, pert, DL, DGi, DU, DU2, PV);
-    for (int r = lane; r < n; r += 64) xv[r] = hash_uniform(r + 1, jm + 7);
-    __syncthreads();
-    for (int iter = 0; iter < 2; ++iter) {
-      if (lane == 0) tri_solve(xv, n, DL, DGi, DU, DU2, PV);
-      __syncthreads();
-      // orthogonalise against the earlier members of the cluster, normalise
-      for (int pass = 0; pass < (jm > j0 ? 2 : 1); ++pass) {
-        for (int q = j0; q < jm; ++q) {
-          double dot = 0.0;
-          for (int r = lane; r < n; r += 64) dot = fma(gld(X, (size_t)r * nb + q), xv[r], dot);
-          dot = wave_sum(dot);
-          for (int r = lane; r < n; r += 64) xv[r] = fma(-dot, gld(X, (size_t)r * nb + q), xv[r]);
-          __syncthreads();
-        }
-        double amax = 0.0;
-        for (int r = lane; r < n; r += 64) amax = fmax(amax, fabs(xv[r]));
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
-        const double ia = amax > 0.0 ? 1.0 / amax : 1.0;
-        double s2 = 0.0;
-        for (int r = lane; r < n; r += 64) {
-          const double v = xv[r] * ia;
-          s2 = fma(v, v, s2);
-        }
-        s2 = wave_sum(s2);
-        const double inv = s2 > 0.0 ? ia / sqrt(s2) : 0.0;
-        for (int r = lane; r < n; r += 64) xv[r] *= inv;
-        __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = j0; q < jm; ++q) {
+        double dot = 0.0;
+        for (int r = lane; r < n; r += 64) dot = fma(gld(X, (size_t)r * nb + q), gld(X, (size_t)r * nb + jm), dot);
+        dot = wave_sum(dot);
+        for (int r = lane; r < n; r += 64)
+          gst(X, (size_t)r * nb + jm, fma(-dot, gld(X, (size_t)r * nb + q), gld(X, (size_t)r * nb + jm)));
       }
+      double s2 = 0.0;
+      for (int r = lane; r < n; r += 64) {
+        const double v = gld(X, (size_t)r * nb + jm);
+        s2 = fma(v, v, s2);
+      }
+      s2 = wave_sum(s2);
+      const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+      for (int r = lane; r < n; r += 64) gst(X, (size_t)r * nb + jm, gld(X, (size_t)r * nb + jm) * inv);
     }
-    for (int r = lane; r < n; r += 64) gst(X, (size_t)r * nb + jm, xv[r]);
-    __threadfence_block();
-    __syncthreads();
   }
 }
 
@@ -611,6 +647,7 @@ hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int 
     hipLaunchKernelGGL(tridiag_invit<true>, dim3(nb, n_items), dim3(64), sizeof(double) * 8 * n_max, st, items);
   else
     hipLaunchKernelGGL(tridiag_invit<false>, dim3(nb, n_items), dim3(64), sizeof(double) * 3 * n_max, st, items);
+  hipLaunchKernelGGL(tridiag_cluster_gs, dim3(nb, n_items), dim3(64), 0, st, items);
   return hipGetLastError();
 }
 
