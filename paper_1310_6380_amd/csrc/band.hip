@@ -1313,7 +1313,24 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_s1(const EigItem *__
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = czero<R>();
     if (tt < kq) {
-      for (int r = tt + rg; r < m; r += RG) {   // V(r, tt) = 0 for r < tt
+      // V(r, tt) = 0 for r < tt; four rows per round, their loads issued together
+      constexpr int UR = 4;
+      int r = tt + rg;
+      for (; r + (UR - 1) * RG < m; r += UR * RG) {
+        C vl[UR];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) vl[u] = gld(Vp, (size_t)tt * ld + r + u * RG);
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+          const int ru = r + u * RG;
+          const C v = (ru == tt) ? mkc<R>(R(1), R(0)) : vl[u];
+          const C *zr = Z + zidx(c0 + HB + ru, 0, nc);
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            if (c < ncl) acc[c] = cfma_cj(v, zr[c], acc[c]);
+        }
+      }
+      for (; r < m; r += RG) {
         const C vl = gld(Vp, (size_t)tt * ld + r);
         const C v = (r == tt) ? mkc<R>(R(1), R(0)) : vl;
         const C *zr = Z + zidx(c0 + HB + r, 0, nc);

@@ -11,7 +11,7 @@ import pytest
 
 from oracle import mixed_oracle as mo
 from oracle.compare import band_error
-from synth import Cell, circle_cell, config0, config1, kpath_gxmg, layered_cell, random_iso_props
+from synth import Cell, circle_cell, config0, config1, config3, kpath_gxmg, layered_cell, random_iso_props
 
 pytestmark = pytest.mark.gpu
 
@@ -144,6 +144,26 @@ def test_config1_full_size_sampled(ctx):
     ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, c["M"], c["M"], c["Q"][pick], c["n_bands"])
     err = band_error(om[pick], ref)
     _say("  config1 error", err)
+    assert err <= TOL64
+
+
+def test_config3_full_size_sampled(ctx):
+    """4096-phase Voronoi cell on 128 x 128, 31 x 31 plane waves (2N = 1922),
+    24 bands: every k of the 60-point path on the GPU, two of them (Gamma, with
+    its two zero modes, and an interior point) checked against the oracle.
+    Exercises the large-order paths: panel class RPT = 4, the LDS stage-2
+    back-transform (n - 1 > 64 HB) and the tridiagonal kernels at n = 1922."""
+    c = config3()
+    cell = c["cell"]
+    _say("config3 full size")
+    plan = ctx.cell(cell.phase, cell.props).plan(c["M"])
+    om = plan.solve(c["Q"], c["n_bands"])
+    assert om.shape == (60, 24) and np.all(np.isfinite(om))
+    assert np.all(np.diff(om, axis=1) >= 0)
+    pick = [0, 41]
+    ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, c["M"], c["M"], c["Q"][pick], c["n_bands"])
+    err = band_error(om[pick], ref)
+    _say("  config3 error", err)
     assert err <= TOL64
 
 
