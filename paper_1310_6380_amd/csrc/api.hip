@@ -865,7 +865,7 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     int *ctl = reinterpret_cast<int *>(ctx->ws.as<char>() + ctl_off);
     if (e == hipSuccess) e = launch_stage2(d_items, n_items, n_max, fp32, ctl, st);
     if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, n_max, nb, st);
-    if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_max, nb, fp32, st);
+    if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_min, n_max, nb, fp32, st);
     if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, n_max, nb, st);
     return e;
   };

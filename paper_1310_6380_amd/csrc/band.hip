@@ -408,6 +408,14 @@ struct CMma<double> {
     ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, ci, 0, 0, 0);
     ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, ci, 0, 0, 0);
   }
+  // Three-product form of the complex step (Gauss): p1 += a_re b_re,
+  // p2 += a_im b_im, p3 += (a_re + a_im)(b_re + b_im); then
+  // re = p1 - p2, im = p3 - p1 - p2.  Three real products instead of four.
+  MVPB_DEV static void step3(cd a, cd b, acc &p1, acc &p2, acc &p3) {
+    p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, p1, 0, 0, 0);
+    p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.im, p2, 0, 0, 0);
+    p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re + a.im, b.re + b.im, p3, 0, 0, 0);
+  }
   MVPB_DEV static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 template <>
@@ -419,6 +427,11 @@ struct CMma<float> {
     cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.im, b.im, cr, 0, 0, 0);
     ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, b.im, ci, 0, 0, 0);
     ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, b.re, ci, 0, 0, 0);
+  }
+  MVPB_DEV static void step3(cf a, cf b, acc &p1, acc &p2, acc &p3) {
+    p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, b.re, p1, 0, 0, 0);
+    p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, b.im, p2, 0, 0, 0);
+    p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re + a.im, b.re + b.im, p3, 0, 0, 0);
   }
   MVPB_DEV static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
@@ -656,11 +669,13 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
     Wc[k][i] = ld_or0<R>(Wm, (size_t)k * ld + gc, gc < m && kr);
   }
   lds_barrier();
-  typename M::acc cr[4], ci[4];
+  // three-product complex steps (three real matrix-core products each)
+  typename M::acc p1[4], p2[4], p3[4];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
-    cr[rb] = M::zero();
-    ci[rb] = M::zero();
+    p1[rb] = M::zero();
+    p2[rb] = M::zero();
+    p3[rb] = M::zero();
   }
 #pragma unroll
   for (int k0 = 0; k0 < HB; k0 += 4) {
@@ -670,8 +685,8 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
     for (int rb = 0; rb < 4; ++rb) {
       const C bv = conj(Vr[k0 + ak][16 * rb + ai]);   // conj(V[r][k])
       const C bw = conj(Wr[k0 + ak][16 * rb + ai]);   // conj(W[r][k])
-      M::step(aw, bv, cr[rb], ci[rb]);
-      M::step(av, bw, cr[rb], ci[rb]);
+      M::step3(aw, bv, p1[rb], p2[rb], p3[rb]);
+      M::step3(av, bw, p1[rb], p2[rb], p3[rb]);
     }
   }
 #pragma unroll
@@ -681,7 +696,8 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
     for (int v = 0; v < 4; ++v) {
       const int gc = cc0 + 16 * wv + M::row(lane, v);
       if (gc < m && gr < m) {
-        const C d = mkc<R>(cr[rb][v], -ci[rb][v]);   // D[r][c] = conj(Out[c][r])
+        const R ore = p1[rb][v] - p2[rb][v], oim = p3[rb][v] - p1[rb][v] - p2[rb][v];
+        const C d = mkc<R>(ore, -oim);   // D[r][c] = conj(Out[c][r])
         gst(A22, (size_t)gc * ld + gr, cur[rb][v] - d);
       }
     }
@@ -1077,6 +1093,7 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
   __shared__ C S[HB][8], S2[HB][8], Tm[HB][HB + 1];
   const EigItem it = items[blockIdx.y];
   const int n = 2 * it.N, nb = it.nb;
+  if (n - 1 <= 64 * HB) return;   // item of the wavefront kernel (backtransform_2s_wave)
   const int cbase = blockIdx.x * nc;
   if (cbase >= nb) return;
   const int ncl = min(nc, nb - cbase);
@@ -1179,6 +1196,7 @@ backtransform_2s_wave(const EigItem *__restrict__ items) {
   typedef cx<R> C;
   const EigItem it = items[blockIdx.y];
   const int n = 2 * it.N, nb = it.nb;
+  if (n - 1 > 64 * HB) return;   // item of the LDS kernel (backtransform_2s)
   const int lane = threadIdx.x & 63;
   const int cb = (blockIdx.x * BTW_WAVES + (threadIdx.x >> 6)) * BTW_COLS;   // first column of the wavefront
   if (cb >= nb) return;   // whole wavefronts
@@ -1522,25 +1540,25 @@ int backtransform_cols(int n_max, bool fp32) {
   return (int)std::min<size_t>(8, std::max<size_t>(1, std::min(cap, cap2)));
 }
 
-hipError_t launch_backtransform(const EigItem *items, int n_items, int n_max, int nb, bool fp32, hipStream_t st) {
+hipError_t launch_backtransform(const EigItem *items, int n_items, int n_min, int n_max, int nb, bool fp32,
+                                hipStream_t st) {
   ProfScope ps(K_BACKTRANSFORM, st);
   const int nc = backtransform_cols(n_max, fp32);
   const int groups = (nb + nc - 1) / nc;
   const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
   const size_t sh = zbytes(n_max, nc, es);
-  // stage 2: one wavefront per column pair while every block of a sweep has a lane
-  const bool wave = n_max - 1 <= 64 * HB;
+  // stage 2, per item: the wavefront kernel while every block of a sweep has
+  // a lane (n - 1 <= 64 HB), else the LDS kernel; each skips the other's items
+  const bool any_wave = n_min - 1 <= 64 * HB, any_lds = n_max - 1 > 64 * HB;
   const dim3 gw((nb + BTW_WAVES * BTW_COLS - 1) / (BTW_WAVES * BTW_COLS), n_items);
   if (fp32) {
-    if (wave)
-      hipLaunchKernelGGL((backtransform_2s_wave<float>), gw, dim3(BTW_WAVES * 64), 0, st, items);
-    else
+    if (any_wave) hipLaunchKernelGGL((backtransform_2s_wave<float>), gw, dim3(BTW_WAVES * 64), 0, st, items);
+    if (any_lds)
       hipLaunchKernelGGL((backtransform_2s<float>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
     hipLaunchKernelGGL((backtransform_s1<float>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
   } else {
-    if (wave)
-      hipLaunchKernelGGL((backtransform_2s_wave<double>), gw, dim3(BTW_WAVES * 64), 0, st, items);
-    else
+    if (any_wave) hipLaunchKernelGGL((backtransform_2s_wave<double>), gw, dim3(BTW_WAVES * 64), 0, st, items);
+    if (any_lds)
       hipLaunchKernelGGL((backtransform_2s<double>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
     hipLaunchKernelGGL((backtransform_s1<double>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
   }

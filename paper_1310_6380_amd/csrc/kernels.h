@@ -117,7 +117,8 @@ hipError_t launch_stage1(const ItemPart *parts, int n_parts, bool fp32);
 size_t hb2st_ctl_ints(int n_items);
 hipError_t launch_stage2(const EigItem *items, int n_items, int n_max, bool fp32, int *ctl, hipStream_t st);
 // Eigenvectors of C(k) from those of the tridiagonal matrix (X -> Y).
-hipError_t launch_backtransform(const EigItem *items, int n_items, int n_max, int nb, bool fp32, hipStream_t st);
+hipError_t launch_backtransform(const EigItem *items, int n_items, int n_min, int n_max, int nb, bool fp32,
+                                hipStream_t st);
 int backtransform_cols(int n_max, bool fp32);
 long long refl_total(int n);   // number of stage-2 reflectors of an item of order n
 
