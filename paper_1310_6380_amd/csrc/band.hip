@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
       fl |= ((in && r == t) ? 1u : 0u) << (25 + 2 * u);
     }
   };
-  typename M::acc cr = M::zero(), ci = M::zero();
+  typename M::acc p1 = M::zero(), p2 = M::zero(), p3 = M::zero();   // three-product complex steps
   const int ai = lane & 15, ak = lane >> 4;   // operand slot of this lane
   fetch(0);
   for (int cb0 = 0; cb0 < m; cb0 += TC) {
@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
     for (int k0 = 0; k0 < TC; k0 += 4) {
       const C a = tile[k0 + ak][16 * wv + ai];
       const C b = Vc[k0 + ak][ai];
-      M::step(a, b, cr, ci);
+      M::step3(a, b, p1, p2, p3);
     }
     lds_barrier();
   }
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int rr = 16 * wv + M::row(lane, v), t = lane & 15;
-    const C x = mkc<R>(cr[v], ci[v]);
+    const C x = mkc<R>(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
     X0s[rr * (HB + 1) + t] = x;
     if (r0 + rr < m) gst(X0, (size_t)t * ld + r0 + rr, x);
   }
