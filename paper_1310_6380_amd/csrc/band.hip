@@ -31,7 +31,6 @@
 
 namespace mvpb {
 
-constexpr int PQ_THREADS = 512;       // workgroup of the panel factorization
 constexpr int HB_LDB = 2 * HB + 1;   // stored subdiagonals of the band copy (0 .. 2 HB)
 constexpr int BT_THREADS = 512;
 
@@ -47,7 +46,11 @@ MVPB_DEV void wave_reduce_step(double *v, int lane) {
   if constexpr (S < 6) {
     constexpr int o = 32 >> S;
     constexpr int cur = D >> S;
-    if constexpr (cur >= 2) {
+    if constexpr (cur >= 2 && S <= 1) {
+      constexpr int h = cur / 2;
+#pragma unroll
+      for (int k = 0; k < h; ++k) v[k] = swap_add<S>(v[k], v[k + h]);
+    } else if constexpr (cur >= 2) {
       constexpr int h = cur / 2;
       const bool hi = (lane & o) != 0;
 #pragma unroll
@@ -138,11 +141,11 @@ MVPB_DEV cx<R> ld_or0(const cx<R> *p, size_t idx, bool ok) {
 // Output: V (unit lower trapezoidal, strictly below its diagonal) and R (on
 // and above) in place, T (upper, kq x kq) in T1[p].
 // ---------------------------------------------------------------------------
-template <typename R, int RPT, int NT>
+template <typename R, int RPT, int SW, int NT, int LO>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
 he2hb_panel(const EigItem *__restrict__ items, int p) {
   typedef cx<R> C;
-  constexpr int SW = HB / RPT;                 // sub-panel width held in registers
+  static_assert(HB % SW == 0 && SW * RPT <= 2 * HB, "sub-panel width divides the panel; registers bounded");
   constexpr int DC = 2 * SW;                   // column-step reduction size (doubles)
   constexpr int CW = SW < HB ? 16 / SW : 1;    // other columns per cross-reduction round
   constexpr int DX = 2 * SW * CW;              // cross-reduction size (doubles)
@@ -159,8 +162,8 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
   __shared__ C taus[SW];
   const EigItem it = items[blockIdx.x];
   const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
-  // this launch handles the items whose panel height is in (RPT/2, RPT] x NT
-  if (m <= (RPT / 2) * NT || m > RPT * NT) return;
+  // this launch handles the items whose panel height is in (LO, RPT NT]
+  if (m <= LO || m > RPT * NT) return;
   const int kq = min(m, HB);
   const size_t ld = (size_t)n;
   C *__restrict__ P = (C *)it.A + (size_t)c0 * ld + (c0 + HB);
@@ -190,7 +193,8 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
           for (int q = 0; q < SW; ++q) rowj[jj & 1][q] = x[0][q];
         }
         // partials over rows r > j, by position q: q = 0: |P[r][j]|^2;
-        // 0 < q < nfw: conj(P[r][j]) P[r][j+q]; q >= nfw: conj(V[r][l]) P[r][j]
+        // q > 0: conj(P[r][j]) x_q (x_q the column at position q: a later
+        // column of the panel for q < nfw, a finished reflector after)
         double acc[DC];
 #pragma unroll
         for (int q = 0; q < DC; ++q) acc[q] = 0.0;
@@ -198,13 +202,15 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
         for (int s = 0; s < RPT; ++s) {
           const int r = tid + NT * s;
           if (r > j && r < m) {
-            const C xj = x[s][0];
-            acc[0] += (double)(xj.re * xj.re + xj.im * xj.im);
+            // accumulated in FP64 with one FMA per real product
+            const cx<double> xj = mkc<double>((double)x[s][0].re, (double)x[s][0].im);
+            acc[0] = fma(xj.re, xj.re, fma(xj.im, xj.im, acc[0]));
 #pragma unroll
             for (int q = 1; q < SW; ++q) {
-              const C c = (q < nfw) ? cfma_cj(xj, x[s][q], czero<R>()) : cfma_cj(x[s][q], xj, czero<R>());
-              acc[2 * q] += (double)c.re;
-              acc[2 * q + 1] += (double)c.im;
+              const cx<double> c = cfma_cj(xj, mkc<double>((double)x[s][q].re, (double)x[s][q].im),
+                                           mkc<double>(acc[2 * q], acc[2 * q + 1]));
+              acc[2 * q] = c.re;
+              acc[2 * q + 1] = c.im;
             }
           }
         }
@@ -215,7 +221,8 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
         C tau, scale;
         make_reflector<R>(alpha, sums[0], beta, tau, scale);
         const C taub = conj(tau);
-        // w_q = v^H P[:, j+q] = P[j][j+q] + conj(scale) d_q for 0 < q < nfw
+        // w_q = v^H P[:, j+q] = P[j][j+q] + conj(scale) d_q for 0 < q < nfw,
+        // zero for the other positions (their update below is then exact)
         C wv[SW];
 #pragma unroll
         for (int q = 0; q < SW; ++q) {
@@ -228,18 +235,18 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
           if (r < m && r >= j) {
             const bool diag = (r == j);
             const C vr = diag ? mkc<R>(R(1), R(0)) : x[s][0] * scale;
-            const C tv = taub * vr;
+            const C ntv = czero<R>() - taub * vr;
 #pragma unroll
-            for (int q = 1; q < SW; ++q)
-              if (q < nfw) x[s][q] = x[s][q] - tv * wv[q];
+            for (int q = 1; q < SW; ++q) x[s][q] = cfma(ntv, wv[q], x[s][q]);
             x[s][0] = diag ? mkc<R>((R)beta, R(0)) : vr;
           }
         }
         // for T of the sub-panel (formed after its last column):
-        // u_l = v_l^H v_j = conj(V[j][l]) + scale g_l (column cs+l at position nfw+l)
+        // u_l = v_l^H v_j = conj(V[j][l]) + scale g_l (column cs+l at position
+        // nfw+l), g_l = sum over r > j of conj(V[r][l]) P[r][j]
         if (tid < jj) {
           const int q = nfw + tid;
-          const C g = mkc<R>((R)sums[2 * q], (R)sums[2 * q + 1]);
+          const C g = mkc<R>((R)sums[2 * q], (R)-sums[2 * q + 1]);
           Ub[tid][jj] = conj(rj[q]) + scale * g;
         }
         if (tid == 0) taus[jj] = tau;
@@ -1417,15 +1424,15 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_s1(const EigItem *__
 // item's own panel height, so an item's arithmetic does not depend on the
 // other items of the launch: one launch per height class present, and the
 // items of the other classes return at once.
-// Panel height classes (lo, hi]: the register blocking RPT and the workgroup
-// size NT with lo = (RPT/2) NT and hi = RPT NT.  Every wavefront repeats the
-// per-column reductions, but a smaller workgroup needs sub-panels (RPT > 1)
-// whose cross updates cost more: 512 threads measured fastest throughout.
-template <typename R, int RPT, int NT>
+// Panel height classes (LO, RPT NT]: RPT rows per thread, sub-panels of SW
+// columns, NT threads.  Every wavefront repeats the per-column reductions, so
+// fewer wavefronts are faster, while sub-panels (SW < 16) add cross updates:
+// whole 16-column panels with two rows per thread up to m = 1024.
+template <typename R, int RPT, int SW, int NT, int LO>
 static void launch_panel_class(const EigItem *items, int n_items, int p, int m_lo, int m_hi, hipStream_t st) {
-  const int lo = (RPT / 2) * NT, hi = RPT * NT;   // class: lo < m <= hi
-  if (m_hi <= lo || m_lo > hi) return;
-  hipLaunchKernelGGL((he2hb_panel<R, RPT, NT>), dim3(n_items), dim3(NT), 0, st, items, p);
+  constexpr int hi = RPT * NT;   // class: LO < m <= hi
+  if (m_hi <= LO || m_lo > hi) return;
+  hipLaunchKernelGGL((he2hb_panel<R, RPT, SW, NT, LO>), dim3(n_items), dim3(NT), 0, st, items, p);
 }
 
 // Compute units of the current device (cached per device).
@@ -1470,10 +1477,10 @@ static hipError_t launch_stage1_t(const ItemPart *parts, int n_parts) {
       const int m_lo = std::max(1, pt.n_min - c0 - HB);
       {
         ProfScope ps(K_PANEL, st);
-        launch_panel_class<R, 1, PQ_THREADS>(items, n_items, p, m_lo, m, st);
-        launch_panel_class<R, 2, PQ_THREADS>(items, n_items, p, m_lo, m, st);
-        launch_panel_class<R, 4, PQ_THREADS>(items, n_items, p, m_lo, m, st);
-        launch_panel_class<R, 8, PQ_THREADS>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 2, 16, 256, 0>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 2, 16, 512, 512>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 4, 4, 512, 1024>(items, n_items, p, m_lo, m, st);
+        launch_panel_class<R, 8, 2, 512, 2048>(items, n_items, p, m_lo, m, st);
       }
       const int nrb = (m + 63) / 64;
       {

@@ -98,6 +98,31 @@ template <int S>
 MVPB_DEV float xchg(float v) {
   return __uint_as_float(xchg_u32<S>(__float_as_uint(v)));
 }
+// Halving step over stage S = 0 or 1 for two values at once: lanes whose
+// stage-S bit (32 >> S) is clear return a + a(partner), the others
+// b(partner) + b.  One lane-swap per 32-bit word and no select: the swap
+// trades the upper half-group of a with the lower half-group of b.
+template <int S>
+MVPB_DEV double swap_add(double a, double b) {
+  static_assert(S == 0 || S == 1, "lane-swap stages only");
+  const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+  const unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32);
+  const unsigned blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+  unsigned l0, l1, h0, h1;
+  if constexpr (S == 0) {
+    const auto rl = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+  } else {
+    const auto rl = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+  }
+  const double x0 = __longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0));
+  const double x1 = __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1));
+  return x0 + x1;
+}
 // Partner value of stage S for a complex number.
 template <int S, typename R>
 MVPB_DEV cx<R> xchg_c(cx<R> v) {
