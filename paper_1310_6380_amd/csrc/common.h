@@ -85,7 +85,7 @@ MVPB_DEV unsigned xchg_u32(unsigned v) {
     return (__lane_id() & 16) ? r[0] : r[1];
   } else {
     constexpr int ctrl = S == 2 ? 0x140 : S == 3 ? 0x141 : S == 4 ? 0x4E : 0xB1;
-    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, false);
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, true);
   }
 }
 template <int S>
