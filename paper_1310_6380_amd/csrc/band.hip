@@ -443,20 +443,39 @@ struct CMma<float> {
   MVPB_DEV static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// Work slots of the stage-1 products, S per item, item-major.  Workgroups
+// are dealt to the 8 XCDs round-robin by launch order, so workgroup b takes
+// slot (b % 8) per + b / 8: each XCD works through one contiguous range of
+// slots, and the operands shared by the slots of one item (V, W, X0) are
+// fetched into one or two of the XCDs' L2 caches instead of all eight.  The
+// mapping is a bijection for any placement; only the cache reuse depends on it.
+constexpr int N_XCD = 8;
+MVPB_DEV bool xcd_slot(int S, int n_items, int &item, int &slot) {
+  const int total = n_items * S, per = (total + N_XCD - 1) / N_XCD;
+  const int b = (int)blockIdx.x;
+  const int g = (b % N_XCD) * per + b / N_XCD;
+  if (g >= total) return false;
+  item = g / S;
+  slot = g % S;
+  return true;
+}
+static int xcd_grid(int S, int n_items) { return N_XCD * ((n_items * S + N_XCD - 1) / N_XCD); }
+
 // X0 for row block rb (64 rows) on the matrix cores: wavefront wv owns rows
 // 16 wv .. 16 wv + 15 and all HB = 16 columns; column blocks of TC are
 // staged in LDS (the next block is loaded into registers meanwhile).
 template <typename R>
-__global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ items, int p) {
+__global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ items, int n_items, int S, int p) {
   typedef cx<R> C;
   typedef CMma<R> M;
   constexpr int TC = 32;
   constexpr int PER = 64 * TC / 256;   // tile elements loaded per thread
   __shared__ C tile[TC][65];        // tile[cc][rr] = A22(rb*64 + rr, cb*TC + cc); X0 of the block at the end
   __shared__ C Vc[TC][HB + 1];      // V rows of the column block
-  const EigItem it = items[blockIdx.y];
+  int item, rb;
+  if (!xcd_slot(S, n_items, item, rb)) return;
+  const EigItem it = items[item];
   const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
-  const int rb = blockIdx.x;
   if (m <= 0 || rb * 64 >= m) return;
   const int kq = min(m, HB);
   const size_t ld = (size_t)n;
@@ -561,12 +580,13 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
 // Stage 1c.  W = X0 T - V Y / 2 with Y = T^H (V^H X0) T, for row block rb.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ items, int p) {
+__global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ items, int n_items, int S, int p) {
   typedef cx<R> C;
   __shared__ C G[HB][HB + 1], Tm[HB][HB + 1], Q1[HB][HB + 1], Y[HB][HB + 1];
-  const EigItem it = items[blockIdx.y];
+  int item, rb;
+  if (!xcd_slot(S, n_items, item, rb)) return;
+  const EigItem it = items[item];
   const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
-  const int rb = blockIdx.x;
   if (m <= 0 || rb * 64 >= m) return;
   const int kq = min(m, HB);
   const size_t ld = (size_t)n;
@@ -632,15 +652,16 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
 // never read).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ items, int p) {
+__global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ items, int n_items, int S, int p) {
   typedef cx<R> C;
   typedef CMma<R> M;
   __shared__ C Vr[HB][65], Wr[HB][65], Vc[HB][65], Wc[HB][65];   // [k][i]: rows (r) / columns (c) of the tile
-  const EigItem it = items[blockIdx.y];
+  int item, t;
+  if (!xcd_slot(S, n_items, item, t)) return;
+  const EigItem it = items[item];
   const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
   if (m <= 0) return;
   const int nt = (m + 63) / 64;
-  const int t = blockIdx.x;
   if (t >= nt * (nt + 1) / 2) return;
   int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -1485,15 +1506,16 @@ static hipError_t launch_stage1_t(const ItemPart *parts, int n_parts) {
       const int nrb = (m + 63) / 64;
       {
         ProfScope ps(K_HEMM, st);
-        hipLaunchKernelGGL((he2hb_hemm<R>), dim3(nrb, n_items), dim3(256), 0, st, items, p);
+        hipLaunchKernelGGL((he2hb_hemm<R>), dim3(xcd_grid(nrb, n_items)), dim3(256), 0, st, items, n_items, nrb, p);
       }
       {
         ProfScope ps(K_WFORM, st);
-        hipLaunchKernelGGL((he2hb_wform<R>), dim3(nrb, n_items), dim3(256), 0, st, items, p);
+        hipLaunchKernelGGL((he2hb_wform<R>), dim3(xcd_grid(nrb, n_items)), dim3(256), 0, st, items, n_items, nrb, p);
       }
       {
         ProfScope ps(K_HER2K, st);
-        hipLaunchKernelGGL((he2hb_her2k<R>), dim3(nrb * (nrb + 1) / 2, n_items), dim3(256), 0, st, items, p);
+        const int ntile = nrb * (nrb + 1) / 2;
+        hipLaunchKernelGGL((he2hb_her2k<R>), dim3(xcd_grid(ntile, n_items)), dim3(256), 0, st, items, n_items, ntile, p);
       }
     }
   }
