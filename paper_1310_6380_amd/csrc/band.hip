@@ -489,9 +489,11 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
   // Raw values with per-element flags (bit 0: in range, bit 1: read
   // transposed, so conjugate; bit 2: diagonal, so real), applied at the LDS
   // store so that the loads stay in flight during the products.
-  C nxt[PER], vnx[2];
-  unsigned fl = 0;
-  auto fetch = [&](int cb0) {
+  // Two register buffers: the loads of the next two column blocks are in
+  // flight while one block is multiplied.
+  C nxA[PER], vnA[2], nxB[PER], vnB[2];
+  unsigned flA = 0, flB = 0;
+  auto fetch = [&](int cb0, C (&nxt)[PER], C (&vnx)[2], unsigned &fl) {
     const bool above = cb0 >= r0 + 64;   // entirely right of the diagonal block
     fl = 0;
 #pragma unroll
@@ -515,10 +517,7 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
       fl |= ((in && r == t) ? 1u : 0u) << (25 + 2 * u);
     }
   };
-  typename M::acc p1 = M::zero(), p2 = M::zero(), p3 = M::zero();   // three-product complex steps
-  const int ai = lane & 15, ak = lane >> 4;   // operand slot of this lane
-  fetch(0);
-  for (int cb0 = 0; cb0 < m; cb0 += TC) {
+  auto stage = [&](int cb0, const C (&nxt)[PER], const C (&vnx)[2], unsigned fl) {
     const bool above = cb0 >= r0 + 64;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -537,14 +536,31 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
       const unsigned f = fl >> (24 + 2 * u);
       Vc[e % TC][e / TC] = (f & 1u) ? vnx[u] : ((f & 2u) ? mkc<R>(R(1), R(0)) : czero<R>());
     }
-    lds_barrier();
-    fetch(cb0 + TC);   // in flight during the products below (past the end: clamped, unused)
+  };
+  typename M::acc p1 = M::zero(), p2 = M::zero(), p3 = M::zero();   // three-product complex steps
+  const int ai = lane & 15, ak = lane >> 4;   // operand slot of this lane
+  auto products = [&]() {
 #pragma unroll
     for (int k0 = 0; k0 < TC; k0 += 4) {
       const C a = tile[k0 + ak][16 * wv + ai];
       const C b = Vc[k0 + ak][ai];
       M::step3(a, b, p1, p2, p3);
     }
+  };
+  // blocks past the end are fetched from clamped addresses and never used
+  fetch(0, nxA, vnA, flA);
+  fetch(TC, nxB, vnB, flB);
+  for (int cb0 = 0; cb0 < m; cb0 += 2 * TC) {
+    stage(cb0, nxA, vnA, flA);
+    lds_barrier();
+    fetch(cb0 + 2 * TC, nxA, vnA, flA);
+    products();
+    lds_barrier();
+    if (cb0 + TC >= m) break;
+    stage(cb0 + TC, nxB, vnB, flB);
+    lds_barrier();
+    fetch(cb0 + 3 * TC, nxB, vnB, flB);
+    products();
     lds_barrier();
   }
   // X0 rows of this block: lane holds D[row][t = lane % 16]
