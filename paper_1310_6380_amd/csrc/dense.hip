@@ -13,10 +13,13 @@ namespace mvpb {
 // zero) for a batch of N x N matrices, blocked by 64:
 //   potrf_diag    factor of the diagonal block jb and its inverse (one
 //                 workgroup per matrix, in LDS);
-//   potrf_panel   L[i, jb] = A[i, jb] L_jj^-H for the row blocks below;
-//   potrf_update  A[i, k] -= L[i, jb] L[k, jb]^H on the lower trailing tiles;
-//   potri_row     X[i, j] = -X_ii sum_{k=j}^{i-1} L[i, k] X[k, j], row block
-//                 i at a time (X_ii from potrf_diag).
+//   potrf_panel   L[i, jb] = A[i, jb] L_jj^-H for the row blocks below, and
+//                 X[jb, c] = X_jj Y[jb, c] for the blocks c left of jb;
+//   potrf_update  A[i, k] -= L[i, jb] L[k, jb]^H on the lower trailing tiles,
+//                 and Y[i, c] -= L[i, jb] X[jb, c] for i below jb, c <= jb.
+// Y[i, c] = -sum_{k=c}^{i-1} L[i, k] X[k, c] is built up in the blocks of X
+// below the diagonal over the steps k (block forward substitution of
+// L X = I), and X[i, c] = X_ii Y[i, c] once step i has the factor of block i.
 // status[b] = j+1 if the pivot of column j of matrix b was not positive; the
 // later launches skip that matrix.
 // ---------------------------------------------------------------------------
@@ -36,7 +39,7 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
   cd *A = Aarr[b];
   cd *X = Xarr[b];
   const int nb = min(CB, N - jb);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, r_ = tid & (CB - 1), c_ = tid / CB;
   const size_t ld = (size_t)N;
   for (int e = tid; e < CB * CB; e += 256) {
     const int r = e % CB, c = e / CB;
@@ -59,17 +62,20 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
       if (r == 0) dg[j] = sq;
     }
     __syncthreads();
-    const int m = nb - j - 1;
-    // D[r][c] -= L[r][j] conj(L[c][j]) for j < c <= r
-    for (int e = tid; e < m * m; e += 256) {
-      const int r = j + 1 + e % m, c = j + 1 + e / m;
-      if (r >= c) D[r][c] = D[r][c] - D[r][j] * conj(D[c][j]);
-    }
+    // thread (row r = tid % 64, columns c = tid / 64 + 4 i): no index division
+    // D[r][c] -= L[r][j] conj(L[c][j]) for j < c <= r;
     // Di[r][c] -= L[r][j] Di[j][c] for r > j, c <= j
-    const int w = j + 1;
-    for (int e = tid; e < m * w; e += 256) {
-      const int r = j + 1 + e % m, c = e / m;
-      Di[r][c] = Di[r][c] - D[r][j] * Di[j][c];
+    if (r_ > j && r_ < nb) {
+      const cd lrj = D[r_][j];
+#pragma unroll 4
+      for (int i = 0; i < CB / 4; ++i) {
+        const int c = c_ + 4 * i;
+        if (c <= j) {
+          Di[r_][c] = Di[r_][c] - lrj * Di[j][c];
+        } else if (c <= r_) {
+          D[r_][c] = D[r_][c] - lrj * conj(D[c][j]);
+        }
+      }
     }
     __syncthreads();
   }
@@ -88,8 +94,46 @@ __global__ void __launch_bounds__(256) potrf_panel(cd *const *Aarr, cd *const *X
   const int b = blockIdx.y;
   if (status[b]) return;
   cd *A = Aarr[b];
-  const cd *X = Xarr[b];
+  cd *X = Xarr[b];
   const int nb = min(CB, N - jb);
+  const int m = N - jb - nb, rbn = m > 0 ? (m + CB - 1) / CB : 0;
+  const size_t ldx = (size_t)N;
+  if ((int)blockIdx.x >= rbn) {
+    // X[jb, c-block] = X_jj Y[jb, c-block] in place (c-block left of jb, full
+    // width); no other workgroup of the launch touches that block
+    const int c0 = (blockIdx.x - rbn) * CB;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    for (int e = tid; e < CB * CB; e += 256) {
+      const int r = e % CB, k = e / CB;
+      Di[r][k] = (r < nb && k < nb && r >= k) ? X[(size_t)(jb + k) * ldx + jb + r] : mk(0.0, 0.0);
+      P[r][k] = (r < nb) ? X[(size_t)(c0 + k) * ldx + jb + r] : mk(0.0, 0.0);   // P[k'][c] = Y[jb + k'][c0 + c]
+    }
+    __syncthreads();
+    cd acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
+    for (int k = 0; k < nb; ++k) {
+      cd pv[4], dv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) pv[a] = Di[tx + 16 * a][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dv[c] = P[k][ty + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int r = tx + 16 * a;
+        if (r < nb) X[(size_t)(c0 + ty + 16 * c) * ldx + jb + r] = acc[a][c];
+      }
+    return;
+  }
   const int i0 = jb + nb + blockIdx.x * CB;
   if (i0 >= N) return;
   const int rows = min(CB, N - i0);
@@ -130,7 +174,8 @@ __global__ void __launch_bounds__(256) potrf_panel(cd *const *Aarr, cd *const *X
 }
 
 // A[i, k] -= L[i, jb] L[k, jb]^H on the lower 64 x 64 tiles right of jb+nb
-__global__ void __launch_bounds__(256) potrf_update(cd *const *Aarr, const int *status, int N, int jb) {
+__global__ void __launch_bounds__(256) potrf_update(cd *const *Aarr, cd *const *Xarr, const int *status, int N,
+                                                     int jb) {
   __shared__ cd Lr[CB][CB + 1];   // Lr[r][k] = L(tile rows, jb+k)
   __shared__ cd Lc[CB][CB + 1];   // Lc[c][k] = L(tile cols, jb+k)
   const int b = blockIdx.y;
@@ -141,7 +186,56 @@ __global__ void __launch_bounds__(256) potrf_update(cd *const *Aarr, const int *
   if (m <= 0) return;
   const int nt = (m + CB - 1) / CB;
   const int t = blockIdx.x;
-  if (t >= nt * (nt + 1) / 2) return;
+  if (t >= nt * (nt + 1) / 2) {
+    // Y[i-block, c-block] -= L[i-block, jb] X[jb, c-block] for the row blocks
+    // i below jb and the column blocks c <= jb (the first contribution, c = jb,
+    // is written without reading: Y starts at zero)
+    const int jn = jb / CB + 1, t2 = t - nt * (nt + 1) / 2;
+    const int I = t2 / jn, Cb = t2 % jn;
+    if (I >= nt) return;
+    cd *X = Xarr[b];
+    const int r0 = q0 + I * CB, cx0 = Cb * CB;
+    const bool first = cx0 == jb;
+    const int cols = first ? nb : CB;
+    const size_t ld = (size_t)N;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    for (int e = tid; e < CB * CB; e += 256) {
+      const int i = e % CB, k = e / CB;   // rows fastest in both loads
+      Lr[i][k] = (r0 + i < N && k < nb) ? A[(size_t)(jb + k) * ld + r0 + i] : mk(0.0, 0.0);
+      Lc[i][k] = (k < cols && i < nb) ? X[(size_t)(cx0 + k) * ld + jb + i] : mk(0.0, 0.0);   // Lc[k'][c] = X[jb+k'][cx0+c]
+    }
+    __syncthreads();
+    cd acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
+    for (int k = 0; k < nb; ++k) {
+      cd pv[4], dv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) pv[a] = Lr[tx + 16 * a][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dv[c] = Lc[k][ty + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int cc = ty + 16 * c;
+      if (cc >= cols) continue;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int r = r0 + tx + 16 * a;
+        if (r < N) {
+          cd *dst = X + (size_t)(cx0 + cc) * ld + r;
+          *dst = first ? mk(0.0, 0.0) - acc[a][c] : *dst - acc[a][c];
+        }
+      }
+    }
+    return;
+  }
   int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
   while (I * (I + 1) / 2 > t) --I;
@@ -186,91 +280,6 @@ __global__ void __launch_bounds__(256) potrf_update(cd *const *Aarr, const int *
   }
 }
 
-// X[i-block, j-block] = -X_ii sum_{k=j}^{i-1} L[i, k] X[k, j] for j < i = ib
-__global__ void __launch_bounds__(256) potri_row(cd *const *Aarr, cd *const *Xarr, const int *status, int N,
-                                                  int ib) {
-  __shared__ cd Ls[CB][17];    // Ls[r][kk] = L(i rows, k cols chunk)
-  __shared__ cd Xs[16][CB + 1];   // Xs[kk][c] = X(k rows chunk, j cols)
-  __shared__ cd Ts[CB][CB + 1];
-  const int b = blockIdx.y;
-  if (status[b]) return;
-  const cd *A = Aarr[b];
-  cd *X = Xarr[b];
-  const int jbk = blockIdx.x;
-  const int i0 = ib * CB, j0 = jbk * CB;
-  const int rows = min(CB, N - i0), cols = min(CB, N - j0);
-  const size_t ld = (size_t)N;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  cd acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
-  // T = sum over k = j0 .. i0-1 of L[i rows, k] X[k, j cols]
-  for (int k0 = j0; k0 < i0; k0 += 16) {
-    for (int e = tid; e < CB * 16; e += 256) {
-      const int r = e % CB, kk = e / CB;
-      Ls[r][kk] = (r < rows) ? A[(size_t)(k0 + kk) * ld + i0 + r] : mk(0.0, 0.0);
-      const int kr = e / CB, cc = e % CB;   // same flattening for Xs
-      Xs[kr][cc] = (cc < cols) ? X[(size_t)(j0 + cc) * ld + k0 + kr] : mk(0.0, 0.0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
-      cd pv[4], dv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) pv[a] = Ls[tx + 16 * a][kk];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) dv[c] = Xs[kk][ty + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Ts[tx + 16 * a][ty + 16 * c] = acc[a][c];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
-  // X_ii (lower) times T, X_ii staged 16 columns at a time in Ls
-  for (int k0 = 0; k0 < rows; k0 += 16) {
-    __syncthreads();
-    for (int e = tid; e < CB * 16; e += 256) {
-      const int r = e % CB, kk = e / CB, k = k0 + kk;
-      Ls[r][kk] = (r < rows && k < rows && r >= k) ? X[(size_t)(i0 + k) * ld + i0 + r] : mk(0.0, 0.0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
-      if (k0 + kk >= rows) break;
-      cd pv[4], dv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) pv[a] = Ls[tx + 16 * a][kk];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) dv[c] = Ts[k0 + kk][ty + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int cc = ty + 16 * c;
-    if (cc >= cols) continue;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = tx + 16 * a;
-      if (r < rows) X[(size_t)(j0 + cc) * ld + i0 + r] = mk(0.0, 0.0) - acc[a][c];
-    }
-  }
-}
-
 __global__ void zero_upper_blocks(cd *const *Xarr, const int *status, int N) {
   // strict upper block part of X (block rows above the diagonal block)
   const int b = blockIdx.y;
@@ -292,18 +301,16 @@ hipError_t launch_potrf_trtri(cd *const *A, cd *const *Linv, int *status, int co
   ProfScope ps(K_POTRF, st);
   hipLaunchKernelGGL(clear_status, dim3((count + 255) / 256), dim3(256), 0, st, status, count);
   for (int jb = 0; jb < N; jb += CB) {
-    const int nb = std::min(CB, N - jb);
+    const int nb = std::min(CB, N - jb), J = jb / CB;
     hipLaunchKernelGGL(potrf_diag, dim3(count), dim3(256), 0, st, A, Linv, status, N, jb);
-    const int m = N - jb - nb;
-    if (m > 0) {
-      const int rb = (m + CB - 1) / CB;
-      hipLaunchKernelGGL(potrf_panel, dim3(rb, count), dim3(256), 0, st, A, Linv, status, N, jb);
-      hipLaunchKernelGGL(potrf_update, dim3(rb * (rb + 1) / 2, count), dim3(256), 0, st, A, status, N, jb);
-    }
+    const int m = N - jb - nb, rb = m > 0 ? (m + CB - 1) / CB : 0;
+    // panel tiles, then the J blocks of X left of the diagonal block
+    if (rb + J > 0) hipLaunchKernelGGL(potrf_panel, dim3(rb + J, count), dim3(256), 0, st, A, Linv, status, N, jb);
+    // trailing tiles, then rb (J + 1) tiles of the inverse
+    if (m > 0)
+      hipLaunchKernelGGL(potrf_update, dim3(rb * (rb + 1) / 2 + rb * (J + 1), count), dim3(256), 0, st, A, Linv,
+                         status, N, jb);
   }
-  const int nbk = (N + CB - 1) / CB;
-  for (int ib = 1; ib < nbk; ++ib)
-    hipLaunchKernelGGL(potri_row, dim3(ib, count), dim3(256), 0, st, A, Linv, status, N, ib);
   hipLaunchKernelGGL(zero_upper_blocks, dim3(64, count), dim3(256), 0, st, Linv, status, N);
   return hipGetLastError();
 }
