@@ -34,12 +34,13 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
   __shared__ cd D[CB][CB + 1];
   __shared__ cd Di[CB][CB + 1];
   __shared__ double dg[CB];
+  __shared__ cd colj[CB];   // column j of L below the diagonal
   const int b = blockIdx.x;
   if (status[b]) return;
   cd *A = Aarr[b];
   cd *X = Xarr[b];
   const int nb = min(CB, N - jb);
-  const int tid = threadIdx.x, r_ = tid & (CB - 1), c_ = tid / CB;
+  const int tid = threadIdx.x, c_ = tid & (CB - 1), w_ = tid / CB;
   const size_t ld = (size_t)N;
   for (int e = tid; e < CB * CB; e += 256) {
     const int r = e % CB, c = e / CB;
@@ -57,23 +58,27 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
     // column j of L below the diagonal, row j of the inverse (entries c <= j)
     if (tid < CB) {
       const int r = tid;
-      if (r > j && r < nb) D[r][j] = inv * D[r][j];
+      if (r > j && r < nb) {
+        const cd l = inv * D[r][j];
+        D[r][j] = l;
+        colj[r] = l;
+      }
       if (r <= j) Di[j][r] = inv * Di[j][r];
       if (r == 0) dg[j] = sq;
     }
     __syncthreads();
-    // thread (row r = tid % 64, columns c = tid / 64 + 4 i): no index division
+    // lane = column c, wavefront w = rows r = w (mod 4) below j:
     // D[r][c] -= L[r][j] conj(L[c][j]) for j < c <= r;
-    // Di[r][c] -= L[r][j] Di[j][c] for r > j, c <= j
-    if (r_ > j && r_ < nb) {
-      const cd lrj = D[r_][j];
-#pragma unroll 4
-      for (int i = 0; i < CB / 4; ++i) {
-        const int c = c_ + 4 * i;
-        if (c <= j) {
-          Di[r_][c] = Di[r_][c] - lrj * Di[j][c];
-        } else if (c <= r_) {
-          D[r_][c] = D[r_][c] - lrj * conj(D[c][j]);
+    // Di[r][c] -= L[r][j] Di[j][c] for c <= j
+    {
+      const cd lcj = conj(colj[c_]);   // used for c > j only
+      const cd dij = Di[j][c_];         // used for c <= j only
+      for (int r = j + 1 + ((w_ - j - 1) & 3); r < nb; r += 4) {
+        const cd lrj = colj[r];
+        if (c_ <= j) {
+          Di[r][c_] = Di[r][c_] - lrj * dij;
+        } else if (c_ <= r) {
+          D[r][c_] = D[r][c_] - lrj * lcj;
         }
       }
     }
