@@ -766,18 +766,29 @@ __global__ void __launch_bounds__(256) rr_product(const EigItem *__restrict__ it
 #pragma unroll
     for (int b = 0; b < RRP_BC; ++b) acc[b] = mk(0.0, 0.0);
     for (int c0 = 0; c0 < n; c0 += 64) {
+      // a full block's 16 entries of C for this thread are loaded at once,
+      // before the Y block is staged (same summation order as the loop below)
+      const int cmax = min(64, n - c0);
+      const bool full = cmax == 64 && r < rows;
+      cd a[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) a[u] = gld(Cm, full ? (size_t)(c0 + ks + 4 * u) * ld + r0 + r : 0);
       __syncthreads();
       for (int e = tid; e < 64 * RRP_BC; e += 256) {
         const int cc = e % 64, b = e / 64;
         Ys[cc][b] = (c0 + cc < n && b < bc) ? gld(Y, (size_t)(b0 + b) * ld + c0 + cc) : mk(0.0, 0.0);
       }
       __syncthreads();
-      if (r < rows) {
-        const int cmax = min(64, n - c0);
-        for (int cc = ks; cc < cmax; cc += 4) {
-          const cd a = gld(Cm, (size_t)(c0 + cc) * ld + r0 + r);
+      if (full) {
 #pragma unroll
-          for (int b = 0; b < RRP_BC; ++b) acc[b] = cfma(a, Ys[cc][b], acc[b]);
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+          for (int b = 0; b < RRP_BC; ++b) acc[b] = cfma(a[u], Ys[ks + 4 * u][b], acc[b]);
+      } else if (r < rows) {
+        for (int cc = ks; cc < cmax; cc += 4) {
+          const cd av = gld(Cm, (size_t)(c0 + cc) * ld + r0 + r);
+#pragma unroll
+          for (int b = 0; b < RRP_BC; ++b) acc[b] = cfma(av, Ys[cc][b], acc[b]);
         }
       }
     }
