@@ -666,7 +666,7 @@ static void item_layout(int n, int nb, bool fp32, size_t *sz, int *count) {
   sz[k++] = es * (size_t)n * HB;                 // Wm
   sz[k++] = es * nrb * HB * HB;                  // M0p
   sz[k++] = es * npan * HB * HB;                 // T1
-  sz[k++] = es * (size_t)n * (2 * HB + 1);       // WB
+  sz[k++] = es * ((size_t)n + WB_PAD_COLS) * (2 * HB + 1);  // WB (zero columns after the last)
   sz[k++] = es * nrefl * HB;                     // V2
   sz[k++] = es * nrefl;                          // tau2
   sz[k++] = sizeof(double) * n;                  // d

@@ -833,7 +833,9 @@ constexpr int HB2ST_CTL_ITEM = 16, HB2ST_CTL_TABLE = 32, HB2ST_MAX_XCC = 16;
 size_t hb2st_ctl_ints(int n_items) { return HB2ST_CTL_TABLE + (size_t)HB2ST_MAX_XCC * 8 * ((n_items + 7) / 8); }
 
 // Copy the band (subdiagonals 0 .. HB) of the stage-1 result into the
-// working band WB (subdiagonals HB+1 .. 2 HB zero) and clear the item's
+// working band WB (subdiagonals HB+1 .. 2 HB zero, entries of rows >= n and
+// the WB_PAD_COLS columns after the last zero: the bulge chasing never writes
+// them, so its block loads read zeros there without masks) and clear the item's
 // progress counters: flag[0] error, flag[1] abort, flag[2 + i] blocks done by
 // sweep i.
 template <typename R>
@@ -846,7 +848,7 @@ __global__ void __launch_bounds__(256) hb2st_init(const EigItem *__restrict__ it
   const size_t ld = (size_t)n;
   const C *A = (const C *)it.A;
   C *WB = (C *)it.WB;
-  const size_t total = (size_t)n * HB_LDB;
+  const size_t total = ((size_t)n + WB_PAD_COLS) * HB_LDB;
   for (size_t e = blockIdx.x * (size_t)256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
     const int c = (int)(e / HB_LDB), d = (int)(e % HB_LDB), r = c + d;
     const bool ok = d <= HB && r < n;
@@ -995,14 +997,14 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
       // annihilated and the diagonal block D = A[J_k, J_k]
       C y[4], dq[4];
       if (k == 0) {
-        const C x = ld_or0<R>(WB, (size_t)i * HB_LDB + 1 + q, q < L);
+        const C x = gld(WB, (size_t)i * HB_LDB + 1 + q);   // zero past row n - 1
 #pragma unroll
         for (int t = 0; t < 4; ++t) y[t] = x;
       } else {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int c = 4 * g + t;
-          y[t] = ld_or0<R>(WB, (size_t)(ps + c) * HB_LDB + HB + q - c, q < L);
+          y[t] = gld(WB, (size_t)(ps + c) * HB_LDB + HB + q - c);   // zero past row n - 1
         }
       }
 #pragma unroll
@@ -1010,7 +1012,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
         const int c = 4 * g + t;
         const bool lo = q >= c;
         const size_t idx = lo ? (size_t)(s + c) * HB_LDB + q - c : (size_t)(s + q) * HB_LDB + c - q;
-        C v = ld_or0<R>(WB, idx, q < L && c < L);
+        C v = gld(WB, idx);   // zero past row or column n - 1 (padding columns)
         if (!lo) v.im = -v.im;
         dq[t] = v;
       }

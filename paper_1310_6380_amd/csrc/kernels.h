@@ -22,6 +22,10 @@ constexpr int MAX_N = 4096;
 // Half bandwidth of the band form produced by the first reduction stage
 // (also the length of the bulge-chasing reflectors of the second stage).
 constexpr int HB = 16;
+// Columns of zeros after the n columns of the bulge-chasing band copy: every
+// entry a block reads past row or column n - 1 is then a stored zero, and the
+// block loads need no bounds masks.
+constexpr int WB_PAD_COLS = HB;
 // LDS budget of the back-transform's eigenvector block.
 constexpr int BT_LDS_BYTES = 128 * 1024;
 // Largest number of bands per solve (Rayleigh-Ritz block in LDS).
