@@ -935,6 +935,9 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
   if (tid == 0) abort_s = 0;
   __syncthreads();
   const int w = tid >> 6, lane = tid & 63, q = lane & 15, g = lane >> 4;
+  // lane parts of the block offsets from the diagonal entry (s, s): the
+  // entries (s + q, s - HB + 4 g + t), (s + q, s + 4 g + t), (s + 4 g + t, s + q)
+  const int oy = (HB_LDB - 1) * (4 * g - HB) + q, olo = (HB_LDB - 1) * 4 * g + q, oup = (HB_LDB - 1) * q + 4 * g;
   bool aborted = false;
   const int R_ = CH_WAVES / G, gp = G * P;
   // the wavefront that runs sweep j of this workgroup's share
@@ -992,27 +995,31 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
       }
       const int s = i + 1 + k * HB;
       const int L = min(HB, n - s);
-      const int ps = s - HB;   // J_{k-1} = [s-HB, s-1] (k >= 1)
+      // entry (s + a, s + b) of the band copy, a >= b, is Ws[(HB_LDB - 1) b + a]:
+      // every access of the block is a lane constant plus a multiple of t
+      C *const Ws = WB + (size_t)s * HB_LDB;
       // ---- every load of the task at once: the column / block being
       // annihilated and the diagonal block D = A[J_k, J_k]
       C y[4], dq[4];
       if (k == 0) {
-        const C x = gld(WB, (size_t)i * HB_LDB + 1 + q);   // zero past row n - 1
+        const C x = gld(Ws + (q - (HB_LDB - 1)), 0);   // entry (s + q, s - 1); zero past row n - 1
 #pragma unroll
         for (int t = 0; t < 4; ++t) y[t] = x;
       } else {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int c = 4 * g + t;
-          y[t] = gld(WB, (size_t)(ps + c) * HB_LDB + HB + q - c);   // zero past row n - 1
+          y[t] = gld(Ws + (oy + (HB_LDB - 1) * t), 0);   // entry (s + q, s - HB + c); zero past row n - 1
         }
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int c = 4 * g + t;
         const bool lo = q >= c;
-        const size_t idx = lo ? (size_t)(s + c) * HB_LDB + q - c : (size_t)(s + q) * HB_LDB + c - q;
-        C v = gld(WB, idx);   // zero past row or column n - 1 (padding columns)
+        // entry (s + q, s + c) below the diagonal, else (s + c, s + q) conjugated;
+        // zero past row or column n - 1 (padding columns)
+        const C *pd = lo ? Ws + (olo + (HB_LDB - 1) * t) : Ws + (oup + t);
+        C v = gld(pd, 0);
         if (!lo) v.im = -v.im;
         dq[t] = v;
       }
@@ -1045,7 +1052,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
       vq = (q == 0) ? mkc<R>(R(1), R(0)) : (q < L ? x * scale : czero<R>());
       const C betac = (q == 0) ? mkc<R>((R)beta, R(0)) : czero<R>();
       if (k == 0) {
-        if (g == 0 && q < L) gst(WB, (size_t)i * HB_LDB + 1 + q, betac);
+        if (g == 0 && q < L) gst(Ws + (q - (HB_LDB - 1)), 0, betac);
       } else {
         if (g == 0) y[0] = betac;
         // (c) columns c >= 1: y <- y - conj(tau) v (v^H y)
@@ -1062,7 +1069,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int c = 4 * g + t;
-            gst(WB, (size_t)(ps + c) * HB_LDB + HB + q - c, y[t]);
+            gst(Ws + (oy + (HB_LDB - 1) * t), 0, y[t]);
           }
         }
       }
@@ -1090,7 +1097,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
             if (c <= q) {
               C v = dq[t] - vq * conj(wc[t]) - wq * conj(vc[t]);
               if (c == q) v.im = R(0);
-              gst(WB, (size_t)(s + c) * HB_LDB + q - c, v);
+              gst(Ws + (olo + (HB_LDB - 1) * t), 0, v);
             }
           }
         }
