@@ -204,6 +204,33 @@ def variant_batched(mvpb, ctx, steps, warmup):
             "precision": "fp64"}, out["om"], cfg
 
 
+def variant_hex_polygons(mvpb, ctx, steps, warmup):
+    """Steel cylinders (d = 4 mm) in epoxy on the hexagonal lattice
+    (a = 6.023 mm), the example of Sec. 5, given as polygons (the cell
+    parallelogram, a 256-gon of the disk's area and its clockwise hole):
+    21x21 plane waves (2N = 882), 60 k on X-Gamma-J-X, 12 bands, FP64.  Also
+    reports the complete stop bands over the path."""
+    from synth import hex_steel_epoxy, kpath_xgjx
+    c = hex_steel_epoxy(256)
+    dcell = ctx.cell_polygons(c.polygons, c.poly_phase, c.props, c.lattice)
+    M, nb = 10, 12
+    Q = kpath_xgjx(60)
+    out = {}
+
+    def step():
+        plan = dcell.plan(M)
+        out["om"] = plan.solve(Q, nb)
+        plan.close()
+
+    dt = run_timed(step, steps, warmup, mvpb, "hex polygons")
+    f = out["om"] / (2.0 * np.pi) / 1e3
+    gaps = [[round(float(f[:, b].max()), 1), round(float(f[:, b + 1].min()), 1)]
+            for b in range(nb - 1) if f[:, b + 1].min() - f[:, b].max() >= 10.0]
+    return {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt, "precision": "fp64",
+            "two_N": 2 * (2 * M + 1) ** 2, "k_points": int(Q.shape[0]), "n_bands": nb,
+            "stop_bands_khz": gaps, "paper_stop_bands_khz_at_M5": [[120, 262], [427, 473]]}, out["om"], (c, M, Q, nb)
+
+
 def variant_surrogate(mvpb, ctx, n_train=4096, n_test=256, epochs=30):
     """Binary GRF cells on 32x32 (correlation length 4 px, fill U[0.2,0.8]),
     labels by the batched FP64 solver at 15x15 plane waves, 40 k, 10 bands;
@@ -370,12 +397,14 @@ def main():
                      "traffic": measured_traffic(name)})
     omega = om_dev.to_numpy(np.float64, (Q.shape[0], nb))
     variants = {}
-    om_mixed = om_batch = cfg2 = om_prec = cfg3 = None
+    om_mixed = om_batch = cfg2 = om_prec = cfg3 = om_hex = hexcfg = None
     if not args.no_variants:
         variants["mixed_1132_phase"], om_mixed = variant_mixed(mvpb, ctx, dcell, M, Q, nb, args.steps, args.warmup)
         variants["batched_256_cells"], om_batch, cfg2 = variant_batched(mvpb, ctx, max(1, args.steps // 2), 1)
         variants["surrogate_grf_cells"] = variant_surrogate(mvpb, ctx)
         variants["precision_4096_phase"], om_prec, cfg3 = variant_precision(mvpb, ctx)
+        variants["hex_steel_epoxy_polygons"], om_hex, hexcfg = variant_hex_polygons(mvpb, ctx, args.steps,
+                                                                                    args.warmup)
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -406,6 +435,15 @@ def main():
             ref3, _ = mo.bands(c3.phase, c3.props, c3.lattice, cfg3["M"], cfg3["M"], cfg3["Q"][kk], cfg3["n_bands"])
             for name, om in om_prec.items():
                 variants["precision_4096_phase"][name]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om[kk], ref3)
+        if om_hex is not None:
+            from oracle import mixed_oracle as mo
+            from oracle.compare import band_error
+            hc, hM, hQ, hnb = hexcfg
+            kk = [0, 17, 41]
+            progress("cpu baseline: oracle on the hexagonal polygon cell,", len(kk), "k-points")
+            I = mo.polygon_integral_tables(hc.polygons, hc.poly_phase, hc.n_phases, hc.lattice, hM, hM)
+            refh, _ = mo.bands(None, hc.props, hc.lattice, hM, hM, hQ[kk], hnb, I_p=I)
+            variants["hex_steel_epoxy_polygons"]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om_hex[kk], refh)
     print(json.dumps(out), flush=True)
 
 

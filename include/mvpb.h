@@ -99,6 +99,23 @@ int mvpb_ctx_destroy(mvpb_ctx ctx);
 int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], int nx, int ny,
                             const int32_t *phase, int n_phases, int prop_kind,
                             const double *props, mvpb_cell *out);
+/* A unit cell given as polygons (Sec. 4.1: the subdomain integrals of
+ * eqs. (eo), (ep) taken exactly over each polygon instead of the centroid
+ * rule of Sec. 3; polygons may carry any number of phases, as in the
+ * hexagonal examples of Sec. 5).  Polygon i has phase poly_phase[i] and the
+ * vertices xy[2v], xy[2v+1] (Cartesian, same units as the lattice) for v in
+ * [vert_offset[i], vert_offset[i+1]); vert_offset[0] = 0, at least 3
+ * vertices each, the closing edge implied.  A counter-clockwise polygon adds
+ * its area to its phase, a clockwise one subtracts it (a hole is a clockwise
+ * copy of its boundary in the enclosing phase).  The signed areas must tile
+ * the cell: their sum equals |det A| to 1e-9 relative and no phase ends up
+ * negative, else MVPB_E_INVALID.  props as for pixel cells.  Structure
+ * factors of polygon cells are computed in FP64 for every precision setting.
+ * Host pointers; deep-copied. */
+int mvpb_cell_create_polygons(mvpb_ctx ctx, const double lattice[4], int n_polys,
+                              const int32_t *poly_phase, const int32_t *vert_offset,
+                              const double *xy, int n_phases, int prop_kind,
+                              const double *props, mvpb_cell *out);
 int mvpb_cell_destroy(mvpb_cell cell);
 
 /* Build the k-independent part of the method for cutoff (M1, M2):

@@ -163,7 +163,8 @@ def pixel_integrals(phase, n_phases, area, m_vals, q_vals):
 
 
 def polygon_integral(verts, dG):
-    """int over a simple polygon (vertices CCW, Cartesian) of exp(i dG . x) dA.
+    """int over a simple polygon (vertices CCW, Cartesian) of exp(i dG . x) dA;
+    for clockwise vertices the same sum is minus that integral (a hole).
 
     Divergence theorem with F = -i dG/|dG|^2 exp(i dG.x):  for dG != 0,
         sum over edges e of (-i/|dG|^2) (dG . n_e) L_e exp(i dG . m_e) sinc_u(dG . t_e L_e / 2),
@@ -217,6 +218,21 @@ def subdomain_integral_tables(cell_phase, n_phases, lattice, M1, M2):
     m_vals = np.arange(-2 * M1, 2 * M1 + 1)
     q_vals = np.arange(-2 * M2, 2 * M2 + 1)
     return pixel_integrals(cell_phase, n_phases, area, m_vals, q_vals)
+
+
+def polygon_integral_tables(polygons, poly_phase, n_phases, lattice, M1, M2):
+    """I_p on the full (4 M1 + 1) x (4 M2 + 1) difference grid for a polygon
+    cell: the sum over the polygons of phase p of their integrals (clockwise
+    polygons subtract), at dG = 2 pi T (m, q) (Sec. 4: K_n = 2 pi T (Q + n))."""
+    _, T, _, _ = lattice_quantities(lattice)
+    m_vals = np.arange(-2 * M1, 2 * M1 + 1)
+    q_vals = np.arange(-2 * M2, 2 * M2 + 1)
+    mq = np.stack(np.meshgrid(m_vals, q_vals, indexing="ij"), axis=-1).astype(np.float64)
+    dG = 2.0 * np.pi * (mq @ T.T)
+    out = np.zeros((n_phases, m_vals.size, q_vals.size), dtype=np.complex128)
+    for verts, p in zip(polygons, poly_phase):
+        out[int(p)] += polygon_integral(verts, dG)
+    return out
 
 
 def phase_sum_tables(I_p, props, phase_weights=None):

@@ -205,8 +205,14 @@ struct mvpb_cell_s {
   double T[4];       // A^-1, row-major
   double area = 0.0;
   int nx = 0, ny = 0, n_phases = 0;
-  DevBuf phase;      // int32 [nx*ny]
+  DevBuf phase;      // int32 [nx*ny] (pixel cells)
   DevBuf wtab;       // double [n_phases][4]
+  // polygon cells
+  bool polygons = false;
+  int n_edges = 0;
+  DevBuf edges;      // double [n_edges][4]: midpoint, edge vector
+  DevBuf ephase;     // int32 [n_edges]
+  double f0[4] = {0.0, 0.0, 0.0, 0.0};   // weighted phase areas (dG = 0)
 };
 
 struct mvpb_plan_s {
@@ -309,6 +315,25 @@ static bool lattice_ok(const double *L, double *T, double *area) {
   return true;
 }
 
+// Weights of the four structure-factor fields per phase (isotropic E, nu,
+// rho rows): plane-strain compliances d11 + d12 = 1/(2(lam+mu)) =
+// (1+nu)(1-2nu)/E and d11 - d12 = 1/(2 mu) = (1+nu)/E (the shear weight is
+// d33 = 2 (d11 - d12)), the density, and 1 (the partition of unity).
+static int phase_weight_table(int n_phases, const double *props, std::vector<double> &w) {
+  w.assign((size_t)n_phases * 4, 0.0);
+  for (int p = 0; p < n_phases; ++p) {
+    const double E = props[3 * p], nu = props[3 * p + 1], rho = props[3 * p + 2];
+    if (!(E > 0.0) || !isfinite(E)) return set_err(MVPB_E_INVALID, "phase %d: E must be positive", p);
+    if (!(nu > -1.0 && nu < 0.5)) return set_err(MVPB_E_INVALID, "phase %d: nu must be in (-1, 0.5)", p);
+    if (!(rho > 0.0) || !isfinite(rho)) return set_err(MVPB_E_INVALID, "phase %d: rho must be positive", p);
+    w[4 * p + 0] = (1.0 + nu) * (1.0 - 2.0 * nu) / E;
+    w[4 * p + 1] = (1.0 + nu) / E;
+    w[4 * p + 2] = rho;
+    w[4 * p + 3] = 1.0;
+  }
+  return MVPB_OK;
+}
+
 extern "C" int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], int nx, int ny,
                                        const int32_t *phase, int n_phases, int prop_kind, const double *props,
                                        mvpb_cell *out) {
@@ -324,19 +349,9 @@ extern "C" int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], in
   for (size_t i = 0; i < (size_t)nx * ny; ++i)
     if (phase[i] < 0 || phase[i] >= n_phases)
       return set_err(MVPB_E_INVALID, "phase id %d at pixel %zu out of range [0,%d)", phase[i], i, n_phases);
-  std::vector<double> w((size_t)n_phases * 4);
-  for (int p = 0; p < n_phases; ++p) {
-    const double E = props[3 * p], nu = props[3 * p + 1], rho = props[3 * p + 2];
-    if (!(E > 0.0) || !isfinite(E)) return set_err(MVPB_E_INVALID, "phase %d: E must be positive", p);
-    if (!(nu > -1.0 && nu < 0.5)) return set_err(MVPB_E_INVALID, "phase %d: nu must be in (-1, 0.5)", p);
-    if (!(rho > 0.0) || !isfinite(rho)) return set_err(MVPB_E_INVALID, "phase %d: rho must be positive", p);
-    // plane-strain compliances: d11 + d12 = 1/(2(lam+mu)) = (1+nu)(1-2nu)/E,
-    // d11 - d12 = 1/(2 mu) = (1+nu)/E; the shear weight d33 = 2 (d11 - d12).
-    w[4 * p + 0] = (1.0 + nu) * (1.0 - 2.0 * nu) / E;
-    w[4 * p + 1] = (1.0 + nu) / E;
-    w[4 * p + 2] = rho;
-    w[4 * p + 3] = 1.0;
-  }
+  std::vector<double> w;
+  rc = phase_weight_table(n_phases, props, w);
+  if (rc) return rc;
   HIP_TRY(hipSetDevice(ctx->device));
   mvpb_cell c = new mvpb_cell_s();
   c->ctx = ctx;
@@ -354,6 +369,90 @@ extern "C" int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], in
     e = hipMemcpyAsync(c->phase.p, phase, sizeof(int32_t) * nx * ny, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->wtab.p, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return set_err(MVPB_E_NOMEM, "cell upload: %s", hipGetErrorString(e));
+  }
+  ctx->children++;
+  *out = c;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_cell_create_polygons(mvpb_ctx ctx, const double lattice[4], int n_polys,
+                                         const int32_t *poly_phase, const int32_t *vert_offset, const double *xy,
+                                         int n_phases, int prop_kind, const double *props, mvpb_cell *out) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!lattice || !poly_phase || !vert_offset || !xy || !props || !out)
+    return set_err(MVPB_E_INVALID, "NULL argument");
+  if (n_polys <= 0) return set_err(MVPB_E_INVALID, "n_polys must be positive");
+  if (n_phases <= 0) return set_err(MVPB_E_INVALID, "n_phases must be positive");
+  if (prop_kind != MVPB_PROP_ISO_E_NU_RHO)
+    return set_err(MVPB_E_UNSUPPORTED, "property kind %d not supported", prop_kind);
+  double T[4], area;
+  if (!lattice_ok(lattice, T, &area)) return set_err(MVPB_E_INVALID, "degenerate or non-finite lattice");
+  if (vert_offset[0] != 0) return set_err(MVPB_E_INVALID, "vert_offset[0] must be 0");
+  std::vector<double> eg;
+  std::vector<int32_t> ep;
+  std::vector<double> aph((size_t)n_phases, 0.0);
+  double total = 0.0;
+  for (int i = 0; i < n_polys; ++i) {
+    const int v0 = vert_offset[i], v1 = vert_offset[i + 1], nv = v1 - v0;
+    if (nv < 3) return set_err(MVPB_E_INVALID, "polygon %d has %d vertices (at least 3)", i, nv);
+    const int ph = poly_phase[i];
+    if (ph < 0 || ph >= n_phases)
+      return set_err(MVPB_E_INVALID, "polygon %d: phase id %d out of range [0,%d)", i, ph, n_phases);
+    double a2 = 0.0;   // twice the signed area (shoelace)
+    for (int k = 0; k < nv; ++k) {
+      const double *pa = xy + 2 * (size_t)(v0 + k), *pb = xy + 2 * (size_t)(v0 + (k + 1) % nv);
+      if (!isfinite(pa[0]) || !isfinite(pa[1])) return set_err(MVPB_E_INVALID, "polygon %d: non-finite vertex", i);
+      a2 += pa[0] * pb[1] - pb[0] * pa[1];
+      eg.push_back(0.5 * (pa[0] + pb[0]));
+      eg.push_back(0.5 * (pa[1] + pb[1]));
+      eg.push_back(pb[0] - pa[0]);
+      eg.push_back(pb[1] - pa[1]);
+      ep.push_back(ph);
+    }
+    aph[ph] += 0.5 * a2;
+    total += 0.5 * a2;
+  }
+  // the phases partition the cell: signed areas add up to |Omega|, none negative
+  const double tol = 1e-9 * area;
+  if (fabs(total - area) > tol)
+    return set_err(MVPB_E_INVALID, "polygons must tile the unit cell: signed area %.12g, cell area %.12g", total,
+                   area);
+  for (int p = 0; p < n_phases; ++p)
+    if (aph[p] < -tol) return set_err(MVPB_E_INVALID, "phase %d has negative signed area %.6g", p, aph[p]);
+  std::vector<double> w;
+  rc = phase_weight_table(n_phases, props, w);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(ctx->device));
+  mvpb_cell c = new mvpb_cell_s();
+  c->ctx = ctx;
+  memcpy(c->lattice, lattice, sizeof c->lattice);
+  memcpy(c->T, T, sizeof T);
+  c->area = area;
+  c->n_phases = n_phases;
+  c->polygons = true;
+  c->n_edges = (int)ep.size();
+  for (int k = 0; k < 4; ++k) {
+    double f = 0.0;
+    for (int p = 0; p < n_phases; ++p) f += w[4 * p + k] * aph[p];
+    c->f0[k] = f;
+  }
+  c->wtab.pool = &ctx->pool;
+  c->edges.pool = &ctx->pool;
+  c->ephase.pool = &ctx->pool;
+  hipError_t e = c->wtab.alloc(sizeof(double) * w.size());
+  if (e == hipSuccess) e = c->edges.alloc(sizeof(double) * eg.size());
+  if (e == hipSuccess) e = c->ephase.alloc(sizeof(int32_t) * ep.size());
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->wtab.p, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->edges.p, eg.data(), sizeof(double) * eg.size(), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ephase.p, ep.data(), sizeof(int32_t) * ep.size(), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     delete c;
@@ -384,7 +483,12 @@ static int run_structure_factors(mvpb_cell c, int M1, int M2, int precision, Dev
   HIP_TRY(X.reserve(std::max(plain, mfma)));
   HIP_TRY(F.reserve(sizeof(cd) * 4 * (size_t)nm * nq));
   hipStream_t st = c->ctx->stream;
-  if (precision & MVPB_PREC_SF_PLAIN64) {
+  if (c->polygons) {
+    // closed-form edge sums in FP64 for every precision setting
+    HIP_TRY(X.reserve(sf_poly_scratch_bytes(c->n_edges, M1, M2)));
+    HIP_TRY(launch_structure_factors_poly(c->edges.as<double>(), c->ephase.as<int32_t>(), c->wtab.as<double>(),
+                                          c->n_edges, c->T, c->f0, M1, M2, X.as<cd>(), F.as<cd>(), st));
+  } else if (precision & MVPB_PREC_SF_PLAIN64) {
     HIP_TRY(launch_structure_factors_f64(c->phase.as<int32_t>(), c->wtab.as<double>(), c->nx, c->ny, M1, M2,
                                          c->area, X.as<cd>(), F.as<cd>(), st));
   } else {

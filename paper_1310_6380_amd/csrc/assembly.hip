@@ -105,6 +105,94 @@ hipError_t launch_structure_factors_f64(const int32_t *phase, const double *wtab
 }
 
 // ---------------------------------------------------------------------------
+// Structure factors of a polygon cell: the subdomain integrals of
+// exp(i dG.x) (Sec. 4.1, eqs. (eo), (ep)) in closed form.  By the divergence
+// theorem, for dG != 0 the integral over a polygon is the sum over its
+// oriented edges (midpoint m, edge vector d) of
+//   (-i / |dG|^2) (dG_x d_y - dG_y d_x) exp(i dG.m) sin(dG.d / 2) / (dG.d / 2),
+// and a clockwise polygon contributes minus the integral over its area, so
+// holes are clockwise copies of their boundary.  dG = 2 pi T (m, q) on the
+// (4 M1 + 1) x (4 M2 + 1) grid of the pixel path, F in the same layout.
+// Pass 1: partial sums of one chunk of SFP_EDGES edges at 256 grid points per
+// workgroup; pass 2: the chunks added in order.  FP64 throughout.
+// ---------------------------------------------------------------------------
+constexpr int SFP_EDGES = 256;
+
+__global__ void __launch_bounds__(256) sf_poly_partial(const double *__restrict__ edges, const int *__restrict__ ephase,
+                                                       const double *__restrict__ wtab, int n_edges, double T00,
+                                                       double T01, double T10, double T11, int M1, int M2,
+                                                       cd *__restrict__ P) {
+  __shared__ double eg[SFP_EDGES][4];
+  __shared__ double ew[SFP_EDGES][4];
+  const int nq = 4 * M2 + 1, npt = (4 * M1 + 1) * nq;
+  const int chunk = blockIdx.y, e0 = chunk * SFP_EDGES, ne = min(SFP_EDGES, n_edges - e0);
+  for (int e = threadIdx.x; e < ne; e += 256) {
+    const int ph = ephase[e0 + e];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      eg[e][k] = edges[(size_t)(e0 + e) * 4 + k];
+      ew[e][k] = wtab[4 * ph + k];
+    }
+  }
+  __syncthreads();
+  const int pt = blockIdx.x * 256 + threadIdx.x;
+  if (pt >= npt) return;
+  const int m = pt / nq - 2 * M1, q = pt % nq - 2 * M2;
+  const double gx = 2.0 * M_PI * (T00 * m + T01 * q), gy = 2.0 * M_PI * (T10 * m + T11 * q);
+  cd acc[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc[k] = mk(0.0, 0.0);
+  if (m != 0 || q != 0) {
+    const double ig2 = 1.0 / (gx * gx + gy * gy);
+    for (int e = 0; e < ne; ++e) {
+      const double a = gx * eg[e][0] + gy * eg[e][1];
+      const double u = 0.5 * (gx * eg[e][2] + gy * eg[e][3]);
+      const double c = gx * eg[e][3] - gy * eg[e][2];
+      double sa, ca;
+      sincos(a, &sa, &ca);
+      const double f = c * ig2 * (u == 0.0 ? 1.0 : sin(u) / u);
+      // (-i) f (cos a + i sin a)
+      const double re = f * sa, im = -f * ca;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] = acc[k] + ew[e][k] * mk(re, im);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) P[((size_t)chunk * 4 + k) * npt + pt] = acc[k];
+}
+
+__global__ void __launch_bounds__(256) sf_poly_reduce(const cd *__restrict__ P, int n_chunks, int npt, int center,
+                                                      double f00, double f01, double f02, double f03,
+                                                      cd *__restrict__ F) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= 4 * npt) return;
+  const int k = t / npt, pt = t % npt;
+  cd s = mk(0.0, 0.0);
+  for (int c = 0; c < n_chunks; ++c) s = s + P[((size_t)c * 4 + k) * npt + pt];
+  if (pt == center) s = mk(k == 0 ? f00 : k == 1 ? f01 : k == 2 ? f02 : f03, 0.0);
+  F[(size_t)k * npt + pt] = s;
+}
+
+size_t sf_poly_scratch_bytes(int n_edges, int M1, int M2) {
+  const size_t chunks = (size_t)std::max(1, (n_edges + SFP_EDGES - 1) / SFP_EDGES);
+  return sizeof(cd) * chunks * 4 * (size_t)(4 * M1 + 1) * (4 * M2 + 1);
+}
+
+hipError_t launch_structure_factors_poly(const double *edges, const int *ephase, const double *wtab, int n_edges,
+                                         const double T[4], const double f0[4], int M1, int M2, cd *X, cd *F,
+                                         hipStream_t st) {
+  ProfScope ps(K_SF, st);
+  const int npt = (4 * M1 + 1) * (4 * M2 + 1);
+  const int chunks = std::max(1, (n_edges + SFP_EDGES - 1) / SFP_EDGES);
+  hipLaunchKernelGGL(sf_poly_partial, dim3((npt + 255) / 256, chunks), dim3(256), 0, st, edges, ephase, wtab,
+                     n_edges, T[0], T[1], T[2], T[3], M1, M2, X);
+  const int center = (2 * M1) * (4 * M2 + 1) + 2 * M2;
+  hipLaunchKernelGGL(sf_poly_reduce, dim3((4 * npt + 255) / 256), dim3(256), 0, st, X, chunks, npt, center, f0[0],
+                     f0[1], f0[2], f0[3], F);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Structure factors on the matrix cores.  The same factored contraction as
 // above, F_w = S o (E1 . W_w . E2^T), as two real/complex GEMM passes tiled
 // 16 x 16 per wavefront:

@@ -78,6 +78,14 @@ hipError_t launch_structure_factors_f64(const int32_t *phase, const double *wtab
 // X: scratch of 8 * nx * (4 M2 + 1) doubles.
 hipError_t launch_structure_factors_mfma(int prec, const int32_t *phase, const double *wtab, int nx, int ny, int M1,
                                          int M2, double area, double *X, cd *F, hipStream_t st);
+// Polygon cells: edges[e] = {mid_x, mid_y, d_x, d_y} (Cartesian, d = end -
+// start in the polygon's orientation), ephase[e] its polygon's phase;
+// f0[4] = the weighted phase areas (the dG = 0 entry).  X: scratch of
+// sf_poly_scratch_bytes(n_edges, M1, M2) bytes.
+size_t sf_poly_scratch_bytes(int n_edges, int M1, int M2);
+hipError_t launch_structure_factors_poly(const double *edges, const int *ephase, const double *wtab, int n_edges,
+                                         const double T[4], const double f0[4], int M1, int M2, cd *X, cd *F,
+                                         hipStream_t st);
 hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T0, cd *T1, cd *T2,
                                    hipStream_t st);
 hipError_t launch_combine(const cd *Xp, int N, double s, cd *coef, hipStream_t st);

@@ -46,7 +46,7 @@ EXPORTS = [
     "mvpb_kpath_square", "mvpb_ctx_profile", "mvpb_ctx_profile_read", "mvpb_plan_create_batch",
     "mvpb_sur_create", "mvpb_sur_destroy", "mvpb_sur_n_params", "mvpb_sur_get_params", "mvpb_sur_set_params",
     "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step", "mvpb_copy_device",
-    "mvpb_ctx_profile_mask",
+    "mvpb_ctx_profile_mask", "mvpb_cell_create_polygons",
 ]
 N_KERNELS = 15
 
@@ -76,6 +76,8 @@ def load(path: str = LIB_PATH):
     lib.mvpb_ctx_create.argtypes = [I, P, ctypes.c_size_t, ctypes.POINTER(P)]
     lib.mvpb_ctx_destroy.argtypes = [P]
     lib.mvpb_cell_create_pixels.argtypes = [P, D, I, I, ctypes.POINTER(ctypes.c_int32), I, I, D, ctypes.POINTER(P)]
+    lib.mvpb_cell_create_polygons.argtypes = [P, D, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                              D, I, I, D, ctypes.POINTER(P)]
     lib.mvpb_cell_destroy.argtypes = [P]
     lib.mvpb_plan_create.argtypes = [P, I, I, I, ctypes.POINTER(P)]
     lib.mvpb_plan_dofs.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
@@ -249,6 +251,11 @@ class Context:
     def cell(self, phase, props, lattice=None):
         return Cell(self, phase, props, lattice)
 
+    def cell_polygons(self, polygons, poly_phase, props, lattice):
+        """A polygon cell: ``polygons`` a list of [n_i, 2] vertex arrays
+        (Cartesian; counter-clockwise adds, clockwise subtracts)."""
+        return Cell.from_polygons(self, polygons, poly_phase, props, lattice)
+
     def plans(self, cells, Ms, precision: int = PREC_FP64) -> list:
         """Plans for many cells at once (batched per-cell assembly)."""
         n = len(cells)
@@ -295,6 +302,27 @@ class Cell:
                                            ph.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), pr.shape[0],
                                            PROP_ISO_E_NU_RHO, _dptr(pr), ctypes.byref(h)))
         self.h = h
+
+    @classmethod
+    def from_polygons(cls, ctx: Context, polygons, poly_phase, props, lattice):
+        lib = load()
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.h = None
+        verts = [np.asarray(v, dtype=np.float64).reshape(-1, 2) for v in polygons]
+        off = np.zeros(len(verts) + 1, dtype=np.int32)
+        off[1:] = np.cumsum([v.shape[0] for v in verts])
+        xy = np.ascontiguousarray(np.concatenate(verts, axis=0).reshape(-1))
+        ph = np.ascontiguousarray(np.asarray(poly_phase, dtype=np.int32))
+        pr = np.ascontiguousarray(np.asarray(props, dtype=np.float64).reshape(-1, 3))
+        lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(4))
+        h = ctypes.c_void_p()
+        I32 = ctypes.POINTER(ctypes.c_int32)
+        _check(lib.mvpb_cell_create_polygons(ctx.h, _dptr(lat), len(verts), ph.ctypes.data_as(I32),
+                                             off.ctypes.data_as(I32), _dptr(xy), pr.shape[0],
+                                             PROP_ISO_E_NU_RHO, _dptr(pr), ctypes.byref(h)))
+        self.h = h
+        return self
 
     def close(self):
         if self.h:

@@ -18,7 +18,8 @@ __all__ = [
     "Cell", "rng_for", "SQUARE", "circle_cell", "voronoi_phase_map", "random_iso_props",
     "inclusion_phase_map", "grf_phase_map", "layered_cell", "kpath_gxmg",
     "config0", "config1", "config2", "config3", "config4_cells", "workload",
-    "INCLUSION_PROPS", "MATRIX_PROPS",
+    "INCLUSION_PROPS", "MATRIX_PROPS", "PolygonCell", "iso_from_c11_c44", "hex_lattice",
+    "hex_cylinder_cell", "hex_steel_epoxy", "kpath_xgjx",
 ]
 
 SQUARE = np.array([[1.0, 0.0], [0.0, 1.0]])
@@ -163,6 +164,94 @@ def kpath_gxmg(n_k: int) -> np.ndarray:
     """
     corners = np.array([[0.0, 0.0], [0.5, 0.0], [0.5, 0.5], [0.0, 0.0]])
     seg = np.linalg.norm(np.diff(corners, axis=0), axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    if n_k == 1:
+        return corners[:1].copy()
+    s = np.linspace(0.0, cum[-1], n_k)
+    out = np.empty((n_k, 2))
+    for t, si in enumerate(s):
+        k = min(int(np.searchsorted(cum, si, side="right")) - 1, len(seg) - 1)
+        u = (si - cum[k]) / seg[k]
+        out[t] = corners[k] + u * (corners[k + 1] - corners[k])
+    return out
+
+
+# --------------------------------------------------------------------------
+# Polygon cells on the hexagonal lattice (the paper's Sec. 5 example geometry)
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class PolygonCell:
+    lattice: np.ndarray          # [2,2] rows h1, h2 (metres)
+    polygons: list               # [n_i, 2] Cartesian vertices; CCW adds, CW subtracts
+    poly_phase: np.ndarray       # [n_polys] int32
+    props: np.ndarray            # [P, 3] (E, nu, rho)
+
+    @property
+    def n_phases(self) -> int:
+        return int(self.props.shape[0])
+
+
+def iso_from_c11_c44(c11: float, c44: float, rho: float):
+    """(E, nu, rho) of an isotropic solid given C11 = lambda + 2 mu, C44 = mu."""
+    mu = c44
+    lam = c11 - 2.0 * c44
+    E = mu * (3.0 * lam + 2.0 * mu) / (lam + mu)
+    nu = lam / (2.0 * (lam + mu))
+    return (E, nu, rho)
+
+
+# steel cylinders in epoxy (Sec. 5; C11, C44 in Pa, rho in kg/m^3)
+STEEL = iso_from_c11_c44(264e9, 81e9, 7780.0)
+EPOXY = iso_from_c11_c44(7.54e9, 1.48e9, 1142.0)
+
+
+def hex_lattice(a: float) -> np.ndarray:
+    """Rows h1 = a (1, 0), h2 = a (1/2, sqrt(3)/2)."""
+    return np.array([[a, 0.0], [0.5 * a, 0.5 * np.sqrt(3.0) * a]])
+
+
+def _ngon(centre, radius: float, n: int, ccw: bool = True) -> np.ndarray:
+    t = 2.0 * np.pi * np.arange(n) / n
+    if not ccw:
+        t = -t
+    return np.stack([centre[0] + radius * np.cos(t), centre[1] + radius * np.sin(t)], axis=1)
+
+
+def hex_cylinder_cell(a: float, d: float, inc, mat, n_gon: int = 256) -> PolygonCell:
+    """One cylinder of diameter d at the centre of the primitive hexagonal cell.
+
+    Polygons: the cell parallelogram (matrix, CCW), the cylinder as a regular
+    n-gon (inclusion, CCW) and the same n-gon clockwise in the matrix phase (the
+    hole).  The n-gon's circumradius gives it the disk's area, so the filling
+    fraction is exact.
+    """
+    L = hex_lattice(a)
+    h1, h2 = L[0], L[1]
+    para = np.array([[0.0, 0.0], h1, h1 + h2, h2])
+    centre = 0.5 * (h1 + h2)
+    r = 0.5 * d
+    R = r * np.sqrt(2.0 * np.pi / (n_gon * np.sin(2.0 * np.pi / n_gon)))
+    polys = [para, _ngon(centre, R, n_gon, True), _ngon(centre, R, n_gon, False)]
+    phase = np.array([0, 1, 0], dtype=np.int32)
+    props = np.array([mat, inc], dtype=np.float64)
+    return PolygonCell(L, polys, phase, props)
+
+
+def hex_steel_epoxy(n_gon: int = 256) -> PolygonCell:
+    """Steel cylinders (d = 4 mm) in epoxy, hexagonal lattice a = 6.023 mm (Sec. 5)."""
+    return hex_cylinder_cell(6.023e-3, 4.0e-3, STEEL, EPOXY, n_gon)
+
+
+def kpath_xgjx(n_k: int) -> np.ndarray:
+    """n_k points equally spaced in arc length on X - Gamma - J - X of the
+    hexagonal Brillouin zone (X: edge midpoint (1/2, 0), J: corner (2/3, 1/3),
+    fractional coordinates of q1, q2 for the lattice of ``hex_lattice``)."""
+    corners = np.array([[0.5, 0.0], [0.0, 0.0], [2.0 / 3.0, 1.0 / 3.0], [0.5, 0.0]])
+    # arc length in Cartesian k: q1, q2 of the unit hexagonal lattice
+    q = 2.0 * np.pi * np.linalg.inv(hex_lattice(1.0)).T
+    cart = corners @ q
+    seg = np.linalg.norm(np.diff(cart, axis=0), axis=1)
     cum = np.concatenate([[0.0], np.cumsum(seg)])
     if n_k == 1:
         return corners[:1].copy()

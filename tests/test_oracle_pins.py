@@ -342,3 +342,54 @@ def test_eigenvectors_residual_and_normalisation():
     # stress eigenvector satisfies the second Galerkin equation Phi S + H* U = 0
     S = mo.stress_vector(mats, U)
     assert np.linalg.norm(mats["Phi"] @ S + mats["Hs"] @ U) < 1e-12 * np.linalg.norm(mats["Hs"] @ U)
+
+
+def _stop_bands_khz(omega):
+    """Complete gaps between consecutive bands over the sampled path, in kHz."""
+    f = np.asarray(omega) / (2.0 * np.pi) / 1e3
+    out = []
+    for b in range(f.shape[1] - 1):
+        lo, hi = f[:, b].max(), f[:, b + 1].min()
+        if hi > lo:
+            out.append((b, lo, hi))
+    return out
+
+
+def _wide_gaps(gaps, min_width_khz=10.0):
+    return [(lo, hi) for _, lo, hi in gaps if hi - lo >= min_width_khz]
+
+
+def test_hex_steel_epoxy_stop_bands_match_paper():
+    """P14 (Sec. 5, golden): steel cylinders in epoxy on the hexagonal lattice,
+    M = 5, X-Gamma-J-X: the all-angle stop bands the paper states."""
+    from synth import hex_steel_epoxy, kpath_xgjx, iso_from_c11_c44
+    gold = json.load(open(os.path.join(HERE, "golden", "hex_stop_bands.json")))
+    c = hex_steel_epoxy(256)
+    assert np.allclose(c.lattice[0], [gold["a_m"], 0.0])
+    assert np.allclose(c.props[1], iso_from_c11_c44(*gold["steel_c11_c44_rho"]))
+    assert np.allclose(c.props[0], iso_from_c11_c44(*gold["epoxy_c11_c44_rho"]))
+    M = gold["M"]
+    I = mo.polygon_integral_tables(c.polygons, c.poly_phase, c.n_phases, c.lattice, M, M)
+    om, _ = mo.bands(None, c.props, c.lattice, M, M, kpath_xgjx(31), 12, I_p=I)
+    wide = _wide_gaps(_stop_bands_khz(om))
+    assert len(wide) == len(gold["stop_bands_khz"]), wide
+    for (lo, hi), (glo, ghi) in zip(wide, gold["stop_bands_khz"]):
+        assert abs(lo - glo) <= 0.02 * glo and abs(hi - ghi) <= 0.02 * ghi, (lo, hi, glo, ghi)
+
+
+def test_polygon_cell_partition_and_holes():
+    """P3 for polygon cells: a cylinder cut out of the cell as a clockwise
+    polygon leaves sum_p I_p = |Omega| delta (signed areas tile the cell), and
+    I(-dG) = conj I(dG)."""
+    from synth import hex_steel_epoxy
+    c = hex_steel_epoxy(64)
+    M = 4
+    I = mo.polygon_integral_tables(c.polygons, c.poly_phase, c.n_phases, c.lattice, M, M)
+    _, _, area, _ = mo.lattice_quantities(c.lattice)
+    J = I.sum(axis=0)
+    ref = np.zeros_like(J)
+    ref[2 * M, 2 * M] = area
+    assert np.max(np.abs(J - ref)) <= 1e-14 * area
+    assert np.allclose(I[:, ::-1, ::-1], I.conj(), atol=1e-15 * area)
+    # phase areas: the n-gon has the disk's area
+    assert abs(I[1, 2 * M, 2 * M].real - np.pi * (2e-3) ** 2) <= 1e-12 * area
