@@ -231,6 +231,28 @@ def variant_hex_polygons(mvpb, ctx, steps, warmup):
             "stop_bands_khz": gaps, "paper_stop_bands_khz_at_M5": [[120, 262], [427, 473]]}, out["om"], (c, M, Q, nb)
 
 
+def variant_hex_1132(mvpb, ctx, steps, warmup):
+    """The 1132-element hexagonal cell of Sec. 5 (elements of steel's stiffness,
+    density 10^6 x centroid height), as 1132 polygons: 21x21 plane waves
+    (2N = 882), 60 k on X-Gamma-J-X, 18 bands, FP64."""
+    from synth import hex_graded_1132, kpath_xgjx
+    c = hex_graded_1132()
+    dcell = ctx.cell_polygons(c.polygons, c.poly_phase, c.props, c.lattice)
+    M, nb = 10, 18
+    Q = kpath_xgjx(60)
+    out = {}
+
+    def step():
+        plan = dcell.plan(M)
+        out["om"] = plan.solve(Q, nb)
+        plan.close()
+
+    dt = run_timed(step, steps, warmup, mvpb, "hex 1132 elements")
+    return {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt, "precision": "fp64",
+            "two_N": 2 * (2 * M + 1) ** 2, "k_points": int(Q.shape[0]), "n_bands": nb,
+            "polygons": len(c.polygons)}, out["om"], (c, M, Q, nb)
+
+
 def variant_surrogate(mvpb, ctx, n_train=4096, n_test=256, epochs=30):
     """Binary GRF cells on 32x32 (correlation length 4 px, fill U[0.2,0.8]),
     labels by the batched FP64 solver at 15x15 plane waves, 40 k, 10 bands;
@@ -397,7 +419,7 @@ def main():
                      "traffic": measured_traffic(name)})
     omega = om_dev.to_numpy(np.float64, (Q.shape[0], nb))
     variants = {}
-    om_mixed = om_batch = cfg2 = om_prec = cfg3 = om_hex = hexcfg = None
+    om_mixed = om_batch = cfg2 = om_prec = cfg3 = om_hex = hexcfg = om_h1132 = h1132cfg = None
     if not args.no_variants:
         variants["mixed_1132_phase"], om_mixed = variant_mixed(mvpb, ctx, dcell, M, Q, nb, args.steps, args.warmup)
         variants["batched_256_cells"], om_batch, cfg2 = variant_batched(mvpb, ctx, max(1, args.steps // 2), 1)
@@ -405,6 +427,8 @@ def main():
         variants["precision_4096_phase"], om_prec, cfg3 = variant_precision(mvpb, ctx)
         variants["hex_steel_epoxy_polygons"], om_hex, hexcfg = variant_hex_polygons(mvpb, ctx, args.steps,
                                                                                     args.warmup)
+        variants["hex_1132_element_polygons"], om_h1132, h1132cfg = variant_hex_1132(mvpb, ctx, args.steps,
+                                                                                     args.warmup)
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -444,6 +468,15 @@ def main():
             I = mo.polygon_integral_tables(hc.polygons, hc.poly_phase, hc.n_phases, hc.lattice, hM, hM)
             refh, _ = mo.bands(None, hc.props, hc.lattice, hM, hM, hQ[kk], hnb, I_p=I)
             variants["hex_steel_epoxy_polygons"]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om_hex[kk], refh)
+        if om_h1132 is not None:
+            from oracle import mixed_oracle as mo
+            from oracle.compare import band_error
+            hc, hM, hQ, hnb = h1132cfg
+            kk = [9, 33]
+            progress("cpu baseline: oracle on the 1132-element hexagonal cell,", len(kk), "k-points")
+            I = mo.polygon_integral_tables(hc.polygons, hc.poly_phase, hc.n_phases, hc.lattice, hM, hM)
+            refh, _ = mo.bands(None, hc.props, hc.lattice, hM, hM, hQ[kk], hnb, I_p=I)
+            variants["hex_1132_element_polygons"]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om_h1132[kk], refh)
     print(json.dumps(out), flush=True)
 
 

@@ -19,7 +19,7 @@ __all__ = [
     "inclusion_phase_map", "grf_phase_map", "layered_cell", "kpath_gxmg",
     "config0", "config1", "config2", "config3", "config4_cells", "workload",
     "INCLUSION_PROPS", "MATRIX_PROPS", "PolygonCell", "iso_from_c11_c44", "hex_lattice",
-    "hex_cylinder_cell", "hex_steel_epoxy", "kpath_xgjx",
+    "hex_cylinder_cell", "hex_steel_epoxy", "kpath_xgjx", "hex_graded_1132",
 ]
 
 SQUARE = np.array([[1.0, 0.0], [0.0, 1.0]])
@@ -241,6 +241,33 @@ def hex_cylinder_cell(a: float, d: float, inc, mat, n_gon: int = 256) -> Polygon
 def hex_steel_epoxy(n_gon: int = 256) -> PolygonCell:
     """Steel cylinders (d = 4 mm) in epoxy, hexagonal lattice a = 6.023 mm (Sec. 5)."""
     return hex_cylinder_cell(6.023e-3, 4.0e-3, STEEL, EPOXY, n_gon)
+
+
+def hex_graded_1132(a: float = 6.023e-3, n: int = 24, n_quads: int = 20) -> PolygonCell:
+    """The 1132-element hexagonal cell of Sec. 5: every element its own phase
+    with steel's stiffness (C11 = 264 GPa, C44 = 81 GPa) and the density
+    rho_i = 10^6 x (x2 of the element's centroid, metres) kg/m^3.
+
+    Mesh: the primitive cell cut into n x n small parallelograms; the first
+    ``n_quads`` stay whole and the others are split into two triangles, which
+    gives 2 n^2 - n_quads = 1132 elements for n = 24."""
+    L = hex_lattice(a)
+    h1, h2 = L[0], L[1]
+    polys = []
+    for i in range(n):
+        for j in range(n):
+            p00 = (i / n) * h1 + (j / n) * h2
+            p10 = ((i + 1) / n) * h1 + (j / n) * h2
+            p11 = ((i + 1) / n) * h1 + ((j + 1) / n) * h2
+            p01 = (i / n) * h1 + ((j + 1) / n) * h2
+            if len(polys) < n_quads:
+                polys.append(np.array([p00, p10, p11, p01]))
+            else:
+                polys.append(np.array([p00, p10, p11]))
+                polys.append(np.array([p00, p11, p01]))
+    E, nu, _ = iso_from_c11_c44(264e9, 81e9, 1.0)
+    props = np.array([(E, nu, 1e6 * float(np.mean(v[:, 1]))) for v in polys], dtype=np.float64)
+    return PolygonCell(L, polys, np.arange(len(polys), dtype=np.int32), props)
 
 
 def kpath_xgjx(n_k: int) -> np.ndarray:

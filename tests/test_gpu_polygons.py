@@ -11,7 +11,7 @@ import pytest
 
 from oracle import mixed_oracle as mo
 from oracle.compare import band_error
-from synth import hex_steel_epoxy, kpath_xgjx, random_iso_props
+from synth import hex_graded_1132, hex_steel_epoxy, kpath_xgjx, random_iso_props
 
 pytestmark = pytest.mark.gpu
 
@@ -122,3 +122,19 @@ def test_polygon_cell_rejects_bad_input(ctx):
         with pytest.raises(mvpb.MvpbError) as ei:
             ctx.cell_polygons(polys, ph, c.props, c.lattice)
         assert ei.value.code == -1
+
+
+def test_hex_1132_element_cell_matches_oracle(ctx):
+    """The 1132-element hexagonal cell of Sec. 5 (every element its own phase,
+    density from the centroid height) at M = 3, where the paper reports
+    convergence; 18 bands on X-Gamma-J-X."""
+    c = hex_graded_1132()
+    M, nb = 3, 18
+    Q = kpath_xgjx(9)
+    _say("1132-element hexagonal cell, M =", M)
+    om = ctx.cell_polygons(c.polygons, c.poly_phase, c.props, c.lattice).plan(M).solve(Q, nb)
+    I = mo.polygon_integral_tables(c.polygons, c.poly_phase, c.n_phases, c.lattice, M, M)
+    ref, _ = mo.bands(None, c.props, c.lattice, M, M, Q, nb, I_p=I)
+    err = band_error(om, ref)
+    _say("  band error", err)
+    assert err <= TOL64, err
