@@ -152,6 +152,18 @@ int mvpb_plan_destroy(mvpb_plan plan);
 int mvpb_solve(mvpb_plan plan, int n_k, const double *Q, int n_bands, double *omega, double *U,
                unsigned flags);
 
+/* Stress modes S = -Phi^-1 H* U (Sec. 3, after eq. (eigenvalueproblem); H
+ * and Phi of Sec. 4.1 eqs. (eh), (ep)) of displacement modes U, for the
+ * isotropic cells of this library.  Q as for mvpb_solve; U: n_k*n_bands*2N
+ * complex values in the layout mvpb_solve writes (any normalisation: S is
+ * linear in U).  S: space for n_k*n_bands*3N complex values,
+ * S[((t*n_bands + b)*3N + r)], r < N the sigma_11, N <= r < 2N the sigma_22,
+ * r >= 2N the sigma_12 coefficients, plane-wave order as for U.  Host
+ * pointers unless MVPB_F_DEVICE_PTRS (then U and S are device pointers).
+ * 1 <= n_bands <= 2N. */
+int mvpb_stress_modes(mvpb_plan plan, int n_k, const double *Q, int n_bands, const double *U,
+                      double *S, unsigned flags);
+
 /* Many plans at once: all (plan, k) items in one batched launch sequence
  * (captured in a HIP graph and replayed).  n_k[p] points for plan p taken
  * from Q[p] (host pointers), results to omega[p][t*n_bands + b] (host

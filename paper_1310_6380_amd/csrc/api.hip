@@ -222,6 +222,7 @@ struct mvpb_plan_s {
   double area = 0.0;
   DevBuf coef;       // 15 N x N
   DevBuf linvR;      // N x N, L_R^-1
+  DevBuf linvSD;     // 2 N x N: L_Sigma^-1, L_Delta^-1 (stress modes)
 };
 
 namespace mvpb {
@@ -651,9 +652,13 @@ static int build_plan_group(mvpb_ctx ctx, const mvpb_cell *cells, int g, int M1,
     pl->area = cells[c]->area;
     pl->coef.pool = &ctx->pool;
     pl->linvR.pool = &ctx->pool;
+    pl->linvSD.pool = &ctx->pool;
     made.push_back(pl);
     e = pl->coef.alloc(sizeof(cd) * 15 * NN);
     if (e == hipSuccess) e = pl->linvR.alloc(sizeof(cd) * NN);
+    if (e == hipSuccess) e = pl->linvSD.alloc(sizeof(cd) * 2 * NN);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pl->linvSD.p, Li + (3 * c + 0) * NN, sizeof(cd) * 2 * NN, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = launch_combine(Xm + 18 * NN * c, N, 0.5 * pl->area * pl->area, pl->coef.as<cd>(), st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(pl->linvR.p, Li + (3 * c + 2) * NN, sizeof(cd) * NN, hipMemcpyDeviceToDevice, st);
@@ -1031,6 +1036,60 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     }
     HIP_TRY(hipStreamSynchronize(st));
   }
+  return MVPB_OK;
+}
+
+static bool q_ok(const double *Q, int n);
+
+extern "C" int mvpb_stress_modes(mvpb_plan p, int n_k, const double *Q, int n_bands, const double *U, double *S,
+                                 unsigned flags) {
+  if (!p || !Q || !U || !S) return set_err(MVPB_E_INVALID, "NULL argument");
+  if (n_k < 0) return set_err(MVPB_E_INVALID, "n_k must be non-negative");
+  if (n_k == 0) return MVPB_OK;
+  if (n_bands < 1 || n_bands > 2 * p->N) return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, 2N]", n_bands);
+  if (!q_ok(Q, n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
+  mvpb_ctx ctx = p->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ProfBind pb(ctx);
+  hipStream_t st = ctx->stream;
+  const bool dev = flags & MVPB_F_DEVICE_PTRS;
+  const int N = p->N, nb = n_bands;
+  const size_t NN = (size_t)N * N, blk = (size_t)3 * N * nb;   // one k: three N x nb blocks
+  const size_t u_bytes = sizeof(cd) * (size_t)n_k * nb * 2 * N, s_bytes = sizeof(cd) * (size_t)n_k * blk;
+  DevBuf qd(&ctx->pool), ud(&ctx->pool), sd(&ctx->pool), X(&ctx->pool), Y(&ctx->pool), ptrs(&ctx->pool);
+  HIP_TRY(qd.alloc(sizeof(double) * 2 * (size_t)n_k));
+  HIP_TRY(hipMemcpyAsync(qd.p, Q, sizeof(double) * 2 * (size_t)n_k, hipMemcpyHostToDevice, st));
+  const cd *u_in = (const cd *)U;
+  cd *s_out = (cd *)S;
+  if (!dev) {
+    HIP_TRY(ud.alloc(u_bytes));
+    HIP_TRY(hipMemcpyAsync(ud.p, U, u_bytes, hipMemcpyHostToDevice, st));
+    u_in = ud.as<cd>();
+    HIP_TRY(sd.alloc(s_bytes));
+    s_out = sd.as<cd>();
+  }
+  HIP_TRY(X.alloc(s_bytes));
+  HIP_TRY(Y.alloc(s_bytes));
+  HIP_TRY(launch_stress_rhs(u_in, qd.as<double>(), n_k, nb, p->M1, p->M2, p->T, p->area, X.as<cd>(), st));
+  // Y = L^-1 X, then X = L^-H Y: Sigma^-1 on block 0, Delta^-1 on blocks 1, 2
+  std::vector<const void *> hp;
+  for (int j = 0; j < 3; ++j)
+    for (int t = 0; t < n_k; ++t) hp.push_back(p->linvSD.as<cd>() + (j == 0 ? 0 : NN));
+  for (int j = 0; j < 3; ++j)
+    for (int t = 0; t < n_k; ++t) hp.push_back(X.as<cd>() + (size_t)t * blk + (size_t)j * N * nb);
+  for (int j = 0; j < 3; ++j)
+    for (int t = 0; t < n_k; ++t) hp.push_back(Y.as<cd>() + (size_t)t * blk + (size_t)j * N * nb);
+  const size_t m = (size_t)3 * n_k;
+  HIP_TRY(ptrs.alloc(sizeof(void *) * hp.size()));
+  HIP_TRY(hipMemcpyAsync(ptrs.p, hp.data(), sizeof(void *) * hp.size(), hipMemcpyHostToDevice, st));
+  void **dp = ptrs.as<void *>();
+  GemmBatch b1{(const cd *const *)dp, (const cd *const *)(dp + m), (cd *const *)(dp + 2 * m), nullptr, N, N, N};
+  HIP_TRY(launch_zgemm(OP_N, OP_N, N, nb, N, mk(1.0, 0.0), b1, mk(0.0, 0.0), (int)m, st));
+  GemmBatch b2{(const cd *const *)dp, (const cd *const *)(dp + 2 * m), (cd *const *)(dp + m), nullptr, N, N, N};
+  HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), b2, mk(0.0, 0.0), (int)m, st));
+  HIP_TRY(launch_stress_combine(X.as<cd>(), n_k, nb, N, s_out, st));
+  if (!dev) HIP_TRY(hipMemcpyAsync(S, s_out, s_bytes, hipMemcpyDeviceToHost, st));
+  if (!(flags & MVPB_F_ASYNC) || !dev) HIP_TRY(hipStreamSynchronize(st));
   return MVPB_OK;
 }
 

@@ -193,6 +193,65 @@ hipError_t launch_structure_factors_poly(const double *edges, const int *ephase,
 }
 
 // ---------------------------------------------------------------------------
+// Stress modes (Sec. 3: S = -Phi^-1 H* U, the stress coefficients of an
+// eigenmode).  With exact integration the overlap J is |Omega| I, so
+// H* = -H^T is diagonal per plane wave: V11 = -i|Omega| K1 u1,
+// V22 = -i|Omega| K2 u2, V12 = -i|Omega| (K2 u1 + K1 u2), K_n = 2 pi T (Q + n)
+// (Sec. 4.1 eq. (eh)).  For an isotropic cell the normal-stress block of Phi
+// is [[A, B], [B, A]] with A + B = Sigma, A - B = Delta, and the shear block
+// is 2 Delta (eq. (ep), d33 = 2 (d11 - d12)), so
+//   S11 = -(Sigma^-1 (V11 + V22) + Delta^-1 (V11 - V22)) / 2,
+//   S22 = -(Sigma^-1 (V11 + V22) - Delta^-1 (V11 - V22)) / 2,
+//   S12 = -Delta^-1 V12 / 2.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) stress_rhs(const cd *__restrict__ U, const double *__restrict__ Q, int nb,
+                                                  int M1, int M2, double T00, double T01, double T10, double T11,
+                                                  double area, cd *__restrict__ X) {
+  const int N = (2 * M1 + 1) * (2 * M2 + 1);
+  const int t = blockIdx.y;
+  const int e = blockIdx.x * 256 + threadIdx.x;   // (r, b), r fastest
+  if (e >= N * nb) return;
+  const int r = e % N, b = e / N;
+  const double q1 = Q[2 * t] + (double)(r / (2 * M2 + 1) - M1), q2 = Q[2 * t + 1] + (double)(r % (2 * M2 + 1) - M2);
+  const double k1 = 2.0 * M_PI * (T00 * q1 + T01 * q2), k2 = 2.0 * M_PI * (T10 * q1 + T11 * q2);
+  const cd *u = U + ((size_t)t * nb + b) * 2 * N;
+  const cd u1 = u[r], u2 = u[N + r];
+  // -i |Omega| z = |Omega| (z.im, -z.re)
+  auto mi = [&](cd z) { return mk(area * z.im, -area * z.re); };
+  const cd v11 = mi(k1 * u1), v22 = mi(k2 * u2), v12 = mi(k2 * u1 + k1 * u2);
+  cd *x = X + (size_t)t * 3 * N * nb;
+  x[(size_t)b * N + r] = v11 + v22;
+  x[(size_t)N * nb + (size_t)b * N + r] = v11 - v22;
+  x[(size_t)2 * N * nb + (size_t)b * N + r] = v12;
+}
+
+__global__ void __launch_bounds__(256) stress_combine(const cd *__restrict__ Z, int nb, int N, cd *__restrict__ S) {
+  const int t = blockIdx.y;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= N * nb) return;
+  const int r = e % N, b = e / N;
+  const cd *z = Z + (size_t)t * 3 * N * nb + (size_t)b * N + r;
+  const cd zs = z[0], zd = z[(size_t)N * nb], z12 = z[(size_t)2 * N * nb];
+  cd *s = S + ((size_t)t * nb + b) * 3 * N;
+  s[r] = -0.5 * (zs + zd);
+  s[N + r] = -0.5 * (zs - zd);
+  s[2 * N + r] = -0.5 * z12;
+}
+
+hipError_t launch_stress_rhs(const cd *U, const double *Q, int n_k, int nb, int M1, int M2, const double T[4],
+                             double area, cd *X, hipStream_t st) {
+  const int N = (2 * M1 + 1) * (2 * M2 + 1);
+  hipLaunchKernelGGL(stress_rhs, dim3((N * nb + 255) / 256, n_k), dim3(256), 0, st, U, Q, nb, M1, M2, T[0], T[1],
+                     T[2], T[3], area, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_stress_combine(const cd *Z, int n_k, int nb, int N, cd *S, hipStream_t st) {
+  hipLaunchKernelGGL(stress_combine, dim3((N * nb + 255) / 256, n_k), dim3(256), 0, st, Z, nb, N, S);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Structure factors on the matrix cores.  The same factored contraction as
 // above, F_w = S o (E1 . W_w . E2^T), as two real/complex GEMM passes tiled
 // 16 x 16 per wavefront:

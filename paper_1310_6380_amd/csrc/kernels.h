@@ -83,6 +83,14 @@ hipError_t launch_structure_factors_mfma(int prec, const int32_t *phase, const d
 // f0[4] = the weighted phase areas (the dG = 0 entry).  X: scratch of
 // sf_poly_scratch_bytes(n_edges, M1, M2) bytes.
 size_t sf_poly_scratch_bytes(int n_edges, int M1, int M2);
+// Stress modes S = -Phi^-1 H* U (isotropic cells).  stress_rhs: from U
+// [n_k][nb][2N] (complex) the three right-hand sides X[t][j] (N x nb,
+// column-major), j = 0: V11 + V22, 1: V11 - V22, 2: V12 with V = H* U;
+// stress_combine: S[t][b][3N] from Z[t][j] = (Sigma^-1, Delta^-1, Delta^-1)
+// applied to X[t][j].  Q: device [n_k][2].
+hipError_t launch_stress_rhs(const cd *U, const double *Q, int n_k, int nb, int M1, int M2, const double T[4],
+                             double area, cd *X, hipStream_t st);
+hipError_t launch_stress_combine(const cd *Z, int n_k, int nb, int N, cd *S, hipStream_t st);
 hipError_t launch_structure_factors_poly(const double *edges, const int *ephase, const double *wtab, int n_edges,
                                          const double T[4], const double f0[4], int M1, int M2, cd *X, cd *F,
                                          hipStream_t st);

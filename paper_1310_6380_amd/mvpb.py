@@ -46,7 +46,7 @@ EXPORTS = [
     "mvpb_kpath_square", "mvpb_ctx_profile", "mvpb_ctx_profile_read", "mvpb_plan_create_batch",
     "mvpb_sur_create", "mvpb_sur_destroy", "mvpb_sur_n_params", "mvpb_sur_get_params", "mvpb_sur_set_params",
     "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step", "mvpb_copy_device",
-    "mvpb_ctx_profile_mask", "mvpb_cell_create_polygons",
+    "mvpb_ctx_profile_mask", "mvpb_cell_create_polygons", "mvpb_stress_modes",
 ]
 N_KERNELS = 15
 
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
     lib.mvpb_cell_create_polygons.argtypes = [P, D, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                               D, I, I, D, ctypes.POINTER(P)]
     lib.mvpb_cell_destroy.argtypes = [P]
+    lib.mvpb_stress_modes.argtypes = [P, I, D, I, D, D, ctypes.c_uint]
     lib.mvpb_plan_create.argtypes = [P, I, I, I, ctypes.POINTER(P)]
     lib.mvpb_plan_dofs.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.mvpb_plan_destroy.argtypes = [P]
@@ -378,6 +379,20 @@ class Plan:
         _check(lib.mvpb_solve(self.h, Q.shape[0], _dptr(Q), n_bands, ctypes.c_void_p(om.ctypes.data),
                               ctypes.c_void_p(U.ctypes.data) if vectors else None, 0))
         return (om, U) if vectors else om
+
+    def stress(self, Q, U):
+        """Stress modes S = -Phi^-1 H* U [n_k, n_bands, 3N] of displacement modes
+        U [n_k, n_bands, 2N] (as returned by solve(..., vectors=True))."""
+        lib = load()
+        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, 2))
+        U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+        nk, nb = U.shape[0], U.shape[1]
+        if U.shape[2] != self.n_u or nk != Q.shape[0]:
+            raise ValueError("U must be [n_k, n_bands, 2N] for the Q list")
+        S = np.zeros((nk, nb, self.n_s), dtype=np.complex128)
+        _check(lib.mvpb_stress_modes(self.h, nk, _dptr(Q), nb, U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0))
+        return S
 
     def solve_device(self, Q, n_bands: int, omega_ptr: int, flags: int = F_DEVICE_PTRS):
         """Write frequencies to device memory at omega_ptr (e.g. DeviceBuffer.value)."""
