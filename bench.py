@@ -253,6 +253,22 @@ def variant_hex_1132(mvpb, ctx, steps, warmup):
             "polygons": len(c.polygons)}, out["om"], (c, M, Q, nb)
 
 
+def variant_stress(mvpb, ctx, dcell, M, Q, nb, steps, warmup):
+    """Same cell and k list as the headline, FP64, with the displacement modes
+    U and the stress modes S = -Phi^-1 H* U returned to the host."""
+    out = {}
+
+    def step():
+        plan = dcell.plan(M)
+        om, U = plan.solve(Q, nb, vectors=True)
+        out["om"], out["U"], out["S"] = om, U, plan.stress(Q, U)
+        plan.close()
+
+    dt = run_timed(step, steps, warmup, mvpb, "stress modes")
+    return {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt, "precision": "fp64",
+            "outputs": "omega, U (2N per band), S (3N per band), host"}, out
+
+
 def variant_surrogate(mvpb, ctx, n_train=4096, n_test=256, epochs=30):
     """Binary GRF cells on 32x32 (correlation length 4 px, fill U[0.2,0.8]),
     labels by the batched FP64 solver at 15x15 plane waves, 40 k, 10 bands;
@@ -419,9 +435,11 @@ def main():
                      "traffic": measured_traffic(name)})
     omega = om_dev.to_numpy(np.float64, (Q.shape[0], nb))
     variants = {}
-    om_mixed = om_batch = cfg2 = om_prec = cfg3 = om_hex = hexcfg = om_h1132 = h1132cfg = None
+    om_mixed = om_batch = cfg2 = om_prec = cfg3 = om_hex = hexcfg = om_h1132 = h1132cfg = stress_out = None
     if not args.no_variants:
         variants["mixed_1132_phase"], om_mixed = variant_mixed(mvpb, ctx, dcell, M, Q, nb, args.steps, args.warmup)
+        variants["stress_modes_1132_phase"], stress_out = variant_stress(mvpb, ctx, dcell, M, Q, nb,
+                                                                        max(1, args.steps // 2), 1)
         variants["batched_256_cells"], om_batch, cfg2 = variant_batched(mvpb, ctx, max(1, args.steps // 2), 1)
         variants["surrogate_grf_cells"] = variant_surrogate(mvpb, ctx)
         variants["precision_4096_phase"], om_prec, cfg3 = variant_precision(mvpb, ctx)
@@ -459,6 +477,18 @@ def main():
             ref3, _ = mo.bands(c3.phase, c3.props, c3.lattice, cfg3["M"], cfg3["M"], cfg3["Q"][kk], cfg3["n_bands"])
             for name, om in om_prec.items():
                 variants["precision_4096_phase"][name]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om[kk], ref3)
+        if stress_out is not None:
+            from oracle import mixed_oracle as mo
+            kk = [5, 30]
+            progress("cpu baseline: oracle stress modes on", len(kk), "k-points")
+            I = mo.subdomain_integral_tables(cell.phase, cell.n_phases, cell.lattice, M, M)
+            tabs = mo.phase_sum_tables(I, cell.props)
+            worst = 0.0
+            for t in kk:
+                mats = mo.assemble(I, cell.props, cell.lattice, M, M, Q[t], tables=tabs)
+                ref = mo.stress_vector(mats, stress_out["U"][t].T)
+                worst = max(worst, float(np.max(np.abs(stress_out["S"][t].T - ref)) / np.max(np.abs(ref))))
+            variants["stress_modes_1132_phase"]["max_rel_stress_err_vs_fp64_oracle"] = worst
         if om_hex is not None:
             from oracle import mixed_oracle as mo
             from oracle.compare import band_error
