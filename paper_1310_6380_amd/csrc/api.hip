@@ -1021,8 +1021,23 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     HIP_TRY(ptrs.alloc(sizeof(void *) * hp.size()));
     HIP_TRY(hipMemcpyAsync(ptrs.p, hp.data(), sizeof(void *) * hp.size(), hipMemcpyHostToDevice, st));
     void **dp = ptrs.as<void *>();
-    // all items of one call share N (single plan) or are issued per item
-    for (int i = 0; i < n_items; ++i) {
+    // items of one N (every mvpb_solve call): two batched products and one
+    // normalisation over all of them; otherwise item by item
+    bool same_n = true;
+    for (int i = 1; i < n_items; ++i) same_n = same_n && jobs[i].plan->N == jobs[0].plan->N;
+    if (same_n) {
+      const int N = jobs[0].plan->N, n = 2 * N;
+      GemmBatch b1{(const cd *const *)(dp + 0 * n_items), (const cd *const *)(dp + 2 * n_items),
+                   (cd *const *)(dp + 4 * n_items), nullptr, N, n, n};
+      HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), b1, mk(0.0, 0.0), n_items, st));
+      GemmBatch b2{(const cd *const *)(dp + 1 * n_items), (const cd *const *)(dp + 3 * n_items),
+                   (cd *const *)(dp + 5 * n_items), nullptr, N, n, n};
+      HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), b2, mk(0.0, 0.0), n_items, st));
+      // the output indices of the items are a permutation of 0 .. n_items-1
+      hipLaunchKernelGGL(normalize_phase, dim3(n_items * nb), dim3(256), 0, st, (cd *)U_dev, n, n_items * nb);
+      HIP_TRY(hipGetLastError());
+    }
+    for (int i = 0; i < n_items && !same_n; ++i) {
       const int N = jobs[i].plan->N, n = 2 * N;
       GemmBatch b1{(const cd *const *)(dp + 0 * n_items + i), (const cd *const *)(dp + 2 * n_items + i),
                    (cd *const *)(dp + 4 * n_items + i), nullptr, N, n, n};
