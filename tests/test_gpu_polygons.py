@@ -138,3 +138,21 @@ def test_hex_1132_element_cell_matches_oracle(ctx):
     err = band_error(om, ref)
     _say("  band error", err)
     assert err <= TOL64, err
+
+
+def test_polygon_cells_in_batched_solve(ctx):
+    """Polygon and pixel cells of different cutoffs through the batched plan
+    build and the batched solve: the same frequencies as one solve each."""
+    c = hex_steel_epoxy(32)
+    pc = ctx.cell_polygons(c.polygons, c.poly_phase, c.props, c.lattice)
+    rng = np.random.default_rng(3)
+    phase = rng.integers(0, 2, (8, 8)).astype(np.int32)
+    xc = ctx.cell(phase, random_iso_props(2, rng), np.eye(2))
+    cells, Ms = [pc, xc, pc], [3, 4, 5]
+    Qs = [kpath_xgjx(5), np.array([[0.1, 0.2], [0.5, 0.0]]), kpath_xgjx(4)]
+    _say("polygon cells in a batched solve")
+    plans = ctx.plans(cells, Ms)
+    outs = ctx.solve_batch(plans, Qs, 8)
+    for cell, M, Q, om in zip(cells, Ms, Qs, outs):
+        ref = cell.plan(M).solve(Q, 8)
+        assert np.max(np.abs(om - ref) / np.maximum(np.abs(ref), 1e-300 + np.abs(ref).max() * 1e-12)) <= 1e-9
