@@ -73,6 +73,7 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
     {
       const cd lcj = conj(colj[c_]);   // used for c > j only
       const cd dij = Di[j][c_];         // used for c <= j only
+#pragma unroll 4
       for (int r = j + 1 + ((w_ - j - 1) & 3); r < nb; r += 4) {
         const cd lrj = colj[r];
         if (c_ <= j) {
