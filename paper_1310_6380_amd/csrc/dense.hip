@@ -29,10 +29,12 @@ constexpr int CB = 64;
 // elimination scales column j of L and row j of the inverse, then updates
 // the trailing lower triangle of the block and the rows of the inverse below
 // j (forward elimination of [L | I]).  The diagonal of L is kept apart so that
-// the pivot of the next step is read without a third barrier.
+// the pivot of the next step is read without a third barrier.  [Xi | L] sit
+// side by side in one LDS array, so that in the update every lane (column c
+// of [Xi | L]) does the same read-modify-write per row: of Xi for c <= j, of
+// L for c > j (the upper triangle of L is updated too, never read).
 __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xarr, int *status, int N, int jb) {
-  __shared__ cd D[CB][CB + 1];
-  __shared__ cd Di[CB][CB + 1];
+  __shared__ cd DD[CB][2 * CB + 1];   // DD[r][c] = Xi[r][c], DD[r][CB + c] = L[r][c]
   __shared__ double dg[CB];
   __shared__ cd colj[CB];   // column j of L below the diagonal
   const int b = blockIdx.x;
@@ -44,12 +46,12 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
   const size_t ld = (size_t)N;
   for (int e = tid; e < CB * CB; e += 256) {
     const int r = e % CB, c = e / CB;
-    D[r][c] = (r < nb && c < nb && r >= c) ? A[(size_t)(jb + c) * ld + jb + r] : mk(0.0, 0.0);
-    Di[r][c] = mk(r == c ? 1.0 : 0.0, 0.0);
+    DD[r][CB + c] = (r < nb && c < nb && r >= c) ? A[(size_t)(jb + c) * ld + jb + r] : mk(0.0, 0.0);
+    DD[r][c] = mk(r == c ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
-    const double piv = D[j][j].re;
+    const double piv = DD[j][CB + j].re;
     if (!(piv > 0.0) || !isfinite(piv)) {
       if (tid == 0) status[b] = jb + j + 1;
       return;   // uniform: every thread read the same pivot
@@ -59,36 +61,29 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
     if (tid < CB) {
       const int r = tid;
       if (r > j && r < nb) {
-        const cd l = inv * D[r][j];
-        D[r][j] = l;
+        const cd l = inv * DD[r][CB + j];
+        DD[r][CB + j] = l;
         colj[r] = l;
       }
-      if (r <= j) Di[j][r] = inv * Di[j][r];
+      if (r <= j) DD[j][r] = inv * DD[j][r];
       if (r == 0) dg[j] = sq;
     }
     __syncthreads();
     // lane = column c, wavefront w = rows r = w (mod 4) below j:
-    // D[r][c] -= L[r][j] conj(L[c][j]) for j < c <= r;
-    // Di[r][c] -= L[r][j] Di[j][c] for c <= j
+    // Xi[r][c] -= L[r][j] Xi[j][c] for c <= j; L[r][c] -= L[r][j] conj(L[c][j]) for c > j
     {
-      const cd lcj = conj(colj[c_]);   // used for c > j only
-      const cd dij = Di[j][c_];         // used for c <= j only
+      const bool inv_col = c_ <= j;
+      const int cc = inv_col ? c_ : CB + c_;
+      const cd op = inv_col ? DD[j][c_] : conj(colj[c_]);
 #pragma unroll 4
-      for (int r = j + 1 + ((w_ - j - 1) & 3); r < nb; r += 4) {
-        const cd lrj = colj[r];
-        if (c_ <= j) {
-          Di[r][c_] = Di[r][c_] - lrj * dij;
-        } else if (c_ <= r) {
-          D[r][c_] = D[r][c_] - lrj * lcj;
-        }
-      }
+      for (int r = j + 1 + ((w_ - j - 1) & 3); r < nb; r += 4) DD[r][cc] = DD[r][cc] - colj[r] * op;
     }
     __syncthreads();
   }
   for (int e = tid; e < nb * nb; e += 256) {
     const int r = e % nb, c = e / nb;
-    if (r >= c) A[(size_t)(jb + c) * ld + jb + r] = (r == c) ? mk(dg[r], 0.0) : D[r][c];
-    X[(size_t)(jb + c) * ld + jb + r] = (r >= c) ? Di[r][c] : mk(0.0, 0.0);
+    if (r >= c) A[(size_t)(jb + c) * ld + jb + r] = (r == c) ? mk(dg[r], 0.0) : DD[r][CB + c];
+    X[(size_t)(jb + c) * ld + jb + r] = (r >= c) ? DD[r][c] : mk(0.0, 0.0);
   }
 }
 
