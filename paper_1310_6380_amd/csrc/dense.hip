@@ -317,8 +317,16 @@ hipError_t launch_potrf_trtri(cd *const *A, cd *const *Linv, int *status, int co
 }
 
 // ---------------------------------------------------------------------------
-// Batched complex GEMM, 64 x 64 tiles, 256 threads, 4 x 4 outputs per thread.
+// Batched complex GEMM, 64 x 64 tiles, 256 threads, on the FP64 matrix cores:
+// wavefront wv owns tile rows 16 wv .. 16 wv + 15 and the four 16 x 16 column
+// blocks.  Each complex step is three real 16x16x4 products (Gauss:
+// p1 = ar br, p2 = ai bi, p3 = (ar + ai)(br + bi); re = p1 - p2,
+// im = p3 - p1 - p2).  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// of a 4-deep step and holds D[l / 16 + 4 v][l % 16].  (Deeper K tiles with
+// the next tile prefetched into registers need more than 256 registers and
+// halve the occupancy: slower.)
 // ---------------------------------------------------------------------------
+typedef double zd4_t __attribute__((ext_vector_type(4)));
 template <int OPA, int OPB>
 __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, cd alpha, GemmBatch bt, cd beta) {
   constexpr int BM = 64, BN = 64, BK = 8;
@@ -330,12 +338,11 @@ __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, cd alph
   cd *__restrict__ C = bt.C[b];
   const double *__restrict__ s = bt.s ? bt.s[b] : nullptr;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  cd acc[4][4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int ai = lane & 15, ak = lane >> 4;
+  zd4_t p1[4], p2[4], p3[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
+  for (int c = 0; c < 4; ++c) p1[c] = p2[c] = p3[c] = zd4_t{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += BK) {
     // A tile: 64 x 8
     for (int e = tid; e < BM * BK; e += 256) {
@@ -360,32 +367,31 @@ __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, cd alph
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      cd av[4], bv[4];
+    for (int kk = 0; kk < BK; kk += 4) {
+      const cd av = As[kk + ak][16 * wv + ai];
+      const double as = av.re + av.im;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][ty + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(av[a], bv[c], acc[a][c]);
+      for (int c = 0; c < 4; ++c) {
+        const cd bv = Bs[kk + ak][16 * c + ai];
+        p1[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.re, bv.re, p1[c], 0, 0, 0);
+        p2[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.im, bv.im, p2[c], 0, 0, 0);
+        p3[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bv.re + bv.im, p3[c], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
   const bool use_beta = (beta.re != 0.0 || beta.im != 0.0);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const int gj = n0 + ty + 16 * c;
-    if (gj >= N) continue;
+    const int gj = n0 + 16 * c + ai;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int gi = m0 + tx + 16 * a;
-      if (gi >= M) continue;
-      cd v = alpha * acc[a][c];
+    for (int v = 0; v < 4; ++v) {
+      const int gi = m0 + 16 * wv + ak + 4 * v;
+      if (gj >= N || gi >= M) continue;
+      cd x = alpha * mk(p1[c][v] - p2[c][v], p3[c][v] - p1[c][v] - p2[c][v]);
       cd *dst = C + (size_t)gj * bt.ldc + gi;
-      if (use_beta) v = v + beta * (*dst);
-      *dst = v;
+      if (use_beta) x = x + beta * (*dst);
+      *dst = x;
     }
   }
 }
