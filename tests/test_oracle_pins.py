@@ -393,3 +393,25 @@ def test_polygon_cell_partition_and_holes():
     assert np.allclose(I[:, ::-1, ::-1], I.conj(), atol=1e-15 * area)
     # phase areas: the n-gon has the disk's area
     assert abs(I[1, 2 * M, 2 * M].real - np.pi * (2e-3) ** 2) <= 1e-12 * area
+
+
+def test_hex_1132_element_cell_tiles_the_cell():
+    """The 1132-element hexagonal cell (Sec. 5): exactly 1132 elements, every
+    one its own phase, counter-clockwise, tiling the primitive cell (partition
+    of unity of the oracle's polygon integrals), density 10^6 x centroid x2."""
+    from synth import hex_graded_1132
+    c = hex_graded_1132()
+    assert len(c.polygons) == 1132 and c.n_phases == 1132
+    areas = np.array([0.5 * np.sum(v[:, 0] * np.roll(v[:, 1], -1) - np.roll(v[:, 0], -1) * v[:, 1])
+                      for v in c.polygons])
+    assert np.all(areas > 0)
+    _, _, area, _ = mo.lattice_quantities(c.lattice)
+    assert abs(areas.sum() - area) <= 1e-12 * area
+    cent_y = np.array([np.mean(v[:, 1]) for v in c.polygons])
+    assert np.allclose(c.props[:, 2], 1e6 * cent_y)
+    M = 2
+    I = mo.polygon_integral_tables(c.polygons, c.poly_phase, c.n_phases, c.lattice, M, M)
+    J = I.sum(axis=0)
+    ref = np.zeros_like(J)
+    ref[2 * M, 2 * M] = area
+    assert np.max(np.abs(J - ref)) <= 1e-13 * area
