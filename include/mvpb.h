@@ -50,7 +50,7 @@ enum {
   MVPB_E_NOT_PD = -2,      /* a compliance/density matrix is not positive definite */
   MVPB_E_NOMEM = -3,       /* device allocation failed or workspace cap exceeded */
   MVPB_E_DEVICE = -4,      /* HIP runtime error */
-  MVPB_E_UNSUPPORTED = -5  /* valid request that this build does not implement */
+  MVPB_E_UNSUPPORTED = -5  /* valid request that the library does not implement */
 };
 
 /* Property table layouts (one row per phase). */

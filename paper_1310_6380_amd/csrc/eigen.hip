@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigIte
   const double glo = ldexp(gl, -sex) - slack, ghi = ldexp(gu, -sex) + slack;
   const double tol_abs = 2.0 * DBL_EPSILON * bn;
   __syncthreads();
-  // round 0: one set of probes for every eigenvalue
+  // pass 0: one set of probes for every eigenvalue
   {
     const double x = glo + (ghi - glo) * (double)(tid + 1) / (double)(BISI_THREADS + 1);
     xs[tid] = x;
