@@ -144,7 +144,8 @@ int mvpb_plan_destroy(mvpb_plan plan);
  *   U[((t*n_bands + b)*2N + r)], r < N the u1 coefficients, r >= N the u2
  *   coefficients, in the plane-wave order I = (alpha+M1)(2M2+1)+(beta+M2);
  *   normalised to U^H Omega U = 1 with the largest-modulus entry real > 0.
- * 1 <= n_bands <= 2N.  Q, omega and U are host pointers unless
+ * 1 <= n_bands <= min(2N, 64) (the FP64 Rayleigh-Ritz block is held in
+ * on-chip memory).  Q, omega and U are host pointers unless
  * MVPB_F_DEVICE_PTRS is set (then omega and U are device pointers; Q stays
  * on the host).  If the device could not finish a point (the reduction to
  * tridiagonal form gave up waiting on a hand-over), its frequencies are NaN;
@@ -186,6 +187,19 @@ int mvpb_structure_factors(mvpb_cell cell, int M1, int M2, int precision, double
  * Gamma.  Q: host pointer, 2*n_k doubles. */
 int mvpb_kpath_square(int n_k, double *Q);
 
+/* n_k Bloch vectors equally spaced in arc length (measured in Cartesian k,
+ * k = Q1 q^1 + Q2 q^2 with the reciprocal vectors of Sec. 2 for the lattice
+ * rows h1, h2) along the polyline through the symmetry points named by
+ * `path`, both ends included.  Letters (fractional coordinates):
+ * G = (0, 0), X = (1/2, 0), Y = (0, 1/2), M = (1/2, 1/2) and J = (2/3, 1/3),
+ * the zone corner of the hexagonal lattice h1 = a(1, 0), h2 = a(1/2, sqrt3/2).
+ * "GXMG" is the square-lattice path of Sec. 5 (same points as
+ * mvpb_kpath_square), "XGJX" the hexagonal path X-Gamma-J-X of Sec. 5.
+ * n_k = 1 gives the first point.  Q: host pointer, 2*n_k doubles.  Unknown
+ * letters, a path longer than 63 letters or a degenerate lattice:
+ * MVPB_E_INVALID. */
+int mvpb_kpath(const double lattice[4], const char *path, int n_k, double *Q);
+
 /* Plain device-to-device copy of `bytes` bytes (a multiple of 16, buffers
  * 16-byte aligned and not overlapping) by one kernel (copy16) on the context
  * stream; returns when it has finished.  It reads and writes each byte once,
@@ -220,6 +234,15 @@ int mvpb_sur_gradients(mvpb_sur net, int batch, const uint8_t *cells, const floa
 /* one Adam step on the batch; *loss (nullable) is the loss before the step */
 int mvpb_sur_train_step(mvpb_sur net, int batch, const uint8_t *cells, const float *target, float lr,
                         float *loss, unsigned flags);
+/* Checkpoint: the parameters, both Adam moments, the Adam step counter, the
+ * product precision and the initialisation seed, written to the file `path`
+ * (host-endian binary, a 40-byte header then 3 * n_params floats).
+ * mvpb_sur_load creates a network on ctx for batches up to max_batch from
+ * such a file; training continues exactly where the saved network stopped.
+ * A file that is not such a checkpoint (or holds non-finite values):
+ * MVPB_E_INVALID. */
+int mvpb_sur_save(mvpb_sur net, const char *path);
+int mvpb_sur_load(mvpb_ctx ctx, const char *path, int max_batch, mvpb_sur *out);
 
 /* Kernel timers (diagnostics).  With profiling on, every kernel launch of a
  * context is bracketed by HIP events on the context stream and its device

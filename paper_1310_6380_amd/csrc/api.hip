@@ -157,7 +157,17 @@ struct mvpb_ctx_s {
   DevBuf ws{&pool};      // per-solve workspace (grow-only)
   DevBuf items{&pool};   // item table
   DevBuf scratch{&pool}; // small host-visible results staging
-  std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences by batch signature
+  // Captured launch sequences of the eigensolve, keyed by everything that
+  // fixes their launch shapes (item orders, bands, precision, stage-1 parts;
+  // see launch_signature).  The kernels find their matrices through the item
+  // table, which is uploaded before every replay, so a graph never refers to
+  // a plan.  At most MAX_GRAPHS are kept; the least recently used goes first.
+  struct GraphEntry {
+    hipGraphExec_t exec;
+    unsigned long long last_use;
+  };
+  std::map<std::string, GraphEntry> graphs;
+  unsigned long long graph_clock = 0;
   std::vector<EigItem> host_items;                // staging of the item table (kept alive for async copies)
   Profiler prof;
   int children = 0;     // live cells and plans
@@ -167,7 +177,7 @@ struct mvpb_ctx_s {
 static void ctx_free(mvpb_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   c->graphs.clear();
   c->ws.release();
   c->items.release();
@@ -803,6 +813,12 @@ static size_t item_bytes(int n, int nb, bool fp32) {
   return s;
 }
 
+// Bulge-chasing control words of a launch sequence over n items (placed
+// after the items in the workspace).
+static size_t ctl_bytes(size_t n_items) { return align256(sizeof(int) * hb2st_ctl_ints((int)n_items)); }
+// Workspace of a launch sequence over n items of per bytes each.
+static size_t solve_bytes(size_t n_items, size_t per) { return n_items * per + ctl_bytes(n_items); }
+
 static EigItem carve_item(char *base, int n, int nb, bool fp32) {
   size_t sz[32];
   int cnt = 0;
@@ -894,8 +910,26 @@ struct Job {
   int out_index;   // position in the caller's flattened output
 };
 
+constexpr size_t MAX_GRAPHS = 16;
+
+// Everything the launch shapes of one eigensolve sequence depend on: the
+// order 2N of every item in table order (which fixes the workspace carving,
+// the stage-1 parts' size ranges and the grids), the bands, the reduction
+// precision and the number of stage-1 parts.
+static std::string launch_signature(const std::vector<Job> &jobs, int nb, bool fp32, int parts) {
+  std::string k;
+  k.reserve(16 + 4 * jobs.size());
+  auto put = [&](int v) { k.append(reinterpret_cast<const char *>(&v), sizeof v); };
+  put(nb);
+  put(fp32 ? 1 : 0);
+  put(parts);
+  put((int)jobs.size());
+  for (const Job &j : jobs) put(j.plan->N);
+  return k;
+}
+
 static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double *omega_dev, double *U_dev,
-                     bool use_graph, const std::string &graph_key) {
+                     bool use_graph) {
   // the reduction precision is shared by every item of one launch sequence
   const bool fp32 = jobs.empty() ? false : (jobs[0].plan->prec & MVPB_PREC_EIG_FP32_RR64) != 0;
   hipStream_t st = ctx->stream;
@@ -910,14 +944,14 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     n_min = std::min(n_min, n);
   }
   const size_t ctl_off = total;   // bulge-chasing launch control words after the items
-  total += align256(sizeof(int) * hb2st_ctl_ints(n_items));
+  total += ctl_bytes(n_items);
   if (ctx->cap && total > ctx->cap)
     return set_err(MVPB_E_NOMEM, "workspace %zu bytes exceeds the cap of %zu bytes", total, ctx->cap);
   const bool realloc = total > ctx->ws.bytes || sizeof(EigItem) * n_items > ctx->items.bytes;
   if (realloc) {
     // captured graphs point into the old buffers
     HIP_TRY(hipStreamSynchronize(st));
-    for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second.exec);
     ctx->graphs.clear();
   }
   HIP_TRY(ctx->ws.reserve(total));
@@ -979,9 +1013,18 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     return e;
   };
   if (use_graph) {
+    const std::string graph_key = launch_signature(jobs, nb, fp32, stage1_parts());
     auto found = ctx->graphs.find(graph_key);
     hipGraphExec_t exec = nullptr;
     if (found == ctx->graphs.end()) {
+      if (ctx->graphs.size() >= MAX_GRAPHS) {
+        auto lru = ctx->graphs.begin();
+        for (auto it = ctx->graphs.begin(); it != ctx->graphs.end(); ++it)
+          if (it->second.last_use < lru->second.last_use) lru = it;
+        HIP_TRY(hipStreamSynchronize(st));
+        (void)hipGraphExecDestroy(lru->second.exec);
+        ctx->graphs.erase(lru);
+      }
       hipGraph_t g;
       HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       Profiler *saved = t_prof;
@@ -994,9 +1037,10 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
       e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return set_err(MVPB_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-      ctx->graphs[graph_key] = exec;
+      ctx->graphs[graph_key] = mvpb_ctx_s::GraphEntry{exec, ++ctx->graph_clock};
     } else {
-      exec = found->second;
+      exec = found->second.exec;
+      found->second.last_use = ++ctx->graph_clock;
     }
     HIP_TRY(hipGraphLaunch(exec, st));
   } else {
@@ -1141,12 +1185,15 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
   hipStream_t st = ctx->stream;
   const bool dev = flags & MVPB_F_DEVICE_PTRS;
   const int n = 2 * p->N;
-  // chunk the k list so that the workspace stays within the cap
-  int chunk = n_k;
+  // chunk the k list so that the workspace (items and the bulge-chasing
+  // control words) stays within the cap
   const size_t per = item_bytes(n, n_bands, (p->prec & MVPB_PREC_EIG_FP32_RR64) != 0);
   const size_t budget = ctx->cap ? ctx->cap : (size_t)32 << 30;
-  if (per > budget) return set_err(MVPB_E_NOMEM, "one item needs %zu bytes, cap is %zu", per, budget);
-  chunk = (int)std::min<size_t>((size_t)n_k, budget / per);
+  if (solve_bytes(1, per) > budget)
+    return set_err(MVPB_E_NOMEM, "one item needs %zu bytes, cap is %zu", solve_bytes(1, per), budget);
+  int chunk = (int)std::min<size_t>((size_t)n_k, budget / per);
+  while (chunk > 1 && solve_bytes(chunk, per) > budget) --chunk;
+  const bool graph = !(ctx->prof.on);
   DevBuf om_dev(&ctx->pool), u_dev(&ctx->pool);
   double *om_out = omega;
   double *u_out = U;
@@ -1163,7 +1210,7 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
     std::vector<Job> jobs(kc);
     for (int t = 0; t < kc; ++t) jobs[t] = Job{p, Q[2 * (k0 + t)], Q[2 * (k0 + t) + 1], t};
     int rc = run_items(ctx, jobs, n_bands, om_out + (size_t)k0 * n_bands,
-                       u_out ? u_out + 2 * (size_t)k0 * n_bands * n : nullptr, false, "");
+                       u_out ? u_out + 2 * (size_t)k0 * n_bands * n : nullptr, graph);
     if (rc) return rc;
   }
   if (!dev) {
@@ -1187,13 +1234,6 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
   if (n_bands < 1 || n_bands > RR_MAX_BANDS) return set_err(MVPB_E_INVALID, "n_bands = %d out of range", n_bands);
   std::vector<Job> jobs;
   std::vector<size_t> base(n_plans + 1, 0);
-  // signature of the batch (plans, k lists, bands) for the graph cache
-  uint64_t hsh = 1469598103934665603ull;
-  auto mix = [&](const void *p, size_t len) {
-    const unsigned char *b = (const unsigned char *)p;
-    for (size_t i = 0; i < len; ++i) hsh = (hsh ^ b[i]) * 1099511628211ull;
-  };
-  mix(&n_bands, sizeof n_bands);
   for (int i = 0; i < n_plans; ++i) {
     if (!plans[i] || plans[i]->ctx != ctx) return set_err(MVPB_E_INVALID, "plan %d missing or from another context", i);
     if (n_k[i] < 0 || (n_k[i] > 0 && (!Q[i] || !omega[i]))) return set_err(MVPB_E_INVALID, "plan %d: bad k list", i);
@@ -1202,15 +1242,9 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
       return set_err(MVPB_E_INVALID, "plan %d: all plans of a batch need the same eigensolver precision", i);
     if (!q_ok(Q[i], n_k[i])) return set_err(MVPB_E_INVALID, "plan %d: non-finite Bloch vector", i);
     base[i + 1] = base[i] + n_k[i];
-    mix(&plans[i], sizeof(void *));
-    mix(&n_k[i], sizeof(int));
-    if (n_k[i] > 0) mix(Q[i], sizeof(double) * 2 * n_k[i]);
     for (int t = 0; t < n_k[i]; ++t)
       jobs.push_back(Job{plans[i], Q[i][2 * t], Q[i][2 * t + 1], (int)(base[i] + t)});
   }
-  char keybuf[32];
-  snprintf(keybuf, sizeof keybuf, "%016llx", (unsigned long long)hsh);
-  const std::string key = keybuf;
   if (jobs.empty()) return MVPB_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
@@ -1222,7 +1256,6 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
   DevBuf om(&ctx->pool);
   HIP_TRY(om.alloc(sizeof(double) * base[n_plans] * n_bands));
   size_t j0 = 0;
-  int chunk = 0;
   while (j0 < jobs.size()) {
     size_t j1 = j0, bytes = 0;
     const int n0 = 2 * jobs[j0].plan->N;
@@ -1230,16 +1263,16 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
       const size_t b = item_bytes(2 * jobs[j1].plan->N, n_bands, fp32);
       // keep items of one chunk within a factor ~1.5 in order so that the
       // launch sequence sized for the largest wastes little on the rest
-      if (j1 > j0 && (bytes + b > budget || 3 * jobs[j1].plan->N < n0)) break;
+      if (j1 > j0 && (bytes + b + ctl_bytes(j1 - j0 + 1) > budget || 3 * jobs[j1].plan->N < n0)) break;
       bytes += b;
       ++j1;
     }
-    if (bytes > budget) return set_err(MVPB_E_NOMEM, "one item needs %zu bytes, cap is %zu", bytes, budget);
+    if (bytes + ctl_bytes(j1 - j0) > budget)
+      return set_err(MVPB_E_NOMEM, "one item needs %zu bytes, cap is %zu", bytes + ctl_bytes(j1 - j0), budget);
     std::vector<Job> part(jobs.begin() + j0, jobs.begin() + j1);
-    rc = run_items(ctx, part, n_bands, om.as<double>(), nullptr, true, key + "#" + std::to_string(chunk));
+    rc = run_items(ctx, part, n_bands, om.as<double>(), nullptr, true);
     if (rc) return rc;
     j0 = j1;
-    ++chunk;
   }
   const bool dev = flags & MVPB_F_DEVICE_PTRS;
   for (int i = 0; i < n_plans; ++i) {
@@ -1297,6 +1330,56 @@ extern "C" int mvpb_kpath_square(int n_k, double *Q) {
     const double u = (s - cum[k]) / seg[k];
     Q[2 * t] = cx[k] + u * (cx[k + 1] - cx[k]);
     Q[2 * t + 1] = cy[k] + u * (cy[k + 1] - cy[k]);
+  }
+  return MVPB_OK;
+}
+
+// Symmetry points by letter, fractional in (q1, q2).
+static bool kpoint(char c, double *q) {
+  switch (c) {
+    case 'G': q[0] = 0.0; q[1] = 0.0; return true;
+    case 'X': q[0] = 0.5; q[1] = 0.0; return true;
+    case 'Y': q[0] = 0.0; q[1] = 0.5; return true;
+    case 'M': q[0] = 0.5; q[1] = 0.5; return true;
+    case 'J': q[0] = 2.0 / 3.0; q[1] = 1.0 / 3.0; return true;
+    default: return false;
+  }
+}
+
+extern "C" int mvpb_kpath(const double lattice[4], const char *path, int n_k, double *Q) {
+  if (!lattice || !path || !Q || n_k < 1) return set_err(MVPB_E_INVALID, "bad arguments");
+  double T[4], area;
+  if (!lattice_ok(lattice, T, &area)) return set_err(MVPB_E_INVALID, "degenerate or non-finite lattice");
+  const int nc = (int)strnlen(path, 64);
+  if (nc < 1 || nc >= 64) return set_err(MVPB_E_INVALID, "path must have 1 to 63 letters");
+  std::vector<double> fr(2 * nc), cum(nc, 0.0);
+  for (int c = 0; c < nc; ++c)
+    if (!kpoint(path[c], &fr[2 * c])) return set_err(MVPB_E_INVALID, "unknown symmetry point '%c'", path[c]);
+  // arc length in Cartesian k = Q1 q^1 + Q2 q^2, q^i = 2 pi (column i of T)
+  auto cart = [&](const double *f, double *k) {
+    k[0] = 2.0 * M_PI * (T[0] * f[0] + T[1] * f[1]);
+    k[1] = 2.0 * M_PI * (T[2] * f[0] + T[3] * f[1]);
+  };
+  for (int c = 1; c < nc; ++c) {
+    double a[2], b[2];
+    cart(&fr[2 * (c - 1)], a);
+    cart(&fr[2 * c], b);
+    cum[c] = cum[c - 1] + hypot(b[0] - a[0], b[1] - a[1]);
+  }
+  if (n_k == 1 || nc == 1 || !(cum[nc - 1] > 0.0)) {
+    if (n_k > 1) return set_err(MVPB_E_INVALID, "path of zero length for %d points", n_k);
+    Q[0] = fr[0];
+    Q[1] = fr[1];
+    return MVPB_OK;
+  }
+  for (int t = 0; t < n_k; ++t) {
+    const double s = cum[nc - 1] * (double)t / (double)(n_k - 1);
+    int k = 0;
+    while (k < nc - 2 && s >= cum[k + 1]) ++k;
+    const double len = cum[k + 1] - cum[k];
+    const double u = len > 0.0 ? (s - cum[k]) / len : 0.0;
+    Q[2 * t] = fr[2 * k] + u * (fr[2 * k + 2] - fr[2 * k]);
+    Q[2 * t + 1] = fr[2 * k + 1] + u * (fr[2 * k + 3] - fr[2 * k + 1]);
   }
   return MVPB_OK;
 }

@@ -12,6 +12,7 @@
 // (v_mfma_f32_16x16x16bf16_1k); master weights and Adam moments stay FP32.
 #include <math.h>
 #include <stdio.h>
+#include <string.h>
 
 #include <vector>
 
@@ -339,6 +340,7 @@ struct mvpb_sur_s {
   int n_params = 0;
   int off[12];
   long long step = 0;
+  uint64_t seed = 0;
   Buf<float> params, grads, m, v;
   Buf<float> act[5];        // act[0] input [B,32,32,1]; act[l+1] output of conv l (NHWC)
   Buf<float> col, dcol, dact, dact2;
@@ -479,6 +481,7 @@ extern "C" int mvpb_sur_create(mvpb_ctx ctx, int max_batch, int precision, uint6
   net->st = ctx_stream(ctx);
   net->max_batch = max_batch;
   net->bf16 = precision == 1;
+  net->seed = seed;
   net->n_params = param_offsets(net->off);
   const size_t B = max_batch;
   size_t colmax = 0, actmax = 0;
@@ -635,5 +638,86 @@ extern "C" int mvpb_sur_train_step(mvpb_sur net, int batch, const uint8_t *cells
                      net->m.p, net->v.p, net->n_params, lr, b1, b2, 1e-8f, c1, c2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "adam: %s", hipGetErrorString(e));
+  return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Checkpoints: header, then the parameters and both Adam moments (FP32,
+// little-endian as in memory).
+// ---------------------------------------------------------------------------
+namespace {
+struct SurHeader {
+  char magic[8];          // "MVPBSUR1"
+  int32_t version;        // 1
+  int32_t n_params;
+  int32_t precision;      // 0 FP32, 1 BF16 products
+  int32_t reserved;
+  int64_t step;           // Adam steps taken (bias-correction counter)
+  uint64_t seed;          // initialisation seed of the network
+};
+const char kSurMagic[8] = {'M', 'V', 'P', 'B', 'S', 'U', 'R', '1'};
+}  // namespace
+
+extern "C" int mvpb_sur_save(mvpb_sur net, const char *path) {
+  if (!net || !path) return set_error(MVPB_E_INVALID, "NULL argument");
+  (void)hipSetDevice(ctx_device(net->ctx));
+  const size_t n = (size_t)net->n_params;
+  std::vector<float> buf(3 * n);
+  hipError_t e = hipMemcpyAsync(buf.data(), net->params.p, sizeof(float) * n, hipMemcpyDeviceToHost, net->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(buf.data() + n, net->m.p, sizeof(float) * n, hipMemcpyDeviceToHost, net->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(buf.data() + 2 * n, net->v.p, sizeof(float) * n, hipMemcpyDeviceToHost, net->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->st);
+  if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "save: %s", hipGetErrorString(e));
+  SurHeader h{};
+  memcpy(h.magic, kSurMagic, 8);
+  h.version = 1;
+  h.n_params = net->n_params;
+  h.precision = net->bf16 ? 1 : 0;
+  h.step = net->step;
+  h.seed = net->seed;
+  FILE *f = fopen(path, "wb");
+  if (!f) return set_error(MVPB_E_INVALID, "cannot open %s for writing", path);
+  const bool ok = fwrite(&h, sizeof h, 1, f) == 1 && fwrite(buf.data(), sizeof(float), 3 * n, f) == 3 * n;
+  const bool closed = fclose(f) == 0;
+  if (!ok || !closed) return set_error(MVPB_E_INVALID, "write to %s failed", path);
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_sur_load(mvpb_ctx ctx, const char *path, int max_batch, mvpb_sur *out) {
+  if (!ctx || !path || !out) return set_error(MVPB_E_INVALID, "NULL argument");
+  FILE *f = fopen(path, "rb");
+  if (!f) return set_error(MVPB_E_INVALID, "cannot open %s", path);
+  SurHeader h{};
+  std::vector<float> buf;
+  bool ok = fread(&h, sizeof h, 1, f) == 1 && memcmp(h.magic, kSurMagic, 8) == 0 && h.version == 1 &&
+            (h.precision == 0 || h.precision == 1) && h.step >= 0;
+  int off[12];
+  ok = ok && h.n_params == param_offsets(off);
+  if (ok) {
+    buf.resize(3 * (size_t)h.n_params);
+    ok = fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;   // nothing after the moments
+  }
+  fclose(f);
+  if (!ok) return set_error(MVPB_E_INVALID, "%s is not a surrogate checkpoint of this network", path);
+  for (float x : buf)
+    if (!isfinite(x)) return set_error(MVPB_E_INVALID, "%s holds non-finite values", path);
+  mvpb_sur net = nullptr;
+  int rc = mvpb_sur_create(ctx, max_batch, h.precision, h.seed, &net);
+  if (rc) return rc;
+  const size_t n = (size_t)h.n_params;
+  hipError_t e = hipMemcpyAsync(net->params.p, buf.data(), sizeof(float) * n, hipMemcpyHostToDevice, net->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(net->m.p, buf.data() + n, sizeof(float) * n, hipMemcpyHostToDevice, net->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(net->v.p, buf.data() + 2 * n, sizeof(float) * n, hipMemcpyHostToDevice, net->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->st);
+  if (e != hipSuccess) {
+    mvpb_sur_destroy(net);
+    return set_error(MVPB_E_DEVICE, "load: %s", hipGetErrorString(e));
+  }
+  net->step = h.step;
+  *out = net;
   return MVPB_OK;
 }

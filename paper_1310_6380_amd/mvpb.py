@@ -46,7 +46,8 @@ EXPORTS = [
     "mvpb_kpath_square", "mvpb_ctx_profile", "mvpb_ctx_profile_read", "mvpb_plan_create_batch",
     "mvpb_sur_create", "mvpb_sur_destroy", "mvpb_sur_n_params", "mvpb_sur_get_params", "mvpb_sur_set_params",
     "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step", "mvpb_copy_device",
-    "mvpb_ctx_profile_mask", "mvpb_cell_create_polygons", "mvpb_stress_modes",
+    "mvpb_ctx_profile_mask", "mvpb_cell_create_polygons", "mvpb_stress_modes", "mvpb_kpath",
+    "mvpb_sur_save", "mvpb_sur_load",
 ]
 N_KERNELS = 15
 
@@ -88,6 +89,7 @@ def load(path: str = LIB_PATH):
                                      ctypes.POINTER(P), ctypes.c_uint]
     lib.mvpb_structure_factors.argtypes = [P, I, I, I, D]
     lib.mvpb_kpath_square.argtypes = [I, D]
+    lib.mvpb_kpath.argtypes = [D, ctypes.c_char_p, I, D]
     lib.mvpb_plan_create_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I,
                                            ctypes.POINTER(P)]
     F = ctypes.POINTER(ctypes.c_float)
@@ -99,6 +101,8 @@ def load(path: str = LIB_PATH):
     lib.mvpb_sur_infer.argtypes = [P, I, P, P, ctypes.c_uint]
     lib.mvpb_sur_gradients.argtypes = [P, I, P, P, F, P, ctypes.c_uint]
     lib.mvpb_sur_train_step.argtypes = [P, I, P, P, ctypes.c_float, F, ctypes.c_uint]
+    lib.mvpb_sur_save.argtypes = [P, ctypes.c_char_p]
+    lib.mvpb_sur_load.argtypes = [P, ctypes.c_char_p, I, ctypes.POINTER(P)]
     lib.mvpb_copy_device.argtypes = [P, P, P, ctypes.c_size_t]
     lib.mvpb_ctx_profile.argtypes = [P, I]
     lib.mvpb_ctx_profile_mask.argtypes = [P, ctypes.c_ulonglong]
@@ -194,6 +198,15 @@ def version() -> str:
 def kpath_square(n_k: int) -> np.ndarray:
     Q = np.zeros((n_k, 2), dtype=np.float64)
     _check(load().mvpb_kpath_square(n_k, _dptr(Q)))
+    return Q
+
+
+def kpath(lattice, path: str, n_k: int) -> np.ndarray:
+    """Bloch vectors (fractional Q) equally spaced in Cartesian arc length along
+    the symmetry points of ``path`` (letters G, X, Y, M, J)."""
+    lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(4))
+    Q = np.zeros((n_k, 2), dtype=np.float64)
+    _check(load().mvpb_kpath(_dptr(lat), path.encode(), n_k, _dptr(Q)))
     return Q
 
 
@@ -430,6 +443,24 @@ class Surrogate:
             self.close()
         except Exception:
             pass
+
+    def save(self, path: str):
+        """Checkpoint (parameters, Adam moments and step) to ``path``."""
+        _check(load().mvpb_sur_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, ctx: Context, path: str, max_batch: int = 256):
+        """A network restored from a checkpoint written by ``save``."""
+        lib = load()
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib.mvpb_sur_load(ctx.h, os.fsencode(path), max_batch, ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int()
+        _check(lib.mvpb_sur_n_params(h, ctypes.byref(n)))
+        self.n_params = n.value
+        return self
 
     def get_params(self) -> np.ndarray:
         p = np.zeros(self.n_params, dtype=np.float32)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_1310_6380_amd import mvpb
-from synth import kpath_gxmg
+from synth import hex_lattice, kpath_gxmg, kpath_xgjx
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -40,6 +40,41 @@ def test_kpath_rejects_bad_arguments():
     lib = mvpb.load()
     assert lib.mvpb_kpath_square(0, None) == mvpb.E_INVALID
     assert "bad" in lib.mvpb_last_error().decode()
+    for lat, path, n_k in ((np.eye(2), "GQ", 4), (np.zeros((2, 2)), "GX", 4), (np.eye(2), "", 3),
+                           (np.eye(2), "G" * 70, 3), (np.eye(2), "GG", 3), (np.eye(2), "GX", 0)):
+        with pytest.raises(mvpb.MvpbError) as ei:
+            mvpb.kpath(lat, path, n_k)
+        assert ei.value.code == mvpb.E_INVALID
+
+
+@pytest.mark.parametrize("n_k", [1, 2, 7, 30, 60])
+def test_general_kpath_square_and_hexagonal(n_k):
+    """Square Gamma-X-M-Gamma (same points as the square helper) and the
+    hexagonal X-Gamma-J-X of the paper's examples, spaced in Cartesian arc length."""
+    assert np.allclose(mvpb.kpath(np.eye(2), "GXMG", n_k), kpath_gxmg(n_k), atol=1e-15)
+    # the lattice constant scales k, not the fractional points
+    assert np.allclose(mvpb.kpath(6.023e-3 * np.eye(2), "GXMG", n_k), kpath_gxmg(n_k), atol=1e-15)
+    assert np.allclose(mvpb.kpath(hex_lattice(6.023e-3), "XGJX", n_k), kpath_xgjx(n_k), atol=1e-14)
+
+
+def test_general_kpath_is_uniform_in_cartesian_arc_length():
+    """On an oblique lattice consecutive points are equally far apart in
+    Cartesian k (the path has no corner between them) and the corners lie on the
+    path at their arc-length position."""
+    lat = np.array([[1.3, 0.2], [-0.4, 0.9]])
+    q = 2 * np.pi * np.linalg.inv(lat).T
+    Q = mvpb.kpath(lat, "GXMYG", 401)
+    k = Q @ q
+    steps = np.linalg.norm(np.diff(k, axis=0), axis=1)
+    pts = np.array([[0, 0], [0.5, 0], [0.5, 0.5], [0, 0.5], [0, 0]]) @ q
+    seg = np.linalg.norm(np.diff(pts, axis=0), axis=1)
+    total = seg.sum()
+    assert np.allclose(Q[0], [0, 0]) and np.allclose(Q[-1], [0, 0], atol=1e-15)
+    # steps that do not straddle a corner have the nominal length exactly;
+    # the others are shorter (the chord across the corner)
+    h = total / 400
+    assert np.all(steps <= h * (1 + 1e-12))
+    assert np.sum(np.abs(steps - h) > 1e-12 * h) <= 3
 
 
 def test_null_handles_are_rejected():

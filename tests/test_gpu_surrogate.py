@@ -130,3 +130,36 @@ def test_screening_fallback_with_zero_tolerance(ctx):
     stats = sc.screen(ctx, net, cells, b=2, rounds=1, n_candidates=64, top_k=3, tol=0.0)
     assert stats["fallbacks"] == stats["verified"] == 3
     net.close()
+
+
+def test_checkpoint_resumes_training_exactly(ctx, tmp_path):
+    """Save after a few Adam steps, load into a new network: the parameters
+    are equal, and the next steps of both networks give identical losses and
+    parameters (the moments and the step counter were restored)."""
+    from paper_1310_6380_amd import mvpb
+    print("surrogate checkpoint", flush=True)
+    net = mvpb.Surrogate(ctx, max_batch=8, precision=1, seed=3)
+    cells, target = _batch(8, 4)
+    for _ in range(3):
+        net.train_step(cells, target, 1e-3)
+    path = str(tmp_path / "sur.ckpt")
+    net.save(path)
+    net2 = mvpb.Surrogate.load(ctx, path, max_batch=8)
+    assert np.array_equal(net.get_params(), net2.get_params())
+    after = []
+    for _ in range(2):
+        assert net.train_step(cells, target, 1e-3) == net2.train_step(cells, target, 1e-3)
+        after.append(net.get_params())
+    assert np.array_equal(net.get_params(), net2.get_params())
+    # the same parameters with the moments cleared take a different step
+    net3 = mvpb.Surrogate(ctx, max_batch=8, precision=1, seed=3)
+    net3.set_params(mvpb.Surrogate.load(ctx, path, max_batch=8).get_params())
+    net3.train_step(cells, target, 1e-3)
+    assert not np.array_equal(net3.get_params(), after[0])
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b"not a checkpoint")
+    with pytest.raises(mvpb.MvpbError) as ei:
+        mvpb.Surrogate.load(ctx, str(bad))
+    assert ei.value.code == mvpb.E_INVALID
+    for n in (net, net2, net3):
+        n.close()
