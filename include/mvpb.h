@@ -182,6 +182,22 @@ int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plans, const in
  * 4*(4M1+1)*(4M2+1) complex values. */
 int mvpb_structure_factors(mvpb_cell cell, int M1, int M2, int precision, double *F);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * structure factors as mvpb_structure_factors, same kernels and layout, but
+ * F is a DEVICE pointer owned by the caller (4*(4M1+1)*(4M2+1) complex
+ * values) and the call allocates nothing.  The two DFT passes keep their
+ * intermediate sums in a fixed device array of 16 MiB per GPU (held until
+ * the process ends); its address is looked up when a context is created on
+ * the device.  Scratch needed: 64*nx*(4M2+1) bytes for pixel cells
+ * (matrix-core passes; 64*nx*(4M2+1) with MVPB_PREC_SF_PLAIN64 too),
+ * 64*ceil(n_edges/256)*(4M1+1)*(4M2+1) bytes for polygon cells; a request
+ * above 16 MiB returns MVPB_E_NOMEM.  Every call on one GPU shares that
+ * array, so calls that overlap in time on one GPU (two streams, two host
+ * threads) race and must be serialised by the caller.  Returns after the
+ * context stream has finished unless MVPB_F_ASYNC is passed. */
+int mvpb_structure_factors_noalloc(mvpb_cell cell, int M1, int M2, int precision, double *F, unsigned flags);
+
 /* Points equally spaced in arc length on Gamma(0,0)-X(1/2,0)-M(1/2,1/2)-Gamma
  * (the boundary of the irreducible zone of a square lattice), both ends
  * Gamma.  Q: host pointer, 2*n_k doubles. */

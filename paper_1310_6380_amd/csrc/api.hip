@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -252,6 +253,8 @@ void ctx_retain(mvpb_ctx c) { c->children++; }
 void ctx_release_child(mvpb_ctx c) { ctx_release(c); }
 }  // namespace mvpb
 
+static hipError_t scratch_setup(int device);   // fixed scratch of the allocation-free call (below)
+
 static int check_ctx(mvpb_ctx c) {
   if (!c) return set_err(MVPB_E_INVALID, "NULL context");
   if (c->closing) return set_err(MVPB_E_INVALID, "context has been destroyed");
@@ -272,6 +275,7 @@ extern "C" int mvpb_ctx_create(int device, void *hip_stream, size_t workspace_ca
   if (device < 0 || device >= ndev) return set_err(MVPB_E_INVALID, "device %d out of range [0,%d)", device, ndev);
   HIP_TRY(hipSetDevice(device));
   HIP_TRY(init_kernel_attributes());
+  HIP_TRY(scratch_setup(device));
   mvpb_ctx c = new mvpb_ctx_s();
   c->device = device;
   c->cap = workspace_cap;
@@ -538,6 +542,69 @@ extern "C" int mvpb_structure_factors(mvpb_cell c, int M1, int M2, int precision
   const size_t cnt = 4 * (size_t)(4 * M1 + 1) * (4 * M2 + 1);
   HIP_TRY(hipMemcpyAsync(F, Fd.p, sizeof(cd) * cnt, hipMemcpyDeviceToHost, c->ctx->stream));
   HIP_TRY(hipStreamSynchronize(c->ctx->stream));
+  return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Structure factors without allocation: the scratch of the two DFT passes
+// lives in a fixed file-scope device array; each device holds its own copy,
+// whose address is looked up once per device when a context is created there.
+// ---------------------------------------------------------------------------
+constexpr size_t SF_SCRATCH_BYTES = (size_t)16 << 20;
+static __device__ __align__(256) char scratch[SF_SCRATCH_BYTES];
+constexpr int SCRATCH_DEVICES = 64;
+static void *g_scratch_ptr[SCRATCH_DEVICES];   // device address of `scratch` per device (NULL: not looked up)
+static std::mutex g_scratch_mu;
+
+// With `device` current: record the device address of its scratch array.
+static hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= SCRATCH_DEVICES) return hipSuccess;   // the allocation-free call then refuses
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+// Bytes of pass scratch the structure factors of cell c at (M1, M2) need.
+static size_t sf_scratch_need(mvpb_cell c, int M1, int M2, int precision) {
+  const size_t nq = (size_t)(4 * M2 + 1);
+  if (c->polygons) return sf_poly_scratch_bytes(c->n_edges, M1, M2);
+  if (precision & MVPB_PREC_SF_PLAIN64) return sizeof(cd) * 4 * (size_t)c->nx * nq;
+  return sizeof(double) * 8 * (size_t)c->nx * nq;
+}
+
+extern "C" int mvpb_structure_factors_noalloc(mvpb_cell c, int M1, int M2, int precision, double *F,
+                                              unsigned flags) {
+  if (!c || !F) return set_err(MVPB_E_INVALID, "NULL argument");
+  int rc = check_cutoff(M1, M2);
+  if (rc) return rc;
+  rc = check_precision(precision);
+  if (rc) return rc;
+  mvpb_ctx ctx = c->ctx;
+  if (ctx->device < 0 || ctx->device >= SCRATCH_DEVICES || !g_scratch_ptr[ctx->device])
+    return set_err(MVPB_E_UNSUPPORTED, "no fixed scratch on device %d", ctx->device);
+  const size_t need = sf_scratch_need(c, M1, M2, precision);
+  if (need > SF_SCRATCH_BYTES)
+    return set_err(MVPB_E_NOMEM, "structure factors at M = (%d, %d) need %zu bytes of scratch; the fixed scratch holds %zu",
+                   M1, M2, need, SF_SCRATCH_BYTES);
+  HIP_TRY(hipSetDevice(ctx->device));
+  ProfBind pb(nullptr);   // no timer events (they are created on demand)
+  void *ptr = g_scratch_ptr[ctx->device];
+  hipStream_t st = ctx->stream;
+  if (c->polygons) {
+    HIP_TRY(launch_structure_factors_poly(c->edges.as<double>(), c->ephase.as<int32_t>(), c->wtab.as<double>(),
+                                          c->n_edges, c->T, c->f0, M1, M2, (cd *)ptr, (cd *)F, st));
+  } else if (precision & MVPB_PREC_SF_PLAIN64) {
+    HIP_TRY(launch_structure_factors_f64(c->phase.as<int32_t>(), c->wtab.as<double>(), c->nx, c->ny, M1, M2,
+                                         c->area, (cd *)ptr, (cd *)F, st));
+  } else {
+    HIP_TRY(launch_structure_factors_mfma(precision & 3, c->phase.as<int32_t>(), c->wtab.as<double>(), c->nx, c->ny,
+                                          M1, M2, c->area, (double *)ptr, (cd *)F, st));
+  }
+  if (!(flags & MVPB_F_ASYNC)) HIP_TRY(hipStreamSynchronize(st));
   return MVPB_OK;
 }
 

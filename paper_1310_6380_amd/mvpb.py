@@ -47,7 +47,7 @@ EXPORTS = [
     "mvpb_sur_create", "mvpb_sur_destroy", "mvpb_sur_n_params", "mvpb_sur_get_params", "mvpb_sur_set_params",
     "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step", "mvpb_copy_device",
     "mvpb_ctx_profile_mask", "mvpb_cell_create_polygons", "mvpb_stress_modes", "mvpb_kpath",
-    "mvpb_sur_save", "mvpb_sur_load",
+    "mvpb_sur_save", "mvpb_sur_load", "mvpb_structure_factors_noalloc",
 ]
 N_KERNELS = 15
 
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
     lib.mvpb_solve_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(D), I,
                                      ctypes.POINTER(P), ctypes.c_uint]
     lib.mvpb_structure_factors.argtypes = [P, I, I, I, D]
+    lib.mvpb_structure_factors_noalloc.argtypes = [P, I, I, I, P, ctypes.c_uint]
     lib.mvpb_kpath_square.argtypes = [I, D]
     lib.mvpb_kpath.argtypes = [D, ctypes.c_char_p, I, D]
     lib.mvpb_plan_create_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I,
@@ -354,6 +355,16 @@ class Cell:
         _check(load().mvpb_structure_factors(self.h, M1, M2, precision,
                                              F.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return F
+
+    def structure_factors_noalloc(self, M1: int, M2: int, out: "DeviceBuffer", precision: int = PREC_FP64,
+                                  flags: int = 0):
+        """mvpb_structure_factors_noalloc into the caller's device buffer ``out``
+        (4*(4M1+1)*(4M2+1) complex doubles); the library allocates nothing."""
+        need = 16 * 4 * (4 * M1 + 1) * (4 * M2 + 1)
+        if out.nbytes < need:
+            raise ValueError(f"output buffer holds {out.nbytes} bytes, {need} needed")
+        _check(load().mvpb_structure_factors_noalloc(self.h, M1, M2, precision, out.ptr, flags))
+        return out
 
     def plan(self, M1: int, M2: int = None, precision: int = PREC_FP64):
         return Plan(self, M1, M1 if M2 is None else M2, precision)
