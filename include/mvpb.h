@@ -50,24 +50,45 @@ enum {
   MVPB_E_NOT_PD = -2,      /* a compliance/density matrix is not positive definite */
   MVPB_E_NOMEM = -3,       /* device allocation failed or workspace cap exceeded */
   MVPB_E_DEVICE = -4,      /* HIP runtime error */
-  MVPB_E_UNSUPPORTED = -5  /* valid request that the library does not implement */
+  MVPB_E_UNSUPPORTED = -5, /* valid request that the library does not implement */
+  MVPB_E_ACCURACY = -6     /* a solve with the FP32 reduction (MVPB_PREC_EIG_FP32_RR64)
+                              estimates a frequency error above the context's bar (see
+                              mvpb_ctx_set_accuracy); unlike every other error, the
+                              outputs of that solve ARE written */
 };
 
 /* Property table layouts (one row per phase). */
 enum {
-  MVPB_PROP_ISO_E_NU_RHO = 0 /* E [Pa], nu, rho [kg/m^3]; isotropic plane strain (Sec. 4) */
+  MVPB_PROP_ISO_E_NU_RHO = 0, /* E [Pa], nu, rho [kg/m^3]; isotropic (planar cells: plane
+                                 strain, Sec. 4) */
+  MVPB_PROP_VOIGT_D_RHO = 1   /* general compliance: the engineering-Voigt compliance matrix
+                                 d (strain = d stress with engineering shear strains, i.e. the
+                                 weights c_s c_t D_jkmn of the Phi blocks of Sec. 4.1 eq. (ep),
+                                 c = 1 on normal and 2 on shear components: d13 = 2 D1112,
+                                 d33 = 4 D1212 in the plane), upper triangle row by row, then
+                                 rho [kg/m^3].  Planar cells (stress order 11, 22, 12): d11,
+                                 d12, d13, d22, d23, d33, rho (7 values); voxel cells (11, 22,
+                                 33, 23, 13, 12): the 21 entries d11 .. d16, d22 .. d26, ...,
+                                 d66, then rho (22 values).  Positive definite, rho > 0.
+                                 Pixel and voxel cells only. */
 };
 
 /* Precision of a plan: bit flags.  The structure-factor contraction runs on
- * the matrix cores (FP64 by default); at most one of SF_FP32 / SF_BF16 may be
- * set.  EIG_FP32_RR64 may be combined with either. */
+ * the matrix cores (FP64 by default); the low two bits select one of FP64,
+ * SF_FP32, SF_BF16 and SF_BF16X3.  EIG_FP32_RR64 may be combined with any. */
 enum {
   MVPB_PREC_FP64 = 0,           /* everything in FP64 */
   MVPB_PREC_SF_FP32 = 1,        /* structure factors: FP32 inputs, FP32 accumulate */
   MVPB_PREC_SF_BF16 = 2,        /* structure factors: BF16 inputs, FP32 accumulate */
+  MVPB_PREC_SF_BF16X3 = 3,      /* structure factors: every input split into two BF16
+                                   parts hi + lo, each product as the three BF16 products
+                                   lo*hi + hi*lo + hi*hi, FP32 accumulate (Henry, Tang and
+                                   Heinecke, ARITH 2019) */
   MVPB_PREC_EIG_FP32_RR64 = 4,  /* FP32 reduction to tridiagonal form and back-transform,
                                    FP64 Rayleigh-Ritz refinement on the FP64 operator */
-  MVPB_PREC_SF_PLAIN64 = 8      /* structure factors by the scalar FP64 kernel (cross-check) */
+  MVPB_PREC_SF_PLAIN64 = 8,     /* structure factors by the scalar FP64 kernel (cross-check) */
+  MVPB_PREC_GENERAL = 16        /* build an isotropic planar cell's plan in the general layout
+                                   (full Phi, as for MVPB_PROP_VOIGT_D_RHO cells; cross-check) */
 };
 
 /* Flags of mvpb_solve / mvpb_solve_batch. */
@@ -89,6 +110,24 @@ const char *mvpb_version(void);
 int mvpb_ctx_create(int device, void *hip_stream, size_t workspace_cap, mvpb_ctx *out);
 int mvpb_ctx_destroy(mvpb_ctx ctx);
 
+/* Accuracy bar of the mixed-precision eigensolve.  After the FP64
+ * Rayleigh-Ritz step of a solve with the FP32 reduction, every refined pair
+ * (theta, z) has its residual r = C z - theta z computed in FP64 on the FP64
+ * operator, and the error of theta is estimated to second order as
+ * |r|^2 / (rho - theta) with rho = r^H C r / |r|^2 the Rayleigh quotient of
+ * the residual (r is orthogonal to the Ritz space, so rho - theta is its
+ * effective distance to the rest of the spectrum; |r| if rho <= theta),
+ * expressed as a relative frequency error: estimate / (2 theta), or
+ * estimate / (2 theta_top) for bands below 1e-3 of the top frequency
+ * (acoustic modes at and next to Gamma).  It is an estimate, not a bound.
+ * A synchronous mvpb_solve / mvpb_solve_batch with the FP32 reduction
+ * returns MVPB_E_ACCURACY (outputs written) when the largest estimate
+ * exceeds `tol` (default 1e-5; 0 turns the check off).  FP64 solves report
+ * 0 and are never refused.  With MVPB_F_ASYNC nothing is checked. */
+int mvpb_ctx_set_accuracy(mvpb_ctx ctx, double tol);
+/* Largest estimate of the last synchronous solve on ctx (0 before any). */
+int mvpb_ctx_last_accuracy(mvpb_ctx ctx, double *estimate);
+
 /* A unit cell given as an nx x ny pixel map of phase ids.
  * lattice[4] = {h1x, h1y, h2x, h2y} (rows of the matrix A of Sec. 4).
  * phase[i*ny + j] is the phase of pixel (i, j), i along h1, in [0, n_phases).
@@ -97,6 +136,19 @@ int mvpb_ctx_destroy(mvpb_ctx ctx);
  * (ISO: E > 0, -1 < nu < 0.5, rho > 0).  Phases with no pixel are allowed.
  * Host pointers; deep-copied. */
 int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], int nx, int ny,
+                            const int32_t *phase, int n_phases, int prop_kind,
+                            const double *props, mvpb_cell *out);
+/* A three-dimensional unit cell (the spatial form of the method: Sec. 2,
+ * Sec. 2.3 with test functions in three fractional coordinates,
+ * 3(2M+1)^3 displacement and 6(2M+1)^3 stress unknowns) given as an
+ * nx x ny x nz voxel map.  lattice[9] = rows h1, h2, h3 of A.
+ * phase[(i*ny + j)*nz + k] is the phase of voxel (i, j, k), i along h1, k
+ * along h3; voxel (i,j,k) covers H1 in [i/nx,(i+1)/nx], H2 in [j/ny,(j+1)/ny],
+ * H3 in [k/nz,(k+1)/nz].  props: n_phases rows of kind ISO (E, nu, rho;
+ * three-dimensional isotropic compliance) or VOIGT_D_RHO (22 values).
+ * Plans of voxel cells come from mvpb_plan_create3 and use the general
+ * layout.  Host pointers; deep-copied. */
+int mvpb_cell_create_voxels(mvpb_ctx ctx, const double lattice[9], int nx, int ny, int nz,
                             const int32_t *phase, int n_phases, int prop_kind,
                             const double *props, mvpb_cell *out);
 /* A unit cell given as polygons (Sec. 4.1: the subdomain integrals of
@@ -109,7 +161,7 @@ int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], int nx, int n
  * its area to its phase, a clockwise one subtracts it (a hole is a clockwise
  * copy of its boundary in the enclosing phase).  The signed areas must tile
  * the cell: their sum equals |det A| to 1e-9 relative and no phase ends up
- * negative, else MVPB_E_INVALID.  props as for pixel cells.  Structure
+ * negative, else MVPB_E_INVALID.  props of kind ISO only.  Structure
  * factors of polygon cells are computed in FP64 for every precision setting.
  * Host pointers; deep-copied. */
 int mvpb_cell_create_polygons(mvpb_ctx ctx, const double lattice[4], int n_polys,
@@ -126,25 +178,39 @@ int mvpb_cell_destroy(mvpb_cell cell);
  * N = (2M1+1)(2M2+1) <= 4096.  Returns MVPB_E_NOT_PD if Phi or Omega is
  * not positive definite. */
 int mvpb_plan_create(mvpb_cell cell, int M1, int M2, int precision, mvpb_plan *out);
+/* Plans of the general layout: used for cells whose compliance is given as
+ * a full matrix (MVPB_PROP_VOIGT_D_RHO), for voxel cells, and on request
+ * (MVPB_PREC_GENERAL).  The whole stress-space compliance matrix Phi
+ * (n_s = 3N or 6N square, Sec. 4.1 eq. (ep) and its spatial form) and
+ * Omega are factored; the reduced operator is quadratic in the Bloch vector
+ * with (d+1)(d+2)/2 coefficient matrices of order n_u = dN (d = 2 planar,
+ * 3 spatial).  Structure factors are computed in FP64 for every precision
+ * setting; MVPB_PREC_EIG_FP32_RR64 applies.  Requires d N <= 4096.
+ * mvpb_plan_create3 takes the cutoff of every axis (M3 = 0 for a planar
+ * cell, which is then the same as mvpb_plan_create). */
+int mvpb_plan_create3(mvpb_cell cell, int M1, int M2, int M3, int precision, mvpb_plan *out);
 /* Plans for n cells of one context at once (same precision): cells with
  * equal cutoffs share batched launches for the factorisations and the
  * coefficient GEMMs.  out[i] receives the plan of cells[i]; on error no plan
  * is returned (MVPB_E_NOT_PD names the failing cell index). */
 int mvpb_plan_create_batch(mvpb_ctx ctx, int n, const mvpb_cell *cells, const int *M1, const int *M2,
                            int precision, mvpb_plan *out);
-/* n_u = 2N displacement unknowns, n_s = 3N stress unknowns (Sec. 4.1). */
+/* n_u = dN displacement unknowns, n_s = 3N (planar) or 6N (spatial) stress
+ * unknowns (Sec. 4.1; Sec. 2.3). */
 int mvpb_plan_dofs(mvpb_plan plan, int *n_u, int *n_s);
 int mvpb_plan_destroy(mvpb_plan plan);
 
 /* Solve for the lowest n_bands at each of n_k Bloch vectors.
- * Q[2*t + i] = Q_i of point t (k = Q1 q^1 + Q2 q^2, finite).
+ * Q[d*t + i] = Q_i of point t (k = Q_i q^i, finite), d = 2 for planar cells
+ * and 3 for voxel cells.
  * omega[t*n_bands + b]: frequencies in rad/s, ascending per point
  *   (sqrt(max(lambda, 0))).
- * U: NULL or space for n_k*n_bands*2N complex values (interleaved re, im),
- *   U[((t*n_bands + b)*2N + r)], r < N the u1 coefficients, r >= N the u2
- *   coefficients, in the plane-wave order I = (alpha+M1)(2M2+1)+(beta+M2);
+ * U: NULL or space for n_k*n_bands*n_u complex values (interleaved re, im),
+ *   U[((t*n_bands + b)*n_u + c*N + r)], the coefficients of displacement
+ *   component c in the plane-wave order I = (alpha+M1)(2M2+1)+(beta+M2)
+ *   (voxel cells: I = ((alpha+M1)(2M2+1)+(beta+M2))(2M3+1)+(gamma+M3));
  *   normalised to U^H Omega U = 1 with the largest-modulus entry real > 0.
- * 1 <= n_bands <= min(2N, 64) (the FP64 Rayleigh-Ritz block is held in
+ * 1 <= n_bands <= min(n_u, 64) (the FP64 Rayleigh-Ritz block is held in
  * on-chip memory).  Q, omega and U are host pointers unless
  * MVPB_F_DEVICE_PTRS is set (then omega and U are device pointers; Q stays
  * on the host).  If the device could not finish a point (the reduction to
@@ -154,24 +220,33 @@ int mvpb_solve(mvpb_plan plan, int n_k, const double *Q, int n_bands, double *om
                unsigned flags);
 
 /* Stress modes S = -Phi^-1 H* U (Sec. 3, after eq. (eigenvalueproblem); H
- * and Phi of Sec. 4.1 eqs. (eh), (ep)) of displacement modes U, for the
- * isotropic cells of this library.  Q as for mvpb_solve; U: n_k*n_bands*2N
- * complex values in the layout mvpb_solve writes (any normalisation: S is
- * linear in U).  S: space for n_k*n_bands*3N complex values,
- * S[((t*n_bands + b)*3N + r)], r < N the sigma_11, N <= r < 2N the sigma_22,
- * r >= 2N the sigma_12 coefficients, plane-wave order as for U.  Host
- * pointers unless MVPB_F_DEVICE_PTRS (then U and S are device pointers).
- * 1 <= n_bands <= 2N. */
+ * and Phi of Sec. 4.1 eqs. (eh), (ep)) of displacement modes U, for every
+ * plan (isotropic and general layouts).  Q as for mvpb_solve; U:
+ * n_k*n_bands*n_u complex values in the layout mvpb_solve writes (any
+ * normalisation: S is linear in U).  S: space for n_k*n_bands*n_s complex
+ * values, S[((t*n_bands + b)*n_s + c*N + r)], c the Voigt stress component
+ * (planar 11, 22, 12; spatial 11, 22, 33, 23, 13, 12), plane-wave order as
+ * for U.  Host pointers unless MVPB_F_DEVICE_PTRS (then U and S are device
+ * pointers).  1 <= n_bands <= n_u. */
 int mvpb_stress_modes(mvpb_plan plan, int n_k, const double *Q, int n_bands, const double *U,
                       double *S, unsigned flags);
 
 /* Many plans at once: all (plan, k) items in one batched launch sequence
  * (captured in a HIP graph and replayed).  n_k[p] points for plan p taken
  * from Q[p] (host pointers), results to omega[p][t*n_bands + b] (host
- * pointers, or device pointers with MVPB_F_DEVICE_PTRS).  Every plan must
- * belong to ctx and have 2N >= n_bands. */
+ * pointers, or device pointers with MVPB_F_DEVICE_PTRS; Q[p] holds d
+ * components per point as for mvpb_solve).  Every plan must belong to ctx
+ * and have n_u >= n_bands. */
 int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plans, const int *n_k,
                      const double *const *Q, int n_bands, double *const *omega, unsigned flags);
+
+/* Structure factors of the general layout (pixel and voxel cells):
+ * F[((f*(4M1+1) + m+2M1)*(4M2+1) + q+2M2)*(4M3+1) + r+2M3] (complex,
+ * interleaved) = sum_p w_f(p) int_{Omega_p} exp(i 2 pi (m H1 + q H2 + r H3)) dx
+ * for the fields f = the upper triangle of the engineering-Voigt compliance
+ * matrix (row by row) and, last, rho: 7 fields for planar cells (M3 = 0),
+ * 22 for voxel cells.  FP64.  F: host pointer. */
+int mvpb_structure_factors_general(mvpb_cell cell, int M1, int M2, int M3, double *F);
 
 /* Phase-summed structure factors of a cell on the difference grid
  * (debug/parity access to the first step of the method):

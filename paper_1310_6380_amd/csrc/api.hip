@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -158,6 +159,9 @@ struct mvpb_ctx_s {
   DevBuf ws{&pool};      // per-solve workspace (grow-only)
   DevBuf items{&pool};   // item table
   DevBuf scratch{&pool}; // small host-visible results staging
+  DevBuf accbuf{&pool};  // one double: largest error estimate of the bands of the current solve
+  double acc_tol = 1e-5; // accuracy bar of solves with the FP32 reduction (0: no check)
+  double last_acc = 0.0; // largest error estimate of the last synchronous solve
   // Captured launch sequences of the eigensolve, keyed by everything that
   // fixes their launch shapes (item orders, bands, precision, stage-1 parts;
   // see launch_signature).  The kernels find their matrices through the item
@@ -183,6 +187,7 @@ static void ctx_free(mvpb_ctx c) {
   c->ws.release();
   c->items.release();
   c->scratch.release();
+  c->accbuf.release();
   c->pool.trim();
   c->prof.reset();
   for (int q = 0; q < MAX_SIDE; ++q) {
@@ -224,6 +229,13 @@ struct mvpb_cell_s {
   DevBuf edges;      // double [n_edges][4]: midpoint, edge vector
   DevBuf ephase;     // int32 [n_edges]
   double f0[4] = {0.0, 0.0, 0.0, 0.0};   // weighted phase areas (dG = 0)
+  // general compliance / spatial cells
+  int dim = 2;          // 2: planar cell, 3: voxel cell
+  int nz = 1;           // voxels along h3 (1 for planar cells)
+  double T3[9] = {};    // A^-1 row-major, dim x dim packed (planar cells: = T)
+  bool general = false; // compliance given as a full matrix or spatial cell: only the general plan applies
+  int nf = 0;           // weight fields of the general structure factors
+  DevBuf gwtab;         // double [n_phases][nf]: Voigt compliance (upper triangle), rho (pixel/voxel cells)
 };
 
 struct mvpb_plan_s {
@@ -231,9 +243,16 @@ struct mvpb_plan_s {
   int M1 = 0, M2 = 0, N = 0, prec = 0;
   double T[4];
   double area = 0.0;
-  DevBuf coef;       // 15 N x N
+  DevBuf coef;       // isotropic layout: 15 N x N; general layout: (dim+1)(dim+2)/2 of n x n
   DevBuf linvR;      // N x N, L_R^-1
-  DevBuf linvSD;     // 2 N x N: L_Sigma^-1, L_Delta^-1 (stress modes)
+  DevBuf linvSD;     // 2 N x N: L_Sigma^-1, L_Delta^-1 (stress modes, isotropic layout)
+  int dim = 0;       // 0: isotropic planar layout; 2, 3: general layout (full Phi)
+  int n = 0;         // displacement unknowns = order of the reduced operator
+  int nsig = 0;      // stress unknowns
+  int qdim = 2;      // components of a Bloch vector Q
+  int M3 = 0;
+  double T3[9] = {}; // A^-1 row-major, qdim x qdim packed
+  DevBuf linvPhi;    // general layout: L_Phi^-1 (nsig x nsig)
 };
 
 namespace mvpb {
@@ -349,6 +368,73 @@ static int phase_weight_table(int n_phases, const double *props, std::vector<dou
   return MVPB_OK;
 }
 
+// Engineering-Voigt compliance matrix (the Phi weights c_s c_t D_jkmn of
+// Sec. 4.1 eq. (ep), c = 1 on normal and 2 on shear components) of every phase,
+// upper triangle row-major, then rho: the weight fields of the general plan.
+// dim 2: stress order 11, 22, 12 (plane strain for isotropic rows);
+// dim 3: 11, 22, 33, 23, 13, 12.  Rows of kind VOIGT_D_RHO hold the upper
+// triangle and rho directly; the matrix must be positive definite.
+static int general_weight_table(int dim, int n_phases, int prop_kind, const double *props, std::vector<double> &w,
+                                int *nf_out) {
+  const int ns = dim == 2 ? 3 : 6, nt = ns * (ns + 1) / 2, nf = nt + 1;
+  w.assign((size_t)n_phases * nf, 0.0);
+  for (int p = 0; p < n_phases; ++p) {
+    double D[6][6] = {};
+    double rho;
+    if (prop_kind == MVPB_PROP_ISO_E_NU_RHO) {
+      const double E = props[3 * p], nu = props[3 * p + 1];
+      rho = props[3 * p + 2];
+      if (!(E > 0.0) || !isfinite(E)) return set_err(MVPB_E_INVALID, "phase %d: E must be positive", p);
+      if (!(nu > -1.0 && nu < 0.5)) return set_err(MVPB_E_INVALID, "phase %d: nu must be in (-1, 0.5)", p);
+      if (dim == 2) {   // plane strain
+        D[0][0] = D[1][1] = (1.0 + nu) * (1.0 - nu) / E;
+        D[0][1] = D[1][0] = -nu * (1.0 + nu) / E;
+        D[2][2] = 2.0 * (1.0 + nu) / E;
+      } else {
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) D[a][b] = (a == b) ? 1.0 / E : -nu / E;
+        for (int a = 3; a < 6; ++a) D[a][a] = 2.0 * (1.0 + nu) / E;
+      }
+    } else {
+      const double *r = props + (size_t)p * nf;
+      int k = 0;
+      for (int a = 0; a < ns; ++a)
+        for (int b = a; b < ns; ++b) {
+          if (!isfinite(r[k])) return set_err(MVPB_E_INVALID, "phase %d: non-finite compliance", p);
+          D[a][b] = D[b][a] = r[k++];
+        }
+      rho = r[nt];
+    }
+    if (!(rho > 0.0) || !isfinite(rho)) return set_err(MVPB_E_INVALID, "phase %d: rho must be positive", p);
+    // positive definite: Cholesky of the scaled matrix
+    double L[6][6] = {};
+    for (int j = 0; j < ns; ++j) {
+      double dj = D[j][j];
+      for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k];
+      if (!(dj > 1e-12 * D[j][j]) || !(D[j][j] > 0.0))
+        return set_err(MVPB_E_INVALID, "phase %d: compliance matrix is not positive definite", p);
+      L[j][j] = sqrt(dj);
+      for (int i = j + 1; i < ns; ++i) {
+        double v = D[i][j];
+        for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+        L[i][j] = v / L[j][j];
+      }
+    }
+    double *o = w.data() + (size_t)p * nf;
+    int k = 0;
+    for (int a = 0; a < ns; ++a)
+      for (int b = a; b < ns; ++b) o[k++] = D[a][b];
+    o[nt] = rho;
+  }
+  *nf_out = nf;
+  return MVPB_OK;
+}
+
+static int prop_stride(int dim, int prop_kind) {
+  if (prop_kind == MVPB_PROP_ISO_E_NU_RHO) return 3;
+  return dim == 2 ? 7 : 22;
+}
+
 extern "C" int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], int nx, int ny,
                                        const int32_t *phase, int n_phases, int prop_kind, const double *props,
                                        mvpb_cell *out) {
@@ -357,33 +443,117 @@ extern "C" int mvpb_cell_create_pixels(mvpb_ctx ctx, const double lattice[4], in
   if (!lattice || !phase || !props || !out) return set_err(MVPB_E_INVALID, "NULL argument");
   if (nx <= 0 || ny <= 0 || nx > 4096 || ny > 4096) return set_err(MVPB_E_INVALID, "bad grid %d x %d", nx, ny);
   if (n_phases <= 0) return set_err(MVPB_E_INVALID, "n_phases must be positive");
-  if (prop_kind != MVPB_PROP_ISO_E_NU_RHO)
+  if (prop_kind != MVPB_PROP_ISO_E_NU_RHO && prop_kind != MVPB_PROP_VOIGT_D_RHO)
     return set_err(MVPB_E_UNSUPPORTED, "property kind %d not supported", prop_kind);
   double T[4], area;
   if (!lattice_ok(lattice, T, &area)) return set_err(MVPB_E_INVALID, "degenerate or non-finite lattice");
   for (size_t i = 0; i < (size_t)nx * ny; ++i)
     if (phase[i] < 0 || phase[i] >= n_phases)
       return set_err(MVPB_E_INVALID, "phase id %d at pixel %zu out of range [0,%d)", phase[i], i, n_phases);
-  std::vector<double> w;
-  rc = phase_weight_table(n_phases, props, w);
+  const bool iso = prop_kind == MVPB_PROP_ISO_E_NU_RHO;
+  std::vector<double> w, gw;
+  if (iso) {
+    rc = phase_weight_table(n_phases, props, w);
+    if (rc) return rc;
+  }
+  int nf = 0;
+  rc = general_weight_table(2, n_phases, prop_kind, props, gw, &nf);
   if (rc) return rc;
   HIP_TRY(hipSetDevice(ctx->device));
   mvpb_cell c = new mvpb_cell_s();
   c->ctx = ctx;
   memcpy(c->lattice, lattice, sizeof c->lattice);
   memcpy(c->T, T, sizeof T);
+  memcpy(c->T3, T, sizeof T);
   c->area = area;
   c->nx = nx;
   c->ny = ny;
   c->n_phases = n_phases;
+  c->general = !iso;
+  c->nf = nf;
   c->phase.pool = &ctx->pool;
   c->wtab.pool = &ctx->pool;
+  c->gwtab.pool = &ctx->pool;
   hipError_t e = c->phase.alloc(sizeof(int32_t) * nx * ny);
-  if (e == hipSuccess) e = c->wtab.alloc(sizeof(double) * w.size());
+  if (e == hipSuccess && iso) e = c->wtab.alloc(sizeof(double) * w.size());
+  if (e == hipSuccess) e = c->gwtab.alloc(sizeof(double) * gw.size());
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->phase.p, phase, sizeof(int32_t) * nx * ny, hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess)
+  if (e == hipSuccess && iso)
     e = hipMemcpyAsync(c->wtab.p, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->gwtab.p, gw.data(), sizeof(double) * gw.size(), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return set_err(MVPB_E_NOMEM, "cell upload: %s", hipGetErrorString(e));
+  }
+  ctx->children++;
+  *out = c;
+  return MVPB_OK;
+}
+
+// A = rows h1, h2, h3; T = A^-1 (row-major), vol = |det A|.
+static bool lattice3_ok(const double *L, double *T, double *vol) {
+  for (int i = 0; i < 9; ++i)
+    if (!isfinite(L[i])) return false;
+  const double c00 = L[4] * L[8] - L[5] * L[7], c01 = L[5] * L[6] - L[3] * L[8], c02 = L[3] * L[7] - L[4] * L[6];
+  const double det = L[0] * c00 + L[1] * c01 + L[2] * c02;
+  if (!(fabs(det) > 0.0) || !isfinite(det)) return false;
+  // inverse = adjugate / det (adjugate = transpose of the cofactor matrix)
+  T[0] = c00 / det;
+  T[3] = c01 / det;
+  T[6] = c02 / det;
+  T[1] = (L[2] * L[7] - L[1] * L[8]) / det;
+  T[4] = (L[0] * L[8] - L[2] * L[6]) / det;
+  T[7] = (L[1] * L[6] - L[0] * L[7]) / det;
+  T[2] = (L[1] * L[5] - L[2] * L[4]) / det;
+  T[5] = (L[2] * L[3] - L[0] * L[5]) / det;
+  T[8] = (L[0] * L[4] - L[1] * L[3]) / det;
+  *vol = fabs(det);
+  return true;
+}
+
+extern "C" int mvpb_cell_create_voxels(mvpb_ctx ctx, const double lattice[9], int nx, int ny, int nz,
+                                       const int32_t *phase, int n_phases, int prop_kind, const double *props,
+                                       mvpb_cell *out) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!lattice || !phase || !props || !out) return set_err(MVPB_E_INVALID, "NULL argument");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx > 1024 || ny > 1024 || nz > 1024 || (long)nx * ny * nz > (1L << 26))
+    return set_err(MVPB_E_INVALID, "bad grid %d x %d x %d", nx, ny, nz);
+  if (n_phases <= 0) return set_err(MVPB_E_INVALID, "n_phases must be positive");
+  if (prop_kind != MVPB_PROP_ISO_E_NU_RHO && prop_kind != MVPB_PROP_VOIGT_D_RHO)
+    return set_err(MVPB_E_UNSUPPORTED, "property kind %d not supported", prop_kind);
+  double T[9], vol;
+  if (!lattice3_ok(lattice, T, &vol)) return set_err(MVPB_E_INVALID, "degenerate or non-finite lattice");
+  const size_t nvox = (size_t)nx * ny * nz;
+  for (size_t i = 0; i < nvox; ++i)
+    if (phase[i] < 0 || phase[i] >= n_phases)
+      return set_err(MVPB_E_INVALID, "phase id %d at voxel %zu out of range [0,%d)", phase[i], i, n_phases);
+  std::vector<double> gw;
+  int nf = 0;
+  rc = general_weight_table(3, n_phases, prop_kind, props, gw, &nf);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(ctx->device));
+  mvpb_cell c = new mvpb_cell_s();
+  c->ctx = ctx;
+  c->dim = 3;
+  memcpy(c->T3, T, sizeof T);
+  c->area = vol;
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->n_phases = n_phases;
+  c->general = true;
+  c->nf = nf;
+  c->phase.pool = &ctx->pool;
+  c->gwtab.pool = &ctx->pool;
+  hipError_t e = c->phase.alloc(sizeof(int32_t) * nvox);
+  if (e == hipSuccess) e = c->gwtab.alloc(sizeof(double) * gw.size());
+  if (e == hipSuccess) e = hipMemcpyAsync(c->phase.p, phase, sizeof(int32_t) * nvox, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->gwtab.p, gw.data(), sizeof(double) * gw.size(), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     delete c;
@@ -507,7 +677,7 @@ static int run_structure_factors(mvpb_cell c, int M1, int M2, int precision, Dev
     HIP_TRY(launch_structure_factors_f64(c->phase.as<int32_t>(), c->wtab.as<double>(), c->nx, c->ny, M1, M2,
                                          c->area, X.as<cd>(), F.as<cd>(), st));
   } else {
-    const int sf = precision & 3;  // 0: FP64, 1: FP32, 2: BF16 matrix-core contraction
+    const int sf = precision & 3;  // 0: FP64, 1: FP32, 2: BF16, 3: split-BF16 matrix-core contraction
     HIP_TRY(launch_structure_factors_mfma(sf, c->phase.as<int32_t>(), c->wtab.as<double>(), c->nx, c->ny, M1, M2,
                                           c->area, X.as<double>(), F.as<cd>(), st));
   }
@@ -516,7 +686,7 @@ static int run_structure_factors(mvpb_cell c, int M1, int M2, int precision, Dev
 
 static int check_precision(int precision) {
   const int sf = precision & 3;
-  if ((precision & ~15) || sf == 3 || ((precision & MVPB_PREC_SF_PLAIN64) && sf))
+  if ((precision & ~31) || ((precision & MVPB_PREC_SF_PLAIN64) && sf))
     return set_err(MVPB_E_INVALID, "bad precision flags %d", precision);
   return MVPB_OK;
 }
@@ -530,6 +700,8 @@ static int check_cutoff(int M1, int M2) {
 
 extern "C" int mvpb_structure_factors(mvpb_cell c, int M1, int M2, int precision, double *F) {
   if (!c || !F) return set_err(MVPB_E_INVALID, "NULL argument");
+  if (c->general)
+    return set_err(MVPB_E_UNSUPPORTED, "cell has a general compliance or is spatial: use mvpb_structure_factors_general");
   int rc = check_cutoff(M1, M2);
   if (rc) return rc;
   rc = check_precision(precision);
@@ -540,6 +712,41 @@ extern "C" int mvpb_structure_factors(mvpb_cell c, int M1, int M2, int precision
   rc = run_structure_factors(c, M1, M2, precision, X, Fd);
   if (rc) return rc;
   const size_t cnt = 4 * (size_t)(4 * M1 + 1) * (4 * M2 + 1);
+  HIP_TRY(hipMemcpyAsync(F, Fd.p, sizeof(cd) * cnt, hipMemcpyDeviceToHost, c->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(c->ctx->stream));
+  return MVPB_OK;
+}
+
+static int check_cutoff3(const mvpb_cell c, int M1, int M2, int M3) {
+  if (M1 < 0 || M2 < 0 || M3 < 0) return set_err(MVPB_E_INVALID, "cutoffs must be non-negative");
+  if (c->dim == 2 && M3 != 0) return set_err(MVPB_E_INVALID, "a planar cell takes M3 = 0");
+  const long N = (long)(2 * M1 + 1) * (2 * M2 + 1) * (2 * M3 + 1);
+  if (c->dim * N > MAX_N) return set_err(MVPB_E_UNSUPPORTED, "%d N = %ld exceeds %d", c->dim, c->dim * N, MAX_N);
+  return MVPB_OK;
+}
+
+// Weight fields of the general plan on the difference grid (pixel and voxel cells).
+static int run_structure_factors_general(mvpb_cell c, int M1, int M2, int M3, DevBuf &X1, DevBuf &X2, DevBuf &F) {
+  if (c->polygons) return set_err(MVPB_E_UNSUPPORTED, "general compliance is not available for polygon cells");
+  const size_t nm = 4 * M1 + 1, nq = 4 * M2 + 1, nr = 4 * M3 + 1, nf = c->nf;
+  HIP_TRY(X1.reserve(sizeof(cd) * nf * c->nx * c->ny * nr));
+  HIP_TRY(X2.reserve(sizeof(cd) * nf * c->nx * nq * nr));
+  HIP_TRY(F.reserve(sizeof(cd) * nf * nm * nq * nr));
+  HIP_TRY(launch_structure_factors_general(c->phase.as<int32_t>(), c->gwtab.as<double>(), c->nf, c->nx, c->ny, c->nz,
+                                           M1, M2, M3, c->area, X1.as<cd>(), X2.as<cd>(), F.as<cd>(), c->ctx->stream));
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_structure_factors_general(mvpb_cell c, int M1, int M2, int M3, double *F) {
+  if (!c || !F) return set_err(MVPB_E_INVALID, "NULL argument");
+  int rc = check_cutoff3(c, M1, M2, M3);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(c->ctx->device));
+  ProfBind pb(c->ctx);
+  DevBuf X1(&c->ctx->pool), X2(&c->ctx->pool), Fd(&c->ctx->pool);
+  rc = run_structure_factors_general(c, M1, M2, M3, X1, X2, Fd);
+  if (rc) return rc;
+  const size_t cnt = (size_t)c->nf * (4 * M1 + 1) * (4 * M2 + 1) * (4 * M3 + 1);
   HIP_TRY(hipMemcpyAsync(F, Fd.p, sizeof(cd) * cnt, hipMemcpyDeviceToHost, c->ctx->stream));
   HIP_TRY(hipStreamSynchronize(c->ctx->stream));
   return MVPB_OK;
@@ -579,6 +786,7 @@ static size_t sf_scratch_need(mvpb_cell c, int M1, int M2, int precision) {
 extern "C" int mvpb_structure_factors_noalloc(mvpb_cell c, int M1, int M2, int precision, double *F,
                                               unsigned flags) {
   if (!c || !F) return set_err(MVPB_E_INVALID, "NULL argument");
+  if (c->general) return set_err(MVPB_E_UNSUPPORTED, "cell has a general compliance or is spatial");
   int rc = check_cutoff(M1, M2);
   if (rc) return rc;
   rc = check_precision(precision);
@@ -724,8 +932,11 @@ static int build_plan_group(mvpb_ctx ctx, const mvpb_cell *cells, int g, int M1,
     pl->M1 = M1;
     pl->M2 = M2;
     pl->N = N;
+    pl->n = 2 * N;
+    pl->nsig = 3 * N;
     pl->prec = precision;
     memcpy(pl->T, cells[c]->T, sizeof pl->T);
+    memcpy(pl->T3, cells[c]->T, sizeof pl->T);
     pl->area = cells[c]->area;
     pl->coef.pool = &ctx->pool;
     pl->linvR.pool = &ctx->pool;
@@ -752,6 +963,176 @@ static int build_plan_group(mvpb_ctx ctx, const mvpb_cell *cells, int g, int M1,
   return MVPB_OK;
 }
 
+// Voigt index of the stress component (a, b) (planar: 11, 22, 12; spatial:
+// 11, 22, 33, 23, 13, 12).
+static int voigt_index(int dim, int a, int b) {
+  if (a == b) return a;
+  if (dim == 2) return 2;
+  const int lo = std::min(a, b), hi = std::max(a, b);
+  return lo == 1 ? 3 : (hi == 2 ? 4 : 5);   // (1,2) -> 3, (0,2) -> 4, (0,1) -> 5
+}
+
+// Plan of the general layout for one pixel or voxel cell: weight fields on the
+// difference grid, the full Phi (n_s N square) and R = T(rho) by block-Toeplitz
+// scatter, their Cholesky factors and inverse factors, the matrices
+// Z_l = (I (x) L_R^-1) H'_l L_P^-H (l = 0: the G part of K, l >= 1: the unit
+// Bloch part along axis l), and the coefficients |Omega|^2 (Z_l Z_m^H + ...)
+// of C(k) (see general.hip).
+static int build_plan_general(mvpb_cell c, int M1, int M2, int M3, int precision, mvpb_plan *out) {
+  mvpb_ctx ctx = c->ctx;
+  hipStream_t st = ctx->stream;
+  const int d = c->dim, ns = d == 2 ? 3 : 6;
+  const int N = (2 * M1 + 1) * (2 * M2 + 1) * (2 * M3 + 1), n = d * N, nsig = ns * N;
+  const int nc = (d + 1) * (d + 2) / 2;
+  const size_t NN = (size_t)N * N, SS = (size_t)nsig * nsig, nn = (size_t)n * n;
+  Pool *pool = &ctx->pool;
+  DevBuf X1(pool), X2(pool), F(pool), Phi(pool), R(pool), stat(pool), gvec(pool), Z(pool), ptrs(pool);
+  int rc = run_structure_factors_general(c, M1, M2, M3, X1, X2, F);
+  if (rc) return rc;
+  std::unique_ptr<mvpb_plan_s> pl(new mvpb_plan_s());
+  pl->ctx = ctx;
+  pl->coef.pool = pl->linvR.pool = pl->linvSD.pool = pl->linvPhi.pool = pool;
+  HIP_TRY(Phi.alloc(sizeof(cd) * SS));
+  HIP_TRY(pl->linvPhi.alloc(sizeof(cd) * SS));
+  HIP_TRY(R.alloc(sizeof(cd) * NN));
+  HIP_TRY(pl->linvR.alloc(sizeof(cd) * NN));
+  HIP_TRY(stat.alloc(sizeof(int) * 2));
+  HIP_TRY(Z.alloc(sizeof(cd) * (d + 1) * (size_t)n * nsig));
+  HIP_TRY(pl->coef.alloc(sizeof(cd) * nc * nn));
+  // Phi block (s, t) from field f(min, max) (upper-triangle packing), R from rho
+  int fmap[36];
+  for (int a = 0; a < ns; ++a)
+    for (int b = 0; b < ns; ++b) {
+      const int lo = std::min(a, b), hi = std::max(a, b);
+      fmap[a * ns + b] = lo * ns - lo * (lo - 1) / 2 + (hi - lo);
+    }
+  const int frho = c->nf - 1;
+  HIP_TRY(launch_toeplitz_blocks(F.as<cd>(), M1, M2, M3, N, ns, fmap, Phi.as<cd>(), st));
+  HIP_TRY(launch_toeplitz_blocks(F.as<cd>(), M1, M2, M3, N, 1, &frho, R.as<cd>(), st));
+  // G_l vectors (signed plane-wave indices): G_l[i] = 2 pi (T n_i)_l
+  std::vector<double> gv((size_t)d * N);
+  for (int a = -M1; a <= M1; ++a)
+    for (int b = -M2; b <= M2; ++b)
+      for (int e = -M3; e <= M3; ++e) {
+        const int i = ((a + M1) * (2 * M2 + 1) + (b + M2)) * (2 * M3 + 1) + (e + M3);
+        const double nv[3] = {(double)a, (double)b, (double)e};
+        for (int l = 0; l < d; ++l) {
+          double acc = 0.0;
+          for (int j = 0; j < d; ++j) acc += c->T3[l * d + j] * nv[j];
+          gv[(size_t)l * N + i] = 2.0 * M_PI * acc;
+        }
+      }
+  HIP_TRY(gvec.alloc(sizeof(double) * gv.size()));
+  HIP_TRY(hipMemcpyAsync(gvec.p, gv.data(), sizeof(double) * gv.size(), hipMemcpyHostToDevice, st));
+  cd *P = Phi.as<cd>(), *LP = pl->linvPhi.as<cd>(), *Rm = R.as<cd>(), *LR = pl->linvR.as<cd>(), *Zm = Z.as<cd>();
+  cd *coef = pl->coef.as<cd>();
+  const double *gd = gvec.as<double>();
+  // Device pointer table: consecutive lists per batched launch.
+  std::vector<const void *> tab = {P, LP, Rm, LR};
+  auto list = [&](std::vector<const void *> v) {
+    const size_t o = tab.size();
+    tab.insert(tab.end(), v.begin(), v.end());
+    return o;
+  };
+  // B_s = (columns s N .. (s+1) N - 1 of L_P^-1)^H (N x nsig)
+  auto Bs = [&](int s_) { return (const void *)(LP + (size_t)s_ * N * nsig); };
+  // Z_0 block a = sum_b L_R^-1 diag(G_b) B_{voigt(a,b)}: one launch per b over a
+  size_t z0[3][4];
+  for (int b = 0; b < d; ++b) {
+    std::vector<const void *> A, B, C, S;
+    for (int a = 0; a < d; ++a) {
+      A.push_back(LR);
+      B.push_back(Bs(voigt_index(d, a, b)));
+      C.push_back(Zm + (size_t)a * N);
+      S.push_back(gd + (size_t)b * N);
+    }
+    z0[b][0] = list(A);
+    z0[b][1] = list(B);
+    z0[b][2] = list(C);
+    z0[b][3] = list(S);
+  }
+  // Z_l block a = L_R^-1 B_{voigt(a, l-1)}, l = 1 .. d: one launch
+  size_t zl[3];
+  {
+    std::vector<const void *> A, B, C;
+    for (int l = 1; l <= d; ++l)
+      for (int a = 0; a < d; ++a) {
+        A.push_back(LR);
+        B.push_back(Bs(voigt_index(d, a, l - 1)));
+        C.push_back(Zm + (size_t)l * n * nsig + (size_t)a * N);
+      }
+    zl[0] = list(A);
+    zl[1] = list(B);
+    zl[2] = list(C);
+  }
+  // coefficients |Omega|^2 Z_l Z_m^H for l <= m, then + |Omega|^2 Z_m Z_l^H for l < m
+  size_t c1[3], c2[3];
+  int n2 = 0;
+  {
+    std::vector<const void *> A1, B1, C1, A2, B2, C2;
+    int q = 0;
+    for (int l = 0; l <= d; ++l)
+      for (int m = l; m <= d; ++m, ++q) {
+        A1.push_back(Zm + (size_t)l * n * nsig);
+        B1.push_back(Zm + (size_t)m * n * nsig);
+        C1.push_back(coef + (size_t)q * nn);
+        if (l < m) {
+          A2.push_back(Zm + (size_t)m * n * nsig);
+          B2.push_back(Zm + (size_t)l * n * nsig);
+          C2.push_back(coef + (size_t)q * nn);
+        }
+      }
+    n2 = (int)A2.size();
+    c1[0] = list(A1); c1[1] = list(B1); c1[2] = list(C1);
+    c2[0] = list(A2); c2[1] = list(B2); c2[2] = list(C2);
+  }
+  HIP_TRY(ptrs.alloc(sizeof(void *) * tab.size()));
+  HIP_TRY(hipMemcpyAsync(ptrs.p, tab.data(), sizeof(void *) * tab.size(), hipMemcpyHostToDevice, st));
+  void **dp = ptrs.as<void *>();
+  auto cp = [&](size_t o) { return (const cd *const *)(dp + o); };
+  HIP_TRY(launch_potrf_trtri((cd *const *)dp, (cd *const *)(dp + 1), stat.as<int>(), 1, nsig, st));
+  HIP_TRY(launch_potrf_trtri((cd *const *)(dp + 2), (cd *const *)(dp + 3), stat.as<int>() + 1, 1, N, st));
+  int hstat[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(hstat, stat.p, sizeof hstat, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hstat[0] || hstat[1])
+    return set_err(MVPB_E_NOT_PD, "%s is not positive definite (pivot %d)",
+                   hstat[0] ? "compliance matrix Phi" : "density matrix Omega", (hstat[0] ? hstat[0] : hstat[1]) - 1);
+  for (int b = 0; b < d; ++b) {
+    GemmBatch bt{cp(z0[b][0]), cp(z0[b][1]), (cd *const *)(dp + z0[b][2]), (const double *const *)(dp + z0[b][3]),
+                 N, nsig, n};
+    HIP_TRY(launch_zgemm(OP_N, OP_C, N, nsig, N, mk(1.0, 0.0), bt, mk(b == 0 ? 0.0 : 1.0, 0.0), d, st));
+  }
+  {
+    GemmBatch bt{cp(zl[0]), cp(zl[1]), (cd *const *)(dp + zl[2]), nullptr, N, nsig, n};
+    HIP_TRY(launch_zgemm(OP_N, OP_C, N, nsig, N, mk(1.0, 0.0), bt, mk(0.0, 0.0), d * d, st));
+  }
+  const double v2 = c->area * c->area;
+  {
+    GemmBatch bt{cp(c1[0]), cp(c1[1]), (cd *const *)(dp + c1[2]), nullptr, n, n, n};
+    HIP_TRY(launch_zgemm(OP_N, OP_C, n, n, nsig, mk(v2, 0.0), bt, mk(0.0, 0.0), nc, st));
+  }
+  {
+    GemmBatch bt{cp(c2[0]), cp(c2[1]), (cd *const *)(dp + c2[2]), nullptr, n, n, n};
+    HIP_TRY(launch_zgemm(OP_N, OP_C, n, n, nsig, mk(v2, 0.0), bt, mk(1.0, 0.0), n2, st));
+  }
+  pl->M1 = M1;
+  pl->M2 = M2;
+  pl->M3 = M3;
+  pl->N = N;
+  pl->prec = precision;
+  pl->dim = d;
+  pl->n = n;
+  pl->nsig = nsig;
+  pl->qdim = d;
+  pl->area = c->area;
+  memcpy(pl->T, c->T, sizeof pl->T);
+  memcpy(pl->T3, c->T3, sizeof pl->T3);
+  ctx->children++;
+  *out = pl.release();
+  return MVPB_OK;
+}
+
 extern "C" int mvpb_plan_create(mvpb_cell c, int M1, int M2, int precision, mvpb_plan *out) {
   if (!c || !out) return set_err(MVPB_E_INVALID, "NULL argument");
   int rc = check_cutoff(M1, M2);
@@ -760,10 +1141,32 @@ extern "C" int mvpb_plan_create(mvpb_cell c, int M1, int M2, int precision, mvpb
   if (rc) return rc;
   mvpb_ctx ctx = c->ctx;
   if (ctx->closing) return set_err(MVPB_E_INVALID, "context has been destroyed");
+  if (c->dim != 2) return set_err(MVPB_E_INVALID, "a voxel cell needs mvpb_plan_create3");
   HIP_TRY(hipSetDevice(ctx->device));
   ProfBind pb(ctx);
   mvpb_plan pl = nullptr;
-  rc = build_plan_group(ctx, &c, 1, M1, M2, precision, &pl, 0);
+  if (c->general || (precision & MVPB_PREC_GENERAL))
+    rc = build_plan_general(c, M1, M2, 0, precision, &pl);
+  else
+    rc = build_plan_group(ctx, &c, 1, M1, M2, precision, &pl, 0);
+  if (rc) return rc;
+  *out = pl;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_plan_create3(mvpb_cell c, int M1, int M2, int M3, int precision, mvpb_plan *out) {
+  if (!c || !out) return set_err(MVPB_E_INVALID, "NULL argument");
+  int rc = check_cutoff3(c, M1, M2, M3);
+  if (rc) return rc;
+  rc = check_precision(precision);
+  if (rc) return rc;
+  if (c->dim == 2) return mvpb_plan_create(c, M1, M2, precision, out);
+  mvpb_ctx ctx = c->ctx;
+  if (ctx->closing) return set_err(MVPB_E_INVALID, "context has been destroyed");
+  HIP_TRY(hipSetDevice(ctx->device));
+  ProfBind pb(ctx);
+  mvpb_plan pl = nullptr;
+  rc = build_plan_general(c, M1, M2, M3, precision, &pl);
   if (rc) return rc;
   *out = pl;
   return MVPB_OK;
@@ -776,13 +1179,32 @@ extern "C" int mvpb_plan_create_batch(mvpb_ctx ctx, int n, const mvpb_cell *cell
   if (n < 0 || (n > 0 && (!cells || !M1 || !M2 || !out))) return set_err(MVPB_E_INVALID, "NULL argument");
   rc = check_precision(precision);
   if (rc) return rc;
+  bool general = (precision & MVPB_PREC_GENERAL) != 0;
   for (int i = 0; i < n; ++i) {
     if (!cells[i] || cells[i]->ctx != ctx) return set_err(MVPB_E_INVALID, "cell %d missing or from another context", i);
+    if (cells[i]->dim != 2) return set_err(MVPB_E_INVALID, "cell %d is a voxel cell: use mvpb_plan_create3", i);
     rc = check_cutoff(M1[i], M2[i]);
     if (rc) return rc;
+    general = general || cells[i]->general;
   }
   HIP_TRY(hipSetDevice(ctx->device));
   ProfBind pb(ctx);
+  if (general) {
+    // general layout: one build per cell
+    std::vector<mvpb_plan> res(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+      rc = (cells[i]->general || (precision & MVPB_PREC_GENERAL))
+               ? build_plan_general(cells[i], M1[i], M2[i], 0, precision, &res[i])
+               : build_plan_group(ctx, &cells[i], 1, M1[i], M2[i], precision, &res[i], i);
+      if (rc) {
+        for (mvpb_plan p : res)
+          if (p) mvpb_plan_destroy(p);
+        return rc;
+      }
+    }
+    for (int i = 0; i < n; ++i) out[i] = res[i];
+    return MVPB_OK;
+  }
   // group by cutoff, keep each group's temporaries under ~8 GB
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -821,8 +1243,8 @@ extern "C" int mvpb_plan_create_batch(mvpb_ctx ctx, int n, const mvpb_cell *cell
 
 extern "C" int mvpb_plan_dofs(mvpb_plan p, int *n_u, int *n_s) {
   if (!p) return set_err(MVPB_E_INVALID, "NULL plan");
-  if (n_u) *n_u = 2 * p->N;
-  if (n_s) *n_s = 3 * p->N;
+  if (n_u) *n_u = p->n;
+  if (n_s) *n_s = p->nsig;
   return MVPB_OK;
 }
 
@@ -868,6 +1290,7 @@ static void item_layout(int n, int nb, bool fp32, size_t *sz, int *count) {
   sz[k++] = sizeof(cd) * ((size_t)(n + 63) / 64) * 2 * nb * nb;  // Gp
   sz[k++] = sizeof(cd) * (size_t)nb * nb;        // Lr
   sz[k++] = fp32 ? sizeof(cf) * (size_t)n * nb : 0;  // Yb (FP32 path only)
+  sz[k++] = sizeof(double);                      // acc
   *count = k;
 }
 
@@ -921,6 +1344,7 @@ static EigItem carve_item(char *base, int n, int nb, bool fp32) {
   it.Lr = (cd *)take();
   char *yb = take();
   it.Yb = fp32 ? (void *)yb : (void *)it.Y;
+  it.acc = (double *)take();
   return it;
 }
 
@@ -970,11 +1394,45 @@ __global__ void gather_omega(const EigItem *items, int n_items, int nb, double *
   out[(size_t)it.slot * nb + b] = v;
 }
 
+__global__ void set_double(double *p, double v) { *p = v; }
+
+// Largest error estimate of the items' refined bands into *out (running max
+// over the launch sequences of one solve).
+__global__ void __launch_bounds__(256) max_acc(const EigItem *items, int n_items, double *out) {
+  __shared__ double red[4];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n_items; i += 256) v = fmax(v, *items[i].acc);
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = fmax(fmax(fmax(*out, red[0]), fmax(red[1], red[2])), red[3]);
+}
+
+// Start of a solve: clear the running error estimate.
+static int acc_begin(mvpb_ctx ctx) {
+  HIP_TRY(ctx->accbuf.reserve(sizeof(double)));
+  hipLaunchKernelGGL(set_double, dim3(1), dim3(1), 0, ctx->stream, ctx->accbuf.as<double>(), 0.0);
+  HIP_TRY(hipGetLastError());
+  return MVPB_OK;
+}
+
+// End of a synchronous solve (stream drained): record the estimate and apply
+// the accuracy bar to solves with the FP32 reduction.
+static int acc_finish(mvpb_ctx ctx, bool fp32) {
+  double v = 0.0;
+  HIP_TRY(hipMemcpy(&v, ctx->accbuf.p, sizeof v, hipMemcpyDeviceToHost));
+  ctx->last_acc = v;
+  if (fp32 && ctx->acc_tol > 0.0 && !(v <= ctx->acc_tol))
+    return set_err(MVPB_E_ACCURACY, "estimated relative frequency error %.3g exceeds the bar %.3g", v,
+                   ctx->acc_tol);
+  return MVPB_OK;
+}
+
 // One batch of work items that share a workspace allocation.
 struct Job {
   mvpb_plan plan;
-  double Q1, Q2;
-  int out_index;   // position in the caller's flattened output
+  double Q1, Q2, Q3;   // Bloch vector in the reciprocal basis (Q3 = 0 for planar plans)
+  int out_index;       // position in the caller's flattened output
 };
 
 constexpr size_t MAX_GRAPHS = 16;
@@ -991,7 +1449,10 @@ static std::string launch_signature(const std::vector<Job> &jobs, int nb, bool f
   put(fp32 ? 1 : 0);
   put(parts);
   put((int)jobs.size());
-  for (const Job &j : jobs) put(j.plan->N);
+  for (const Job &j : jobs) {
+    put(j.plan->n);
+    put(j.plan->dim);
+  }
   return k;
 }
 
@@ -1004,8 +1465,11 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   if (n_items == 0) return MVPB_OK;
   size_t total = 0;
   int n_max = 0, n_min = 1 << 30;
+  bool any_iso = false, any_general = false;
   for (const Job &j : jobs) {
-    const int n = 2 * j.plan->N;
+    const int n = j.plan->n;
+    any_iso = any_iso || j.plan->dim == 0;
+    any_general = any_general || j.plan->dim != 0;
     total += item_bytes(n, nb, fp32);
     n_max = std::max(n_max, n);
     n_min = std::min(n_min, n);
@@ -1030,23 +1494,35 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   size_t off = 0;
   for (int i = 0; i < n_items; ++i) {
     const Job &j = jobs[i];
-    const int n = 2 * j.plan->N;
+    const int n = j.plan->n;
     EigItem it = carve_item(ctx->ws.as<char>() + off, n, nb, fp32);
     off += item_bytes(n, nb, fp32);
     it.coef = j.plan->coef.as<cd>();
     it.N = j.plan->N;
+    it.n = n;
+    it.dim = j.plan->dim;
+    it.check = fp32 ? 1 : 0;
     it.nb = nb;
     it.slot = j.out_index;
-    const double *T = j.plan->T;
-    it.kap1 = 2.0 * M_PI * (T[0] * j.Q1 + T[1] * j.Q2);
-    it.kap2 = 2.0 * M_PI * (T[2] * j.Q1 + T[3] * j.Q2);
+    // kappa = 2 pi T Q (Cartesian Bloch vector)
+    const int qd = j.plan->qdim;
+    const double *T = j.plan->T3;
+    const double q[3] = {j.Q1, j.Q2, j.Q3};
+    double kap[3] = {0.0, 0.0, 0.0};
+    for (int l = 0; l < qd; ++l)
+      for (int m = 0; m < qd; ++m) kap[l] += 2.0 * M_PI * T[l * qd + m] * q[m];
+    it.kap1 = kap[0];
+    it.kap2 = kap[1];
+    it.kap3 = kap[2];
     items[i] = it;
   }
   HIP_TRY(hipMemcpyAsync(ctx->items.p, items.data(), sizeof(EigItem) * n_items, hipMemcpyHostToDevice, st));
   const EigItem *d_items = ctx->items.as<EigItem>();
 
   auto enqueue = [&]() -> hipError_t {
-    hipError_t e = launch_form_operator(d_items, n_items, n_max, fp32, st);
+    hipError_t e = hipSuccess;
+    if (any_iso) e = launch_form_operator(d_items, n_items, n_max, fp32, st);
+    if (e == hipSuccess && any_general) e = launch_form_operator_general(d_items, n_items, n_max, fp32, st);
     // stage 1 in independent parts of the items, one per stream
     ItemPart parts[MAX_SIDE + 1];
     const int n_parts = std::max(1, std::min(stage1_parts(), n_items));
@@ -1058,8 +1534,8 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
       pt.n_min = 1 << 30;
       pt.n_max = 0;
       for (int i = i0; i < i1; ++i) {
-        pt.n_min = std::min(pt.n_min, 2 * jobs[i].plan->N);
-        pt.n_max = std::max(pt.n_max, 2 * jobs[i].plan->N);
+        pt.n_min = std::min(pt.n_min, jobs[i].plan->n);
+        pt.n_max = std::max(pt.n_max, jobs[i].plan->n);
       }
       pt.stream = q == 0 ? st : ctx->side[q - 1];
     }
@@ -1076,7 +1552,7 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     if (e == hipSuccess) e = launch_stage2(d_items, n_items, n_max, fp32, ctl, st);
     if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, n_max, nb, st);
     if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_min, n_max, nb, fp32, st);
-    if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, n_max, nb, st);
+    if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, n_max, nb, fp32, st);
     return e;
   };
   if (use_graph) {
@@ -1117,47 +1593,46 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   hipLaunchKernelGGL(gather_omega, dim3((n_items * nb + 255) / 256), dim3(256), 0, st, d_items, n_items, nb,
                      omega_dev);
   HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(max_acc, dim3(1), dim3(256), 0, st, d_items, n_items, ctx->accbuf.as<double>());
+  HIP_TRY(hipGetLastError());
   if (U_dev) {
-    // U_t = [L_R^-H Z_t(0:N, :); L_R^-H Z_t(N:2N, :)], written in caller order
+    // U_t block c = L_R^-H Z_t(c N : (c+1) N, :) for the d displacement
+    // components (d = n / N), written in caller order
     std::vector<const void *> hp;
-    hp.reserve(6 * n_items);
-    for (int i = 0; i < n_items; ++i) hp.push_back(jobs[i].plan->linvR.p);
-    for (int i = 0; i < n_items; ++i) hp.push_back(jobs[i].plan->linvR.p);
-    for (int i = 0; i < n_items; ++i) hp.push_back(items[i].Z);
-    for (int i = 0; i < n_items; ++i) hp.push_back(items[i].Z + jobs[i].plan->N);
-    for (int i = 0; i < n_items; ++i) hp.push_back(U_dev + (size_t)jobs[i].out_index * nb * 2 * jobs[i].plan->N * 2);
-    for (int i = 0; i < n_items; ++i)
-      hp.push_back(U_dev + ((size_t)jobs[i].out_index * nb * 2 * jobs[i].plan->N + jobs[i].plan->N) * 2);
+    int dmax = 0;
+    for (int i = 0; i < n_items; ++i) dmax = std::max(dmax, jobs[i].plan->n / jobs[i].plan->N);
+    // table per component c: [A: n_items][B: n_items][C: n_items]
+    for (int c = 0; c < dmax; ++c) {
+      for (int i = 0; i < n_items; ++i) hp.push_back(jobs[i].plan->linvR.p);
+      for (int i = 0; i < n_items; ++i)
+        hp.push_back(items[i].Z + (size_t)std::min(c, jobs[i].plan->n / jobs[i].plan->N - 1) * jobs[i].plan->N);
+      for (int i = 0; i < n_items; ++i) {
+        const Job &jb = jobs[i];
+        const int dd = jb.plan->n / jb.plan->N;
+        hp.push_back(U_dev + ((size_t)jb.out_index * nb * jb.plan->n + (size_t)std::min(c, dd - 1) * jb.plan->N) * 2);
+      }
+    }
     DevBuf ptrs(&ctx->pool);
     HIP_TRY(ptrs.alloc(sizeof(void *) * hp.size()));
     HIP_TRY(hipMemcpyAsync(ptrs.p, hp.data(), sizeof(void *) * hp.size(), hipMemcpyHostToDevice, st));
     void **dp = ptrs.as<void *>();
-    // items of one N (every mvpb_solve call): two batched products and one
+    auto at = [&](int c, int part, int i) { return dp + (size_t)c * 3 * n_items + (size_t)part * n_items + i; };
+    // items of one operator (every mvpb_solve call): d batched products and one
     // normalisation over all of them; otherwise item by item
     bool same_n = true;
-    for (int i = 1; i < n_items; ++i) same_n = same_n && jobs[i].plan->N == jobs[0].plan->N;
-    if (same_n) {
-      const int N = jobs[0].plan->N, n = 2 * N;
-      GemmBatch b1{(const cd *const *)(dp + 0 * n_items), (const cd *const *)(dp + 2 * n_items),
-                   (cd *const *)(dp + 4 * n_items), nullptr, N, n, n};
-      HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), b1, mk(0.0, 0.0), n_items, st));
-      GemmBatch b2{(const cd *const *)(dp + 1 * n_items), (const cd *const *)(dp + 3 * n_items),
-                   (cd *const *)(dp + 5 * n_items), nullptr, N, n, n};
-      HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), b2, mk(0.0, 0.0), n_items, st));
-      // the output indices of the items are a permutation of 0 .. n_items-1
-      hipLaunchKernelGGL(normalize_phase, dim3(n_items * nb), dim3(256), 0, st, (cd *)U_dev, n, n_items * nb);
-      HIP_TRY(hipGetLastError());
-    }
-    for (int i = 0; i < n_items && !same_n; ++i) {
-      const int N = jobs[i].plan->N, n = 2 * N;
-      GemmBatch b1{(const cd *const *)(dp + 0 * n_items + i), (const cd *const *)(dp + 2 * n_items + i),
-                   (cd *const *)(dp + 4 * n_items + i), nullptr, N, n, n};
-      HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), b1, mk(0.0, 0.0), 1, st));
-      GemmBatch b2{(const cd *const *)(dp + 1 * n_items + i), (const cd *const *)(dp + 3 * n_items + i),
-                   (cd *const *)(dp + 5 * n_items + i), nullptr, N, n, n};
-      HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), b2, mk(0.0, 0.0), 1, st));
-      hipLaunchKernelGGL(normalize_phase, dim3(nb), dim3(256), 0, st,
-                         (cd *)(U_dev + (size_t)jobs[i].out_index * nb * n * 2), n, nb);
+    for (int i = 1; i < n_items; ++i)
+      same_n = same_n && jobs[i].plan->N == jobs[0].plan->N && jobs[i].plan->n == jobs[0].plan->n;
+    const int groups = same_n ? 1 : n_items;
+    for (int g = 0; g < groups; ++g) {
+      const int i0 = same_n ? 0 : g, cnt = same_n ? n_items : 1;
+      const int N = jobs[i0].plan->N, n = jobs[i0].plan->n, dd = n / N;
+      for (int c = 0; c < dd; ++c) {
+        GemmBatch bt{(const cd *const *)at(c, 0, i0), (const cd *const *)at(c, 1, i0), (cd *const *)at(c, 2, i0),
+                     nullptr, N, n, n};
+        HIP_TRY(launch_zgemm(OP_C, OP_N, N, nb, N, mk(1.0, 0.0), bt, mk(0.0, 0.0), cnt, st));
+      }
+      cd *u0 = (cd *)(U_dev + (same_n ? 0 : (size_t)jobs[i0].out_index * nb * n * 2));
+      hipLaunchKernelGGL(normalize_phase, dim3(cnt * nb), dim3(256), 0, st, u0, n, cnt * nb);
       HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(st));
@@ -1165,20 +1640,58 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   return MVPB_OK;
 }
 
-static bool q_ok(const double *Q, int n);
+static bool q_ok(const double *Q, int count);
 
 extern "C" int mvpb_stress_modes(mvpb_plan p, int n_k, const double *Q, int n_bands, const double *U, double *S,
                                  unsigned flags) {
   if (!p || !Q || !U || !S) return set_err(MVPB_E_INVALID, "NULL argument");
   if (n_k < 0) return set_err(MVPB_E_INVALID, "n_k must be non-negative");
   if (n_k == 0) return MVPB_OK;
-  if (n_bands < 1 || n_bands > 2 * p->N) return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, 2N]", n_bands);
-  if (!q_ok(Q, n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
+  if (n_bands < 1 || n_bands > p->n) return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, n_u]", n_bands);
+  if (!q_ok(Q, p->qdim * n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
   mvpb_ctx ctx = p->ctx;
   HIP_TRY(hipSetDevice(ctx->device));
   ProfBind pb(ctx);
   hipStream_t st = ctx->stream;
   const bool dev = flags & MVPB_F_DEVICE_PTRS;
+  if (p->dim != 0) {
+    // general layout: X = H* U, then S = -L_P^-H (L_P^-1 X) with the plan's inverse factor
+    const int nb = n_bands, n = p->n, ns = p->nsig, qd = p->qdim;
+    const size_t u_bytes = sizeof(cd) * (size_t)n_k * nb * n, s_bytes = sizeof(cd) * (size_t)n_k * nb * ns;
+    DevBuf qd_(&ctx->pool), ud(&ctx->pool), sd(&ctx->pool), X(&ctx->pool), Y(&ctx->pool), ptrs(&ctx->pool);
+    HIP_TRY(qd_.alloc(sizeof(double) * qd * (size_t)n_k));
+    HIP_TRY(hipMemcpyAsync(qd_.p, Q, sizeof(double) * qd * (size_t)n_k, hipMemcpyHostToDevice, st));
+    const cd *u_in = (const cd *)U;
+    cd *s_out = (cd *)S;
+    if (!dev) {
+      HIP_TRY(ud.alloc(u_bytes));
+      HIP_TRY(hipMemcpyAsync(ud.p, U, u_bytes, hipMemcpyHostToDevice, st));
+      u_in = ud.as<cd>();
+      HIP_TRY(sd.alloc(s_bytes));
+      s_out = sd.as<cd>();
+    }
+    HIP_TRY(X.alloc(s_bytes));
+    HIP_TRY(Y.alloc(s_bytes));
+    HIP_TRY(launch_stress_rhs_general(u_in, qd_.as<double>(), n_k, nb, p->dim, p->M1, p->M2, p->M3, p->T3, p->area,
+                                      X.as<cd>(), st));
+    std::vector<const void *> hp;
+    for (int t = 0; t < n_k; ++t) hp.push_back(p->linvPhi.p);
+    for (int t = 0; t < n_k; ++t) hp.push_back(X.as<cd>() + (size_t)t * nb * ns);
+    for (int t = 0; t < n_k; ++t) hp.push_back(Y.as<cd>() + (size_t)t * nb * ns);
+    for (int t = 0; t < n_k; ++t) hp.push_back(s_out + (size_t)t * nb * ns);
+    HIP_TRY(ptrs.alloc(sizeof(void *) * hp.size()));
+    HIP_TRY(hipMemcpyAsync(ptrs.p, hp.data(), sizeof(void *) * hp.size(), hipMemcpyHostToDevice, st));
+    void **dp = ptrs.as<void *>();
+    GemmBatch b1{(const cd *const *)dp, (const cd *const *)(dp + n_k), (cd *const *)(dp + 2 * n_k), nullptr, ns, ns,
+                 ns};
+    HIP_TRY(launch_zgemm(OP_N, OP_N, ns, nb, ns, mk(1.0, 0.0), b1, mk(0.0, 0.0), n_k, st));
+    GemmBatch b2{(const cd *const *)dp, (const cd *const *)(dp + 2 * n_k), (cd *const *)(dp + 3 * n_k), nullptr, ns,
+                 ns, ns};
+    HIP_TRY(launch_zgemm(OP_C, OP_N, ns, nb, ns, mk(-1.0, 0.0), b2, mk(0.0, 0.0), n_k, st));
+    if (!dev) HIP_TRY(hipMemcpyAsync(S, s_out, s_bytes, hipMemcpyDeviceToHost, st));
+    if (!(flags & MVPB_F_ASYNC) || !dev) HIP_TRY(hipStreamSynchronize(st));
+    return MVPB_OK;
+  }
   const int N = p->N, nb = n_bands;
   const size_t NN = (size_t)N * N, blk = (size_t)3 * N * nb;   // one k: three N x nb blocks
   const size_t u_bytes = sizeof(cd) * (size_t)n_k * nb * 2 * N, s_bytes = sizeof(cd) * (size_t)n_k * blk;
@@ -1232,8 +1745,9 @@ static int check_failed_items(const double *om, size_t count, int nb) {
   return MVPB_OK;
 }
 
-static bool q_ok(const double *Q, int n) {
-  for (int i = 0; i < 2 * n; ++i)
+// count doubles of Bloch-vector components, all finite
+static bool q_ok(const double *Q, int count) {
+  for (int i = 0; i < count; ++i)
     if (!isfinite(Q[i])) return false;
   return true;
 }
@@ -1243,15 +1757,16 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
   if (!p || !Q || !omega) return set_err(MVPB_E_INVALID, "NULL argument");
   if (n_k < 0) return set_err(MVPB_E_INVALID, "n_k must be non-negative");
   if (n_k == 0) return MVPB_OK;
-  if (n_bands < 1 || n_bands > 2 * p->N || n_bands > RR_MAX_BANDS)
-    return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, min(2N=%d, %d)]", n_bands, 2 * p->N, RR_MAX_BANDS);
-  if (!q_ok(Q, n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
+  if (n_bands < 1 || n_bands > p->n || n_bands > RR_MAX_BANDS)
+    return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, min(n_u=%d, %d)]", n_bands, p->n, RR_MAX_BANDS);
+  const int qd = p->qdim;
+  if (!q_ok(Q, qd * n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
   mvpb_ctx ctx = p->ctx;
   HIP_TRY(hipSetDevice(ctx->device));
   ProfBind pb(ctx);
   hipStream_t st = ctx->stream;
   const bool dev = flags & MVPB_F_DEVICE_PTRS;
-  const int n = 2 * p->N;
+  const int n = p->n;
   // chunk the k list so that the workspace (items and the bulge-chasing
   // control words) stays within the cap
   const size_t per = item_bytes(n, n_bands, (p->prec & MVPB_PREC_EIG_FP32_RR64) != 0);
@@ -1261,6 +1776,9 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
   int chunk = (int)std::min<size_t>((size_t)n_k, budget / per);
   while (chunk > 1 && solve_bytes(chunk, per) > budget) --chunk;
   const bool graph = !(ctx->prof.on);
+  const bool fp32 = (p->prec & MVPB_PREC_EIG_FP32_RR64) != 0;
+  int rc = acc_begin(ctx);
+  if (rc) return rc;
   DevBuf om_dev(&ctx->pool), u_dev(&ctx->pool);
   double *om_out = omega;
   double *u_out = U;
@@ -1275,9 +1793,12 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
   for (int k0 = 0; k0 < n_k; k0 += chunk) {
     const int kc = std::min(chunk, n_k - k0);
     std::vector<Job> jobs(kc);
-    for (int t = 0; t < kc; ++t) jobs[t] = Job{p, Q[2 * (k0 + t)], Q[2 * (k0 + t) + 1], t};
-    int rc = run_items(ctx, jobs, n_bands, om_out + (size_t)k0 * n_bands,
-                       u_out ? u_out + 2 * (size_t)k0 * n_bands * n : nullptr, graph);
+    for (int t = 0; t < kc; ++t) {
+      const double *q = Q + (size_t)qd * (k0 + t);
+      jobs[t] = Job{p, q[0], q[1], qd == 3 ? q[2] : 0.0, t};
+    }
+    rc = run_items(ctx, jobs, n_bands, om_out + (size_t)k0 * n_bands,
+                   u_out ? u_out + 2 * (size_t)k0 * n_bands * n : nullptr, graph);
     if (rc) return rc;
   }
   if (!dev) {
@@ -1285,9 +1806,11 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
     if (U)
       HIP_TRY(hipMemcpyAsync(U, u_out, sizeof(double) * 2 * (size_t)n_k * n_bands * n, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    return check_failed_items(omega, (size_t)n_k * n_bands, n_bands);
+    rc = check_failed_items(omega, (size_t)n_k * n_bands, n_bands);
+    return rc ? rc : acc_finish(ctx, fp32);
   } else if (!(flags & MVPB_F_ASYNC)) {
     HIP_TRY(hipStreamSynchronize(st));
+    return acc_finish(ctx, fp32);
   }
   return MVPB_OK;
 }
@@ -1304,33 +1827,38 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
   for (int i = 0; i < n_plans; ++i) {
     if (!plans[i] || plans[i]->ctx != ctx) return set_err(MVPB_E_INVALID, "plan %d missing or from another context", i);
     if (n_k[i] < 0 || (n_k[i] > 0 && (!Q[i] || !omega[i]))) return set_err(MVPB_E_INVALID, "plan %d: bad k list", i);
-    if (2 * plans[i]->N < n_bands) return set_err(MVPB_E_INVALID, "plan %d: n_bands > 2N", i);
+    if (plans[i]->n < n_bands) return set_err(MVPB_E_INVALID, "plan %d: n_bands > n_u", i);
     if ((plans[i]->prec & MVPB_PREC_EIG_FP32_RR64) != (plans[0]->prec & MVPB_PREC_EIG_FP32_RR64))
       return set_err(MVPB_E_INVALID, "plan %d: all plans of a batch need the same eigensolver precision", i);
-    if (!q_ok(Q[i], n_k[i])) return set_err(MVPB_E_INVALID, "plan %d: non-finite Bloch vector", i);
+    const int qd = plans[i]->qdim;
+    if (!q_ok(Q[i], qd * n_k[i])) return set_err(MVPB_E_INVALID, "plan %d: non-finite Bloch vector", i);
     base[i + 1] = base[i] + n_k[i];
-    for (int t = 0; t < n_k[i]; ++t)
-      jobs.push_back(Job{plans[i], Q[i][2 * t], Q[i][2 * t + 1], (int)(base[i] + t)});
+    for (int t = 0; t < n_k[i]; ++t) {
+      const double *q = Q[i] + (size_t)qd * t;
+      jobs.push_back(Job{plans[i], q[0], q[1], qd == 3 ? q[2] : 0.0, (int)(base[i] + t)});
+    }
   }
   if (jobs.empty()) return MVPB_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   // largest items first so the longest work starts earliest; chunks of
   // similar size share one launch sequence (captured once, replayed)
-  std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.plan->N > b.plan->N; });
+  std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.plan->n > b.plan->n; });
   const bool fp32 = (jobs[0].plan->prec & MVPB_PREC_EIG_FP32_RR64) != 0;
   const size_t budget = ctx->cap ? ctx->cap : (size_t)24 << 30;
+  rc = acc_begin(ctx);
+  if (rc) return rc;
   DevBuf om(&ctx->pool);
   HIP_TRY(om.alloc(sizeof(double) * base[n_plans] * n_bands));
   size_t j0 = 0;
   while (j0 < jobs.size()) {
     size_t j1 = j0, bytes = 0;
-    const int n0 = 2 * jobs[j0].plan->N;
+    const int n0 = jobs[j0].plan->n;
     while (j1 < jobs.size()) {
-      const size_t b = item_bytes(2 * jobs[j1].plan->N, n_bands, fp32);
+      const size_t b = item_bytes(jobs[j1].plan->n, n_bands, fp32);
       // keep items of one chunk within a factor ~1.5 in order so that the
       // launch sequence sized for the largest wastes little on the rest
-      if (j1 > j0 && (bytes + b + ctl_bytes(j1 - j0 + 1) > budget || 3 * jobs[j1].plan->N < n0)) break;
+      if (j1 > j0 && (bytes + b + ctl_bytes(j1 - j0 + 1) > budget || 3 * jobs[j1].plan->n < 2 * n0)) break;
       bytes += b;
       ++j1;
     }
@@ -1353,6 +1881,23 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
       rc = check_failed_items(omega[i], (size_t)n_k[i] * n_bands, n_bands);
       if (rc) return rc;
     }
+  if (!dev || !(flags & MVPB_F_ASYNC)) return acc_finish(ctx, fp32);
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_ctx_set_accuracy(mvpb_ctx ctx, double tol) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!(tol >= 0.0) || !isfinite(tol)) return set_err(MVPB_E_INVALID, "tolerance must be finite and >= 0");
+  ctx->acc_tol = tol;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_ctx_last_accuracy(mvpb_ctx ctx, double *estimate) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!estimate) return set_err(MVPB_E_INVALID, "NULL argument");
+  *estimate = ctx->last_acc;
   return MVPB_OK;
 }
 

@@ -259,7 +259,8 @@ hipError_t launch_stress_combine(const cd *Z, int n_k, int nb, int N, cd *S, hip
 //   pass B: F_w = S o (E1 . X_w)      (nm x nx) . (nx x nq), complex
 // Precision P: 0 = FP64 inputs / FP64 accumulate (v_mfma_f64_16x16x4f64),
 // 1 = FP32 inputs / FP32 accumulate (v_mfma_f32_16x16x4f32), 2 = BF16 inputs
-// / FP32 accumulate (v_mfma_f32_16x16x16bf16_1k).  Trig factors are computed
+// / FP32 accumulate (v_mfma_f32_16x16x16bf16_1k), 3 = split BF16 (three BF16
+// products per product, FP32 accumulate).  Trig factors are computed
 // in FP64 with exact argument reduction and rounded to the input type.
 // Operand layout (16 x 16 x K): lane l supplies A[l%16][k] and B[k][l%16]
 // for its K-slot, k = (l/16)*KPL + v; it receives D[row(l,v)][l%16] with
@@ -318,6 +319,37 @@ struct Mma<2> {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
   }
   MVPB_DEV static double round_in(double x) { return (double)bf16_value(bf16_bits((float)x)); }
+  MVPB_DEV static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+// Split BF16: every FP32-rounded input x is carried as hi = bf16(x) plus
+// lo = bf16(x - hi) (16 significant bits together), and each product as the
+// three BF16 matrix-core products lo*hi + hi*lo + hi*hi in FP32 accumulation
+// (the lo*lo term, below 2^-16 of the product, is dropped).  This is the
+// three-product bfloat16 scheme of Henry, Tang and Heinecke (ARITH 2019).
+template <>
+struct Mma<3> {
+  typedef float acc;
+  typedef f4_t acc4;
+  static constexpr int KPL = 4;
+  MVPB_DEV static acc4 zero() { return acc4{0.f, 0.f, 0.f, 0.f}; }
+  MVPB_DEV static void split(const double (&x)[4], s4_t &hi, s4_t &lo) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float f = (float)x[v];
+      const short h = bf16_bits(f);
+      hi[v] = h;
+      lo[v] = bf16_bits(f - bf16_value(h));
+    }
+  }
+  MVPB_DEV static acc4 mma(const double (&a)[4], const double (&b)[4], acc4 c) {
+    s4_t ah, al, bh, bl;
+    split(a, ah, al);
+    split(b, bh, bl);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+  }
+  MVPB_DEV static double round_in(double x) { return (double)(float)x; }
   MVPB_DEV static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
@@ -440,6 +472,10 @@ hipError_t launch_structure_factors_mfma(int prec, const int32_t *phase, const d
       hipLaunchKernelGGL(sf_mfma_pass_a<1>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
       hipLaunchKernelGGL(sf_mfma_pass_b<1>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
       break;
+    case 3:
+      hipLaunchKernelGGL(sf_mfma_pass_a<3>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
+      hipLaunchKernelGGL(sf_mfma_pass_b<3>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
+      break;
     default:
       hipLaunchKernelGGL(sf_mfma_pass_a<2>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
       hipLaunchKernelGGL(sf_mfma_pass_b<2>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
@@ -538,6 +574,7 @@ template <typename Item, typename R>
 __global__ void __launch_bounds__(256) form_operator(const Item *__restrict__ items, int tiles_max) {
   __shared__ cd tile[32][33];
   const Item it = items[blockIdx.y];
+  if (it.dim != 0) return;   // general layout: form_operator_general
   const int N = it.N, n = 2 * N;
   const int nt = (n + 31) / 32;
   // linear lower-triangle tile index -> (I, J), I >= J

@@ -161,7 +161,7 @@ he2hb_panel(const EigItem *__restrict__ items, int p) {
   __shared__ C Ub[SW][SW + 1];   // u of each column of the sub-panel
   __shared__ C taus[SW];
   const EigItem it = items[blockIdx.x];
-  const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
+  const int n = it.n, c0 = p * HB, m = n - c0 - HB;
   // this launch handles the items whose panel height is in (LO, RPT NT]
   if (m <= LO || m > RPT * NT) return;
   const int kq = min(m, HB);
@@ -475,7 +475,7 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
   int item, rb;
   if (!xcd_slot(S, n_items, item, rb)) return;
   const EigItem it = items[item];
-  const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
+  const int n = it.n, c0 = p * HB, m = n - c0 - HB;
   if (m <= 0 || rb * 64 >= m) return;
   const int kq = min(m, HB);
   const size_t ld = (size_t)n;
@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
   int item, rb;
   if (!xcd_slot(S, n_items, item, rb)) return;
   const EigItem it = items[item];
-  const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
+  const int n = it.n, c0 = p * HB, m = n - c0 - HB;
   if (m <= 0 || rb * 64 >= m) return;
   const int kq = min(m, HB);
   const size_t ld = (size_t)n;
@@ -675,7 +675,7 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
   int item, t;
   if (!xcd_slot(S, n_items, item, t)) return;
   const EigItem it = items[item];
-  const int n = 2 * it.N, c0 = p * HB, m = n - c0 - HB;
+  const int n = it.n, c0 = p * HB, m = n - c0 - HB;
   if (m <= 0) return;
   const int nt = (m + 63) / 64;
   if (t >= nt * (nt + 1) / 2) return;
@@ -844,7 +844,7 @@ __global__ void __launch_bounds__(256) hb2st_init(const EigItem *__restrict__ it
   if (blockIdx.x == 0 && blockIdx.y == 0)
     for (int e = threadIdx.x; e < ctl_ints; e += 256) gst(ctl, e, e < HB2ST_CTL_TABLE ? 0 : -1);
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N;
+  const int n = it.n;
   const size_t ld = (size_t)n;
   const C *A = (const C *)it.A;
   C *WB = (C *)it.WB;
@@ -864,7 +864,7 @@ template <typename R>
 __global__ void __launch_bounds__(256) hb2st_fini(const EigItem *__restrict__ items) {
   typedef cx<R> C;
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N;
+  const int n = it.n;
   const C *WB = (const C *)it.WB;
   for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
     gst(it.d, r, (double)gld(WB, (size_t)r * HB_LDB).re);
@@ -925,7 +925,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
   const int item = claim[0], a = claim[1];
   if (item < 0 || item >= n_items) return;
   const EigItem it = items[item];
-  const int n = 2 * it.N;
+  const int n = it.n;
   C *__restrict__ WB = (C *)it.WB;
   C *__restrict__ V2 = (C *)it.V2;
   C *__restrict__ tau2 = (C *)it.tau2;
@@ -1145,7 +1145,7 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
   C *Z = (C *)shraw;   // Z[zidx(r, c, nc)]
   __shared__ C S[HB][8], S2[HB][8], Tm[HB][HB + 1];
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, nb = it.nb;
+  const int n = it.n, nb = it.nb;
   if (n - 1 <= 64 * HB) return;   // item of the wavefront kernel (backtransform_2s_wave)
   const int cbase = blockIdx.x * nc;
   if (cbase >= nb) return;
@@ -1248,7 +1248,7 @@ __global__ void __launch_bounds__(BTW_WAVES * 64) __attribute__((amdgpu_waves_pe
 backtransform_2s_wave(const EigItem *__restrict__ items) {
   typedef cx<R> C;
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, nb = it.nb;
+  const int n = it.n, nb = it.nb;
   if (n - 1 > 64 * HB) return;   // item of the LDS kernel (backtransform_2s)
   const int lane = threadIdx.x & 63;
   const int cb = (blockIdx.x * BTW_WAVES + (threadIdx.x >> 6)) * BTW_COLS;   // first column of the wavefront
@@ -1356,7 +1356,7 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_s1(const EigItem *__
   C *Z = (C *)shraw;   // Z[zidx(r, c, nc)]
   __shared__ C S[HB][8], S2[HB][9], Tm[HB][HB + 1];
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, nb = it.nb;
+  const int n = it.n, nb = it.nb;
   const int cbase = blockIdx.x * nc;
   if (cbase >= nb) return;
   const int ncl = min(nc, nb - cbase);

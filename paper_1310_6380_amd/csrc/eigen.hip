@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigIte
   __shared__ int act_s[RR_MAX_BANDS];
   __shared__ int nact_s;
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, nb_all = it.nb, g0 = blockIdx.x;
+  const int n = it.n, nb_all = it.nb, g0 = blockIdx.x;
   if (g0 >= nb_all) return;
   const int nb = (nb_all - g0 + BISI_GROUPS - 1) / BISI_GROUPS;   // eigenvalues of this workgroup
   double *dd = shd, *ee = dd + n, *e2p = ee + n;
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(64) tridiag_twisted(const EigItem *__restrict_
   extern __shared__ double shd[];   // dd, ee, dp, dm (n each)
   __shared__ double red[3];
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, nb = it.nb, j = blockIdx.x;
+  const int n = it.n, nb = it.nb, j = blockIdx.x;
   if (j >= nb) return;
   const int lane = threadIdx.x;
   double *dd = shd, *ee = dd + n, *dp = ee + n, *dm = dp + n;
@@ -545,7 +545,7 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
   extern __shared__ double shd[];
   __shared__ double red[3];
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, nb = it.nb, jm = blockIdx.x;
+  const int n = it.n, nb = it.nb, jm = blockIdx.x;
   if (jm >= nb) return;
   const int lane = threadIdx.x;
   double *dd = shd, *ee = dd + n, *xv = ee + n;
@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
 __global__ void __launch_bounds__(64) tridiag_cluster_gs(const EigItem *__restrict__ items) {
   __shared__ double red[3];
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, nb = it.nb, j0 = blockIdx.x;
+  const int n = it.n, nb = it.nb, j0 = blockIdx.x;
   if (j0 >= nb) return;
   const int lane = threadIdx.x;
   // |T| from the Gershgorin bounds, read straight from d and e
@@ -737,23 +737,31 @@ MVPB_DEV void jacobi_eig(cd (*Gs)[RR_MAX_BANDS + 1], cd (*Vs)[RR_MAX_BANDS + 1],
 //                blocks' Gram partials Y_b^H Z_b, Y_b^H Y_b;
 //    rr_small    G = Y^H C Y, M = Y^H Y; M = L L^H; eigenpairs of
 //                L^-1 G L^-H (cyclic Jacobi, parallel round-robin pairs);
-//                vectors Y L^-H V, lambda ascending, omega = sqrt(max(lambda, 0)).
+//                vectors Y L^-H V, lambda ascending, omega = sqrt(max(lambda, 0));
+//                items with an error estimate (FP32 reduction) also get the
+//                residuals of the refined pairs, a second rr_product pass over
+//                them and rr_estimate.
 // ---------------------------------------------------------------------------
 constexpr int RR_MAXB = RR_MAX_BANDS;
 constexpr int RRP_BC = 24;   // bands per pass of the product kernel
 
+// RES: the residual pass of items with an error estimate (the vectors are the
+// residuals R that rr_small left in the inverse-iteration scratch; only the
+// Gram partials R^H C R, R^H R are kept).
+template <bool RES>
 __global__ void __launch_bounds__(256) rr_product(const EigItem *__restrict__ items) {
   extern __shared__ __align__(16) unsigned char rr_raw[];
   __shared__ cd Ys[64][RRP_BC + 1];
   const EigItem it = items[blockIdx.y];
-  const int n = 2 * it.N, nb = it.nb;
+  if (RES && !it.check) return;
+  const int n = it.n, nb = it.nb;
   const int rb = blockIdx.x, r0 = rb * 64;
   if (r0 >= n) return;
   const size_t ld = (size_t)n;
   cd *Yr = (cd *)rr_raw;       // [64][nb]
   cd *Zr = Yr + 64 * nb;       // [64][nb]
   const int tid = threadIdx.x, r = tid & 63, ks = tid >> 6;
-  const cd *__restrict__ Y = it.Y;
+  const cd *__restrict__ Y = RES ? (const cd *)it.lu : it.Y;
   const cd *__restrict__ Cm = it.Ak;
   const int rows = min(64, n - r0);
   for (int e = tid; e < 64 * nb; e += 256) {
@@ -803,10 +811,11 @@ __global__ void __launch_bounds__(256) rr_product(const EigItem *__restrict__ it
     }
   }
   cd *Z = it.Z;
-  for (int e = tid; e < rows * nb; e += 256) {
-    const int rr = e % rows, b = e / rows;
-    gst(Z, (size_t)b * ld + r0 + rr, Zr[rr * nb + b]);
-  }
+  if (!RES)
+    for (int e = tid; e < rows * nb; e += 256) {
+      const int rr = e % rows, b = e / rows;
+      gst(Z, (size_t)b * ld + r0 + rr, Zr[rr * nb + b]);
+    }
   // Gram partials of this row block: [0] Y^H Z, [1] Y^H Y
   cd *Gp = it.Gp + (size_t)rb * 2 * nb * nb;
   for (int e = tid; e < nb * nb; e += 256) {
@@ -832,7 +841,7 @@ __global__ void __launch_bounds__(256) rr_small(const EigItem *__restrict__ item
   __shared__ int perm[RR_MAXB];
   __shared__ double evs[RR_MAXB];
   const EigItem it = items[blockIdx.x];
-  const int n = 2 * it.N, nb = it.nb;
+  const int n = it.n, nb = it.nb;
   const int tid = threadIdx.x;
   const size_t ld = (size_t)n;
   const int nrb = (n + 63) / 64;
@@ -942,9 +951,28 @@ __global__ void __launch_bounds__(256) rr_small(const EigItem *__restrict__ item
     }
   }
   __syncthreads();
-  // Z = Y P(:, perm)
   const cd *Y = it.Y;
   cd *Z = it.Z;
+  if (it.check) {
+    // residuals of the refined pairs, R(:, b) = (C Y) p_b - theta_b Y p_b
+    // (p_b = column perm[b] of P), into the free inverse-iteration scratch
+    // before Z (= C Y) is overwritten; rr_product and rr_estimate take
+    // them from there
+    cd *Rv = (cd *)it.lu;
+    for (size_t e = tid; e < (size_t)n * nb; e += T) {
+      const int r = (int)(e % n), b = (int)(e / n);
+      const int pbb = perm[b];
+      const double th = evs[pbb];
+      cd acc = mk(0.0, 0.0);
+      for (int a = 0; a < nb; ++a)
+        acc = cfma(gld(Z, (size_t)a * ld + r) - th * gld(Y, (size_t)a * ld + r), Gs[a][pbb], acc);
+      gst(Rv, e, acc);
+    }
+    __syncthreads();
+  } else if (tid == 0) {
+    *it.acc = 0.0;
+  }
+  // Z = Y P(:, perm)
   for (size_t e = tid; e < (size_t)n * nb; e += T) {
     const int r = (int)(e % n), b = (int)(e / n);
     const int pbb = perm[b];
@@ -954,11 +982,50 @@ __global__ void __launch_bounds__(256) rr_small(const EigItem *__restrict__ item
   }
 }
 
-hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st) {
+// Error estimate of the refined bands of an item with check set: with the
+// residual r_b = C z_b - theta_b z_b of the unit Ritz vector z_b and its
+// Rayleigh quotient rho_b = r_b^H C r_b / |r_b|^2, the second-order estimate
+// e_b = |r_b|^2 / (rho_b - theta_b) of theta_b - lambda (the residual is
+// orthogonal to the Ritz space, so rho_b - theta_b is its effective
+// distance to the rest of the spectrum; |r_b| itself if rho_b <= theta_b),
+// as a relative frequency error e_b / (2 theta_b), or e_b / (2 theta_top)
+// below 1e-3 of the top frequency.  *acc = the largest over the bands.
+__global__ void __launch_bounds__(64) rr_estimate(const EigItem *__restrict__ items) {
+  const EigItem &it = items[blockIdx.x];
+  if (!it.check) return;
+  const int n = it.n, nb = it.nb, nrb = (n + 63) / 64;
+  const double top = fmax(it.lam[nb - 1], 0.0);
+  double worst = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 64) {
+    double g = 0.0, m = 0.0;
+    for (int q = 0; q < nrb; ++q) {
+      const cd *P = it.Gp + (size_t)q * 2 * nb * nb;
+      g += gld(P, (size_t)b * nb + b).re;
+      m += gld(P, (size_t)nb * nb + (size_t)b * nb + b).re;
+    }
+    const double th = it.lam[b];
+    double e = 0.0;
+    if (m > 0.0) {
+      const double rho = g / m;
+      e = rho > th ? m / (rho - th) : sqrt(m);
+    }
+    const double den = 2.0 * (th >= 1e-6 * top ? th : top);
+    const double est = (e == 0.0) ? 0.0 : (den > 0.0 ? e / den : INFINITY);
+    worst = fmax(worst, est);
+  }
+  for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
+  if (threadIdx.x == 0) *it.acc = worst;
+}
+
+hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, int nb, bool check, hipStream_t st) {
   ProfScope ps(K_RR, st);
   const int nrb = (n_max + 63) / 64;
-  hipLaunchKernelGGL(rr_product, dim3(nrb, n_items), dim3(256), sizeof(cd) * 2 * 64 * nb, st, items);
+  hipLaunchKernelGGL(rr_product<false>, dim3(nrb, n_items), dim3(256), sizeof(cd) * 2 * 64 * nb, st, items);
   hipLaunchKernelGGL(rr_small, dim3(n_items), dim3(256), 0, st, items);
+  if (check) {
+    hipLaunchKernelGGL(rr_product<true>, dim3(nrb, n_items), dim3(256), sizeof(cd) * 2 * 64 * nb, st, items);
+    hipLaunchKernelGGL(rr_estimate, dim3(n_items), dim3(64), 0, st, items);
+  }
   return hipGetLastError();
 }
 
@@ -976,7 +1043,10 @@ hipError_t init_kernel_attributes() {
     e = hipFuncSetAttribute((const void *)tridiag_invit<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(sizeof(double) * 3 * MAX_N));
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)rr_product, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void *)rr_product<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(cd) * 2 * 64 * RR_MAX_BANDS));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)rr_product<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(sizeof(cd) * 2 * 64 * RR_MAX_BANDS));
   if (e != hipSuccess) return e;
   return init_band_attributes();

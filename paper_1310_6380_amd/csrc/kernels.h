@@ -37,9 +37,12 @@ constexpr int RR_MAX_BANDS = 64;
 // path, complex float on the FP32 one.
 struct EigItem {
   // operator formation
-  const cd *coef;   // 15 coefficient matrices, N x N each (plan-owned)
-  double kap1, kap2;
-  int N;            // plane waves; the operator has order n = 2N
+  const cd *coef;   // coefficient matrices of C(k) (plan-owned): dim 0: 15 of N x N (isotropic
+                    // planar layout); dim 2, 3: (dim+1)(dim+2)/2 of n x n (general layout)
+  double kap1, kap2, kap3;  // Cartesian Bloch vector kappa = 2 pi T Q
+  int N;            // plane waves
+  int n;            // order of the operator (2N planar, 3N spatial)
+  int dim;          // coefficient layout, see coef
   int nb;           // bands wanted
   int slot;         // row of this item's frequencies in the output
   // stage 1: dense -> band
@@ -69,12 +72,15 @@ struct EigItem {
   cd *Lr;           // nb x nb Cholesky factor of Y^H Y
   double *lam;      // nb refined eigenvalues (lambda = omega^2)
   double *omega;    // nb output frequencies (device)
+  double *acc;      // 1: largest a posteriori relative frequency error estimate of the refined bands
+  int check;        // 1: compute that estimate (FP32 reduction), 0: acc = 0
 };
 
 // assembly.hip
 hipError_t launch_structure_factors_f64(const int32_t *phase, const double *wtab, int nx, int ny, int M1,
                                         int M2, double area, cd *X, cd *F, hipStream_t st);
-// Matrix-core variant: prec 0 = FP64, 1 = FP32, 2 = BF16 inputs (FP32 accumulate).
+// Matrix-core variant: prec 0 = FP64, 1 = FP32, 2 = BF16 inputs (FP32 accumulate),
+// 3 = split BF16 (hi + lo inputs, three BF16 products, FP32 accumulate).
 // X: scratch of 8 * nx * (4 M2 + 1) doubles.
 hipError_t launch_structure_factors_mfma(int prec, const int32_t *phase, const double *wtab, int nx, int ny, int M1,
                                          int M2, double area, double *X, cd *F, hipStream_t st);
@@ -98,6 +104,20 @@ hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T0, c
                                    hipStream_t st);
 hipError_t launch_combine(const cd *Xp, int N, double s, cd *coef, hipStream_t st);
 hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, bool fp32, hipStream_t st);
+
+// general.hip: general compliance and voxel cells (full Phi).
+// Weight fields [nf][4M1+1][4M2+1][4M3+1] of a pixel (nz = 1, M3 = 0) or
+// voxel cell; X1: nf nx ny (4M3+1), X2: nf nx (4M2+1)(4M3+1) complex scratch.
+hipError_t launch_structure_factors_general(const int32_t *phase, const double *gw, int nf, int nx, int ny, int nz,
+                                            int M1, int M2, int M3, double vol, cd *X1, cd *X2, cd *F,
+                                            hipStream_t st);
+// out (nblk N square, column-major): block (s, t) = Toeplitz matrix of field fmap[s nblk + t].
+hipError_t launch_toeplitz_blocks(const cd *F, int M1, int M2, int M3, int N, int nblk, const int *fmap, cd *out,
+                                  hipStream_t st);
+hipError_t launch_form_operator_general(const EigItem *items, int n_items, int n_max, bool fp32, hipStream_t st);
+// X = H* U per point (U [n_k][nb][d N], X [n_k][nb][n_s N]); Q [n_k][d] device; T row-major d x d.
+hipError_t launch_stress_rhs_general(const cd *U, const double *Q, int n_k, int nb, int d, int M1, int M2, int M3,
+                                     const double *T, double vol, cd *X, hipStream_t st);
 
 // dense.hip
 // Cholesky (lower, in place) and explicit inverse of the factor for `count`
@@ -145,6 +165,6 @@ long long refl_total(int n);   // number of stage-2 reflectors of an item of ord
 // eigen.hip
 hipError_t init_kernel_attributes();  // once per device, before the first launch
 hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st);
-hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st);
+hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, int nb, bool check, hipStream_t st);
 
 }  // namespace mvpb

@@ -27,14 +27,18 @@ E_NOT_PD = -2
 E_NOMEM = -3
 E_DEVICE = -4
 E_UNSUPPORTED = -5
+E_ACCURACY = -6
 
 PROP_ISO_E_NU_RHO = 0
+PROP_VOIGT_D_RHO = 1
 
 PREC_FP64 = 0
 PREC_SF_FP32 = 1
 PREC_SF_BF16 = 2
+PREC_SF_BF16X3 = 3
 PREC_EIG_FP32_RR64 = 4
 PREC_SF_PLAIN64 = 8
+PREC_GENERAL = 16
 
 F_DEVICE_PTRS = 1
 F_ASYNC = 2
@@ -47,7 +51,8 @@ EXPORTS = [
     "mvpb_sur_create", "mvpb_sur_destroy", "mvpb_sur_n_params", "mvpb_sur_get_params", "mvpb_sur_set_params",
     "mvpb_sur_infer", "mvpb_sur_gradients", "mvpb_sur_train_step", "mvpb_copy_device",
     "mvpb_ctx_profile_mask", "mvpb_cell_create_polygons", "mvpb_stress_modes", "mvpb_kpath",
-    "mvpb_sur_save", "mvpb_sur_load", "mvpb_structure_factors_noalloc",
+    "mvpb_sur_save", "mvpb_sur_load", "mvpb_structure_factors_noalloc", "mvpb_ctx_set_accuracy",
+    "mvpb_ctx_last_accuracy", "mvpb_cell_create_voxels", "mvpb_plan_create3", "mvpb_structure_factors_general",
 ]
 N_KERNELS = 15
 
@@ -80,6 +85,10 @@ def load(path: str = LIB_PATH):
     lib.mvpb_cell_create_polygons.argtypes = [P, D, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                               D, I, I, D, ctypes.POINTER(P)]
     lib.mvpb_cell_destroy.argtypes = [P]
+    lib.mvpb_cell_create_voxels.argtypes = [P, D, I, I, I, ctypes.POINTER(ctypes.c_int32), I, I, D,
+                                            ctypes.POINTER(P)]
+    lib.mvpb_plan_create3.argtypes = [P, I, I, I, I, ctypes.POINTER(P)]
+    lib.mvpb_structure_factors_general.argtypes = [P, I, I, I, D]
     lib.mvpb_stress_modes.argtypes = [P, I, D, I, D, D, ctypes.c_uint]
     lib.mvpb_plan_create.argtypes = [P, I, I, I, ctypes.POINTER(P)]
     lib.mvpb_plan_dofs.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
@@ -106,6 +115,8 @@ def load(path: str = LIB_PATH):
     lib.mvpb_sur_load.argtypes = [P, ctypes.c_char_p, I, ctypes.POINTER(P)]
     lib.mvpb_copy_device.argtypes = [P, P, P, ctypes.c_size_t]
     lib.mvpb_ctx_profile.argtypes = [P, I]
+    lib.mvpb_ctx_set_accuracy.argtypes = [P, ctypes.c_double]
+    lib.mvpb_ctx_last_accuracy.argtypes = [P, D]
     lib.mvpb_ctx_profile_mask.argtypes = [P, ctypes.c_ulonglong]
     lib.mvpb_ctx_profile_read.argtypes = [P, I, D, ctypes.POINTER(ctypes.c_longlong),
                                           ctypes.POINTER(ctypes.c_char_p)]
@@ -235,6 +246,17 @@ class Context:
     def profile(self, enable: bool = True):
         _check(load().mvpb_ctx_profile(self.h, 1 if enable else 0))
 
+    def set_accuracy(self, tol: float):
+        """Bar on the estimated relative frequency error of solves with the
+        FP32 reduction (0 turns the check off)."""
+        _check(load().mvpb_ctx_set_accuracy(self.h, float(tol)))
+
+    def last_accuracy(self) -> float:
+        """Largest error estimate of the refined bands of the last synchronous solve."""
+        v = ctypes.c_double()
+        _check(load().mvpb_ctx_last_accuracy(self.h, ctypes.byref(v)))
+        return v.value
+
     def profile_only(self, names):
         """Time only the named kernel families (empty: stop timing)."""
         ids = [self.kernel_names().index(n) for n in names]
@@ -266,6 +288,10 @@ class Context:
     def cell(self, phase, props, lattice=None):
         return Cell(self, phase, props, lattice)
 
+    def cell_voxels(self, phase, props, lattice=None):
+        """A voxel cell (three-dimensional); phase [nx, ny, nz]."""
+        return Cell.from_voxels(self, phase, props, lattice)
+
     def cell_polygons(self, polygons, poly_phase, props, lattice):
         """A polygon cell: ``polygons`` a list of [n_i, 2] vertex arrays
         (Cartesian; counter-clockwise adds, clockwise subtracts)."""
@@ -283,6 +309,7 @@ class Context:
         for i in range(n):
             p = Plan.__new__(Plan)
             p.ctx = self
+            p.qdim = 2
             p.h = ctypes.c_void_p(out[i])
             nu, ns = ctypes.c_int(), ctypes.c_int()
             _check(load().mvpb_plan_dofs(p.h, ctypes.byref(nu), ctypes.byref(ns)))
@@ -293,7 +320,8 @@ class Context:
     def solve_batch(self, plans, Qs, n_bands: int) -> list:
         lib = load()
         n = len(plans)
-        Qs = [np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1, 2)) for q in Qs]
+        Qs = [np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1, getattr(p, "qdim", 2)))
+              for q, p in zip(Qs, plans)]
         outs = [np.zeros((q.shape[0], n_bands)) for q in Qs]
         ph = (ctypes.c_void_p * n)(*[p.h for p in plans])
         nk = (ctypes.c_int * n)(*[q.shape[0] for q in Qs])
@@ -303,20 +331,55 @@ class Context:
         return outs
 
 
+def _prop_kind(props, dim: int):
+    """Rows of (E, nu, rho) -> ISO; rows of the engineering-Voigt compliance
+    upper triangle plus rho (7 planar, 22 spatial values) -> VOIGT_D_RHO."""
+    pr = np.asarray(props, dtype=np.float64)
+    width = pr.shape[-1] if pr.ndim == 2 else 3
+    voigt = 7 if dim == 2 else 22
+    if width == 3:
+        return PROP_ISO_E_NU_RHO, np.ascontiguousarray(pr.reshape(-1, 3))
+    if width == voigt:
+        return PROP_VOIGT_D_RHO, np.ascontiguousarray(pr.reshape(-1, voigt))
+    raise ValueError(f"property rows must have 3 (E, nu, rho) or {voigt} (Voigt compliance, rho) values")
+
+
 class Cell:
-    """A pixel unit cell: phase map [nx, ny] (i along h1) and (E, nu, rho) rows."""
+    """A pixel unit cell: phase map [nx, ny] (i along h1) and per-phase rows of
+    (E, nu, rho) or of the engineering-Voigt compliance (d11, d12, d13, d22,
+    d23, d33) and rho."""
 
     def __init__(self, ctx: Context, phase, props, lattice=None):
         lib = load()
         self.ctx = ctx
+        self.dim = 2
         ph = np.ascontiguousarray(np.asarray(phase, dtype=np.int32))
-        pr = np.ascontiguousarray(np.asarray(props, dtype=np.float64).reshape(-1, 3))
+        kind, pr = _prop_kind(props, 2)
         lat = np.ascontiguousarray(np.asarray(lattice if lattice is not None else np.eye(2), dtype=np.float64).reshape(4))
         h = ctypes.c_void_p()
         _check(lib.mvpb_cell_create_pixels(ctx.h, _dptr(lat), ph.shape[0], ph.shape[1],
                                            ph.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), pr.shape[0],
-                                           PROP_ISO_E_NU_RHO, _dptr(pr), ctypes.byref(h)))
+                                           kind, _dptr(pr), ctypes.byref(h)))
         self.h = h
+
+    @classmethod
+    def from_voxels(cls, ctx: Context, phase, props, lattice=None):
+        """A voxel cell: phase map [nx, ny, nz] (i along h1, k along h3), rows
+        of (E, nu, rho) or of the 21 Voigt compliances and rho."""
+        lib = load()
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.h = None
+        self.dim = 3
+        ph = np.ascontiguousarray(np.asarray(phase, dtype=np.int32))
+        kind, pr = _prop_kind(props, 3)
+        lat = np.ascontiguousarray(np.asarray(lattice if lattice is not None else np.eye(3), dtype=np.float64).reshape(9))
+        h = ctypes.c_void_p()
+        _check(lib.mvpb_cell_create_voxels(ctx.h, _dptr(lat), ph.shape[0], ph.shape[1], ph.shape[2],
+                                           ph.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), pr.shape[0], kind,
+                                           _dptr(pr), ctypes.byref(h)))
+        self.h = h
+        return self
 
     @classmethod
     def from_polygons(cls, ctx: Context, polygons, poly_phase, props, lattice):
@@ -324,6 +387,7 @@ class Cell:
         self = cls.__new__(cls)
         self.ctx = ctx
         self.h = None
+        self.dim = 2
         verts = [np.asarray(v, dtype=np.float64).reshape(-1, 2) for v in polygons]
         off = np.zeros(len(verts) + 1, dtype=np.int32)
         off[1:] = np.cumsum([v.shape[0] for v in verts])
@@ -366,19 +430,36 @@ class Cell:
         _check(load().mvpb_structure_factors_noalloc(self.h, M1, M2, precision, out.ptr, flags))
         return out
 
-    def plan(self, M1: int, M2: int = None, precision: int = PREC_FP64):
-        return Plan(self, M1, M1 if M2 is None else M2, precision)
+    def structure_factors_general(self, M1: int, M2: int, M3: int = 0) -> np.ndarray:
+        """Weight fields of the general layout [nf, 4M1+1, 4M2+1, 4M3+1] (Voigt
+        compliance upper triangle, then rho)."""
+        nf = 7 if self.dim == 2 else 22
+        F = np.zeros((nf, 4 * M1 + 1, 4 * M2 + 1, 4 * M3 + 1), dtype=np.complex128)
+        _check(load().mvpb_structure_factors_general(self.h, M1, M2, M3,
+                                                     F.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return F
+
+    def plan(self, M1: int, M2: int = None, precision: int = PREC_FP64, M3: int = None):
+        """Plan at cutoff (M1, M2[, M3]); a voxel cell takes M3 (default: M1)."""
+        M2 = M1 if M2 is None else M2
+        if self.dim == 3:
+            return Plan(self, M1, M2, precision, M1 if M3 is None else M3)
+        return Plan(self, M1, M2, precision)
 
 
 class Plan:
     """k-independent part of the method for one cell and cutoff."""
 
-    def __init__(self, cell: Cell, M1: int, M2: int, precision: int = PREC_FP64):
+    def __init__(self, cell: Cell, M1: int, M2: int, precision: int = PREC_FP64, M3: int = None):
         lib = load()
         self.ctx = cell.ctx
         h = ctypes.c_void_p()
-        _check(lib.mvpb_plan_create(cell.h, M1, M2, precision, ctypes.byref(h)))
+        if M3 is None:
+            _check(lib.mvpb_plan_create(cell.h, M1, M2, precision, ctypes.byref(h)))
+        else:
+            _check(lib.mvpb_plan_create3(cell.h, M1, M2, M3, precision, ctypes.byref(h)))
         self.h = h
+        self.qdim = getattr(cell, "dim", 2)
         nu, ns = ctypes.c_int(), ctypes.c_int()
         _check(lib.mvpb_plan_dofs(h, ctypes.byref(nu), ctypes.byref(ns)))
         self.n_u, self.n_s = nu.value, ns.value
@@ -395,9 +476,9 @@ class Plan:
             pass
 
     def solve(self, Q, n_bands: int, vectors: bool = False):
-        """Frequencies [n_k, n_bands] (rad/s) and optionally U [n_k, n_bands, 2N]."""
+        """Frequencies [n_k, n_bands] (rad/s) and optionally U [n_k, n_bands, n_u]."""
         lib = load()
-        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, 2))
+        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, self.qdim))
         om = np.zeros((Q.shape[0], n_bands))
         U = np.zeros((Q.shape[0], n_bands, self.n_u), dtype=np.complex128) if vectors else None
         _check(lib.mvpb_solve(self.h, Q.shape[0], _dptr(Q), n_bands, ctypes.c_void_p(om.ctypes.data),
@@ -405,14 +486,14 @@ class Plan:
         return (om, U) if vectors else om
 
     def stress(self, Q, U):
-        """Stress modes S = -Phi^-1 H* U [n_k, n_bands, 3N] of displacement modes
-        U [n_k, n_bands, 2N] (as returned by solve(..., vectors=True))."""
+        """Stress modes S = -Phi^-1 H* U [n_k, n_bands, n_s] of displacement modes
+        U [n_k, n_bands, n_u] (as returned by solve(..., vectors=True))."""
         lib = load()
-        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, 2))
+        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, self.qdim))
         U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
         nk, nb = U.shape[0], U.shape[1]
         if U.shape[2] != self.n_u or nk != Q.shape[0]:
-            raise ValueError("U must be [n_k, n_bands, 2N] for the Q list")
+            raise ValueError("U must be [n_k, n_bands, n_u] for the Q list")
         S = np.zeros((nk, nb, self.n_s), dtype=np.complex128)
         _check(lib.mvpb_stress_modes(self.h, nk, _dptr(Q), nb, U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0))
@@ -421,7 +502,7 @@ class Plan:
     def solve_device(self, Q, n_bands: int, omega_ptr: int, flags: int = F_DEVICE_PTRS):
         """Write frequencies to device memory at omega_ptr (e.g. DeviceBuffer.value)."""
         lib = load()
-        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, 2))
+        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, self.qdim))
         _check(lib.mvpb_solve(self.h, Q.shape[0], _dptr(Q), n_bands, ctypes.c_void_p(omega_ptr), None,
                               flags | F_DEVICE_PTRS))
 

@@ -19,7 +19,8 @@ __all__ = [
     "inclusion_phase_map", "grf_phase_map", "layered_cell", "kpath_gxmg",
     "config0", "config1", "config2", "config3", "config4_cells", "workload",
     "INCLUSION_PROPS", "MATRIX_PROPS", "PolygonCell", "iso_from_c11_c44", "hex_lattice",
-    "hex_cylinder_cell", "hex_steel_epoxy", "kpath_xgjx", "hex_graded_1132",
+    "hex_cylinder_cell", "hex_steel_epoxy", "kpath_xgjx", "hex_graded_1132", "random_voigt_props",
+    "voigt_rows_to_matrices",
 ]
 
 SQUARE = np.array([[1.0, 0.0], [0.0, 1.0]])
@@ -76,6 +77,37 @@ def random_iso_props(n: int, rng: np.random.Generator) -> np.ndarray:
     nu = rng.uniform(0.2, 0.4, n)
     rho = np.exp(rng.uniform(np.log(1000.0), np.log(8000.0), n))
     return np.stack([E, nu, rho], axis=1)
+
+
+def random_voigt_props(n: int, rng: np.random.Generator, dim: int = 2) -> np.ndarray:
+    """Rows of a random symmetric positive-definite engineering-Voigt
+    compliance matrix (stress order 11, 22, 12 in the plane; 11, 22, 33, 23,
+    13, 12 in space) with every normal-shear coupling non-zero, scaled like
+    a 10-300 GPa solid, as its upper triangle row by row, then rho
+    log-uniform in [1000, 8000] kg/m^3: 7 values per row in the plane, 22 in
+    space."""
+    ns = 3 if dim == 2 else 6
+    iu = np.triu_indices(ns)
+    rows = []
+    for _ in range(n):
+        B = rng.normal(size=(ns, ns))
+        W = (B @ B.T + ns * np.eye(ns)) * 10.0 ** rng.uniform(-11.5, -10.5)
+        rho = np.exp(rng.uniform(np.log(1000.0), np.log(8000.0)))
+        rows.append(np.concatenate([W[iu], [rho]]))
+    return np.array(rows)
+
+
+def voigt_rows_to_matrices(rows: np.ndarray, dim: int = 2):
+    """Per-phase symmetric compliance matrices and densities from rows in the
+    layout of ``random_voigt_props``."""
+    ns = 3 if dim == 2 else 6
+    iu = np.triu_indices(ns)
+    rows = np.asarray(rows, dtype=np.float64)
+    W = np.zeros((rows.shape[0], ns, ns))
+    for p, r in enumerate(rows):
+        W[p][iu] = r[:-1]
+        W[p] = W[p] + np.triu(W[p], 1).T
+    return W, rows[:, -1].copy()
 
 
 def voronoi_phase_map(nx: int, ny: int, sites: np.ndarray) -> np.ndarray:
