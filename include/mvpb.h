@@ -231,6 +231,28 @@ int mvpb_solve(mvpb_plan plan, int n_k, const double *Q, int n_bands, double *om
 int mvpb_stress_modes(mvpb_plan plan, int n_k, const double *Q, int n_bands, const double *U,
                       double *S, unsigned flags);
 
+/* Sensitivities of the eigenvalues lambda = omega^2 to the material of every
+ * pixel or voxel, for gradient-based band-structure design (Sec. 1 and
+ * Sec. 6 motivate optimisation).  Differentiating eq. (eigenvalueproblem)
+ * (A U = lambda Omega U, A = H Phi^-1 H*, Sec. 3) at a simple eigenvalue
+ * with U^H Omega U = 1 gives d lambda = -S^H dPhi S - lambda U^H dOmega U,
+ * S = -Phi^-1 H* U.  The design variables of element p are its weight fields
+ * w_f: the engineering-Voigt compliance entries (the Phi weights of Sec. 4.1
+ * eq. (ep); upper triangle row by row, a shear-normal entry w_st moving
+ * both blocks (s, t) and (t, s)) and, last, its density (eq. (eo)):
+ * 7 fields for planar cells, 22 for voxel cells.
+ * Q, n_bands as for mvpb_solve; omega [n_k][n_bands] and U
+ * [n_k][n_bands][n_u] as mvpb_solve returned them (U normalised to
+ * U^H Omega U = 1).  G: space for n_k*n_bands*nf*cells doubles,
+ * G[((t*n_bands + b)*nf + f)*cells + (i*ny + j)*nz + k] = d lambda_b(k_t) /
+ * d w_f(i, j, k) (nz = 1 for pixel cells).  At a degenerate eigenvalue only
+ * the sum over the degenerate bands is defined.  Pixel and voxel cells
+ * only (MVPB_E_UNSUPPORTED for polygon cells).  Host pointers unless
+ * MVPB_F_DEVICE_PTRS (then omega, U and G are device pointers; Q stays on
+ * the host). */
+int mvpb_band_sensitivities(mvpb_plan plan, int n_k, const double *Q, int n_bands, const double *omega,
+                            const double *U, double *G, unsigned flags);
+
 /* Many plans at once: all (plan, k) items in one batched launch sequence
  * (captured in a HIP graph and replayed).  n_k[p] points for plan p taken
  * from Q[p] (host pointers), results to omega[p][t*n_bands + b] (host

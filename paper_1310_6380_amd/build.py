@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmvpb.so")
-SOURCES = ["api.hip", "assembly.hip", "band.hip", "dense.hip", "eigen.hip", "general.hip", "surrogate.hip"]
+SOURCES = ["api.hip", "assembly.hip", "band.hip", "dense.hip", "eigen.hip", "general.hip", "sensitivity.hip", "surrogate.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

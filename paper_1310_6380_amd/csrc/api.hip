@@ -253,6 +253,7 @@ struct mvpb_plan_s {
   int M3 = 0;
   double T3[9] = {}; // A^-1 row-major, qdim x qdim packed
   DevBuf linvPhi;    // general layout: L_Phi^-1 (nsig x nsig)
+  int gx = 0, gy = 0, gz = 0;   // pixel / voxel grid of the cell (0: polygon cell)
 };
 
 namespace mvpb {
@@ -934,6 +935,11 @@ static int build_plan_group(mvpb_ctx ctx, const mvpb_cell *cells, int g, int M1,
     pl->N = N;
     pl->n = 2 * N;
     pl->nsig = 3 * N;
+    if (!cells[c]->polygons) {
+      pl->gx = cells[c]->nx;
+      pl->gy = cells[c]->ny;
+      pl->gz = 1;
+    }
     pl->prec = precision;
     memcpy(pl->T, cells[c]->T, sizeof pl->T);
     memcpy(pl->T3, cells[c]->T, sizeof pl->T);
@@ -1126,6 +1132,9 @@ static int build_plan_general(mvpb_cell c, int M1, int M2, int M3, int precision
   pl->nsig = nsig;
   pl->qdim = d;
   pl->area = c->area;
+  pl->gx = c->nx;
+  pl->gy = c->ny;
+  pl->gz = c->nz;
   memcpy(pl->T, c->T, sizeof pl->T);
   memcpy(pl->T3, c->T3, sizeof pl->T3);
   ctx->children++;
@@ -1641,6 +1650,62 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
 }
 
 static bool q_ok(const double *Q, int count);
+
+extern "C" int mvpb_stress_modes(mvpb_plan p, int n_k, const double *Q, int n_bands, const double *U, double *S,
+                                 unsigned flags);
+
+extern "C" int mvpb_band_sensitivities(mvpb_plan p, int n_k, const double *Q, int n_bands, const double *omega,
+                                       const double *U, double *G, unsigned flags) {
+  if (!p || !Q || !omega || !U || !G) return set_err(MVPB_E_INVALID, "NULL argument");
+  if (n_k < 0) return set_err(MVPB_E_INVALID, "n_k must be non-negative");
+  if (n_k == 0) return MVPB_OK;
+  if (n_bands < 1 || n_bands > p->n) return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, n_u]", n_bands);
+  if (!q_ok(Q, p->qdim * n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
+  if (p->gx <= 0) return set_err(MVPB_E_UNSUPPORTED, "sensitivities need a pixel or voxel cell");
+  mvpb_ctx ctx = p->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ProfBind pb(ctx);
+  hipStream_t st = ctx->stream;
+  const bool dev = flags & MVPB_F_DEVICE_PTRS;
+  const int d = p->dim == 0 ? 2 : p->dim, ns = d == 2 ? 3 : 6, nf = ns * (ns + 1) / 2 + 1;
+  const int n = p->n, nsig = p->nsig;
+  const size_t items = (size_t)n_k * n_bands, cells = (size_t)p->gx * p->gy * p->gz;
+  const size_t q1 = 4 * p->M1 + 1, q2 = 4 * p->M2 + 1, q3 = 4 * p->M3 + 1;
+  DevBuf ud(&ctx->pool), od(&ctx->pool), Sd(&ctx->pool), Cw(&ctx->pool), Y1(&ctx->pool), Y2(&ctx->pool),
+      Gd(&ctx->pool);
+  const cd *u = (const cd *)U;
+  const double *om = omega;
+  if (!dev) {
+    HIP_TRY(ud.alloc(sizeof(cd) * items * n));
+    HIP_TRY(hipMemcpyAsync(ud.p, U, sizeof(cd) * items * n, hipMemcpyHostToDevice, st));
+    u = ud.as<cd>();
+    HIP_TRY(od.alloc(sizeof(double) * items));
+    HIP_TRY(hipMemcpyAsync(od.p, omega, sizeof(double) * items, hipMemcpyHostToDevice, st));
+    om = od.as<double>();
+  }
+  HIP_TRY(Sd.alloc(sizeof(cd) * items * nsig));
+  int rc = mvpb_stress_modes(p, n_k, Q, n_bands, (const double *)u, Sd.as<double>(),
+                             MVPB_F_DEVICE_PTRS | MVPB_F_ASYNC);
+  if (rc) return rc;
+  // chunks of items whose correlation and pass buffers stay within 2 GiB
+  const size_t per = sizeof(cd) * nf * (q1 * q2 * q3 + p->gx * q2 * q3 + p->gx * p->gy * q3) +
+                     (dev ? 0 : sizeof(double) * nf * cells);
+  const size_t chunk = std::max<size_t>(1, std::min(items, ((size_t)2 << 30) / per));
+  HIP_TRY(Cw.alloc(sizeof(cd) * chunk * nf * q1 * q2 * q3));
+  HIP_TRY(Y1.alloc(sizeof(cd) * chunk * nf * p->gx * q2 * q3));
+  HIP_TRY(Y2.alloc(sizeof(cd) * chunk * nf * p->gx * p->gy * q3));
+  if (!dev) HIP_TRY(Gd.alloc(sizeof(double) * chunk * nf * cells));
+  for (size_t i0 = 0; i0 < items; i0 += chunk) {
+    const size_t cnt = std::min(chunk, items - i0);
+    double *g = dev ? G + i0 * nf * cells : Gd.as<double>();
+    HIP_TRY(launch_sensitivities(u + i0 * n, Sd.as<cd>() + i0 * nsig, om + i0, (int)cnt, d, p->M1, p->M2, p->M3,
+                                 p->gx, p->gy, p->gz, p->area, Cw.as<cd>(), Y1.as<cd>(), Y2.as<cd>(), g, st));
+    if (!dev)
+      HIP_TRY(hipMemcpyAsync(G + i0 * nf * cells, g, sizeof(double) * cnt * nf * cells, hipMemcpyDeviceToHost, st));
+  }
+  if (!dev || !(flags & MVPB_F_ASYNC)) HIP_TRY(hipStreamSynchronize(st));
+  return MVPB_OK;
+}
 
 extern "C" int mvpb_stress_modes(mvpb_plan p, int n_k, const double *Q, int n_bands, const double *U, double *S,
                                  unsigned flags) {

@@ -119,6 +119,14 @@ hipError_t launch_form_operator_general(const EigItem *items, int n_items, int n
 hipError_t launch_stress_rhs_general(const cd *U, const double *Q, int n_k, int nb, int d, int M1, int M2, int M3,
                                      const double *T, double vol, cd *X, hipStream_t st);
 
+// sensitivity.hip: d lambda / d w_f of every pixel / voxel for n_items (point,
+// band) items: U [items][d N], S [items][n_s N], omega [items] (device);
+// scratch Cw: items nf (4M1+1)(4M2+1)(4M3+1), Y1: items nf nx (4M2+1)(4M3+1),
+// Y2: items nf nx ny (4M3+1) complex; G [items][nf][nx][ny][nz].
+hipError_t launch_sensitivities(const cd *U, const cd *S, const double *omega, int n_items, int d, int M1, int M2,
+                                int M3, int nx, int ny, int nz, double vol, cd *Cw, cd *Y1, cd *Y2, double *G,
+                                hipStream_t st);
+
 // dense.hip
 // Cholesky (lower, in place) and explicit inverse of the factor for `count`
 // matrices A[b] (N x N, column-major); Linv[b] receives L^-1 (lower, the

@@ -53,6 +53,7 @@ EXPORTS = [
     "mvpb_ctx_profile_mask", "mvpb_cell_create_polygons", "mvpb_stress_modes", "mvpb_kpath",
     "mvpb_sur_save", "mvpb_sur_load", "mvpb_structure_factors_noalloc", "mvpb_ctx_set_accuracy",
     "mvpb_ctx_last_accuracy", "mvpb_cell_create_voxels", "mvpb_plan_create3", "mvpb_structure_factors_general",
+    "mvpb_band_sensitivities",
 ]
 N_KERNELS = 15
 
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
                                             ctypes.POINTER(P)]
     lib.mvpb_plan_create3.argtypes = [P, I, I, I, I, ctypes.POINTER(P)]
     lib.mvpb_structure_factors_general.argtypes = [P, I, I, I, D]
+    lib.mvpb_band_sensitivities.argtypes = [P, I, D, I, P, P, P, ctypes.c_uint]
     lib.mvpb_stress_modes.argtypes = [P, I, D, I, D, D, ctypes.c_uint]
     lib.mvpb_plan_create.argtypes = [P, I, I, I, ctypes.POINTER(P)]
     lib.mvpb_plan_dofs.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
@@ -498,6 +500,22 @@ class Plan:
         _check(lib.mvpb_stress_modes(self.h, nk, _dptr(Q), nb, U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0))
         return S
+
+    def sensitivities(self, Q, omega, U, grid_shape):
+        """d lambda / d w_f of every pixel / voxel: [n_k, n_bands, nf, *grid_shape]
+        from the (omega, U) that solve(..., vectors=True) returned."""
+        lib = load()
+        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, self.qdim))
+        om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+        nk, nb = om.shape
+        if U.shape != (nk, nb, self.n_u) or Q.shape[0] != nk:
+            raise ValueError("omega [n_k, n_bands] and U [n_k, n_bands, n_u] must match the Q list")
+        nf = 7 if self.qdim == 2 else 22
+        G = np.zeros((nk, nb, nf) + tuple(grid_shape))
+        _check(lib.mvpb_band_sensitivities(self.h, nk, _dptr(Q), nb, ctypes.c_void_p(om.ctypes.data),
+                                           ctypes.c_void_p(U.ctypes.data), ctypes.c_void_p(G.ctypes.data), 0))
+        return G
 
     def solve_device(self, Q, n_bands: int, omega_ptr: int, flags: int = F_DEVICE_PTRS):
         """Write frequencies to device memory at omega_ptr (e.g. DeviceBuffer.value)."""
