@@ -112,25 +112,60 @@ def measured_traffic(kernel: str):
     return None
 
 
-def cpu_baseline(cell, M, Q, nb, omega_gpu, n_sample):
-    from oracle import mixed_oracle as mo
-    from oracle.compare import band_error
+def cpu_info():
+    """CPU model, usable cores and the BLAS the oracle's LAPACK calls run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = []
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        for i in threadpool_info():
+            blas.append({"api": i.get("internal_api"), "version": i.get("version"),
+                         "threads": i.get("num_threads"), "library": os.path.basename(i.get("filepath", ""))})
     except Exception:
-        threads = os.cpu_count() or 1
-    idx = np.linspace(0, Q.shape[0] - 1, n_sample).round().astype(int)
-    progress("cpu baseline: oracle on", n_sample, "k-points")
+        pass
+    return {"cpu_model": model, "cores": len(os.sched_getaffinity(0)), "blas": blas}
+
+
+def cpu_baseline(cell, M, Q, nb, omega_gpu, n_single=6):
+    """The oracle on every k-point of the headline cell with all host cores
+    (its LAPACK threads), and on n_single of them with one thread."""
+    from oracle import mixed_oracle as mo
+    from oracle.compare import band_error
+    info = cpu_info()
+    threads = max([b["threads"] or 1 for b in info["blas"]] or [1])
+    progress("cpu baseline: oracle on all", Q.shape[0], "k-points,", threads, "threads")
     t0 = time.perf_counter()
-    ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, M, M, Q[idx], nb)
+    ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, M, M, Q, nb)
     dt = time.perf_counter() - t0
-    err = band_error(omega_gpu[idx], ref)
+    err = band_error(omega_gpu, ref)
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        idx = np.linspace(0, Q.shape[0] - 1, n_single).round().astype(int)
+        progress("cpu baseline: oracle on", n_single, "k-points, 1 thread")
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            mo.bands(cell.phase, cell.props, cell.lattice, M, M, Q[idx], nb)
+            d1 = time.perf_counter() - t1
+        single = {"value": n_single / d1, "unit": "solves/s", "threads": 1,
+                  "sample": f"{n_single} of the {Q.shape[0]} k-points (incl. the subdomain integrals), {d1:.1f} s"}
+    except Exception as exc:   # threadpoolctl missing: report the all-core figure only
+        single = {"error": str(exc)}
     return ({
-        "value": n_sample / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-        "sample": f"{n_sample} of the {Q.shape[0]} k-points of the same cell (incl. its subdomain integrals), "
+        "value": Q.shape[0] / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+        "sample": f"all {Q.shape[0]} k-points of the headline cell (incl. its subdomain integrals), "
                   f"NumPy/SciPy LAPACK, {dt:.1f} s",
-    }, err, idx, ref)
+        "cpu_model": info["cpu_model"], "host_cores": info["cores"], "blas": info["blas"],
+        "single_thread": single,
+    }, err, np.arange(Q.shape[0]), ref)
 
 
 def batched_error(cfg, om_batch, n_cells=4, n_k=3):
@@ -200,8 +235,18 @@ def variant_batched(mvpb, ctx, steps, warmup):
 
     dt = run_timed(step, steps, warmup, mvpb, "batched")
     items = len(cells) * Q.shape[0]
+    # one more plan build with every kernel timed: assembly roofline
+    ctx.profile(True)
+    plans = ctx.plans(cells, Ms)
+    mvpb.device_synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    for p in plans:
+        p.close()
+    roof = assembly_roofline(mvpb, ctx, cfg, cells, prof)
     return {"value": items / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt, "items": items,
-            "precision": "fp64"}, out["om"], cfg
+            "precision": "fp64", "assembly_roofline": roof,
+            "plan_build_kernel_ms": {k: v[0] for k, v in prof.items() if v[1]}}, out["om"], cfg
 
 
 def variant_hex_polygons(mvpb, ctx, steps, warmup):
@@ -269,28 +314,40 @@ def variant_stress(mvpb, ctx, dcell, M, Q, nb, steps, warmup):
             "outputs": "omega, U (2N per band), S (3N per band), host"}, out
 
 
-def variant_surrogate(mvpb, ctx, n_train=4096, n_test=256, epochs=30):
+def variant_surrogate(mvpb, ctx, n_train=8192, n_test=1024, epochs=60, label_chunk=512):
     """Binary GRF cells on 32x32 (correlation length 4 px, fill U[0.2,0.8]),
     labels by the batched FP64 solver at 15x15 plane waves, 40 k, 10 bands;
     network trained by the library's kernels (BF16 matrix cores) on the
-    standardised labels; inference timed on batches of 4096 cells.  One
-    "solve" = one cell at one k."""
+    standardised labels (cosine step-size decay); held-out error on cells it
+    has not seen; inference timed on batches of 4096 cells; what it gains:
+    the best verified gap among its 32 top-ranked held-out cells against 32
+    random ones (same number of plain solves), and a screening loop with
+    plain-solve verification and fallback.  One "solve" = one cell at one k."""
     from paper_1310_6380_amd import screening as sc
     from synth import config4_cells
     cells = config4_cells(0, n_train + n_test)
     t0 = time.perf_counter()
-    y = sc.label_cells(ctx, cells)
+    y = sc.label_cells(ctx, cells, chunk=label_chunk)
     t_label = time.perf_counter() - t0
     progress("surrogate labels", cells.shape[0], "cells in", round(t_label, 1), "s")
     norm = sc.Normalizer(y[:n_train])
     net = mvpb.Surrogate(ctx, max_batch=4096, precision=1, seed=0)
     t0 = time.perf_counter()
-    sc.train(net, cells[:n_train], y[:n_train], epochs=epochs, batch=256, lr=1e-3, log=progress, norm=norm)
+    losses = sc.train(net, cells[:n_train], y[:n_train], epochs=epochs, batch=256, lr=2e-3, lr_end=2e-5,
+                      log=progress, norm=norm)
     t_train = time.perf_counter() - t0
     pred = sc.predict(net, cells[n_train:], norm)
     err = sc.relative_errors(pred, y[n_train:])
     ref = y[n_train:].reshape(-1, sc.N_K, sc.N_BANDS)
     rel_top = np.abs(pred.reshape(ref.shape) - ref) / ref[:, :, -1:]
+    # gain at an equal budget of plain solves (32 cells verified each)
+    b, budget = 2, 32
+    tg = sc.band_gap(y[n_train:], b)
+    pick = np.argsort(-sc.band_gap(pred, b))[:budget]
+    rng = np.random.default_rng(0)
+    draws = np.stack([rng.choice(tg.size, budget, replace=False) for _ in range(400)])
+    best_r = tg[draws].max(axis=1)
+    frac = float(np.mean(tg >= tg[pick].max()))
     batch = np.resize(cells[n_train:], (4096, 32, 32))
     dcells = mvpb.DeviceBuffer(batch.size).upload(batch)
     dout = mvpb.DeviceBuffer(4 * 4096 * 400)
@@ -299,33 +356,61 @@ def variant_surrogate(mvpb, ctx, n_train=4096, n_test=256, epochs=30):
         net.infer_device(4096, dcells.value, dout.value)
 
     dt = run_timed(step, 5, 2, mvpb, "surrogate inference")
-    stats = sc.screen(ctx, net, cells[:64], b=2, rounds=2, n_candidates=4096, top_k=16, log=progress, norm=norm)
+    stats = sc.screen(ctx, net, cells[:64], b=b, rounds=2, n_candidates=4096, top_k=16, log=progress, norm=norm)
     net.close()
     return {"value": 4096 * sc.N_K / dt, "unit": "solves/s", "cells_per_s": 4096 / dt,
             "ms_per_batch_4096": 1e3 * dt, "precision": "bf16 matrix cores, fp32 accumulate",
             "held_out_rel_err": {"p50": float(np.median(err)), "p99": float(np.percentile(err, 99)),
                                  "max": float(err.max()), "cells": int(n_test),
+                                 "definition": "per cell, worst relative error over its 400 outputs",
                                  "median_rel_to_top_band": float(np.median(rel_top))},
-            "train": {"cells": n_train, "epochs": epochs, "seconds": t_train},
+            "train": {"cells": n_train, "epochs": epochs, "seconds": t_train, "final_loss": float(losses[-1]),
+                      "cells_per_s": n_train * epochs / t_train},
             "labels": {"cells": int(cells.shape[0]), "solves_per_s": cells.shape[0] * sc.N_K / t_label},
+            "gain_equal_budget": {"band_pair": [b, b + 1], "budget_cells": budget,
+                                  "surrogate_best_gap": float(tg[pick].max()),
+                                  "surrogate_mean_gap": float(tg[pick].mean()),
+                                  "random_best_gap_p50": float(np.median(best_r)),
+                                  "random_best_gap_p90": float(np.percentile(best_r, 90)),
+                                  "random_solves_to_reach_surrogate_best": float(sc.N_K / max(frac, 1e-9))},
             "screening": {"candidates": stats["predicted"], "verified": stats["verified"],
                           "fallback_rate": stats["fallbacks"] / max(1, stats["verified"]),
                           "best_verified_gap_b2_b3": stats["best_gap"],
+                          "rounds": stats["rounds"],
                           "surrogate_s_per_cell": stats["t_surrogate"] / stats["predicted"],
                           "solve_s_per_cell": stats["t_solve"] / stats["verified"]}}
 
 
+def run_median(fn, steps, warmup, mvpb, name=""):
+    """Median of `steps` individually timed steps (device drained around
+    each) after `warmup` untimed ones."""
+    for _ in range(warmup):
+        fn()
+    mvpb.device_synchronize()
+    ts = []
+    for i in range(steps):
+        t0 = time.perf_counter()
+        fn()
+        mvpb.device_synchronize()
+        ts.append(time.perf_counter() - t0)
+    progress(name, "median of", steps, "steps:", round(1e3 * float(np.median(ts)), 2), "ms")
+    return float(np.median(ts))
+
+
 def variant_precision(mvpb, ctx):
     """4096 Voronoi phases on 128x128, 31x31 plane waves (2N = 1922), 60 k,
-    24 bands: FP64, FP32 and BF16 structure factors, and FP32 reduction with
-    FP64 Rayleigh-Ritz.  One step per precision after one warm-up."""
+    24 bands: structure factors in FP64, FP32, BF16 and split BF16, and the
+    FP32 reduction with FP64 Rayleigh-Ritz (alone and with split-BF16 or
+    FP32 structure factors).  3 warm-up steps, median of 5."""
     from synth import config3
     cfg = config3()
     cell, M, Q, nb = cfg["cell"], cfg["M"], cfg["Q"], cfg["n_bands"]
     dcell = ctx.cell(cell.phase, cell.props, cell.lattice)
     res, oms = {}, {}
     for name, prec in (("fp64", mvpb.PREC_FP64), ("sf_fp32", mvpb.PREC_SF_FP32), ("sf_bf16", mvpb.PREC_SF_BF16),
-                       ("sf_fp32_eig_fp32_rr64", mvpb.PREC_SF_FP32 | mvpb.PREC_EIG_FP32_RR64)):
+                       ("sf_bf16x3", mvpb.PREC_SF_BF16X3), ("eig_fp32_rr64", mvpb.PREC_EIG_FP32_RR64),
+                       ("sf_fp32_eig_fp32_rr64", mvpb.PREC_SF_FP32 | mvpb.PREC_EIG_FP32_RR64),
+                       ("sf_bf16x3_eig_fp32_rr64", mvpb.PREC_SF_BF16X3 | mvpb.PREC_EIG_FP32_RR64)):
         out = {}
 
         def step():
@@ -333,10 +418,185 @@ def variant_precision(mvpb, ctx):
             out["om"] = plan.solve(Q, nb)
             plan.close()
 
-        dt = run_timed(step, 1, 1, mvpb, "precision " + name)
-        res[name] = {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt}
+        ctx.set_accuracy(0.0)   # every variant is timed and reported, whatever its estimate
+        try:
+            dt = run_median(step, 5, 3, mvpb, "precision " + name)
+        finally:
+            ctx.set_accuracy(1e-5)
+        res[name] = {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt,
+                     "offered_as_mixed_path": name != "sf_bf16"}
+        if prec & mvpb.PREC_EIG_FP32_RR64:
+            res[name]["estimated_rel_freq_err"] = ctx.last_accuracy()
         oms[name] = out["om"]
     return res, oms, cfg
+
+
+def variant_simple_cell(mvpb, ctx, steps=20, warmup=3):
+    """The simple inclusion cell: circle r = 0.3a on 16x16 pixels (E 70 GPa,
+    nu 0.33, rho 2700 in E 3.5 GPa, nu 0.35, rho 1180), 7x7 plane waves
+    (2N = 98), 30 k on Gamma-X-M-Gamma, 6 bands, FP64; plan build + solve per
+    step, median of 20."""
+    from synth import config0
+    c = config0()
+    cell, M, Q, nb = c["cell"], c["M"], c["Q"], c["n_bands"]
+    dcell = ctx.cell(cell.phase, cell.props, cell.lattice)
+    om_dev = mvpb.DeviceBuffer(8 * Q.shape[0] * nb)
+
+    def step():
+        plan = dcell.plan(M)
+        plan.solve_device(Q, nb, om_dev.value)
+        plan.close()
+
+    dt = run_median(step, steps, warmup, mvpb, "simple cell")
+    om = om_dev.to_numpy(np.float64, (Q.shape[0], nb))
+    return {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt, "precision": "fp64",
+            "two_N": 2 * (2 * M + 1) ** 2, "k_points": int(Q.shape[0]), "n_bands": nb,
+            "timing": "median of %d steps after %d warm-ups" % (steps, warmup)}, om, c
+
+
+def variant_anisotropic(mvpb, ctx, steps=5, warmup=2):
+    """General layout: the 1132-phase Voronoi map of the headline with a
+    random full engineering-Voigt compliance per phase (shear-normal coupling
+    non-zero, seeded), 21x21 plane waves (2N = 882, full 3N x 3N Phi
+    factored), 60 k, 18 bands, FP64."""
+    from synth import config1, random_voigt_props, rng_for
+    c = config1()
+    rows = random_voigt_props(c["cell"].n_phases, rng_for(101, 0))
+    dcell = ctx.cell(c["cell"].phase, rows)
+    M, Q, nb = c["M"], c["Q"], c["n_bands"]
+    out = {}
+
+    def step():
+        plan = dcell.plan(M)
+        out["om"] = plan.solve(Q, nb)
+        plan.close()
+
+    dt = run_median(step, steps, warmup, mvpb, "anisotropic")
+    return {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt, "precision": "fp64",
+            "two_N": 2 * (2 * M + 1) ** 2, "k_points": int(Q.shape[0]), "n_bands": nb}, out["om"], (c, rows)
+
+
+def kpath_cubic(n_k):
+    """n_k points equally spaced in arc length on Gamma-X-M-Gamma-R of a cubic
+    lattice (fractional: X = (1/2,0,0), M = (1/2,1/2,0), R = (1/2,1/2,1/2))."""
+    pts = np.array([[0, 0, 0], [0.5, 0, 0], [0.5, 0.5, 0], [0, 0, 0], [0.5, 0.5, 0.5]], dtype=np.float64)
+    seg = np.linalg.norm(np.diff(pts, axis=0), axis=1)
+    s = np.linspace(0.0, seg.sum(), n_k)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    out = []
+    for t in s:
+        k = min(np.searchsorted(cum, t, side="right") - 1, len(seg) - 1)
+        f = (t - cum[k]) / seg[k]
+        out.append(pts[k] + f * (pts[k + 1] - pts[k]))
+    return np.array(out)
+
+
+def sphere_voxels(n, r=0.3):
+    x = (np.arange(n) + 0.5) / n - 0.5
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    return (X ** 2 + Y ** 2 + Z ** 2 <= r * r).astype(np.int32)
+
+
+def variant_voxels(mvpb, ctx, steps=5, warmup=2):
+    """Three-dimensional cell: a sphere r = 0.3a of the inclusion material in
+    the matrix of the simple cell, 16^3 voxels, 7^3 plane waves (3N = 1029
+    displacement, 6N = 2058 stress unknowns), 30 k on Gamma-X-M-Gamma-R,
+    12 bands, FP64."""
+    from synth import INCLUSION_PROPS, MATRIX_PROPS
+    phase = sphere_voxels(16)
+    props = np.array([MATRIX_PROPS, INCLUSION_PROPS])
+    dcell = ctx.cell_voxels(phase, props)
+    M, nb = 3, 12
+    Q = kpath_cubic(30)
+    out = {}
+
+    def step():
+        plan = dcell.plan(M)
+        out["om"] = plan.solve(Q, nb)
+        plan.close()
+
+    dt = run_median(step, steps, warmup, mvpb, "voxels")
+    return {"value": Q.shape[0] / dt, "unit": "solves/s", "ms_per_step": 1e3 * dt, "precision": "fp64",
+            "three_N": 3 * (2 * M + 1) ** 3, "k_points": int(Q.shape[0]), "n_bands": nb}, out["om"], (phase, props, M, Q, nb)
+
+
+def variant_sensitivities(mvpb, ctx, dcell, M, Q, nb, steps=3, warmup=1):
+    """d lambda / d w_f of every pixel of the headline cell (7 fields x 4096
+    pixels) for every band and k of the headline workload, returned to the
+    host; timed after the solve that supplies omega and U."""
+    plan = dcell.plan(M)
+    om, U = plan.solve(Q, nb, vectors=True)
+
+    def step():
+        plan.sensitivities(Q, om, U, (64, 64))
+
+    dt = run_median(step, steps, warmup, mvpb, "sensitivities")
+    plan.close()
+    items = Q.shape[0] * nb
+    return {"value": items / dt, "unit": "(k, band) gradients/s", "ms_per_step": 1e3 * dt,
+            "outputs_per_item": 7 * 64 * 64, "items": items, "precision": "fp64"}
+
+
+def variant_optimisation(mvpb, ctx, iters=10):
+    """Gradient-based band-gap design: a seeded GRF 32x32 start, per-pixel
+    material fraction between the two materials of the simple cell, 15x15
+    plane waves, 40 k on Gamma-X-M-Gamma, gap between bands 3 and 4; every
+    step verified by a plain FP64 solve."""
+    from paper_1310_6380_amd.optimize import Design
+    from synth import INCLUSION_PROPS, MATRIX_PROPS, config4_cells
+    d = Design(ctx, MATRIX_PROPS, INCLUSION_PROPS, M=7, Q=mvpb.kpath_square(40), b=2)
+    x0 = config4_cells(0, 1)[0].astype(np.float64)
+    t0 = time.perf_counter()
+    x, hist = d.optimise(x0, iters=iters, log=progress)
+    dt = time.perf_counter() - t0
+    return {"iterations": iters, "gap_start": float(hist[0]), "gap_end": float(hist[-1]),
+            "accepted_steps": len(hist) - 1, "plain_solves": d.solves, "seconds": dt,
+            "solves_per_s": d.solves / dt}
+
+
+def assembly_roofline(mvpb, ctx, cfg, cells_dev, prof):
+    """Roofline of the batched plan build's assembly kernels from the kernel
+    timers of one step: the Toeplitz scatter against HBM (algorithmic bytes:
+    the 3 N x N complex blocks written per cell) and the structure factors
+    against the FP64 matrix-core peak (algorithmic flops of the two
+    contractions per cell: 4 fields x (4 nx ny nq + 8 nm nq nx) real flops)."""
+    w_bytes = 0.0
+    sf_flops = 0.0
+    for c in cfg["cells"]:
+        M, nx, ny = c["M"], c["cell"].nx, c["cell"].ny
+        N = (2 * M + 1) ** 2
+        nm = nq = 4 * M + 1
+        w_bytes += 3.0 * N * N * 16.0
+        sf_flops += 4.0 * (4.0 * nx * ny * nq + 8.0 * nm * nq * nx)
+    out = {}
+    t_sc, n_sc = prof.get("toeplitz_scatter", (0.0, 0))
+    if n_sc:
+        ach = w_bytes / (t_sc / 1e3) / 1e9
+        out["toeplitz_scatter"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": ach / HBM_PEAK_GBS, "launches": n_sc, "ms": t_sc,
+                                   "algorithmic_bytes": w_bytes}
+    t_sf, n_sf = prof.get("structure_factors", (0.0, 0))
+    if n_sf:
+        ach = sf_flops / (t_sf / 1e3) / 1e12
+        out["structure_factors"] = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": ach / FP64_PEAK_TFLOPS, "launches": n_sf, "ms": t_sf,
+                                    "algorithmic_flops": sf_flops}
+    return out
+
+
+PAPER_NUMBERS = [
+    {"what": "1132-element hexagonal cell (one phase per element), 18 branches", "time": "18.5 s (abstract: under 20 s)",
+     "k_points": "not stated; 70 assumed", "derived_solves_per_s": 70 / 18.5, "plane_waves": "M = 3 (2N = 98)",
+     "hardware": "NVIDIA Quadro K2000 (Kepler, 384 CUDA cores, 2 GB) in a desktop, Python + CUDA; precision not stated",
+     "compare_with": "variants.hex_1132_element_polygons (2N = 882)"},
+    {"what": "first branches of a simpler cell", "time": "about 2 s (abstract: under 2.5 s)", "k_points": "70",
+     "derived_solves_per_s": 70 / 2.5, "plane_waves": "small M (about 2)",
+     "hardware": "NVIDIA Quadro K2000, desktop; precision not stated",
+     "compare_with": "variants.simple_cell (2N = 98)"},
+    {"what": "full band structure, 18 branches, 1000 elements", "time": "90 s", "k_points": "70",
+     "derived_solves_per_s": 70 / 90.0, "plane_waves": "M = 5 (2N = 242)",
+     "hardware": "NVIDIA Quadro K2000, desktop; precision not stated", "compare_with": "value (2N = 882)"},
+]
 
 
 def copy_calibration(mib: int):
@@ -361,13 +621,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=6, help="k-points timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=6,
+                    help="k-points timed on the CPU oracle with one thread (0 = skip the CPU baseline)")
+    ap.add_argument("--surrogate-full", action="store_true",
+                    help="only the surrogate study at full scale: 50 000 GRF cells, 45 000 trained, 5 000 held out")
     ap.add_argument("--no-variants", action="store_true", help="only the headline FP64 workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB once with the library's plain copy kernel (counter calibration)")
     args = ap.parse_args()
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
+        return
+    if args.surrogate_full:
+        from paper_1310_6380_amd import mvpb
+        ctx = mvpb.Context(0)
+        res = variant_surrogate(mvpb, ctx, n_train=45000, n_test=5000, epochs=60, label_chunk=1024)
+        print(json.dumps({"surrogate_grf_cells_full": res}), flush=True)
+        ctx.close()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note",
@@ -436,8 +706,16 @@ def main():
     omega = om_dev.to_numpy(np.float64, (Q.shape[0], nb))
     variants = {}
     om_mixed = om_batch = cfg2 = om_prec = cfg3 = om_hex = hexcfg = om_h1132 = h1132cfg = stress_out = None
+    om_c0 = c0cfg = om_an = ancfg = om_vox = voxcfg = None
     if not args.no_variants:
-        variants["mixed_1132_phase"], om_mixed = variant_mixed(mvpb, ctx, dcell, M, Q, nb, args.steps, args.warmup)
+        variants["simple_cell"], om_c0, c0cfg = variant_simple_cell(mvpb, ctx)
+        ctx.set_accuracy(0.0)
+        try:
+            variants["mixed_1132_phase"], om_mixed = variant_mixed(mvpb, ctx, dcell, M, Q, nb, args.steps,
+                                                                   args.warmup)
+            variants["mixed_1132_phase"]["estimated_rel_freq_err"] = ctx.last_accuracy()
+        finally:
+            ctx.set_accuracy(1e-5)
         variants["stress_modes_1132_phase"], stress_out = variant_stress(mvpb, ctx, dcell, M, Q, nb,
                                                                         max(1, args.steps // 2), 1)
         variants["batched_256_cells"], om_batch, cfg2 = variant_batched(mvpb, ctx, max(1, args.steps // 2), 1)
@@ -447,6 +725,10 @@ def main():
                                                                                     args.warmup)
         variants["hex_1132_element_polygons"], om_h1132, h1132cfg = variant_hex_1132(mvpb, ctx, args.steps,
                                                                                      args.warmup)
+        variants["anisotropic_1132_phase"], om_an, ancfg = variant_anisotropic(mvpb, ctx)
+        variants["voxel_sphere_3d"], om_vox, voxcfg = variant_voxels(mvpb, ctx)
+        variants["sensitivities_1132_phase"] = variant_sensitivities(mvpb, ctx, dcell, M, Q, nb)
+        variants["gradient_band_gap_design"] = variant_optimisation(mvpb, ctx)
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -456,6 +738,7 @@ def main():
                    "k_points": int(Q.shape[0]), "n_bands": nb, "two_N": n},
         "roofline": roof,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof_all.items() if v[1]},
+        "paper_reference": PAPER_NUMBERS,
     }
     if variants:
         out["variants"] = variants
@@ -466,6 +749,38 @@ def main():
         if om_mixed is not None:
             from oracle.compare import band_error
             variants["mixed_1132_phase"]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om_mixed[ref_idx], ref)
+        if om_c0 is not None:
+            from oracle import mixed_oracle as mo
+            from oracle.compare import band_error
+            c0 = c0cfg["cell"]
+            t0 = time.perf_counter()
+            ref0, _ = mo.bands(c0.phase, c0.props, c0.lattice, c0cfg["M"], c0cfg["M"], c0cfg["Q"], c0cfg["n_bands"])
+            d0 = time.perf_counter() - t0
+            variants["simple_cell"]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om_c0, ref0)
+            variants["simple_cell"]["cpu_oracle"] = {"value": c0cfg["Q"].shape[0] / d0, "unit": "solves/s",
+                                                     "sample": "all 30 k-points", "cores": cb["cores"]}
+        if om_an is not None:
+            from oracle import mixed_oracle as mo
+            from oracle.compare import band_error
+            from synth import voigt_rows_to_matrices
+            c1, rows = ancfg
+            W, rho = voigt_rows_to_matrices(rows, 2)
+            props = np.stack([np.ones(len(rho)), np.zeros(len(rho)), rho], axis=1)
+            kk = [3, 40]
+            progress("cpu baseline: anisotropic oracle on", len(kk), "k-points")
+            I = mo.subdomain_integral_tables(c1["cell"].phase, len(rho), c1["cell"].lattice, M, M)
+            tabs = mo.phase_sum_tables(I, props, phase_weights=W)
+            refa = np.array([mo.solve_k(mo.assemble(I, props, c1["cell"].lattice, M, M, Q[t], tables=tabs), nb)[0]
+                             for t in kk])
+            variants["anisotropic_1132_phase"]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om_an[kk], refa)
+        if om_vox is not None:
+            from oracle import mixed3d_oracle as m3
+            from oracle.compare import band_error
+            phase3, props3, M3, Q3, nb3 = voxcfg
+            kk = [0, 11, 23]
+            progress("cpu baseline: three-dimensional oracle on", len(kk), "k-points")
+            refv, _ = m3.bands3(phase3, props3, np.eye(3), M3, M3, M3, Q3[kk], nb3)
+            variants["voxel_sphere_3d"]["max_rel_freq_err_vs_fp64_oracle"] = band_error(om_vox[kk], refv)
         if om_batch is not None:
             variants["batched_256_cells"]["max_rel_freq_err_vs_fp64_oracle"] = batched_error(cfg2, om_batch)
         if om_prec is not None:

@@ -841,14 +841,46 @@ static int build_plan_group(mvpb_ctx ctx, const mvpb_cell *cells, int g, int M1,
   HIP_TRY(P.alloc(sizeof(cd) * 6 * NN * g));
   HIP_TRY(Xp.alloc(sizeof(cd) * 18 * NN * g));
   cd *Tm = mats.as<cd>(), *Li = linv.as<cd>(), *Pm = P.as<cd>(), *Xm = Xp.as<cd>();
-  // structure factors and Sigma = T(d11+d12), Delta = T(d11-d12), R = T(rho)
-  for (int c = 0; c < g; ++c) {
-    int rc = run_structure_factors(cells[c], M1, M2, precision, X, F1);
-    if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(F.as<cd>() + c * fsz, F1.p, sizeof(cd) * fsz, hipMemcpyDeviceToDevice, st));
-    cd *Tc = Tm + 3 * NN * c;
-    HIP_TRY(launch_toeplitz_scatter(F.as<cd>() + c * fsz, M1, M2, N, Tc, Tc + NN, Tc + 2 * NN, st));
+  // structure factors: runs of pixel cells on one grid in one launch pair on
+  // the matrix cores, other cells one by one
+  {
+    DevBuf tabs(pool);
+    int c = 0;
+    while (c < g) {
+      const mvpb_cell c0 = cells[c];
+      int c1 = c + 1;
+      const bool batchable = !c0->polygons && !(precision & MVPB_PREC_SF_PLAIN64);
+      while (batchable && c1 < g && !cells[c1]->polygons && cells[c1]->nx == c0->nx && cells[c1]->ny == c0->ny) ++c1;
+      if (batchable && c1 - c > 1) {
+        const int cnt = c1 - c;
+        std::vector<const void *> tb;
+        for (int k = c; k < c1; ++k) tb.push_back(cells[k]->phase.p);
+        for (int k = c; k < c1; ++k) tb.push_back(cells[k]->wtab.p);
+        std::vector<double> areas(cnt);
+        for (int k = 0; k < cnt; ++k) areas[k] = cells[c + k]->area;
+        const size_t tbytes = sizeof(void *) * tb.size();
+        HIP_TRY(tabs.reserve(tbytes + sizeof(double) * cnt));
+        HIP_TRY(hipMemcpyAsync(tabs.p, tb.data(), tbytes, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(tabs.as<char>() + tbytes, areas.data(), sizeof(double) * cnt, hipMemcpyHostToDevice,
+                               st));
+        HIP_TRY(X.reserve(sizeof(double) * 8 * (size_t)c0->nx * (4 * M2 + 1) * cnt));
+        void **tp = tabs.as<void *>();
+        HIP_TRY(launch_structure_factors_mfma_batch(precision & 3, (const int32_t *const *)tp,
+                                                    (const double *const *)(tp + cnt),
+                                                    (const double *)(tabs.as<char>() + tbytes), cnt, c0->nx, c0->ny,
+                                                    M1, M2, X.as<double>(), F.as<cd>() + c * fsz, st));
+      } else {
+        for (int k = c; k < c1; ++k) {
+          int rc = run_structure_factors(cells[k], M1, M2, precision, X, F1);
+          if (rc) return rc;
+          HIP_TRY(hipMemcpyAsync(F.as<cd>() + k * fsz, F1.p, sizeof(cd) * fsz, hipMemcpyDeviceToDevice, st));
+        }
+      }
+      c = c1;
+    }
   }
+  // Sigma = T(d11+d12), Delta = T(d11-d12), R = T(rho) of every cell in one launch
+  HIP_TRY(launch_toeplitz_scatter(F.as<cd>(), M1, M2, N, Tm, g, st));
   // G_l vectors per cell: G_0 = 1, G_l = 2 pi (T n)_l at Q = 0
   std::vector<double> gv(3 * (size_t)N * g);
   for (int c = 0; c < g; ++c)

@@ -360,12 +360,27 @@ MVPB_DEV void twiddle(long num, int n, double *c, double *s) {
   sincospi((double)t / (double)n, s, c);
 }
 
+// Cells of one launch: a single cell (tables NULL) or one cell per
+// blockIdx.y (device tables of phase maps, weight tables and areas).
+struct SfCells {
+  const int32_t *phase;
+  const double *wtab;
+  double area;
+  const int32_t *const *phases;
+  const double *const *wtabs;
+  const double *areas;
+  size_t xstride;   // doubles of pass scratch per cell
+  size_t fstride;   // complex outputs per cell
+};
+
 // Pass A: one wavefront per (w, 16-row tile of i, 16-column tile of q).
 // X is stored in FP64 as re/im planes [4][nx][nq].
 template <int P>
-__global__ void __launch_bounds__(256) sf_mfma_pass_a(const int32_t *__restrict__ phase, const double *__restrict__ wtab,
-                                                      int nx, int ny, int M2, double *__restrict__ XR,
-                                                      double *__restrict__ XI) {
+__global__ void __launch_bounds__(256) sf_mfma_pass_a(SfCells cs, int nx, int ny, int M2, double *__restrict__ X) {
+  const int32_t *__restrict__ phase = cs.phases ? cs.phases[blockIdx.y] : cs.phase;
+  const double *__restrict__ wtab = cs.wtabs ? cs.wtabs[blockIdx.y] : cs.wtab;
+  double *__restrict__ XR = X + blockIdx.y * cs.xstride;
+  double *__restrict__ XI = XR + (size_t)4 * nx * (4 * M2 + 1);
   typedef Mma<P> T;
   constexpr int K = 4 * T::KPL;
   const int nq = 4 * M2 + 1;
@@ -406,9 +421,12 @@ __global__ void __launch_bounds__(256) sf_mfma_pass_a(const int32_t *__restrict_
 
 // Pass B: one wavefront per (w, 16-row tile of m, 16-column tile of q).
 template <int P>
-__global__ void __launch_bounds__(256) sf_mfma_pass_b(const double *__restrict__ XR, const double *__restrict__ XI,
-                                                      int nx, int ny, int M1, int M2, double area,
-                                                      cd *__restrict__ F) {
+__global__ void __launch_bounds__(256) sf_mfma_pass_b(SfCells cs, const double *__restrict__ X, int nx, int ny, int M1,
+                                                      int M2, cd *__restrict__ Fout) {
+  const double *__restrict__ XR = X + blockIdx.y * cs.xstride;
+  const double *__restrict__ XI = XR + (size_t)4 * nx * (4 * M2 + 1);
+  const double area = cs.areas ? cs.areas[blockIdx.y] : cs.area;
+  cd *__restrict__ F = Fout + blockIdx.y * cs.fstride;
   typedef Mma<P> T;
   constexpr int K = 4 * T::KPL;
   const int nm = 4 * M1 + 1, nq = 4 * M2 + 1;
@@ -455,33 +473,42 @@ __global__ void __launch_bounds__(256) sf_mfma_pass_b(const double *__restrict__
   }
 }
 
+template <int P>
+static void sf_mfma_launch(const SfCells &cs, int count, int nx, int ny, int M1, int M2, double *X, cd *F,
+                           hipStream_t st) {
+  const int nq = 4 * M2 + 1, nm = 4 * M1 + 1;
+  const int ta = 4 * ((nx + 15) / 16) * ((nq + 15) / 16);
+  const int tb = 4 * ((nm + 15) / 16) * ((nq + 15) / 16);
+  hipLaunchKernelGGL(sf_mfma_pass_a<P>, dim3((ta + 3) / 4, count), dim3(256), 0, st, cs, nx, ny, M2, X);
+  hipLaunchKernelGGL(sf_mfma_pass_b<P>, dim3((tb + 3) / 4, count), dim3(256), 0, st, cs, X, nx, ny, M1, M2, F);
+}
+
+static hipError_t sf_mfma_dispatch(int prec, const SfCells &cs, int count, int nx, int ny, int M1, int M2, double *X,
+                                   cd *F, hipStream_t st) {
+  ProfScope ps(K_SF, st);
+  switch (prec) {
+    case 0: sf_mfma_launch<0>(cs, count, nx, ny, M1, M2, X, F, st); break;
+    case 1: sf_mfma_launch<1>(cs, count, nx, ny, M1, M2, X, F, st); break;
+    case 3: sf_mfma_launch<3>(cs, count, nx, ny, M1, M2, X, F, st); break;
+    default: sf_mfma_launch<2>(cs, count, nx, ny, M1, M2, X, F, st); break;
+  }
+  return hipGetLastError();
+}
+
 // X must hold 2 * 4 * nx * (4 M2 + 1) doubles.
 hipError_t launch_structure_factors_mfma(int prec, const int32_t *phase, const double *wtab, int nx, int ny, int M1,
                                          int M2, double area, double *X, cd *F, hipStream_t st) {
-  const int nq = 4 * M2 + 1, nm = 4 * M1 + 1;
-  double *XR = X, *XI = X + (size_t)4 * nx * nq;
-  const int ta = 4 * ((nx + 15) / 16) * ((nq + 15) / 16);
-  const int tb = 4 * ((nm + 15) / 16) * ((nq + 15) / 16);
-  ProfScope ps(K_SF, st);
-  switch (prec) {
-    case 0:
-      hipLaunchKernelGGL(sf_mfma_pass_a<0>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
-      hipLaunchKernelGGL(sf_mfma_pass_b<0>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
-      break;
-    case 1:
-      hipLaunchKernelGGL(sf_mfma_pass_a<1>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
-      hipLaunchKernelGGL(sf_mfma_pass_b<1>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
-      break;
-    case 3:
-      hipLaunchKernelGGL(sf_mfma_pass_a<3>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
-      hipLaunchKernelGGL(sf_mfma_pass_b<3>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
-      break;
-    default:
-      hipLaunchKernelGGL(sf_mfma_pass_a<2>, dim3((ta + 3) / 4), dim3(256), 0, st, phase, wtab, nx, ny, M2, XR, XI);
-      hipLaunchKernelGGL(sf_mfma_pass_b<2>, dim3((tb + 3) / 4), dim3(256), 0, st, XR, XI, nx, ny, M1, M2, area, F);
-      break;
-  }
-  return hipGetLastError();
+  SfCells cs{phase, wtab, area, nullptr, nullptr, nullptr, 0, 0};
+  return sf_mfma_dispatch(prec, cs, 1, nx, ny, M1, M2, X, F, st);
+}
+
+hipError_t launch_structure_factors_mfma_batch(int prec, const int32_t *const *phases, const double *const *wtabs,
+                                               const double *areas, int count, int nx, int ny, int M1, int M2,
+                                               double *X, cd *F, hipStream_t st) {
+  const size_t xstride = (size_t)8 * nx * (4 * M2 + 1);
+  const size_t fstride = (size_t)4 * (4 * M1 + 1) * (4 * M2 + 1);
+  SfCells cs{nullptr, nullptr, 0.0, phases, wtabs, areas, xstride, fstride};
+  return sf_mfma_dispatch(prec, cs, count, nx, ny, M1, M2, X, F, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -489,13 +516,17 @@ hipError_t launch_structure_factors_mfma(int prec, const int32_t *phase, const d
 // 2 (rho).  Column-major N x N outputs.  n_r = (alpha_r, beta_r) with
 // r = (alpha+M1)(2M2+1) + (beta+M2).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) toeplitz_scatter(const cd *__restrict__ F, int M1, int M2, int N,
-                                                        cd *__restrict__ T0, cd *__restrict__ T1,
-                                                        cd *__restrict__ T2) {
+__global__ void __launch_bounds__(256) toeplitz_scatter(const cd *__restrict__ Fin, int M1, int M2, int N,
+                                                        cd *__restrict__ T0in, size_t tstride) {
   const int nb = 2 * M2 + 1, nm = 4 * M1 + 1, nq = 4 * M2 + 1;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (r >= N) return;
+  // cell blockIdx.z: its four fields and its three matrices, stored one after the other
+  const cd *__restrict__ F = Fin + (size_t)blockIdx.z * 4 * nm * nq;
+  cd *__restrict__ T0 = T0in + (size_t)blockIdx.z * tstride;
+  cd *__restrict__ T1 = T0 + (size_t)N * N;
+  cd *__restrict__ T2 = T1 + (size_t)N * N;
   const int ar = r / nb, br = r - ar * nb;
   const int ac = c / nb, bc = c - ac * nb;
   const int dm = ac - ar + 2 * M1, dq = bc - br + 2 * M2;
@@ -506,10 +537,10 @@ __global__ void __launch_bounds__(256) toeplitz_scatter(const cd *__restrict__ F
   T2[dst] = F[(size_t)2 * nm * nq + o];
 }
 
-hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T0, cd *T1, cd *T2,
-                                   hipStream_t st) {
+hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T, int count, hipStream_t st) {
   ProfScope ps(K_SCATTER, st);
-  hipLaunchKernelGGL(toeplitz_scatter, dim3((N + 255) / 256, N), dim3(256), 0, st, F, M1, M2, N, T0, T1, T2);
+  hipLaunchKernelGGL(toeplitz_scatter, dim3((N + 255) / 256, N, count), dim3(256), 0, st, F, M1, M2, N, T,
+                     (size_t)3 * N * N);
   return hipGetLastError();
 }
 

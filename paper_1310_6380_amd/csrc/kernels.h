@@ -100,8 +100,13 @@ hipError_t launch_stress_combine(const cd *Z, int n_k, int nb, int N, cd *S, hip
 hipError_t launch_structure_factors_poly(const double *edges, const int *ephase, const double *wtab, int n_edges,
                                          const double T[4], const double f0[4], int M1, int M2, cd *X, cd *F,
                                          hipStream_t st);
-hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T0, cd *T1, cd *T2,
-                                   hipStream_t st);
+// count cells: F [count][4][4M1+1][4M2+1], T [count][3][N][N] (Sigma, Delta, rho blocks)
+hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T, int count, hipStream_t st);
+// count pixel cells of one grid size in one launch pair: device tables of phase
+// maps, weight tables and areas; X: count * 8 nx (4M2+1) doubles; F: count * 4 (4M1+1)(4M2+1).
+hipError_t launch_structure_factors_mfma_batch(int prec, const int32_t *const *phases, const double *const *wtabs,
+                                               const double *areas, int count, int nx, int ny, int M1, int M2,
+                                               double *X, cd *F, hipStream_t st);
 hipError_t launch_combine(const cd *Xp, int N, double s, cd *coef, hipStream_t st);
 hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, bool fp32, hipStream_t st);
 

@@ -9,7 +9,9 @@
 // data pass is a gather col2im (every input pixel collects its taps, so no
 // atomics and bitwise-reproducible results).  GEMMs run either as FP32 FMA
 // tiles or on the matrix cores with BF16 inputs and FP32 accumulation
-// (v_mfma_f32_16x16x16bf16_1k); master weights and Adam moments stay FP32.
+// (v_mfma_f32_16x16x32_bf16), bias and ReLU applied in the GEMM epilogue,
+// long reductions split over workgroups; master weights and Adam moments
+// stay FP32.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -23,47 +25,77 @@
 namespace mvpb {
 
 // ---------------------------------------------------------------------------
-// GEMM, row-major: C[M x N] = alpha op(A) op(B) + beta C.
+// GEMM, row-major: C[M x N] = act(alpha op(A) op(B) + beta C + bias).
 // op(A) = A (A[i*lda+k]) or A^T (A[k*lda+i]); op(B) = B (B[k*ldb+j]) or B^T (B[j*ldb+k]).
+// Long reductions (the weight gradients of the convolutions sum over every
+// output pixel of the batch) are split over blockIdx.z: split z sums its K
+// range into its own slice of a partial buffer, and gemm_reduce adds the
+// slices in a fixed order (reproducible), applying alpha, beta and bias.
 // ---------------------------------------------------------------------------
-constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int GBM = 64, GBN = 64;
 
-template <int TA, int TB>
-MVPB_DEV void load_tiles(const float *A, int lda, const float *B, int ldb, int M, int N, int K, int m0, int n0,
-                         int k0, float (&As)[GBK][GBM + 4], float (&Bs)[GBK][GBN + 4]) {
+struct GemmArgs {
+  int M, N, K;
+  float alpha, beta;
+  const float *A;
+  int lda;
+  const float *B;
+  int ldb;
+  float *C;          // output, or the partial buffer [splits][M][N] when kchunk < K
+  int ldc;
+  int kchunk;        // K range of one split
+  const float *bias; // per column, nullable (applied when not split)
+  int relu;
+};
+
+template <int TA, int TB, int BK>
+MVPB_DEV void load_tiles(const GemmArgs &g, int m0, int n0, int k0, int k1, float (&As)[BK][GBM + 4],
+                         float (&Bs)[BK][GBN + 4]) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < GBM * GBK; e += 256) {
+  for (int e = tid; e < GBM * BK; e += 256) {
     int i, k;
-    if (TA == 0) { i = e / GBK; k = e % GBK; } else { k = e / GBM; i = e % GBM; }
+    if (TA == 0) { i = e / BK; k = e % BK; } else { k = e / GBM; i = e % GBM; }
     const int gi = m0 + i, gk = k0 + k;
     float v = 0.f;
-    if (gi < M && gk < K) v = TA == 0 ? A[(size_t)gi * lda + gk] : A[(size_t)gk * lda + gi];
+    if (gi < g.M && gk < k1) v = TA == 0 ? g.A[(size_t)gi * g.lda + gk] : g.A[(size_t)gk * g.lda + gi];
     As[k][i] = v;
   }
-  for (int e = tid; e < GBK * GBN; e += 256) {
+  for (int e = tid; e < BK * GBN; e += 256) {
     int k, j;
-    if (TB == 0) { k = e / GBN; j = e % GBN; } else { j = e / GBK; k = e % GBK; }
+    if (TB == 0) { k = e / GBN; j = e % GBN; } else { j = e / BK; k = e % BK; }
     const int gk = k0 + k, gj = n0 + j;
     float v = 0.f;
-    if (gk < K && gj < N) v = TB == 0 ? B[(size_t)gk * ldb + gj] : B[(size_t)gj * ldb + gk];
+    if (gk < k1 && gj < g.N) v = TB == 0 ? g.B[(size_t)gk * g.ldb + gj] : g.B[(size_t)gj * g.ldb + gk];
     Bs[k][j] = v;
   }
 }
 
+// Store one result: straight (with alpha, beta, bias, ReLU) or into the split's partial slice.
+MVPB_DEV void gemm_store(const GemmArgs &g, int i, int j, float acc) {
+  if (i >= g.M || j >= g.N) return;
+  if (g.kchunk < g.K) {
+    g.C[((size_t)blockIdx.z * g.M + i) * g.N + j] = acc;
+    return;
+  }
+  float *c = g.C + (size_t)i * g.ldc + j;
+  float v = g.alpha * acc + (g.beta != 0.f ? g.beta * *c : 0.f) + (g.bias ? g.bias[j] : 0.f);
+  *c = g.relu ? fmaxf(v, 0.f) : v;
+}
+
 template <int TA, int TB>
-__global__ void __launch_bounds__(256) sgemm_f32(int M, int N, int K, float alpha, const float *__restrict__ A, int lda,
-                                                 const float *__restrict__ B, int ldb, float beta,
-                                                 float *__restrict__ C, int ldc) {
-  __shared__ float As[GBK][GBM + 4];
-  __shared__ float Bs[GBK][GBN + 4];
+__global__ void __launch_bounds__(256) sgemm_f32(GemmArgs g) {
+  constexpr int BK = 16;
+  __shared__ float As[BK][GBM + 4];
+  __shared__ float Bs[BK][GBN + 4];
   const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int kb = blockIdx.z * g.kchunk, ke = min(g.K, kb + g.kchunk);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += GBK) {
-    load_tiles<TA, TB>(A, lda, B, ldb, M, N, K, m0, n0, k0, As, Bs);
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    load_tiles<TA, TB, BK>(g, m0, n0, k0, ke, As, Bs);
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < GBK; ++kk) {
+    for (int kk = 0; kk < BK; ++kk) {
       float a[4], b[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[q] = As[kk][ty + 16 * q];
@@ -77,38 +109,26 @@ __global__ void __launch_bounds__(256) sgemm_f32(int M, int N, int K, float alph
     __syncthreads();
   }
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int i = m0 + ty + 16 * p;
-    if (i >= M) continue;
+  for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = n0 + tx + 16 * q;
-      if (j >= N) continue;
-      float *c = C + (size_t)i * ldc + j;
-      *c = alpha * acc[p][q] + (beta != 0.f ? beta * *c : 0.f);
-    }
-  }
+    for (int q = 0; q < 4; ++q) gemm_store(g, m0 + ty + 16 * p, n0 + tx + 16 * q, acc[p][q]);
 }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
-typedef short s4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
-MVPB_DEV short to_bf16(float f) {  // round to nearest even
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
-}
-
-// Matrix-core GEMM: 64 x 64 block tile, 4 wavefronts of 32 x 32 (2 x 2 MFMA
-// 16 x 16 x 16 tiles).  Lane l feeds A[row = l%16][k = 4(l/16)+v] and
-// B[k = 4(l/16)+v][col = l%16] and receives D[4(l/16)+v][l%16].
+// Matrix-core GEMM: 64 x 64 block tile, 4 wavefronts of 32 x 32 (2 x 2
+// v_mfma_f32_16x16x32_bf16 tiles, 32-deep K steps).  Lane l feeds
+// A[row = l%16][k = 8(l/16)+v] and B[k = 8(l/16)+v][col = l%16], v < 8, and
+// receives D[4(l/16)+v][l%16], v < 4.  Inputs are rounded to BF16 (nearest
+// even) when they leave LDS; accumulation is FP32.
 template <int TA, int TB>
-__global__ void __launch_bounds__(256) sgemm_bf16(int M, int N, int K, float alpha, const float *__restrict__ A, int lda,
-                                                  const float *__restrict__ B, int ldb, float beta,
-                                                  float *__restrict__ C, int ldc) {
-  __shared__ float As[GBK][GBM + 4];
-  __shared__ float Bs[GBK][GBN + 4];
+__global__ void __launch_bounds__(256) sgemm_bf16(GemmArgs g) {
+  constexpr int BK = 32;
+  __shared__ float As[BK][GBM + 4];
+  __shared__ float Bs[BK][GBN + 4];
   const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int kb = blockIdx.z * g.kchunk, ke = min(g.K, kb + g.kchunk);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   f4v acc[2][2];
@@ -116,22 +136,22 @@ __global__ void __launch_bounds__(256) sgemm_bf16(int M, int N, int K, float alp
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[p][q] = f4v{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += GBK) {
-    load_tiles<TA, TB>(A, lda, B, ldb, M, N, K, m0, n0, k0, As, Bs);
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    load_tiles<TA, TB, BK>(g, m0, n0, k0, ke, As, Bs);
     __syncthreads();
-    s4v af[2], bf[2];
+    bf8v af[2], bf[2];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) af[p][v] = to_bf16(As[4 * (lane >> 4) + v][wr + 16 * p + (lane & 15)]);
+      for (int v = 0; v < 8; ++v) af[p][v] = (__bf16)As[8 * (lane >> 4) + v][wr + 16 * p + (lane & 15)];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) bf[q][v] = to_bf16(Bs[4 * (lane >> 4) + v][wc + 16 * q + (lane & 15)]);
+      for (int v = 0; v < 8; ++v) bf[q][v] = (__bf16)Bs[8 * (lane >> 4) + v][wc + 16 * q + (lane & 15)];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
-      for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[p], bf[q], acc[p][q], 0, 0, 0);
+      for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p], bf[q], acc[p][q], 0, 0, 0);
     __syncthreads();
   }
 #pragma unroll
@@ -139,31 +159,61 @@ __global__ void __launch_bounds__(256) sgemm_bf16(int M, int N, int K, float alp
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = m0 + wr + 16 * p + 4 * (lane >> 4) + v;
-        const int j = n0 + wc + 16 * q + (lane & 15);
-        if (i < M && j < N) {
-          float *c = C + (size_t)i * ldc + j;
-          *c = alpha * acc[p][q][v] + (beta != 0.f ? beta * *c : 0.f);
-        }
-      }
+      for (int v = 0; v < 4; ++v)
+        gemm_store(g, m0 + wr + 16 * p + 4 * (lane >> 4) + v, n0 + wc + 16 * q + (lane & 15), acc[p][q][v]);
+}
+
+// C = act(alpha sum_z P[z] + beta C + bias), slices added in order z = 0, 1, ...
+__global__ void __launch_bounds__(256) gemm_reduce(const float *__restrict__ P, int splits, int M, int N, float alpha,
+                                                   float beta, float *__restrict__ C, int ldc,
+                                                   const float *__restrict__ bias, int relu) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * N) return;
+  const int i = e / N, j = e % N;
+  float acc = 0.f;
+  for (int z = 0; z < splits; ++z) acc += P[(size_t)z * M * N + e];
+  float *c = C + (size_t)i * ldc + j;
+  float v = alpha * acc + (beta != 0.f ? beta * *c : 0.f) + (bias ? bias[j] : 0.f);
+  *c = relu ? fmaxf(v, 0.f) : v;
+}
+
+// Split K so that every output tile gets enough workgroups: long reductions
+// (K >= 4096) are cut into chunks of at least 1024, at most 128 chunks, and
+// only while the output tiles alone leave the chip idle.
+static int gemm_splits(int M, int N, int K) {
+  const long tiles = (long)((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
+  if (K < 4096 || tiles >= 256) return 1;
+  int sp = (int)std::min<long>(128, (512 + tiles - 1) / tiles);
+  sp = std::min(sp, std::max(1, K / 1024));
+  return sp;
 }
 
 static hipError_t gemm(bool bf16, int ta, int tb, int M, int N, int K, float alpha, const float *A, int lda,
-                       const float *B, int ldb, float beta, float *C, int ldc, hipStream_t st) {
-  dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM);
-#define MVPB_GEMM_CASE(TA, TB)                                                                             \
-  if (ta == TA && tb == TB) {                                                                              \
-    if (bf16)                                                                                              \
-      hipLaunchKernelGGL((sgemm_bf16<TA, TB>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc); \
-    else                                                                                                   \
-      hipLaunchKernelGGL((sgemm_f32<TA, TB>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);  \
+                       const float *B, int ldb, float beta, float *C, int ldc, hipStream_t st,
+                       const float *bias = nullptr, int relu = 0, float *split_buf = nullptr,
+                       size_t split_cap = 0) {
+  int sp = gemm_splits(M, N, K);
+  if ((size_t)sp * M * N > split_cap || !split_buf) sp = 1;
+  const int align = bf16 ? 32 : 16;
+  const int kchunk = sp == 1 ? K : ((K + sp - 1) / sp + align - 1) / align * align;
+  sp = (K + kchunk - 1) / kchunk;
+  GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, sp == 1 ? C : split_buf, ldc, kchunk, bias, relu};
+  dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, sp);
+#define MVPB_GEMM_CASE(TA, TB)                                                            \
+  if (ta == TA && tb == TB) {                                                             \
+    if (bf16)                                                                             \
+      hipLaunchKernelGGL((sgemm_bf16<TA, TB>), grid, dim3(256), 0, st, g);                \
+    else                                                                                  \
+      hipLaunchKernelGGL((sgemm_f32<TA, TB>), grid, dim3(256), 0, st, g);                 \
   }
   MVPB_GEMM_CASE(0, 0)
   MVPB_GEMM_CASE(0, 1)
   MVPB_GEMM_CASE(1, 0)
   MVPB_GEMM_CASE(1, 1)
 #undef MVPB_GEMM_CASE
+  if (sp > 1)
+    hipLaunchKernelGGL(gemm_reduce, dim3((M * N + 255) / 256), dim3(256), 0, st, split_buf, sp, M, N, alpha, beta, C,
+                       ldc, bias, relu);
   return hipGetLastError();
 }
 
@@ -215,29 +265,32 @@ __global__ void col2im(const float *__restrict__ dcol, float *__restrict__ da, i
   }
 }
 
-__global__ void bias_act(float *__restrict__ z, const float *__restrict__ bias, size_t rows, int C, int relu) {
-  const size_t total = rows * C;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    float v = z[e] + bias[e % C];
-    z[e] = relu ? fmaxf(v, 0.f) : v;
-  }
-}
-
 __global__ void relu_mask(float *__restrict__ d, const float *__restrict__ a, size_t n) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
     if (!(a[e] > 0.f)) d[e] = 0.f;
 }
 
-// db[c] = sum_r d[r][c]; one block per 64-column slab, fixed reduction order
-__global__ void __launch_bounds__(256) column_sums(const float *__restrict__ d, size_t rows, int C, float *__restrict__ db) {
-  __shared__ float part[4][64];
+// Partial column sums: block (x, y) sums rows y, y + gridDim.y, ... of the
+// 64-column slab x into part[y][c]; column_sums_fin adds the parts in order.
+__global__ void __launch_bounds__(256) column_sums(const float *__restrict__ d, size_t rows, int C,
+                                                   float *__restrict__ part) {
+  __shared__ float red[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
   float acc = 0.f;
   if (c < C)
-    for (size_t r = g; r < rows; r += 4) acc += d[r * C + c];
-  part[g][threadIdx.x & 63] = acc;
+    for (size_t r = (size_t)blockIdx.y * 4 + g; r < rows; r += (size_t)gridDim.y * 4) acc += d[r * C + c];
+  red[g][threadIdx.x & 63] = acc;
   __syncthreads();
-  if (g == 0 && c < C) db[c] = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
+  if (g == 0 && c < C) part[(size_t)blockIdx.y * C + c] = red[0][threadIdx.x] + red[1][threadIdx.x] +
+                                                           red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ void column_sums_fin(const float *__restrict__ part, int parts, int C, float *__restrict__ db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  float acc = 0.f;
+  for (int p = 0; p < parts; ++p) acc += part[(size_t)p * C + c];
+  db[c] = acc;
 }
 
 // dout = 2 (out - y) / n and per-block partial sums of (out - y)^2
@@ -297,6 +350,8 @@ struct Layer {
 };
 const Layer kConv[4] = {{1, 32, 1, 32, 32}, {32, 32, 2, 32, 32}, {32, 32, 2, 16, 16}, {32, 32, 2, 8, 8}};
 constexpr int kFcIn = 512, kFcHid = 256, kOut = 400, kPix = 32 * 32;
+constexpr size_t kSplitCap = (size_t)2 << 20;   // floats of split-K partial slices
+constexpr int kColParts = 256;                  // row blocks of the bias-gradient sums
 
 int param_offsets(int *off) {  // 12 tensors
   int o = 0, t = 0;
@@ -345,16 +400,33 @@ struct mvpb_sur_s {
   Buf<float> act[5];        // act[0] input [B,32,32,1]; act[l+1] output of conv l (NHWC)
   Buf<float> col, dcol, dact, dact2;
   Buf<float> h, out, dout, dh, dflat, partial;
+  Buf<float> split;     // partial slices of split-K GEMMs
+  Buf<float> colpart;   // partial column sums (bias gradients)
   Buf<uint8_t> cells;
   Buf<float> target;
 };
 
 extern "C" int mvpb_sur_destroy(mvpb_sur net);
 
+// GEMM with the network's precision and split-K scratch.
+static hipError_t net_gemm(mvpb_sur net, int ta, int tb, int M, int N, int K, const float *A, int lda, const float *B,
+                           int ldb, float *C, int ldc, const float *bias = nullptr, int relu = 0) {
+  return gemm(net->bf16, ta, tb, M, N, K, 1.f, A, lda, B, ldb, 0.f, C, ldc, net->st, bias, relu, net->split.p,
+              net->split.n);
+}
+
+// db[c] = sum over rows of d[r][c] (blocks of rows, then the blocks in order).
+static void col_sums(mvpb_sur net, const float *d, size_t rows, int C, float *db) {
+  const int parts = (int)std::min<size_t>(kColParts, (rows + 511) / 512);
+  hipLaunchKernelGGL(column_sums, dim3((C + 63) / 64, parts), dim3(256), 0, net->st, d, rows, C, net->colpart.p);
+  hipLaunchKernelGGL(column_sums_fin, dim3((C + 255) / 256), dim3(256), 0, net->st, net->colpart.p, parts, C, db);
+}
+
 static int sur_forward(mvpb_sur net, int B) {
   hipStream_t st = net->st;
   float *P = net->params.p;
-  for (int l = 0; l < 4; ++l) {
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < 4 && e == hipSuccess; ++l) {
     const Layer &L = kConv[l];
     const int Ho = L.H / L.s, Wo = L.W / L.s;
     const size_t rows = (size_t)B * Ho * Wo;
@@ -362,25 +434,17 @@ static int sur_forward(mvpb_sur net, int B) {
     const size_t tot = rows * K;
     hipLaunchKernelGGL(im2col, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 65535)), dim3(256), 0, st,
                        net->act[l].p, net->col.p, B, L.H, L.W, L.ci, L.s);
-    hipError_t e = gemm(net->bf16, 0, 0, (int)rows, L.co, K, 1.f, net->col.p, K, P + net->off[2 * l], L.co, 0.f,
-                        net->act[l + 1].p, L.co, st);
-    if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "surrogate gemm: %s", hipGetErrorString(e));
-    hipLaunchKernelGGL(bias_act, dim3((unsigned)std::min<size_t>((rows * L.co + 255) / 256, 65535)), dim3(256), 0, st,
-                       net->act[l + 1].p, P + net->off[2 * l + 1], rows, L.co, 1);
+    // convolution as one GEMM, bias and ReLU in its epilogue
+    e = net_gemm(net, 0, 0, (int)rows, L.co, K, net->col.p, K, P + net->off[2 * l], L.co, net->act[l + 1].p, L.co,
+                 P + net->off[2 * l + 1], 1);
   }
   // fc1 (ReLU), fc2
-  hipError_t e = gemm(net->bf16, 0, 0, B, kFcHid, kFcIn, 1.f, net->act[4].p, kFcIn, P + net->off[8], kFcHid, 0.f,
-                      net->h.p, kFcHid, st);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(bias_act, dim3((B * kFcHid + 255) / 256), dim3(256), 0, st, net->h.p, P + net->off[9],
-                       (size_t)B, kFcHid, 1);
-    e = gemm(net->bf16, 0, 0, B, kOut, kFcHid, 1.f, net->h.p, kFcHid, P + net->off[10], kOut, 0.f, net->out.p, kOut, st);
-  }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(bias_act, dim3((B * kOut + 255) / 256), dim3(256), 0, st, net->out.p, P + net->off[11],
-                       (size_t)B, kOut, 0);
-    e = hipGetLastError();
-  }
+  if (e == hipSuccess)
+    e = net_gemm(net, 0, 0, B, kFcHid, kFcIn, net->act[4].p, kFcIn, P + net->off[8], kFcHid, net->h.p, kFcHid,
+                 P + net->off[9], 1);
+  if (e == hipSuccess)
+    e = net_gemm(net, 0, 0, B, kOut, kFcHid, net->h.p, kFcHid, P + net->off[10], kOut, net->out.p, kOut,
+                 P + net->off[11], 0);
   if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "surrogate forward: %s", hipGetErrorString(e));
   return MVPB_OK;
 }
@@ -389,19 +453,15 @@ static int sur_forward(mvpb_sur net, int B) {
 static int sur_backward(mvpb_sur net, int B) {
   hipStream_t st = net->st;
   float *P = net->params.p, *G = net->grads.p;
-  hipError_t e = gemm(net->bf16, 1, 0, kFcHid, kOut, B, 1.f, net->h.p, kFcHid, net->dout.p, kOut, 0.f,
-                      G + net->off[10], kOut, st);
-  hipLaunchKernelGGL(column_sums, dim3((kOut + 63) / 64), dim3(256), 0, st, net->dout.p, (size_t)B, kOut, G + net->off[11]);
-  if (e == hipSuccess)
-    e = gemm(net->bf16, 0, 1, B, kFcHid, kOut, 1.f, net->dout.p, kOut, P + net->off[10], kOut, 0.f, net->dh.p, kFcHid, st);
+  hipError_t e = net_gemm(net, 1, 0, kFcHid, kOut, B, net->h.p, kFcHid, net->dout.p, kOut, G + net->off[10], kOut);
+  col_sums(net, net->dout.p, (size_t)B, kOut, G + net->off[11]);
+  if (e == hipSuccess) e = net_gemm(net, 0, 1, B, kFcHid, kOut, net->dout.p, kOut, P + net->off[10], kOut, net->dh.p, kFcHid);
   hipLaunchKernelGGL(relu_mask, dim3((B * kFcHid + 255) / 256), dim3(256), 0, st, net->dh.p, net->h.p, (size_t)B * kFcHid);
   if (e == hipSuccess)
-    e = gemm(net->bf16, 1, 0, kFcIn, kFcHid, B, 1.f, net->act[4].p, kFcIn, net->dh.p, kFcHid, 0.f, G + net->off[8],
-             kFcHid, st);
-  hipLaunchKernelGGL(column_sums, dim3((kFcHid + 63) / 64), dim3(256), 0, st, net->dh.p, (size_t)B, kFcHid, G + net->off[9]);
+    e = net_gemm(net, 1, 0, kFcIn, kFcHid, B, net->act[4].p, kFcIn, net->dh.p, kFcHid, G + net->off[8], kFcHid);
+  col_sums(net, net->dh.p, (size_t)B, kFcHid, G + net->off[9]);
   if (e == hipSuccess)
-    e = gemm(net->bf16, 0, 1, B, kFcIn, kFcHid, 1.f, net->dh.p, kFcHid, P + net->off[8], kFcHid, 0.f, net->dact.p,
-             kFcIn, st);
+    e = net_gemm(net, 0, 1, B, kFcIn, kFcHid, net->dh.p, kFcHid, P + net->off[8], kFcHid, net->dact.p, kFcIn);
   if (e != hipSuccess) return set_error(MVPB_E_DEVICE, "surrogate backward: %s", hipGetErrorString(e));
   float *da = net->dact.p, *da_next = net->dact2.p;
   for (int l = 3; l >= 0; --l) {
@@ -412,15 +472,15 @@ static int sur_backward(mvpb_sur net, int B) {
     // dz = da * relu'(act[l+1])
     hipLaunchKernelGGL(relu_mask, dim3((unsigned)std::min<size_t>((rows * L.co + 255) / 256, 65535)), dim3(256), 0, st,
                        da, net->act[l + 1].p, rows * L.co);
-    // dW = col^T dz (col recomputed), db = column sums of dz
+    // dW = col^T dz (col recomputed; split over the output pixels), db = column sums of dz
     const size_t tot = rows * K;
     hipLaunchKernelGGL(im2col, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 65535)), dim3(256), 0, st,
                        net->act[l].p, net->col.p, B, L.H, L.W, L.ci, L.s);
-    e = gemm(net->bf16, 1, 0, K, L.co, (int)rows, 1.f, net->col.p, K, da, L.co, 0.f, G + net->off[2 * l], L.co, st);
-    hipLaunchKernelGGL(column_sums, dim3((L.co + 63) / 64), dim3(256), 0, st, da, rows, L.co, G + net->off[2 * l + 1]);
+    e = net_gemm(net, 1, 0, K, L.co, (int)rows, net->col.p, K, da, L.co, G + net->off[2 * l], L.co);
+    col_sums(net, da, rows, L.co, G + net->off[2 * l + 1]);
     if (l > 0 && e == hipSuccess) {
       // dcol = dz W^T, then gather back onto the input pixels
-      e = gemm(net->bf16, 0, 1, (int)rows, K, L.co, 1.f, da, L.co, P + net->off[2 * l], L.co, 0.f, net->dcol.p, K, st);
+      e = net_gemm(net, 0, 1, (int)rows, K, L.co, da, L.co, P + net->off[2 * l], L.co, net->dcol.p, K);
       const size_t tin = (size_t)B * L.H * L.W * L.ci;
       hipLaunchKernelGGL(col2im, dim3((unsigned)std::min<size_t>((tin + 255) / 256, 65535)), dim3(256), 0, st,
                          net->dcol.p, da_next, B, L.H, L.W, L.ci, L.s);
@@ -511,6 +571,8 @@ extern "C" int mvpb_sur_create(mvpb_ctx ctx, int max_batch, int precision, uint6
   A(net->dout, B * kOut);
   A(net->partial, 64);
   A(net->target, B * kOut);
+  A(net->split, kSplitCap);
+  A(net->colpart, (size_t)kColParts * kOut);
   if (e == hipSuccess) e = net->cells.alloc(B * kPix);
   if (e != hipSuccess) {
     delete net;

@@ -73,16 +73,18 @@ def predict(net: mvpb.Surrogate, cells, norm: Normalizer = None, chunk: int = 40
 
 
 def train(net: mvpb.Surrogate, cells, labels, epochs=20, batch=256, lr=1e-3, seed=0, log=None,
-          norm: Normalizer = None):
+          norm: Normalizer = None, lr_end=None):
     """Adam on shuffled mini-batches; every batch is shifted by a random
     circular translation (the bands of a periodic cell are invariant to it).
-    With norm the network is fitted to the standardised targets."""
+    With norm the network is fitted to the standardised targets.  With lr_end
+    the step size follows a cosine from lr down to lr_end over the epochs."""
     if norm is not None:
         labels = norm.encode(labels)
     rng = np.random.default_rng(seed)
     n = cells.shape[0]
     losses = []
     for ep in range(epochs):
+        lr_ep = lr if lr_end is None else lr_end + 0.5 * (lr - lr_end) * (1.0 + np.cos(np.pi * ep / max(1, epochs)))
         order = rng.permutation(n)
         tot = 0.0
         nb = 0
@@ -90,7 +92,7 @@ def train(net: mvpb.Surrogate, cells, labels, epochs=20, batch=256, lr=1e-3, see
             idx = order[b0:b0 + batch]
             sy, sx = rng.integers(0, 32, 2)
             x = np.roll(cells[idx], (int(sy), int(sx)), axis=(1, 2))
-            tot += net.train_step(x, labels[idx], lr)
+            tot += net.train_step(x, labels[idx], lr_ep)
             nb += 1
         losses.append(tot / max(nb, 1))
         if log:
