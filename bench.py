@@ -655,6 +655,17 @@ def main():
 
     om_dev = mvpb.DeviceBuffer(8 * Q.shape[0] * nb)   # outputs stay in HBM
 
+    # launch shape of the eigensolve for this operator size, by the library's autotuner
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "tuning.json")
+        tplan = dcell.plan(M)
+        tune_ms = tplan.autotune(Q, nb, cache)
+        tplan.close()
+        with open(cache) as fh:
+            tune_entry = [json.loads(line.strip().rstrip(",")) for line in fh if '"device"' in line]
+    progress("autotuned launch shape:", tune_entry)
+
     def step():
         plan = dcell.plan(M)
         plan.solve_device(Q, nb, om_dev.value)
@@ -739,6 +750,7 @@ def main():
         "roofline": roof,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof_all.items() if v[1]},
         "paper_reference": PAPER_NUMBERS,
+        "autotune": {"ms_per_solve_call": tune_ms, "entries": tune_entry},
     }
     if variants:
         out["variants"] = variants

@@ -313,6 +313,32 @@ int mvpb_kpath_square(int n_k, double *Q);
  * MVPB_E_INVALID. */
 int mvpb_kpath(const double lattice[4], const char *path, int n_k, double *Q);
 
+/* Autotuning of the eigensolve's launch shape (per context and size class
+ * of the operator order, n rounded up to a multiple of 128): the number of
+ * independent stage-1 parts (streams), the number of consecutive
+ * bulge-chasing sweeps dealt to one workgroup's wavefronts and the most
+ * workgroups per item of the bulge chasing.  mvpb_autotune times the solve
+ * of the plan's n_k points (Q as for mvpb_solve) under candidate shapes
+ * (coordinate search from the defaults, median of three replays of the
+ * captured launch sequence each, HIP events on the context stream), keeps
+ * the fastest for this context and, if cache_path is not NULL, merges it
+ * into that JSON file (one entry per device name and size class).
+ * *best_ms (nullable) receives its time.  The shapes change the schedule,
+ * not the arithmetic: results are bitwise those of the defaults.
+ * mvpb_ctx_load_tuning applies the file's entries for this context's device
+ * (*n_loaded, nullable: how many); MVPB_E_INVALID for a missing file or a
+ * malformed entry. */
+int mvpb_autotune(mvpb_plan plan, int n_k, const double *Q, int n_bands, const char *cache_path,
+                  double *best_ms);
+int mvpb_ctx_load_tuning(mvpb_ctx ctx, const char *path, int *n_loaded);
+
+/* Polls of a bounded hand-over wait of the bulge chasing before the point
+ * gives up (its frequencies NaN, MVPB_E_DEVICE from host-pointer solves);
+ * 0 restores the default (2^24).  The waits are bounded so that every
+ * kernel exits even if a launch is not resident as planned; a small limit
+ * forces the give-up path (used to test it). */
+int mvpb_ctx_set_wait_limit(mvpb_ctx ctx, long long spins);
+
 /* Plain device-to-device copy of `bytes` bytes (a multiple of 16, buffers
  * 16-byte aligned and not overlapping) by one kernel (copy16) on the context
  * stream; returns when it has finished.  It reads and writes each byte once,

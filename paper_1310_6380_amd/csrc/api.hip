@@ -134,17 +134,19 @@ struct DevBuf {
   T *as() const { return reinterpret_cast<T *>(p); }
 };
 
-// Side streams of a context, and the number of independent parts stage 1 of
-// a solve is split into (one stream each; MVPB_STAGE1_PARTS overrides it).
+// Side streams of a context (stage 1 of a solve runs in up to MAX_SIDE + 1
+// independent parts, one stream each).
 constexpr int MAX_SIDE = 3;
-static int stage1_parts() {
-  static const int v = [] {
-    const char *e = getenv("MVPB_STAGE1_PARTS");
-    const int k = e ? atoi(e) : 0;
-    return (k >= 1 && k <= MAX_SIDE + 1) ? k : 2;
-  }();
-  return v;
-}
+
+// Launch shape of the eigensolve for one size class of operators (chosen by
+// mvpb_autotune or loaded from its cache; defaults otherwise).
+struct TuneParams {
+  int parts = 2;    // stage-1 parts (streams)
+  int group = 0;    // bulge chasing: sweeps per workgroup group (0: 8)
+  int wg_max = 0;   // bulge chasing: most workgroups per item (0: 4)
+};
+// Size class of an operator of order n (the key of the tuning table).
+static int size_class(int n) { return (n + 127) / 128; }
 
 struct mvpb_ctx_s {
   int device = 0;
@@ -174,6 +176,8 @@ struct mvpb_ctx_s {
   std::map<std::string, GraphEntry> graphs;
   unsigned long long graph_clock = 0;
   std::vector<EigItem> host_items;                // staging of the item table (kept alive for async copies)
+  std::map<int, TuneParams> tune;                 // launch shapes by size class
+  long long spin_limit = 0;                       // bounded-wait polls of the bulge chasing (0: default)
   Profiler prof;
   int children = 0;     // live cells and plans
   bool closing = false; // mvpb_ctx_destroy called while children were alive
@@ -314,9 +318,13 @@ extern "C" int mvpb_ctx_create(int device, void *hip_stream, size_t workspace_ca
     e = hipStreamCreateWithFlags(&c->side[q], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[q], hipEventDisableTiming);
   }
+  // the running error estimate every eigensolve launch sequence updates
+  if (e == hipSuccess) e = c->accbuf.reserve(sizeof(double));
+  if (e == hipSuccess) e = hipMemsetAsync(c->accbuf.p, 0, sizeof(double), c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     ctx_free(c);
-    return set_err(MVPB_E_DEVICE, "side stream: %s", hipGetErrorString(e));
+    return set_err(MVPB_E_DEVICE, "context set-up: %s", hipGetErrorString(e));
   }
   *out = c;
   return MVPB_OK;
@@ -1482,13 +1490,18 @@ constexpr size_t MAX_GRAPHS = 16;
 // order 2N of every item in table order (which fixes the workspace carving,
 // the stage-1 parts' size ranges and the grids), the bands, the reduction
 // precision and the number of stage-1 parts.
-static std::string launch_signature(const std::vector<Job> &jobs, int nb, bool fp32, int parts) {
+static std::string launch_signature(const std::vector<Job> &jobs, int nb, bool fp32, int parts,
+                                    const Stage2Shape &sh) {
   std::string k;
-  k.reserve(16 + 4 * jobs.size());
+  k.reserve(32 + 8 * jobs.size());
   auto put = [&](int v) { k.append(reinterpret_cast<const char *>(&v), sizeof v); };
   put(nb);
   put(fp32 ? 1 : 0);
   put(parts);
+  put(sh.group);
+  put(sh.wg_max);
+  put((int)(sh.spin_limit & 0x7fffffff));
+  put((int)(sh.spin_limit >> 31));
   put((int)jobs.size());
   for (const Job &j : jobs) {
     put(j.plan->n);
@@ -1504,6 +1517,9 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   hipStream_t st = ctx->stream;
   const int n_items = (int)jobs.size();
   if (n_items == 0) return MVPB_OK;
+  // the sequence ends with a write of the running error estimate
+  if (!ctx->accbuf.p || ctx->accbuf.bytes < sizeof(double))
+    return set_err(MVPB_E_DEVICE, "context has no error-estimate buffer");
   size_t total = 0;
   int n_max = 0, n_min = 1 << 30;
   bool any_iso = false, any_general = false;
@@ -1516,6 +1532,17 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     n_min = std::min(n_min, n);
   }
   const size_t ctl_off = total;   // bulge-chasing launch control words after the items
+  // launch shape of this size class
+  TuneParams tp;
+  {
+    auto f = ctx->tune.find(size_class(n_max));
+    if (f != ctx->tune.end()) tp = f->second;
+  }
+  const int parts_wanted = std::max(1, std::min(tp.parts, MAX_SIDE + 1));
+  Stage2Shape sh;
+  sh.group = tp.group;
+  sh.wg_max = tp.wg_max;
+  sh.spin_limit = ctx->spin_limit;
   total += ctl_bytes(n_items);
   if (ctx->cap && total > ctx->cap)
     return set_err(MVPB_E_NOMEM, "workspace %zu bytes exceeds the cap of %zu bytes", total, ctx->cap);
@@ -1566,7 +1593,7 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     if (e == hipSuccess && any_general) e = launch_form_operator_general(d_items, n_items, n_max, fp32, st);
     // stage 1 in independent parts of the items, one per stream
     ItemPart parts[MAX_SIDE + 1];
-    const int n_parts = std::max(1, std::min(stage1_parts(), n_items));
+    const int n_parts = std::max(1, std::min(parts_wanted, n_items));
     for (int q = 0; q < n_parts; ++q) {
       const int i0 = (int)((long long)n_items * q / n_parts), i1 = (int)((long long)n_items * (q + 1) / n_parts);
       ItemPart &pt = parts[q];
@@ -1590,14 +1617,14 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
       if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->ev_join[q - 1], 0);
     }
     int *ctl = reinterpret_cast<int *>(ctx->ws.as<char>() + ctl_off);
-    if (e == hipSuccess) e = launch_stage2(d_items, n_items, n_max, fp32, ctl, st);
+    if (e == hipSuccess) e = launch_stage2(d_items, n_items, n_max, fp32, ctl, sh, st);
     if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, n_max, nb, st);
     if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_min, n_max, nb, fp32, st);
     if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, n_max, nb, fp32, st);
     return e;
   };
   if (use_graph) {
-    const std::string graph_key = launch_signature(jobs, nb, fp32, stage1_parts());
+    const std::string graph_key = launch_signature(jobs, nb, fp32, parts_wanted, sh);
     auto found = ctx->graphs.find(graph_key);
     hipGraphExec_t exec = nullptr;
     if (found == ctx->graphs.end()) {
@@ -1995,6 +2022,196 @@ extern "C" int mvpb_ctx_last_accuracy(mvpb_ctx ctx, double *estimate) {
   if (rc) return rc;
   if (!estimate) return set_err(MVPB_E_INVALID, "NULL argument");
   *estimate = ctx->last_acc;
+  return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning of the eigensolve's launch shape
+// ---------------------------------------------------------------------------
+static std::string device_key(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string k = std::string(prop.gcnArchName) + " " + prop.name;
+  for (char &c : k)
+    if (c == '"' || c == '\\' || c == '\n') c = ' ';
+  return k;
+}
+
+// Number after "key": in line (NAN if absent).
+static double json_number(const std::string &line, const char *key) {
+  const std::string pat = std::string("\"") + key + "\":";
+  const size_t at = line.find(pat);
+  if (at == std::string::npos) return NAN;
+  return strtod(line.c_str() + at + pat.size(), nullptr);
+}
+
+static std::string json_string(const std::string &line, const char *key) {
+  const std::string pat = std::string("\"") + key + "\": \"";
+  const size_t at = line.find(pat);
+  if (at == std::string::npos) return "";
+  const size_t b = at + pat.size(), e = line.find('"', b);
+  return e == std::string::npos ? "" : line.substr(b, e - b);
+}
+
+// Entries of a tuning cache: one JSON object per line inside "entries".
+static std::vector<std::string> read_entries(const char *path) {
+  std::vector<std::string> out;
+  FILE *f = fopen(path, "r");
+  if (!f) return out;
+  char buf[1024];
+  while (fgets(buf, sizeof buf, f)) {
+    std::string line(buf);
+    if (line.find("\"device\"") != std::string::npos) {
+      while (!line.empty() && (line.back() == '\n' || line.back() == ',' || line.back() == ' ')) line.pop_back();
+      out.push_back(line);
+    }
+  }
+  fclose(f);
+  return out;
+}
+
+extern "C" int mvpb_ctx_load_tuning(mvpb_ctx ctx, const char *path, int *n_loaded) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!path) return set_err(MVPB_E_INVALID, "NULL path");
+  FILE *f = fopen(path, "r");
+  if (!f) return set_err(MVPB_E_INVALID, "cannot open %s", path);
+  fclose(f);
+  const std::string dev = device_key(ctx->device);
+  int n = 0;
+  for (const std::string &line : read_entries(path)) {
+    if (json_string(line, "device") != dev) continue;
+    const double cls = json_number(line, "n_class"), parts = json_number(line, "parts"),
+                 group = json_number(line, "hb2st_group"), wg = json_number(line, "hb2st_wg");
+    if (!(cls >= 1) || !(parts >= 1 && parts <= MAX_SIDE + 1) || !(group >= 0 && group <= 8) || !(wg >= 0 && wg <= 4))
+      return set_err(MVPB_E_INVALID, "%s: malformed tuning entry", path);
+    TuneParams tp;
+    tp.parts = (int)parts;
+    tp.group = (int)group;
+    tp.wg_max = (int)wg;
+    ctx->tune[(int)cls] = tp;
+    ++n;
+  }
+  if (n_loaded) *n_loaded = n;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_ctx_set_wait_limit(mvpb_ctx ctx, long long spins) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (spins < 0) return set_err(MVPB_E_INVALID, "spins must be >= 0");
+  ctx->spin_limit = spins;
+  return MVPB_OK;
+}
+
+extern "C" int mvpb_autotune(mvpb_plan p, int n_k, const double *Q, int n_bands, const char *cache_path,
+                             double *best_ms) {
+  if (!p || !Q) return set_err(MVPB_E_INVALID, "NULL argument");
+  if (n_k < 1) return set_err(MVPB_E_INVALID, "n_k must be positive");
+  if (n_bands < 1 || n_bands > p->n || n_bands > RR_MAX_BANDS)
+    return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, min(n_u, %d)]", n_bands, RR_MAX_BANDS);
+  const int qd = p->qdim;
+  if (!q_ok(Q, qd * n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
+  mvpb_ctx ctx = p->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  ProfBind pb(nullptr);
+  hipStream_t st = ctx->stream;
+  const bool fp32 = (p->prec & MVPB_PREC_EIG_FP32_RR64) != 0;
+  const size_t need = solve_bytes(n_k, item_bytes(p->n, n_bands, fp32));
+  if (ctx->cap && need > ctx->cap)
+    return set_err(MVPB_E_NOMEM, "the %d points need %zu bytes of workspace, cap is %zu", n_k, need, ctx->cap);
+  std::vector<Job> jobs(n_k);
+  for (int t = 0; t < n_k; ++t) {
+    const double *q = Q + (size_t)qd * t;
+    jobs[t] = Job{p, q[0], q[1], qd == 3 ? q[2] : 0.0, t};
+  }
+  DevBuf om(&ctx->pool);
+  HIP_TRY(om.alloc(sizeof(double) * (size_t)n_k * n_bands));
+  int rc0 = acc_begin(ctx);
+  if (rc0) return rc0;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int cls = size_class(p->n);
+  const auto saved = ctx->tune;
+  // median of three timed runs of the captured launch sequence (the first
+  // run of a shape captures it)
+  auto trial = [&](const TuneParams &tp, double *ms) -> int {
+    ctx->tune[cls] = tp;
+    int rc = run_items(ctx, jobs, n_bands, om.as<double>(), nullptr, true);
+    if (rc) return rc;
+    double t[3];
+    for (int r = 0; r < 3; ++r) {
+      HIP_TRY(hipEventRecord(e0, st));
+      rc = run_items(ctx, jobs, n_bands, om.as<double>(), nullptr, true);
+      if (rc) return rc;
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float f = 0.f;
+      HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+      t[r] = f;
+    }
+    std::sort(t, t + 3);
+    *ms = t[1];
+    return MVPB_OK;
+  };
+  // coordinate search from the defaults: stage-1 parts, then the sweep
+  // grouping, then the workgroups per item of the bulge chasing
+  TuneParams best;
+  double best_t = 0.0;
+  int rc = trial(best, &best_t);
+  const int parts_c[] = {1, 3, 4}, group_c[] = {1, 2, 4}, wg_c[] = {1, 2};
+  for (int v : parts_c) {
+    if (rc) break;
+    TuneParams tp = best;
+    tp.parts = v;
+    double t = 0.0;
+    rc = trial(tp, &t);
+    if (!rc && t < best_t) best = tp, best_t = t;
+  }
+  for (int v : group_c) {
+    if (rc) break;
+    TuneParams tp = best;
+    tp.group = v;
+    double t = 0.0;
+    rc = trial(tp, &t);
+    if (!rc && t < best_t) best = tp, best_t = t;
+  }
+  for (int v : wg_c) {
+    if (rc) break;
+    TuneParams tp = best;
+    tp.wg_max = v;
+    double t = 0.0;
+    rc = trial(tp, &t);
+    if (!rc && t < best_t) best = tp, best_t = t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    ctx->tune = saved;
+    return rc;
+  }
+  ctx->tune[cls] = best;
+  if (best_ms) *best_ms = best_t;
+  if (cache_path) {
+    // merge: every entry of the file except this device's entry for this class
+    const std::string dev = device_key(ctx->device);
+    std::vector<std::string> keep;
+    for (const std::string &line : read_entries(cache_path))
+      if (!(json_string(line, "device") == dev && (int)json_number(line, "n_class") == cls)) keep.push_back(line);
+    char mine[512];
+    snprintf(mine, sizeof mine,
+             "{\"device\": \"%s\", \"n_class\": %d, \"n\": %d, \"n_bands\": %d, \"items\": %d, "
+             "\"parts\": %d, \"hb2st_group\": %d, \"hb2st_wg\": %d, \"ms\": %.4f}",
+             dev.c_str(), cls, p->n, n_bands, n_k, best.parts, best.group, best.wg_max, best_t);
+    keep.push_back(mine);
+    FILE *f = fopen(cache_path, "w");
+    if (!f) return set_err(MVPB_E_INVALID, "cannot write %s", cache_path);
+    fprintf(f, "{\"mvpb_tuning\": 1, \"entries\": [\n");
+    for (size_t i = 0; i < keep.size(); ++i) fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+    fprintf(f, "]}\n");
+    fclose(f);
+  }
   return MVPB_OK;
 }
 

@@ -823,7 +823,6 @@ MVPB_DEV cx<R> row16_sum_c(cx<R> v) {
 
 static_assert(HB == 16, "the lane layout of the bulge-chasing kernel assumes HB = 16");
 constexpr int CH_WAVES = 8;
-constexpr long long CH_SPIN_LIMIT = 1ll << 24;
 // workgroups per item of the bulge chasing (more than one only while every
 // workgroup of the launch can be resident at once, one per CU)
 constexpr int HB2ST_MAX_WG = 4;
@@ -894,7 +893,7 @@ MVPB_DEV int xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1
 // invalidates its L1 before reading the producer's blocks.
 template <typename R>
 __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict__ items, int n_items, int P, int G,
-                                                      int *ctl) {
+                                                      int *ctl, long long spin_limit) {
   typedef cx<R> C;
   __shared__ int prog[CH_WAVES];
   __shared__ int abort_s;
@@ -911,7 +910,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
         item = atomicAdd(ctl + HB2ST_CTL_ITEM, 1);
         __hip_atomic_store(entry, item, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
-        for (long long spins = 0; spins < CH_SPIN_LIMIT; ++spins) {
+        for (long long spins = 0; spins < spin_limit; ++spins) {
           item = __hip_atomic_load(entry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (item >= 0) break;
           __builtin_amdgcn_s_sleep(2);
@@ -961,7 +960,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
               aborted = true;
               break;
             }
-            if (++spins > CH_SPIN_LIMIT) {
+            if (++spins > spin_limit) {
               aborted = true;
               break;
             }
@@ -974,7 +973,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
               aborted = true;
               break;
             }
-            if (++spins > CH_SPIN_LIMIT) {
+            if (++spins > spin_limit) {
               aborted = true;
               break;
             }
@@ -1494,17 +1493,6 @@ static int device_cus() {
   return g_cu_count[dev];
 }
 
-// Sweeps per group of the bulge-chasing layout (a divisor of CH_WAVES);
-// MVPB_HB2ST_GROUP overrides it for tuning.
-static int hb2st_group() {
-  static const int g = [] {
-    const char *e = getenv("MVPB_HB2ST_GROUP");
-    const int v = e ? atoi(e) : 0;
-    return (v >= 1 && v <= CH_WAVES && CH_WAVES % v == 0) ? v : CH_WAVES;
-  }();
-  return g;
-}
-
 // Stage 1 of every part, step by step: the parts are independent sets of
 // items on their own streams, so that one part's latency-bound panel overlaps
 // the other's bandwidth-bound trailing update.
@@ -1555,10 +1543,14 @@ hipError_t launch_stage1(const ItemPart *parts, int n_parts, bool fp32) {
 // hb2st_ctl_ints(n_items) ints.  Every workgroup of the launch must be
 // resident at once when P > 1, so nothing else may run beside it.
 template <typename R>
-static hipError_t launch_stage2_t(const EigItem *items, int n_items, int n_max, int *ctl, hipStream_t st) {
+static hipError_t launch_stage2_t(const EigItem *items, int n_items, int n_max, int *ctl, const Stage2Shape &sh,
+                                  hipStream_t st) {
   {
     const int nmax_items_xcd = (n_items + 7) / 8;
-    const int P = std::max(1, std::min(HB2ST_MAX_WG, device_cus() / (8 * nmax_items_xcd)));
+    const int wg_max = sh.wg_max >= 1 ? std::min(sh.wg_max, HB2ST_MAX_WG) : HB2ST_MAX_WG;
+    const int P = std::max(1, std::min(wg_max, device_cus() / (8 * nmax_items_xcd)));
+    const int G = (sh.group >= 1 && sh.group <= CH_WAVES && CH_WAVES % sh.group == 0) ? sh.group : CH_WAVES;
+    const long long spin_limit = sh.spin_limit > 0 ? sh.spin_limit : (1ll << 24);
     const int chunks = (n_max - 1 + HB - 1) / HB;
     {
       ProfScope ps(K_HB2ST_IO, st);
@@ -1567,8 +1559,8 @@ static hipError_t launch_stage2_t(const EigItem *items, int n_items, int n_max, 
     }
     {
       ProfScope ps(K_HB2ST, st);
-      hipLaunchKernelGGL((hb2st<R>), dim3(8 * nmax_items_xcd * P), dim3(CH_WAVES * 64), 0, st, items, n_items, P,
-                         hb2st_group(), ctl);
+      hipLaunchKernelGGL((hb2st<R>), dim3(8 * nmax_items_xcd * P), dim3(CH_WAVES * 64), 0, st, items, n_items, P, G,
+                         ctl, spin_limit);
     }
     {
       ProfScope ps(K_HB2ST_IO, st);
@@ -1578,9 +1570,10 @@ static hipError_t launch_stage2_t(const EigItem *items, int n_items, int n_max, 
   return hipGetLastError();
 }
 
-hipError_t launch_stage2(const EigItem *items, int n_items, int n_max, bool fp32, int *ctl, hipStream_t st) {
-  return fp32 ? launch_stage2_t<float>(items, n_items, n_max, ctl, st)
-              : launch_stage2_t<double>(items, n_items, n_max, ctl, st);
+hipError_t launch_stage2(const EigItem *items, int n_items, int n_max, bool fp32, int *ctl, const Stage2Shape &sh,
+                         hipStream_t st) {
+  return fp32 ? launch_stage2_t<float>(items, n_items, n_max, ctl, sh, st)
+              : launch_stage2_t<double>(items, n_items, n_max, ctl, sh, st);
 }
 
 // Eigenvector columns per back-transform workgroup: bounded by the LDS

@@ -166,9 +166,19 @@ struct ItemPart {
 // interleaved step by step on their own streams.
 hipError_t launch_stage1(const ItemPart *parts, int n_parts, bool fp32);
 // Band to tridiagonal (stage 2, bulge chasing) and d, e of all items; ctl
-// points to hb2st_ctl_ints(n_items) ints of device memory.
+// points to hb2st_ctl_ints(n_items) ints of device memory.  Launch shape:
+// group = consecutive sweeps dealt to one workgroup's wavefronts (a divisor
+// of 8; 0: 8), wg_max = most workgroups per item (0: 4; fewer when the
+// launch would not be resident at once), spin_limit = polls of a bounded
+// hand-over wait before the item gives up (0: 2^24).
+struct Stage2Shape {
+  int group = 0;
+  int wg_max = 0;
+  long long spin_limit = 0;
+};
 size_t hb2st_ctl_ints(int n_items);
-hipError_t launch_stage2(const EigItem *items, int n_items, int n_max, bool fp32, int *ctl, hipStream_t st);
+hipError_t launch_stage2(const EigItem *items, int n_items, int n_max, bool fp32, int *ctl, const Stage2Shape &sh,
+                         hipStream_t st);
 // Eigenvectors of C(k) from those of the tridiagonal matrix (X -> Y).
 hipError_t launch_backtransform(const EigItem *items, int n_items, int n_min, int n_max, int nb, bool fp32,
                                 hipStream_t st);

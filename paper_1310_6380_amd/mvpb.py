@@ -53,7 +53,7 @@ EXPORTS = [
     "mvpb_ctx_profile_mask", "mvpb_cell_create_polygons", "mvpb_stress_modes", "mvpb_kpath",
     "mvpb_sur_save", "mvpb_sur_load", "mvpb_structure_factors_noalloc", "mvpb_ctx_set_accuracy",
     "mvpb_ctx_last_accuracy", "mvpb_cell_create_voxels", "mvpb_plan_create3", "mvpb_structure_factors_general",
-    "mvpb_band_sensitivities",
+    "mvpb_band_sensitivities", "mvpb_autotune", "mvpb_ctx_load_tuning", "mvpb_ctx_set_wait_limit",
 ]
 N_KERNELS = 15
 
@@ -91,6 +91,9 @@ def load(path: str = LIB_PATH):
     lib.mvpb_plan_create3.argtypes = [P, I, I, I, I, ctypes.POINTER(P)]
     lib.mvpb_structure_factors_general.argtypes = [P, I, I, I, D]
     lib.mvpb_band_sensitivities.argtypes = [P, I, D, I, P, P, P, ctypes.c_uint]
+    lib.mvpb_autotune.argtypes = [P, I, D, I, ctypes.c_char_p, D]
+    lib.mvpb_ctx_load_tuning.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I)]
+    lib.mvpb_ctx_set_wait_limit.argtypes = [P, ctypes.c_longlong]
     lib.mvpb_stress_modes.argtypes = [P, I, D, I, D, D, ctypes.c_uint]
     lib.mvpb_plan_create.argtypes = [P, I, I, I, ctypes.POINTER(P)]
     lib.mvpb_plan_dofs.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
@@ -252,6 +255,16 @@ class Context:
         """Bar on the estimated relative frequency error of solves with the
         FP32 reduction (0 turns the check off)."""
         _check(load().mvpb_ctx_set_accuracy(self.h, float(tol)))
+
+    def load_tuning(self, path: str) -> int:
+        """Apply the launch shapes a tuning cache holds for this device; returns how many."""
+        n = ctypes.c_int()
+        _check(load().mvpb_ctx_load_tuning(self.h, os.fsencode(path), ctypes.byref(n)))
+        return n.value
+
+    def set_wait_limit(self, spins: int):
+        """Polls of a bulge-chasing hand-over wait before a point gives up (0: default)."""
+        _check(load().mvpb_ctx_set_wait_limit(self.h, int(spins)))
 
     def last_accuracy(self) -> float:
         """Largest error estimate of the refined bands of the last synchronous solve."""
@@ -500,6 +513,15 @@ class Plan:
         _check(lib.mvpb_stress_modes(self.h, nk, _dptr(Q), nb, U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0))
         return S
+
+    def autotune(self, Q, n_bands: int, cache_path: str = None) -> float:
+        """Pick the fastest launch shape for this plan's operator size (kept by
+        the context, merged into cache_path if given); returns its time in ms."""
+        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.float64).reshape(-1, self.qdim))
+        ms = ctypes.c_double()
+        _check(load().mvpb_autotune(self.h, Q.shape[0], _dptr(Q), n_bands,
+                                    os.fsencode(cache_path) if cache_path else None, ctypes.byref(ms)))
+        return ms.value
 
     def sensitivities(self, Q, omega, U, grid_shape):
         """d lambda / d w_f of every pixel / voxel: [n_k, n_bands, nf, *grid_shape]

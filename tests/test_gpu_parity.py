@@ -392,3 +392,54 @@ def test_repeated_solves_replay_identically(ctx):
     oa3 = pa.solve(Q, 6)
     ctx.profile(False)
     assert np.array_equal(oa1, oa3)
+
+
+# ----------------------------------------------------------------- launch shapes
+
+def test_autotune_caches_shapes_and_keeps_results(ctx, tmp_path):
+    """The autotuner times candidate launch shapes of the eigensolve, keeps the
+    fastest, writes a cache that a new context loads, and the shapes change
+    the schedule only: frequencies are bitwise those of the defaults."""
+    from paper_1310_6380_amd import mvpb
+    cell = _rand_cell(16, 16, 3, 61)
+    Q = kpath_gxmg(24)
+    ref = ctx.cell(cell.phase, cell.props).plan(6).solve(Q, 10)
+    path = str(tmp_path / "tuning.json")
+    c2 = mvpb.Context(0)
+    try:
+        plan = c2.cell(cell.phase, cell.props).plan(6)
+        ms = plan.autotune(Q, 10, path)
+        _say("autotuned", ms, "ms", open(path).read())
+        assert ms > 0 and np.array_equal(plan.solve(Q, 10), ref)
+        plan.close()
+    finally:
+        c2.close()
+    c3 = mvpb.Context(0)
+    try:
+        assert c3.load_tuning(path) == 1
+        assert np.array_equal(c3.cell(cell.phase, cell.props).plan(6).solve(Q, 10), ref)
+    finally:
+        c3.close()
+
+
+def test_bulge_chasing_give_up_path(ctx):
+    """A bounded hand-over wait of one poll makes the bulge chasing give up:
+    every kernel still exits, the points come back as NaN and the call returns
+    MVPB_E_DEVICE; the default limit then solves the same plan correctly."""
+    from paper_1310_6380_amd import mvpb
+    c = config1()
+    cell = c["cell"]
+    c2 = mvpb.Context(0)
+    try:
+        plan = c2.cell(cell.phase, cell.props).plan(c["M"])
+        Q = c["Q"][:8]
+        c2.set_wait_limit(1)
+        with pytest.raises(mvpb.MvpbError) as ei:
+            plan.solve(Q, c["n_bands"])
+        assert ei.value.code == mvpb.E_DEVICE
+        c2.set_wait_limit(0)
+        om = plan.solve(Q, c["n_bands"])
+        ref, _ = mo.bands(cell.phase, cell.props, cell.lattice, c["M"], c["M"], Q[[0, 5]], c["n_bands"])
+        assert band_error(om[[0, 5]], ref) <= TOL64
+    finally:
+        c2.close()
