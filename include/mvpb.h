@@ -210,10 +210,13 @@ int mvpb_plan_destroy(mvpb_plan plan);
  *   component c in the plane-wave order I = (alpha+M1)(2M2+1)+(beta+M2)
  *   (voxel cells: I = ((alpha+M1)(2M2+1)+(beta+M2))(2M3+1)+(gamma+M3));
  *   normalised to U^H Omega U = 1 with the largest-modulus entry real > 0.
- * 1 <= n_bands <= min(n_u, 64) (the FP64 Rayleigh-Ritz block is held in
- * on-chip memory).  Q, omega and U are host pointers unless
- * MVPB_F_DEVICE_PTRS is set (then omega and U are device pointers; Q stays
- * on the host).  If the device could not finish a point (the reduction to
+ * 1 <= n_bands <= min(n_u, 256) for FP64 plans: up to 64 bands the
+ * frequencies and vectors are refined by an FP64 Rayleigh-Ritz step (its
+ * block is held in on-chip memory), beyond that they come straight from
+ * the FP64 tridiagonal eigenpairs and the back-transform.  Plans with
+ * MVPB_PREC_EIG_FP32_RR64 take 1 <= n_bands <= min(n_u, 64).  Q, omega and
+ * U are host pointers unless MVPB_F_DEVICE_PTRS is set (then omega and U
+ * are device pointers; Q stays on the host).  If the device could not finish a point (the reduction to
  * tridiagonal form gave up waiting on a hand-over), its frequencies are NaN;
  * with host pointers the call then returns MVPB_E_DEVICE. */
 int mvpb_solve(mvpb_plan plan, int n_k, const double *Q, int n_bands, double *omega, double *U,

@@ -1336,8 +1336,9 @@ static void item_layout(int n, int nb, bool fp32, size_t *sz, int *count) {
   sz[k++] = sizeof(double) * nb;                 // omega
   sz[k++] = sizeof(cd) * (size_t)n * nb;         // Y
   sz[k++] = sizeof(cd) * (size_t)n * nb;         // Z
-  sz[k++] = sizeof(cd) * ((size_t)(n + 63) / 64) * 2 * nb * nb;  // Gp
-  sz[k++] = sizeof(cd) * (size_t)nb * nb;        // Lr
+  const bool rr = nb <= RR_MAX_BANDS;            // the Rayleigh-Ritz step runs
+  sz[k++] = rr ? sizeof(cd) * ((size_t)(n + 63) / 64) * 2 * nb * nb : 0;  // Gp
+  sz[k++] = rr ? sizeof(cd) * (size_t)nb * nb : 0;                      // Lr
   sz[k++] = fp32 ? sizeof(cf) * (size_t)n * nb : 0;  // Yb (FP32 path only)
   sz[k++] = sizeof(double);                      // acc
   *count = k;
@@ -1620,7 +1621,9 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     if (e == hipSuccess) e = launch_stage2(d_items, n_items, n_max, fp32, ctl, sh, st);
     if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, n_max, nb, st);
     if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_min, n_max, nb, fp32, st);
-    if (e == hipSuccess) e = launch_rayleigh_ritz(d_items, n_items, n_max, nb, fp32, st);
+    if (e == hipSuccess)
+      e = nb <= RR_MAX_BANDS ? launch_rayleigh_ritz(d_items, n_items, n_max, nb, fp32, st)
+                             : launch_tridiag_results(d_items, n_items, nb, st);
     return e;
   };
   if (use_graph) {
@@ -1672,8 +1675,9 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
     // table per component c: [A: n_items][B: n_items][C: n_items]
     for (int c = 0; c < dmax; ++c) {
       for (int i = 0; i < n_items; ++i) hp.push_back(jobs[i].plan->linvR.p);
-      for (int i = 0; i < n_items; ++i)
-        hp.push_back(items[i].Z + (size_t)std::min(c, jobs[i].plan->n / jobs[i].plan->N - 1) * jobs[i].plan->N);
+      for (int i = 0; i < n_items; ++i)   // refined vectors (Z) or, beyond RR_MAX_BANDS, the back-transformed ones (Y)
+        hp.push_back((nb <= RR_MAX_BANDS ? items[i].Z : items[i].Y) +
+                     (size_t)std::min(c, jobs[i].plan->n / jobs[i].plan->N - 1) * jobs[i].plan->N);
       for (int i = 0; i < n_items; ++i) {
         const Job &jb = jobs[i];
         const int dd = jb.plan->n / jb.plan->N;
@@ -1881,8 +1885,9 @@ extern "C" int mvpb_solve(mvpb_plan p, int n_k, const double *Q, int n_bands, do
   if (!p || !Q || !omega) return set_err(MVPB_E_INVALID, "NULL argument");
   if (n_k < 0) return set_err(MVPB_E_INVALID, "n_k must be non-negative");
   if (n_k == 0) return MVPB_OK;
-  if (n_bands < 1 || n_bands > p->n || n_bands > RR_MAX_BANDS)
-    return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, min(n_u=%d, %d)]", n_bands, p->n, RR_MAX_BANDS);
+  const int bmax = (p->prec & MVPB_PREC_EIG_FP32_RR64) ? RR_MAX_BANDS : MAX_BANDS;
+  if (n_bands < 1 || n_bands > p->n || n_bands > bmax)
+    return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, min(n_u=%d, %d)]", n_bands, p->n, bmax);
   const int qd = p->qdim;
   if (!q_ok(Q, qd * n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
   mvpb_ctx ctx = p->ctx;
@@ -1945,7 +1950,7 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
   if (rc) return rc;
   if (n_plans < 0 || (n_plans > 0 && (!plans || !n_k || !Q || !omega)))
     return set_err(MVPB_E_INVALID, "NULL argument");
-  if (n_bands < 1 || n_bands > RR_MAX_BANDS) return set_err(MVPB_E_INVALID, "n_bands = %d out of range", n_bands);
+  if (n_bands < 1 || n_bands > MAX_BANDS) return set_err(MVPB_E_INVALID, "n_bands = %d out of range", n_bands);
   std::vector<Job> jobs;
   std::vector<size_t> base(n_plans + 1, 0);
   for (int i = 0; i < n_plans; ++i) {
@@ -1954,6 +1959,8 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
     if (plans[i]->n < n_bands) return set_err(MVPB_E_INVALID, "plan %d: n_bands > n_u", i);
     if ((plans[i]->prec & MVPB_PREC_EIG_FP32_RR64) != (plans[0]->prec & MVPB_PREC_EIG_FP32_RR64))
       return set_err(MVPB_E_INVALID, "plan %d: all plans of a batch need the same eigensolver precision", i);
+    if ((plans[i]->prec & MVPB_PREC_EIG_FP32_RR64) && n_bands > RR_MAX_BANDS)
+      return set_err(MVPB_E_INVALID, "the FP32 reduction takes at most %d bands", RR_MAX_BANDS);
     const int qd = plans[i]->qdim;
     if (!q_ok(Q[i], qd * n_k[i])) return set_err(MVPB_E_INVALID, "plan %d: non-finite Bloch vector", i);
     base[i + 1] = base[i] + n_k[i];
@@ -2108,8 +2115,9 @@ extern "C" int mvpb_autotune(mvpb_plan p, int n_k, const double *Q, int n_bands,
                              double *best_ms) {
   if (!p || !Q) return set_err(MVPB_E_INVALID, "NULL argument");
   if (n_k < 1) return set_err(MVPB_E_INVALID, "n_k must be positive");
-  if (n_bands < 1 || n_bands > p->n || n_bands > RR_MAX_BANDS)
-    return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, min(n_u, %d)]", n_bands, RR_MAX_BANDS);
+  const int bmax = (p->prec & MVPB_PREC_EIG_FP32_RR64) ? RR_MAX_BANDS : MAX_BANDS;
+  if (n_bands < 1 || n_bands > p->n || n_bands > bmax)
+    return set_err(MVPB_E_INVALID, "n_bands = %d outside [1, min(n_u, %d)]", n_bands, bmax);
   const int qd = p->qdim;
   if (!q_ok(Q, qd * n_k)) return set_err(MVPB_E_INVALID, "non-finite Bloch vector");
   mvpb_ctx ctx = p->ctx;

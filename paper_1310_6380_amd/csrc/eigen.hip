@@ -125,14 +125,16 @@ __device__ __forceinline__ int sturm_count_minors(const double *__restrict__ dd,
 // still wider than a few ulps of |T|.
 constexpr int BISI_THREADS = 256;
 constexpr int BISI_GROUPS = 4;
+constexpr int BISI_MAX = MAX_BANDS / BISI_GROUPS;   // eigenvalues of one workgroup
+static_assert(BISI_MAX * BISI_GROUPS == MAX_BANDS && BISI_MAX <= BISI_THREADS / 4, "probes per open eigenvalue");
 __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigItem *__restrict__ items) {
   extern __shared__ double shd[];   // dd (n), ee (n), e2p (n + 1)
   __shared__ double red[3 * (BISI_THREADS / 64)];
   __shared__ double xs[BISI_THREADS];
   __shared__ int cnt_s[BISI_THREADS];
-  __shared__ int first_s[BISI_THREADS / 64][RR_MAX_BANDS];
-  __shared__ double lo_s[RR_MAX_BANDS], hi_s[RR_MAX_BANDS];
-  __shared__ int act_s[RR_MAX_BANDS];
+  __shared__ int first_s[BISI_THREADS / 64][BISI_MAX];
+  __shared__ double lo_s[BISI_MAX], hi_s[BISI_MAX];
+  __shared__ int act_s[BISI_MAX];
   __shared__ int nact_s;
   const EigItem it = items[blockIdx.y];
   const int n = it.n, nb_all = it.nb, g0 = blockIdx.x;
@@ -191,7 +193,7 @@ __global__ void __launch_bounds__(BISI_THREADS) tridiag_bisect_item(const EigIte
     __syncthreads();
     const int na = nact_s;
     if (na == 0) break;
-    const int P = BISI_THREADS / na;   // probes per open eigenvalue (>= 16 for nb <= 64)
+    const int P = BISI_THREADS / na;   // probes per open eigenvalue (>= 4 for nb <= MAX_BANDS)
     const int a = tid / P, pq = tid % P;
     if (a < na) {
       const int j = act_s[a];
@@ -1026,6 +1028,22 @@ hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, in
     hipLaunchKernelGGL(rr_product<true>, dim3(nrb, n_items), dim3(256), sizeof(cd) * 2 * 64 * nb, st, items);
     hipLaunchKernelGGL(rr_estimate, dim3(n_items), dim3(64), 0, st, items);
   }
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) tridiag_results(const EigItem *__restrict__ items) {
+  const EigItem &it = items[blockIdx.x];
+  for (int b = threadIdx.x; b < it.nb; b += 256) {
+    const double lam = it.lam_t[b];
+    it.lam[b] = lam;
+    it.omega[b] = sqrt(fmax(lam, 0.0));
+  }
+  if (threadIdx.x == 0) *it.acc = 0.0;
+}
+
+hipError_t launch_tridiag_results(const EigItem *items, int n_items, int nb, hipStream_t st) {
+  (void)nb;
+  hipLaunchKernelGGL(tridiag_results, dim3(n_items), dim3(256), 0, st, items);
   return hipGetLastError();
 }
 

@@ -28,8 +28,14 @@ constexpr int HB = 16;
 constexpr int WB_PAD_COLS = HB;
 // LDS budget of the back-transform's eigenvector block.
 constexpr int BT_LDS_BYTES = 128 * 1024;
-// Largest number of bands per solve (Rayleigh-Ritz block in LDS).
+// Most bands of a solve that ends with the FP64 Rayleigh-Ritz step (its
+// block is held in LDS; the FP32 reduction always needs that step).
 constexpr int RR_MAX_BANDS = 64;
+// Most bands of an FP64 solve: beyond RR_MAX_BANDS the frequencies and
+// vectors come straight from the tridiagonal eigenpairs and the
+// back-transform (the FP64 reduction is backward stable; the refinement is
+// for the FP32 one).
+constexpr int MAX_BANDS = 256;
 
 // One (cell, k) work item of the eigensolve.  All pointers are device memory
 // owned by the solve that built the item table.  Buffers marked (R) hold
@@ -189,5 +195,8 @@ long long refl_total(int n);   // number of stage-2 reflectors of an item of ord
 hipError_t init_kernel_attributes();  // once per device, before the first launch
 hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st);
 hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, int nb, bool check, hipStream_t st);
+// Solves beyond RR_MAX_BANDS (FP64): lambda, omega from the tridiagonal
+// eigenvalues, no estimate (acc = 0); the vectors stay in Y.
+hipError_t launch_tridiag_results(const EigItem *items, int n_items, int nb, hipStream_t st);
 
 }  // namespace mvpb

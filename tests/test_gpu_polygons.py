@@ -156,3 +156,30 @@ def test_polygon_cells_in_batched_solve(ctx):
     for cell, M, Q, om in zip(cells, Ms, Qs, outs):
         ref = cell.plan(M).solve(Q, 8)
         assert np.max(np.abs(om - ref) / np.maximum(np.abs(ref), 1e-300 + np.abs(ref).max() * 1e-12)) <= 1e-9
+
+
+def test_hex_all_242_eigenvalues(ctx):
+    """Sec. 5 computes every eigenvalue of the steel/epoxy cell at M = 5
+    (2N = 242): all 242 bands per k beyond the Rayleigh-Ritz block (the
+    frequencies and vectors straight from the FP64 tridiagonal eigenpairs),
+    against the oracle, the vectors Omega-orthonormal."""
+    c = hex_steel_epoxy(64)
+    M, nb = 5, 242
+    Q = kpath_xgjx(7)
+    _say("hex all eigenvalues, M =", M)
+    plan = ctx.cell_polygons(c.polygons, c.poly_phase, c.props, c.lattice).plan(M)
+    om, U = plan.solve(Q, nb, vectors=True)
+    assert om.shape == (7, 242) and np.all(np.isfinite(om))
+    I = mo.polygon_integral_tables(c.polygons, c.poly_phase, c.n_phases, c.lattice, M, M)
+    ref, _ = mo.bands(None, c.props, c.lattice, M, M, Q, nb, I_p=I)
+    err = band_error(om, ref)
+    _say("  band error", err)
+    assert err <= TOL64, err
+    tabs = mo.phase_sum_tables(I, c.props)
+    mats = mo.assemble(I, c.props, c.lattice, M, M, Q[3], tables=tabs)
+    G = U[3].conj() @ mats["Omega"] @ U[3].T
+    assert np.max(np.abs(G - np.eye(nb))) <= 1e-8
+    # the largest band count with the Rayleigh-Ritz step and the smallest without agree on their bands
+    o64 = plan.solve(Q, 64)
+    o65 = plan.solve(Q, 65)
+    assert band_error(o65[:, :64], o64) <= TOL64
