@@ -96,13 +96,18 @@ def roofline_models(n: int, nb: int):
     }
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, shape):
     """Calibrated HBM bytes per launch of `kernel` from the committed counter
-    summary of this workload, or None when it is missing or was taken on
-    other sources of that kernel."""
+    summary of this workload, or None when it is missing, was taken on other
+    sources of that kernel or on another launch shape (items per launch)."""
     from paper_1310_6380_amd.profile_summary import source_digest
     path = os.path.join(HERE, "profiles", "hbm_traffic_voronoi1132_fp64.md")
     if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        text = fh.read()
+    want = "launch shape: " + ",".join(str(v) for v in shape)
+    if want not in text:
         return None
     with open(path) as fh:
         for line in fh:
@@ -625,12 +630,58 @@ def main():
                     help="k-points timed on the CPU oracle with one thread (0 = skip the CPU baseline)")
     ap.add_argument("--surrogate-full", action="store_true",
                     help="only the surrogate study at full scale: 50 000 GRF cells, 45 000 trained, 5 000 held out")
+    ap.add_argument("--surrogate-kernels", action="store_true",
+                    help="only the surrogate's kernels (for profiling): 30 training steps of 256 seeded GRF cells "
+                         "and 5 inference batches of 4096")
+    ap.add_argument("--shape", default="",
+                    help="fixed launch shape 'parts,group,workgroups' of the headline instead of autotuning it")
+    ap.add_argument("--assembly", action="store_true",
+                    help="only the batched plan build of the 256-cell inclusion workload, twice (for profiling)")
     ap.add_argument("--no-variants", action="store_true", help="only the headline FP64 workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB once with the library's plain copy kernel (counter calibration)")
     args = ap.parse_args()
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
+        return
+    if args.surrogate_kernels:
+        from paper_1310_6380_amd import mvpb
+        from synth import config4_cells
+        ctx = mvpb.Context(0)
+        net = mvpb.Surrogate(ctx, max_batch=4096, precision=1, seed=0)
+        cells = config4_cells(0, 4096)
+        y = np.random.default_rng(0).uniform(0.1, 1.0, (4096, 400)).astype(np.float32)
+        dc = mvpb.DeviceBuffer(cells.size).upload(cells)
+        dy = mvpb.DeviceBuffer(y.nbytes).upload(y)
+        dout = mvpb.DeviceBuffer(y.nbytes)
+        t0 = time.perf_counter()
+        for i in range(30):
+            net.train_step_device(256, dc.value + 1024 * 256 * (i % 16), dy.value + 4 * 400 * 256 * (i % 16))
+        mvpb.device_synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            net.infer_device(4096, dc.value, dout.value)
+        mvpb.device_synchronize()
+        t2 = time.perf_counter()
+        print(json.dumps({"surrogate_kernels": {"train_ms_per_step_256": 1e3 * (t1 - t0) / 30,
+                                                "infer_ms_per_batch_4096": 1e3 * (t2 - t1) / 5}}), flush=True)
+        net.close()
+        ctx.close()
+        return
+    if args.assembly:
+        from paper_1310_6380_amd import mvpb
+        from synth import config2
+        ctx = mvpb.Context(0)
+        cfg = config2()
+        cells = [ctx.cell(c["cell"].phase, c["cell"].props, c["cell"].lattice) for c in cfg["cells"]]
+        Ms = [c["M"] for c in cfg["cells"]]
+        for step in range(2):
+            plans = ctx.plans(cells, Ms)
+            mvpb.device_synchronize()
+            for p in plans:
+                p.close()
+            progress("assembly step", step + 1)
+        ctx.close()
         return
     if args.surrogate_full:
         from paper_1310_6380_amd import mvpb
@@ -656,15 +707,22 @@ def main():
     om_dev = mvpb.DeviceBuffer(8 * Q.shape[0] * nb)   # outputs stay in HBM
 
     # launch shape of the eigensolve for this operator size, by the library's autotuner
-    import tempfile
-    with tempfile.TemporaryDirectory() as td:
-        cache = os.path.join(td, "tuning.json")
-        tplan = dcell.plan(M)
-        tune_ms = tplan.autotune(Q, nb, cache)
-        tplan.close()
-        with open(cache) as fh:
-            tune_entry = [json.loads(line.strip().rstrip(",")) for line in fh if '"device"' in line]
-    progress("autotuned launch shape:", tune_entry)
+    # (or fixed with --shape, e.g. to profile the shape a bench run chose)
+    tune_ms, tune_entry = None, []
+    if args.shape:
+        parts, group, wg = (int(v) for v in args.shape.split(","))
+        ctx.set_launch_shape(n, parts, group, wg)
+    else:
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            cache = os.path.join(td, "tuning.json")
+            tplan = dcell.plan(M)
+            tune_ms = tplan.autotune(Q, nb, cache)
+            tplan.close()
+            with open(cache) as fh:
+                tune_entry = [json.loads(line.strip().rstrip(",")) for line in fh if '"device"' in line]
+    shape = ctx.launch_shape(n)
+    progress("launch shape (parts, group, workgroups):", shape, tune_entry)
 
     def step():
         plan = dcell.plan(M)
@@ -713,7 +771,7 @@ def main():
         roof.update({"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                      "algorithmic_per_launch": per_launch,
                      "algorithmic_unit": "bytes" if unit == "GB/s" else "flops",
-                     "traffic": measured_traffic(name)})
+                     "traffic": measured_traffic(name, shape)})
     omega = om_dev.to_numpy(np.float64, (Q.shape[0], nb))
     variants = {}
     om_mixed = om_batch = cfg2 = om_prec = cfg3 = om_hex = hexcfg = om_h1132 = h1132cfg = stress_out = None
@@ -750,7 +808,7 @@ def main():
         "roofline": roof,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof_all.items() if v[1]},
         "paper_reference": PAPER_NUMBERS,
-        "autotune": {"ms_per_solve_call": tune_ms, "entries": tune_entry},
+        "autotune": {"ms_per_solve_call": tune_ms, "entries": tune_entry, "launch_shape": list(shape)},
     }
     if variants:
         out["variants"] = variants

@@ -323,7 +323,8 @@ int mvpb_kpath(const double lattice[4], const char *path, int n_k, double *Q);
  * workgroups per item of the bulge chasing.  mvpb_autotune times the solve
  * of the plan's n_k points (Q as for mvpb_solve) under candidate shapes
  * (coordinate search from the defaults, median of three replays of the
- * captured launch sequence each, HIP events on the context stream), keeps
+ * captured launch sequence each, HIP events on the context stream; a
+ * candidate replaces the best so far only if it is 2 % faster), keeps
  * the fastest for this context and, if cache_path is not NULL, merges it
  * into that JSON file (one entry per device name and size class).
  * *best_ms (nullable) receives its time.  The shapes change the schedule,
@@ -334,6 +335,11 @@ int mvpb_kpath(const double lattice[4], const char *path, int n_k, double *Q);
 int mvpb_autotune(mvpb_plan plan, int n_k, const double *Q, int n_bands, const char *cache_path,
                   double *best_ms);
 int mvpb_ctx_load_tuning(mvpb_ctx ctx, const char *path, int *n_loaded);
+/* The launch shape of the size class of operator order n, set explicitly
+ * (parts 1..4, group 0 (= 8), 1, 2, 4 or 8, wg_max 0 (= 4) .. 4) or read
+ * back (defaults 2, 0, 0 when the class has none). */
+int mvpb_ctx_set_launch_shape(mvpb_ctx ctx, int n, int parts, int group, int wg_max);
+int mvpb_ctx_get_launch_shape(mvpb_ctx ctx, int n, int *parts, int *group, int *wg_max);
 
 /* Polls of a bounded hand-over wait of the bulge chasing before the point
  * gives up (its frequencies NaN, MVPB_E_DEVICE from host-pointer solves);

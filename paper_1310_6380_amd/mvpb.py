@@ -54,6 +54,7 @@ EXPORTS = [
     "mvpb_sur_save", "mvpb_sur_load", "mvpb_structure_factors_noalloc", "mvpb_ctx_set_accuracy",
     "mvpb_ctx_last_accuracy", "mvpb_cell_create_voxels", "mvpb_plan_create3", "mvpb_structure_factors_general",
     "mvpb_band_sensitivities", "mvpb_autotune", "mvpb_ctx_load_tuning", "mvpb_ctx_set_wait_limit",
+    "mvpb_ctx_set_launch_shape", "mvpb_ctx_get_launch_shape",
 ]
 N_KERNELS = 15
 
@@ -94,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.mvpb_autotune.argtypes = [P, I, D, I, ctypes.c_char_p, D]
     lib.mvpb_ctx_load_tuning.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I)]
     lib.mvpb_ctx_set_wait_limit.argtypes = [P, ctypes.c_longlong]
+    lib.mvpb_ctx_set_launch_shape.argtypes = [P, I, I, I, I]
+    lib.mvpb_ctx_get_launch_shape.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.mvpb_stress_modes.argtypes = [P, I, D, I, D, D, ctypes.c_uint]
     lib.mvpb_plan_create.argtypes = [P, I, I, I, ctypes.POINTER(P)]
     lib.mvpb_plan_dofs.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
@@ -261,6 +264,16 @@ class Context:
         n = ctypes.c_int()
         _check(load().mvpb_ctx_load_tuning(self.h, os.fsencode(path), ctypes.byref(n)))
         return n.value
+
+    def set_launch_shape(self, n: int, parts: int, group: int = 0, wg_max: int = 0):
+        """Launch shape of the eigensolve for operators of order n's size class."""
+        _check(load().mvpb_ctx_set_launch_shape(self.h, n, parts, group, wg_max))
+
+    def launch_shape(self, n: int):
+        """(parts, group, wg_max) used for operators of order n."""
+        v = [ctypes.c_int() for _ in range(3)]
+        _check(load().mvpb_ctx_get_launch_shape(self.h, n, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def set_wait_limit(self, spins: int):
         """Polls of a bulge-chasing hand-over wait before a point gives up (0: default)."""

@@ -9,6 +9,13 @@
       (FETCH_SIZE, then WRITE_SIZE, both in KiB per dispatch), each scaled by
       what the same counter reads for the library's plain copy kernel (copy16)
       moving B bytes each way.
+  python -m paper_1310_6380_amd.profile_summary mfma DIR --cmd "..."
+      matrix-core figures per kernel from one ``--pmc
+      SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_MFMA_MOPS_BF16
+      SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE --kernel-trace`` run: matrix-core
+      flops per dispatch (512 per MOP), their rate over the traced duration
+      against the dense peak of the type, and the matrix-core busy share
+      (busy cycles over GRBM_GUI_ACTIVE times the 1024 SIMDs).
 
 Both print Markdown on stdout.  Each traffic row carries the digest of the
 source file of its kernel (and the shared headers) it was taken on; figures
@@ -95,8 +102,9 @@ def read_stats(dirpath: str):
     return sorted(out, key=lambda t: -t[2])
 
 
-def read_counters(dirpath: str, counter: str):
-    """{kernel base name: [value per dispatch]} of one counter."""
+def read_counters(dirpath: str, counter: str, reduce=None):
+    """{kernel base name: [value per dispatch]} of one counter (rows of a
+    dispatch summed, or combined by ``reduce``)."""
     with open(_find(dirpath, "counter_collection.csv")) as fh:
         rows = list(csv.reader(fh))
     h = rows[0]
@@ -104,13 +112,15 @@ def read_counters(dirpath: str, counter: str):
     ck = _col(h, "Kernel_Name", "Kernel-Name", "kernel_name")
     cc = _col(h, "Counter_Name", "Counter-Name", "counter_name")
     cv = _col(h, "Counter_Value", "Counter-Value", "counter_value")
-    per = collections.defaultdict(float)
+    per = {}
     names = {}
     for r in rows[1:]:
         if not r or r[cc] != counter:
             continue
-        per[r[cd]] += float(r[cv])
-        names[r[cd]] = base_name(r[ck])
+        v = float(r[cv])
+        d = r[cd]
+        per[d] = v if d not in per else (reduce(per[d], v) if reduce else per[d] + v)
+        names[d] = base_name(r[ck])
     out = collections.defaultdict(list)
     for d, v in per.items():
         out[names[d]].append(v)
@@ -162,6 +172,64 @@ def cmd_traffic(a):
         print(f"| {k} | {nd} | {fa:.1f} | {wa:.1f} | {b:.0f} | {source_digest(k)} |")
 
 
+def read_durations(dirpath: str):
+    """{dispatch id: (kernel base name, duration ns)} from a kernel trace."""
+    with open(_find(dirpath, "kernel_trace.csv")) as fh:
+        rows = list(csv.reader(fh))
+    h = rows[0]
+    cd = _col(h, "Dispatch_Id", "Dispatch-Id", "dispatch_id")
+    ck = _col(h, "Kernel_Name", "Kernel-Name", "kernel_name")
+    cs, ce = _col(h, "Start_Timestamp", "Start-Timestamp"), _col(h, "End_Timestamp", "End-Timestamp")
+    return {r[cd]: (base_name(r[ck]), float(r[ce]) - float(r[cs])) for r in rows[1:] if r}
+
+
+SIMDS = 1024            # 256 compute units x 4 SIMDs
+PEAK_TFLOPS = {"F64": 78.6, "BF16": 2500.0}
+
+
+def cmd_mfma(a):
+    dur = read_durations(a.dir)
+    with open(_find(a.dir, "counter_collection.csv")) as fh:
+        rows = list(csv.reader(fh))
+    h = rows[0]
+    cd, cc, cv = (_col(h, "Dispatch_Id", "Dispatch-Id", "dispatch_id"), _col(h, "Counter_Name", "Counter-Name"),
+                  _col(h, "Counter_Value", "Counter-Value"))
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    for r in rows[1:]:
+        if not r:
+            continue
+        v = float(r[cv])
+        d = per[r[cd]]
+        if r[cc] == "GRBM_GUI_ACTIVE":
+            d[r[cc]] = max(d[r[cc]], v)
+        else:
+            d[r[cc]] += v
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    for d, cnt in per.items():
+        if d not in dur:
+            continue
+        name, ns = dur[d]
+        g = agg[name]
+        g["n"] += 1
+        g["ns"] += ns
+        for k, v in cnt.items():
+            g[k] += v
+    print(f"# {a.title}\n")
+    print(f"command: `{a.cmd}`\n")
+    print("| kernel | dispatches | avg us | FP64 MFMA GFLOP/dispatch | FP64 TFLOP/s (of 78.6) | "
+          "BF16 MFMA GFLOP/dispatch | BF16 TFLOP/s (of 2500) | matrix cores busy | source digest |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|---|")
+    order = sorted(agg.items(), key=lambda kv: -kv[1]["ns"])
+    for name, g in order[: a.top]:
+        n = g["n"]
+        f64 = 512.0 * g["SQ_INSTS_VALU_MFMA_MOPS_F64"] / n
+        b16 = 512.0 * g["SQ_INSTS_VALU_MFMA_MOPS_BF16"] / n
+        us = g["ns"] / n / 1e3
+        busy = g["SQ_VALU_MFMA_BUSY_CYCLES"] / max(1.0, g["GRBM_GUI_ACTIVE"] * SIMDS)
+        print(f"| {name} | {int(n)} | {us:.1f} | {f64 / 1e9:.4f} | {f64 / (us * 1e6) if us else 0:.2f} | "
+              f"{b16 / 1e9:.4f} | {b16 / (us * 1e6) if us else 0:.2f} | {100 * busy:.1f}% | {source_digest(name)} |")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -178,8 +246,13 @@ def main(argv=None):
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--cmd-copy", required=True)
     t.add_argument("--title", default="HBM traffic per dispatch")
+    m = sub.add_parser("mfma")
+    m.add_argument("dir")
+    m.add_argument("--cmd", required=True)
+    m.add_argument("--title", default="matrix-core counters per dispatch")
+    m.add_argument("--top", type=int, default=30)
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic}[a.what](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "mfma": cmd_mfma}[a.what](a)
 
 
 if __name__ == "__main__":
