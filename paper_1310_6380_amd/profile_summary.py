@@ -13,9 +13,10 @@
       matrix-core figures per kernel from one ``--pmc
       SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_MFMA_MOPS_BF16
       SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE --kernel-trace`` run: matrix-core
-      flops per dispatch (512 per MOP), their rate over the traced duration
-      against the dense peak of the type, and the matrix-core busy share
-      (busy cycles over GRBM_GUI_ACTIVE times the 1024 SIMDs).
+      flops per dispatch (512 per MOP) and their rate over the traced
+      duration against the dense peak of the type (the busy-cycle counter is
+      collected but not reported: its normalisation per SIMD is not
+      established on this part).
 
 Both print Markdown on stdout.  Each traffic row carries the digest of the
 source file of its kernel (and the shared headers) it was taken on; figures
@@ -183,10 +184,6 @@ def read_durations(dirpath: str):
     return {r[cd]: (base_name(r[ck]), float(r[ce]) - float(r[cs])) for r in rows[1:] if r}
 
 
-SIMDS = 1024            # 256 compute units x 4 SIMDs
-PEAK_TFLOPS = {"F64": 78.6, "BF16": 2500.0}
-
-
 def cmd_mfma(a):
     dur = read_durations(a.dir)
     with open(_find(a.dir, "counter_collection.csv")) as fh:
@@ -217,17 +214,16 @@ def cmd_mfma(a):
     print(f"# {a.title}\n")
     print(f"command: `{a.cmd}`\n")
     print("| kernel | dispatches | avg us | FP64 MFMA GFLOP/dispatch | FP64 TFLOP/s (of 78.6) | "
-          "BF16 MFMA GFLOP/dispatch | BF16 TFLOP/s (of 2500) | matrix cores busy | source digest |")
-    print("|---|---:|---:|---:|---:|---:|---:|---:|---|")
+          "BF16 MFMA GFLOP/dispatch | BF16 TFLOP/s (of 2500) | source digest |")
+    print("|---|---:|---:|---:|---:|---:|---:|---|")
     order = sorted(agg.items(), key=lambda kv: -kv[1]["ns"])
     for name, g in order[: a.top]:
         n = g["n"]
         f64 = 512.0 * g["SQ_INSTS_VALU_MFMA_MOPS_F64"] / n
         b16 = 512.0 * g["SQ_INSTS_VALU_MFMA_MOPS_BF16"] / n
         us = g["ns"] / n / 1e3
-        busy = g["SQ_VALU_MFMA_BUSY_CYCLES"] / max(1.0, g["GRBM_GUI_ACTIVE"] * SIMDS)
         print(f"| {name} | {int(n)} | {us:.1f} | {f64 / 1e9:.4f} | {f64 / (us * 1e6) if us else 0:.2f} | "
-              f"{b16 / 1e9:.4f} | {b16 / (us * 1e6) if us else 0:.2f} | {100 * busy:.1f}% | {source_digest(name)} |")
+              f"{b16 / 1e9:.4f} | {b16 / (us * 1e6) if us else 0:.2f} | {source_digest(name)} |")
 
 
 def main(argv=None):
