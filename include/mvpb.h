@@ -265,6 +265,38 @@ int mvpb_band_sensitivities(mvpb_plan plan, int n_k, const double *Q, int n_band
 int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plans, const int *n_k,
                      const double *const *Q, int n_bands, double *const *omega, unsigned flags);
 
+/* Band structure of many pixel cells in one call, plan build included:
+ * the structure factors of every cell (Sec. 4.1, per-pixel closed forms
+ * summed on the matrix cores), its Toeplitz blocks (eqs. (eh), (eo), (ep)),
+ * the Cholesky factors and coefficient matrices of the reduced operator
+ * C(k) (Sec. 3, eq. (eigenvalueproblem)), and the eigensolve of every
+ * (cell, k) pair, enqueued as ONE captured HIP graph.  The graph is kept
+ * (at most 4 per context, least recently used dropped) and replayed by a
+ * later call of the same shape: the same cell count, and per cell (in
+ * cutoff order) the same cutoff, pixel grid and k count, with the same
+ * n_bands, precision and launch shapes.  Per-call data (phase maps, phase
+ * tables, lattices, Bloch vectors) reach the kernels through device tables
+ * uploaded before each launch, so a replay needs no host work beyond one
+ * copy.  The plans are not kept: their matrices live in a context-owned
+ * workspace (grow-only, within the context's workspace cap).
+ *   cells[i]: isotropic pixel cells of ctx (MVPB_E_UNSUPPORTED for polygon,
+ *             voxel and general-compliance cells);
+ *   M1[i], M2[i]: cutoffs, 2 N <= the plan limit;
+ *   precision: as for mvpb_plan_create without MVPB_PREC_SF_PLAIN64 and
+ *             MVPB_PREC_GENERAL (MVPB_E_UNSUPPORTED);
+ *   n_k[i] >= 0 points of cell i in Q[i] (host, 2 reduced coordinates
+ *             each), results to omega[i][t * n_bands + b] (host pointers, or
+ *             device pointers with MVPB_F_DEVICE_PTRS);
+ *   n_bands: 1 .. min(2 N_i, 256), or 64 with MVPB_PREC_EIG_FP32_RR64.
+ * Always returns after the results are written (MVPB_F_ASYNC is ignored).
+ * Errors: MVPB_E_NOT_PD names the first cell (caller's index) whose
+ * compliance or density matrix failed to factor (its results are not
+ * meaningful, the other cells' are); MVPB_E_NOMEM if the workspace would
+ * exceed the cap; MVPB_E_ACCURACY and MVPB_E_DEVICE as for mvpb_solve. */
+int mvpb_solve_cells(mvpb_ctx ctx, int n_cells, const mvpb_cell *cells, const int *M1, const int *M2,
+                     int precision, const int *n_k, const double *const *Q, int n_bands,
+                     double *const *omega, unsigned flags);
+
 /* Structure factors of the general layout (pixel and voxel cells):
  * F[((f*(4M1+1) + m+2M1)*(4M2+1) + q+2M2)*(4M3+1) + r+2M3] (complex,
  * interleaved) = sum_p w_f(p) int_{Omega_p} exp(i 2 pi (m H1 + q H2 + r H3)) dx

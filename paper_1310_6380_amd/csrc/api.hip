@@ -176,6 +176,13 @@ struct mvpb_ctx_s {
   std::map<std::string, GraphEntry> graphs;
   unsigned long long graph_clock = 0;
   std::vector<EigItem> host_items;                // staging of the item table (kept alive for async copies)
+  // mvpb_solve_cells: workspace (plain device allocation, grow-only), its
+  // captured graphs (keyed by the call's shape, at most MAX_CELL_GRAPHS) and
+  // the staging of the per-call tables
+  DevBuf cws;
+  std::map<std::string, GraphEntry> cell_graphs;
+  std::vector<char> cell_stage;
+  std::vector<hipEvent_t> cell_events;            // stage-1 fork/join events, MAX_SIDE + 1 per chunk
   std::map<int, TuneParams> tune;                 // launch shapes by size class
   long long spin_limit = 0;                       // bounded-wait polls of the bulge chasing (0: default)
   Profiler prof;
@@ -188,6 +195,11 @@ static void ctx_free(mvpb_ctx c) {
   (void)hipStreamSynchronize(c->stream);
   for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   c->graphs.clear();
+  for (auto &kv : c->cell_graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  c->cell_graphs.clear();
+  for (hipEvent_t ev : c->cell_events) (void)hipEventDestroy(ev);
+  c->cell_events.clear();
+  c->cws.release();
   c->ws.release();
   c->items.release();
   c->scratch.release();
@@ -1511,6 +1523,58 @@ static std::string launch_signature(const std::vector<Job> &jobs, int nb, bool f
   return k;
 }
 
+// The eigensolve launch sequence over the items of a device table whose
+// operator orders are `orders` (table order): operator formation, stage 1 in
+// independent parts on the context's streams, bulge chasing, tridiagonal
+// eigenpairs, back-transform, Rayleigh-Ritz (or the tridiagonal results
+// beyond RR_MAX_BANDS).  ctl: the bulge-chasing control words.
+static hipError_t enqueue_eigensolve(mvpb_ctx ctx, const EigItem *d_items, const std::vector<int> &orders,
+                                     bool any_iso, bool any_general, int nb, bool fp32, int parts_wanted,
+                                     const Stage2Shape &sh, int *ctl, hipStream_t st, hipEvent_t ev_fork,
+                                     const hipEvent_t *ev_join) {
+  const int n_items = (int)orders.size();
+  int n_max = 0, n_min = 1 << 30;
+  for (int n : orders) {
+    n_max = std::max(n_max, n);
+    n_min = std::min(n_min, n);
+  }
+  hipError_t e = hipSuccess;
+  if (any_iso) e = launch_form_operator(d_items, n_items, n_max, fp32, st);
+  if (e == hipSuccess && any_general) e = launch_form_operator_general(d_items, n_items, n_max, fp32, st);
+  // stage 1 in independent parts of the items, one per stream
+  ItemPart parts[MAX_SIDE + 1];
+  const int n_parts = std::max(1, std::min(parts_wanted, n_items));
+  for (int q = 0; q < n_parts; ++q) {
+    const int i0 = (int)((long long)n_items * q / n_parts), i1 = (int)((long long)n_items * (q + 1) / n_parts);
+    ItemPart &pt = parts[q];
+    pt.items = d_items + i0;
+    pt.n_items = i1 - i0;
+    pt.n_min = 1 << 30;
+    pt.n_max = 0;
+    for (int i = i0; i < i1; ++i) {
+      pt.n_min = std::min(pt.n_min, orders[i]);
+      pt.n_max = std::max(pt.n_max, orders[i]);
+    }
+    pt.stream = q == 0 ? st : ctx->side[q - 1];
+  }
+  if (e == hipSuccess && n_parts > 1) {
+    e = hipEventRecord(ev_fork, st);
+    for (int q = 1; q < n_parts && e == hipSuccess; ++q) e = hipStreamWaitEvent(parts[q].stream, ev_fork, 0);
+  }
+  if (e == hipSuccess) e = launch_stage1(parts, n_parts, fp32);
+  for (int q = 1; q < n_parts && e == hipSuccess; ++q) {
+    e = hipEventRecord(ev_join[q - 1], parts[q].stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev_join[q - 1], 0);
+  }
+  if (e == hipSuccess) e = launch_stage2(d_items, n_items, n_max, fp32, ctl, sh, st);
+  if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, n_max, nb, st);
+  if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_min, n_max, nb, fp32, st);
+  if (e == hipSuccess)
+    e = nb <= RR_MAX_BANDS ? launch_rayleigh_ritz(d_items, n_items, n_max, nb, fp32, st)
+                           : launch_tridiag_results(d_items, n_items, nb, st);
+  return e;
+}
+
 static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double *omega_dev, double *U_dev,
                      bool use_graph) {
   // the reduction precision is shared by every item of one launch sequence
@@ -1588,43 +1652,12 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   HIP_TRY(hipMemcpyAsync(ctx->items.p, items.data(), sizeof(EigItem) * n_items, hipMemcpyHostToDevice, st));
   const EigItem *d_items = ctx->items.as<EigItem>();
 
+  std::vector<int> orders(n_items);
+  for (int i = 0; i < n_items; ++i) orders[i] = jobs[i].plan->n;
+  int *ctl = reinterpret_cast<int *>(ctx->ws.as<char>() + ctl_off);
   auto enqueue = [&]() -> hipError_t {
-    hipError_t e = hipSuccess;
-    if (any_iso) e = launch_form_operator(d_items, n_items, n_max, fp32, st);
-    if (e == hipSuccess && any_general) e = launch_form_operator_general(d_items, n_items, n_max, fp32, st);
-    // stage 1 in independent parts of the items, one per stream
-    ItemPart parts[MAX_SIDE + 1];
-    const int n_parts = std::max(1, std::min(parts_wanted, n_items));
-    for (int q = 0; q < n_parts; ++q) {
-      const int i0 = (int)((long long)n_items * q / n_parts), i1 = (int)((long long)n_items * (q + 1) / n_parts);
-      ItemPart &pt = parts[q];
-      pt.items = d_items + i0;
-      pt.n_items = i1 - i0;
-      pt.n_min = 1 << 30;
-      pt.n_max = 0;
-      for (int i = i0; i < i1; ++i) {
-        pt.n_min = std::min(pt.n_min, jobs[i].plan->n);
-        pt.n_max = std::max(pt.n_max, jobs[i].plan->n);
-      }
-      pt.stream = q == 0 ? st : ctx->side[q - 1];
-    }
-    if (e == hipSuccess && n_parts > 1) {
-      e = hipEventRecord(ctx->ev_fork, st);
-      for (int q = 1; q < n_parts && e == hipSuccess; ++q) e = hipStreamWaitEvent(parts[q].stream, ctx->ev_fork, 0);
-    }
-    if (e == hipSuccess) e = launch_stage1(parts, n_parts, fp32);
-    for (int q = 1; q < n_parts && e == hipSuccess; ++q) {
-      e = hipEventRecord(ctx->ev_join[q - 1], parts[q].stream);
-      if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->ev_join[q - 1], 0);
-    }
-    int *ctl = reinterpret_cast<int *>(ctx->ws.as<char>() + ctl_off);
-    if (e == hipSuccess) e = launch_stage2(d_items, n_items, n_max, fp32, ctl, sh, st);
-    if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, n_max, nb, st);
-    if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_min, n_max, nb, fp32, st);
-    if (e == hipSuccess)
-      e = nb <= RR_MAX_BANDS ? launch_rayleigh_ritz(d_items, n_items, n_max, nb, fp32, st)
-                             : launch_tridiag_results(d_items, n_items, nb, st);
-    return e;
+    return enqueue_eigensolve(ctx, d_items, orders, any_iso, any_general, nb, fp32, parts_wanted, sh, ctl, st,
+                              ctx->ev_fork, ctx->ev_join);
   };
   if (use_graph) {
     const std::string graph_key = launch_signature(jobs, nb, fp32, parts_wanted, sh);
@@ -2014,6 +2047,450 @@ extern "C" int mvpb_solve_batch(mvpb_ctx ctx, int n_plans, const mvpb_plan *plan
     }
   if (!dev || !(flags & MVPB_F_ASYNC)) return acc_finish(ctx, fp32);
   return MVPB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Many pixel cells: plan build and eigensolve in one captured graph
+// ---------------------------------------------------------------------------
+constexpr size_t MAX_CELL_GRAPHS = 4;
+
+namespace {
+// Cells of one cutoff at sorted positions [c0, c1), with their offsets in
+// the workspace (o_*) and in the per-call table region (t_*, bytes).
+struct CellGroup {
+  int M1, M2, N, c0, c1;
+  size_t o_coef;                      // coefficient matrices of cell c0
+  size_t t_ptrs;                      // pointer table of the factorisations and GEMMs
+  size_t n_ptrs, o_inv, o_pA, o_pB, o_pC, o_pS, o_xA, o_xB, o_xC;   // entries in it
+  size_t t_gvec, t_scale;             // G vectors (3 N per cell), combine scales
+  struct Run {                        // structure-factor launch: cells of one grid
+    int k0, cnt;
+    size_t t_tab;                     // phase pointers, weight-table pointers, areas
+  };
+  std::vector<Run> runs;
+};
+struct CellChunk {                    // eigensolve launch sequence over sorted jobs [j0, j1)
+  size_t j0, j1;
+  size_t t_items;                     // item table
+  TuneParams tp;
+};
+}  // namespace
+
+extern "C" int mvpb_solve_cells(mvpb_ctx ctx, int n_cells, const mvpb_cell *cells, const int *M1, const int *M2,
+                                int precision, const int *n_k, const double *const *Q, int n_bands,
+                                double *const *omega, unsigned flags) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (n_cells < 0 || (n_cells > 0 && (!cells || !M1 || !M2 || !n_k || !Q || !omega)))
+    return set_err(MVPB_E_INVALID, "NULL argument");
+  rc = check_precision(precision);
+  if (rc) return rc;
+  if (precision & (MVPB_PREC_SF_PLAIN64 | MVPB_PREC_GENERAL))
+    return set_err(MVPB_E_UNSUPPORTED, "mvpb_solve_cells takes the matrix-core structure factors and the isotropic layout");
+  const bool fp32 = (precision & MVPB_PREC_EIG_FP32_RR64) != 0;
+  const int bmax = fp32 ? RR_MAX_BANDS : MAX_BANDS;
+  if (n_bands < 1 || n_bands > bmax) return set_err(MVPB_E_INVALID, "n_bands = %d out of range 1..%d", n_bands, bmax);
+  std::vector<size_t> base(n_cells + 1, 0);
+  for (int i = 0; i < n_cells; ++i) {
+    const mvpb_cell c = cells[i];
+    if (!c || c->ctx != ctx) return set_err(MVPB_E_INVALID, "cell %d missing or from another context", i);
+    if (c->polygons || c->dim != 2 || c->general)
+      return set_err(MVPB_E_UNSUPPORTED, "cell %d: mvpb_solve_cells takes isotropic pixel cells", i);
+    rc = check_cutoff(M1[i], M2[i]);
+    if (rc) return rc;
+    if (2 * (2 * M1[i] + 1) * (2 * M2[i] + 1) < n_bands) return set_err(MVPB_E_INVALID, "cell %d: n_bands > n_u", i);
+    if (n_k[i] < 0 || (n_k[i] > 0 && (!Q[i] || !omega[i]))) return set_err(MVPB_E_INVALID, "cell %d: bad k list", i);
+    if (!q_ok(Q[i], 2 * n_k[i])) return set_err(MVPB_E_INVALID, "cell %d: non-finite Bloch vector", i);
+    base[i + 1] = base[i] + n_k[i];
+  }
+  if (n_cells == 0) return MVPB_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const int sfp = precision & 3;
+
+  // cells sorted by cutoff, then grid: groups of one cutoff, runs of one grid
+  std::vector<int> ord(n_cells);
+  for (int i = 0; i < n_cells; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (M1[a] != M1[b]) return M1[a] < M1[b];
+    if (M2[a] != M2[b]) return M2[a] < M2[b];
+    if (cells[a]->nx != cells[b]->nx) return cells[a]->nx < cells[b]->nx;
+    return cells[a]->ny < cells[b]->ny;
+  });
+  std::vector<int> pos(n_cells);   // sorted position of caller cell i
+  for (int s = 0; s < n_cells; ++s) pos[ord[s]] = s;
+  size_t tab = 0;   // table region bytes
+  auto take_tab = [&](size_t b) {
+    const size_t o = tab;
+    tab += align256(b);
+    return o;
+  };
+  std::vector<CellGroup> groups;
+  size_t coef_bytes = 0, temp_bytes = 0;
+  for (int s = 0; s < n_cells;) {
+    CellGroup g{};
+    g.M1 = M1[ord[s]];
+    g.M2 = M2[ord[s]];
+    g.N = (2 * g.M1 + 1) * (2 * g.M2 + 1);
+    g.c0 = s;
+    // at most ~8 GB of temporaries and 2048 cells (GEMM grid depth 18 per cell) per group
+    const size_t per = 30 * (size_t)g.N * g.N * sizeof(cd) + 64 * (size_t)g.N * sizeof(cd);
+    const int gmax = (int)std::max<size_t>(1, std::min<size_t>(2048, ((size_t)8 << 30) / per));
+    while (s < n_cells && M1[ord[s]] == g.M1 && M2[ord[s]] == g.M2 && s - g.c0 < gmax) ++s;
+    g.c1 = s;
+    const size_t cnt = g.c1 - g.c0, NN = (size_t)g.N * g.N;
+    const int nm = 4 * g.M1 + 1, nq = 4 * g.M2 + 1;
+    g.o_coef = coef_bytes;
+    coef_bytes += align256(sizeof(cd) * 15 * NN * cnt);
+    size_t xmax = 0;
+    for (int k = g.c0; k < g.c1;) {
+      CellGroup::Run r{k, 0, 0};
+      const mvpb_cell c0 = cells[ord[k]];
+      while (k < g.c1 && cells[ord[k]]->nx == c0->nx && cells[ord[k]]->ny == c0->ny) ++k;
+      r.cnt = k - r.k0;
+      r.t_tab = take_tab((2 * sizeof(void *) + sizeof(double)) * r.cnt);
+      xmax = std::max(xmax, sizeof(double) * 8 * (size_t)c0->nx * nq * r.cnt);
+      g.runs.push_back(r);
+    }
+    // temporaries of the group: F, X, Toeplitz matrices, inverse factors, P, products
+    const size_t t = align256(sizeof(cd) * 4 * (size_t)nm * nq * cnt) + align256(xmax) +
+                     4 * align256(sizeof(cd) * 3 * NN * cnt) /* mats, linv: 3 NN each; P: 6 NN */ +
+                     align256(sizeof(cd) * 18 * NN * cnt);
+    temp_bytes = std::max(temp_bytes, t);
+    g.n_ptrs = 6 * cnt + 4 * 6 * cnt + 3 * 18 * cnt;
+    g.t_ptrs = take_tab(sizeof(void *) * g.n_ptrs);
+    g.t_gvec = take_tab(sizeof(double) * 3 * (size_t)g.N * cnt);
+    g.t_scale = take_tab(sizeof(double) * cnt);
+    groups.push_back(std::move(g));
+  }
+  // jobs, largest operators first; chunks as in mvpb_solve_batch
+  struct CJob {
+    int s;         // sorted cell position
+    int t;         // k index
+  };
+  std::vector<CJob> jobs;
+  for (int s = 0; s < n_cells; ++s)
+    for (int t = 0; t < n_k[ord[s]]; ++t) jobs.push_back(CJob{s, t});
+  auto order_of = [&](const CJob &j) { return 2 * (2 * M1[ord[j.s]] + 1) * (2 * M2[ord[j.s]] + 1); };
+  std::stable_sort(jobs.begin(), jobs.end(), [&](const CJob &a, const CJob &b) { return order_of(a) > order_of(b); });
+  const size_t stat_bytes = align256(sizeof(int) * 3 * n_cells);
+  const size_t om_bytes = align256(sizeof(double) * base[n_cells] * n_bands);
+  const size_t fixed = coef_bytes + temp_bytes + stat_bytes + om_bytes;
+  size_t budget = (size_t)24 << 30;
+  if (ctx->cap) {
+    if (fixed + tab >= ctx->cap)
+      return set_err(MVPB_E_NOMEM, "plan build of %d cells needs %zu bytes, cap is %zu", n_cells, fixed + tab, ctx->cap);
+    budget = std::min(budget, ctx->cap - fixed - tab);
+  }
+  std::vector<CellChunk> chunks;
+  size_t item_region = 0;
+  for (size_t j0 = 0; j0 < jobs.size();) {
+    size_t j1 = j0, bytes = 0;
+    const int n0 = order_of(jobs[j0]);
+    while (j1 < jobs.size()) {
+      const size_t b = item_bytes(order_of(jobs[j1]), n_bands, fp32);
+      if (j1 > j0 && (bytes + b + ctl_bytes(j1 - j0 + 1) > budget || 3 * order_of(jobs[j1]) < 2 * n0)) break;
+      bytes += b;
+      ++j1;
+    }
+    bytes += ctl_bytes(j1 - j0);
+    if (bytes > budget) return set_err(MVPB_E_NOMEM, "one item needs %zu bytes, the budget is %zu", bytes, budget);
+    CellChunk ch{j0, j1, take_tab(sizeof(EigItem) * (j1 - j0)), TuneParams{}};
+    auto f = ctx->tune.find(size_class(n0));
+    if (f != ctx->tune.end()) ch.tp = f->second;
+    chunks.push_back(ch);
+    item_region = std::max(item_region, bytes);
+    j0 = j1;
+  }
+  // workspace: tables | coefficients | status | temporaries | frequencies | items
+  const size_t o_coef = align256(tab), o_stat = o_coef + coef_bytes, o_temp = o_stat + stat_bytes,
+               o_om = o_temp + temp_bytes, o_items = o_om + om_bytes, total = o_items + item_region;
+  if (ctx->cap && total > ctx->cap)
+    return set_err(MVPB_E_NOMEM, "workspace %zu bytes exceeds the cap of %zu bytes", total, ctx->cap);
+  // the staging may still feed an earlier copy; graphs point into the workspace
+  HIP_TRY(hipStreamSynchronize(st));
+  if (total > ctx->cws.bytes) {
+    for (auto &kv : ctx->cell_graphs) (void)hipGraphExecDestroy(kv.second.exec);
+    ctx->cell_graphs.clear();
+    ctx->cws.pool = nullptr;
+    HIP_TRY(ctx->cws.alloc(total));
+  }
+  char *W = ctx->cws.as<char>();
+  int *stat = reinterpret_cast<int *>(W + o_stat);
+  double *om = reinterpret_cast<double *>(W + o_om);
+
+  // per-call tables
+  std::vector<char> &stage = ctx->cell_stage;
+  stage.assign(tab, 0);
+  auto put_ptr = [&](size_t off, size_t i, const void *p) { memcpy(stage.data() + off + i * sizeof(void *), &p, sizeof p); };
+  auto put_dbl = [&](size_t off, size_t i, double v) { memcpy(stage.data() + off + i * sizeof(double), &v, sizeof v); };
+  for (CellGroup &g : groups) {
+    const size_t cnt = g.c1 - g.c0, NN = (size_t)g.N * g.N;
+    const int nm = 4 * g.M1 + 1, nq = 4 * g.M2 + 1;
+    for (const CellGroup::Run &r : g.runs)
+      for (int k = 0; k < r.cnt; ++k) {
+        const mvpb_cell c = cells[ord[r.k0 + k]];
+        put_ptr(r.t_tab, k, c->phase.p);
+        put_ptr(r.t_tab, r.cnt + k, c->wtab.p);
+        put_dbl(r.t_tab + 2 * sizeof(void *) * r.cnt, k, c->area);
+      }
+    char *tp = W + o_temp;
+    cd *F = reinterpret_cast<cd *>(tp);
+    tp += align256(sizeof(cd) * 4 * (size_t)nm * nq * cnt);
+    (void)F;
+    size_t xmax = 0;
+    for (const CellGroup::Run &r : g.runs)
+      xmax = std::max(xmax, sizeof(double) * 8 * (size_t)cells[ord[r.k0]]->nx * nq * r.cnt);
+    tp += align256(xmax);
+    cd *Tm = reinterpret_cast<cd *>(tp);
+    tp += align256(sizeof(cd) * 3 * NN * cnt);
+    cd *Li = reinterpret_cast<cd *>(tp);
+    tp += align256(sizeof(cd) * 3 * NN * cnt);
+    cd *Pm = reinterpret_cast<cd *>(tp);
+    tp += 2 * align256(sizeof(cd) * 3 * NN * cnt);
+    cd *Xm = reinterpret_cast<cd *>(tp);
+    const double *gvd = reinterpret_cast<const double *>(W + g.t_gvec);
+    // the pointer table of build_plan_group's factorisation and GEMMs
+    size_t e = 0;
+    auto push = [&](const void *p) { put_ptr(g.t_ptrs, e++, p); };
+    for (size_t c = 0; c < cnt; ++c)
+      for (int i = 0; i < 3; ++i) push(Tm + (3 * c + i) * NN);
+    g.o_inv = e;
+    for (size_t c = 0; c < cnt; ++c)
+      for (int i = 0; i < 3; ++i) push(Li + (3 * c + i) * NN);
+    g.o_pA = e;
+    for (size_t c = 0; c < cnt; ++c)
+      for (int x = 0; x < 2; ++x)
+        for (int l = 0; l < 3; ++l) push(Li + (3 * c + 2) * NN);
+    g.o_pB = e;
+    for (size_t c = 0; c < cnt; ++c)
+      for (int x = 0; x < 2; ++x)
+        for (int l = 0; l < 3; ++l) push(Li + (3 * c + x) * NN);
+    g.o_pC = e;
+    for (size_t c = 0; c < cnt; ++c)
+      for (int x = 0; x < 2; ++x)
+        for (int l = 0; l < 3; ++l) push(Pm + (6 * c + x * 3 + l) * NN);
+    g.o_pS = e;
+    for (size_t c = 0; c < cnt; ++c)
+      for (int x = 0; x < 2; ++x)
+        for (int l = 0; l < 3; ++l) push(gvd + 3 * (size_t)g.N * c + l * g.N);
+    g.o_xA = e;
+    for (size_t c = 0; c < cnt; ++c)
+      for (int x = 0; x < 2; ++x)
+        for (int l = 0; l < 3; ++l)
+          for (int m = 0; m < 3; ++m) push(Pm + (6 * c + x * 3 + l) * NN);
+    g.o_xB = e;
+    for (size_t c = 0; c < cnt; ++c)
+      for (int x = 0; x < 2; ++x)
+        for (int l = 0; l < 3; ++l)
+          for (int m = 0; m < 3; ++m) push(Pm + (6 * c + x * 3 + m) * NN);
+    g.o_xC = e;
+    for (size_t c = 0; c < cnt; ++c)
+      for (int x = 0; x < 2; ++x)
+        for (int l = 0; l < 3; ++l)
+          for (int m = 0; m < 3; ++m) push(Xm + (18 * c + x * 9 + l * 3 + m) * NN);
+    if (e != g.n_ptrs) return set_err(MVPB_E_DEVICE, "internal: pointer table of %zu entries, expected %zu", e, g.n_ptrs);
+    // G_l vectors at Q = 0 and the coefficient scales |Omega|^2 / 2
+    for (size_t c = 0; c < cnt; ++c) {
+      const mvpb_cell cl = cells[ord[g.c0 + c]];
+      for (int a = -g.M1; a <= g.M1; ++a)
+        for (int b = -g.M2; b <= g.M2; ++b) {
+          const size_t r = (size_t)(a + g.M1) * (2 * g.M2 + 1) + (b + g.M2);
+          const size_t o = 3 * (size_t)g.N * c;
+          put_dbl(g.t_gvec, o + r, 1.0);
+          put_dbl(g.t_gvec, o + g.N + r, 2.0 * M_PI * (cl->T[0] * a + cl->T[1] * b));
+          put_dbl(g.t_gvec, o + 2 * g.N + r, 2.0 * M_PI * (cl->T[2] * a + cl->T[3] * b));
+        }
+      put_dbl(g.t_scale, c, 0.5 * cl->area * cl->area);
+    }
+  }
+  // item tables: each chunk carves its items from the start of the item region
+  std::vector<size_t> grp_of(n_cells);
+  for (size_t gi = 0; gi < groups.size(); ++gi)
+    for (int s = groups[gi].c0; s < groups[gi].c1; ++s) grp_of[s] = gi;
+  for (const CellChunk &ch : chunks) {
+    size_t off = 0;
+    for (size_t j = ch.j0; j < ch.j1; ++j) {
+      const CJob &jb = jobs[j];
+      const int ci = ord[jb.s];
+      const CellGroup &g = groups[grp_of[jb.s]];
+      const int n = 2 * g.N;
+      EigItem it = carve_item(W + o_items + off, n, n_bands, fp32);
+      off += item_bytes(n, n_bands, fp32);
+      it.coef = reinterpret_cast<cd *>(W + o_coef + g.o_coef) + (size_t)(jb.s - g.c0) * 15 * g.N * g.N;
+      it.N = g.N;
+      it.n = n;
+      it.dim = 0;
+      it.check = fp32 ? 1 : 0;
+      it.nb = n_bands;
+      it.slot = (int)(base[ci] + jb.t);
+      const double *q = Q[ci] + 2 * (size_t)jb.t;
+      const double *T = cells[ci]->T;
+      it.kap1 = 2.0 * M_PI * (T[0] * q[0] + T[1] * q[1]);
+      it.kap2 = 2.0 * M_PI * (T[2] * q[0] + T[3] * q[1]);
+      it.kap3 = 0.0;
+      memcpy(stage.data() + ch.t_items + (j - ch.j0) * sizeof(EigItem), &it, sizeof it);
+    }
+  }
+  // fork/join events of every chunk's stage 1 (one set per chunk, so that the
+  // captured dependencies of one chunk never alias another's)
+  while (ctx->cell_events.size() < chunks.size() * (MAX_SIDE + 1)) {
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    ctx->cell_events.push_back(ev);
+  }
+  rc = acc_begin(ctx);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(W, stage.data(), tab, hipMemcpyHostToDevice, st));
+
+  // the launch sequence: every group's plan build, then every chunk's eigensolve
+  auto enqueue = [&]() -> hipError_t {
+    hipError_t e = hipSuccess;
+    int *gstat = stat;
+    for (const CellGroup &g : groups) {
+      const int cnt = g.c1 - g.c0;
+      const size_t NN = (size_t)g.N * g.N;
+      const int nm = 4 * g.M1 + 1, nq = 4 * g.M2 + 1;
+      const size_t fsz = (size_t)4 * nm * nq;
+      char *tp = W + o_temp;
+      cd *F = reinterpret_cast<cd *>(tp);
+      tp += align256(sizeof(cd) * fsz * cnt);
+      double *X = reinterpret_cast<double *>(tp);
+      for (const CellGroup::Run &r : g.runs) {
+        void **tb = reinterpret_cast<void **>(W + r.t_tab);
+        const mvpb_cell c0 = cells[ord[r.k0]];
+        if (e == hipSuccess)
+          e = launch_structure_factors_mfma_batch(sfp, (const int32_t *const *)tb, (const double *const *)(tb + r.cnt),
+                                                  reinterpret_cast<const double *>(tb + 2 * r.cnt), r.cnt, c0->nx,
+                                                  c0->ny, g.M1, g.M2, X, F + (size_t)(r.k0 - g.c0) * fsz, st);
+      }
+      size_t xmax = 0;
+      for (const CellGroup::Run &r : g.runs)
+        xmax = std::max(xmax, sizeof(double) * 8 * (size_t)cells[ord[r.k0]]->nx * nq * r.cnt);
+      tp += align256(xmax);
+      cd *Tm = reinterpret_cast<cd *>(tp);
+      tp += align256(sizeof(cd) * 3 * NN * cnt);
+      tp += align256(sizeof(cd) * 3 * NN * cnt);   // inverse factors
+      tp += 2 * align256(sizeof(cd) * 3 * NN * cnt);   // P
+      cd *Xm = reinterpret_cast<cd *>(tp);
+      void **dp = reinterpret_cast<void **>(W + g.t_ptrs);
+      if (e == hipSuccess) e = launch_toeplitz_scatter(F, g.M1, g.M2, g.N, Tm, cnt, st);
+      if (e == hipSuccess) e = launch_potrf_trtri((cd *const *)dp, (cd *const *)(dp + g.o_inv), gstat, 3 * cnt, g.N, st);
+      if (e == hipSuccess) e = launch_identity_if_failed((cd *const *)(dp + g.o_inv), gstat, 3 * cnt, g.N, st);
+      if (e == hipSuccess) {
+        GemmBatch bt{(const cd *const *)(dp + g.o_pA), (const cd *const *)(dp + g.o_pB), (cd *const *)(dp + g.o_pC),
+                     (const double *const *)(dp + g.o_pS), g.N, g.N, g.N};
+        e = launch_zgemm(OP_N, OP_C, g.N, g.N, g.N, mk(1.0, 0.0), bt, mk(0.0, 0.0), 6 * cnt, st);
+      }
+      if (e == hipSuccess) {
+        GemmBatch bt{(const cd *const *)(dp + g.o_xA), (const cd *const *)(dp + g.o_xB), (cd *const *)(dp + g.o_xC),
+                     nullptr, g.N, g.N, g.N};
+        e = launch_zgemm(OP_N, OP_C, g.N, g.N, g.N, mk(1.0, 0.0), bt, mk(0.0, 0.0), 18 * cnt, st);
+      }
+      if (e == hipSuccess)
+        e = launch_combine_batch(Xm, g.N, reinterpret_cast<const double *>(W + g.t_scale),
+                                 reinterpret_cast<cd *>(W + o_coef + g.o_coef), cnt, st);
+      gstat += 3 * cnt;
+    }
+    int *ctl = nullptr;
+    for (const CellChunk &ch : chunks) {
+      const int cnt = (int)(ch.j1 - ch.j0);
+      std::vector<int> orders(cnt);
+      for (int i = 0; i < cnt; ++i) orders[i] = order_of(jobs[ch.j0 + i]);
+      size_t item_sum = 0;
+      for (int n : orders) item_sum += item_bytes(n, n_bands, fp32);
+      ctl = reinterpret_cast<int *>(W + o_items + item_sum);
+      const EigItem *d_items = reinterpret_cast<const EigItem *>(W + ch.t_items);
+      Stage2Shape sh;
+      sh.group = ch.tp.group;
+      sh.wg_max = ch.tp.wg_max;
+      sh.spin_limit = ctx->spin_limit;
+      const int parts = std::max(1, std::min(ch.tp.parts, MAX_SIDE + 1));
+      const hipEvent_t *ev = ctx->cell_events.data() + (size_t)(&ch - chunks.data()) * (MAX_SIDE + 1);
+      if (e == hipSuccess)
+        e = enqueue_eigensolve(ctx, d_items, orders, true, false, n_bands, fp32, parts, sh, ctl, st, ev[0], ev + 1);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(gather_omega, dim3((cnt * n_bands + 255) / 256), dim3(256), 0, st, d_items, cnt, n_bands, om);
+        hipLaunchKernelGGL(max_acc, dim3(1), dim3(256), 0, st, d_items, cnt, ctx->accbuf.as<double>());
+        e = hipGetLastError();
+      }
+    }
+    return e;
+  };
+  // the graph of this shape (captured on first use)
+  std::string key;
+  {
+    auto put = [&](long long v) { key.append(reinterpret_cast<const char *>(&v), sizeof v); };
+    put(precision);
+    put(n_bands);
+    put(ctx->spin_limit);
+    put((long long)budget);
+    put(n_cells);
+    for (int s = 0; s < n_cells; ++s) {
+      const int i = ord[s];
+      put(M1[i]);
+      put(M2[i]);
+      put(cells[i]->nx);
+      put(cells[i]->ny);
+      put(n_k[i]);
+    }
+    for (const CellChunk &ch : chunks) {
+      put(ch.tp.parts);
+      put(ch.tp.group);
+      put(ch.tp.wg_max);
+    }
+  }
+  hipGraphExec_t exec = nullptr;
+  auto found = ctx->cell_graphs.find(key);
+  if (found == ctx->cell_graphs.end()) {
+    if (ctx->cell_graphs.size() >= MAX_CELL_GRAPHS) {
+      auto lru = ctx->cell_graphs.begin();
+      for (auto it = ctx->cell_graphs.begin(); it != ctx->cell_graphs.end(); ++it)
+        if (it->second.last_use < lru->second.last_use) lru = it;
+      HIP_TRY(hipStreamSynchronize(st));
+      (void)hipGraphExecDestroy(lru->second.exec);
+      ctx->cell_graphs.erase(lru);
+    }
+    hipGraph_t gr;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    Profiler *saved = t_prof;
+    t_prof = nullptr;  // no event records inside the captured graph
+    hipError_t e = enqueue();
+    t_prof = saved;
+    hipError_t e2 = hipStreamEndCapture(st, &gr);
+    if (e != hipSuccess) return set_err(MVPB_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return set_err(MVPB_E_DEVICE, "graph capture end: %s", hipGetErrorString(e2));
+    e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return set_err(MVPB_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    ctx->cell_graphs[key] = mvpb_ctx_s::GraphEntry{exec, ++ctx->graph_clock};
+  } else {
+    exec = found->second.exec;
+    found->second.last_use = ++ctx->graph_clock;
+  }
+  HIP_TRY(hipGraphLaunch(exec, st));
+  // results, then the factorisation status of every cell
+  const bool dev = flags & MVPB_F_DEVICE_PTRS;
+  for (int i = 0; i < n_cells; ++i) {
+    if (n_k[i] == 0) continue;
+    HIP_TRY(hipMemcpyAsync(omega[i], om + base[i] * n_bands, sizeof(double) * n_k[i] * n_bands,
+                           dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  }
+  std::vector<int> hstat(3 * (size_t)n_cells, 0);
+  HIP_TRY(hipMemcpyAsync(hstat.data(), stat, sizeof(int) * 3 * n_cells, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const char *names[3] = {"compliance block Phi(d11+d12)", "compliance block Phi(d11-d12)", "density matrix Omega"};
+  for (int i = 0; i < n_cells; ++i)
+    for (int m = 0; m < 3; ++m)
+      if (hstat[3 * (size_t)pos[i] + m])
+        return set_err(MVPB_E_NOT_PD, "cell %d: %s is not positive definite (pivot %d)", i, names[m],
+                       hstat[3 * (size_t)pos[i] + m] - 1);
+  if (!dev)
+    for (int i = 0; i < n_cells; ++i) {
+      rc = check_failed_items(omega[i], (size_t)n_k[i] * n_bands, n_bands);
+      if (rc) return rc;
+    }
+  return acc_finish(ctx, fp32);
 }
 
 extern "C" int mvpb_ctx_set_accuracy(mvpb_ctx ctx, double tol) {

@@ -555,10 +555,15 @@ hipError_t launch_toeplitz_scatter(const cd *F, int M1, int M2, int N, cd *T, in
 // all scaled by s = |Omega|^2 / 2.  Output order:
 //   0..2 A11, 3..5 A22, 6..8 A12, 9..11 A21, 12 S0, 13 D0, 14 G0.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) combine_coefficients(const cd *__restrict__ Xp, size_t NN, double s,
-                                                            cd *__restrict__ coef) {
+// blockIdx.y: cell of a batch (products 18 NN and coefficients 15 NN apart),
+// its scale scales[blockIdx.y] when a table is given.
+__global__ void __launch_bounds__(256) combine_coefficients(const cd *__restrict__ Xp0, size_t NN, double s0,
+                                                            const double *__restrict__ scales, cd *__restrict__ coef0) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= NN) return;
+  const cd *__restrict__ Xp = Xp0 + (size_t)blockIdx.y * 18 * NN;
+  cd *__restrict__ coef = coef0 + (size_t)blockIdx.y * 15 * NN;
+  const double s = scales ? scales[blockIdx.y] : s0;
 #define S_(l, m) Xp[(size_t)(0 * 9 + (l) * 3 + (m)) * NN + e]
 #define D_(l, m) Xp[(size_t)(1 * 9 + (l) * 3 + (m)) * NN + e]
   const cd s00 = S_(0, 0), s01 = S_(0, 1), s02 = S_(0, 2), s10 = S_(1, 0), s11 = S_(1, 1), s12 = S_(1, 2),
@@ -589,7 +594,15 @@ hipError_t launch_combine(const cd *Xp, int N, double s, cd *coef, hipStream_t s
   const size_t NN = (size_t)N * N;
   ProfScope ps(K_COMBINE, st);
   hipLaunchKernelGGL(combine_coefficients, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, st, Xp, NN, s,
-                     coef);
+                     (const double *)nullptr, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine_batch(const cd *Xp, int N, const double *scales, cd *coef, int count, hipStream_t st) {
+  const size_t NN = (size_t)N * N;
+  ProfScope ps(K_COMBINE, st);
+  hipLaunchKernelGGL(combine_coefficients, dim3((unsigned)((NN + 255) / 256), count), dim3(256), 0, st, Xp, NN, 0.0,
+                     scales, coef);
   return hipGetLastError();
 }
 

@@ -298,6 +298,26 @@ __global__ void clear_status(int *status, int count) {
   if (t < count) status[t] = 0;
 }
 
+// Inverse factors of the matrices whose factorisation stopped (status set)
+// replaced by the identity, so that work which follows them in one launch
+// sequence sees finite, well-conditioned input; the caller reports the
+// failure from the status words.
+__global__ void identity_if_failed(cd *const *Xarr, const int *status, int N) {
+  const int b = blockIdx.y;
+  if (!status[b]) return;
+  cd *X = Xarr[b];
+  const size_t total = (size_t)N * N;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % N), c = (int)(e / N);
+    X[e] = mk(r == c ? 1.0 : 0.0, 0.0);
+  }
+}
+
+hipError_t launch_identity_if_failed(cd *const *Linv, const int *status, int count, int N, hipStream_t st) {
+  hipLaunchKernelGGL(identity_if_failed, dim3(64, count), dim3(256), 0, st, Linv, status, N);
+  return hipGetLastError();
+}
+
 hipError_t launch_potrf_trtri(cd *const *A, cd *const *Linv, int *status, int count, int N, hipStream_t st) {
   ProfScope ps(K_POTRF, st);
   hipLaunchKernelGGL(clear_status, dim3((count + 255) / 256), dim3(256), 0, st, status, count);

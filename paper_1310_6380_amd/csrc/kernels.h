@@ -114,6 +114,8 @@ hipError_t launch_structure_factors_mfma_batch(int prec, const int32_t *const *p
                                                const double *areas, int count, int nx, int ny, int M1, int M2,
                                                double *X, cd *F, hipStream_t st);
 hipError_t launch_combine(const cd *Xp, int N, double s, cd *coef, hipStream_t st);
+// count cells: products Xp + c 18 N^2, coefficients coef + c 15 N^2, scale scales[c] (device)
+hipError_t launch_combine_batch(const cd *Xp, int N, const double *scales, cd *coef, int count, hipStream_t st);
 hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, bool fp32, hipStream_t st);
 
 // general.hip: general compliance and voxel cells (full Phi).
@@ -144,6 +146,7 @@ hipError_t launch_sensitivities(const cd *U, const cd *S, const double *omega, i
 // strict upper part zeroed).  status[b] = 0 on success, j+1 if the pivot of
 // column j was not positive.
 hipError_t launch_potrf_trtri(cd *const *A, cd *const *Linv, int *status, int count, int N, hipStream_t st);
+hipError_t launch_identity_if_failed(cd *const *Linv, const int *status, int count, int N, hipStream_t st);
 
 enum Op { OP_N = 0, OP_C = 1 };
 // Batched complex GEMM: C[b] = alpha * op(A[b]) * diag(s[b]) * op(B[b]) + beta * C[b].

@@ -54,7 +54,7 @@ EXPORTS = [
     "mvpb_sur_save", "mvpb_sur_load", "mvpb_structure_factors_noalloc", "mvpb_ctx_set_accuracy",
     "mvpb_ctx_last_accuracy", "mvpb_cell_create_voxels", "mvpb_plan_create3", "mvpb_structure_factors_general",
     "mvpb_band_sensitivities", "mvpb_autotune", "mvpb_ctx_load_tuning", "mvpb_ctx_set_wait_limit",
-    "mvpb_ctx_set_launch_shape", "mvpb_ctx_get_launch_shape",
+    "mvpb_ctx_set_launch_shape", "mvpb_ctx_get_launch_shape", "mvpb_solve_cells",
 ]
 N_KERNELS = 15
 
@@ -104,6 +104,8 @@ def load(path: str = LIB_PATH):
     lib.mvpb_solve.argtypes = [P, I, D, I, P, P, ctypes.c_uint]
     lib.mvpb_solve_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(D), I,
                                      ctypes.POINTER(P), ctypes.c_uint]
+    lib.mvpb_solve_cells.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I, ctypes.POINTER(I),
+                                     ctypes.POINTER(D), I, ctypes.POINTER(P), ctypes.c_uint]
     lib.mvpb_structure_factors.argtypes = [P, I, I, I, D]
     lib.mvpb_structure_factors_noalloc.argtypes = [P, I, I, I, P, ctypes.c_uint]
     lib.mvpb_kpath_square.argtypes = [I, D]
@@ -344,6 +346,22 @@ class Context:
             p.n_u, p.n_s = nu.value, ns.value
             res.append(p)
         return res
+
+    def solve_cells(self, cells, Ms, Qs, n_bands: int, precision: int = PREC_FP64) -> list:
+        """Bands of many pixel cells, plan build and eigensolve in one captured
+        graph (replayed by later calls of the same shape)."""
+        lib = load()
+        n = len(cells)
+        Qs = [np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1, 2)) for q in Qs]
+        outs = [np.zeros((q.shape[0], n_bands)) for q in Qs]
+        ch = (ctypes.c_void_p * n)(*[c.h for c in cells])
+        m1 = (ctypes.c_int * n)(*[int(M if np.isscalar(M) else M[0]) for M in Ms])
+        m2 = (ctypes.c_int * n)(*[int(M if np.isscalar(M) else M[1]) for M in Ms])
+        nk = (ctypes.c_int * n)(*[q.shape[0] for q in Qs])
+        qp = (ctypes.POINTER(ctypes.c_double) * n)(*[_dptr(q) for q in Qs])
+        op = (ctypes.c_void_p * n)(*[o.ctypes.data for o in outs])
+        _check(lib.mvpb_solve_cells(self.h, n, ch, m1, m2, precision, nk, qp, n_bands, op, 0))
+        return outs
 
     def solve_batch(self, plans, Qs, n_bands: int) -> list:
         lib = load()
