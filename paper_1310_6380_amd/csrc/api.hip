@@ -156,6 +156,10 @@ struct mvpb_ctx_s {
   // events of the fork from and the joins back to it
   hipStream_t side[MAX_SIDE] = {};
   hipEvent_t ev_fork = nullptr, ev_join[MAX_SIDE] = {};
+  // look-ahead streams of stage 1 (one per part) and the events of a launch
+  // sequence's steps (grow-only; a sequence never records one event twice)
+  hipStream_t la[MAX_SIDE + 1] = {};
+  std::vector<hipEvent_t> la_events;
   size_t cap = 0;
   Pool pool;          // declared before every buffer that returns to it
   DevBuf ws{&pool};      // per-solve workspace (grow-only)
@@ -213,6 +217,13 @@ static void ctx_free(mvpb_ctx c) {
     }
     if (c->ev_join[q]) (void)hipEventDestroy(c->ev_join[q]);
   }
+  for (int q = 0; q <= MAX_SIDE; ++q)
+    if (c->la[q]) {
+      (void)hipStreamSynchronize(c->la[q]);
+      (void)hipStreamDestroy(c->la[q]);
+    }
+  for (hipEvent_t ev : c->la_events) (void)hipEventDestroy(ev);
+  c->la_events.clear();
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -330,6 +341,7 @@ extern "C" int mvpb_ctx_create(int device, void *hip_stream, size_t workspace_ca
     e = hipStreamCreateWithFlags(&c->side[q], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[q], hipEventDisableTiming);
   }
+  for (int q = 0; q <= MAX_SIDE && e == hipSuccess; ++q) e = hipStreamCreateWithFlags(&c->la[q], hipStreamNonBlocking);
   // the running error estimate every eigensolve launch sequence updates
   if (e == hipSuccess) e = c->accbuf.reserve(sizeof(double));
   if (e == hipSuccess) e = hipMemsetAsync(c->accbuf.p, 0, sizeof(double), c->stream);
@@ -1523,6 +1535,22 @@ static std::string launch_signature(const std::vector<Job> &jobs, int nb, bool f
   return k;
 }
 
+// Events of the stage-1 steps of one eigensolve launch sequence over items of
+// order at most n_max in `parts` parts.
+static size_t la_events_needed(int n_max, int parts) { return (size_t)2 * parts * stage1_steps(n_max); }
+
+// Grow the context's step-event pool to at least `count` events (outside any
+// capture).
+static hipError_t reserve_la_events(mvpb_ctx ctx, size_t count) {
+  while (ctx->la_events.size() < count) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    ctx->la_events.push_back(ev);
+  }
+  return hipSuccess;
+}
+
 // The eigensolve launch sequence over the items of a device table whose
 // operator orders are `orders` (table order): operator formation, stage 1 in
 // independent parts on the context's streams, bulge chasing, tridiagonal
@@ -1531,7 +1559,7 @@ static std::string launch_signature(const std::vector<Job> &jobs, int nb, bool f
 static hipError_t enqueue_eigensolve(mvpb_ctx ctx, const EigItem *d_items, const std::vector<int> &orders,
                                      bool any_iso, bool any_general, int nb, bool fp32, int parts_wanted,
                                      const Stage2Shape &sh, int *ctl, hipStream_t st, hipEvent_t ev_fork,
-                                     const hipEvent_t *ev_join) {
+                                     const hipEvent_t *ev_join, const hipEvent_t *la_ev) {
   const int n_items = (int)orders.size();
   int n_max = 0, n_min = 1 << 30;
   for (int n : orders) {
@@ -1556,6 +1584,8 @@ static hipError_t enqueue_eigensolve(mvpb_ctx ctx, const EigItem *d_items, const
       pt.n_max = std::max(pt.n_max, orders[i]);
     }
     pt.stream = q == 0 ? st : ctx->side[q - 1];
+    pt.aside = ctx->la[q];
+    pt.ev = la_ev + (size_t)q * 2 * stage1_steps(n_max);
   }
   if (e == hipSuccess && n_parts > 1) {
     e = hipEventRecord(ev_fork, st);
@@ -1655,9 +1685,10 @@ static int run_items(mvpb_ctx ctx, const std::vector<Job> &jobs, int nb, double 
   std::vector<int> orders(n_items);
   for (int i = 0; i < n_items; ++i) orders[i] = jobs[i].plan->n;
   int *ctl = reinterpret_cast<int *>(ctx->ws.as<char>() + ctl_off);
+  HIP_TRY(reserve_la_events(ctx, la_events_needed(n_max, parts_wanted)));
   auto enqueue = [&]() -> hipError_t {
     return enqueue_eigensolve(ctx, d_items, orders, any_iso, any_general, nb, fp32, parts_wanted, sh, ctl, st,
-                              ctx->ev_fork, ctx->ev_join);
+                              ctx->ev_fork, ctx->ev_join, ctx->la_events.data());
   };
   if (use_graph) {
     const std::string graph_key = launch_signature(jobs, nb, fp32, parts_wanted, sh);
@@ -2339,6 +2370,11 @@ extern "C" int mvpb_solve_cells(mvpb_ctx ctx, int n_cells, const mvpb_cell *cell
     HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     ctx->cell_events.push_back(ev);
   }
+  // step events of the chunks' stage 1, one range per chunk
+  std::vector<size_t> la_base(chunks.size() + 1, 0);
+  for (size_t c = 0; c < chunks.size(); ++c)
+    la_base[c + 1] = la_base[c] + la_events_needed(order_of(jobs[chunks[c].j0]), MAX_SIDE + 1);
+  HIP_TRY(reserve_la_events(ctx, la_base[chunks.size()]));
   rc = acc_begin(ctx);
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(W, stage.data(), tab, hipMemcpyHostToDevice, st));
@@ -2408,7 +2444,8 @@ extern "C" int mvpb_solve_cells(mvpb_ctx ctx, int n_cells, const mvpb_cell *cell
       const int parts = std::max(1, std::min(ch.tp.parts, MAX_SIDE + 1));
       const hipEvent_t *ev = ctx->cell_events.data() + (size_t)(&ch - chunks.data()) * (MAX_SIDE + 1);
       if (e == hipSuccess)
-        e = enqueue_eigensolve(ctx, d_items, orders, true, false, n_bands, fp32, parts, sh, ctl, st, ev[0], ev + 1);
+        e = enqueue_eigensolve(ctx, d_items, orders, true, false, n_bands, fp32, parts, sh, ctl, st, ev[0], ev + 1,
+                               ctx->la_events.data() + la_base[&ch - chunks.data()]);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(gather_omega, dim3((cnt * n_bands + 255) / 256), dim3(256), 0, st, d_items, cnt, n_bands, om);
         hipLaunchKernelGGL(max_acc, dim3(1), dim3(256), 0, st, d_items, cnt, ctx->accbuf.as<double>());

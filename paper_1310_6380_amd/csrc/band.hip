@@ -593,12 +593,19 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
 }
 
 // ---------------------------------------------------------------------------
-// Stage 1c.  W = X0 T - V Y / 2 with Y = T^H (V^H X0) T, for row block rb.
+// Stage 1c.  W = X0 T - V Y / 2 with Y = T^H (V^H X0) T, for row block rb;
+// then this block's rows of the next panel's columns (the first HB columns of
+// A22, its diagonal block included) get the update of panel p at once,
+// A22(r, c) -= W(r) V(c)^H + V(r) W(c)^H for c < HB, r >= c, so that the
+// next panel can be factored while the rest of A22 is updated.  Every
+// workgroup forms W of rows 0 .. HB-1 itself for the second term.
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ items, int n_items, int S, int p) {
   typedef cx<R> C;
   __shared__ C G[HB][HB + 1], Tm[HB][HB + 1], Q1[HB][HB + 1], Y[HB][HB + 1];
+  __shared__ C Wr[64][HB + 1];                                    // W of the block's rows
+  __shared__ C X0t[HB][HB + 1], V0[HB][HB + 1], W0[HB][HB + 1];   // rows 0 .. HB-1
   int item, rb;
   if (!xcd_slot(S, n_items, item, rb)) return;
   const EigItem it = items[item];
@@ -610,12 +617,18 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
   const int nrb = (m + 63) / 64;
   const C *M0p = (const C *)it.M0p;
   const C *T1 = (const C *)it.T1 + (size_t)p * HB * HB;
+  const C *X0 = (const C *)it.X0;
+  const C *Vp = (const C *)it.A + (size_t)c0 * ld + (c0 + HB);
+  C *A22 = (C *)it.A + (size_t)(c0 + HB) * ld + (c0 + HB);
+  C *Wm = (C *)it.Wm;
   for (int e = tid; e < HB * HB; e += 256) {
     const int i = e % HB, jx = e / HB;
     C s = czero<R>();
     for (int b = 0; b < nrb; ++b) s = s + gld(M0p, (size_t)b * HB * HB + e);
     G[i][jx] = s;
     Tm[i][jx] = gld(T1, e);
+    X0t[i][jx] = i < m ? gld(X0, (size_t)jx * ld + i) : czero<R>();
+    V0[i][jx] = panel_v<R>(Vp, ld, i, jx, m, kq);
   }
   __syncthreads();
   for (int e = tid; e < HB * HB; e += 256) {
@@ -632,16 +645,13 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
     Y[i][jx] = s;
   }
   __syncthreads();
-  const C *X0 = (const C *)it.X0;
-  const C *Vp = (const C *)it.A + (size_t)c0 * ld + (c0 + HB);
-  C *Wm = (C *)it.Wm;
   const int rr = tid & 63, tq = tid >> 6;
   const int r = rb * 64 + rr;
-  if (r >= m) return;
+  const bool live = r < m;
   C xr[HB], vr[HB];
 #pragma unroll
   for (int t = 0; t < HB; ++t) {
-    xr[t] = gld(X0, (size_t)t * ld + r);
+    xr[t] = ld_or0<R>(X0, (size_t)t * ld + r, live);
     vr[t] = panel_v<R>(Vp, ld, r, t, m, kq);
   }
 #pragma unroll
@@ -653,12 +663,40 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
       if (l <= t) s = cfma(xr[l], Tm[l][t], s);
       s = s - R(0.5) * (vr[l] * Y[l][t]);
     }
-    gst(Wm, (size_t)t * ld + r, s);
+    Wr[rr][t] = s;
+    if (live) gst(Wm, (size_t)t * ld + r, s);
+  }
+  for (int e = tid; e < HB * HB; e += 256) {
+    const int i = e % HB, t = e / HB;
+    C s = czero<R>();
+#pragma unroll
+    for (int l = 0; l < HB; ++l) {
+      if (l <= t) s = cfma(X0t[i][l], Tm[l][t], s);
+      s = s - R(0.5) * (V0[i][l] * Y[l][t]);
+    }
+    W0[i][t] = s;
+  }
+  __syncthreads();
+  // the next panel's columns c < kq, rows r >= c of this block
+#pragma unroll
+  for (int cc = 0; cc < HB / 4; ++cc) {
+    const int c = tq * (HB / 4) + cc;
+    if (live && c < kq && r >= c) {
+      C x = gld(A22, (size_t)c * ld + r);
+#pragma unroll
+      for (int k = 0; k < HB; ++k) {
+        x = x - Wr[rr][k] * conj(V0[c][k]);
+        x = x - vr[k] * conj(W0[c][k]);
+      }
+      if (r == c) x.im = R(0);
+      gst(A22, (size_t)c * ld + r, x);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Stage 1d.  A22 <- A22 - W V^H - V W^H on the lower 64 x 64 tiles, on the
+// Stage 1d.  A22 <- A22 - W V^H - V W^H on the lower 64 x 64 tiles of
+// A22[HB:, HB:] (the first HB columns had it from the W formation), on the
 // matrix cores.  The update D = W V^H + V W^H is Hermitian: the product is
 // formed for the transposed position, Out[c][r] = D[c][r] (columns of the
 // tile as the M index), so that a lane's outputs D[r][c] = conj(Out[c][r])
@@ -676,8 +714,9 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
   if (!xcd_slot(S, n_items, item, t)) return;
   const EigItem it = items[item];
   const int n = it.n, c0 = p * HB, m = n - c0 - HB;
-  if (m <= 0) return;
-  const int nt = (m + 63) / 64;
+  const int mt = m - HB;   // order of the updated part A22[HB:, HB:]; its rows are factor rows + HB
+  if (mt <= 0) return;
+  const int nt = (mt + 63) / 64;
   if (t >= nt * (nt + 1) / 2) return;
   int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -685,7 +724,7 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
   const int J = t - I * (I + 1) / 2;
   const int kq = min(m, HB);
   const size_t ld = (size_t)n;
-  C *__restrict__ A22 = (C *)it.A + (size_t)(c0 + HB) * ld + (c0 + HB);
+  C *__restrict__ A22 = (C *)it.A + (size_t)(c0 + 2 * HB) * ld + (c0 + 2 * HB);
   const C *__restrict__ Vp = (const C *)it.A + (size_t)c0 * ld + (c0 + HB);
   const C *__restrict__ Wm = (const C *)it.Wm;
   const int r0 = I * 64, cc0 = J * 64;
@@ -700,12 +739,12 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gc = cc0 + 16 * wv + M::row(lane, v);
-      cur[rb][v] = ld_raw<R>(A22, (size_t)gc * ld + gr, gc < m && gr < m);   // stored only in bounds
+      cur[rb][v] = ld_raw<R>(A22, (size_t)gc * ld + gr, gc < mt && gr < mt);   // stored only in bounds
     }
   }
   for (int e = tid; e < 64 * HB; e += 256) {
     const int i = e & 63, k = e >> 6;
-    const int gr = r0 + i, gc = cc0 + i;
+    const int gr = r0 + i + HB, gc = cc0 + i + HB;   // factor rows
     const bool kr = k < kq;
     Vr[k][i] = panel_v<R>(Vp, ld, gr, k, m, kq);
     Wr[k][i] = ld_or0<R>(Wm, (size_t)k * ld + gr, gr < m && kr);
@@ -739,7 +778,7 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gc = cc0 + 16 * wv + M::row(lane, v);
-      if (gc < m && gr < m) {
+      if (gc < mt && gr < mt) {
         const R ore = p1[rb][v] - p2[rb][v], oim = p3[rb][v] - p1[rb][v] - p2[rb][v];
         const C d = mkc<R>(ore, -oim);   // D[r][c] = conj(Out[c][r])
         gst(A22, (size_t)gc * ld + gr, cur[rb][v] - d);
@@ -1495,17 +1534,22 @@ static int device_cus() {
 
 // Stage 1 of every part, step by step: the parts are independent sets of
 // items on their own streams, so that one part's latency-bound panel overlaps
-// the other's bandwidth-bound trailing update.
+// the other's bandwidth-bound trailing update.  Within a part, panel p+1
+// (whose columns the W formation of panel p has updated) is factored on the
+// part's stream while the rest of the trailing matrix gets the update of
+// panel p on the part's look-ahead stream; the product with the trailing
+// matrix of panel p+1 waits for both.
 template <typename R>
 static hipError_t launch_stage1_t(const ItemPart *parts, int n_parts) {
   int steps = 0;
-  for (int q = 0; q < n_parts; ++q) steps = std::max(steps, (parts[q].n_max - 1) / HB + 1);
-  for (int p = 0; p < steps; ++p) {
-    for (int q = 0; q < n_parts; ++q) {
+  for (int q = 0; q < n_parts; ++q) steps = std::max(steps, stage1_steps(parts[q].n_max));
+  hipError_t e = hipSuccess;
+  for (int p = 0; p < steps && e == hipSuccess; ++p) {
+    for (int q = 0; q < n_parts && e == hipSuccess; ++q) {
       const ItemPart &pt = parts[q];
       const EigItem *items = pt.items;
       const int n_items = pt.n_items;
-      hipStream_t st = pt.stream;
+      hipStream_t st = pt.stream, sa = pt.aside;
       const int c0 = p * HB, m = pt.n_max - c0 - HB;
       if (n_items <= 0 || m <= 0) continue;
       const int m_lo = std::max(1, pt.n_min - c0 - HB);
@@ -1516,6 +1560,8 @@ static hipError_t launch_stage1_t(const ItemPart *parts, int n_parts) {
         launch_panel_class<R, 4, 4, 512, 1024>(items, n_items, p, m_lo, m, st);
         launch_panel_class<R, 8, 2, 512, 2048>(items, n_items, p, m_lo, m, st);
       }
+      if (p > 0) e = hipStreamWaitEvent(st, pt.ev[2 * (p - 1) + 1], 0);   // update of panel p-1 done
+      if (e != hipSuccess) break;
       const int nrb = (m + 63) / 64;
       {
         ProfScope ps(K_HEMM, st);
@@ -1525,13 +1571,24 @@ static hipError_t launch_stage1_t(const ItemPart *parts, int n_parts) {
         ProfScope ps(K_WFORM, st);
         hipLaunchKernelGGL((he2hb_wform<R>), dim3(xcd_grid(nrb, n_items)), dim3(256), 0, st, items, n_items, nrb, p);
       }
-      {
-        ProfScope ps(K_HER2K, st);
-        const int ntile = nrb * (nrb + 1) / 2;
-        hipLaunchKernelGGL((he2hb_her2k<R>), dim3(xcd_grid(ntile, n_items)), dim3(256), 0, st, items, n_items, ntile, p);
+      e = hipEventRecord(pt.ev[2 * p], st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(sa, pt.ev[2 * p], 0);
+      if (e != hipSuccess) break;
+      const int nrt = (m - HB + 63) / 64;
+      if (nrt > 0) {
+        ProfScope ps(K_HER2K, sa);
+        const int ntile = nrt * (nrt + 1) / 2;
+        hipLaunchKernelGGL((he2hb_her2k<R>), dim3(xcd_grid(ntile, n_items)), dim3(256), 0, sa, items, n_items, ntile, p);
       }
+      e = hipEventRecord(pt.ev[2 * p + 1], sa);
     }
   }
+  // every part's stream waits for its last update
+  for (int q = 0; q < n_parts && e == hipSuccess; ++q) {
+    const int ns = stage1_steps(parts[q].n_max);
+    if (parts[q].n_items > 0 && ns > 0) e = hipStreamWaitEvent(parts[q].stream, parts[q].ev[2 * (ns - 1) + 1], 0);
+  }
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

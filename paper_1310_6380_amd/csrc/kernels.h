@@ -170,9 +170,17 @@ struct ItemPart {
   const EigItem *items = nullptr;
   int n_items = 0, n_min = 0, n_max = 0;
   hipStream_t stream = nullptr;
+  // look-ahead: the trailing update of panel p runs on `aside` while panel
+  // p+1 is factored on `stream`; ev holds 2 stage1_steps(n_max) events
+  // (W of panel p formed, update of panel p done), each recorded once
+  hipStream_t aside = nullptr;
+  const hipEvent_t *ev = nullptr;
 };
+// Panels of stage 1 for an operator of order n (those with rows below the band).
+inline int stage1_steps(int n) { return n > HB ? (n - HB - 1) / HB + 1 : 0; }
 // Reduction to band form (stage 1) of every part, the parts' launches
-// interleaved step by step on their own streams.
+// interleaved step by step on their own streams; every part's `stream` has
+// waited for its `aside` stream when the call returns.
 hipError_t launch_stage1(const ItemPart *parts, int n_parts, bool fp32);
 // Band to tridiagonal (stage 2, bulge chasing) and d, e of all items; ctl
 // points to hb2st_ctl_ints(n_items) ints of device memory.  Launch shape:
