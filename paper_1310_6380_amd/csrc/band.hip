@@ -603,9 +603,11 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
 template <typename R>
 __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ items, int n_items, int S, int p) {
   typedef cx<R> C;
-  __shared__ C G[HB][HB + 1], Tm[HB][HB + 1], Q1[HB][HB + 1], Y[HB][HB + 1];
-  __shared__ C Wr[64][HB + 1];                                    // W of the block's rows
-  __shared__ C X0t[HB][HB + 1], V0[HB][HB + 1], W0[HB][HB + 1];   // rows 0 .. HB-1
+  typedef CMma<R> M;
+  typedef typename M::acc A4;
+  // G holds W of rows 0 .. HB-1 once Q1 is formed
+  __shared__ C G[HB][HB + 1], Tm[HB][HB + 1], Q1[HB][HB + 1], Y[HB][HB + 1], V0[HB][HB + 1];
+  __shared__ C Wr[64][HB + 1];   // W of the block's rows
   int item, rb;
   if (!xcd_slot(S, n_items, item, rb)) return;
   const EigItem it = items[item];
@@ -613,7 +615,8 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
   if (m <= 0 || rb * 64 >= m) return;
   const int kq = min(m, HB);
   const size_t ld = (size_t)n;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int ai = lane & 15, ak = lane >> 4;
   const int nrb = (m + 63) / 64;
   const C *M0p = (const C *)it.M0p;
   const C *T1 = (const C *)it.T1 + (size_t)p * HB * HB;
@@ -621,75 +624,84 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
   const C *Vp = (const C *)it.A + (size_t)c0 * ld + (c0 + HB);
   C *A22 = (C *)it.A + (size_t)(c0 + HB) * ld + (c0 + HB);
   C *Wm = (C *)it.Wm;
-  for (int e = tid; e < HB * HB; e += 256) {
-    const int i = e % HB, jx = e / HB;
+  {
+    const int i = tid % HB, jx = tid / HB;   // 256 threads = HB x HB
     C s = czero<R>();
-    for (int b = 0; b < nrb; ++b) s = s + gld(M0p, (size_t)b * HB * HB + e);
+    for (int b = 0; b < nrb; ++b) s = s + gld(M0p, (size_t)b * HB * HB + tid);
     G[i][jx] = s;
-    Tm[i][jx] = gld(T1, e);
-    X0t[i][jx] = i < m ? gld(X0, (size_t)jx * ld + i) : czero<R>();
+    Tm[i][jx] = gld(T1, tid);
     V0[i][jx] = panel_v<R>(Vp, ld, i, jx, m, kq);
   }
   __syncthreads();
-  for (int e = tid; e < HB * HB; e += 256) {
-    const int i = e % HB, jx = e / HB;
+  {
+    const int i = tid % HB, jx = tid / HB;
     C s = czero<R>();
     for (int l = 0; l <= jx; ++l) s = cfma(G[i][l], Tm[l][jx], s);
     Q1[i][jx] = s;
   }
   __syncthreads();
-  for (int e = tid; e < HB * HB; e += 256) {
-    const int i = e % HB, jx = e / HB;
+  {
+    const int i = tid % HB, jx = tid / HB;
     C s = czero<R>();
     for (int l = 0; l <= i; ++l) s = cfma_cj(Tm[l][i], Q1[l][jx], s);
     Y[i][jx] = s;
   }
   __syncthreads();
-  const int rr = tid & 63, tq = tid >> 6;
-  const int r = rb * 64 + rr;
-  const bool live = r < m;
-  C xr[HB], vr[HB];
+  // W = X0 T - V Y / 2 for 16 rows r0 .. r0+15 on the matrix cores (T is upper
+  // triangular and zero-padded, so the full products are exact); a lane ends
+  // with W(r0 + M::row(lane, v), ai)
+  auto wrows = [&](int r0, A4 &p1, A4 &p2, A4 &p3) {
+    p1 = M::zero();
+    p2 = M::zero();
+    p3 = M::zero();
+    const int ra = r0 + ai;
 #pragma unroll
-  for (int t = 0; t < HB; ++t) {
-    xr[t] = ld_or0<R>(X0, (size_t)t * ld + r, live);
-    vr[t] = panel_v<R>(Vp, ld, r, t, m, kq);
-  }
-#pragma unroll
-  for (int tt = 0; tt < HB / 4; ++tt) {
-    const int t = tq * (HB / 4) + tt;
-    C s = czero<R>();
-#pragma unroll
-    for (int l = 0; l < HB; ++l) {
-      if (l <= t) s = cfma(xr[l], Tm[l][t], s);
-      s = s - R(0.5) * (vr[l] * Y[l][t]);
+    for (int k0 = 0; k0 < HB; k0 += 4) {
+      const C a = ld_or0<R>(X0, (size_t)(k0 + ak) * ld + ra, ra < m);
+      M::step3(a, Tm[k0 + ak][ai], p1, p2, p3);
     }
-    Wr[rr][t] = s;
-    if (live) gst(Wm, (size_t)t * ld + r, s);
-  }
-  for (int e = tid; e < HB * HB; e += 256) {
-    const int i = e % HB, t = e / HB;
-    C s = czero<R>();
 #pragma unroll
-    for (int l = 0; l < HB; ++l) {
-      if (l <= t) s = cfma(X0t[i][l], Tm[l][t], s);
-      s = s - R(0.5) * (V0[i][l] * Y[l][t]);
+    for (int k0 = 0; k0 < HB; k0 += 4) {
+      const C a = panel_v<R>(Vp, ld, ra, k0 + ak, m, kq);
+      M::step3(a, R(-0.5) * Y[k0 + ak][ai], p1, p2, p3);
     }
-    W0[i][t] = s;
+  };
+  {
+    A4 p1, p2, p3;
+    wrows(64 * rb + 16 * wv, p1, p2, p3);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = 16 * wv + M::row(lane, v), r = 64 * rb + rr;
+      const C w = mkc<R>(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
+      Wr[rr][ai] = w;
+      if (r < m) gst(Wm, (size_t)ai * ld + r, w);
+    }
+  }
+  if (wv == 0) {   // W of rows 0 .. HB-1 into G (no longer needed)
+    A4 p1, p2, p3;
+    wrows(0, p1, p2, p3);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) G[M::row(lane, v)][ai] = mkc<R>(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
   }
   __syncthreads();
-  // the next panel's columns c < kq, rows r >= c of this block
+  // this block's rows of the next panel's columns c < kq (r >= c):
+  // A22(r, c) -= sum_k W(r, k) conj(V(c, k)) + V(r, k) conj(W(c, k))
+  {
+    A4 p1 = M::zero(), p2 = M::zero(), p3 = M::zero();
+    const int ra = 64 * rb + 16 * wv + ai;
 #pragma unroll
-  for (int cc = 0; cc < HB / 4; ++cc) {
-    const int c = tq * (HB / 4) + cc;
-    if (live && c < kq && r >= c) {
-      C x = gld(A22, (size_t)c * ld + r);
+    for (int k0 = 0; k0 < HB; k0 += 4) M::step3(Wr[16 * wv + ai][k0 + ak], conj(V0[ai][k0 + ak]), p1, p2, p3);
 #pragma unroll
-      for (int k = 0; k < HB; ++k) {
-        x = x - Wr[rr][k] * conj(V0[c][k]);
-        x = x - vr[k] * conj(W0[c][k]);
+    for (int k0 = 0; k0 < HB; k0 += 4)
+      M::step3(panel_v<R>(Vp, ld, ra, k0 + ak, m, kq), conj(G[ai][k0 + ak]), p1, p2, p3);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 64 * rb + 16 * wv + M::row(lane, v), c = ai;
+      if (r < m && c < kq && r >= c) {
+        C x = gld(A22, (size_t)c * ld + r) - mkc<R>(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
+        if (r == c) x.im = R(0);
+        gst(A22, (size_t)c * ld + r, x);
       }
-      if (r == c) x.im = R(0);
-      gst(A22, (size_t)c * ld + r, x);
     }
   }
 }
