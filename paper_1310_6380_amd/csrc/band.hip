@@ -489,10 +489,11 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
   // Raw values with per-element flags (bit 0: in range, bit 1: read
   // transposed, so conjugate; bit 2: diagonal, so real), applied at the LDS
   // store so that the loads stay in flight during the products.
-  // Two register buffers: the loads of the next two column blocks are in
-  // flight while one block is multiplied.
-  C nxA[PER], vnA[2], nxB[PER], vnB[2];
-  unsigned flA = 0, flB = 0;
+  // One register buffer: the loads of the next column block are in flight
+  // while this one is multiplied (a second buffer gained nothing: the loop
+  // head waits for every outstanding load).
+  C nxA[PER], vnA[2];
+  unsigned flA = 0;
   auto fetch = [&](int cb0, C (&nxt)[PER], C (&vnx)[2], unsigned &fl) {
     const bool above = cb0 >= r0 + 64;   // entirely right of the diagonal block
     fl = 0;
@@ -547,19 +548,14 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
       M::step3(a, b, p1, p2, p3);
     }
   };
-  // blocks past the end are fetched from clamped addresses and never used
+  // one block ahead: the loads of the next block are in flight during the
+  // products of this one (blocks past the end are fetched from clamped
+  // addresses and never used)
   fetch(0, nxA, vnA, flA);
-  fetch(TC, nxB, vnB, flB);
-  for (int cb0 = 0; cb0 < m; cb0 += 2 * TC) {
+  for (int cb0 = 0; cb0 < m; cb0 += TC) {
     stage(cb0, nxA, vnA, flA);
     lds_barrier();
-    fetch(cb0 + 2 * TC, nxA, vnA, flA);
-    products();
-    lds_barrier();
-    if (cb0 + TC >= m) break;
-    stage(cb0 + TC, nxB, vnB, flB);
-    lds_barrier();
-    fetch(cb0 + 3 * TC, nxB, vnB, flB);
+    fetch(cb0 + TC, nxA, vnA, flA);
     products();
     lds_barrier();
   }
@@ -626,9 +622,17 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
   C *Wm = (C *)it.Wm;
   {
     const int i = tid % HB, jx = tid / HB;   // 256 threads = HB x HB
-    C s = czero<R>();
-    for (int b = 0; b < nrb; ++b) s = s + gld(M0p, (size_t)b * HB * HB + tid);
-    G[i][jx] = s;
+    // the row blocks' partials in four independent chains (loads in flight together)
+    C s0 = czero<R>(), s1 = czero<R>(), s2 = czero<R>(), s3 = czero<R>();
+    int b = 0;
+    for (; b + 4 <= nrb; b += 4) {
+      s0 = s0 + gld(M0p, (size_t)b * HB * HB + tid);
+      s1 = s1 + gld(M0p, (size_t)(b + 1) * HB * HB + tid);
+      s2 = s2 + gld(M0p, (size_t)(b + 2) * HB * HB + tid);
+      s3 = s3 + gld(M0p, (size_t)(b + 3) * HB * HB + tid);
+    }
+    for (; b < nrb; ++b) s0 = s0 + gld(M0p, (size_t)b * HB * HB + tid);
+    G[i][jx] = (s0 + s1) + (s2 + s3);
     Tm[i][jx] = gld(T1, tid);
     V0[i][jx] = panel_v<R>(Vp, ld, i, jx, m, kq);
   }
