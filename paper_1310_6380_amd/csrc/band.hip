@@ -450,6 +450,8 @@ struct CMma<float> {
 // fetched into one or two of the XCDs' L2 caches instead of all eight.  The
 // mapping is a bijection for any placement; only the cache reuse depends on it.
 constexpr int N_XCD = 8;
+// Column-block width of the trailing-matrix product (LDS tile 64 x HEMM_TC)
+constexpr int HEMM_TC = 32;
 MVPB_DEV bool xcd_slot(int S, int n_items, int &item, int &slot) {
   const int total = n_items * S, per = (total + N_XCD - 1) / N_XCD;
   const int b = (int)blockIdx.x;
@@ -468,8 +470,10 @@ template <typename R>
 __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ items, int n_items, int S, int p) {
   typedef cx<R> C;
   typedef CMma<R> M;
-  constexpr int TC = 32;
+  constexpr int TC = HEMM_TC;
   constexpr int PER = 64 * TC / 256;   // tile elements loaded per thread
+  constexpr int VPER = TC * HB / 256;  // reflector elements loaded per thread
+  static_assert(3 * PER + 2 * VPER <= 64, "element flags fit one 64-bit word");
   __shared__ C tile[TC][65];        // tile[cc][rr] = A22(rb*64 + rr, cb*TC + cc); X0 of the block at the end
   __shared__ C Vc[TC][HB + 1];      // V rows of the column block
   int item, rb;
@@ -492,9 +496,9 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
   // One register buffer: the loads of the next column block are in flight
   // while this one is multiplied (a second buffer gained nothing: the loop
   // head waits for every outstanding load).
-  C nxA[PER], vnA[2];
-  unsigned flA = 0;
-  auto fetch = [&](int cb0, C (&nxt)[PER], C (&vnx)[2], unsigned &fl) {
+  C nxA[PER], vnA[VPER];
+  unsigned long long flA = 0;
+  auto fetch = [&](int cb0, C (&nxt)[PER], C (&vnx)[VPER], unsigned long long &fl) {
     const bool above = cb0 >= r0 + 64;   // entirely right of the diagonal block
     fl = 0;
 #pragma unroll
@@ -506,35 +510,35 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
       const bool in = gr < m && gc < m, lower = gr >= gc;
       const size_t idx = lower ? (size_t)gc * ld + gr : (size_t)gr * ld + gc;
       nxt[u] = ld_raw<R>(A22, idx, in);
-      fl |= ((in ? 1u : 0u) | (lower ? 0u : 2u) | (gr == gc ? 4u : 0u)) << (3 * u);
+      fl |= (unsigned long long)((in ? 1u : 0u) | (lower ? 0u : 2u) | (gr == gc ? 4u : 0u)) << (3 * u);
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < VPER; ++u) {
       const int e = tid + 256 * u;
       const int r = cb0 + e % TC, t = e / TC;
       const bool in = r < m && t < kq;
       vnx[u] = ld_raw<R>(Vp, (size_t)t * ld + r, in && r > t);
-      fl |= ((in && r > t) ? 1u : 0u) << (24 + 2 * u);
-      fl |= ((in && r == t) ? 1u : 0u) << (25 + 2 * u);
+      fl |= (unsigned long long)((in && r > t) ? 1u : 0u) << (3 * PER + 2 * u);
+      fl |= (unsigned long long)((in && r == t) ? 1u : 0u) << (3 * PER + 1 + 2 * u);
     }
   };
-  auto stage = [&](int cb0, const C (&nxt)[PER], const C (&vnx)[2], unsigned fl) {
+  auto stage = [&](int cb0, const C (&nxt)[PER], const C (&vnx)[VPER], unsigned long long fl) {
     const bool above = cb0 >= r0 + 64;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 256 * u;
       int rr, cc;
       if (above) { cc = e % TC; rr = e / TC; } else { rr = e & 63; cc = e >> 6; }
-      const unsigned f = fl >> (3 * u);
+      const unsigned f = (unsigned)(fl >> (3 * u));
       C v = nxt[u];
       if (f & 2u) v.im = -v.im;
       if (f & 4u) v.im = R(0);
       tile[cc][rr] = (f & 1u) ? v : czero<R>();
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < VPER; ++u) {
       const int e = tid + 256 * u;
-      const unsigned f = fl >> (24 + 2 * u);
+      const unsigned f = (unsigned)(fl >> (3 * PER + 2 * u));
       Vc[e % TC][e / TC] = (f & 1u) ? vnx[u] : ((f & 2u) ? mkc<R>(R(1), R(0)) : czero<R>());
     }
   };
@@ -559,33 +563,32 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
     products();
     lds_barrier();
   }
-  // X0 rows of this block: lane holds D[row][t = lane % 16]
+  // X0 rows of this block (a lane holds D[16 wv + M::row(lane, v)][lane % 16])
+  // and the Gram partial G[i][t] = sum over the block's rows of conj(V[r][i])
+  // X0[r][t] on the matrix cores: the accumulators are the B operand as they
+  // stand (K = the lane's rows)
   C *X0 = (C *)it.X0;
-  C *X0s = &tile[0][0];   // [64][HB + 1]
+  typename M::acc g1 = M::zero(), g2 = M::zero(), g3 = M::zero();
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int rr = 16 * wv + M::row(lane, v), t = lane & 15;
+    const int rr = 16 * wv + M::row(lane, v);
     const C x = mkc<R>(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
-    X0s[rr * (HB + 1) + t] = x;
-    if (r0 + rr < m) gst(X0, (size_t)t * ld + r0 + rr, x);
+    if (r0 + rr < m) gst(X0, (size_t)ai * ld + r0 + rr, x);
+    M::step3(conj(panel_v<R>(Vp, ld, r0 + rr, ai, m, kq)), x, g1, g2, g3);
   }
-  // Gram partial G[i][j] = sum_rr conj(V[rr][i]) X0[rr][j]; V rows of the block in Vc
+  // the four wavefronts' partials summed in LDS (the tile is free)
+  static_assert(4 * HB * HB <= TC * 65, "Gram partials fit the tile buffer");
+  C *Gs = &tile[0][0];   // [wave][i][t]
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    Gs[(wv * HB + M::row(lane, v)) * HB + ai] = mkc<R>(g1[v] - g2[v], g3[v] - g1[v] - g2[v]);
   lds_barrier();
-  C *Vr = &Vc[0][0];   // [64][HB] would not fit: two passes of 32 rows
-  C *M0p = (C *)it.M0p + (size_t)rb * HB * HB;
-  C gsum = czero<R>();
-  const int gi = tid % HB, gj = tid / HB;   // 256 threads = HB x HB
-  for (int h = 0; h < 2; ++h) {
-    for (int e = tid; e < 32 * HB; e += 256) {
-      const int i = e % 32, t = e / 32;
-      Vr[i * (HB + 1) + t] = panel_v<R>(Vp, ld, r0 + 32 * h + i, t, m, kq);
-    }
-    lds_barrier();
-    for (int rr = 0; rr < 32; ++rr)
-      gsum = cfma_cj(Vr[rr * (HB + 1) + gi], X0s[(32 * h + rr) * (HB + 1) + gj], gsum);
-    lds_barrier();
+  {
+    const int i = tid % HB, tt = tid / HB;   // 256 threads = HB x HB
+    const C sum = Gs[(0 * HB + i) * HB + tt] + Gs[(1 * HB + i) * HB + tt] + Gs[(2 * HB + i) * HB + tt] +
+                  Gs[(3 * HB + i) * HB + tt];
+    gst((C *)it.M0p + (size_t)rb * HB * HB, (size_t)i + (size_t)tt * HB, sum);
   }
-  gst(M0p, (size_t)gi + (size_t)gj * HB, gsum);
 }
 
 // ---------------------------------------------------------------------------
