@@ -369,7 +369,7 @@ int mvpb_autotune(mvpb_plan plan, int n_k, const double *Q, int n_bands, const c
 int mvpb_ctx_load_tuning(mvpb_ctx ctx, const char *path, int *n_loaded);
 /* The launch shape of the size class of operator order n, set explicitly
  * (parts 1..4, group 0 (= 8), 1, 2, 4 or 8, wg_max 0 (= 4) .. 4) or read
- * back (defaults 2, 0, 0 when the class has none). */
+ * back (defaults 1, 0, 0 when the class has none). */
 int mvpb_ctx_set_launch_shape(mvpb_ctx ctx, int n, int parts, int group, int wg_max);
 int mvpb_ctx_get_launch_shape(mvpb_ctx ctx, int n, int *parts, int *group, int *wg_max);
 

@@ -141,7 +141,7 @@ constexpr int MAX_SIDE = 3;
 // Launch shape of the eigensolve for one size class of operators (chosen by
 // mvpb_autotune or loaded from its cache; defaults otherwise).
 struct TuneParams {
-  int parts = 2;    // stage-1 parts (streams)
+  int parts = 1;    // stage-1 parts (each on a stream and a look-ahead stream)
   int group = 0;    // bulge chasing: sweeps per workgroup group (0: 8)
   int wg_max = 0;   // bulge chasing: most workgroups per item (0: 4)
 };
@@ -2711,7 +2711,7 @@ extern "C" int mvpb_autotune(mvpb_plan p, int n_k, const double *Q, int n_bands,
   TuneParams best;
   double best_t = 0.0;
   int rc = trial(best, &best_t);
-  const int parts_c[] = {1, 3, 4}, group_c[] = {1, 2, 4}, wg_c[] = {1, 2};
+  const int parts_c[] = {2, 3, 4}, group_c[] = {1, 2, 4}, wg_c[] = {1, 2};
   const double keep = 0.98;   // a candidate must beat the best so far by 2 % (stable choices under noise)
   for (int v : parts_c) {
     if (rc) break;
