@@ -725,10 +725,11 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
 // never read).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ items, int n_items, int S, int p) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) he2hb_her2k(const EigItem *__restrict__ items, int n_items, int S, int p) {
   typedef cx<R> C;
   typedef CMma<R> M;
-  __shared__ C Vr[HB][65], Wr[HB][65], Vc[HB][65], Wc[HB][65];   // [k][i]: rows (r) / columns (c) of the tile
+  typedef typename M::acc A4;
+  __shared__ C Vr[HB][65], Wr[HB][65];   // [k][i]: factor rows of the tile rows r
   int item, t;
   if (!xcd_slot(S, n_items, item, t)) return;
   const EigItem it = items[item];
@@ -749,46 +750,51 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
   const int r0 = I * 64, cc0 = J * 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int ai = lane & 15, ak = lane >> 4;
-  // the tile values this lane updates: rows r0 + 16 rb + ai, columns
-  // cc0 + 16 wv + M::row(lane, v)
-  C cur[4][4];
+  // the tile values this lane updates (rows r0 + 16 rb + ai, columns
+  // cc0 + 16 wv + M::row(lane, v)) seed the accumulators of four-product
+  // complex steps: cr = -Re A + Re Out, ci = Im A + Im Out, so that
+  // A - conj(Out) = (-cr, ci)
+  A4 cr[4], ci[4];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
     const int gr = r0 + 16 * rb + ai;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gc = cc0 + 16 * wv + M::row(lane, v);
-      cur[rb][v] = ld_raw<R>(A22, (size_t)gc * ld + gr, gc < mt && gr < mt);   // stored only in bounds
+      const C x = ld_or0<R>(A22, (size_t)gc * ld + gr, gc < mt && gr < mt);
+      cr[rb][v] = -x.re;
+      ci[rb][v] = x.im;
     }
   }
+  // factor rows of the tile rows into LDS; those of the tile columns (the
+  // A operand, rows cc0 + 16 wv + ai) straight into registers
   for (int e = tid; e < 64 * HB; e += 256) {
     const int i = e & 63, k = e >> 6;
-    const int gr = r0 + i + HB, gc = cc0 + i + HB;   // factor rows
-    const bool kr = k < kq;
+    const int gr = r0 + i + HB;   // factor rows
     Vr[k][i] = panel_v<R>(Vp, ld, gr, k, m, kq);
-    Wr[k][i] = ld_or0<R>(Wm, (size_t)k * ld + gr, gr < m && kr);
-    Vc[k][i] = panel_v<R>(Vp, ld, gc, k, m, kq);
-    Wc[k][i] = ld_or0<R>(Wm, (size_t)k * ld + gc, gc < m && kr);
+    Wr[k][i] = ld_or0<R>(Wm, (size_t)k * ld + gr, gr < m && k < kq);
+  }
+  C aw[HB / 4], av[HB / 4];
+  {
+    const int gc = cc0 + 16 * wv + ai + HB;
+#pragma unroll
+    for (int k4 = 0; k4 < HB / 4; ++k4) {
+      const int k = 4 * k4 + ak;
+      aw[k4] = ld_or0<R>(Wm, (size_t)k * ld + gc, gc < m && k < kq);   // W[c][k]
+      av[k4] = panel_v<R>(Vp, ld, gc, k, m, kq);                        // V[c][k]
+    }
   }
   lds_barrier();
-  // three-product complex steps (three real matrix-core products each)
-  typename M::acc p1[4], p2[4], p3[4];
+  // Out[c][r] = sum_k W[c][k] conj(V[r][k]) + V[c][k] conj(W[r][k]) = D[c][r]
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb) {
-    p1[rb] = M::zero();
-    p2[rb] = M::zero();
-    p3[rb] = M::zero();
-  }
-#pragma unroll
-  for (int k0 = 0; k0 < HB; k0 += 4) {
-    const C aw = Wc[k0 + ak][16 * wv + ai];   // W[c][k]
-    const C av = Vc[k0 + ak][16 * wv + ai];   // V[c][k]
+  for (int k4 = 0; k4 < HB / 4; ++k4) {
+    const int k0 = 4 * k4;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const C bv = conj(Vr[k0 + ak][16 * rb + ai]);   // conj(V[r][k])
       const C bw = conj(Wr[k0 + ak][16 * rb + ai]);   // conj(W[r][k])
-      M::step3(aw, bv, p1[rb], p2[rb], p3[rb]);
-      M::step3(av, bw, p1[rb], p2[rb], p3[rb]);
+      M::step(aw[k4], bv, cr[rb], ci[rb]);
+      M::step(av[k4], bw, cr[rb], ci[rb]);
     }
   }
 #pragma unroll
@@ -797,11 +803,7 @@ __global__ void __launch_bounds__(256) he2hb_her2k(const EigItem *__restrict__ i
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gc = cc0 + 16 * wv + M::row(lane, v);
-      if (gc < mt && gr < mt) {
-        const R ore = p1[rb][v] - p2[rb][v], oim = p3[rb][v] - p1[rb][v] - p2[rb][v];
-        const C d = mkc<R>(ore, -oim);   // D[r][c] = conj(Out[c][r])
-        gst(A22, (size_t)gc * ld + gr, cur[rb][v] - d);
-      }
+      if (gc < mt && gr < mt) gst(A22, (size_t)gc * ld + gr, mkc<R>(-cr[rb][v], ci[rb][v]));   // D[r][c] = conj(Out[c][r])
     }
   }
 }
@@ -1302,13 +1304,15 @@ MVPB_DEV cx<float> wave_shr1_c(cx<float> v) {
 
 template <typename R>
 __global__ void __launch_bounds__(BTW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-backtransform_2s_wave(const EigItem *__restrict__ items) {
+backtransform_2s_wave(const EigItem *__restrict__ items, int n_items, int S) {
   typedef cx<R> C;
-  const EigItem it = items[blockIdx.y];
+  int item, grp;   // the S column groups of an item on one XCD: its reflectors are fetched into one L2
+  if (!xcd_slot(S, n_items, item, grp)) return;
+  const EigItem it = items[item];
   const int n = it.n, nb = it.nb;
   if (n - 1 > 64 * HB) return;   // item of the LDS kernel (backtransform_2s)
   const int lane = threadIdx.x & 63;
-  const int cb = (blockIdx.x * BTW_WAVES + (threadIdx.x >> 6)) * BTW_COLS;   // first column of the wavefront
+  const int cb = (grp * BTW_WAVES + (threadIdx.x >> 6)) * BTW_COLS;   // first column of the wavefront
   if (cb >= nb) return;   // whole wavefronts
   const int ncw = min(BTW_COLS, nb - cb);
   const size_t ld = (size_t)n;
@@ -1407,14 +1411,17 @@ backtransform_2s_wave(const EigItem *__restrict__ items) {
 // Stage-1 part of the back-transform: Y <- Q1 Y with the block reflectors of
 // the panels, last panel first; nc columns of Y per workgroup in LDS.
 template <typename R>
-__global__ void __launch_bounds__(BT_THREADS) backtransform_s1(const EigItem *__restrict__ items, int nc) {
+__global__ void __launch_bounds__(BT_THREADS) backtransform_s1(const EigItem *__restrict__ items, int nc, int n_items,
+                                                               int groups) {
   typedef cx<R> C;
   extern __shared__ __align__(16) unsigned char shraw[];
   C *Z = (C *)shraw;   // Z[zidx(r, c, nc)]
   __shared__ C S[HB][8], S2[HB][9], Tm[HB][HB + 1];
-  const EigItem it = items[blockIdx.y];
+  int item, grp;   // the column groups of an item on one XCD: its panels are fetched into one L2
+  if (!xcd_slot(groups, n_items, item, grp)) return;
+  const EigItem it = items[item];
   const int n = it.n, nb = it.nb;
-  const int cbase = blockIdx.x * nc;
+  const int cbase = grp * nc;
   if (cbase >= nb) return;
   const int ncl = min(nc, nb - cbase);
   const int tid = threadIdx.x;
@@ -1673,17 +1680,18 @@ hipError_t launch_backtransform(const EigItem *items, int n_items, int n_min, in
   // stage 2, per item: the wavefront kernel while every block of a sweep has
   // a lane (n - 1 <= 64 HB), else the LDS kernel; each skips the other's items
   const bool any_wave = n_min - 1 <= 64 * HB, any_lds = n_max - 1 > 64 * HB;
-  const dim3 gw((nb + BTW_WAVES * BTW_COLS - 1) / (BTW_WAVES * BTW_COLS), n_items);
+  const int gws = (nb + BTW_WAVES * BTW_COLS - 1) / (BTW_WAVES * BTW_COLS);
+  const dim3 gw(xcd_grid(gws, n_items)), g1(xcd_grid(groups, n_items));
   if (fp32) {
-    if (any_wave) hipLaunchKernelGGL((backtransform_2s_wave<float>), gw, dim3(BTW_WAVES * 64), 0, st, items);
+    if (any_wave) hipLaunchKernelGGL((backtransform_2s_wave<float>), gw, dim3(BTW_WAVES * 64), 0, st, items, n_items, gws);
     if (any_lds)
       hipLaunchKernelGGL((backtransform_2s<float>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
-    hipLaunchKernelGGL((backtransform_s1<float>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
+    hipLaunchKernelGGL((backtransform_s1<float>), g1, dim3(BT_THREADS), sh, st, items, nc, n_items, groups);
   } else {
-    if (any_wave) hipLaunchKernelGGL((backtransform_2s_wave<double>), gw, dim3(BTW_WAVES * 64), 0, st, items);
+    if (any_wave) hipLaunchKernelGGL((backtransform_2s_wave<double>), gw, dim3(BTW_WAVES * 64), 0, st, items, n_items, gws);
     if (any_lds)
       hipLaunchKernelGGL((backtransform_2s<double>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
-    hipLaunchKernelGGL((backtransform_s1<double>), dim3(groups, n_items), dim3(BT_THREADS), sh, st, items, nc);
+    hipLaunchKernelGGL((backtransform_s1<double>), g1, dim3(BT_THREADS), sh, st, items, nc, n_items, groups);
   }
   return hipGetLastError();
 }
