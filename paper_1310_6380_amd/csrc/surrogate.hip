@@ -5,9 +5,12 @@
 //   conv1 3x3  1->32 s1, conv2..4 3x3 32->32 s2 (circular padding, ReLU)
 //   flatten 4x4x32 = 512 -> fc1 256 (ReLU) -> fc2 400, mean squared error.
 //
-// Activations are NHWC FP32; convolutions are im2col + GEMM, the backward
-// data pass is a gather col2im (every input pixel collects its taps, so no
-// atomics and bitwise-reproducible results).  GEMMs run either as FP32 FMA
+// Activations are NHWC FP32; a convolution is one GEMM whose A operand is
+// the implicit im2col of its input (the tile loads gather the taps straight
+// from the activations, circular padding, power-of-two grids), also for the
+// weight gradients; the backward data pass is a GEMM into a column buffer
+// and a gather col2im (every input pixel collects its taps, so no atomics
+// and bitwise-reproducible results).  GEMMs run either as FP32 FMA
 // tiles or on the matrix cores with BF16 inputs and FP32 accumulation
 // (v_mfma_f32_16x16x32_bf16), bias and ReLU applied in the GEMM epilogue,
 // long reductions split over workgroups; master weights and Adam moments
@@ -34,10 +37,27 @@ namespace mvpb {
 // ---------------------------------------------------------------------------
 constexpr int GBM = 64, GBN = 64;
 
+// Implicit im2col operand: column matrix col[p][k], p = (b, oy, ox) an output
+// pixel, k = (ky 3 + kx) C + c, col[p][k] = in[b][(s oy + ky - 1) mod H]
+// [(s ox + kx - 1) mod W][c] with H, W, C and the output grid Ho = H / s,
+// Wo = W / s powers of two (given as log2).
+struct ConvA {
+  const float *in = nullptr;   // NHWC input; nullptr: A is an ordinary matrix
+  int lH = 0, lW = 0, lC = 0, lHo = 0, lWo = 0, s = 1;
+};
+MVPB_DEV float conv_col(const ConvA &cv, int p, int k) {
+  const int c = k & ((1 << cv.lC) - 1), tap = k >> cv.lC;
+  const int ky = tap / 3, kx = tap - 3 * ky;
+  const int ox = p & ((1 << cv.lWo) - 1), t = p >> cv.lWo;
+  const int oy = t & ((1 << cv.lHo) - 1), b = t >> cv.lHo;
+  const int y = (cv.s * oy + ky - 1) & ((1 << cv.lH) - 1), x = (cv.s * ox + kx - 1) & ((1 << cv.lW) - 1);
+  return cv.in[(((((size_t)b << cv.lH) + y) << cv.lW) + x) << cv.lC | (size_t)c];
+}
+
 struct GemmArgs {
   int M, N, K;
   float alpha, beta;
-  const float *A;
+  const float *A;   // unused when conv.in is set (op(A) is then the implicit column matrix)
   int lda;
   const float *B;
   int ldb;
@@ -46,6 +66,7 @@ struct GemmArgs {
   int kchunk;        // K range of one split
   const float *bias; // per column, nullable (applied when not split)
   int relu;
+  ConvA conv;
 };
 
 template <int TA, int TB, int BK>
@@ -57,7 +78,12 @@ MVPB_DEV void load_tiles(const GemmArgs &g, int m0, int n0, int k0, int k1, floa
     if (TA == 0) { i = e / BK; k = e % BK; } else { k = e / GBM; i = e % GBM; }
     const int gi = m0 + i, gk = k0 + k;
     float v = 0.f;
-    if (gi < g.M && gk < k1) v = TA == 0 ? g.A[(size_t)gi * g.lda + gk] : g.A[(size_t)gk * g.lda + gi];
+    if (gi < g.M && gk < k1) {
+      if (g.conv.in)   // op(A)[gi][gk] = col[gi][gk] (TA = 0) or col[gk][gi] (TA = 1)
+        v = TA == 0 ? conv_col(g.conv, gi, gk) : conv_col(g.conv, gk, gi);
+      else
+        v = TA == 0 ? g.A[(size_t)gi * g.lda + gk] : g.A[(size_t)gk * g.lda + gi];
+    }
     As[k][i] = v;
   }
   for (int e = tid; e < BK * GBN; e += 256) {
@@ -191,13 +217,13 @@ static int gemm_splits(int M, int N, int K) {
 static hipError_t gemm(bool bf16, int ta, int tb, int M, int N, int K, float alpha, const float *A, int lda,
                        const float *B, int ldb, float beta, float *C, int ldc, hipStream_t st,
                        const float *bias = nullptr, int relu = 0, float *split_buf = nullptr,
-                       size_t split_cap = 0) {
+                       size_t split_cap = 0, const ConvA &conv = ConvA()) {
   int sp = gemm_splits(M, N, K);
   if ((size_t)sp * M * N > split_cap || !split_buf) sp = 1;
   const int align = bf16 ? 32 : 16;
   const int kchunk = sp == 1 ? K : ((K + sp - 1) / sp + align - 1) / align * align;
   sp = (K + kchunk - 1) / kchunk;
-  GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, sp == 1 ? C : split_buf, ldc, kchunk, bias, relu};
+  GemmArgs g{M, N, K, alpha, beta, A, lda, B, ldb, sp == 1 ? C : split_buf, ldc, kchunk, bias, relu, conv};
   dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, sp);
 #define MVPB_GEMM_CASE(TA, TB)                                                            \
   if (ta == TA && tb == TB) {                                                             \
@@ -223,20 +249,6 @@ static hipError_t gemm(bool bf16, int ta, int tb, int M, int N, int K, float alp
 __global__ void cells_to_float(const uint8_t *__restrict__ cells, float *__restrict__ x, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = cells[i] ? 1.f : 0.f;
-}
-
-// col[p][(ky*3+kx)*C + c] = a[b][(s oy + ky - 1) mod H][(s ox + kx - 1) mod W][c], p = (b, oy, ox)
-__global__ void im2col(const float *__restrict__ a, float *__restrict__ col, int B, int H, int W, int C, int s) {
-  const int Ho = H / s, Wo = W / s, K = 9 * C;
-  const size_t total = (size_t)B * Ho * Wo * K;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int k = (int)(e % K);
-    const size_t p = e / K;
-    const int ox = (int)(p % Wo), oy = (int)((p / Wo) % Ho), b = (int)(p / ((size_t)Wo * Ho));
-    const int c = k % C, tap = k / C, ky = tap / 3, kx = tap % 3;
-    const int y = (s * oy + ky - 1 + H) % H, x = (s * ox + kx - 1 + W) % W;
-    col[e] = a[(((size_t)b * H + y) * W + x) * C + c];
-  }
 }
 
 // Gather form of col2im: da[b][y][x][c] = sum over taps of dcol at the output
@@ -398,7 +410,7 @@ struct mvpb_sur_s {
   uint64_t seed = 0;
   Buf<float> params, grads, m, v;
   Buf<float> act[5];        // act[0] input [B,32,32,1]; act[l+1] output of conv l (NHWC)
-  Buf<float> col, dcol, dact, dact2;
+  Buf<float> dcol, dact, dact2;
   Buf<float> h, out, dout, dh, dflat, partial;
   Buf<float> split;     // partial slices of split-K GEMMs
   Buf<float> colpart;   // partial column sums (bias gradients)
@@ -410,9 +422,29 @@ extern "C" int mvpb_sur_destroy(mvpb_sur net);
 
 // GEMM with the network's precision and split-K scratch.
 static hipError_t net_gemm(mvpb_sur net, int ta, int tb, int M, int N, int K, const float *A, int lda, const float *B,
-                           int ldb, float *C, int ldc, const float *bias = nullptr, int relu = 0) {
+                           int ldb, float *C, int ldc, const float *bias = nullptr, int relu = 0,
+                           const ConvA &conv = ConvA()) {
   return gemm(net->bf16, ta, tb, M, N, K, 1.f, A, lda, B, ldb, 0.f, C, ldc, net->st, bias, relu, net->split.p,
-              net->split.n);
+              net->split.n, conv);
+}
+
+static int ilog2_exact(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// The implicit column matrix of conv layer L over the activations `in`.
+static ConvA conv_operand(const Layer &L, const float *in) {
+  ConvA cv;
+  cv.in = in;
+  cv.lH = ilog2_exact(L.H);
+  cv.lW = ilog2_exact(L.W);
+  cv.lC = ilog2_exact(L.ci);
+  cv.lHo = ilog2_exact(L.H / L.s);
+  cv.lWo = ilog2_exact(L.W / L.s);
+  cv.s = L.s;
+  return cv;
 }
 
 // db[c] = sum over rows of d[r][c] (blocks of rows, then the blocks in order).
@@ -431,12 +463,9 @@ static int sur_forward(mvpb_sur net, int B) {
     const int Ho = L.H / L.s, Wo = L.W / L.s;
     const size_t rows = (size_t)B * Ho * Wo;
     const int K = 9 * L.ci;
-    const size_t tot = rows * K;
-    hipLaunchKernelGGL(im2col, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 65535)), dim3(256), 0, st,
-                       net->act[l].p, net->col.p, B, L.H, L.W, L.ci, L.s);
-    // convolution as one GEMM, bias and ReLU in its epilogue
-    e = net_gemm(net, 0, 0, (int)rows, L.co, K, net->col.p, K, P + net->off[2 * l], L.co, net->act[l + 1].p, L.co,
-                 P + net->off[2 * l + 1], 1);
+    // convolution as one GEMM over the implicit column matrix, bias and ReLU in its epilogue
+    e = net_gemm(net, 0, 0, (int)rows, L.co, K, nullptr, K, P + net->off[2 * l], L.co, net->act[l + 1].p, L.co,
+                 P + net->off[2 * l + 1], 1, conv_operand(L, net->act[l].p));
   }
   // fc1 (ReLU), fc2
   if (e == hipSuccess)
@@ -472,11 +501,9 @@ static int sur_backward(mvpb_sur net, int B) {
     // dz = da * relu'(act[l+1])
     hipLaunchKernelGGL(relu_mask, dim3((unsigned)std::min<size_t>((rows * L.co + 255) / 256, 65535)), dim3(256), 0, st,
                        da, net->act[l + 1].p, rows * L.co);
-    // dW = col^T dz (col recomputed; split over the output pixels), db = column sums of dz
-    const size_t tot = rows * K;
-    hipLaunchKernelGGL(im2col, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 65535)), dim3(256), 0, st,
-                       net->act[l].p, net->col.p, B, L.H, L.W, L.ci, L.s);
-    e = net_gemm(net, 1, 0, K, L.co, (int)rows, net->col.p, K, da, L.co, G + net->off[2 * l], L.co);
+    // dW = col^T dz over the implicit column matrix (split over the output pixels), db = column sums of dz
+    e = net_gemm(net, 1, 0, K, L.co, (int)rows, nullptr, K, da, L.co, G + net->off[2 * l], L.co, nullptr, 0,
+                 conv_operand(L, net->act[l].p));
     col_sums(net, da, rows, L.co, G + net->off[2 * l + 1]);
     if (l > 0 && e == hipSuccess) {
       // dcol = dz W^T, then gather back onto the input pixels
@@ -561,7 +588,6 @@ extern "C" int mvpb_sur_create(mvpb_ctx ctx, int max_batch, int precision, uint6
   A(net->v, net->n_params);
   A(net->act[0], B * kPix);
   for (int l = 0; l < 4; ++l) A(net->act[l + 1], B * (kConv[l].H / kConv[l].s) * (kConv[l].W / kConv[l].s) * kConv[l].co);
-  A(net->col, colmax);
   A(net->dcol, colmax);
   A(net->dact, actmax);
   A(net->dact2, actmax);
