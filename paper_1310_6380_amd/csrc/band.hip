@@ -6,18 +6,25 @@
 //                 per item with the panel rows held in registers; builds the
 //                 compact-WY factor T (Q = I - V T V^H).
 //    he2hb_hemm   X0 = A22 V with the trailing Hermitian matrix (lower
-//                 triangle stored), plus per-row-block Gram partials V^H X0.
-//    he2hb_wform  W = X0 T - V (T^H V^H X0 T) / 2.
-//    he2hb_her2k  A22 <- A22 - W V^H - V W^H (lower tiles).
+//                 triangle stored), plus per-row-block Gram partials V^H X0
+//                 formed on the matrix cores from the accumulators.
+//    he2hb_wform  W = X0 T - V (T^H V^H X0 T) / 2, and the update of the
+//                 first HB columns of A22 (the next panel, its diagonal block
+//                 included) by -W V^H - V W^H.
+//    he2hb_her2k  the same update of the rest, A22[HB:, HB:] (lower tiles),
+//                 on a look-ahead stream while the next panel is factored.
 //    Together: A22 <- Q^H A22 Q.
 //  Stage 2 (band -> tridiagonal), hb2st.  Bulge chasing with Householder
-//    reflectors of length HB on a band copy holding 2 HB subdiagonals.  One
-//    workgroup per item; each wavefront runs whole sweeps, and block k of
-//    sweep i starts once sweep i-1 has finished its block k+2, so about
-//    n / (3 HB) sweeps are in flight at once.
-//  Back-transform, backtransform_2s.  The stage-2 reflectors (last sweep
-//    first), then the stage-1 block reflectors (last panel first), applied
-//    to the eigenvectors of the tridiagonal matrix held in LDS.
+//    reflectors of length HB on a band copy holding 2 HB subdiagonals.  A few
+//    workgroups per item, all on one XCD; each wavefront runs whole sweeps,
+//    and block k of sweep i starts once sweep i-1 has finished its blocks
+//    0 .. k+1, so consecutive sweeps run two blocks apart.
+//  Back-transform.  The stage-2 reflectors (last sweep first), then the
+//    stage-1 block reflectors (last panel first), applied to the eigenvectors
+//    of the tridiagonal matrix.  Up to order 64 HB + 1: backtransform_2s_wave
+//    (stage 2, a sliding register window per wavefront), then
+//    backtransform_s1 (stage 1); above it, backtransform_2s does both with
+//    the columns held in LDS.
 #include <float.h>
 #include <stdlib.h>
 
