@@ -609,10 +609,11 @@ hipError_t launch_combine_batch(const cd *Xp, int N, const double *scales, cd *c
 // ---------------------------------------------------------------------------
 // Per-k formation of C(k) (2N x 2N, Hermitian, full storage, column-major)
 // from the coefficient matrices.  One block per 32 x 32 tile (I >= J) of the
-// lower triangle; the upper triangle gets the conjugate transpose through an
-// LDS tile, so the result is exactly Hermitian with a real diagonal.  Two
-// copies are written: the working copy (overwritten by the reduction to
-// tridiagonal form) and the kept copy used by the Rayleigh-Ritz step.
+// lower triangle.  Two copies are written: the working copy, lower triangle
+// only (the reduction to tridiagonal form reads and overwrites nothing
+// else), and the kept copy used by the Rayleigh-Ritz step, whose upper
+// triangle gets the conjugate transpose through an LDS tile, so that it is
+// exactly Hermitian with a real diagonal.
 // ---------------------------------------------------------------------------
 template <typename Item, typename R>
 __global__ void __launch_bounds__(256) form_operator(const Item *__restrict__ items, int tiles_max) {
@@ -662,10 +663,7 @@ __global__ void __launch_bounds__(256) form_operator(const Item *__restrict__ it
   for (int lc = lc0; lc < 32; lc += 8) {
     const int r = J * 32 + lr, c = I * 32 + lc;
     if (r < n && c < n && r < c) {
-      const cd v = conj(tile[lr][lc]);
-      const size_t dst = (size_t)c * n + r;
-      ((cx<R> *)it.A)[dst] = ccast<R>(v);
-      it.Ak[dst] = v;
+      it.Ak[(size_t)c * n + r] = conj(tile[lr][lc]);
     }
   }
 }

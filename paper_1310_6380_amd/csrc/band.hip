@@ -21,10 +21,9 @@
 //    0 .. k+1, so consecutive sweeps run two blocks apart.
 //  Back-transform.  The stage-2 reflectors (last sweep first), then the
 //    stage-1 block reflectors (last panel first), applied to the eigenvectors
-//    of the tridiagonal matrix.  Up to order 64 HB + 1: backtransform_2s_wave
-//    (stage 2, a sliding register window per wavefront), then
-//    backtransform_s1 (stage 1); above it, backtransform_2s does both with
-//    the columns held in LDS.
+//    of the tridiagonal matrix: stage 2 by backtransform_2s_wave (a sliding
+//    register window per wavefront) up to order 64 HB + 1, by
+//    backtransform_2s (columns in LDS) above it; stage 1 by backtransform_s1.
 #include <float.h>
 #include <stdlib.h>
 
@@ -758,10 +757,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int ai = lane & 15, ak = lane >> 4;
   // the tile values this lane updates (rows r0 + 16 rb + ai, columns
-  // cc0 + 16 wv + M::row(lane, v)) seed the accumulators of four-product
-  // complex steps: cr = -Re A + Re Out, ci = Im A + Im Out, so that
-  // A - conj(Out) = (-cr, ci)
-  A4 cr[4], ci[4];
+  // cc0 + 16 wv + M::row(lane, v)) seed the accumulators of three-product
+  // complex steps (p1, p2, p3 of M::step3): with p1 = -Re A, p2 = 0 and
+  // p3 = Im A - Re A to start, A - conj(Out) = (p2 - p1, p3 - p1 - p2)
+  A4 q1[4], q2[4], q3[4];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
     const int gr = r0 + 16 * rb + ai;
@@ -769,8 +768,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
     for (int v = 0; v < 4; ++v) {
       const int gc = cc0 + 16 * wv + M::row(lane, v);
       const C x = ld_or0<R>(A22, (size_t)gc * ld + gr, gc < mt && gr < mt);
-      cr[rb][v] = -x.re;
-      ci[rb][v] = x.im;
+      q1[rb][v] = -x.re;
+      q2[rb][v] = R(0);
+      q3[rb][v] = x.im - x.re;
     }
   }
   // factor rows of the tile rows into LDS; those of the tile columns (the
@@ -800,8 +800,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
     for (int rb = 0; rb < 4; ++rb) {
       const C bv = conj(Vr[k0 + ak][16 * rb + ai]);   // conj(V[r][k])
       const C bw = conj(Wr[k0 + ak][16 * rb + ai]);   // conj(W[r][k])
-      M::step(aw[k4], bv, cr[rb], ci[rb]);
-      M::step(av[k4], bw, cr[rb], ci[rb]);
+      M::step3(aw[k4], bv, q1[rb], q2[rb], q3[rb]);
+      M::step3(av[k4], bw, q1[rb], q2[rb], q3[rb]);
     }
   }
 #pragma unroll
@@ -810,7 +810,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gc = cc0 + 16 * wv + M::row(lane, v);
-      if (gc < mt && gr < mt) gst(A22, (size_t)gc * ld + gr, mkc<R>(-cr[rb][v], ci[rb][v]));   // D[r][c] = conj(Out[c][r])
+      // D[r][c] = conj(Out[c][r])
+      const C o = mkc<R>(q2[rb][v] - q1[rb][v], q3[rb][v] - q1[rb][v] - q2[rb][v]);
+      if (gc < mt && gr < mt) gst(A22, (size_t)gc * ld + gr, o);
     }
   }
 }
@@ -1199,10 +1201,10 @@ MVPB_HD int zidx(int r, int c, int nc) { return r * (nc + 1) + c + (r >> 4); }
 MVPB_HD size_t zbytes(int n, int nc, size_t es) { return es * ((size_t)n * (nc + 1) + (size_t)n / 16 + 1); }
 
 // ---------------------------------------------------------------------------
-// Back-transform.  Z (n x nc columns of the tridiagonal eigenvectors) in LDS;
-// apply the stage-2 reflectors sweep by sweep from the last, then the stage-1
-// block reflectors panel by panel from the last.  Output Y (complex, n x nb,
-// column-major) in the reduction precision.
+// Stage-2 back-transform for orders above 64 HB + 1.  Z (n x nc columns of
+// the tridiagonal eigenvectors) in LDS; apply the stage-2 reflectors sweep by
+// sweep from the last.  Output Yb (complex, n x nb, column-major) in the
+// reduction precision, for the stage-1 part (backtransform_s1).
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__restrict__ items, int nc) {

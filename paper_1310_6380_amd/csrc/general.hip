@@ -152,7 +152,8 @@ hipError_t launch_toeplitz_blocks(const cd *F, int M1, int M2, int M3, int N, in
 // ---------------------------------------------------------------------------
 // C(k) of every general-layout item: lower 32 x 32 tiles computed from the
 // coefficient matrices (index of the pair l <= m: l (d+1) - l (l-1)/2 + m - l),
-// written to A (reduction precision, both triangles) and to the kept FP64 copy.
+// written to A (reduction precision, lower triangle) and to the kept FP64 copy
+// (both triangles).
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ void __launch_bounds__(256) form_operator_general(const EigItem *__restrict__ items) {
@@ -191,10 +192,7 @@ __global__ void __launch_bounds__(256) form_operator_general(const EigItem *__re
   for (int lc = lc0; lc < 32; lc += 8) {
     const int r = J * 32 + lr, c = I * 32 + lc;
     if (r < n && c < n && r < c) {
-      const cd v = conj(tile[lr][lc]);
-      const size_t dst = (size_t)c * n + r;
-      ((cx<R> *)it.A)[dst] = ccast<R>(v);
-      it.Ak[dst] = v;
+      it.Ak[(size_t)c * n + r] = conj(tile[lr][lc]);   // the working copy keeps its lower triangle only
     }
   }
 }
