@@ -1535,9 +1535,10 @@ static std::string launch_signature(const std::vector<Job> &jobs, int nb, bool f
   return k;
 }
 
-// Events of the stage-1 steps of one eigensolve launch sequence over items of
-// order at most n_max in `parts` parts.
-static size_t la_events_needed(int n_max, int parts) { return (size_t)2 * parts * stage1_steps(n_max); }
+// Events of one eigensolve launch sequence over items of order at most n_max
+// in `parts` parts: two per stage-1 step and part, then the fork and join of
+// the tridiagonal eigenvectors.
+static size_t la_events_needed(int n_max, int parts) { return (size_t)2 * parts * stage1_steps(n_max) + 2; }
 
 // Grow the context's step-event pool to at least `count` events (outside any
 // capture).
@@ -1597,7 +1598,10 @@ static hipError_t enqueue_eigensolve(mvpb_ctx ctx, const EigItem *d_items, const
     if (e == hipSuccess) e = hipStreamWaitEvent(st, ev_join[q - 1], 0);
   }
   if (e == hipSuccess) e = launch_stage2(d_items, n_items, n_max, fp32, ctl, sh, st);
-  if (e == hipSuccess) e = launch_tridiag_eig(d_items, n_items, n_max, nb, st);
+  if (e == hipSuccess) {
+    const hipEvent_t *tev = la_ev + (size_t)2 * std::max(1, parts_wanted) * stage1_steps(n_max);
+    e = launch_tridiag_eig(d_items, n_items, n_max, nb, st, ctx->la[0], tev[0], tev[1]);
+  }
   if (e == hipSuccess) e = launch_backtransform(d_items, n_items, n_min, n_max, nb, fp32, st);
   if (e == hipSuccess)
     e = nb <= RR_MAX_BANDS ? launch_rayleigh_ritz(d_items, n_items, n_max, nb, fp32, st)

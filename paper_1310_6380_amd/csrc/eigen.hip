@@ -640,15 +640,29 @@ __global__ void __launch_bounds__(64) tridiag_cluster_gs(const EigItem *__restri
   }
 }
 
-hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st) {
+hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st,
+                              hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_join) {
   ProfScope ps(K_TRIDIAG, st);
   hipLaunchKernelGGL(tridiag_bisect_item, dim3(BISI_GROUPS, n_items), dim3(BISI_THREADS),
                      sizeof(double) * (3 * n_max + 1), st, items);
-  hipLaunchKernelGGL(tridiag_twisted, dim3(nb, n_items), dim3(64), sizeof(double) * 4 * n_max, st, items);
+  const bool two = side != nullptr && ev_fork != nullptr && ev_join != nullptr;
+  hipStream_t si = st;
+  if (two) {
+    hipError_t e = hipEventRecord(ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_fork, 0);
+    if (e != hipSuccess) return e;
+    si = side;
+  }
   if (n_max <= INV_LDS_MAX_N)
-    hipLaunchKernelGGL(tridiag_invit<true>, dim3(nb, n_items), dim3(64), sizeof(double) * 8 * n_max, st, items);
+    hipLaunchKernelGGL(tridiag_invit<true>, dim3(nb, n_items), dim3(64), sizeof(double) * 8 * n_max, si, items);
   else
-    hipLaunchKernelGGL(tridiag_invit<false>, dim3(nb, n_items), dim3(64), sizeof(double) * 3 * n_max, st, items);
+    hipLaunchKernelGGL(tridiag_invit<false>, dim3(nb, n_items), dim3(64), sizeof(double) * 3 * n_max, si, items);
+  hipLaunchKernelGGL(tridiag_twisted, dim3(nb, n_items), dim3(64), sizeof(double) * 4 * n_max, st, items);
+  if (two) {
+    hipError_t e = hipEventRecord(ev_join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev_join, 0);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(tridiag_cluster_gs, dim3(nb, n_items), dim3(64), 0, st, items);
   return hipGetLastError();
 }

@@ -204,7 +204,11 @@ long long refl_total(int n);   // number of stage-2 reflectors of an item of ord
 
 // eigen.hip
 hipError_t init_kernel_attributes();  // once per device, before the first launch
-hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st);
+// side: a stream (with two events) on which the inverse iteration of cluster
+// members runs beside the twisted factorizations of the isolated eigenvalues
+// (they write disjoint eigenvector columns), or nullptr for one stream.
+hipError_t launch_tridiag_eig(const EigItem *items, int n_items, int n_max, int nb, hipStream_t st,
+                              hipStream_t side = nullptr, hipEvent_t ev_fork = nullptr, hipEvent_t ev_join = nullptr);
 hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, int nb, bool check, hipStream_t st);
 // Solves beyond RR_MAX_BANDS (FP64): lambda, omega from the tridiagonal
 // eigenvalues, no estimate (acc = 0); the vectors stay in Y.
