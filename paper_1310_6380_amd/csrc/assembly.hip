@@ -615,56 +615,85 @@ hipError_t launch_combine_batch(const cd *Xp, int N, const double *scales, cd *c
 // triangle gets the conjugate transpose through an LDS tile, so that it is
 // exactly Hermitian with a real diagonal.
 // ---------------------------------------------------------------------------
+// Items per workgroup of the formation: a workgroup forms one tile for
+// FO_ITEMS consecutive items, its coefficient entries loaded once while the
+// items share a cell (same coefficient matrices), so that the loads are paid
+// once for the k points of a cell.
+constexpr int FO_ITEMS = 4;
+
 template <typename Item, typename R>
-__global__ void __launch_bounds__(256) form_operator(const Item *__restrict__ items, int tiles_max) {
+__global__ void __launch_bounds__(256) form_operator(const Item *__restrict__ items, int n_items) {
   __shared__ cd tile[32][33];
-  const Item it = items[blockIdx.y];
-  if (it.dim != 0) return;   // general layout: form_operator_general
-  const int N = it.N, n = 2 * N;
-  const int nt = (n + 31) / 32;
   // linear lower-triangle tile index -> (I, J), I >= J
-  int t = blockIdx.x;
-  if (t >= nt * (nt + 1) / 2) return;
+  const int t = blockIdx.y;
   int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
   while (I * (I + 1) / 2 > t) --I;
   const int J = t - I * (I + 1) / 2;
-  const double k1 = it.kap1, k2 = it.kap2;
-  const size_t NN = (size_t)N * N;
-  const cd *cf = it.coef;
   const int lr = threadIdx.x & 31, lc0 = threadIdx.x >> 5;
-  for (int lc = lc0; lc < 32; lc += 8) {
-    const int r = I * 32 + lr, c = J * 32 + lc;
-    cd v = mk(0.0, 0.0);
-    if (r < n && c < n && r >= c) {
-      const int br = r >= N, bc = c >= N;
-      const int i = r - br * N, j = c - bc * N;
-      const size_t e = (size_t)j * N + i;
-      if (!br && !bc) {
-        v = cf[e] + k1 * cf[NN + e] + k2 * cf[2 * NN + e] + (k1 * k1) * cf[12 * NN + e] +
-            (k2 * k2) * cf[13 * NN + e];
-      } else if (br && bc) {
-        v = cf[3 * NN + e] + k1 * cf[4 * NN + e] + k2 * cf[5 * NN + e] + (k1 * k1) * cf[13 * NN + e] +
-            (k2 * k2) * cf[12 * NN + e];
-      } else if (!br && bc) {
-        v = cf[6 * NN + e] + k1 * cf[7 * NN + e] + k2 * cf[8 * NN + e] + (k1 * k2) * cf[14 * NN + e];
-      } else {
-        v = cf[9 * NN + e] + k1 * cf[10 * NN + e] + k2 * cf[11 * NN + e] + (k1 * k2) * cf[14 * NN + e];
+  // this thread's entries (rows I*32 + lr, columns J*32 + lc0 + 8u): the up to
+  // five coefficient entries each, and whether the entry is in a mixed block
+  cd a[4][5];
+  bool mixed[4];
+  const cd *cf_loaded = nullptr;
+  int n_loaded = -1;
+  for (int ii = 0; ii < FO_ITEMS; ++ii) {
+    const int item = blockIdx.x * FO_ITEMS + ii;
+    if (item >= n_items) break;   // uniform
+    const Item it = items[item];
+    if (it.dim != 0) continue;    // general layout: form_operator_general
+    const int N = it.N, n = 2 * N;
+    const int nt = (n + 31) / 32;
+    if (t >= nt * (nt + 1) / 2) continue;
+    const cd *cf = it.coef;
+    if (cf != cf_loaded || N != n_loaded) {
+      const size_t NN = (size_t)N * N;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = I * 32 + lr, c = J * 32 + lc0 + 8 * u;
+        const bool in = r < n && c < n && r >= c;
+        const int br = r >= N, bc = c >= N;
+        const int i = r - br * N, j = c - bc * N;
+        const size_t e = in ? (size_t)j * N + i : 0;
+        // blocks (0,0), (1,1): 1, k1, k2, k1^2, k2^2; (0,1), (1,0): 1, k1, k2, k1 k2
+        const int m0 = !br && !bc ? 0 : (br && bc ? 3 : (!br ? 6 : 9));
+        const int m3 = !br && !bc ? 12 : (br && bc ? 13 : 14);
+        const int m4 = !br && !bc ? 13 : 12;
+        mixed[u] = br != bc;
+        a[u][0] = cf[(size_t)m0 * NN + e];
+        a[u][1] = cf[(size_t)(m0 + 1) * NN + e];
+        a[u][2] = cf[(size_t)(m0 + 2) * NN + e];
+        a[u][3] = cf[(size_t)m3 * NN + e];
+        a[u][4] = mixed[u] ? mk(0.0, 0.0) : cf[(size_t)m4 * NN + e];
       }
-      if (r == c) v.im = 0.0;
-      const size_t dst = (size_t)c * n + r;
-      ((cx<R> *)it.A)[dst] = ccast<R>(v);
-      it.Ak[dst] = v;
+      cf_loaded = cf;
+      n_loaded = N;
     }
-    tile[lc][lr] = v;
-  }
-  __syncthreads();
-  // mirrored tile (J, I): element (r', c') = (J*32 + lr, I*32 + lc) with r' < c'
-  for (int lc = lc0; lc < 32; lc += 8) {
-    const int r = J * 32 + lr, c = I * 32 + lc;
-    if (r < n && c < n && r < c) {
-      it.Ak[(size_t)c * n + r] = conj(tile[lr][lc]);
+    const double k1 = it.kap1, k2 = it.kap2;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int lc = lc0 + 8 * u;
+      const int r = I * 32 + lr, c = J * 32 + lc;
+      cd v = mk(0.0, 0.0);
+      if (r < n && c < n && r >= c) {
+        if (!mixed[u])
+          v = a[u][0] + k1 * a[u][1] + k2 * a[u][2] + (k1 * k1) * a[u][3] + (k2 * k2) * a[u][4];
+        else
+          v = a[u][0] + k1 * a[u][1] + k2 * a[u][2] + (k1 * k2) * a[u][3];
+        if (r == c) v.im = 0.0;
+        const size_t dst = (size_t)c * n + r;
+        ((cx<R> *)it.A)[dst] = ccast<R>(v);
+        it.Ak[dst] = v;
+      }
+      tile[lc][lr] = v;
     }
+    __syncthreads();
+    // mirrored tile (J, I): element (r', c') = (J*32 + lr, I*32 + lc) with r' < c'
+    for (int lc = lc0; lc < 32; lc += 8) {
+      const int r = J * 32 + lr, c = I * 32 + lc;
+      if (r < n && c < n && r < c) it.Ak[(size_t)c * n + r] = conj(tile[lr][lc]);
+    }
+    __syncthreads();
   }
 }
 
@@ -673,9 +702,11 @@ hipError_t launch_form_operator(const EigItem *items, int n_items, int n_max, bo
   const int tiles = nt * (nt + 1) / 2;
   ProfScope ps(K_FORM, st);
   if (fp32)
-    hipLaunchKernelGGL((form_operator<EigItem, float>), dim3(tiles, n_items), dim3(256), 0, st, items, tiles);
+    hipLaunchKernelGGL((form_operator<EigItem, float>), dim3((n_items + FO_ITEMS - 1) / FO_ITEMS, tiles), dim3(256), 0,
+                       st, items, n_items);
   else
-    hipLaunchKernelGGL((form_operator<EigItem, double>), dim3(tiles, n_items), dim3(256), 0, st, items, tiles);
+    hipLaunchKernelGGL((form_operator<EigItem, double>), dim3((n_items + FO_ITEMS - 1) / FO_ITEMS, tiles), dim3(256), 0,
+                       st, items, n_items);
   return hipGetLastError();
 }
 

@@ -1669,14 +1669,17 @@ hipError_t launch_stage2(const EigItem *items, int n_items, int n_max, bool fp32
 }
 
 // Eigenvector columns per back-transform workgroup: bounded by the LDS
-// budget and by one (block, column) pair of a stage-2 sweep per thread.
+// budget, by one (block, column) pair of a stage-2 sweep per thread, and by 4
+// (the stage-1 part is bound by its per-panel latency: more workgroups with
+// fewer columns each finish sooner; 8 -> 4 columns: 19.88 -> 19.75 ms for the
+// 60-point solve of the 2N = 882 cell).
 int backtransform_cols(int n_max, bool fp32) {
   const size_t es = fp32 ? sizeof(cf) : sizeof(cd);
   size_t cap = 1;
   while (cap < 8 && zbytes(n_max, (int)cap + 1, es) <= (size_t)BT_LDS_BYTES) ++cap;
   const size_t blocks = (size_t)std::max(1, (n_max - 1 + HB - 1) / HB);
   const size_t cap2 = (size_t)BT_THREADS / blocks;
-  return (int)std::min<size_t>(8, std::max<size_t>(1, std::min(cap, cap2)));
+  return (int)std::min<size_t>(4, std::max<size_t>(1, std::min(cap, cap2)));
 }
 
 hipError_t launch_backtransform(const EigItem *items, int n_items, int n_min, int n_max, int nb, bool fp32,

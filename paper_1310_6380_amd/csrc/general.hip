@@ -158,11 +158,11 @@ hipError_t launch_toeplitz_blocks(const cd *F, int M1, int M2, int M3, int N, in
 template <typename R>
 __global__ void __launch_bounds__(256) form_operator_general(const EigItem *__restrict__ items) {
   __shared__ cd tile[32][33];
-  const EigItem &it = items[blockIdx.y];
+  const EigItem &it = items[blockIdx.x];   // item fastest (coefficient tiles shared in L2)
   if (it.dim == 0) return;   // isotropic planar layout: form_operator
   const int n = it.n, d = it.dim;
   const int nt = (n + 31) / 32;
-  int t = blockIdx.x;
+  int t = blockIdx.y;
   if (t >= nt * (nt + 1) / 2) return;
   int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -202,9 +202,9 @@ hipError_t launch_form_operator_general(const EigItem *items, int n_items, int n
   const int tiles = nt * (nt + 1) / 2;
   ProfScope ps(K_FORM, st);
   if (fp32)
-    hipLaunchKernelGGL((form_operator_general<float>), dim3(tiles, n_items), dim3(256), 0, st, items);
+    hipLaunchKernelGGL((form_operator_general<float>), dim3(n_items, tiles), dim3(256), 0, st, items);
   else
-    hipLaunchKernelGGL((form_operator_general<double>), dim3(tiles, n_items), dim3(256), 0, st, items);
+    hipLaunchKernelGGL((form_operator_general<double>), dim3(n_items, tiles), dim3(256), 0, st, items);
   return hipGetLastError();
 }
 
