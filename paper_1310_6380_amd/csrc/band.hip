@@ -1182,7 +1182,7 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
       }
       // the reflector for the back-transform (after the release: not waited for)
       if (g == 0) {
-        MVPB_GAS R *dst = (MVPB_GAS R *)(V2 + (size_t)(roff + k) * HB + q);
+        MVPB_GAS R *dst = (MVPB_GAS R *)(V2 + (size_t)roff * HB + (size_t)q * nsteps + k);
         __builtin_nontemporal_store(vq.re, dst);
         __builtin_nontemporal_store(vq.im, dst + 1);
       }
@@ -1237,11 +1237,11 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
     const int ic = max(i, 0);
     const int nsteps = (n - 1 - ic + HB - 1) / HB;
     const int k = min(tid / ncl, nsteps - 1);
-    const long long ri = rtot - refl_count(n - 1 - ic) + k;
-    const C *v = V2 + (size_t)ri * HB;
+    const long long r0 = rtot - refl_count(n - 1 - ic);
+    const C *v = V2 + (size_t)r0 * HB + k;
 #pragma unroll
-    for (int j = 0; j < HB; ++j) vv[j] = gld(v, j);
-    tau = gld(tau2, ri);
+    for (int j = 0; j < HB; ++j) vv[j] = gld(v, (size_t)j * nsteps);
+    tau = gld(tau2, r0 + k);
   };
   // three register stages: sweep i (applied now), i-1 and i-2 (in flight)
   C va[HB], vb[HB], vc2[HB], ta = czero<R>(), tb = czero<R>(), tc = czero<R>();
@@ -1295,9 +1295,11 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
 // next lane (DPP wave shift) and lane 0 takes row i of the tridiagonal
 // eigenvector.  The register slot of a window row rotates with the sweep
 // count, so the sweep loop is unrolled 16 times to keep every index static.
-// The reflectors of one sweep are consecutive in V2 (one 16-vector per
-// block) and are loaded one sweep ahead; the wavefronts of a workgroup are
-// columns of one item and read the same reflectors (the CU's L1 serves them).
+// The reflectors of one sweep are stored row by row (entry j of every block's
+// reflector consecutive), so that a load of entry j by the 64 lanes is one
+// contiguous run; they are loaded one sweep ahead, and the wavefronts of a
+// workgroup are columns of one item and read the same reflectors (the CU's
+// L1 serves them).
 constexpr int BTW_WAVES = 4;   // wavefronts per workgroup
 constexpr int BTW_COLS = 2;    // eigenvector columns per wavefront
 template <typename R>
@@ -1338,10 +1340,11 @@ backtransform_2s_wave(const EigItem *__restrict__ items, int n_items, int S) {
     const int ic = max(i, 0);
     const int nsteps = (n - 1 - ic + HB - 1) / HB;
     const bool ok = i >= 0 && lane < nsteps;
-    const long long ri = rtot - refl_count(n - 1 - ic) + min(lane, nsteps - 1);
+    const long long r0 = rtot - refl_count(n - 1 - ic);
+    const int kl = min(lane, nsteps - 1);
 #pragma unroll
-    for (int j = 0; j < HB; ++j) v[j] = gld(V2, (size_t)ri * HB + j);
-    const C t = gld(tau2, ri);
+    for (int j = 0; j < HB; ++j) v[j] = gld(V2, (size_t)r0 * HB + (size_t)j * nsteps + kl);
+    const C t = gld(tau2, r0 + kl);
     tau = ok ? t : czero<R>();
 #pragma unroll
     for (int q = 0; q < BTW_COLS; ++q) xin[q] = (R)gld(X, (size_t)(ic + 1) * nb + cb + min(q, ncw - 1));
