@@ -1180,12 +1180,10 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
           __hip_atomic_store(gflag + 2 + i, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
-      // the reflector for the back-transform (after the release: not waited for)
-      if (g == 0) {
-        MVPB_GAS R *dst = (MVPB_GAS R *)(V2 + (size_t)roff * HB + (size_t)q * nsteps + k);
-        __builtin_nontemporal_store(vq.re, dst);
-        __builtin_nontemporal_store(vq.im, dst + 1);
-      }
+      // the reflector for the back-transform (after the release: not waited
+      // for); entry q of consecutive blocks shares a cache line, which the L2
+      // completes over the following blocks of the sweep
+      if (g == 0) gst(V2 + (size_t)roff * HB + (size_t)q * nsteps + k, 0, vq);
       if (lane == 0) gst(tau2, roff + k, tau);
       vprev = vq;
       tauprev = tau;
