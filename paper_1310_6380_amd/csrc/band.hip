@@ -895,6 +895,17 @@ constexpr int CH_WAVES = 8;
 // workgroups per item of the bulge chasing (more than one only while every
 // workgroup of the launch can be resident at once, one per CU)
 constexpr int HB2ST_MAX_WG = 4;
+// Layout of the bulge-chasing reflectors of one sweep (nsteps blocks of HB
+// entries, starting at its first reflector's index times HB): chunks of
+// V2_CHUNK consecutive blocks, entry-major within a chunk (entry j of the
+// chunk's blocks consecutive; the last chunk is narrower), so that the
+// writer emits one contiguous run per chunk and a back-transform load of one
+// entry by consecutive blocks reads runs of V2_CHUNK entries.
+constexpr int V2_CHUNK = 8;
+MVPB_HD size_t v2_index(int nsteps, int k, int j) {
+  const int c = k / V2_CHUNK, wd = min(V2_CHUNK, nsteps - c * V2_CHUNK);
+  return (size_t)c * V2_CHUNK * HB + (size_t)j * wd + (k % V2_CHUNK);
+}
 // launch control words of the bulge chasing: per-XCD slot counters, the next
 // item, and the item of every group of P workgroups (per XCD)
 constexpr int HB2ST_CTL_ITEM = 16, HB2ST_CTL_TABLE = 32, HB2ST_MAX_XCC = 16;
@@ -967,6 +978,9 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
   __shared__ int prog[CH_WAVES];
   __shared__ int abort_s;
   __shared__ int claim[2];
+  // reflectors of the last V2_CHUNK blocks of each wavefront's sweep, written
+  // out as one contiguous run per chunk (layout of v2_index)
+  __shared__ C vstage[CH_WAVES][V2_CHUNK][HB];
   if (threadIdx.x == 0) {
     const int gmax = (int)(gridDim.x / P);   // groups an XCD can hold
     const int x = xcc_id();
@@ -1181,9 +1195,17 @@ __global__ void __launch_bounds__(CH_WAVES * 64) hb2st(const EigItem *__restrict
         }
       }
       // the reflector for the back-transform (after the release: not waited
-      // for); entry q of consecutive blocks shares a cache line, which the L2
-      // completes over the following blocks of the sweep
-      if (g == 0) gst(V2 + (size_t)roff * HB + (size_t)q * nsteps + k, 0, vq);
+      // for), staged until its chunk of V2_CHUNK blocks is complete
+      if (g == 0) vstage[w][k % V2_CHUNK][q] = vq;
+      if (k % V2_CHUNK == V2_CHUNK - 1 || k == nsteps - 1) {
+        const int c = k / V2_CHUNK, wd = k % V2_CHUNK + 1;
+        MVPB_GAS R *dst = (MVPB_GAS R *)(V2 + (size_t)roff * HB + (size_t)c * V2_CHUNK * HB);
+        for (int e = lane; e < wd * HB; e += 64) {
+          const C v = vstage[w][e % wd][e / wd];   // entry j = e / wd of block c V2_CHUNK + e % wd
+          __builtin_nontemporal_store(v.re, dst + 2 * e);
+          __builtin_nontemporal_store(v.im, dst + 2 * e + 1);
+        }
+      }
       if (lane == 0) gst(tau2, roff + k, tau);
       vprev = vq;
       tauprev = tau;
@@ -1236,9 +1258,9 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
     const int nsteps = (n - 1 - ic + HB - 1) / HB;
     const int k = min(tid / ncl, nsteps - 1);
     const long long r0 = rtot - refl_count(n - 1 - ic);
-    const C *v = V2 + (size_t)r0 * HB + k;
+    const C *v = V2 + (size_t)r0 * HB;
 #pragma unroll
-    for (int j = 0; j < HB; ++j) vv[j] = gld(v, (size_t)j * nsteps);
+    for (int j = 0; j < HB; ++j) vv[j] = gld(v, v2_index(nsteps, k, j));
     tau = gld(tau2, r0 + k);
   };
   // three register stages: sweep i (applied now), i-1 and i-2 (in flight)
@@ -1293,11 +1315,11 @@ __global__ void __launch_bounds__(BT_THREADS) backtransform_2s(const EigItem *__
 // next lane (DPP wave shift) and lane 0 takes row i of the tridiagonal
 // eigenvector.  The register slot of a window row rotates with the sweep
 // count, so the sweep loop is unrolled 16 times to keep every index static.
-// The reflectors of one sweep are stored row by row (entry j of every block's
-// reflector consecutive), so that a load of entry j by the 64 lanes is one
-// contiguous run; they are loaded one sweep ahead, and the wavefronts of a
-// workgroup are columns of one item and read the same reflectors (the CU's
-// L1 serves them).
+// The reflectors of one sweep are stored in chunks of V2_CHUNK blocks, entry
+// j of a chunk's blocks consecutive (v2_index), so that a load of entry j by
+// the 64 lanes touches 8 runs of 128 bytes; they are loaded one sweep ahead,
+// and the wavefronts of a workgroup are columns of one item and read the same
+// reflectors (the CU's L1 serves them).
 constexpr int BTW_WAVES = 4;   // wavefronts per workgroup
 constexpr int BTW_COLS = 2;    // eigenvector columns per wavefront
 template <typename R>
@@ -1341,7 +1363,7 @@ backtransform_2s_wave(const EigItem *__restrict__ items, int n_items, int S) {
     const long long r0 = rtot - refl_count(n - 1 - ic);
     const int kl = min(lane, nsteps - 1);
 #pragma unroll
-    for (int j = 0; j < HB; ++j) v[j] = gld(V2, (size_t)r0 * HB + (size_t)j * nsteps + kl);
+    for (int j = 0; j < HB; ++j) v[j] = gld(V2, (size_t)r0 * HB + v2_index(nsteps, kl, j));
     const C t = gld(tau2, r0 + kl);
     tau = ok ? t : czero<R>();
 #pragma unroll

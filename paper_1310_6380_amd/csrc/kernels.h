@@ -60,7 +60,7 @@ struct EigItem {
   void *T1;         // (R) ceil(n/HB) x HB x HB compact-WY factors of the panels
   // stage 2: band -> tridiagonal
   void *WB;         // (R) n x (2 HB + 1) band working copy
-  void *V2;         // (R) reflectors of the bulge chasing, HB entries each; per sweep entry-major (entry j of its blocks consecutive)
+  void *V2;         // (R) reflectors of the bulge chasing, HB entries each; per sweep in chunks of 8 blocks, entry-major in a chunk
   void *tau2;       // (R) their scalars
   double *d;        // n diagonal
   double *e;        // n off-diagonal (real)
