@@ -8,6 +8,8 @@
 //     eigenpairs of Y^H C Y, omega = sqrt(max(lambda, 0)).
 #include <float.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 #include "prof.h"
@@ -229,65 +231,96 @@ constexpr int TCH = 8;
 // One pivoted elimination step of T - sh I (row r): state (dr, ur) in, out.
 MVPB_DEV void lu_step(int r, double lr, double dns, double un, double pert, double &dr, double &ur,
                       double *__restrict__ DL, double *__restrict__ DGi, double *__restrict__ DU,
-                      double *__restrict__ DU2, double *__restrict__ PV) {
-  if (fabs(dr) >= fabs(lr)) {
-    const double ip = fast_rcp(dr == 0.0 ? pert : dr);
-    const double f = lr * ip;
-    DGi[r] = ip; DU[r] = ur; DU2[r] = 0.0; DL[r] = f; PV[r] = 0.0;
-    dr = dns - f * ur;
-    ur = un;
-  } else {
-    const double ip = fast_rcp(lr);
-    const double f = dr * ip;
-    DGi[r] = ip; DU[r] = dns; DU2[r] = un; DL[r] = f; PV[r] = 1.0;
-    dr = ur - f * dns;
-    ur = -f * un;
-  }
+                      double *__restrict__ DU2, double *__restrict__ PV, double &fo, bool &sw) {
+  // pivot row: the current one if |dr| >= |lr|, else the next (swap); the
+  // two cases by selects, so that the dependent chain has no branch
+  const bool keep = fabs(dr) >= fabs(lr);
+  const double piv = keep ? dr : lr;   // lr != 0 when it is the pivot
+  const double ip = fast_rcp(piv == 0.0 ? pert : piv);
+  const double f = (keep ? lr : dr) * ip;
+  DGi[r] = ip;
+  DU[r] = keep ? ur : dns;
+  DU2[r] = keep ? 0.0 : un;
+  DL[r] = f;
+  PV[r] = keep ? 0.0 : 1.0;
+  dr = (keep ? dns : ur) - f * (keep ? ur : dns);
+  ur = keep ? un : -f * un;
+  fo = f;
+  sw = !keep;
+}
+
+// Forward step r of (P, L)^-1 applied to x: with the carried value cur (row r
+// after the earlier steps) and x[r+1], writes x[r] and carries row r+1.
+MVPB_DEV void fwd_step(int r, bool sw, double f, double nxt, double &cur, double *__restrict__ xv) {
+  const double br = sw ? nxt : cur;
+  const double br1 = sw ? cur : nxt;
+  xv[r] = br;
+  cur = br1 - f * br;
 }
 
 // LU with partial pivoting of T - sh I: multipliers DL, reciprocal pivots DGi,
-// first and second superdiagonal of U (DU, DU2), row swaps PV (0/1).
+// first and second superdiagonal of U (DU, DU2), row swaps PV (0/1).  With
+// FWD, the forward substitution of x <- (T - sh I)^-1 x runs in the same pass
+// (the same operations as in tri_solve, one row behind the factorisation).
+template <bool FWD>
 MVPB_DEV void tri_lu(const double *__restrict__ dd, const double *__restrict__ ee, int n, double sh, double pert,
                      double *__restrict__ DL, double *__restrict__ DGi, double *__restrict__ DU,
-                     double *__restrict__ DU2, double *__restrict__ PV) {
+                     double *__restrict__ DU2, double *__restrict__ PV, double *__restrict__ xv) {
   double dr = dd[0] - sh, ur = (n > 1) ? ee[0] : 0.0;
+  double cur = FWD ? xv[0] : 0.0;
+  double f;
+  bool sw;
   int r = 0;
-  // a full chunk at r needs ee[r .. r+TCH] and dd[r+1 .. r+TCH], all < n-1 / < n
+  // a full chunk at r needs ee[r .. r+TCH], dd[r+1 .. r+TCH] and xv[r+1 .. r+TCH], all < n-1 / < n
   if (r + TCH < n - 1) {
-    double ec[TCH + 1], dc[TCH];
+    double ec[TCH + 1], dc[TCH], xc[TCH];
 #pragma unroll
     for (int u = 0; u <= TCH; ++u) ec[u] = ee[r + u];
 #pragma unroll
-    for (int u = 0; u < TCH; ++u) dc[u] = dd[r + 1 + u];
+    for (int u = 0; u < TCH; ++u) {
+      dc[u] = dd[r + 1 + u];
+      xc[u] = FWD ? xv[r + 1 + u] : 0.0;
+    }
     for (; r + TCH < n - 1; r += TCH) {
-      double en[TCH + 1], dn[TCH];
+      double en[TCH + 1], dn[TCH], xn[TCH];
       const bool more = r + 2 * TCH < n - 1;
       if (more) {
 #pragma unroll
         for (int u = 0; u <= TCH; ++u) en[u] = ee[r + TCH + u];
 #pragma unroll
-        for (int u = 0; u < TCH; ++u) dn[u] = dd[r + TCH + 1 + u];
+        for (int u = 0; u < TCH; ++u) {
+          dn[u] = dd[r + TCH + 1 + u];
+          xn[u] = FWD ? xv[r + TCH + 1 + u] : 0.0;
+        }
       }
 #pragma unroll
-      for (int u = 0; u < TCH; ++u) lu_step(r + u, ec[u], dc[u] - sh, ec[u + 1], pert, dr, ur, DL, DGi, DU, DU2, PV);
+      for (int u = 0; u < TCH; ++u) {
+        lu_step(r + u, ec[u], dc[u] - sh, ec[u + 1], pert, dr, ur, DL, DGi, DU, DU2, PV, f, sw);
+        if (FWD) fwd_step(r + u, sw, f, xc[u], cur, xv);
+      }
       if (more) {
 #pragma unroll
         for (int u = 0; u <= TCH; ++u) ec[u] = en[u];
 #pragma unroll
-        for (int u = 0; u < TCH; ++u) dc[u] = dn[u];
+        for (int u = 0; u < TCH; ++u) {
+          dc[u] = dn[u];
+          xc[u] = xn[u];
+        }
       }
     }
   }
-  for (; r < n - 1; ++r)
-    lu_step(r, ee[r], dd[r + 1] - sh, (r < n - 2) ? ee[r + 1] : 0.0, pert, dr, ur, DL, DGi, DU, DU2, PV);
+  for (; r < n - 1; ++r) {
+    lu_step(r, ee[r], dd[r + 1] - sh, (r < n - 2) ? ee[r + 1] : 0.0, pert, dr, ur, DL, DGi, DU, DU2, PV, f, sw);
+    if (FWD) fwd_step(r, sw, f, xv[r + 1], cur, xv);
+  }
   DGi[n - 1] = fast_rcp(dr == 0.0 ? pert : dr);
+  if (FWD) xv[n - 1] = cur;
 }
 
-// x <- (T - sh I)^-1 x with the factors of tri_lu (x in place).
-MVPB_DEV void tri_solve(double *__restrict__ xv, int n, const double *__restrict__ DL,
-                        const double *__restrict__ DGi, const double *__restrict__ DU,
-                        const double *__restrict__ DU2, const double *__restrict__ PV) {
-  // forward: apply P and L^-1.  Step r reads x[r+1], PV[r], DL[r]; writes x[r].
+// Forward part of tri_solve: apply P and L^-1.  Step r reads x[r+1], PV[r],
+// DL[r]; writes x[r].
+MVPB_DEV void tri_solve_fwd(double *__restrict__ xv, int n, const double *__restrict__ DL,
+                            const double *__restrict__ PV) {
   double cur = xv[0];
   int r = 0;
   if (r + TCH < n - 1) {
@@ -336,29 +369,44 @@ MVPB_DEV void tri_solve(double *__restrict__ xv, int n, const double *__restrict
     cur = br1 - DL[r] * br;
   }
   xv[n - 1] = cur;
+}
+
+// Backward part of tri_solve: substitution with U.
+MVPB_DEV void tri_solve_back(double *__restrict__ xv, int n, const double *__restrict__ DGi,
+                             const double *__restrict__ DU, const double *__restrict__ DU2) {
   // backward substitution with U, rows n-1 .. 0.  Step r reads x[r], DU[r],
   // DU2[r], DGi[r]; writes x[r].  Rescaling (rare) touches the rows above r.
   double x1 = 0.0, x2 = 0.0, sc = 1.0;
-  int rr = n - 1;
-  auto bstep = [&](int q, double b, double u1, double u2, double gi) {
+  // C1, C2: the terms of rows q+1, q+2 exist (every row but the last two)
+  auto bstep = [&](auto c1, auto c2, int q, double b, double u1, double u2, double gi) {
     double sacc = sc * b;
-    if (q + 1 < n) sacc -= u1 * x1;
-    if (q + 2 < n) sacc -= u2 * x2;
+    if (decltype(c1)::value) sacc -= u1 * x1;
+    if (decltype(c2)::value) sacc -= u2 * x2;
     double x = sacc * gi;
-    if (!isfinite(x)) x = 0.0;
-    if (fabs(x) > 1e150) {
-      // keep the iterate finite: rescale what is solved and what is left
-      const double f = 1e-150;
-      for (int t = q + 1; t < n; ++t) xv[t] *= f;
-      x1 *= f;
-      x2 *= f;
-      sc *= f;
-      x *= f;
+    if (!(fabs(x) <= 1e150)) {   // not finite, or too large: one test on the common path
+      if (!isfinite(x)) {
+        x = 0.0;
+      } else {
+        // keep the iterate finite: rescale what is solved and what is left
+        const double f = 1e-150;
+        for (int t = q + 1; t < n; ++t) xv[t] *= f;
+        x1 *= f;
+        x2 *= f;
+        sc *= f;
+        x *= f;
+      }
     }
     xv[q] = x;
     x2 = x1;
     x1 = x;
   };
+  using T0 = std::integral_constant<bool, false>;
+  using T1 = std::integral_constant<bool, true>;
+  int rr = n - 1;
+  if (rr >= 0) bstep(T0{}, T0{}, rr, xv[rr], DU[rr], DU2[rr], DGi[rr]);
+  --rr;
+  if (rr >= 0) bstep(T1{}, T0{}, rr, xv[rr], DU[rr], DU2[rr], DGi[rr]);
+  --rr;
   if (rr - TCH + 1 >= 0) {
     double bc[TCH], uc[TCH], vc[TCH], gc[TCH];
 #pragma unroll
@@ -383,7 +431,7 @@ MVPB_DEV void tri_solve(double *__restrict__ xv, int n, const double *__restrict
         }
       }
 #pragma unroll
-      for (int u = 0; u < TCH; ++u) bstep(rr - u, bc[u], uc[u], vc[u], gc[u]);
+      for (int u = 0; u < TCH; ++u) bstep(T1{}, T1{}, rr - u, bc[u], uc[u], vc[u], gc[u]);
       if (more) {
 #pragma unroll
         for (int u = 0; u < TCH; ++u) {
@@ -395,7 +443,16 @@ MVPB_DEV void tri_solve(double *__restrict__ xv, int n, const double *__restrict
       }
     }
   }
-  for (; rr >= 0; --rr) bstep(rr, xv[rr], DU[rr], DU2[rr], DGi[rr]);
+  for (; rr >= 0; --rr) bstep(T1{}, T1{}, rr, xv[rr], DU[rr], DU2[rr], DGi[rr]);
+}
+
+// x <- (T - sh I)^-1 x with the factors of tri_lu (x in place); fwd = false
+// when tri_lu has already applied the forward part.
+MVPB_DEV void tri_solve(double *__restrict__ xv, int n, const double *__restrict__ DL,
+                        const double *__restrict__ DGi, const double *__restrict__ DU,
+                        const double *__restrict__ DU2, const double *__restrict__ PV, bool fwd = true) {
+  if (fwd) tri_solve_fwd(xv, n, DL, PV);
+  tri_solve_back(xv, n, DGi, DU, DU2);
 }
 
 // Eigenvalues closer than CLUSTER_REL |T| to a neighbour form a cluster: their
@@ -565,11 +622,12 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
   if (!in_cluster(lam, jm, nb, CLUSTER_REL * bnorm)) return;   // isolated: twisted factorization
   const double pert = fmax(DBL_EPSILON * bnorm, 1e-280);
   const double sh = lam[jm];
-  if (lane == 0) tri_lu(dd, ee, n, sh, pert, DL, DGi, DU, DU2, PV);
   for (int r = lane; r < n; r += 64) xv[r] = hash_uniform(r + 1, jm + 7);
   __syncthreads();
+  // the factorisation carries the forward part of the first solve
+  if (lane == 0) tri_lu<true>(dd, ee, n, sh, pert, DL, DGi, DU, DU2, PV, xv);
   for (int iter = 0; iter < 2; ++iter) {
-    if (lane == 0) tri_solve(xv, n, DL, DGi, DU, DU2, PV);
+    if (lane == 0) tri_solve(xv, n, DL, DGi, DU, DU2, PV, iter > 0);
     __syncthreads();
     double amax = 0.0;
     for (int r = lane; r < n; r += 64) amax = fmax(amax, fabs(xv[r]));
@@ -759,12 +817,12 @@ MVPB_DEV void jacobi_eig(cd (*Gs)[RR_MAX_BANDS + 1], cd (*Vs)[RR_MAX_BANDS + 1],
 //                them and rr_estimate.
 // ---------------------------------------------------------------------------
 constexpr int RR_MAXB = RR_MAX_BANDS;
-constexpr int RRP_BC = 24;   // bands per pass of the product kernel
+constexpr int RRP_BC_MAX = 24;   // bands per pass of the product kernel (at most)
 
 // RES: the residual pass of items with an error estimate (the vectors are the
 // residuals R that rr_small left in the inverse-iteration scratch; only the
 // Gram partials R^H C R, R^H R are kept).
-template <bool RES>
+template <bool RES, int RRP_BC>
 __global__ void __launch_bounds__(256) rr_product(const EigItem *__restrict__ items) {
   extern __shared__ __align__(16) unsigned char rr_raw[];
   __shared__ cd Ys[64][RRP_BC + 1];
@@ -1033,13 +1091,32 @@ __global__ void __launch_bounds__(64) rr_estimate(const EigItem *__restrict__ it
   if (threadIdx.x == 0) *it.acc = worst;
 }
 
+// Bands per pass of the product kernel: the smallest of 8, 12, ..., 24 that
+// holds every band in one pass (no products with padding columns beyond
+// it), else passes of 24.
+static const void *rr_product_fn(bool res, int nb) {
+  static const void *const fns[2][5] = {
+      {(const void *)rr_product<false, 8>, (const void *)rr_product<false, 12>, (const void *)rr_product<false, 16>,
+       (const void *)rr_product<false, 20>, (const void *)rr_product<false, 24>},
+      {(const void *)rr_product<true, 8>, (const void *)rr_product<true, 12>, (const void *)rr_product<true, 16>,
+       (const void *)rr_product<true, 20>, (const void *)rr_product<true, 24>}};
+  const int c = nb <= 8 ? 0 : (nb <= 12 ? 1 : (nb <= 16 ? 2 : (nb <= 20 ? 3 : 4)));
+  return fns[res ? 1 : 0][c];
+}
+
+static void launch_rr_product(bool res, int nrb, int n_items, int nb, const EigItem *items, hipStream_t st) {
+  const void *f = rr_product_fn(res, nb);
+  void *args[] = {(void *)&items};
+  (void)hipLaunchKernel(f, dim3(nrb, n_items), dim3(256), args, sizeof(cd) * 2 * 64 * nb, st);
+}
+
 hipError_t launch_rayleigh_ritz(const EigItem *items, int n_items, int n_max, int nb, bool check, hipStream_t st) {
   ProfScope ps(K_RR, st);
   const int nrb = (n_max + 63) / 64;
-  hipLaunchKernelGGL(rr_product<false>, dim3(nrb, n_items), dim3(256), sizeof(cd) * 2 * 64 * nb, st, items);
+  launch_rr_product(false, nrb, n_items, nb, items, st);
   hipLaunchKernelGGL(rr_small, dim3(n_items), dim3(256), 0, st, items);
   if (check) {
-    hipLaunchKernelGGL(rr_product<true>, dim3(nrb, n_items), dim3(256), sizeof(cd) * 2 * 64 * nb, st, items);
+    launch_rr_product(true, nrb, n_items, nb, items, st);
     hipLaunchKernelGGL(rr_estimate, dim3(n_items), dim3(64), 0, st, items);
   }
   return hipGetLastError();
@@ -1074,12 +1151,10 @@ hipError_t init_kernel_attributes() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)tridiag_invit<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(sizeof(double) * 3 * MAX_N));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)rr_product<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(sizeof(cd) * 2 * 64 * RR_MAX_BANDS));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)rr_product<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(sizeof(cd) * 2 * 64 * RR_MAX_BANDS));
+  for (int res = 0; res < 2 && e == hipSuccess; ++res)
+    for (int nb = 8; nb <= RRP_BC_MAX && e == hipSuccess; nb += 4)
+      e = hipFuncSetAttribute(rr_product_fn(res != 0, nb), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(cd) * 2 * 64 * RR_MAX_BANDS));
   if (e != hipSuccess) return e;
   return init_band_attributes();
 }
