@@ -591,14 +591,19 @@ __global__ void __launch_bounds__(64) tridiag_twisted(const EigItem *__restrict_
 }
 
 // 1b. Eigenvectors of cluster members (eigenvalues within CLUSTER_REL |T|
-// of a neighbour) by inverse iteration with a pivoted LU of T - lam I: two
-// solves from a pseudo-random start that differs per member, so that members
-// of a (near-)degenerate cluster come out independent.  One wavefront per
+// of a neighbour) by inverse iteration with a pivoted LU of T - lam I: one
+// solve from a pseudo-random start that differs per member, so that members
+// of a (near-)degenerate cluster come out independent.  With the shift within
+// about eps |T| of the eigenvalue, one solve leaves the components outside
+// the cluster smaller by the ratio of that distance to the gap; the
+// Gram-Schmidt pass below and the Rayleigh-Ritz step after the
+// back-transform act on what remains.  One wavefront per
 // member, all members at once; lane 0 runs the sequential factorisation and
 // solves, the wavefront the normalisation.  tridiag_cluster_gs then
 // orthonormalises every cluster.  LU_LDS: the five LU arrays live in LDS
 // (else in the item's global scratch).
 constexpr int INV_LDS_MAX_N = 2400;
+constexpr int INVIT_SOLVES = 1;
 template <bool LU_LDS>
 __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ items) {
   extern __shared__ double shd[];
@@ -626,7 +631,7 @@ __global__ void __launch_bounds__(64) tridiag_invit(const EigItem *__restrict__ 
   __syncthreads();
   // the factorisation carries the forward part of the first solve
   if (lane == 0) tri_lu<true>(dd, ee, n, sh, pert, DL, DGi, DU, DU2, PV, xv);
-  for (int iter = 0; iter < 2; ++iter) {
+  for (int iter = 0; iter < INVIT_SOLVES; ++iter) {
     if (lane == 0) tri_solve(xv, n, DL, DGi, DU, DU2, PV, iter > 0);
     __syncthreads();
     double amax = 0.0;
