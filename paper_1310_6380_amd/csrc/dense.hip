@@ -24,6 +24,67 @@ namespace mvpb {
 // later launches skip that matrix.
 // ---------------------------------------------------------------------------
 constexpr int CB = 64;
+typedef double zd4_t __attribute__((ext_vector_type(4)));
+
+// D = A B for one 64 x 64 tile from LDS, D(r, c) = sum_{k < K} Ar[r][k] B(k, c)
+// with B(k, c) = Bm[k][c] (TRB false) or conj(Bm[c][k]) (TRB true); entries
+// with k >= K must be zero in both (K is rounded up to the 4-deep step).  On
+// the FP64 matrix cores as D^T = B^T A^T, three real 16x16x4 products per
+// complex step (Gauss: p1 = br ar, p2 = bi ai, p3 = (br + bi)(ar + ai)), so
+// that a lane's results run down a column: wavefront wv owns columns
+// 16 wv .. 16 wv + 15, and lane l holds D(16 rb + l % 16, 16 wv + l / 16 + 4 v)
+// = (p1 - p2, p3 - p1 - p2)[rb][v].
+template <bool TRB>
+MVPB_DEV void tile_mfma(const cd (*Ar)[CB + 1], const cd (*Bm)[CB + 1], int K, zd4_t p1[4], zd4_t p2[4],
+                        zd4_t p3[4]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) p1[rb] = p2[rb] = p3[rb] = zd4_t{0.0, 0.0, 0.0, 0.0};
+  const int c = 16 * wv + li;
+  for (int kk = 0; kk < K; kk += 4) {
+    const int k = kk + lk;
+    const cd bv = TRB ? conj(Bm[c][k]) : Bm[k][c];
+    const double bs = bv.re + bv.im;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const cd av = Ar[16 * rb + li][k];
+      p1[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv.re, av.re, p1[rb], 0, 0, 0);
+      p2[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv.im, av.im, p2[rb], 0, 0, 0);
+      p3[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bs, av.re + av.im, p3[rb], 0, 0, 0);
+    }
+  }
+}
+MVPB_DEV cd tile_value(const zd4_t p1[4], const zd4_t p2[4], const zd4_t p3[4], int rb, int v) {
+  return mk(p1[rb][v] - p2[rb][v], p3[rb][v] - p1[rb][v] - p2[rb][v]);
+}
+
+// Stage 64 x 64 tiles of column-major matrices into LDS: T[i][c0 + k] =
+// M[idx] where where(i, k, idx) holds, else zero.  Thread t takes the entries
+// e = t + 256 u (i = e % 64 fastest, so a wavefront reads one column run);
+// every load is issued, from element 0 where masked, before the first LDS
+// store, so that a thread's loads of both tiles are in flight together.
+constexpr int STAGE_PER_THREAD = CB * CB / 256;
+template <int W1, int W2, typename F1, typename F2>
+MVPB_DEV void stage_tiles(cd (*T1)[W1], int c1, const cd *M1, F1 where1, cd (*T2)[W2], int c2, const cd *M2,
+                          F2 where2) {
+  cd v1[STAGE_PER_THREAD], v2[STAGE_PER_THREAD];
+  bool o1[STAGE_PER_THREAD], o2[STAGE_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < STAGE_PER_THREAD; ++u) {
+    const int e = threadIdx.x + 256 * u, i = e % CB, k = e / CB;
+    size_t x1 = 0, x2 = 0;
+    o1[u] = where1(i, k, x1);
+    o2[u] = where2(i, k, x2);
+    v1[u] = gld(M1, o1[u] ? x1 : 0);
+    v2[u] = gld(M2, o2[u] ? x2 : 0);
+  }
+#pragma unroll
+  for (int u = 0; u < STAGE_PER_THREAD; ++u) {
+    const int e = threadIdx.x + 256 * u, i = e % CB, k = e / CB;
+    T1[i][c1 + k] = o1[u] ? v1[u] : mk(0.0, 0.0);
+    T2[i][c2 + k] = o2[u] ? v2[u] : mk(0.0, 0.0);
+  }
+}
 
 // Factor and inverse of one diagonal block together: step j of the
 // elimination scales column j of L and row j of the inverse, then updates
@@ -44,10 +105,20 @@ __global__ void __launch_bounds__(256) potrf_diag(cd *const *Aarr, cd *const *Xa
   const int nb = min(CB, N - jb);
   const int tid = threadIdx.x, c_ = tid & (CB - 1), w_ = tid / CB;
   const size_t ld = (size_t)N;
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int r = e % CB, c = e / CB;
-    DD[r][CB + c] = (r < nb && c < nb && r >= c) ? A[(size_t)(jb + c) * ld + jb + r] : mk(0.0, 0.0);
-    DD[r][c] = mk(r == c ? 1.0 : 0.0, 0.0);
+  {
+    cd v[STAGE_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < STAGE_PER_THREAD; ++u) {
+      const int e = tid + 256 * u, r = e % CB, c = e / CB;
+      const bool ok = r < nb && c < nb && r >= c;
+      v[u] = gld(A, ok ? (size_t)(jb + c) * ld + jb + r : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_PER_THREAD; ++u) {
+      const int e = tid + 256 * u, r = e % CB, c = e / CB;
+      DD[r][CB + c] = (r < nb && c < nb && r >= c) ? v[u] : mk(0.0, 0.0);
+      DD[r][c] = mk(r == c ? 1.0 : 0.0, 0.0);
+    }
   }
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
@@ -103,35 +174,21 @@ __global__ void __launch_bounds__(256) potrf_panel(cd *const *Aarr, cd *const *X
     // X[jb, c-block] = X_jj Y[jb, c-block] in place (c-block left of jb, full
     // width); no other workgroup of the launch touches that block
     const int c0 = (blockIdx.x - rbn) * CB;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    for (int e = tid; e < CB * CB; e += 256) {
-      const int r = e % CB, k = e / CB;
-      Di[r][k] = (r < nb && k < nb && r >= k) ? X[(size_t)(jb + k) * ldx + jb + r] : mk(0.0, 0.0);
-      P[r][k] = (r < nb) ? X[(size_t)(c0 + k) * ldx + jb + r] : mk(0.0, 0.0);   // P[k'][c] = Y[jb + k'][c0 + c]
-    }
+    const int tid = threadIdx.x, li = tid & 15, lk = (tid & 63) >> 4, wv = tid >> 6;
+    // Di = X_jj (lower); P[k'][c] = Y[jb + k'][c0 + c]
+    stage_tiles(
+        Di, 0, X,
+        [&](int r, int k, size_t &x) { x = (size_t)(jb + k) * ldx + jb + r; return r < nb && k < nb && r >= k; },
+        P, 0, X, [&](int r, int k, size_t &x) { x = (size_t)(c0 + k) * ldx + jb + r; return r < nb; });
     __syncthreads();
-    cd acc[4][4];
+    zd4_t p1[4], p2[4], p3[4];
+    tile_mfma<false>(Di, P, nb, p1, p2, p3);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
-    for (int k = 0; k < nb; ++k) {
-      cd pv[4], dv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) pv[a] = Di[tx + 16 * a][k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) dv[c] = P[k][ty + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int r = tx + 16 * a;
-        if (r < nb) X[(size_t)(c0 + ty + 16 * c) * ldx + jb + r] = acc[a][c];
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rb + li, cc = 16 * wv + lk + 4 * v;
+        if (r < nb) X[(size_t)(c0 + cc) * ldx + jb + r] = tile_value(p1, p2, p3, rb, v);
       }
     return;
   }
@@ -139,39 +196,27 @@ __global__ void __launch_bounds__(256) potrf_panel(cd *const *Aarr, cd *const *X
   if (i0 >= N) return;
   const int rows = min(CB, N - i0);
   const size_t ld = (size_t)N;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int r = e % CB, k = e / CB;
-    P[r][k] = (r < rows && k < nb) ? A[(size_t)(jb + k) * ld + i0 + r] : mk(0.0, 0.0);
-    Di[r][k] = (r < nb && k < nb && r >= k) ? X[(size_t)(jb + k) * ld + jb + r] : mk(0.0, 0.0);
-  }
+  const int tid = threadIdx.x, li = tid & 15, lk = (tid & 63) >> 4, wv = tid >> 6;
+  stage_tiles(
+      P, 0, A, [&](int r, int k, size_t &x) { x = (size_t)(jb + k) * ld + i0 + r; return r < rows && k < nb; }, Di,
+      0, X, [&](int r, int k, size_t &x) { x = (size_t)(jb + k) * ld + jb + r; return r < nb && k < nb && r >= k; });
   __syncthreads();
-  cd acc[4][4];
+  zd4_t p1[4], p2[4], p3[4];
+  tile_mfma<true>(P, Di, nb, p1, p2, p3);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
-  for (int k = 0; k < nb; ++k) {
-    cd pv[4], dv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) pv[a] = P[tx + 16 * a][k];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) dv[c] = conj(Di[ty + 16 * c][k]);
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
-  }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int cc = ty + 16 * c;
-    if (cc >= nb) continue;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = tx + 16 * a;
-      if (r < rows) A[(size_t)(jb + cc) * ld + i0 + r] = acc[a][c];
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * rb + li, cc = 16 * wv + lk + 4 * v;
+      if (cc < nb && r < rows) A[(size_t)(jb + cc) * ld + i0 + r] = tile_value(p1, p2, p3, rb, v);
     }
-  }
+}
+
+MVPB_DEV int tri_row(int t) {   // I with I (I + 1) / 2 <= t < (I + 1) (I + 2) / 2
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  return I;
 }
 
 // A[i, k] -= L[i, jb] L[k, jb]^H on the lower 64 x 64 tiles right of jb+nb
@@ -199,86 +244,64 @@ __global__ void __launch_bounds__(256) potrf_update(cd *const *Aarr, cd *const *
     const bool first = cx0 == jb;
     const int cols = first ? nb : CB;
     const size_t ld = (size_t)N;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    for (int e = tid; e < CB * CB; e += 256) {
-      const int i = e % CB, k = e / CB;   // rows fastest in both loads
-      Lr[i][k] = (r0 + i < N && k < nb) ? A[(size_t)(jb + k) * ld + r0 + i] : mk(0.0, 0.0);
-      Lc[i][k] = (k < cols && i < nb) ? X[(size_t)(cx0 + k) * ld + jb + i] : mk(0.0, 0.0);   // Lc[k'][c] = X[jb+k'][cx0+c]
-    }
+    const int tid = threadIdx.x, li = tid & 15, lk = (tid & 63) >> 4, wv = tid >> 6;
+    // the entries this thread updates, loaded with the tiles (Y starts at zero)
+    cd cur[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * rb + li, cc = 16 * wv + lk + 4 * v;
+        const bool ok = !first && cc < cols && r < N;
+        cur[rb][v] = gld(X, ok ? (size_t)(cx0 + cc) * ld + r : 0);
+      }
+    // Lr[i][k] = L[r0 + i][jb + k]; Lc[k'][c] = X[jb + k'][cx0 + c]
+    stage_tiles(
+        Lr, 0, A, [&](int i, int k, size_t &x) { x = (size_t)(jb + k) * ld + r0 + i; return r0 + i < N && k < nb; },
+        Lc, 0, X, [&](int i, int k, size_t &x) { x = (size_t)(cx0 + k) * ld + jb + i; return k < cols && i < nb; });
     __syncthreads();
-    cd acc[4][4];
+    zd4_t p1[4], p2[4], p3[4];
+    tile_mfma<false>(Lr, Lc, nb, p1, p2, p3);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
-    for (int k = 0; k < nb; ++k) {
-      cd pv[4], dv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) pv[a] = Lr[tx + 16 * a][k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) dv[c] = Lc[k][ty + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int cc = ty + 16 * c;
-      if (cc >= cols) continue;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int r = r0 + tx + 16 * a;
-        if (r < N) {
-          cd *dst = X + (size_t)(cx0 + cc) * ld + r;
-          *dst = first ? mk(0.0, 0.0) - acc[a][c] : *dst - acc[a][c];
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * rb + li, cc = 16 * wv + lk + 4 * v;
+        if (cc < cols && r < N) {
+          const cd c0v = first ? mk(0.0, 0.0) : cur[rb][v];
+          X[(size_t)(cx0 + cc) * ld + r] = c0v - tile_value(p1, p2, p3, rb, v);
         }
       }
-    }
     return;
   }
-  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  while (I * (I + 1) / 2 > t) --I;
+  const int I = tri_row(t);
   const int J = t - I * (I + 1) / 2;
   const int r0 = q0 + I * CB, c0 = q0 + J * CB;
   const size_t ld = (size_t)N;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  for (int e = tid; e < CB * CB; e += 256) {
-    const int i = e % CB, k = e / CB;
-    Lr[i][k] = (r0 + i < N && k < nb) ? A[(size_t)(jb + k) * ld + r0 + i] : mk(0.0, 0.0);
-    Lc[i][k] = (c0 + i < N && k < nb) ? A[(size_t)(jb + k) * ld + c0 + i] : mk(0.0, 0.0);
-  }
-  __syncthreads();
-  cd acc[4][4];
+  const int tid = threadIdx.x, li = tid & 15, lk = (tid & 63) >> 4, wv = tid >> 6;
+  // the entries this thread updates, loaded with the tiles
+  cd cur[4][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = mk(0.0, 0.0);
-  for (int k = 0; k < nb; ++k) {
-    cd pv[4], dv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) pv[a] = Lr[tx + 16 * a][k];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) dv[c] = conj(Lc[ty + 16 * c][k]);
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = cfma(pv[a], dv[c], acc[a][c]);
-  }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int cc = c0 + ty + 16 * c;
-    if (cc >= N) continue;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = r0 + tx + 16 * a;
-      if (r < N && r >= cc) {
-        cd *dst = A + (size_t)cc * ld + r;
-        *dst = *dst - acc[a][c];
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 16 * rb + li, cc = c0 + 16 * wv + lk + 4 * v;
+      const bool ok = cc < N && r < N && r >= cc;
+      cur[rb][v] = gld(A, ok ? (size_t)cc * ld + r : 0);
     }
-  }
+  stage_tiles(
+      Lr, 0, A, [&](int i, int k, size_t &x) { x = (size_t)(jb + k) * ld + r0 + i; return r0 + i < N && k < nb; },
+      Lc, 0, A, [&](int i, int k, size_t &x) { x = (size_t)(jb + k) * ld + c0 + i; return c0 + i < N && k < nb; });
+  __syncthreads();
+  zd4_t p1[4], p2[4], p3[4];
+  tile_mfma<true>(Lr, Lc, nb, p1, p2, p3);
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + 16 * rb + li, cc = c0 + 16 * wv + lk + 4 * v;
+      if (cc < N && r < N && r >= cc) A[(size_t)cc * ld + r] = cur[rb][v] - tile_value(p1, p2, p3, rb, v);
+    }
 }
 
 __global__ void zero_upper_blocks(cd *const *Xarr, const int *status, int N) {
@@ -346,7 +369,6 @@ hipError_t launch_potrf_trtri(cd *const *A, cd *const *Linv, int *status, int co
 // the next tile prefetched into registers need more than 256 registers and
 // halve the occupancy: slower.)
 // ---------------------------------------------------------------------------
-typedef double zd4_t __attribute__((ext_vector_type(4)));
 template <int OPA, int OPB>
 __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, cd alpha, GemmBatch bt, cd beta) {
   constexpr int BM = 64, BN = 64, BK = 8;
@@ -363,27 +385,42 @@ __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, cd alph
   zd4_t p1[4], p2[4], p3[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) p1[c] = p2[c] = p3[c] = zd4_t{0.0, 0.0, 0.0, 0.0};
+  constexpr int PA = BM * BK / 256, PB = BK * BN / 256;   // tile entries per thread
   for (int k0 = 0; k0 < K; k0 += BK) {
-    // A tile: 64 x 8
-    for (int e = tid; e < BM * BK; e += 256) {
-      int i, k;
-      if (OPA == OP_N) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
+    // every load of the step (A tile 64 x 8, its column scales, B tile 8 x 64)
+    // is issued, from element 0 where masked, before the first LDS store
+    cd va[PA], vb[PB];
+    double sa[PA];
+    bool oa[PA], ob[PB];
+#pragma unroll
+    for (int u = 0; u < PA; ++u) {
+      const int e = tid + 256 * u;
+      const int i = (OPA == OP_N) ? e % BM : e / BK, k = (OPA == OP_N) ? e / BM : e % BK;
       const int gi = m0 + i, gk = k0 + k;
-      cd v = mk(0.0, 0.0);
-      if (gi < M && gk < K) {
-        v = (OPA == OP_N) ? A[(size_t)gk * bt.lda + gi] : conj(A[(size_t)gi * bt.lda + gk]);
-        if (s) v = s[gk] * v;
-      }
-      As[k][i] = v;
+      oa[u] = gi < M && gk < K;
+      va[u] = gld(A, oa[u] ? ((OPA == OP_N) ? (size_t)gk * bt.lda + gi : (size_t)gi * bt.lda + gk) : 0);
+      sa[u] = s ? gld(s, oa[u] ? (size_t)gk : 0) : 1.0;
     }
-    // B tile: 8 x 64
-    for (int e = tid; e < BK * BN; e += 256) {
-      int k, j;
-      if (OPB == OP_N) { k = e % BK; j = e / BK; } else { j = e % BN; k = e / BN; }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int e = tid + 256 * u;
+      const int k = (OPB == OP_N) ? e % BK : e / BN, j = (OPB == OP_N) ? e / BK : e % BN;
       const int gk = k0 + k, gj = n0 + j;
-      cd v = mk(0.0, 0.0);
-      if (gk < K && gj < N) v = (OPB == OP_N) ? B[(size_t)gj * bt.ldb + gk] : conj(B[(size_t)gk * bt.ldb + gj]);
-      Bs[k][j] = v;
+      ob[u] = gk < K && gj < N;
+      vb[u] = gld(B, ob[u] ? ((OPB == OP_N) ? (size_t)gj * bt.ldb + gk : (size_t)gk * bt.ldb + gj) : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < PA; ++u) {
+      const int e = tid + 256 * u;
+      const int i = (OPA == OP_N) ? e % BM : e / BK, k = (OPA == OP_N) ? e / BM : e % BK;
+      const cd v = (OPA == OP_N) ? va[u] : conj(va[u]);
+      As[k][i] = oa[u] ? (s ? sa[u] * v : v) : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int e = tid + 256 * u;
+      const int k = (OPB == OP_N) ? e % BK : e / BN, j = (OPB == OP_N) ? e / BK : e % BN;
+      Bs[k][j] = ob[u] ? ((OPB == OP_N) ? vb[u] : conj(vb[u])) : mk(0.0, 0.0);
     }
     __syncthreads();
 #pragma unroll
