@@ -386,12 +386,14 @@ __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, cd alph
 #pragma unroll
   for (int c = 0; c < 4; ++c) p1[c] = p2[c] = p3[c] = zd4_t{0.0, 0.0, 0.0, 0.0};
   constexpr int PA = BM * BK / 256, PB = BK * BN / 256;   // tile entries per thread
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // every load of the step (A tile 64 x 8, its column scales, B tile 8 x 64)
-    // is issued, from element 0 where masked, before the first LDS store
-    cd va[PA], vb[PB];
-    double sa[PA];
-    bool oa[PA], ob[PB];
+  // the loads of step k0 + BK are issued right after the LDS stores of step
+  // k0, so that they are in flight during its matrix-core products; every
+  // load of a step is issued, from element 0 where masked, before the first
+  // LDS store that waits for it
+  cd va[PA], vb[PB];
+  double sa[PA];
+  bool oa[PA], ob[PB];
+  auto load_step = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
       const int e = tid + 256 * u;
@@ -409,6 +411,9 @@ __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, cd alph
       ob[u] = gk < K && gj < N;
       vb[u] = gld(B, ob[u] ? ((OPB == OP_N) ? (size_t)gj * bt.ldb + gk : (size_t)gk * bt.ldb + gj) : 0);
     }
+  };
+  load_step(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
       const int e = tid + 256 * u;
@@ -423,6 +428,7 @@ __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, cd alph
       Bs[k][j] = ob[u] ? ((OPB == OP_N) ? vb[u] : conj(vb[u])) : mk(0.0, 0.0);
     }
     __syncthreads();
+    if (k0 + BK < K) load_step(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const cd av = As[kk + ak][16 * wv + ai];
