@@ -196,6 +196,7 @@ MVPB_DEV void gst(cx<R> *p, size_t i, cx<R> v) {
 MVPB_DEV double gld(const double *p, size_t i) { return *((const MVPB_GAS double *)(p + i)); }
 MVPB_DEV void gst(double *p, size_t i, double v) { *((MVPB_GAS double *)(p + i)) = v; }
 MVPB_DEV int gld(const int *p, size_t i) { return *((const MVPB_GAS int *)(p + i)); }
+MVPB_DEV float gld(const float *p, size_t i) { return *((const MVPB_GAS float *)(p + i)); }
 MVPB_DEV void gst(int *p, size_t i, int v) { *((MVPB_GAS int *)(p + i)) = v; }
 
 // Workgroup barrier that orders LDS accesses only: global loads issued before

@@ -45,13 +45,13 @@ struct ConvA {
   const float *in = nullptr;   // NHWC input; nullptr: A is an ordinary matrix
   int lH = 0, lW = 0, lC = 0, lHo = 0, lWo = 0, s = 1;
 };
-MVPB_DEV float conv_col(const ConvA &cv, int p, int k) {
+MVPB_DEV size_t conv_index(const ConvA &cv, int p, int k) {   // of col[p][k] in the input
   const int c = k & ((1 << cv.lC) - 1), tap = k >> cv.lC;
   const int ky = tap / 3, kx = tap - 3 * ky;
   const int ox = p & ((1 << cv.lWo) - 1), t = p >> cv.lWo;
   const int oy = t & ((1 << cv.lHo) - 1), b = t >> cv.lHo;
   const int y = (cv.s * oy + ky - 1) & ((1 << cv.lH) - 1), x = (cv.s * ox + kx - 1) & ((1 << cv.lW) - 1);
-  return cv.in[(((((size_t)b << cv.lH) + y) << cv.lW) + x) << cv.lC | (size_t)c];
+  return (((((size_t)b << cv.lH) + y) << cv.lW) + x) << cv.lC | (size_t)c;
 }
 
 struct GemmArgs {
@@ -69,43 +69,70 @@ struct GemmArgs {
   ConvA conv;
 };
 
+// Every load of a thread is issued, from element 0 where masked, before its
+// first LDS store, so that all of them are in flight together.
 template <int TA, int TB, int BK>
 MVPB_DEV void load_tiles(const GemmArgs &g, int m0, int n0, int k0, int k1, float (&As)[BK][GBM + 4],
                          float (&Bs)[BK][GBN + 4]) {
+  constexpr int PA = GBM * BK / 256, PB = BK * GBN / 256;
+  static_assert(PA * 256 == GBM * BK && PB * 256 == BK * GBN, "tile entries per thread");
   const int tid = threadIdx.x;
-  for (int e = tid; e < GBM * BK; e += 256) {
-    int i, k;
-    if (TA == 0) { i = e / BK; k = e % BK; } else { k = e / GBM; i = e % GBM; }
+  float va[PA], vb[PB];
+  bool oa[PA], ob[PB];
+#pragma unroll
+  for (int u = 0; u < PA; ++u) {
+    const int e = tid + 256 * u;
+    const int i = TA == 0 ? e / BK : e % GBM, k = TA == 0 ? e % BK : e / GBM;
     const int gi = m0 + i, gk = k0 + k;
-    float v = 0.f;
-    if (gi < g.M && gk < k1) {
-      if (g.conv.in)   // op(A)[gi][gk] = col[gi][gk] (TA = 0) or col[gk][gi] (TA = 1)
-        v = TA == 0 ? conv_col(g.conv, gi, gk) : conv_col(g.conv, gk, gi);
-      else
-        v = TA == 0 ? g.A[(size_t)gi * g.lda + gk] : g.A[(size_t)gk * g.lda + gi];
+    oa[u] = gi < g.M && gk < k1;
+    if (g.conv.in) {   // op(A)[gi][gk] = col[gi][gk] (TA = 0) or col[gk][gi] (TA = 1)
+      const size_t x = TA == 0 ? conv_index(g.conv, gi, gk) : conv_index(g.conv, gk, gi);
+      va[u] = gld(g.conv.in, oa[u] ? x : 0);
+    } else {
+      const size_t x = TA == 0 ? (size_t)gi * g.lda + gk : (size_t)gk * g.lda + gi;
+      va[u] = gld(g.A, oa[u] ? x : 0);
     }
-    As[k][i] = v;
   }
-  for (int e = tid; e < BK * GBN; e += 256) {
-    int k, j;
-    if (TB == 0) { k = e / GBN; j = e % GBN; } else { j = e / BK; k = e % BK; }
+#pragma unroll
+  for (int u = 0; u < PB; ++u) {
+    const int e = tid + 256 * u;
+    const int k = TB == 0 ? e / GBN : e % BK, j = TB == 0 ? e % GBN : e / BK;
     const int gk = k0 + k, gj = n0 + j;
-    float v = 0.f;
-    if (gk < k1 && gj < g.N) v = TB == 0 ? g.B[(size_t)gk * g.ldb + gj] : g.B[(size_t)gj * g.ldb + gk];
-    Bs[k][j] = v;
+    ob[u] = gk < k1 && gj < g.N;
+    vb[u] = gld(g.B, ob[u] ? (TB == 0 ? (size_t)gk * g.ldb + gj : (size_t)gj * g.ldb + gk) : 0);
+  }
+#pragma unroll
+  for (int u = 0; u < PA; ++u) {
+    const int e = tid + 256 * u;
+    const int i = TA == 0 ? e / BK : e % GBM, k = TA == 0 ? e % BK : e / GBM;
+    As[k][i] = oa[u] ? va[u] : 0.f;
+  }
+#pragma unroll
+  for (int u = 0; u < PB; ++u) {
+    const int e = tid + 256 * u;
+    const int k = TB == 0 ? e / GBN : e % BK, j = TB == 0 ? e % GBN : e / BK;
+    Bs[k][j] = ob[u] ? vb[u] : 0.f;
   }
 }
 
-// Store one result: straight (with alpha, beta, bias, ReLU) or into the split's partial slice.
-MVPB_DEV void gemm_store(const GemmArgs &g, int i, int j, float acc) {
+// Store one result: straight (with alpha, beta, the column's bias bj, ReLU)
+// or into the split's partial slice.
+MVPB_DEV void gemm_store(const GemmArgs &g, int i, int j, float acc, float bj) {
   if (i >= g.M || j >= g.N) return;
   if (g.kchunk < g.K) {
     g.C[((size_t)blockIdx.z * g.M + i) * g.N + j] = acc;
     return;
   }
   float *c = g.C + (size_t)i * g.ldc + j;
-  float v = g.alpha * acc + (g.beta != 0.f ? g.beta * *c : 0.f) + (g.bias ? g.bias[j] : 0.f);
+  float v = g.alpha * acc + (g.beta != 0.f ? g.beta * *c : 0.f) + bj;
   *c = g.relu ? fmaxf(v, 0.f) : v;
+}
+// Bias of column j (zero without bias or for a split), loaded from an
+// in-range address so that a thread's loads are in flight together.
+MVPB_DEV float gemm_bias(const GemmArgs &g, int j) {
+  if (!g.bias || g.kchunk < g.K) return 0.f;   // uniform
+  const float b = gld(g.bias, j < g.N ? (size_t)j : 0);
+  return j < g.N ? b : 0.f;
 }
 
 template <int TA, int TB>
@@ -134,10 +161,13 @@ __global__ void __launch_bounds__(256) sgemm_f32(GemmArgs g) {
     }
     __syncthreads();
   }
+  float bj[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) bj[q] = gemm_bias(g, n0 + tx + 16 * q);
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) gemm_store(g, m0 + ty + 16 * p, n0 + tx + 16 * q, acc[p][q]);
+    for (int q = 0; q < 4; ++q) gemm_store(g, m0 + ty + 16 * p, n0 + tx + 16 * q, acc[p][q], bj[q]);
 }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -180,13 +210,16 @@ __global__ void __launch_bounds__(256) sgemm_bf16(GemmArgs g) {
       for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p], bf[q], acc[p][q], 0, 0, 0);
     __syncthreads();
   }
+  float bj[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) bj[q] = gemm_bias(g, n0 + wc + 16 * q + (lane & 15));
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        gemm_store(g, m0 + wr + 16 * p + 4 * (lane >> 4) + v, n0 + wc + 16 * q + (lane & 15), acc[p][q][v]);
+        gemm_store(g, m0 + wr + 16 * p + 4 * (lane >> 4) + v, n0 + wc + 16 * q + (lane & 15), acc[p][q][v], bj[q]);
 }
 
 // C = act(alpha sum_z P[z] + beta C + bias), slices added in order z = 0, 1, ...
