@@ -322,8 +322,20 @@ __global__ void __launch_bounds__(256) column_sums(const float *__restrict__ d, 
   __shared__ float red[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
   float acc = 0.f;
-  if (c < C)
-    for (size_t r = (size_t)blockIdx.y * 4 + g; r < rows; r += (size_t)gridDim.y * 4) acc += d[r * C + c];
+  if (c < C) {
+    // eight rows' loads in flight at a time, added in row order
+    constexpr int U = 8;
+    const size_t r0 = (size_t)blockIdx.y * 4 + g, step = (size_t)gridDim.y * 4;
+    size_t r = r0;
+    for (; r + (U - 1) * step < rows; r += U * step) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = gld(d, (r + u * step) * C + c);
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += v[u];
+    }
+    for (; r < rows; r += step) acc += d[r * C + c];
+  }
   red[g][threadIdx.x & 63] = acc;
   __syncthreads();
   if (g == 0 && c < C) part[(size_t)blockIdx.y * C + c] = red[0][threadIdx.x] + red[1][threadIdx.x] +
@@ -333,8 +345,18 @@ __global__ void __launch_bounds__(256) column_sums(const float *__restrict__ d, 
 __global__ void column_sums_fin(const float *__restrict__ part, int parts, int C, float *__restrict__ db) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
+  // eight parts' loads in flight at a time, added in part order
+  constexpr int U = 8;
   float acc = 0.f;
-  for (int p = 0; p < parts; ++p) acc += part[(size_t)p * C + c];
+  int p = 0;
+  for (; p + U <= parts; p += U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = gld(part, (size_t)(p + u) * C + c);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u];
+  }
+  for (; p < parts; ++p) acc += part[(size_t)p * C + c];
   db[c] = acc;
 }
 
