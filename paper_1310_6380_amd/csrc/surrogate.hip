@@ -229,8 +229,19 @@ __global__ void __launch_bounds__(256) gemm_reduce(const float *__restrict__ P, 
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= M * N) return;
   const int i = e / N, j = e % N;
+  // eight slices' loads in flight at a time, added in slice order
+  constexpr int U = 8;
+  const size_t MN = (size_t)M * N;
   float acc = 0.f;
-  for (int z = 0; z < splits; ++z) acc += P[(size_t)z * M * N + e];
+  int z = 0;
+  for (; z + U <= splits; z += U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = gld(P, (size_t)(z + u) * MN + e);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u];
+  }
+  for (; z < splits; ++z) acc += P[(size_t)z * MN + e];
   float *c = C + (size_t)i * ldc + j;
   float v = alpha * acc + (beta != 0.f ? beta * *c : 0.f) + (bias ? bias[j] : 0.f);
   *c = relu ? fmaxf(v, 0.f) : v;
