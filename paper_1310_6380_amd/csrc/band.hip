@@ -575,12 +575,15 @@ __global__ void __launch_bounds__(256) he2hb_hemm(const EigItem *__restrict__ it
   // stand (K = the lane's rows)
   C *X0 = (C *)it.X0;
   typename M::acc g1 = M::zero(), g2 = M::zero(), g3 = M::zero();
+  C vr[4];   // loaded together, ahead of the X0 stores
+#pragma unroll
+  for (int v = 0; v < 4; ++v) vr[v] = panel_v<R>(Vp, ld, r0 + 16 * wv + M::row(lane, v), ai, m, kq);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int rr = 16 * wv + M::row(lane, v);
     const C x = mkc<R>(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
     if (r0 + rr < m) gst(X0, (size_t)ai * ld + r0 + rr, x);
-    M::step3(conj(panel_v<R>(Vp, ld, r0 + rr, ai, m, kq)), x, g1, g2, g3);
+    M::step3(conj(vr[v]), x, g1, g2, g3);
   }
   // the four wavefronts' partials summed in LDS (the tile is free)
   static_assert(4 * HB * HB <= TC * 65, "Gram partials fit the tile buffer");
@@ -700,18 +703,27 @@ __global__ void __launch_bounds__(256) he2hb_wform(const EigItem *__restrict__ i
   // this block's rows of the next panel's columns c < kq (r >= c):
   // A22(r, c) -= sum_k W(r, k) conj(V(c, k)) + V(r, k) conj(W(c, k))
   {
-    A4 p1 = M::zero(), p2 = M::zero(), p3 = M::zero();
+    // the V entries of the products and the A22 entries this lane updates
+    // (rows of this block only) are loaded together, before the products
     const int ra = 64 * rb + 16 * wv + ai;
+    C vr[HB / 4], cur[4];
+#pragma unroll
+    for (int q = 0; q < HB / 4; ++q) vr[q] = panel_v<R>(Vp, ld, ra, 4 * q + ak, m, kq);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 64 * rb + 16 * wv + M::row(lane, v), c = ai;
+      cur[v] = ld_raw<R>(A22, (size_t)c * ld + r, r < m && c < kq && r >= c);
+    }
+    A4 p1 = M::zero(), p2 = M::zero(), p3 = M::zero();
 #pragma unroll
     for (int k0 = 0; k0 < HB; k0 += 4) M::step3(Wr[16 * wv + ai][k0 + ak], conj(V0[ai][k0 + ak]), p1, p2, p3);
 #pragma unroll
-    for (int k0 = 0; k0 < HB; k0 += 4)
-      M::step3(panel_v<R>(Vp, ld, ra, k0 + ak, m, kq), conj(G[ai][k0 + ak]), p1, p2, p3);
+    for (int k0 = 0; k0 < HB; k0 += 4) M::step3(vr[k0 / 4], conj(G[ai][k0 + ak]), p1, p2, p3);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = 64 * rb + 16 * wv + M::row(lane, v), c = ai;
       if (r < m && c < kq && r >= c) {
-        C x = gld(A22, (size_t)c * ld + r) - mkc<R>(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
+        C x = cur[v] - mkc<R>(p1[v] - p2[v], p3[v] - p1[v] - p2[v]);
         if (r == c) x.im = R(0);
         gst(A22, (size_t)c * ld + r, x);
       }
